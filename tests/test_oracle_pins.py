@@ -1,0 +1,400 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms, brute-force sums written here from scratch, invariances the method
+must have, finite differences and a textbook lattice constant.
+"""
+
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from conftest import built, workload
+from oracle import KE, cells, cpm, ewald, pppm
+
+EPS0 = 1.0 / (4.0 * math.pi * KE)
+
+
+# --------------------------------------------------------------------------
+# helpers written independently of the oracle
+# --------------------------------------------------------------------------
+
+def honeycomb_seff(cx, cy, eta, nmax=60):
+    """Effective Gaussian offset of a charged honeycomb layer.
+
+    The potential of a periodic layer of identical Gaussian charges at one of
+    its own atoms, relative to an ideal sheet of the same areal charge, is
+    -(sigma / 2 eps0) s_eff with
+      s_eff = sqrt(2/pi)/eta - (1/n_b) sum_{G != 0} S_A(G) erfc(|G|/(sqrt2 eta))/|G|,
+    G over the 2D reciprocal lattice of the rectangular cell cx x cy with
+    n_b = 4 basis atoms and S_A(G) = sum_b cos(G.(r_A - r_b)).
+    """
+    basis = np.array([[0, 0], [0, 1 / 3], [0.5, 0.5], [0.5, 5 / 6]]) * [cx, cy]
+    i, j = np.meshgrid(np.arange(-nmax, nmax + 1), np.arange(-nmax, nmax + 1), indexing="ij")
+    G = np.stack([2 * math.pi * i / cx, 2 * math.pi * j / cy], -1).reshape(-1, 2)
+    g = np.linalg.norm(G, axis=1)
+    keep = g > 0
+    G, g = G[keep], g[keep]
+    SA = np.cos((basis[0] - basis) @ G.T).sum(axis=0)
+    from scipy.special import erfc
+    return math.sqrt(2 / math.pi) / eta - np.sum(SA * erfc(g / (math.sqrt(2) * eta)) / g) / 4
+
+
+def empty_charges(w, A, S, dv):
+    return S @ (dv * cpm.drive_vector(w))
+
+
+# --------------------------------------------------------------------------
+# P5 / P6: the empty capacitor
+# --------------------------------------------------------------------------
+
+def test_empty_capacitor_closed_form():
+    """Empty parallel-plate capacitor of Gaussian graphene layers (Eq. 8, 11, 14).
+
+    Doubled cell: Q+ = eps0 A dpsi/(g - s_eff); finite field:
+    Q+ = eps0 A dpsi/(g - s_eff Lz/(Lz - g)).  Every atom of a layer carries
+    the same charge by symmetry.
+    """
+    dv = 2.0
+    w, A, S = built("tiny", "ff")
+    seff = honeycomb_seff(w.box[0] / 6, w.box[1] / 3, w.eta)
+    assert abs(seff - 0.03216) < 5e-6
+    area = w.box[0] * w.box[1]
+    g, lz = 4.34, w.box[2]
+    q = empty_charges(w, A, S, dv)
+    up = w.elec_side > 0
+    qff = EPS0 * area * dv / (g - seff * lz / (lz - g))
+    assert abs(q[up].sum() - qff) < 1e-10 * qff
+    assert np.ptp(q[up]) < 1e-12 * abs(q[up].mean())
+    assert np.ptp(q[~up]) < 1e-12 * abs(q[~up].mean())
+
+    wd, Ad, Sd = built("tiny", "dc")
+    qd = empty_charges(wd, Ad, Sd, dv)
+    qdc = EPS0 * area * dv / (g - seff)
+    for sub in (0, 1):
+        for side in (-1, 1):
+            m = (wd.elec_sub == sub) & (wd.elec_side == side)
+            assert abs(qd[m].sum() - side * qdc) < 1e-10 * qdc
+            assert np.ptp(qd[m]) < 1e-12 * qdc
+    # finite-field / doubled-cell ratio (not 1 for Gaussian electrodes)
+    ratio = (g - seff) / (g - seff * lz / (lz - g))
+    assert abs(q[up].sum() / qd[(wd.elec_sub == 1) & (wd.elec_side > 0)].sum() - ratio) < 1e-9
+
+
+def test_ff_dc_mismatch_shrinks_with_lz():
+    """The FF/DC ratio (g - s)/(g - s Lz/(Lz - g)) tends to 1 as the back region grows."""
+    w0 = workload("tiny", "ff")
+    seff = honeycomb_seff(w0.box[0] / 6, w0.box[1] / 3, w0.eta)
+    g = 4.34
+    prev = None
+    for lz in (6.0, 9.0):
+        w = dataclasses.replace(w0, box=np.array([w0.box[0], w0.box[1], lz])).empty()
+        A, S = cpm.build(w)
+        q = empty_charges(w, A, S, 2.0)[w.elec_side > 0].sum()
+        qdc = EPS0 * w.box[0] * w.box[1] * 2.0 / (g - seff)
+        mismatch = q / qdc - 1.0
+        assert abs(mismatch - ((g - seff) / (g - seff * lz / (lz - g)) - 1)) < 1e-9
+        if prev is not None:
+            assert mismatch < prev
+        prev = mismatch
+
+
+# --------------------------------------------------------------------------
+# P1 / P2 / P7: constraint algebra
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("geometry", ["ff", "dc"])
+def test_kkt_residual_and_neutrality(geometry):
+    """A q* - v lies in span(e) (and e1 for the doubled cell); e.q* = 0 (Eq. 5-7, 12)."""
+    w, A, S = built("tiny", geometry)
+    es = cpm.Electrostatics(w, "ewald")
+    r = cpm.step(w, A, S, es, with_forces=False)
+    q, b, c = r["q"], r["b"], r["c"]
+    v = b + w.dv * c
+    res = A @ q - v
+    basis = [np.ones(w.n_elec)]
+    if geometry == "dc":
+        basis.append(w.elec_sub.astype(float))
+    B = np.stack(basis, 1)
+    coef, *_ = np.linalg.lstsq(B, res, rcond=None)
+    assert np.abs(res - B @ coef).max() < 1e-10 * np.abs(v - v.mean()).max()
+    assert abs(q.sum()) < 1e-12
+    if geometry == "dc":
+        assert abs(q[w.elec_sub == 1].sum()) < 1e-12
+    # S is symmetric, annihilates e (and e1), and is a generalised inverse of A
+    assert np.abs(S - S.T).max() < 1e-14 * np.abs(S).max()
+    assert np.abs(S @ np.ones(w.n_elec)).max() < 1e-13 * np.abs(S).max()
+    assert np.abs(S @ A @ S - S).max() < 1e-10 * np.abs(S).max()
+    P = A @ S
+    assert np.abs(P @ P - P).max() < 1e-10
+    # U_coul identity: 1/2 q.A q = 1/2 q.v at q*
+    assert abs(q @ A @ q - q @ v) < 1e-12 * abs(q @ v)
+
+
+def test_linear_in_dv():
+    """q*(dpsi) = q*(0) + dpsi S c exactly (Eq. 8 and 11 are affine in dpsi)."""
+    w, A, S = built("tiny", "ff")
+    es = cpm.Electrostatics(w, "ewald")
+    q0 = cpm.step(w, A, S, es, dv=0.0, with_forces=False)["q"]
+    for dv in (0.7, 2.0, -1.3):
+        q = cpm.step(w, A, S, es, dv=dv, with_forces=False)["q"]
+        assert np.abs(q - (q0 + dv * S @ cpm.drive_vector(w))).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# P3: invariances
+# --------------------------------------------------------------------------
+
+def test_invariances():
+    w, A, S = built("tiny", "ff")
+    es = cpm.Electrostatics(w, "ewald")
+    r = cpm.step(w, A, S, es)
+    q = r["q"]
+    e = np.ones(w.n_elec)
+    c = cpm.drive_vector(w)
+    # b + const e, A + const e e^T, z -> z + const (drive vector shifts by a multiple of e)
+    assert np.abs(S @ (r["b"] + 3.7 * e + w.dv * c) - q).max() < 1e-13
+    S2 = cpm.projected_inverse(A + 5.0 * np.outer(e, e))
+    assert np.abs(S2 - S).max() < 1e-12 * np.abs(S).max()
+    assert np.abs(S @ (r["b"] + w.dv * (c - 0.25 * e)) - q).max() < 1e-13
+    # lattice translation in x and y of the whole system
+    shift = np.array([0.31, -0.17, 0.0])[:, None]
+    wt = dataclasses.replace(w, elec_xyz=(w.elec_xyz + shift) % w.box[:, None])
+    At, St = cpm.build(wt)
+    rt = cpm.step(wt, At, St, cpm.Electrostatics(wt, "ewald"), site_xyz=(w.site_xyz + shift) % w.box[:, None])
+    assert np.abs(rt["q"] - q).max() < 1e-10
+    assert np.abs(rt["f"] - r["f"]).max() < 1e-9 * np.abs(r["f"]).max()
+    assert abs(rt["u_coul"] - r["u_coul"]) < 1e-10 * abs(r["u_coul"])
+
+
+def test_alpha_independence():
+    """Converged Ewald results do not depend on the splitting parameter."""
+    w, A, S = built("tiny", "ff")
+    res = []
+    for alpha, rcut, kcut in ((2.97, 2.0, 33.0), (4.0, 1.5, 44.0)):
+        wa = dataclasses.replace(w, alpha_exact=alpha, rcut_exact=rcut, kcut_exact=kcut)
+        Aa, Sa = cpm.build(wa)
+        res.append((Aa, cpm.step(wa, Aa, Sa, cpm.Electrostatics(wa, "exact"))))
+    (A1, r1), (A2, r2) = res
+    # A changes by the rank-one constant k_e (pi/V)(1/alpha^2 - 2/eta^2) e e^T
+    vol = np.prod(w.box)
+    const = KE * math.pi / vol * ((1 / 2.97 ** 2 - 1 / 4.0 ** 2))
+    assert np.abs((A1 - A2) - const).max() < 1e-10 * np.abs(A1).max()
+    assert np.abs(r1["q"] - r2["q"]).max() < 1e-11
+    assert np.abs(r1["f"] - r2["f"]).max() < 1e-9 * np.abs(r1["f"]).max()
+    assert abs(r1["u_coul"] - r2["u_coul"]) < 1e-10 * abs(r1["u_coul"])
+
+
+# --------------------------------------------------------------------------
+# P4: brute-force reciprocal sums without splitting
+# --------------------------------------------------------------------------
+
+def _all_k(box, kcut):
+    nmax = [int(kcut * L / (2 * math.pi)) for L in box]
+    n = np.stack(np.meshgrid(*[np.arange(-m, m + 1) for m in nmax], indexing="ij"), -1).reshape(-1, 3)
+    k = 2 * math.pi * n / np.asarray(box)
+    k2 = (k * k).sum(1)
+    keep = (k2 > 0) & (k2 <= kcut ** 2)
+    return k[keep], k2[keep]
+
+
+def test_bruteforce_reciprocal_tiny_cell():
+    """A and b as plain Fourier sums of the Gaussian interactions (no real space).
+
+    Gaussian-Gaussian: (4 pi/V) sum_k exp(-k^2/2eta^2)/k^2 cos(k.r);
+    point-Gaussian:    (4 pi/V) sum_k exp(-k^2/4eta^2)/k^2 cos(k.r).
+    The Ewald A equals this up to k_e (pi/V)(1/alpha^2 - 2/eta^2) e e^T; b is
+    equal outright for a neutral electrolyte.
+    """
+    eta, alpha = 19.79, 2.97
+    box = np.array([0.492, 0.42608, 1.5])
+    rng = np.random.default_rng(7)
+    elec = np.array([[0.0, 0.0, 0.0], [0.0, 0.14203, 0.0], [0.123, 0.21304, 0.0],
+                     [0.123, 0.35507, 0.0], [0.246, 0.0, 0.0], [0.246, 0.14203, 0.0],
+                     [0.369, 0.21304, 0.0], [0.369, 0.35507, 0.0]]).T
+    sites = np.stack([rng.uniform(0, box[0], 4), rng.uniform(0, box[1], 4),
+                      rng.uniform(0.3, 1.2, 4)])
+    sq = np.array([0.78, -0.78, 0.5, -0.5])
+    vol = box.prod()
+    A = ewald.elastance(elec, box, eta, alpha, 2.0, 33.0)
+    k, k2 = _all_k(box, 150.0)
+    ph = k @ elec
+    Ab = KE * 4 * math.pi / vol * (
+        (np.cos(ph) * (np.exp(-k2 / (2 * eta * eta)) / k2)[:, None]).T @ np.cos(ph)
+        + (np.sin(ph) * (np.exp(-k2 / (2 * eta * eta)) / k2)[:, None]).T @ np.sin(ph))
+    const = KE * math.pi / vol * (1 / alpha ** 2 - 2 / eta ** 2)
+    assert np.abs(A - Ab - const).max() < 1e-10 * np.abs(A).max()
+
+    b = ewald.b_vector(elec, sites, sq, box, eta, alpha, 2.0, 33.0)
+    k, k2 = _all_k(box, 210.0)
+    bb = np.zeros(elec.shape[1])
+    wk = KE * 4 * math.pi / vol * np.exp(-k2 / (4 * eta * eta)) / k2
+    for i in range(elec.shape[1]):
+        bb[i] = -np.sum(wk * (np.cos(k @ (elec[:, i:i + 1] - sites)) @ sq))
+    assert np.abs(b - bb).max() < 1e-10 * np.abs(b).max()
+
+
+# --------------------------------------------------------------------------
+# P8 / P12: forces and gradient against finite differences
+# --------------------------------------------------------------------------
+
+def test_forces_match_energy_derivative():
+    """F_j = -dE_cp/dR_j along q*(R) (exact Ewald, central differences, h = 1e-5 nm)."""
+    w, A, S = built("tiny", "ff")
+    es = cpm.Electrostatics(w, "exact")
+    r = cpm.step(w, A, S, es)
+    h = 1e-5
+    fmax = np.abs(r["f"]).max()
+    for j in (0, 17, 63, 99):
+        for d in range(3):
+            xp = w.site_xyz.copy(); xp[d, j] += h
+            xm = w.site_xyz.copy(); xm[d, j] -= h
+            ep = cpm.step(w, A, S, es, site_xyz=xp, with_forces=False)["e_cp"]
+            em = cpm.step(w, A, S, es, site_xyz=xm, with_forces=False)["e_cp"]
+            assert abs(-(ep - em) / (2 * h) - r["f"][d, j]) < 1e-7 * fmax
+
+
+def test_internal_forces_sum_to_zero():
+    """Electrolyte-only Coulomb forces (no electrode charge) conserve momentum."""
+    w = workload("tiny", "ff")
+    f = ewald.coulomb_forces(w.site_xyz, w.site_q, w.elec_xyz, np.zeros(w.n_elec), w.box, w.eta,
+                             w.alpha_exact, w.rcut_exact, w.kcut_exact)
+    assert np.abs(f.sum(axis=1)).max() < 1e-10 * np.abs(f).max()
+
+
+def test_gradient_matches_finite_differences():
+    """d/dR and d/ddpsi of L = sum (q - t)^2 + U_coul by the adjoint (exact Ewald)."""
+    w, A, S = built("tiny", "ff")
+    es = cpm.Electrostatics(w, "exact")
+    t = np.random.default_rng(5).normal(0.0, 0.01, w.n_elec)
+    g = cpm.loss_gradient(w, A, S, es, t)
+
+    def loss(x, dv):
+        r = cpm.step(w, A, S, es, site_xyz=x, dv=dv, with_forces=False)
+        return np.sum((r["q"] - t) ** 2) + r["u_coul"]
+
+    h = 1e-5
+    gmax = np.abs(g["dl_dx"]).max()
+    for j in (3, 50, 91):
+        for d in range(3):
+            xp = w.site_xyz.copy(); xp[d, j] += h
+            xm = w.site_xyz.copy(); xm[d, j] -= h
+            fd = (loss(xp, w.dv) - loss(xm, w.dv)) / (2 * h)
+            assert abs(fd - g["dl_dx"][d, j]) < 1e-7 * gmax
+    fd = (loss(w.site_xyz, w.dv + 1e-4) - loss(w.site_xyz, w.dv - 1e-4)) / 2e-4
+    assert abs(fd - g["dl_ddv"]) < 1e-8 * max(1.0, abs(fd))
+
+
+# --------------------------------------------------------------------------
+# P10: textbook lattice
+# --------------------------------------------------------------------------
+
+def test_rocksalt_madelung_constant():
+    """Point-charge Ewald energy of rock salt gives the Madelung constant 1.747565."""
+    a = 0.5628
+    frac_na = [(0, 0, 0), (0, .5, .5), (.5, 0, .5), (.5, .5, 0)]
+    frac_cl = [(.5, 0, 0), (0, .5, 0), (0, 0, .5), (.5, .5, .5)]
+    xyz = np.array(frac_na + frac_cl).T * a
+    q = np.array([1.0] * 4 + [-1.0] * 4)
+    box = np.array([a, a, a])
+    u = ewald.electrolyte_energy(xyz, q, box, 6.0, 0.95, 70.0)
+    madelung = -u / 4 * (a / 2) / KE
+    assert abs(madelung - 1.747564594633) < 1e-9
+    f = ewald.coulomb_forces(xyz, q, np.zeros((3, 0)), np.zeros(0), box, 19.79, 6.0, 0.95, 70.0)
+    assert np.abs(f).max() < 1e-9
+
+
+# --------------------------------------------------------------------------
+# PPPM pins
+# --------------------------------------------------------------------------
+
+def test_bspline_values_and_partition():
+    # M_5 at the integers: 1/24, 11/24, 11/24, 1/24 (Eulerian numbers / 4!)
+    assert np.allclose(pppm.bspline(5, np.array([1.0, 2.0, 3.0, 4.0])),
+                       np.array([1, 11, 11, 1]) / 24.0, atol=1e-15, rtol=0)
+    u = np.random.default_rng(1).uniform(0, 30, 200)
+    for P in (2, 3, 4, 5, 6, 7):
+        m0 = np.floor(u - P / 2.0) + 1
+        w = np.stack([pppm.bspline(P, u - (m0 + t) + P / 2.0) for t in range(P)])
+        assert np.abs(w.sum(0) - 1).max() < 1e-14
+        # first moment reproduces the position (B-splines are symmetric)
+        assert np.abs((w * (m0 + np.arange(P)[:, None])).sum(0) - u).max() < 1e-12
+
+
+def test_spread_moments_and_constant_interpolation():
+    w = workload("paper", "ff")
+    rho = pppm.spread(w.site_xyz, w.site_q, w.box, w.mesh, w.order)
+    assert abs(rho.sum() - w.site_q.sum()) < 1e-12
+    qabs = np.abs(w.site_q)
+    rho_abs = pppm.spread(w.site_xyz, qabs, w.box, w.mesh, w.order)
+    assert abs(rho_abs.sum() - qabs.sum()) < 1e-10
+    vals = pppm.interpolate(w.elec_xyz, np.full(w.mesh, 2.5), w.box, w.order)
+    assert np.abs(vals - 2.5).max() < 1e-13
+
+
+def test_influence_continuum_limit():
+    """At small k the optimal G is the continuum kernel deconvolved by the assignment.
+
+    Aliases contribute O((kh/2pi)^2P) there, so G(k) U^2(k) -> 4 pi exp(-k^2/4alpha^2)/k^2
+    with U(k) = prod_d sinc(k_d h_d / 2)^P.
+    """
+    box = np.array([3.4, 3.4, 12.625])
+    mesh = (32, 32, 128)
+    h = box / np.array(mesh)
+    G = pppm.influence(box, mesh, 5, 2.21)
+    ns, ks = pppm.mesh_wavevectors(box, mesh)
+    for ix, iy, iz in ((1, 0, 0), (0, 2, 1), (1, 1, 3)):
+        k = np.array([ks[0][ix], ks[1][iy], ks[2][iz]])
+        k2 = k @ k
+        ref = 4 * math.pi * math.exp(-k2 / (4 * 2.21 ** 2)) / k2
+        x = k * h / 2
+        u2 = np.prod(np.where(x == 0, 1.0, np.sin(x) / np.where(x == 0, 1.0, x)) ** 10)
+        assert abs(G[ix, iy, iz] * u2 / ref - 1) < 1e-10
+    # even in k (real-valued potentials)
+    Gm = G[(-np.arange(mesh[0])) % mesh[0]][:, (-np.arange(mesh[1])) % mesh[1]][:, :, (-np.arange(mesh[2])) % mesh[2]]
+    assert np.abs(G - Gm).max() < 1e-14 * np.abs(G).max()
+
+
+def test_pppm_against_exact_ewald():
+    """Discretisation budget: PPPM (order 5, h ~ 0.1 nm) against converged Ewald."""
+    w, A, S = built("tiny", "ff")
+    r1 = cpm.step(w, A, S, cpm.Electrostatics(w, "exact"))
+    r2 = cpm.step(w, A, S, cpm.Electrostatics(w, "pppm"))
+    assert np.abs(r1["q"] - r2["q"]).max() < 2e-5
+    frms = np.sqrt(np.mean((r1["f"] - r2["f"]) ** 2))
+    assert frms / (KE / 0.01) < 1e-5
+    assert abs(r1["u_coul"] - r2["u_coul"]) < 1e-3 * abs(r1["u_coul"])
+
+
+def test_pppm_converges_to_ewald_on_fine_mesh():
+    w, A, S = built("tiny", "ff")
+    wf = dataclasses.replace(w, mesh=(48, 40, 192), order=7, rcut=2.0)
+    b_mesh = cpm.Electrostatics(wf, "pppm").b(w.site_xyz)
+    b_exact = cpm.Electrostatics(w, "exact").b(w.site_xyz)
+    d = b_mesh - b_exact
+    assert np.abs(d - d.mean()).max() < 1e-8 * np.abs(b_exact - b_exact.mean()).max()
+
+
+# --------------------------------------------------------------------------
+# cell binning reference
+# --------------------------------------------------------------------------
+
+def test_cell_binning_is_a_valid_stable_partition():
+    w = workload("paper", "dc")
+    cid, start, order = cells.bin_sites(w.site_xyz, w.box, w.rcut)
+    n = cells.cell_grid(w.box, w.rcut)
+    assert start[-1] == w.n_site and np.all(np.diff(start) >= 0)
+    for c in range(n[0] * n[1] * n[2]):
+        members = order[start[c]:start[c + 1]]
+        assert np.all(np.diff(members) > 0)
+        assert np.all(cid[members] == c)
+    # every site lies inside the box of its cell
+    cz, rem = np.divmod(cid, n[0] * n[1])
+    cy, cx = np.divmod(rem, n[0])
+    for d, cc in enumerate((cx, cy, cz)):
+        x = w.site_xyz[d] % w.box[d]
+        lo = cc * w.box[d] / n[d]
+        hi = (cc + 1) * w.box[d] / n[d]
+        assert np.all(x >= lo - 1e-12) and np.all(x < hi + 1e-12)
