@@ -1,0 +1,174 @@
+/*
+ * cpm.h -- C-ABI of libcpm, the GPU constant-potential electrostatics path.
+ *
+ * Method: Tee & Searles, "Fully Periodic, Computationally Efficient Constant
+ * Potential Molecular Dynamics Simulations of Ionic Liquid Supercapacitors"
+ * (arXiv 2201.12963).  Electrode atoms carry Gaussian charges (Eq. 2); the
+ * Coulomb energy is the quadratic form U = U_elyt - q.b + 1/2 q.A q (Eq. 3);
+ * the electroneutral constant-potential charges are q* = S v with the
+ * projected inverse S = O A^-1 (Eq. 8-9) or O1 O A^-1 for the doubled cell
+ * (Eq. 14-15), and v = b + dV c with c = d (doubled cell) or d - z/Lz
+ * (finite field, Eq. 11 with the lower electrode taken one period up).
+ *
+ * Units: nm, e, V, eV.  Coulomb constant k_e = 1.43996454784 eV nm / e^2.
+ *
+ * Conventions for every call:
+ *  - Arrays are structure-of-arrays, float64, contiguous.  "device" pointers
+ *    are HIP device memory owned by the caller (for instance data_ptr() of a
+ *    contiguous torch tensor); "host" pointers are ordinary host memory.
+ *  - All work is enqueued asynchronously on the stream given to cpm_create
+ *    (or cpm_set_stream).  Nothing blocks unless stated.
+ *  - No exception crosses the ABI.  Every int-returning call returns CPM_OK
+ *    or a negative status; cpm_last_error() then holds a message.
+ *  - A context is not thread-safe.  Calls on one context are ordered by its
+ *    stream; two contexts may run concurrently.
+ *  - Site positions may lie anywhere: every kernel wraps them into the cell.
+ *    Non-finite positions are reported by cpm_sync_status().
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  CPM_OK = 0,
+  CPM_EINVAL = -1,     /* bad descriptor or argument */
+  CPM_ESTATE = -2,     /* call out of order (e.g. solve before build) */
+  CPM_ENOTSPD = -3,    /* elastance matrix not positive definite */
+  CPM_EDEVICE = -4,    /* HIP runtime error */
+  CPM_ENOMEM = -5,     /* device allocation failed / batch too large */
+  CPM_ENONFINITE = -6  /* non-finite input or result */
+};
+
+/* geometry (Sec. II.B of the paper) */
+enum { CPM_FINITE_FIELD = 0, CPM_DOUBLED_CELL = 1 };
+/* reciprocal-space method for the electrolyte sums */
+enum { CPM_KSPACE_EWALD = 0, CPM_KSPACE_PPPM = 1 };
+/* arithmetic of the per-step path: FP64 throughout, or FP32 mesh / FFT /
+ * real space with FP32 accumulation (the elastance build, the inversion,
+ * the neutrality re-projection and the energy sums stay FP64) */
+enum { CPM_FP64 = 0, CPM_MIXED = 1 };
+
+typedef struct cpm_ctx cpm_ctx;
+
+typedef struct {
+  double box[3];        /* Lx, Ly, Lz of the fully periodic cell (nm); doubled cell: the doubled Lz */
+  int geometry;         /* CPM_FINITE_FIELD or CPM_DOUBLED_CELL */
+  int kspace;           /* CPM_KSPACE_EWALD or CPM_KSPACE_PPPM */
+  int precision;        /* CPM_FP64 or CPM_MIXED */
+  double eta;           /* Gaussian width of electrode charges (Eq. 2), 1/nm */
+  double alpha;         /* Ewald splitting of the per-step sums, 1/nm; alpha < eta/sqrt(2) */
+  double rcut;          /* real-space cutoff of the per-step sums, nm */
+  double kcut;          /* EWALD: k-sphere radius, 1/nm (all k != 0 with |k| <= kcut) */
+  int mesh[3];          /* PPPM: mesh points per axis (each a product of 2, 3, 5) */
+  int order;            /* PPPM: B-spline assignment order, 2..7 */
+  /* converged Ewald parameters used once for the elastance matrix A */
+  double alpha_build, rcut_build, kcut_build;
+  int n_elec;           /* number of constant-potential electrode atoms */
+  const double* elec_xyz;        /* host [3][n_elec] */
+  const signed char* elec_side;  /* host [n_elec]: +1 positive, -1 negative electrode (d = side/2) */
+  const unsigned char* elec_sub; /* host [n_elec]: doubled cell, 1 = first sub-cell (e1); NULL for finite field */
+  int n_site;           /* number of electrolyte point charges */
+  const double* site_q; /* host [n_site] charges (e); must sum to zero within 1e-9 */
+} cpm_desc;
+
+/* Create a context: validates the descriptor (alpha < eta/sqrt2, positive
+ * box and cutoffs, mesh factorable, neutral electrolyte, sides +-1,
+ * doubled cell needs elec_sub with both sub-cells non-empty), uploads the
+ * electrodes and prepares the per-step tables (k-vectors or influence
+ * function, electrode spline weights, FFT twiddles, cell lists).
+ * hip_stream may be NULL (the null stream).  *out is NULL on error. */
+int cpm_create(const cpm_desc* desc, void* hip_stream, cpm_ctx** out);
+
+/* Change the stream later calls enqueue on. */
+int cpm_set_stream(cpm_ctx* ctx, void* hip_stream);
+
+/* Once per electrode geometry (Eq. 3, 8-9, 14-15; "precomputed" in
+ * Sec. II.A): builds A in FP64 (Gaussian real-space pairs, k-space as
+ * 2 C C^T with C the sqrt(w)-weighted cos/sin factors, self term), inverts
+ * it, projects S = O A^-1 (and O1 for the doubled cell) and forms S c.
+ * Synchronises the stream.  CPM_ENOTSPD if A is not positive definite. */
+int cpm_build_elastance(cpm_ctx* ctx);
+
+/* One step of the path for one configuration: cell binning, real-space b,
+ * k-space b (Ewald or PPPM), q* = S b + dV S c, k-space and real-space
+ * forces on the sites (plus -Q_j dV/Lz along z for the finite field) and
+ * the energies.
+ *   site_xyz    device [3][n_site]
+ *   dv          potential difference (V)
+ *   q_out       device [n_elec]           electrode charges q*
+ *   f_out       device [3][n_site] or NULL  forces on the sites (eV/nm)
+ *   energy_out  device [2] or NULL          {U_coul, E_cp} (eV): U_coul =
+ *               U_elyt - q.b + 1/2 q.A q; E_cp = U_coul - dV d.q
+ *               (+ dV/Lz (z.q + sum Q_j Z_j) for the finite field), whose
+ *               negative position gradient is f_out.
+ * Repeated calls with identical pointer arguments and dv replay a HIP
+ * graph of the step.  CPM_ESTATE before cpm_build_elastance. */
+int cpm_solve(cpm_ctx* ctx, const double* site_xyz, double dv,
+              double* q_out, double* f_out, double* energy_out);
+
+/* Many frames and potential differences at once (frames independent):
+ *   site_xyz   device [n_frames][3][n_site]
+ *   dv_host    host [n_dv]
+ *   q_out      device [n_frames][n_dv][n_elec]
+ *   f_out      device [n_frames][n_dv][3][n_site] or NULL
+ *   energy_out device [n_frames][n_dv][2] or NULL
+ * The charges of all frames come from one GEMM Q = S B; q and the forces
+ * are affine in dV, so each frame is solved once and the dV sweep is a
+ * rank-one update.  CPM_ENOMEM if the scratch for n_frames does not fit. */
+int cpm_solve_batch(cpm_ctx* ctx, int n_frames, const double* site_xyz,
+                    int n_dv, const double* dv_host,
+                    double* q_out, double* f_out, double* energy_out);
+
+/* Gradient of L = sum_i (q*_i - t_i)^2 + U_coul(R, q*(R)) by the adjoint:
+ * lambda = S [2 (q* - t) + dV c]; dL/dR_j is minus the Coulomb force on
+ * site j with electrode charges q* - lambda; dL/ddV = lambda . c.
+ *   q_target  device [n_elec]
+ *   loss_out  device [1]; dl_dxyz device [3][n_site]; dl_ddv device [1]
+ *   q_out     device [n_elec] or NULL (q* of the forward pass) */
+int cpm_grad(cpm_ctx* ctx, const double* site_xyz, double dv, const double* q_target,
+             double* loss_out, double* dl_dxyz, double* dl_ddv, double* q_out);
+
+/* Copies of internal matrices for tests and checkpoints (synchronises):
+ * which = 0: A, 1: S (projected inverse), 2: S c (n_elec values).
+ * host_out holds n_elec*n_elec (or n_elec) doubles. */
+int cpm_get_matrix(cpm_ctx* ctx, int which, double* host_out);
+
+/* Restore S (and S c) from a host copy instead of building (checkpoint
+ * resume); marks the context built.  host_S [n_elec][n_elec]. */
+int cpm_set_matrix(cpm_ctx* ctx, const double* host_S);
+
+/* Internal per-step buffers of the last cpm_solve, copied to the host
+ * (synchronises).  Returns the element count, or a negative status.
+ * host_out may be NULL to query the count.
+ *   CPM_BUF_CELL_START int32 [n_cells+1]   CPM_BUF_SITE_ORDER int32 [n_site]
+ *   CPM_BUF_PHI_REAL  double [n_elec]  real-space electrolyte potential at electrodes (V)
+ *   CPM_BUF_B         double [n_elec]  the vector b
+ *   CPM_BUF_RHO_MESH  double [Kz][Ky][Kx] electrolyte charge mesh
+ *   CPM_BUF_PHI_MESH  double [Kz][Ky][Kx] electrolyte potential mesh (V)
+ *   CPM_BUF_FIELD_MESH double [3][Kz][Ky][Kx] field of all charges (V/nm)
+ *   CPM_BUF_NCELL     int32 [3]  cells per axis */
+enum {
+  CPM_BUF_CELL_START = 0, CPM_BUF_SITE_ORDER = 1, CPM_BUF_PHI_REAL = 2, CPM_BUF_B = 3,
+  CPM_BUF_RHO_MESH = 4, CPM_BUF_PHI_MESH = 5, CPM_BUF_FIELD_MESH = 6, CPM_BUF_NCELL = 7
+};
+long long cpm_get_buffer(cpm_ctx* ctx, int which, void* host_out);
+
+/* Synchronise the stream and report errors raised inside kernels since the
+ * last call (CPM_ENONFINITE for non-finite positions), then clear them. */
+int cpm_sync_status(cpm_ctx* ctx);
+
+/* Message of the last error on this context (or of the last failed
+ * cpm_create when ctx is NULL).  Never NULL. */
+const char* cpm_last_error(const cpm_ctx* ctx);
+
+/* Free every device allocation and graph of the context.  NULL is a no-op. */
+void cpm_destroy(cpm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPM_H */

@@ -1,0 +1,920 @@
+// C-ABI of libcpm: context set-up, host-side tables, and the orchestration
+// of the per-step kernels (see include/cpm.h for the contract).
+#include "../../include/cpm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace cpm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct GraphEntry {
+  const void* p[6];
+  double dv;
+  int kind;
+  hipGraphExec_t exec;
+  unsigned long long last_use;
+};
+
+}  // namespace
+
+struct cpm_ctx {
+  // ---- descriptor
+  int geometry = 0, kspace = 0, precision = 0;
+  double box[3] = {0, 0, 0};
+  double eta = 0, alpha = 0, rcut = 0, kcut = 0;
+  double alpha_b = 0, rcut_b = 0, kcut_b = 0;
+  int mesh[3] = {0, 0, 0}, order = 0;
+  int n_elec = 0, n_site = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool built = false;
+  bool use_graph = true;
+
+  std::vector<double> hx, hy, hz;          // electrodes (host)
+  std::vector<signed char> side;
+  std::vector<unsigned char> sub;
+  std::vector<double> hq;                  // site charges (host)
+  std::vector<void*> allocs;
+
+  Cell cell{};
+  Cell cell_b{};                           // image counts for the elastance build
+  double self_energy = 0.0;
+
+  // ---- device: electrodes
+  double *d_ex = nullptr, *d_ey = nullptr, *d_ez = nullptr;
+  double *d_c = nullptr, *d_d = nullptr, *d_ze = nullptr, *d_e1 = nullptr;
+  double *d_A = nullptr, *d_S = nullptr, *d_Sc = nullptr;
+  float* d_Sf = nullptr;
+  ElecSet<double> el{};
+  ElecSet<float> elf{};
+  double* d_site_q = nullptr;
+
+  // ---- per-step buffers (capacity cap_frames)
+  int cap_frames = 0;
+  int *d_cell_start = nullptr, *d_order = nullptr, *d_status = nullptr;
+  double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
+  float *d_fx = nullptr, *d_fy = nullptr, *d_fz = nullptr, *d_fq = nullptr;
+  double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
+  double *d_ek = nullptr, *d_ftmp = nullptr, *d_energy_tmp = nullptr, *d_lam = nullptr, *d_scalar = nullptr;
+  double* d_phir = nullptr;
+  float* d_phirf = nullptr;
+  int n_ek = 0;
+
+  // ---- PPPM
+  MeshInfo mi{};
+  FFTPlan1D px{}, py{}, pz{};
+  ZPassArgs za_pot{}, za_field{};
+  double *d_G = nullptr, *d_rho = nullptr, *d_phi = nullptr, *d_E = nullptr, *d_rho_e = nullptr;
+  double2 *d_c1 = nullptr, *d_c2 = nullptr, *d_save = nullptr;
+  float *d_Gf = nullptr, *d_rhof = nullptr, *d_phif = nullptr, *d_Ef = nullptr, *d_rho_ef = nullptr;
+  float2 *d_c1f = nullptr, *d_c2f = nullptr, *d_savef = nullptr;
+  int *d_gidx = nullptr, *d_touch = nullptr, *d_rowptr = nullptr, *d_col = nullptr;
+  double *d_gw = nullptr, *d_val = nullptr;
+  float *d_gwf = nullptr, *d_valf = nullptr;
+  int n_touch = 0, P3 = 0;
+
+  // ---- explicit Ewald
+  int nk = 0;
+  double *d_kv = nullptr, *d_ew = nullptr, *d_Esite = nullptr;
+  double2 *d_eph = nullptr, *d_rhok = nullptr, *d_rhok_all = nullptr;
+
+  // ---- graphs
+  std::vector<GraphEntry> graphs;
+  unsigned long long tick = 0;
+};
+
+namespace {
+
+int fail(cpm_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf; else g_create_error = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, CPM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+int dalloc(cpm_ctx* c, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) return fail(c, CPM_ENOMEM, "hipMalloc of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
+  c->allocs.push_back(*p);
+  return CPM_OK;
+}
+
+template <typename T>
+int upload(cpm_ctx* c, T** p, const std::vector<T>& h) {
+  int r = dalloc(c, p, h.size());
+  if (r) return r;
+  if (!h.empty()) HIP_TRY(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return CPM_OK;
+}
+
+#define TRY(expr) do { int r_ = (expr); if (r_ != CPM_OK) return r_; } while (0)
+
+bool factorize(int n, FFTPlan1D& p) {
+  p.n = n;
+  p.nfac = 0;
+  int m = n;
+  while (m % 4 == 0) { p.fac[p.nfac++] = 4; m /= 4; if (p.nfac >= MAX_FFT_FACTORS) return false; }
+  while (m % 2 == 0) { p.fac[p.nfac++] = 2; m /= 2; if (p.nfac >= MAX_FFT_FACTORS) return false; }
+  while (m % 3 == 0) { p.fac[p.nfac++] = 3; m /= 3; if (p.nfac >= MAX_FFT_FACTORS) return false; }
+  while (m % 5 == 0) { p.fac[p.nfac++] = 5; m /= 5; if (p.nfac >= MAX_FFT_FACTORS) return false; }
+  return m == 1;
+}
+
+// cardinal B-spline M_P(x) on [0, P] (Cox-de Boor recursion)
+double bspline_host(int P, double x) {
+  if (P == 1) return (x >= 0.0 && x < 1.0) ? 1.0 : 0.0;
+  return (x * bspline_host(P - 1, x) + (P - x) * bspline_host(P - 1, x - 1.0)) / (P - 1);
+}
+
+int cell_coord_host(double x, double L, int n) {
+  double t = x / L;
+  double f = t - std::floor(t);
+  int c = (int)std::floor(f * (double)n);
+  return c < n - 1 ? c : n - 1;
+}
+
+double wrap_host(double x, double L) { return x - L * std::floor(x / L); }
+
+// half-space k-vectors with 0 < |k| <= kcut: (n1 > 0) or (n1 == 0, n2 > 0) or (n1 == n2 == 0, n3 > 0)
+void half_kvectors(const double* box, double kcut, std::vector<double>& kx, std::vector<double>& ky,
+                   std::vector<double>& kz) {
+  int nmax[3];
+  for (int d = 0; d < 3; ++d) nmax[d] = (int)std::floor(kcut * box[d] / (2 * M_PI));
+  for (int a = 0; a <= nmax[0]; ++a)
+    for (int b = -nmax[1]; b <= nmax[1]; ++b)
+      for (int c = -nmax[2]; c <= nmax[2]; ++c) {
+        if (a == 0 && (b < 0 || (b == 0 && c <= 0))) continue;
+        double k0 = 2 * M_PI * a / box[0], k1 = 2 * M_PI * b / box[1], k2 = 2 * M_PI * c / box[2];
+        double kk = k0 * k0 + k1 * k1 + k2 * k2;
+        if (kk > kcut * kcut) continue;
+        kx.push_back(k0); ky.push_back(k1); kz.push_back(k2);
+      }
+}
+
+double kweight_host(double k2, double alpha, double vol) {
+  return 4 * M_PI / vol * std::exp(-k2 / (4 * alpha * alpha)) / k2;
+}
+
+// Hockney-Eastwood optimal influence function for ik differentiation, times
+// k_e / V so that the unnormalised inverse transform gives volts.  Layout
+// [kz][ky][kx].  Aliases per axis: every m with |n + m K| <= 2.5 K.
+void influence_host(const double* box, const int* K, int P, double alpha, std::vector<double>& G) {
+  const double vol = box[0] * box[1] * box[2];
+  const int M = K[0] * K[1] * K[2];
+  G.assign(M, 0.0);
+  // per axis and index: alias wavevectors and U^2 factors
+  std::vector<std::vector<double>> ka[3], u2[3];
+  std::vector<double> kb[3];
+  for (int d = 0; d < 3; ++d) {
+    double h = box[d] / K[d];
+    ka[d].resize(K[d]);
+    u2[d].resize(K[d]);
+    kb[d].resize(K[d]);
+    for (int i = 0; i < K[d]; ++i) {
+      int n = (i < (K[d] + 1) / 2) ? i : i - K[d];
+      kb[d][i] = 2 * M_PI * n / box[d];
+      for (int m = -3; m <= 3; ++m) {
+        int nm = n + m * K[d];
+        if (std::abs((double)nm) > 2.5 * K[d]) continue;
+        double k = 2 * M_PI * nm / box[d];
+        double x = k * h / 2;
+        double sinc = (x == 0.0) ? 1.0 : std::sin(x) / x;
+        ka[d][i].push_back(k);
+        u2[d][i].push_back(std::pow(sinc, 2 * P));
+      }
+    }
+  }
+  for (int iz = 0; iz < K[2]; ++iz)
+    for (int iy = 0; iy < K[1]; ++iy)
+      for (int ix = 0; ix < K[0]; ++ix) {
+        double k0 = kb[0][ix], k1 = kb[1][iy], k2 = kb[2][iz];
+        double kk = k0 * k0 + k1 * k1 + k2 * k2;
+        if (kk == 0.0) continue;
+        double num = 0.0, den = 0.0;
+        for (size_t a = 0; a < ka[0][ix].size(); ++a)
+          for (size_t b = 0; b < ka[1][iy].size(); ++b)
+            for (size_t c = 0; c < ka[2][iz].size(); ++c) {
+              double qx = ka[0][ix][a], qy = ka[1][iy][b], qz = ka[2][iz][c];
+              double U2 = u2[0][ix][a] * u2[1][iy][b] * u2[2][iz][c];
+              double q2 = qx * qx + qy * qy + qz * qz;
+              den += U2;
+              if (q2 == 0.0) continue;
+              double R = 4 * M_PI * std::exp(-q2 / (4 * alpha * alpha)) / q2;
+              num += U2 * (k0 * qx + k1 * qy + k2 * qz) * R;
+            }
+        G[((size_t)iz * K[1] + iy) * K[0] + ix] = KE / vol * num / (kk * den * den);
+      }
+}
+
+void free_graphs(cpm_ctx* c) {
+  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+// --------------------------------------------------------------- buffers
+
+int alloc_frames(cpm_ctx* c, int nf) {
+  if (nf <= c->cap_frames) return CPM_OK;
+  // release the previous per-frame buffers by reallocating fresh ones; old
+  // pointers stay in allocs and are freed at destroy (graphs referring to them
+  // are dropped)
+  free_graphs(c);
+  const int ns = c->n_site, ne = c->n_elec, ncl = c->cell.n_cells;
+  const bool mixed = c->precision == CPM_MIXED;
+  TRY(dalloc(c, &c->d_cell_start, (size_t)nf * (ncl + 1)));
+  TRY(dalloc(c, &c->d_order, (size_t)nf * ns));
+  TRY(dalloc(c, &c->d_sx, (size_t)nf * ns));
+  TRY(dalloc(c, &c->d_sy, (size_t)nf * ns));
+  TRY(dalloc(c, &c->d_sz, (size_t)nf * ns));
+  TRY(dalloc(c, &c->d_sq, (size_t)nf * ns));
+  if (mixed) {
+    TRY(dalloc(c, &c->d_fx, (size_t)nf * ns));
+    TRY(dalloc(c, &c->d_fy, (size_t)nf * ns));
+    TRY(dalloc(c, &c->d_fz, (size_t)nf * ns));
+    TRY(dalloc(c, &c->d_fq, (size_t)nf * ns));
+    TRY(dalloc(c, &c->d_phirf, (size_t)nf * ne));
+  }
+  TRY(dalloc(c, &c->d_phir, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_zdip, (size_t)nf));
+  TRY(dalloc(c, &c->d_b, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_Q0, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_qint, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_lam, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_usite, (size_t)nf * ns));
+  TRY(dalloc(c, &c->d_ftmp, (size_t)nf * 3 * ns));
+  TRY(dalloc(c, &c->d_energy_tmp, (size_t)nf * 2));
+  if (c->kspace == CPM_KSPACE_PPPM) {
+    const size_t M = c->mi.M;
+    c->n_ek = c->za_pot.Ky * c->za_pot.nchunk;
+    TRY(dalloc(c, &c->d_ek, (size_t)nf * c->n_ek));
+    if (!mixed) {
+      TRY(dalloc(c, &c->d_rho, nf * M));
+      TRY(dalloc(c, &c->d_phi, nf * M));
+      TRY(dalloc(c, &c->d_E, nf * 3 * M));
+      TRY(dalloc(c, &c->d_rho_e, nf * M));
+      TRY(dalloc(c, &c->d_c1, nf * M));
+      TRY(dalloc(c, &c->d_c2, nf * M));
+      TRY(dalloc(c, &c->d_save, nf * M));
+      HIP_TRY(c, hipMemset(c->d_rho_e, 0, nf * M * sizeof(double)));
+    } else {
+      TRY(dalloc(c, &c->d_rhof, nf * M));
+      TRY(dalloc(c, &c->d_phif, nf * M));
+      TRY(dalloc(c, &c->d_Ef, nf * 3 * M));
+      TRY(dalloc(c, &c->d_rho_ef, nf * M));
+      TRY(dalloc(c, &c->d_c1f, nf * M));
+      TRY(dalloc(c, &c->d_c2f, nf * M));
+      TRY(dalloc(c, &c->d_savef, nf * M));
+      HIP_TRY(c, hipMemset(c->d_rho_ef, 0, nf * M * sizeof(float)));
+    }
+  } else {
+    c->n_ek = c->nk;
+    TRY(dalloc(c, &c->d_ek, (size_t)nf * c->nk));
+    TRY(dalloc(c, &c->d_rhok, (size_t)nf * c->nk));
+    TRY(dalloc(c, &c->d_rhok_all, (size_t)nf * c->nk));
+    TRY(dalloc(c, &c->d_Esite, (size_t)nf * 3 * ns));
+  }
+  HIP_TRY(c, hipDeviceSynchronize());
+  c->cap_frames = nf;
+  return CPM_OK;
+}
+
+// ------------------------------------------------------------ the step
+
+template <typename T> struct Bufs;
+template <> struct Bufs<double> {
+  using T2 = double2;
+  static SiteSet<double> sites(cpm_ctx* c) {
+    return SiteSet<double>{c->d_sx, c->d_sy, c->d_sz, c->d_sq, c->d_order, c->d_cell_start, c->n_site};
+  }
+  static const ElecSet<double>& elec(cpm_ctx* c) { return c->el; }
+  static double* phir(cpm_ctx* c) { return c->d_phir; }
+  static double* rho(cpm_ctx* c) { return c->d_rho; }
+  static double* phi(cpm_ctx* c) { return c->d_phi; }
+  static double* E(cpm_ctx* c) { return c->d_E; }
+  static double* rho_e(cpm_ctx* c) { return c->d_rho_e; }
+  static double2* c1(cpm_ctx* c) { return c->d_c1; }
+  static double2* c2(cpm_ctx* c) { return c->d_c2; }
+  static double2* save(cpm_ctx* c) { return c->d_save; }
+  static const double* G(cpm_ctx* c) { return c->d_G; }
+  static const double* gw(cpm_ctx* c) { return c->d_gw; }
+  static const double* val(cpm_ctx* c) { return c->d_val; }
+};
+template <> struct Bufs<float> {
+  using T2 = float2;
+  static SiteSet<float> sites(cpm_ctx* c) {
+    return SiteSet<float>{c->d_fx, c->d_fy, c->d_fz, c->d_fq, c->d_order, c->d_cell_start, c->n_site};
+  }
+  static const ElecSet<float>& elec(cpm_ctx* c) { return c->elf; }
+  static float* phir(cpm_ctx* c) { return c->d_phirf; }
+  static float* rho(cpm_ctx* c) { return c->d_rhof; }
+  static float* phi(cpm_ctx* c) { return c->d_phif; }
+  static float* E(cpm_ctx* c) { return c->d_Ef; }
+  static float* rho_e(cpm_ctx* c) { return c->d_rho_ef; }
+  static float2* c1(cpm_ctx* c) { return c->d_c1f; }
+  static float2* c2(cpm_ctx* c) { return c->d_c2f; }
+  static float2* save(cpm_ctx* c) { return c->d_savef; }
+  static const float* G(cpm_ctx* c) { return c->d_Gf; }
+  static const float* gw(cpm_ctx* c) { return c->d_gwf; }
+  static const float* val(cpm_ctx* c) { return c->d_valf; }
+};
+
+// Stage 1: positions -> binned sites -> b (frames 0..nf-1)
+template <typename T>
+void enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool keep_spectrum) {
+  using B = Bufs<T>;
+  using T2 = typename B::T2;
+  hipStream_t s = c->stream;
+  const bool mixed = std::is_same<T, float>::value;
+  launch_bin_sites(s, nf, c->n_site, xyz, (size_t)3 * c->n_site, c->d_site_q, c->cell, c->d_cell_start, c->d_order,
+                   c->d_sx, c->d_sy, c->d_sz, c->d_sq, mixed ? c->d_fx : nullptr, mixed ? c->d_fy : nullptr,
+                   mixed ? c->d_fz : nullptr, mixed ? c->d_fq : nullptr, c->d_zdip, c->d_status,
+                   (c->kspace == CPM_KSPACE_PPPM && !mixed) ? c->d_rho : nullptr, c->mi.M,
+                   (c->kspace == CPM_KSPACE_PPPM && mixed) ? c->d_rhof : nullptr);
+  SiteSet<T> st = B::sites(c);
+  launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c));
+  if (c->kspace == CPM_KSPACE_PPPM) {
+    launch_spread_sites_t<T>(s, nf, c->mi, st, B::rho(c));
+    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho(c), nullptr, B::c1(c), nullptr, nullptr);
+    launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr, keep_spectrum ? B::save(c) : nullptr,
+                          0, c->d_ek);
+    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
+    launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b);
+  } else {
+    SiteSet<double> sd = Bufs<double>::sites(c);
+    launch_ewald_sf(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok, c->d_ek);
+    launch_ewald_phi(s, nf, c->nk, c->n_elec, c->d_ew, c->d_eph, c->d_rhok, c->d_phir, c->d_b);
+  }
+}
+
+// Stage 3: Coulomb forces on the sites for electrode charges qa (+ optional
+// second set qb on a shared field mesh Eb), plus real-space energies
+template <typename T>
+void enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, ForceArgs<T> fa) {
+  using B = Bufs<T>;
+  using T2 = typename B::T2;
+  hipStream_t s = c->stream;
+  SiteSet<T> st = B::sites(c);
+  fa.alpha = (T)c->alpha;
+  fa.eta = (T)c->eta;
+  fa.rc2 = (T)(c->rcut * c->rcut);
+  fa.qa = qa;
+  fa.qa_frame_stride = qa_stride;
+  fa.mi = c->mi;
+  if (c->kspace == CPM_KSPACE_PPPM) {
+    launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
+                            B::rho_e(c), c->mi.M);
+    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
+    launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr);
+    // c1 -> Ex (re), Ey (im); c2 -> Ez
+    T* E = B::E(c);
+    const size_t M = c->mi.M;
+    // field meshes are [frame][3][M]
+    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, E, E + M, 3 * M);
+    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c2(c), nullptr, E + 2 * M, nullptr,
+                           3 * M);
+    fa.Ea = E;
+    fa.Ea_frame_stride = 3 * M;
+    fa.Esite = nullptr;
+  } else {
+    SiteSet<double> sd = Bufs<double>::sites(c);
+    launch_ewald_rho_all(s, nf, c->nk, c->n_elec, c->d_eph, qa, qa_stride, c->d_rhok, c->d_rhok_all);
+    launch_ewald_field(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok_all, c->d_Esite);
+    fa.Ea = nullptr;
+    fa.Esite = c->d_Esite;
+  }
+  launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa);
+}
+
+template <typename T>
+int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, double* f_out, double* e_out) {
+  hipStream_t s = c->stream;
+  const bool need_forces = f_out || e_out;
+  enqueue_b<T>(c, 1, xyz, need_forces);
+  launch_charges(s, 1, c->n_elec, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q_out);
+  if (need_forces) {
+    ForceArgs<T> fa{};
+    fa.out_scale = 1.0;
+    fa.field = (c->geometry == CPM_FINITE_FIELD) ? -dv / c->box[2] : 0.0;
+    fa.f_out = f_out ? f_out : c->d_ftmp;
+    fa.f_frame_stride = 3 * (size_t)c->n_site;
+    fa.n_dv = 1;
+    fa.dv = nullptr;
+    fa.u_site = c->d_usite;
+    enqueue_forces<T>(c, 1, q_out, c->n_elec, fa);
+  }
+  if (e_out) {
+    EnergyArgs ea{};
+    ea.n_elec = c->n_elec; ea.n_site = c->n_site; ea.n_ek = c->n_ek;
+    ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
+    ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
+    ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
+    ea.n_dv = 1; ea.dv = nullptr; ea.dv_single = dv; ea.out = e_out;
+    launch_energy(s, 1, ea);
+  }
+  return CPM_OK;
+}
+
+int check_launch(cpm_ctx* c) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, CPM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return CPM_OK;
+}
+
+}  // namespace
+
+// =================================================================== C-ABI
+
+extern "C" {
+
+int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
+  if (out) *out = nullptr;
+  if (!d || !out) return fail(nullptr, CPM_EINVAL, "null descriptor or output pointer");
+  for (int k = 0; k < 3; ++k)
+    if (!(d->box[k] > 0.0) || !std::isfinite(d->box[k])) return fail(nullptr, CPM_EINVAL, "box lengths must be positive");
+  if (d->geometry != CPM_FINITE_FIELD && d->geometry != CPM_DOUBLED_CELL)
+    return fail(nullptr, CPM_EINVAL, "unknown geometry %d", d->geometry);
+  if (d->kspace != CPM_KSPACE_EWALD && d->kspace != CPM_KSPACE_PPPM)
+    return fail(nullptr, CPM_EINVAL, "unknown kspace %d", d->kspace);
+  if (d->precision != CPM_FP64 && d->precision != CPM_MIXED)
+    return fail(nullptr, CPM_EINVAL, "unknown precision %d", d->precision);
+  if (d->precision == CPM_MIXED && d->kspace != CPM_KSPACE_PPPM)
+    return fail(nullptr, CPM_EINVAL, "mixed precision needs the PPPM k-space");
+  if (!(d->eta > 0) || !(d->alpha > 0) || !(d->rcut > 0))
+    return fail(nullptr, CPM_EINVAL, "eta, alpha and rcut must be positive");
+  if (!(d->alpha < d->eta / std::sqrt(2.0)) || !(d->alpha_build < d->eta / std::sqrt(2.0)))
+    return fail(nullptr, CPM_EINVAL, "alpha must be below eta/sqrt(2) (A would not be positive definite)");
+  if (!(d->alpha_build > 0) || !(d->rcut_build > 0) || !(d->kcut_build > 0))
+    return fail(nullptr, CPM_EINVAL, "elastance build parameters must be positive");
+  if (d->n_elec < 2 || !d->elec_xyz || !d->elec_side) return fail(nullptr, CPM_EINVAL, "need >= 2 electrode atoms");
+  if (d->n_site < 0 || (d->n_site > 0 && !d->site_q)) return fail(nullptr, CPM_EINVAL, "bad site charges");
+  if (d->kspace == CPM_KSPACE_EWALD && !(d->kcut > 0)) return fail(nullptr, CPM_EINVAL, "EWALD needs kcut > 0");
+  if (d->kspace == CPM_KSPACE_PPPM && (d->order < 2 || d->order > MAX_ORDER))
+    return fail(nullptr, CPM_EINVAL, "PPPM order must be 2..%d", MAX_ORDER);
+  if (d->geometry == CPM_DOUBLED_CELL && !d->elec_sub) return fail(nullptr, CPM_EINVAL, "doubled cell needs elec_sub");
+  double qsum = 0.0, qabs = 0.0;
+  for (int j = 0; j < d->n_site; ++j) {
+    if (!std::isfinite(d->site_q[j])) return fail(nullptr, CPM_ENONFINITE, "non-finite site charge");
+    qsum += d->site_q[j];
+    qabs += std::fabs(d->site_q[j]);
+  }
+  if (std::fabs(qsum) > 1e-9 * std::max(1.0, qabs)) return fail(nullptr, CPM_EINVAL, "electrolyte is not neutral (sum %g)", qsum);
+  int n1 = 0, npos = 0;
+  for (int i = 0; i < d->n_elec; ++i) {
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(d->elec_xyz[k * d->n_elec + i])) return fail(nullptr, CPM_ENONFINITE, "non-finite electrode position");
+    if (d->elec_side[i] != 1 && d->elec_side[i] != -1) return fail(nullptr, CPM_EINVAL, "elec_side must be +1 or -1");
+    npos += d->elec_side[i] > 0;
+    if (d->geometry == CPM_DOUBLED_CELL) n1 += d->elec_sub[i] != 0;
+  }
+  if (npos == 0 || npos == d->n_elec) return fail(nullptr, CPM_EINVAL, "need atoms on both electrodes");
+  if (d->geometry == CPM_DOUBLED_CELL && (n1 == 0 || n1 == d->n_elec))
+    return fail(nullptr, CPM_EINVAL, "doubled cell needs atoms in both sub-cells");
+
+  cpm_ctx* c = new cpm_ctx();
+  c->geometry = d->geometry; c->kspace = d->kspace; c->precision = d->precision;
+  for (int k = 0; k < 3; ++k) { c->box[k] = d->box[k]; c->mesh[k] = d->mesh[k]; }
+  c->eta = d->eta; c->alpha = d->alpha; c->rcut = d->rcut; c->kcut = d->kcut;
+  c->alpha_b = d->alpha_build; c->rcut_b = d->rcut_build; c->kcut_b = d->kcut_build;
+  c->order = d->order;
+  c->n_elec = d->n_elec; c->n_site = d->n_site;
+  c->stream = (hipStream_t)hip_stream;
+  c->use_graph = hip_stream != nullptr && std::getenv("CPM_NO_GRAPH") == nullptr;
+  const int ne = c->n_elec, ns = c->n_site;
+  c->hx.assign(d->elec_xyz, d->elec_xyz + ne);
+  c->hy.assign(d->elec_xyz + ne, d->elec_xyz + 2 * ne);
+  c->hz.assign(d->elec_xyz + 2 * ne, d->elec_xyz + 3 * ne);
+  c->side.assign(d->elec_side, d->elec_side + ne);
+  if (d->geometry == CPM_DOUBLED_CELL) c->sub.assign(d->elec_sub, d->elec_sub + ne);
+  c->hq.assign(d->site_q, d->site_q + ns);
+
+  auto bad = [&](int code) { std::string e = c->err; cpm_destroy(c); g_create_error = e; return code; };
+  int r;
+
+  // cells
+  Cell& cl = c->cell;
+  cl.n_cells = 1;
+  for (int k = 0; k < 3; ++k) {
+    cl.L[k] = c->box[k];
+    cl.invL[k] = 1.0 / c->box[k];
+    cl.nc[k] = std::max(1, (int)std::floor(c->box[k] / c->rcut));
+    cl.img[k] = (int)std::floor(c->rcut / c->box[k] + 0.5);
+    cl.n_cells *= cl.nc[k];
+  }
+  c->cell_b = cl;
+  for (int k = 0; k < 3; ++k) c->cell_b.img[k] = (int)std::floor(c->rcut_b / c->box[k] + 0.5);
+  if (bin_lds_bytes(ns, cl.n_cells) > 150 * 1024) {
+    fail(c, CPM_EINVAL, "%d sites in %d cells exceed the single-workgroup binning limit", ns, cl.n_cells);
+    return bad(CPM_EINVAL);
+  }
+  double q2 = 0.0;
+  for (double q : c->hq) q2 += q * q;
+  c->self_energy = KE * c->alpha / std::sqrt(M_PI) * q2;
+
+  // electrodes in original order and cell-sorted
+  std::vector<double> dd(ne), ze(ne), cc(ne), e1(ne, 0.0);
+  for (int i = 0; i < ne; ++i) {
+    dd[i] = 0.5 * c->side[i];
+    ze[i] = wrap_host(c->hz[i], c->box[2]);
+    cc[i] = (c->geometry == CPM_DOUBLED_CELL) ? dd[i] : dd[i] - ze[i] / c->box[2];
+    if (c->geometry == CPM_DOUBLED_CELL) e1[i] = c->sub[i] ? 1.0 : 0.0;
+  }
+  std::vector<int> ecell(ne), eorder(ne);
+  for (int i = 0; i < ne; ++i)
+    ecell[i] = (cell_coord_host(c->hz[i], cl.L[2], cl.nc[2]) * cl.nc[1] + cell_coord_host(c->hy[i], cl.L[1], cl.nc[1])) *
+                   cl.nc[0] + cell_coord_host(c->hx[i], cl.L[0], cl.nc[0]);
+  for (int i = 0; i < ne; ++i) eorder[i] = i;
+  std::stable_sort(eorder.begin(), eorder.end(), [&](int a, int b) { return ecell[a] < ecell[b]; });
+  std::vector<int> ecs(cl.n_cells + 1, 0), ecell_sorted(ne);
+  std::vector<double> sxe(ne), sye(ne), sze(ne);
+  std::vector<float> sxf(ne), syf(ne), szf(ne);
+  for (int k = 0; k < ne; ++k) {
+    int i = eorder[k];
+    ecs[ecell[i] + 1]++;
+    ecell_sorted[k] = ecell[i];
+    sxe[k] = wrap_host(c->hx[i], c->box[0]);
+    sye[k] = wrap_host(c->hy[i], c->box[1]);
+    sze[k] = wrap_host(c->hz[i], c->box[2]);
+    sxf[k] = (float)sxe[k]; syf[k] = (float)sye[k]; szf[k] = (float)sze[k];
+  }
+  for (int k = 0; k < cl.n_cells; ++k) ecs[k + 1] += ecs[k];
+  if ((r = upload(c, &c->d_ex, c->hx)) || (r = upload(c, &c->d_ey, c->hy)) || (r = upload(c, &c->d_ez, c->hz)) ||
+      (r = upload(c, &c->d_c, cc)) || (r = upload(c, &c->d_d, dd)) || (r = upload(c, &c->d_ze, ze)) ||
+      (r = upload(c, &c->d_e1, e1)) || (r = upload(c, &c->d_site_q, c->hq)))
+    return bad(r);
+  {
+    double *x, *y, *z; float *xf, *yf, *zf; int *o, *ce, *cs;
+    if ((r = upload(c, &x, sxe)) || (r = upload(c, &y, sye)) || (r = upload(c, &z, sze)) ||
+        (r = upload(c, &xf, sxf)) || (r = upload(c, &yf, syf)) || (r = upload(c, &zf, szf)) ||
+        (r = upload(c, &o, eorder)) || (r = upload(c, &ce, ecell_sorted)) || (r = upload(c, &cs, ecs)))
+      return bad(r);
+    c->el = ElecSet<double>{x, y, z, o, ce, cs, ne};
+    c->elf = ElecSet<float>{xf, yf, zf, o, ce, cs, ne};
+  }
+  if ((r = dalloc(c, &c->d_A, (size_t)ne * ne)) || (r = dalloc(c, &c->d_S, (size_t)ne * ne)) ||
+      (r = dalloc(c, &c->d_Sc, ne)) || (r = dalloc(c, &c->d_status, 4)) || (r = dalloc(c, &c->d_scalar, 8)))
+    return bad(r);
+  if (c->precision == CPM_MIXED && (r = dalloc(c, &c->d_Sf, (size_t)ne * ne))) return bad(r);
+  if (hipMemset(c->d_status, 0, 4 * sizeof(int)) != hipSuccess) { fail(c, CPM_EDEVICE, "memset"); return bad(CPM_EDEVICE); }
+
+  if (c->kspace == CPM_KSPACE_PPPM) {
+    MeshInfo& mi = c->mi;
+    for (int k = 0; k < 3; ++k) {
+      if (c->mesh[k] < 2) { fail(c, CPM_EINVAL, "mesh must have >= 2 points per axis"); return bad(CPM_EINVAL); }
+      mi.K[k] = c->mesh[k];
+      mi.h[k] = c->box[k] / mi.K[k];
+      mi.invh[k] = mi.K[k] / c->box[k];
+    }
+    mi.M = mi.K[0] * mi.K[1] * mi.K[2];
+    mi.order = c->order;
+    c->P3 = c->order * c->order * c->order;
+    FFTPlan1D* plans[3] = {&c->px, &c->py, &c->pz};
+    for (int k = 0; k < 3; ++k) {
+      if (!factorize(mi.K[k], *plans[k])) {
+        fail(c, CPM_EINVAL, "mesh size %d is not a product of 2, 3 and 5", mi.K[k]);
+        return bad(CPM_EINVAL);
+      }
+      std::vector<double2> tw(mi.K[k]);
+      std::vector<float2> twf(mi.K[k]);
+      for (int t = 0; t < mi.K[k]; ++t) {
+        double a = -2 * M_PI * t / mi.K[k];
+        tw[t] = double2{std::cos(a), std::sin(a)};
+        twf[t] = float2{(float)tw[t].x, (float)tw[t].y};
+      }
+      double2* dt; float2* dtf;
+      if ((r = upload(c, &dt, tw)) || (r = upload(c, &dtf, twf))) return bad(r);
+      plans[k]->tw = dt;
+      plans[k]->twf = dtf;
+    }
+    const size_t elt = c->precision == CPM_MIXED ? sizeof(float2) : sizeof(double2);
+    if ((size_t)2 * mi.K[0] * mi.K[1] * elt > 150 * 1024) {
+      fail(c, CPM_EINVAL, "x-y mesh plane too large for LDS");
+      return bad(CPM_EINVAL);
+    }
+    // z pass: columns per workgroup bounded by LDS (3 buffers) and chosen so
+    // that there are at least ~64 workgroups per frame
+    int maxc = (int)std::max<size_t>(1, (96 * 1024) / (3 * mi.K[2] * elt));
+    int nchunk = std::max((mi.K[0] + maxc - 1) / maxc, (64 + mi.K[1] - 1) / mi.K[1]);
+    nchunk = std::min(nchunk, mi.K[0]);
+    int nxc = (mi.K[0] + nchunk - 1) / nchunk;
+    nchunk = (mi.K[0] + nxc - 1) / nxc;
+    ZPassArgs za{};
+    za.Kx = mi.K[0]; za.Ky = mi.K[1]; za.Kz = mi.K[2];
+    za.nxc = nxc; za.nchunk = nchunk;
+    for (int k = 0; k < 3; ++k) za.twopi_L[k] = 2 * M_PI / c->box[k];
+    za.mode = 0;
+    c->za_pot = za;
+    za.mode = 1;
+    c->za_field = za;
+    std::vector<double> G;
+    influence_host(c->box, mi.K, c->order, c->alpha, G);
+    std::vector<float> Gf(G.begin(), G.end());
+    if ((r = upload(c, &c->d_G, G)) || (r = upload(c, &c->d_Gf, Gf))) return bad(r);
+    // electrode stencils (original order) and their transpose by mesh point
+    const int P = c->order, P3 = c->P3;
+    std::vector<int> gidx((size_t)ne * P3);
+    std::vector<double> gw((size_t)ne * P3);
+    const double* pos[3] = {c->hx.data(), c->hy.data(), c->hz.data()};
+    for (int i = 0; i < ne; ++i) {
+      int first[3];
+      double w[3][MAX_ORDER];
+      for (int k = 0; k < 3; ++k) {
+        double u = wrap_host(pos[k][i], c->box[k]) * mi.invh[k];
+        first[k] = (int)std::floor(u - P / 2.0) + 1;
+        for (int t = 0; t < P; ++t) w[k][t] = bspline_host(P, u - (first[k] + t) + P / 2.0);
+      }
+      for (int tz = 0; tz < P; ++tz)
+        for (int ty = 0; ty < P; ++ty)
+          for (int tx = 0; tx < P; ++tx) {
+            int ix = ((first[0] + tx) % mi.K[0] + mi.K[0]) % mi.K[0];
+            int iy = ((first[1] + ty) % mi.K[1] + mi.K[1]) % mi.K[1];
+            int iz = ((first[2] + tz) % mi.K[2] + mi.K[2]) % mi.K[2];
+            size_t t = (size_t)i * P3 + (tz * P + ty) * P + tx;
+            gidx[t] = (iz * mi.K[1] + iy) * mi.K[0] + ix;
+            gw[t] = w[0][tx] * w[1][ty] * w[2][tz];
+          }
+    }
+    std::vector<int> cnt(mi.M, 0);
+    for (size_t t = 0; t < gidx.size(); ++t) cnt[gidx[t]]++;
+    std::vector<int> touch, rowptr(1, 0), col;
+    std::vector<int> slot(mi.M, -1);
+    for (int m = 0; m < mi.M; ++m)
+      if (cnt[m]) { slot[m] = (int)touch.size(); touch.push_back(m); rowptr.push_back(rowptr.back() + cnt[m]); }
+    col.resize(gidx.size());
+    std::vector<double> val(gidx.size());
+    std::vector<int> fillp(rowptr.begin(), rowptr.end() - 1);
+    for (int i = 0; i < ne; ++i)
+      for (int t = 0; t < P3; ++t) {
+        size_t k = (size_t)i * P3 + t;
+        int sl = slot[gidx[k]];
+        col[fillp[sl]] = i;
+        val[fillp[sl]] = gw[k];
+        fillp[sl]++;
+      }
+    c->n_touch = (int)touch.size();
+    std::vector<float> gwf(gw.begin(), gw.end()), valf(val.begin(), val.end());
+    if ((r = upload(c, &c->d_gidx, gidx)) || (r = upload(c, &c->d_gw, gw)) || (r = upload(c, &c->d_gwf, gwf)) ||
+        (r = upload(c, &c->d_touch, touch)) || (r = upload(c, &c->d_rowptr, rowptr)) || (r = upload(c, &c->d_col, col)) ||
+        (r = upload(c, &c->d_val, val)) || (r = upload(c, &c->d_valf, valf)))
+      return bad(r);
+  } else {
+    std::vector<double> kx, ky, kz;
+    half_kvectors(c->box, c->kcut, kx, ky, kz);
+    c->nk = (int)kx.size();
+    if (c->nk == 0) { fail(c, CPM_EINVAL, "kcut admits no k-vectors"); return bad(CPM_EINVAL); }
+    const double vol = c->box[0] * c->box[1] * c->box[2];
+    std::vector<double> kv(3 * (size_t)c->nk), ew(c->nk);
+    std::vector<double2> eph((size_t)c->nk * ne);
+    for (int k = 0; k < c->nk; ++k) {
+      kv[k] = kx[k]; kv[c->nk + k] = ky[k]; kv[2 * c->nk + k] = kz[k];
+      double k2 = kx[k] * kx[k] + ky[k] * ky[k] + kz[k] * kz[k];
+      ew[k] = 2 * KE * kweight_host(k2, c->alpha, vol);
+      for (int i = 0; i < ne; ++i) {
+        double ph = kx[k] * c->hx[i] + ky[k] * c->hy[i] + kz[k] * c->hz[i];
+        eph[(size_t)k * ne + i] = double2{std::cos(ph), std::sin(ph)};
+      }
+    }
+    if ((r = upload(c, &c->d_kv, kv)) || (r = upload(c, &c->d_ew, ew)) || (r = upload(c, &c->d_eph, eph)))
+      return bad(r);
+  }
+  if ((r = alloc_frames(c, 1))) return bad(r);
+  *out = c;
+  return CPM_OK;
+}
+
+int cpm_set_stream(cpm_ctx* c, void* hip_stream) {
+  if (!c) return CPM_EINVAL;
+  if ((hipStream_t)hip_stream != c->stream) free_graphs(c);
+  c->stream = (hipStream_t)hip_stream;
+  c->use_graph = hip_stream != nullptr && std::getenv("CPM_NO_GRAPH") == nullptr;
+  return CPM_OK;
+}
+
+int cpm_build_elastance(cpm_ctx* c) {
+  if (!c) return CPM_EINVAL;
+  const int n = c->n_elec;
+  hipStream_t s = c->stream;
+  // real space and self term
+  const double self_term = (std::sqrt(2.0) * c->eta - 2.0 * c->alpha_b) / std::sqrt(M_PI);
+  launch_elastance_real(s, n, c->d_ex, c->d_ey, c->d_ez, c->cell_b, c->alpha_b, c->eta, c->rcut_b, self_term, c->d_A);
+  // k space: A += C C^T over chunks of k-vectors
+  std::vector<double> kx, ky, kz;
+  half_kvectors(c->box, c->kcut_b, kx, ky, kz);
+  const int nk = (int)kx.size();
+  const double vol = c->box[0] * c->box[1] * c->box[2];
+  std::vector<double> kv(3 * (size_t)nk), sk(nk);
+  for (int k = 0; k < nk; ++k) {
+    kv[k] = kx[k]; kv[nk + k] = ky[k]; kv[2 * nk + k] = kz[k];
+    double k2 = kx[k] * kx[k] + ky[k] * ky[k] + kz[k] * kz[k];
+    sk[k] = std::sqrt(2 * KE * kweight_host(k2, c->alpha_b, vol));
+  }
+  double *d_kv = nullptr, *d_sk = nullptr, *d_C = nullptr, *d_work = nullptr;
+  int r;
+  const int chunk = std::max(64, std::min(nk, (int)((size_t)(256u << 20) / (16 * (size_t)n))));
+  if ((r = upload(c, &d_kv, kv)) || (r = upload(c, &d_sk, sk)) || (r = dalloc(c, &d_C, (size_t)n * 2 * chunk)))
+    return r;
+  for (int k0 = 0; k0 < nk; k0 += chunk) {
+    int nkc = std::min(chunk, nk - k0);
+    launch_phase_matrix(s, n, nkc, k0, nk, d_kv, d_sk, c->d_ex, c->d_ey, c->d_ez, d_C);
+    launch_gemm_nt(s, n, n, 2 * nkc, 1.0, d_C, 2 * nkc, d_C, 2 * nkc, 1.0, c->d_A, n);
+  }
+  launch_symmetrize(s, n, c->d_A);
+  // inverse (in d_S), projections
+  HIP_TRY(c, hipMemcpyAsync(c->d_S, c->d_A, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  double *dinv, *pc, *rx, *u;
+  if ((r = dalloc(c, &dinv, GJ_BLOCK * GJ_BLOCK)) || (r = dalloc(c, &pc, (size_t)n * GJ_BLOCK)) ||
+      (r = dalloc(c, &rx, (size_t)n * GJ_BLOCK)) || (r = dalloc(c, &u, n)))
+    return r;
+  HIP_TRY(c, hipMemsetAsync(c->d_status + 1, 0, sizeof(int), s));
+  launch_gj_invert(s, n, c->d_S, dinv, pc, rx, c->d_status + 1);
+  TRY(check_launch(c));
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->d_status + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (flag) return fail(c, CPM_ENOTSPD, "elastance matrix is not positive definite (coincident electrode atoms?)");
+  launch_matvec(s, n, c->d_S, nullptr, u);                 // u = A^-1 e
+  launch_dot(s, n, u, nullptr, c->d_scalar);                // e.u
+  launch_rank1(s, n, c->d_S, u, c->d_scalar);               // S = A^-1 - u u^T / e.u
+  if (c->geometry == CPM_DOUBLED_CELL) {
+    launch_matvec(s, n, c->d_S, c->d_e1, u);                // w = S e1
+    launch_dot(s, n, u, c->d_e1, c->d_scalar);              // e1.w
+    launch_rank1(s, n, c->d_S, u, c->d_scalar);             // S -= w w^T / e1.w
+  }
+  launch_matvec(s, n, c->d_S, c->d_c, c->d_Sc);            // S c
+  TRY(check_launch(c));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  // the chunk buffers are released now (they are large)
+  for (void* p : {(void*)d_kv, (void*)d_sk, (void*)d_C, (void*)dinv, (void*)pc, (void*)rx, (void*)u}) {
+    hipFree(p);
+    c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
+  }
+  c->built = true;
+  free_graphs(c);
+  return CPM_OK;
+}
+
+int cpm_set_matrix(cpm_ctx* c, const double* host_S) {
+  if (!c || !host_S) return CPM_EINVAL;
+  const int n = c->n_elec;
+  HIP_TRY(c, hipMemcpy(c->d_S, host_S, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice));
+  launch_matvec(c->stream, n, c->d_S, c->d_c, c->d_Sc);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->built = true;
+  free_graphs(c);
+  return CPM_OK;
+}
+
+int cpm_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, double* f_out, double* e_out) {
+  if (!c) return CPM_EINVAL;
+  if (!c->built) return fail(c, CPM_ESTATE, "cpm_solve before cpm_build_elastance");
+  if (!xyz || !q_out) return fail(c, CPM_EINVAL, "site_xyz and q_out are required");
+  if (!std::isfinite(dv)) return fail(c, CPM_ENONFINITE, "non-finite dV");
+  auto enqueue = [&]() {
+    return c->precision == CPM_MIXED ? enqueue_solve<float>(c, xyz, dv, q_out, f_out, e_out)
+                                     : enqueue_solve<double>(c, xyz, dv, q_out, f_out, e_out);
+  };
+  if (!c->use_graph) {
+    TRY(enqueue());
+    return check_launch(c);
+  }
+  const void* key[6] = {xyz, q_out, f_out, e_out, nullptr, nullptr};
+  for (auto& g : c->graphs) {
+    if (g.kind == 0 && g.dv == dv && std::memcmp(g.p, key, sizeof(key)) == 0) {
+      g.last_use = ++c->tick;
+      HIP_TRY(c, hipGraphLaunch(g.exec, c->stream));
+      return CPM_OK;
+    }
+  }
+  hipGraph_t graph;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int r = enqueue();
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  if (r != CPM_OK) return r;
+  if (e != hipSuccess) return fail(c, CPM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  GraphEntry ge{};
+  std::memcpy(ge.p, key, sizeof(key));
+  ge.dv = dv;
+  ge.kind = 0;
+  e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(c, CPM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+  ge.last_use = ++c->tick;
+  if (c->graphs.size() >= 16) {
+    auto it = std::min_element(c->graphs.begin(), c->graphs.end(),
+                               [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+    hipGraphExecDestroy(it->exec);
+    c->graphs.erase(it);
+  }
+  c->graphs.push_back(ge);
+  HIP_TRY(c, hipGraphLaunch(ge.exec, c->stream));
+  return CPM_OK;
+}
+
+int cpm_solve_batch(cpm_ctx* c, int n_frames, const double* xyz, int n_dv, const double* dv_host, double* q_out,
+                    double* f_out, double* e_out) {
+  if (!c) return CPM_EINVAL;
+  return fail(c, CPM_EINVAL, "cpm_solve_batch: not available in this build");
+}
+
+int cpm_grad(cpm_ctx* c, const double* xyz, double dv, const double* q_target, double* loss_out, double* dl_dxyz,
+             double* dl_ddv, double* q_out) {
+  if (!c) return CPM_EINVAL;
+  return fail(c, CPM_EINVAL, "cpm_grad: not available in this build");
+}
+
+int cpm_get_matrix(cpm_ctx* c, int which, double* host_out) {
+  if (!c || !host_out) return CPM_EINVAL;
+  if (!c->built) return fail(c, CPM_ESTATE, "matrices not built");
+  const size_t n = c->n_elec;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (which == 0) HIP_TRY(c, hipMemcpy(host_out, c->d_A, n * n * sizeof(double), hipMemcpyDeviceToHost));
+  else if (which == 1) HIP_TRY(c, hipMemcpy(host_out, c->d_S, n * n * sizeof(double), hipMemcpyDeviceToHost));
+  else if (which == 2) HIP_TRY(c, hipMemcpy(host_out, c->d_Sc, n * sizeof(double), hipMemcpyDeviceToHost));
+  else return fail(c, CPM_EINVAL, "unknown matrix %d", which);
+  return CPM_OK;
+}
+
+long long cpm_get_buffer(cpm_ctx* c, int which, void* host_out) {
+  if (!c) return CPM_EINVAL;
+  const bool pppm = c->kspace == CPM_KSPACE_PPPM;
+  const bool mixed = c->precision == CPM_MIXED;
+  const size_t M = c->mi.M;
+  const void* src = nullptr;
+  size_t count = 0, elt = sizeof(double);
+  std::vector<double> conv;
+  switch (which) {
+    case CPM_BUF_CELL_START: src = c->d_cell_start; count = c->cell.n_cells + 1; elt = sizeof(int); break;
+    case CPM_BUF_SITE_ORDER: src = c->d_order; count = c->n_site; elt = sizeof(int); break;
+    case CPM_BUF_PHI_REAL: src = mixed ? (const void*)c->d_phirf : c->d_phir; count = c->n_elec; if (mixed) elt = 4; break;
+    case CPM_BUF_B: src = c->d_b; count = c->n_elec; break;
+    case CPM_BUF_RHO_MESH: if (!pppm) return 0; src = mixed ? (const void*)c->d_rhof : c->d_rho; count = M; if (mixed) elt = 4; break;
+    case CPM_BUF_PHI_MESH: if (!pppm) return 0; src = mixed ? (const void*)c->d_phif : c->d_phi; count = M; if (mixed) elt = 4; break;
+    case CPM_BUF_FIELD_MESH: if (!pppm) return 0; src = mixed ? (const void*)c->d_Ef : c->d_E; count = 3 * M; if (mixed) elt = 4; break;
+    case CPM_BUF_NCELL:
+      if (host_out) std::memcpy(host_out, c->cell.nc, 3 * sizeof(int));
+      return 3;
+    default: return fail(c, CPM_EINVAL, "unknown buffer %d", which);
+  }
+  if (!host_out) return (long long)count;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (elt == 4 && which != CPM_BUF_CELL_START && which != CPM_BUF_SITE_ORDER) {
+    std::vector<float> tmp(count);
+    HIP_TRY(c, hipMemcpy(tmp.data(), src, count * 4, hipMemcpyDeviceToHost));
+    double* o = (double*)host_out;
+    for (size_t i = 0; i < count; ++i) o[i] = tmp[i];
+  } else {
+    HIP_TRY(c, hipMemcpy(host_out, src, count * elt, hipMemcpyDeviceToHost));
+  }
+  return (long long)count;
+}
+
+int cpm_sync_status(cpm_ctx* c) {
+  if (!c) return CPM_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int st = 0;
+  HIP_TRY(c, hipMemcpy(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemset(c->d_status, 0, sizeof(int)));
+  if (st & 1) return fail(c, CPM_ENONFINITE, "non-finite site position");
+  return CPM_OK;
+}
+
+const char* cpm_last_error(const cpm_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+void cpm_destroy(cpm_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  free_graphs(c);
+  for (void* p : c->allocs) hipFree(p);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+// Internal declarations shared by the HIP translation units of libcpm.
+// Device helpers, parameter blocks passed by value to kernels, and the host
+// launchers each .hip file exports to the C-ABI layer (api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpm {
+
+constexpr double KE = 1.43996454784;   // eV nm / e^2
+constexpr int WAVE = 64;
+constexpr int MAX_FFT_FACTORS = 12;
+constexpr int MAX_ORDER = 7;
+
+// ---------------------------------------------------------------- geometry
+
+struct Cell {          // periodic orthorhombic cell and its cell-list grid
+  double L[3];
+  double invL[3];
+  int nc[3];           // cells per axis, n_d = max(1, floor(L_d / rcut))
+  int img[3];          // extra images per axis: floor(rcut/L + 1/2)
+  int n_cells;
+};
+
+struct FFTPlan1D {     // mixed-radix Stockham plan for one axis
+  int n;
+  int nfac;
+  int fac[MAX_FFT_FACTORS];
+  const double2* tw;   // e^{-2 pi i t / n}, t = 0..n-1
+  const float2* twf;
+};
+
+struct MeshInfo {
+  int K[3];
+  int M;               // Kx*Ky*Kz
+  int order;
+  double h[3];
+  double invh[3];
+};
+
+// ------------------------------------------------------------ device utils
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ double wrap01(double t) { return t - floor(t); }
+
+// cell index of a coordinate along one axis, bit-identical to the integer
+// reference: f = x/L - floor(x/L); c = min(floor(f * n), n - 1)
+__device__ __forceinline__ int cell_coord(double x, double L, int n) {
+  double t = x / L;
+  double f = t - floor(t);
+  int c = (int)floor(f * (double)n);
+  return c < n - 1 ? c : n - 1;
+}
+
+// minimum-image displacement component
+__device__ __forceinline__ double min_image(double d, double L, double invL) {
+  return d - L * rint(d * invL);
+}
+__device__ __forceinline__ float min_image(float d, float L, float invL) {
+  return d - L * rintf(d * invL);
+}
+
+// neighbouring cells along one axis without repeats: offsets -1,0,1 when
+// n >= 3, {0,1} when n == 2, {0} when n == 1
+__device__ __forceinline__ int stencil_count(int n) { return n >= 3 ? 3 : n; }
+__device__ __forceinline__ int stencil_cell(int c, int s, int n) {
+  if (n >= 3) { int v = c + s - 1; return v < 0 ? v + n : (v >= n ? v - n : v); }
+  return (c + s) % n;
+}
+
+template <typename T> struct Real2;
+template <> struct Real2<double> { using type = double2; };
+template <> struct Real2<float> { using type = float2; };
+
+// Centred cardinal B-spline weights along one axis.  A particle at scaled
+// coordinate u (mesh units) touches the P mesh points m = first + t,
+// t = 0..P-1, first = floor(u - P/2) + 1, with weight M_P(u - m + P/2).
+// Writing s = u - P/2 and f = s - floor(s), the argument for point t is
+// f + (P - 1 - t).  The values B[j] = M_n(f + j), j = 0..P-1, follow from
+// the Cox-de Boor recursion M_n(x) = [x M_{n-1}(x) + (n - x) M_{n-1}(x-1)]/(n-1)
+// starting at M_1(f + j) = [j == 0].
+template <typename T>
+__device__ __forceinline__ int spline_weights(T u, int P, T* w) {
+  T s = u - (T)P * (T)0.5;
+  T fl = floor(s);
+  T f = s - fl;
+  T B[MAX_ORDER];
+  B[0] = (T)1;
+#pragma unroll
+  for (int j = 1; j < MAX_ORDER; ++j) B[j] = (T)0;
+  for (int n = 2; n <= P; ++n) {
+    T inv = (T)1 / (T)(n - 1);
+    for (int j = n - 1; j >= 0; --j) {
+      T x = f + (T)j;
+      T prev = (j > 0) ? B[j - 1] : (T)0;
+      B[j] = (x * B[j] + ((T)n - x) * prev) * inv;
+    }
+  }
+  for (int t = 0; t < P; ++t) w[t] = B[P - 1 - t];
+  return (int)fl + 1;
+}
+
+// ------------------------------------------------------ kernel arguments
+
+template <typename T>
+struct SiteSet {       // cell-sorted sites of frame 0 (add frame * n to index)
+  const T* x; const T* y; const T* z; const T* q;
+  const int* order; const int* cell_start;
+  int n;
+};
+
+template <typename T>
+struct ElecSet {       // cell-sorted electrode atoms (static)
+  const T* x; const T* y; const T* z;
+  const int* orig; const int* cell; const int* cell_start;
+  int n;
+};
+
+template <typename T>
+struct ForceArgs {
+  T alpha, eta, rc2;
+  // k-space field meshes (V/nm, k_e included), [frame][3][M] and a shared
+  // second set (or nullptr); mesh geometry for the spline gather
+  const T* Ea; size_t Ea_frame_stride;
+  const T* Eb;
+  MeshInfo mi;
+  // explicit-Ewald path instead of a mesh: k-space field at the sites,
+  // [frame][3][n_site] in cell-sorted order (V/nm), or nullptr
+  const double* Esite;
+  // electrode charges, original order: qa per frame (stride n_elec), qb shared
+  const double* qa; size_t qa_frame_stride;
+  const double* qb;
+  double out_scale;          // multiplies the Coulomb force (e.g. -1 for a gradient)
+  double field;              // -dV/Lz for the finite field (0 otherwise), added along z
+  double fieldb;             // same for the second set (per unit dV)
+  // outputs
+  double* f_out; size_t f_frame_stride;   // [frame][n_dv][3][n_site] original order
+  int n_dv; const double* dv;             // dV values of the sweep (n_dv == 1: dv may be nullptr)
+  double* u_site;                          // [frame][n_site] 1/2 Q_j sum Q_j' g0 (sorted order), or nullptr
+};
+
+struct ZPassArgs {
+  int Kx, Ky, Kz;
+  int nxc;                 // columns per workgroup
+  int nchunk;              // x chunks per y row
+  int mode;                // 0: potential, 1: field (ik)
+  double twopi_L[3];       // 2 pi / L_d
+};
+
+struct EnergyArgs {
+  int n_elec, n_site, n_ek;
+  const double* Q0; const double* b;            // [frame][n_elec]
+  const double* Sc; const double* c; const double* d; const double* ze;   // [n_elec]
+  const double* u_site;                          // [frame][n_site]
+  const double* ek;                              // [frame][n_ek] k-space energy parts
+  const double* zdip;                            // [frame]
+  double self_energy;
+  int ff; double Lz;
+  int n_dv; const double* dv; double dv_single;
+  double* out;                                   // [frame][n_dv][2]
+};
+
+// --------------------------------------------------------------- launchers
+
+// cell binning (k_bin.hip)
+void launch_bin_sites(hipStream_t s, int n_frames, int n_site, const double* xyz, size_t frame_stride,
+                      const double* site_q, Cell cell, int* cell_start, int* site_order,
+                      double* sx, double* sy, double* sz, double* sq, float* fx, float* fy, float* fz,
+                      float* fq, double* zdip, int* status, double* zero_mesh, int mesh_M,
+                      float* zero_meshf);
+
+// real-space sums (k_realspace.hip)
+template <typename T>
+void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
+                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out);
+template <typename T>
+void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
+                          const SiteSet<T>& st, const ForceArgs<T>& fa);
+size_t bin_lds_bytes(int n_site, int n_cells);
+
+// particle-mesh steps (k_pppm.hip)
+template <typename T>
+void launch_spread_sites_t(hipStream_t s, int n_frames, const MeshInfo& mi, const SiteSet<T>& st, T* rho);
+template <typename T>
+void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
+                          const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M);
+template <typename T>
+void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const int* gidx, const T* gw,
+                       const T* phi, int M, const T* phi_real, double* b);
+
+// FFT passes (k_fft.hip)
+template <typename T, typename T2>
+void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
+                     int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
+                     size_t out_re_stride = 0);
+template <typename T, typename T2>
+void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
+                    T2* data1, T2* data2, T2* save, int add_saved, double* energy_part);
+
+// explicit Ewald (k_ewald.hip)
+void launch_ewald_sf(hipStream_t s, int n_frames, int nk, const double* kv, const double* ew,
+                     const SiteSet<double>& st, double2* rho, double* ek);
+void launch_ewald_phi(hipStream_t s, int n_frames, int nk, int n_elec, const double* ew, const double2* eph,
+                      const double2* rho, const double* phi_real, double* b);
+void launch_ewald_rho_all(hipStream_t s, int n_frames, int nk, int n_elec, const double2* eph, const double* q,
+                          size_t q_stride, const double2* rho, double2* out);
+void launch_ewald_field(hipStream_t s, int n_frames, int nk, const double* kv, const double* ew,
+                        const SiteSet<double>& st, const double2* rho, double* E);
+
+// dense linear algebra (k_linalg.hip)
+constexpr int GJ_BLOCK = 32;
+void launch_elastance_real(hipStream_t s, int n, const double* ex, const double* ey, const double* ez,
+                           const Cell& cell, double alpha, double eta, double rcut, double self_term, double* A);
+void launch_phase_matrix(hipStream_t s, int n, int nkc, int k0, int nk, const double* kv, const double* sk,
+                         const double* ex, const double* ey, const double* ez, double* C);
+void launch_gemm_nt(hipStream_t s, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
+                    int ldb, double beta, double* D, int ldd);
+void launch_symmetrize(hipStream_t s, int n, double* A);
+void launch_gj_invert(hipStream_t s, int n, double* A, double* dinv, double* pc, double* rx, int* flag);
+void launch_matvec(hipStream_t s, int n, const double* Mx, const double* x, double* y);
+void launch_dot(hipStream_t s, int n, const double* a, const double* b, double* out);
+void launch_rank1(hipStream_t s, int n, double* S, const double* u, const double* sc);
+void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const double* b, const double* Sc, double dv,
+                    double* Q0, double* q);
+void launch_energy(hipStream_t s, int n_frames, const EnergyArgs& ea);
+void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
+                           const double* Sc, double* q);
+
+}  // namespace cpm

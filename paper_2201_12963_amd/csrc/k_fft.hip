@@ -1,0 +1,283 @@
+// 3D FFT of the PPPM mesh and the Green's-function step, hand-written for
+// the small meshes of this path (a few 10^4 points per frame).
+//
+// Mixed-radix (2, 3, 4, 5) Stockham autosort transform, staged entirely in
+// LDS: a stage of radix R reads R points N/R apart, applies the twiddles
+// e^{-+2 pi i r (j mod Ns)/(Ns R)}, does a length-R DFT and writes R points
+// Ns apart into the other buffer (Ns = product of the radices done so far);
+// after the last stage the data are in natural order.  Twiddles come from a
+// per-length table of e^{-2 pi i t / N}.
+//
+// The 3D transform of one frame is two kernels:
+//   * k_fft_xy: one workgroup per z-plane (Kx x Ky points) transforms x and
+//     y (forward from a real mesh, or inverse to real output meshes);
+//   * k_fft_z:  one workgroup per (y, block of x columns) transforms along
+//     z, multiplies by the influence function (and by -i k for the field,
+//     ik differentiation), transforms back along z, and writes in place.
+// A round trip real mesh -> potential (or field) mesh is therefore
+// fft_xy(forward) -> fft_z -> fft_xy(inverse).  Mesh layout [z][y][x].
+#include "common.h"
+
+namespace cpm {
+
+template <typename T2> struct CT;
+template <> struct CT<double2> { using R = double; };
+template <> struct CT<float2> { using R = float; };
+
+template <typename T2> __device__ __forceinline__ T2 cadd(T2 a, T2 b) { return T2{a.x + b.x, a.y + b.y}; }
+template <typename T2> __device__ __forceinline__ T2 csub(T2 a, T2 b) { return T2{a.x - b.x, a.y - b.y}; }
+template <typename T2> __device__ __forceinline__ T2 cmul(T2 a, T2 b) {
+  return T2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T2, typename R> __device__ __forceinline__ T2 cscale(T2 a, R s) { return T2{a.x * s, a.y * s}; }
+// multiply by sigma * i
+template <typename T2> __device__ __forceinline__ T2 cmul_si(T2 a, int sigma) {
+  return sigma > 0 ? T2{-a.y, a.x} : T2{a.y, -a.x};
+}
+
+// X[m] = sum_r v[r] exp(sigma 2 pi i r m / R), R in {2,3,4,5}
+template <typename T2>
+__device__ __forceinline__ void small_dft(T2* v, int R, int sigma) {
+  using Rl = typename CT<T2>::R;
+  if (R == 2) {
+    T2 a = cadd(v[0], v[1]), b = csub(v[0], v[1]);
+    v[0] = a; v[1] = b;
+  } else if (R == 4) {
+    T2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    T2 s13 = cadd(v[1], v[3]), d13 = cmul_si(csub(v[1], v[3]), sigma);
+    v[0] = cadd(s02, s13); v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13); v[3] = csub(d02, d13);
+  } else if (R == 3) {
+    const Rl h = (Rl)0.86602540378443865;    // sqrt(3)/2
+    T2 s = cadd(v[1], v[2]);
+    T2 d = cmul_si(cscale(csub(v[1], v[2]), h), sigma);
+    T2 m = csub(v[0], cscale(s, (Rl)0.5));
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, d);
+    v[2] = csub(m, d);
+  } else {  // R == 5
+    const Rl c1 = (Rl)0.30901699437494742, c2 = (Rl)-0.80901699437494742;
+    const Rl s1 = (Rl)0.95105651629515357, s2 = (Rl)0.58778525229247313;
+    T2 s14 = cadd(v[1], v[4]), d14 = csub(v[1], v[4]);
+    T2 s23 = cadd(v[2], v[3]), d23 = csub(v[2], v[3]);
+    T2 a1 = cadd(v[0], cadd(cscale(s14, c1), cscale(s23, c2)));
+    T2 a2 = cadd(v[0], cadd(cscale(s14, c2), cscale(s23, c1)));
+    T2 b1 = cmul_si(cadd(cscale(d14, s1), cscale(d23, s2)), sigma);
+    T2 b2 = cmul_si(csub(cscale(d14, s2), cscale(d23, s1)), sigma);
+    v[0] = cadd(v[0], cadd(s14, s23));
+    v[1] = cadd(a1, b1); v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2); v[3] = csub(a2, b2);
+  }
+}
+
+template <typename T2> __device__ __forceinline__ const T2* twiddles(const FFTPlan1D& p);
+template <> __device__ __forceinline__ const double2* twiddles<double2>(const FFTPlan1D& p) { return p.tw; }
+template <> __device__ __forceinline__ const float2* twiddles<float2>(const FFTPlan1D& p) { return p.twf; }
+
+// Transform nlines lines of length p.n held in LDS buffer a (element stride
+// es, line stride ls), ping-ponging with b.  Returns the buffer holding the
+// result.  sigma = -1 forward, +1 inverse (unnormalised).
+template <typename T2>
+__device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, int nlines, int es, int ls, int sigma) {
+  const int N = p.n;
+  const T2* tw = twiddles<T2>(p);
+  T2* src = a;
+  T2* dst = b;
+  int Ns = 1;
+  for (int f = 0; f < p.nfac; ++f) {
+    const int R = p.fac[f];
+    const int nb = N / R;
+    const int tstep = N / (Ns * R);
+    for (int u = threadIdx.x; u < nlines * nb; u += blockDim.x) {
+      const int line = u / nb;
+      const int j = u - line * nb;
+      const T2* in = src + line * ls;
+      T2* out = dst + line * ls;
+      T2 v[5];
+      for (int r = 0; r < R; ++r) v[r] = in[(j + r * nb) * es];
+      const int k = j % Ns;
+      if (Ns > 1) {
+        for (int r = 1; r < R; ++r) {
+          T2 w = tw[r * k * tstep];
+          if (sigma > 0) w.y = -w.y;
+          v[r] = cmul(v[r], w);
+        }
+      }
+      small_dft(v, R, sigma);
+      const int base = (j / Ns) * Ns * R + k;
+      for (int r = 0; r < R; ++r) out[(base + r * Ns) * es] = v[r];
+    }
+    __syncthreads();
+    T2* t = src; src = dst; dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// ------------------------------------------------------------------ x-y pass
+
+// mode 0: forward, real input -> complex output
+// mode 1: inverse, complex input -> real part to out_re (and imaginary part to out_im if given)
+template <typename T, typename T2>
+__global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
+                                                const T* __restrict__ in_re, const T2* __restrict__ in_c,
+                                                T2* __restrict__ out_c, T* __restrict__ out_re,
+                                                T* __restrict__ out_im, size_t out_re_stride) {
+  extern __shared__ unsigned char smem[];
+  const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
+  T2* A = reinterpret_cast<T2*>(smem);
+  T2* B = A + NP;
+  const int z = blockIdx.x;
+  const size_t off = ((size_t)blockIdx.y * Kz + z) * NP;
+  if (mode == 0) {
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) A[i] = T2{in_re[off + i], (T)0};
+  } else {
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) A[i] = in_c[off + i];
+  }
+  __syncthreads();
+  const int sigma = mode == 0 ? -1 : 1;
+  T2* r1 = fft_lines(A, B, px, Ky, 1, Kx, sigma);          // along x
+  T2* o1 = (r1 == A) ? B : A;
+  T2* r2 = fft_lines(r1, o1, py, Kx, Kx, 1, sigma);        // along y
+  if (mode == 0) {
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2[i];
+  } else {
+    const size_t ro = (size_t)blockIdx.y * out_re_stride + (size_t)z * NP;
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) {
+      out_re[ro + i] = r2[i].x;
+      if (out_im) out_im[ro + i] = r2[i].y;
+    }
+  }
+}
+
+// ------------------------------------------------------------------- z pass
+
+template <typename T> __device__ __forceinline__ T mode_k(int i, int K, T twopi_L) {
+  int n = (i < (K + 1) / 2) ? i : i - K;
+  if ((K & 1) == 0 && n == -(K / 2)) return (T)0;   // no derivative at the Nyquist index
+  return (T)n * twopi_L;
+}
+
+// mode 0 (potential): X = FFT_z(data1); if save: save = X; energy partial
+//          1/2 sum G |X|^2; data1 = IFFT_z(G X)
+// mode 1 (field):     X = FFT_z(data1) (+ save if add_saved);
+//          data1 = IFFT_z((-i kx + ky) G X)  [Ex + i Ey after the x-y inverse]
+//          data2 = IFFT_z(-i kz G X)         [Ez]
+template <typename T, typename T2>
+__global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
+                                               T2* __restrict__ data1, T2* __restrict__ data2,
+                                               T2* __restrict__ save, int add_saved,
+                                               double* __restrict__ energy_part) {
+  extern __shared__ unsigned char smem[];
+  __shared__ double red[8];
+  const int Kx = za.Kx, Ky = za.Ky, Kz = za.Kz;
+  const int y = blockIdx.x / za.nchunk;
+  const int x0 = (blockIdx.x - y * za.nchunk) * za.nxc;
+  const int nc = min(za.nxc, Kx - x0);
+  const int NL = nc * Kz;
+  T2* A = reinterpret_cast<T2*>(smem);
+  T2* B = A + za.nxc * Kz;
+  T2* C = B + za.nxc * Kz;
+  const size_t fo = (size_t)blockIdx.y * Kx * Ky * Kz;
+  // LDS layout [z][c]: lines along z have element stride nc, line stride 1
+  for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+    int zz = i / nc, c = i - zz * nc;
+    A[i] = data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c];
+  }
+  __syncthreads();
+  T2* X = fft_lines(A, B, pz, nc, nc, 1, -1);
+  T2* F1 = (X == A) ? B : A;
+  if (za.mode == 0) {
+    double e = 0.0;
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+      int zz = i / nc, c = i - zz * nc;
+      size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
+      T2 v = X[i];
+      if (save) save[fo + g] = v;
+      T gk = G[g];
+      e += (double)gk * ((double)v.x * v.x + (double)v.y * v.y);
+      X[i] = T2{v.x * gk, v.y * gk};
+    }
+    if (energy_part) {
+      e = wave_sum(e);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+    }
+    __syncthreads();
+    if (energy_part && threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+      energy_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.5 * s;
+    }
+    T2* Y = fft_lines(X, F1, pz, nc, nc, 1, +1);
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+      int zz = i / nc, c = i - zz * nc;
+      data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Y[i];
+    }
+  } else {
+    // C keeps the spectrum G X; F1 and X serve as the ping-pong pair of
+    // the first inverse, A and B of the second
+    const T ky = mode_k<T>(y, Ky, (T)za.twopi_L[1]);
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+      int zz = i / nc, c = i - zz * nc;
+      size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
+      T2 v = X[i];
+      if (add_saved) { T2 sv = save[fo + g]; v.x += sv.x; v.y += sv.y; }
+      T gk = G[g];
+      v = T2{v.x * gk, v.y * gk};
+      C[i] = v;
+      T kx = mode_k<T>(x0 + c, Kx, (T)za.twopi_L[0]);
+      F1[i] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};     // (-i kx + ky) v
+    }
+    __syncthreads();
+    T2* Y = fft_lines(F1, X, pz, nc, nc, 1, +1);
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+      int zz = i / nc, c = i - zz * nc;
+      data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Y[i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+      int zz = i / nc;
+      T kz = mode_k<T>(zz, Kz, (T)za.twopi_L[2]);
+      T2 v = C[i];
+      A[i] = T2{kz * v.y, -kz * v.x};                            // -i kz v
+    }
+    __syncthreads();
+    T2* Z = fft_lines(A, B, pz, nc, nc, 1, +1);
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+      int zz = i / nc, c = i - zz * nc;
+      data2[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Z[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename T, typename T2>
+void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
+                     int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
+                     size_t out_re_stride) {
+  size_t lds = 2 * (size_t)px.n * py.n * sizeof(T2);
+  if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
+  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, n_frames), dim3(256), lds, s, px, py, Kz, mode, in_re,
+                     in_c, out_c, out_re, out_im, out_re_stride);
+}
+
+template <typename T, typename T2>
+void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
+                    T2* data1, T2* data2, T2* save, int add_saved, double* energy_part) {
+  size_t lds = 3 * (size_t)za.nxc * za.Kz * sizeof(T2);
+  hipLaunchKernelGGL((k_fft_z<T, T2>), dim3(za.Ky * za.nchunk, n_frames), dim3(256), lds, s, pz, za, G,
+                     data1, data2, save, add_saved, energy_part);
+}
+
+template void launch_fft_xy_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
+                                               int, const double*, const double2*, double2*, double*,
+                                               double*, size_t);
+template void launch_fft_xy_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int, int,
+                                             const float*, const float2*, float2*, float*, float*, size_t);
+template void launch_fft_z_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
+                                              const double*, double2*, double2*, double2*, int, double*);
+template void launch_fft_z_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
+                                            const float*, float2*, float2*, float2*, int, double*);
+
+}  // namespace cpm

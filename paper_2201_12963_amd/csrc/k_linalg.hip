@@ -1,0 +1,387 @@
+// Dense linear algebra of the constant-potential solve, all FP64:
+//   * elastance matrix A (paper Eq. 3): Gaussian-Gaussian real-space pairs,
+//     k-space as 2 k_e C C^T from the cos/sin factor matrix, self term;
+//   * its inverse by blocked Gauss-Jordan elimination without pivoting (A is
+//     symmetric positive definite for alpha < eta/sqrt2, so every pivot block
+//     is too; a non-positive pivot reports CPM_ENOTSPD);
+//   * the projections S = A^-1 - u u^T/(e.u), u = A^-1 e (Eq. 8-9), and for
+//     the doubled cell S <- S - w w^T/(e1.w), w = S e1 (Eq. 14-15);
+//   * the per-step charge solve q = S b + dV S c (one wavefront per row,
+//     streaming S once) and the energy reductions.
+#include "common.h"
+
+namespace cpm {
+
+// ------------------------------------------------------------ elastance
+
+__global__ __launch_bounds__(256) void k_elastance_real(int n, const double* __restrict__ ex,
+                                                        const double* __restrict__ ey, const double* __restrict__ ez,
+                                                        Cell cell, double alpha, double eta, double rc2,
+                                                        double self_term, double* __restrict__ A) {
+  const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (i >= n || j >= n) return;
+  const double eta2 = eta * 0.70710678118654752;   // eta / sqrt(2)
+  double dx0 = min_image(ex[i] - ex[j], cell.L[0], cell.invL[0]);
+  double dy0 = min_image(ey[i] - ey[j], cell.L[1], cell.invL[1]);
+  double dz0 = min_image(ez[i] - ez[j], cell.L[2], cell.invL[2]);
+  double acc = 0.0;
+  for (int a = -cell.img[0]; a <= cell.img[0]; ++a)
+    for (int b = -cell.img[1]; b <= cell.img[1]; ++b)
+      for (int c = -cell.img[2]; c <= cell.img[2]; ++c) {
+        if (i == j && a == 0 && b == 0 && c == 0) continue;
+        double dx = dx0 + a * cell.L[0], dy = dy0 + b * cell.L[1], dz = dz0 + c * cell.L[2];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < rc2) {
+          double r = sqrt(r2);
+          acc += (erfc(alpha * r) - erfc(eta2 * r)) / r;
+        }
+      }
+  if (i == j) acc += self_term;
+  A[(size_t)i * n + j] = KE * acc;
+}
+
+// C[i][c] for the k-vectors k0 .. k0+nkc-1: c < nkc -> s_k cos(k.r_i),
+// c >= nkc -> s_k sin(k.r_i), s_k = sqrt(2 k_e w(k)); row-major n x 2 nkc
+__global__ __launch_bounds__(256) void k_phase_matrix(int n, int nkc, int k0, int nk, const double* __restrict__ kv,
+                                                      const double* __restrict__ sk, const double* __restrict__ ex,
+                                                      const double* __restrict__ ey, const double* __restrict__ ez,
+                                                      double* __restrict__ C) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (c >= nkc) return;
+  const int k = k0 + c;
+  double s, co;
+  sincos(kv[k] * ex[i] + kv[nk + k] * ey[i] + kv[2 * nk + k] * ez[i], &s, &co);
+  C[(size_t)i * 2 * nkc + c] = sk[k] * co;
+  C[(size_t)i * 2 * nkc + nkc + c] = sk[k] * s;
+}
+
+// D[M x N] = beta D + alpha A B^T, A (M x K) and B (N x K) row-major with
+// leading dimensions lda, ldb, D with ldd.  64 x 64 tiles, 16-deep k-slabs
+// through LDS, 4 x 4 outputs per thread.
+__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, double alpha, const double* __restrict__ A,
+                                                 int lda, const double* __restrict__ B, int ldb, double beta,
+                                                 double* __restrict__ D, int ldd) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  double acc[4][4] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int t = threadIdx.x; t < 64 * 16; t += 256) {
+      int r = t >> 4, kk = t & 15;
+      int gi = i0 + r, gj = j0 + r, gk = k0 + kk;
+      As[kk][r] = (gi < M && gk < K) ? A[(size_t)gi * lda + gk] : 0.0;
+      Bs[kk][r] = (gj < N && gk < K) ? B[(size_t)gj * ldb + gk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { a[u] = As[kk][ty + 16 * u]; b[u] = Bs[kk][tx + 16 * u]; }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
+      if (gi < M && gj < N) {
+        double* d = D + (size_t)gi * ldd + gj;
+        *d = (beta == 0.0 ? 0.0 : beta * *d) + alpha * acc[u][v];
+      }
+    }
+}
+
+__global__ void k_symmetrize(int n, double* __restrict__ A) {
+  const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (i >= n || j >= n || j <= i) return;
+  double a = A[(size_t)i * n + j], b = A[(size_t)j * n + i];
+  double m = 0.5 * (a + b);
+  A[(size_t)i * n + j] = m;
+  A[(size_t)j * n + i] = m;
+}
+
+// ---------------------------------------------------- Gauss-Jordan inverse
+
+constexpr int GJ_NB = GJ_BLOCK;
+
+// Invert the nb x nb diagonal block at k0 in LDS (Gauss-Jordan, no
+// pivoting); Dinv -> dinv; flag on a non-positive or non-finite pivot.
+__global__ __launch_bounds__(256) void k_gj_pivot(int n, int k0, int nb, const double* __restrict__ A,
+                                                  double* __restrict__ dinv, int* __restrict__ flag) {
+  __shared__ double D[GJ_NB][GJ_NB + 1];
+  __shared__ double prow[GJ_NB], pcol[GJ_NB];
+  __shared__ double piv;
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+    int r = t / nb, c = t % nb;
+    D[r][c] = A[(size_t)(k0 + r) * n + k0 + c];
+  }
+  __syncthreads();
+  for (int p = 0; p < nb; ++p) {
+    if (threadIdx.x == 0) {
+      piv = D[p][p];
+      if (!(piv > 0.0) || !isfinite(piv)) { atomicOr(flag, 1); piv = 1.0; }
+    }
+    __syncthreads();
+    double ip = 1.0 / piv;
+    for (int t = threadIdx.x; t < nb; t += blockDim.x) { prow[t] = D[p][t]; pcol[t] = D[t][p]; }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+      int r = t / nb, c = t % nb;
+      double v;
+      if (r == p && c == p) v = ip;
+      else if (r == p) v = prow[c] * ip;
+      else if (c == p) v = -pcol[r] * ip;
+      else v = D[r][c] - pcol[r] * prow[c] * ip;
+      D[r][c] = v;
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+    int r = t / nb, c = t % nb;
+    dinv[r * nb + c] = D[r][c];
+  }
+}
+
+// Panels: pc[i][t] = A[i][k0+t] (column block, i outside the pivot rows is
+// what the update needs) and rx[t][j] = (Dinv A[k0.., j]) for j outside the
+// block, Dinv[t][j-k0] inside it.
+__global__ __launch_bounds__(256) void k_gj_panels(int n, int k0, int nb, const double* __restrict__ A,
+                                                   const double* __restrict__ dinv, double* __restrict__ pc,
+                                                   double* __restrict__ rx) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int t = 0; t < nb; ++t) pc[(size_t)j * nb + t] = A[(size_t)j * n + k0 + t];
+  if (j >= k0 && j < k0 + nb) {
+    for (int t = 0; t < nb; ++t) rx[(size_t)t * n + j] = dinv[t * nb + (j - k0)];
+  } else {
+    double col[GJ_NB];
+    for (int t = 0; t < nb; ++t) col[t] = A[(size_t)(k0 + t) * n + j];
+    for (int t = 0; t < nb; ++t) {
+      double s = 0.0;
+      for (int u = 0; u < nb; ++u) s += dinv[t * nb + u] * col[u];
+      rx[(size_t)t * n + j] = s;
+    }
+  }
+}
+
+// A[i][j] = rx[i-k0][j] for i in the block, else (j in block ? 0 : A[i][j]) - sum_t pc[i][t] rx[t][j]
+__global__ __launch_bounds__(256) void k_gj_update(int n, int k0, int nb, double* __restrict__ A,
+                                                   const double* __restrict__ pc, const double* __restrict__ rx) {
+  __shared__ double Ps[64][GJ_NB + 1];
+  __shared__ double Rs[GJ_NB][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  for (int t = threadIdx.x; t < 64 * nb; t += 256) {
+    int r = t / nb, c = t % nb;
+    Ps[r][c] = (i0 + r < n) ? pc[(size_t)(i0 + r) * nb + c] : 0.0;
+  }
+  for (int t = threadIdx.x; t < nb * 64; t += 256) {
+    int r = t / 64, c = t % 64;
+    Rs[r][c] = (j0 + c < n) ? rx[(size_t)r * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int li = ty + 16 * u, lj = tx + 16 * v;
+      int gi = i0 + li, gj = j0 + lj;
+      if (gi >= n || gj >= n) continue;
+      double* a = A + (size_t)gi * n + gj;
+      if (gi >= k0 && gi < k0 + nb) {
+        *a = Rs[gi - k0][lj];
+      } else {
+        double s = 0.0;
+        for (int t = 0; t < nb; ++t) s = fma(Ps[li][t], Rs[t][lj], s);
+        double base = (gj >= k0 && gj < k0 + nb) ? 0.0 : *a;
+        *a = base - s;
+      }
+    }
+}
+
+// ------------------------------------------------------------ projections
+
+// y[i] = sum_j M[i][j] x[j] (x == nullptr: x = 1); one wavefront per row
+__global__ __launch_bounds__(256) void k_matvec(int n, const double* __restrict__ Mx, const double* __restrict__ x,
+                                                double* __restrict__ y) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double* row = Mx + (size_t)i * n;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += WAVE) acc += row[j] * (x ? x[j] : 1.0);
+  acc = wave_sum(acc);
+  if (lane == 0) y[i] = acc;
+}
+
+// out[0] = sum_i a[i] * (b ? b[i] : 1)  (one workgroup)
+__global__ __launch_bounds__(256) void k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                             double* __restrict__ out) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * (b ? b[i] : 1.0);
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+// S[i][j] -= u_i u_j / s
+__global__ void k_rank1(int n, double* __restrict__ S, const double* __restrict__ u, const double* __restrict__ s) {
+  const int j = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (i >= n || j >= n) return;
+  S[(size_t)i * n + j] -= u[i] * u[j] / s[0];
+}
+
+// ------------------------------------------------------------ charge solve
+
+// Q0 = S b (per frame), q = Q0 + dv Sc; one wavefront per row
+__global__ __launch_bounds__(256) void k_charges(int n, const double* __restrict__ S, const double* __restrict__ b_all,
+                                                 const double* __restrict__ Sc, double dv,
+                                                 double* __restrict__ Q0_all, double* __restrict__ q_all) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+  const int frame = blockIdx.y;
+  if (i >= n) return;
+  const double* b = b_all + (size_t)frame * n;
+  double acc = 0.0;
+  if ((n & 1) == 0) {       // rows are 16-byte aligned: stream them as double2
+    const double2* row = reinterpret_cast<const double2*>(S + (size_t)i * n);
+    const int n2 = n >> 1;
+    for (int j = lane; j < n2; j += WAVE) {
+      double2 s = row[j];
+      acc = fma(s.x, b[2 * j], acc);
+      acc = fma(s.y, b[2 * j + 1], acc);
+    }
+  } else {
+    const double* row = S + (size_t)i * n;
+    for (int j = lane; j < n; j += WAVE) acc = fma(row[j], b[j], acc);
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    size_t o = (size_t)frame * n + i;
+    if (Q0_all) Q0_all[o] = acc;
+    if (q_all) q_all[o] = acc + dv * Sc[i];
+  }
+}
+
+// ------------------------------------------------------------ energies
+
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_energy(EnergyArgs ea) {
+  __shared__ double red[4];
+  const int frame = blockIdx.x;
+  const size_t fe = (size_t)frame * ea.n_elec;
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < ea.n_elec; i += blockDim.x) {
+    double Q = ea.Q0[fe + i], bb = ea.b[fe + i], sc = ea.Sc[i], c = ea.c[i], d = ea.d[i], z = ea.ze[i];
+    s[0] += Q * bb; s[1] += sc * bb; s[2] += Q * c; s[3] += sc * c;
+    s[4] += d * Q; s[5] += d * sc; s[6] += z * Q; s[7] += z * sc;
+  }
+  double u = 0.0;
+  for (int j = threadIdx.x; j < ea.n_site; j += blockDim.x) u += ea.u_site[(size_t)frame * ea.n_site + j];
+  double k = 0.0;
+  for (int j = threadIdx.x; j < ea.n_ek; j += blockDim.x) k += ea.ek[(size_t)frame * ea.n_ek + j];
+  double S[8];
+  for (int t = 0; t < 8; ++t) S[t] = block_sum(s[t], red);
+  double U = block_sum(u, red);
+  double K = block_sum(k, red);
+  double u_elyt = U + K - ea.self_energy;
+  double zdip = ea.zdip ? ea.zdip[frame] : 0.0;
+  for (int v = threadIdx.x; v < ea.n_dv; v += blockDim.x) {
+    double dv = ea.dv ? ea.dv[v] : ea.dv_single;
+    double qb = S[0] + dv * S[1];
+    double qv = S[0] + dv * (S[2] + S[1]) + dv * dv * S[3];
+    double dq = S[4] + dv * S[5];
+    double zq = S[6] + dv * S[7];
+    double uc = u_elyt - qb + 0.5 * qv;
+    double ecp = uc - dv * dq;
+    if (ea.ff) ecp += dv / ea.Lz * (zq + zdip);
+    double* o = ea.out + ((size_t)frame * ea.n_dv + v) * 2;
+    o[0] = uc;
+    o[1] = ecp;
+  }
+}
+
+// q[f][v][i] = Q0[f][i] + dv[v] Sc[i]
+__global__ __launch_bounds__(256) void k_expand_charges(int n_elec, int n_dv, const double* __restrict__ dv,
+                                                        const double* __restrict__ Q0, const double* __restrict__ Sc,
+                                                        double* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y, f = blockIdx.z;
+  if (i >= n_elec) return;
+  q[((size_t)f * n_dv + v) * n_elec + i] = Q0[(size_t)f * n_elec + i] + dv[v] * Sc[i];
+}
+
+// ------------------------------------------------------------ launchers
+
+void launch_elastance_real(hipStream_t s, int n, const double* ex, const double* ey, const double* ez,
+                           const Cell& cell, double alpha, double eta, double rcut, double self_term, double* A) {
+  dim3 grid((n + 15) / 16, (n + 15) / 16);
+  hipLaunchKernelGGL(k_elastance_real, grid, dim3(256), 0, s, n, ex, ey, ez, cell, alpha, eta, rcut * rcut,
+                     self_term, A);
+}
+void launch_phase_matrix(hipStream_t s, int n, int nkc, int k0, int nk, const double* kv, const double* sk,
+                         const double* ex, const double* ey, const double* ez, double* C) {
+  hipLaunchKernelGGL(k_phase_matrix, dim3((nkc + 255) / 256, n), dim3(256), 0, s, n, nkc, k0, nk, kv, sk, ex, ey,
+                     ez, C);
+}
+void launch_gemm_nt(hipStream_t s, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
+                    int ldb, double beta, double* D, int ldd) {
+  hipLaunchKernelGGL(k_gemm_nt, dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                     beta, D, ldd);
+}
+void launch_symmetrize(hipStream_t s, int n, double* A) {
+  hipLaunchKernelGGL(k_symmetrize, dim3((n + 15) / 16, (n + 15) / 16), dim3(256), 0, s, n, A);
+}
+void launch_gj_invert(hipStream_t s, int n, double* A, double* dinv, double* pc, double* rx, int* flag) {
+  for (int k0 = 0; k0 < n; k0 += GJ_NB) {
+    int nb = n - k0 < GJ_NB ? n - k0 : GJ_NB;
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, n, k0, nb, A, dinv, flag);
+    hipLaunchKernelGGL(k_gj_panels, dim3((n + 255) / 256), dim3(256), 0, s, n, k0, nb, A, dinv, pc, rx);
+    hipLaunchKernelGGL(k_gj_update, dim3((n + 63) / 64, (n + 63) / 64), dim3(256), 0, s, n, k0, nb, A, pc, rx);
+  }
+}
+void launch_matvec(hipStream_t s, int n, const double* Mx, const double* x, double* y) {
+  hipLaunchKernelGGL(k_matvec, dim3((n + 3) / 4), dim3(256), 0, s, n, Mx, x, y);
+}
+void launch_dot(hipStream_t s, int n, const double* a, const double* b, double* out) {
+  hipLaunchKernelGGL(k_dot, dim3(1), dim3(256), 0, s, n, a, b, out);
+}
+void launch_rank1(hipStream_t s, int n, double* S, const double* u, const double* sc) {
+  hipLaunchKernelGGL(k_rank1, dim3((n + 15) / 16, (n + 15) / 16), dim3(256), 0, s, n, S, u, sc);
+}
+void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const double* b, const double* Sc, double dv,
+                    double* Q0, double* q) {
+  hipLaunchKernelGGL(k_charges, dim3((n + 3) / 4, n_frames), dim3(256), 0, s, n, S, b, Sc, dv, Q0, q);
+}
+void launch_energy(hipStream_t s, int n_frames, const EnergyArgs& ea) {
+  hipLaunchKernelGGL(k_energy, dim3(n_frames), dim3(256), 0, s, ea);
+}
+void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
+                           const double* Sc, double* q) {
+  hipLaunchKernelGGL(k_expand_charges, dim3((n_elec + 255) / 256, n_dv, n_frames), dim3(256), 0, s, n_elec, n_dv, dv,
+                     Q0, Sc, q);
+}
+
+}  // namespace cpm

@@ -1,0 +1,115 @@
+// Particle-mesh steps of PPPM (Hockney-Eastwood, as used by the paper for
+// the long-range electrostatics): B-spline charge assignment of the
+// electrolyte sites and of the electrode charges, and interpolation of the
+// mesh potential at the electrode atoms, which gives the k-space part of b.
+//
+// Electrolyte spreading: one thread per (site, y-row, z-row) of the P x P x P
+// stencil; each thread adds P weighted charges along x to contiguous mesh
+// points with hardware FP64/FP32 atomics (the sites of a wavefront are
+// cell-sorted, so their rows overlap in the same cache lines).
+// Electrode spreading and gathering: the electrodes never move, so their
+// stencils (mesh index and weight of every (atom, point) pair) are tables
+// built once; the spread is then a deterministic sparse gather per touched
+// mesh point, and the potential at an atom is one wavefront-reduced dot
+// product over its P^3 points.
+#include "common.h"
+
+namespace cpm {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread_sites(MeshInfo mi, SiteSet<T> st, T* __restrict__ rho_all) {
+  const int P = mi.order, P2 = P * P;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int frame = blockIdx.y;
+  const int j = gid / P2;
+  if (j >= st.n) return;
+  const int r = gid - j * P2;
+  const int ry = r % P, rz = r / P;
+  const size_t fo = (size_t)frame * st.n;
+  const T x = st.x[fo + j], y = st.y[fo + j], z = st.z[fo + j], q = st.q[fo + j];
+  T wx[MAX_ORDER], wy[MAX_ORDER], wz[MAX_ORDER];
+  int fx = spline_weights<T>(x * (T)mi.invh[0], P, wx);
+  int fy = spline_weights<T>(y * (T)mi.invh[1], P, wy);
+  int fz = spline_weights<T>(z * (T)mi.invh[2], P, wz);
+  const int Kx = mi.K[0], Ky = mi.K[1], Kz = mi.K[2];
+  int iy = fy + ry; iy = (iy % Ky + Ky) % Ky;
+  int iz = fz + rz; iz = (iz % Kz + Kz) % Kz;
+  T qw = q * wy[ry] * wz[rz];
+  T* row = rho_all + (size_t)frame * mi.M + ((size_t)iz * Ky + iy) * Kx;
+  for (int t = 0; t < P; ++t) {
+    int ix = fx + t; ix = (ix % Kx + Kx) % Kx;
+    atomicAdd(row + ix, qw * wx[t]);
+  }
+}
+
+// rho[touch[t]] = sum_k val[k] q[col[k]] over rowptr[t] <= k < rowptr[t+1]
+template <typename T>
+__global__ __launch_bounds__(256) void k_spread_elec(int n_touch, const int* __restrict__ touch,
+                                                     const int* __restrict__ rowptr,
+                                                     const int* __restrict__ col,
+                                                     const T* __restrict__ val,
+                                                     const double* __restrict__ q_all, size_t q_stride,
+                                                     T* __restrict__ rho_all, int M) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int frame = blockIdx.y;
+  if (t >= n_touch) return;
+  const double* q = q_all + (size_t)frame * q_stride;
+  T acc = 0;
+  for (int k = rowptr[t]; k < rowptr[t + 1]; ++k) acc += val[k] * (T)q[col[k]];
+  rho_all[(size_t)frame * M + touch[t]] = acc;
+}
+
+// b_i = -(phi_real_i + sum_t gw[i][t] phi[gidx[i][t]]): one wavefront per atom
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_b(int n_elec, int P3, const int* __restrict__ gidx,
+                                                  const T* __restrict__ gw, const T* __restrict__ phi_all,
+                                                  int M, const T* __restrict__ phi_real_all,
+                                                  double* __restrict__ b_all) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+  const int frame = blockIdx.y;
+  if (i >= n_elec) return;
+  const T* phi = phi_all + (size_t)frame * M;
+  T acc = 0;
+  for (int t = lane; t < P3; t += WAVE) acc += gw[(size_t)i * P3 + t] * phi[gidx[(size_t)i * P3 + t]];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    size_t o = (size_t)frame * n_elec + i;
+    b_all[o] = -((double)phi_real_all[o] + (double)acc);
+  }
+}
+
+template <typename T>
+void launch_spread_sites_t(hipStream_t s, int n_frames, const MeshInfo& mi, const SiteSet<T>& st, T* rho) {
+  int n = st.n * mi.order * mi.order;
+  dim3 grid((n + 255) / 256, n_frames);
+  hipLaunchKernelGGL(k_spread_sites<T>, grid, dim3(256), 0, s, mi, st, rho);
+}
+
+template <typename T>
+void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
+                          const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M) {
+  dim3 grid((n_touch + 255) / 256, n_frames);
+  hipLaunchKernelGGL(k_spread_elec<T>, grid, dim3(256), 0, s, n_touch, touch, rowptr, col, val, q,
+                     q_stride, rho, M);
+}
+
+template <typename T>
+void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const int* gidx, const T* gw,
+                       const T* phi, int M, const T* phi_real, double* b) {
+  dim3 grid((n_elec + 3) / 4, n_frames);
+  hipLaunchKernelGGL(k_gather_b<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b);
+}
+
+template void launch_spread_sites_t<double>(hipStream_t, int, const MeshInfo&, const SiteSet<double>&, double*);
+template void launch_spread_sites_t<float>(hipStream_t, int, const MeshInfo&, const SiteSet<float>&, float*);
+template void launch_spread_elec_t<double>(hipStream_t, int, int, const int*, const int*, const int*,
+                                           const double*, const double*, size_t, double*, int);
+template void launch_spread_elec_t<float>(hipStream_t, int, int, const int*, const int*, const int*,
+                                          const float*, const double*, size_t, float*, int);
+template void launch_gather_b_t<double>(hipStream_t, int, int, int, const int*, const double*, const double*,
+                                        int, const double*, double*);
+template void launch_gather_b_t<float>(hipStream_t, int, int, int, const int*, const float*, const float*,
+                                       int, const float*, double*);
+
+}  // namespace cpm
