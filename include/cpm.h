@@ -157,6 +157,19 @@ enum {
 };
 long long cpm_get_buffer(cpm_ctx* ctx, int which, void* host_out);
 
+/* Kernels of the step, for timing.  cpm_replay_kernel re-enqueues the most
+ * recent launch of one of them `reps` times with the same arguments on the
+ * context's stream (callers bracket it with events to time one kernel).  It
+ * overwrites internal buffers only; outputs of the last step stay valid.
+ * CPM_ESTATE if that kernel has not run yet. */
+enum {
+  CPM_KERNEL_BIN = 0, CPM_KERNEL_REAL_B, CPM_KERNEL_SPREAD_SITES, CPM_KERNEL_FFT_XY_FWD,
+  CPM_KERNEL_FFT_Z_POT, CPM_KERNEL_FFT_XY_INV, CPM_KERNEL_GATHER_B, CPM_KERNEL_CHARGES,
+  CPM_KERNEL_SPREAD_ELEC, CPM_KERNEL_FFT_XY_FWD_E, CPM_KERNEL_FFT_Z_FIELD, CPM_KERNEL_FFT_XY_INV_E,
+  CPM_KERNEL_SITE_FORCES, CPM_KERNEL_ENERGY, CPM_KERNEL_COUNT
+};
+int cpm_replay_kernel(cpm_ctx* ctx, int kernel, int reps);
+
 /* Synchronise the stream and report errors raised inside kernels since the
  * last call (CPM_ENONFINITE for non-finite positions), then clear them. */
 int cpm_sync_status(cpm_ctx* ctx);

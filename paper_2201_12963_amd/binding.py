@@ -22,13 +22,15 @@ FINITE_FIELD, DOUBLED_CELL = 0, 1
 KSPACE_EWALD, KSPACE_PPPM = 0, 1
 FP64, MIXED = 0, 1
 BUF_CELL_START, BUF_SITE_ORDER, BUF_PHI_REAL, BUF_B, BUF_RHO_MESH, BUF_PHI_MESH, BUF_FIELD_MESH, BUF_NCELL = range(8)
+KERNELS = ("bin", "real_b", "spread_sites", "fft_xy_fwd", "fft_z_pot", "fft_xy_inv", "gather_b", "charges",
+           "spread_elec", "fft_xy_fwd_e", "fft_z_field", "fft_xy_inv_e", "site_forces", "energy")
 
 _STATUS_NAMES = {0: "CPM_OK", -1: "CPM_EINVAL", -2: "CPM_ESTATE", -3: "CPM_ENOTSPD", -4: "CPM_EDEVICE",
                  -5: "CPM_ENOMEM", -6: "CPM_ENONFINITE"}
 
 EXPORTED = ("cpm_create", "cpm_set_stream", "cpm_build_elastance", "cpm_solve", "cpm_solve_batch",
             "cpm_grad", "cpm_get_matrix", "cpm_set_matrix", "cpm_get_buffer", "cpm_sync_status",
-            "cpm_last_error", "cpm_destroy")
+            "cpm_last_error", "cpm_destroy", "cpm_replay_kernel")
 
 
 class CpmError(RuntimeError):
@@ -83,6 +85,8 @@ def load_library():
     lib.cpm_set_matrix.restype = ip
     lib.cpm_get_buffer.argtypes = [vp, ip, vp]
     lib.cpm_get_buffer.restype = ctypes.c_longlong
+    lib.cpm_replay_kernel.argtypes = [vp, ip, ip]
+    lib.cpm_replay_kernel.restype = ip
     lib.cpm_sync_status.argtypes = [vp]
     lib.cpm_sync_status.restype = ip
     lib.cpm_last_error.argtypes = [vp]
@@ -215,6 +219,10 @@ class Context:
         if r < 0:
             self._check(int(r))
         return out
+
+    def replay_kernel(self, kernel: int, reps: int):
+        """Re-enqueue the last launch of one step kernel `reps` times (timing hook)."""
+        self._check(self._lib.cpm_replay_kernel(self._ctx, int(kernel), int(reps)))
 
     def sync_status(self) -> int:
         return int(self._lib.cpm_sync_status(self._ctx))

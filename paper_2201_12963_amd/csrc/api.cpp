@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,9 @@ struct cpm_ctx {
   double *d_c = nullptr, *d_d = nullptr, *d_ze = nullptr, *d_e1 = nullptr;
   double *d_A = nullptr, *d_S = nullptr, *d_Sc = nullptr;
   float* d_Sf = nullptr;
+  unsigned short *d_Ssplit = nullptr, *d_bsplit = nullptr;   // three bf16 terms each
+  unsigned char* d_sub1 = nullptr;
+  int n_pad = 0;
   ElecSet<double> el{};
   ElecSet<float> elf{};
   double* d_site_q = nullptr;
@@ -70,6 +74,12 @@ struct cpm_ctx {
   float *d_fx = nullptr, *d_fy = nullptr, *d_fz = nullptr, *d_fq = nullptr;
   double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
   double *d_ek = nullptr, *d_ftmp = nullptr, *d_energy_tmp = nullptr, *d_lam = nullptr, *d_scalar = nullptr;
+  double *d_g = nullptr, *d_qa = nullptr, *d_dv = nullptr;
+  int cap_dv = 0;
+  // k-space field mesh of the electrode charges S c alone (batched dV sweep)
+  double* d_ESc = nullptr;
+  float* d_EScf = nullptr;
+  bool esc_ready = false;
   double* d_phir = nullptr;
   float* d_phirf = nullptr;
   int n_ek = 0;
@@ -91,6 +101,9 @@ struct cpm_ctx {
   int nk = 0;
   double *d_kv = nullptr, *d_ew = nullptr, *d_Esite = nullptr;
   double2 *d_eph = nullptr, *d_rhok = nullptr, *d_rhok_all = nullptr;
+
+  // ---- most recent launch of each step kernel, for timing (cpm_replay_kernel)
+  std::function<void()> last_launch[CPM_KERNEL_COUNT];
 
   // ---- graphs
   std::vector<GraphEntry> graphs;
@@ -266,6 +279,9 @@ int alloc_frames(cpm_ctx* c, int nf) {
   TRY(dalloc(c, &c->d_Q0, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_qint, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_lam, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_g, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_qa, (size_t)nf * ne));
+  if (mixed) TRY(dalloc(c, &c->d_bsplit, (size_t)3 * nf * c->n_pad));
   TRY(dalloc(c, &c->d_usite, (size_t)nf * ns));
   TRY(dalloc(c, &c->d_ftmp, (size_t)nf * 3 * ns));
   TRY(dalloc(c, &c->d_energy_tmp, (size_t)nf * 2));
@@ -305,6 +321,13 @@ int alloc_frames(cpm_ctx* c, int nf) {
 }
 
 // ------------------------------------------------------------ the step
+
+// launch now and remember the launch (arguments by value) for cpm_replay_kernel
+template <typename F>
+void rec(cpm_ctx* c, int id, F&& f) {
+  c->last_launch[id] = std::function<void()>(f);
+  f();
+}
 
 template <typename T> struct Bufs;
 template <> struct Bufs<double> {
@@ -351,20 +374,30 @@ void enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool keep_spectrum) {
   using T2 = typename B::T2;
   hipStream_t s = c->stream;
   const bool mixed = std::is_same<T, float>::value;
-  launch_bin_sites(s, nf, c->n_site, xyz, (size_t)3 * c->n_site, c->d_site_q, c->cell, c->d_cell_start, c->d_order,
-                   c->d_sx, c->d_sy, c->d_sz, c->d_sq, mixed ? c->d_fx : nullptr, mixed ? c->d_fy : nullptr,
-                   mixed ? c->d_fz : nullptr, mixed ? c->d_fq : nullptr, c->d_zdip, c->d_status,
-                   (c->kspace == CPM_KSPACE_PPPM && !mixed) ? c->d_rho : nullptr, c->mi.M,
-                   (c->kspace == CPM_KSPACE_PPPM && mixed) ? c->d_rhof : nullptr);
+  rec(c, CPM_KERNEL_BIN, [=] {
+    launch_bin_sites(s, nf, c->n_site, xyz, (size_t)3 * c->n_site, c->d_site_q, c->cell, c->d_cell_start,
+                     c->d_order, c->d_sx, c->d_sy, c->d_sz, c->d_sq, mixed ? c->d_fx : nullptr,
+                     mixed ? c->d_fy : nullptr, mixed ? c->d_fz : nullptr, mixed ? c->d_fq : nullptr, c->d_zdip,
+                     c->d_status, (c->kspace == CPM_KSPACE_PPPM && !mixed) ? c->d_rho : nullptr, c->mi.M,
+                     (c->kspace == CPM_KSPACE_PPPM && mixed) ? c->d_rhof : nullptr);
+  });
   SiteSet<T> st = B::sites(c);
-  launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c));
+  rec(c, CPM_KERNEL_REAL_B, [=] { launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c)); });
   if (c->kspace == CPM_KSPACE_PPPM) {
-    launch_spread_sites_t<T>(s, nf, c->mi, st, B::rho(c));
-    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho(c), nullptr, B::c1(c), nullptr, nullptr);
-    launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr, keep_spectrum ? B::save(c) : nullptr,
-                          0, c->d_ek);
-    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
-    launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b);
+    rec(c, CPM_KERNEL_SPREAD_SITES, [=] { launch_spread_sites_t<T>(s, nf, c->mi, st, B::rho(c)); });
+    rec(c, CPM_KERNEL_FFT_XY_FWD, [=] {
+      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho(c), nullptr, B::c1(c), nullptr, nullptr);
+    });
+    rec(c, CPM_KERNEL_FFT_Z_POT, [=] {
+      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
+                            keep_spectrum ? B::save(c) : nullptr, 0, c->d_ek);
+    });
+    rec(c, CPM_KERNEL_FFT_XY_INV, [=] {
+      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
+    });
+    rec(c, CPM_KERNEL_GATHER_B, [=] {
+      launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b);
+    });
   } else {
     SiteSet<double> sd = Bufs<double>::sites(c);
     launch_ewald_sf(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok, c->d_ek);
@@ -387,17 +420,25 @@ void enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Forc
   fa.qa_frame_stride = qa_stride;
   fa.mi = c->mi;
   if (c->kspace == CPM_KSPACE_PPPM) {
-    launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
-                            B::rho_e(c), c->mi.M);
-    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
-    launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr);
+    rec(c, CPM_KERNEL_SPREAD_ELEC, [=] {
+      launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
+                              B::rho_e(c), c->mi.M);
+    });
+    rec(c, CPM_KERNEL_FFT_XY_FWD_E, [=] {
+      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
+    });
+    rec(c, CPM_KERNEL_FFT_Z_FIELD, [=] {
+      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr);
+    });
     // c1 -> Ex (re), Ey (im); c2 -> Ez
     T* E = B::E(c);
     const size_t M = c->mi.M;
     // field meshes are [frame][3][M]
-    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, E, E + M, 3 * M);
-    launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c2(c), nullptr, E + 2 * M, nullptr,
-                           3 * M);
+    rec(c, CPM_KERNEL_FFT_XY_INV_E, [=] {
+      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, E, E + M, 3 * M);
+      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c2(c), nullptr, E + 2 * M, nullptr,
+                             3 * M);
+    });
     fa.Ea = E;
     fa.Ea_frame_stride = 3 * M;
     fa.Esite = nullptr;
@@ -408,7 +449,7 @@ void enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Forc
     fa.Ea = nullptr;
     fa.Esite = c->d_Esite;
   }
-  launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa);
+  rec(c, CPM_KERNEL_SITE_FORCES, [=] { launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa); });
 }
 
 template <typename T>
@@ -416,7 +457,16 @@ int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, doubl
   hipStream_t s = c->stream;
   const bool need_forces = f_out || e_out;
   enqueue_b<T>(c, 1, xyz, need_forces);
-  launch_charges(s, 1, c->n_elec, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q_out);
+  if (std::is_same<T, float>::value) {
+    // FP32 GEMV on centred b, FP64 re-projection, then q = Q0 + dV S c
+    rec(c, CPM_KERNEL_CHARGES, [=] {
+      launch_charges_f32(s, 1, c->n_elec, c->d_Sf, c->d_b, c->d_Q0);
+      launch_reproject(s, 1, c->n_elec, c->d_sub1, c->d_Q0);
+      launch_axpy(s, c->n_elec, c->d_Q0, c->d_Sc, dv, q_out);
+    });
+  } else {
+    rec(c, CPM_KERNEL_CHARGES, [=] { launch_charges(s, 1, c->n_elec, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q_out); });
+  }
   if (need_forces) {
     ForceArgs<T> fa{};
     fa.out_scale = 1.0;
@@ -435,7 +485,98 @@ int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, doubl
     ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
     ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
     ea.n_dv = 1; ea.dv = nullptr; ea.dv_single = dv; ea.out = e_out;
-    launch_energy(s, 1, ea);
+    rec(c, CPM_KERNEL_ENERGY, [=] { launch_energy(s, 1, ea); });
+  }
+  return CPM_OK;
+}
+
+// Adjoint of L = sum (q - t)^2 + U_coul through q* = S v(R)
+template <typename T>
+int enqueue_grad(cpm_ctx* c, const double* xyz, double dv, const double* t, double* loss, double* dldx,
+                 double* dldv, double* q_out) {
+  hipStream_t s = c->stream;
+  const int n = c->n_elec;
+  double* q = q_out ? q_out : c->d_qint;
+  enqueue_b<T>(c, 1, xyz, true);
+  launch_charges(s, 1, n, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q);
+  launch_adjoint_rhs(s, n, q, t, c->d_c, dv, c->d_g);
+  launch_charges(s, 1, n, c->d_S, c->d_g, c->d_Sc, 0.0, c->d_lam, nullptr);    // lambda = S g
+  launch_sub(s, n, q, c->d_lam, c->d_qa);
+  ForceArgs<T> fa{};
+  fa.out_scale = -1.0;
+  fa.field = 0.0;
+  fa.f_out = dldx;
+  fa.f_frame_stride = 3 * (size_t)c->n_site;
+  fa.n_dv = 1;
+  fa.u_site = c->d_usite;
+  enqueue_forces<T>(c, 1, c->d_qa, n, fa);
+  EnergyArgs ea{};
+  ea.n_elec = n; ea.n_site = c->n_site; ea.n_ek = c->n_ek;
+  ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
+  ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
+  ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
+  ea.n_dv = 1; ea.dv = nullptr; ea.dv_single = dv; ea.out = c->d_energy_tmp;
+  launch_energy(s, 1, ea);
+  launch_grad_finish(s, n, q, t, c->d_lam, c->d_c, c->d_energy_tmp, loss, dldv);
+  return CPM_OK;
+}
+
+// The field mesh of the electrode charges S c alone: frame-independent, made once.
+template <typename T>
+void enqueue_esc_mesh(cpm_ctx* c, T* out) {
+  using B = Bufs<T>;
+  using T2 = typename B::T2;
+  hipStream_t s = c->stream;
+  const size_t M = c->mi.M;
+  launch_spread_elec_t<T>(s, 1, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), c->d_Sc, c->n_elec,
+                          B::rho_e(c), c->mi.M);
+  launch_fft_xy_t<T, T2>(s, 1, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
+  launch_fft_z_t<T, T2>(s, 1, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), nullptr, 0, nullptr);
+  launch_fft_xy_t<T, T2>(s, 1, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, out, out + M, 3 * M);
+  launch_fft_xy_t<T, T2>(s, 1, c->px, c->py, c->mi.K[2], 1, nullptr, B::c2(c), nullptr, out + 2 * M, nullptr, 3 * M);
+}
+
+// Frames [0, nf) of a batch: b for every frame, Q0 = S B in one GEMM, the
+// forces F_A(Q0) + dV (F_B(S c) + field) and energies for every dV, and the
+// charges Q0 + dV S c.
+template <typename T>
+int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out, double* f_out, double* e_out) {
+  hipStream_t s = c->stream;
+  const int n = c->n_elec;
+  const bool need_forces = f_out || e_out;
+  enqueue_b<T>(c, nf, xyz, need_forces);
+  // Q0[f][i] = sum_j B[f][j] S[i][j]
+  if (std::is_same<T, float>::value) {
+    launch_split_b(s, nf, n, c->n_pad, c->d_b, c->d_bsplit);
+    launch_gemm_bf16x6(s, nf, n, c->n_pad, c->d_bsplit, (size_t)nf * c->n_pad, c->d_Ssplit, (size_t)n * c->n_pad,
+                       c->d_Q0, n);
+    launch_reproject(s, nf, n, c->d_sub1, c->d_Q0);
+  } else {
+    launch_gemm_nt(s, nf, n, n, 1.0, c->d_b, n, c->d_S, n, 0.0, c->d_Q0, n);
+  }
+  launch_expand_charges(s, nf, n, n_dv, c->d_dv, c->d_Q0, c->d_Sc, q_out);
+  if (need_forces) {
+    ForceArgs<T> fa{};
+    fa.out_scale = 1.0;
+    fa.field = 0.0;
+    fa.fieldb = (c->geometry == CPM_FINITE_FIELD) ? -1.0 / c->box[2] : 0.0;
+    fa.qb = c->d_Sc;
+    if (c->kspace == CPM_KSPACE_PPPM) fa.Eb = std::is_same<T, float>::value ? (const T*)c->d_EScf : (const T*)c->d_ESc;
+    fa.f_out = f_out ? f_out : c->d_ftmp;
+    fa.f_frame_stride = f_out ? (size_t)n_dv * 3 * c->n_site : 0;
+    fa.n_dv = f_out ? n_dv : 0;
+    fa.dv = c->d_dv;
+    fa.u_site = c->d_usite;
+    enqueue_forces<T>(c, nf, c->d_Q0, n, fa);
+  }
+  if (e_out) {
+    EnergyArgs ea{};
+    ea.n_elec = n; ea.n_site = c->n_site; ea.n_ek = c->n_ek;
+    ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
+    ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
+    ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
+    ea.n_dv = n_dv; ea.dv = c->d_dv; ea.dv_single = 0.0; ea.out = e_out;
+    launch_energy(s, nf, ea);
   }
   return CPM_OK;
 }
@@ -579,7 +720,13 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   if ((r = dalloc(c, &c->d_A, (size_t)ne * ne)) || (r = dalloc(c, &c->d_S, (size_t)ne * ne)) ||
       (r = dalloc(c, &c->d_Sc, ne)) || (r = dalloc(c, &c->d_status, 4)) || (r = dalloc(c, &c->d_scalar, 8)))
     return bad(r);
-  if (c->precision == CPM_MIXED && (r = dalloc(c, &c->d_Sf, (size_t)ne * ne))) return bad(r);
+  c->n_pad = (ne + 15) / 16 * 16;
+  if (c->precision == CPM_MIXED) {
+    if (ne > 4096) { fail(c, CPM_EINVAL, "mixed precision supports up to 4096 electrode atoms"); return bad(CPM_EINVAL); }
+    if ((r = dalloc(c, &c->d_Sf, (size_t)ne * ne)) || (r = dalloc(c, &c->d_Ssplit, (size_t)3 * ne * c->n_pad)))
+      return bad(r);
+  }
+  if (c->geometry == CPM_DOUBLED_CELL && (r = upload(c, &c->d_sub1, c->sub))) return bad(r);
   if (hipMemset(c->d_status, 0, 4 * sizeof(int)) != hipSuccess) { fail(c, CPM_EDEVICE, "memset"); return bad(CPM_EDEVICE); }
 
   if (c->kspace == CPM_KSPACE_PPPM) {
@@ -766,6 +913,7 @@ int cpm_build_elastance(cpm_ctx* c) {
     launch_rank1(s, n, c->d_S, u, c->d_scalar);             // S -= w w^T / e1.w
   }
   launch_matvec(s, n, c->d_S, c->d_c, c->d_Sc);            // S c
+  if (c->precision == CPM_MIXED) launch_split_matrix(s, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
   TRY(check_launch(c));
   HIP_TRY(c, hipStreamSynchronize(s));
   // the chunk buffers are released now (they are large)
@@ -774,6 +922,7 @@ int cpm_build_elastance(cpm_ctx* c) {
     c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
   }
   c->built = true;
+  c->esc_ready = false;
   free_graphs(c);
   return CPM_OK;
 }
@@ -783,8 +932,10 @@ int cpm_set_matrix(cpm_ctx* c, const double* host_S) {
   const int n = c->n_elec;
   HIP_TRY(c, hipMemcpy(c->d_S, host_S, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice));
   launch_matvec(c->stream, n, c->d_S, c->d_c, c->d_Sc);
+  if (c->precision == CPM_MIXED) launch_split_matrix(c->stream, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->built = true;
+  c->esc_ready = false;
   free_graphs(c);
   return CPM_OK;
 }
@@ -838,13 +989,59 @@ int cpm_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, double* f
 int cpm_solve_batch(cpm_ctx* c, int n_frames, const double* xyz, int n_dv, const double* dv_host, double* q_out,
                     double* f_out, double* e_out) {
   if (!c) return CPM_EINVAL;
-  return fail(c, CPM_EINVAL, "cpm_solve_batch: not available in this build");
+  if (!c->built) return fail(c, CPM_ESTATE, "cpm_solve_batch before cpm_build_elastance");
+  if (n_frames < 0 || n_dv < 1 || !dv_host || (n_frames > 0 && (!xyz || !q_out)))
+    return fail(c, CPM_EINVAL, "bad batch arguments");
+  if (c->kspace != CPM_KSPACE_PPPM) return fail(c, CPM_EINVAL, "the batched form runs on the PPPM k-space");
+  if (n_frames == 0) return CPM_OK;
+  for (int v = 0; v < n_dv; ++v)
+    if (!std::isfinite(dv_host[v])) return fail(c, CPM_ENONFINITE, "non-finite dV");
+  // frames go through in chunks that fit the per-frame scratch
+  const int chunk_max = std::max(1, std::min(n_frames, (int)std::max<long>(1, std::atol(
+      std::getenv("CPM_BATCH_CHUNK") ? std::getenv("CPM_BATCH_CHUNK") : "4096"))));
+  if (c->cap_frames < chunk_max) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int r = alloc_frames(c, chunk_max);
+    if (r) return r;
+  }
+  if (c->cap_dv < n_dv) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int r = dalloc(c, &c->d_dv, n_dv);
+    if (r) return r;
+    c->cap_dv = n_dv;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->d_dv, dv_host, n_dv * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const bool mixed = c->precision == CPM_MIXED;
+  if ((f_out || e_out) && c->kspace == CPM_KSPACE_PPPM && !c->esc_ready) {
+    int r = mixed ? dalloc(c, &c->d_EScf, 3 * (size_t)c->mi.M) : dalloc(c, &c->d_ESc, 3 * (size_t)c->mi.M);
+    if (r) return r;
+    if (mixed) enqueue_esc_mesh<float>(c, c->d_EScf);
+    else enqueue_esc_mesh<double>(c, c->d_ESc);
+    c->esc_ready = true;
+  }
+  const size_t xs = (size_t)3 * c->n_site;
+  for (int f0 = 0; f0 < n_frames; f0 += chunk_max) {
+    int nf = std::min(chunk_max, n_frames - f0);
+    double* q = q_out + (size_t)f0 * n_dv * c->n_elec;
+    double* f = f_out ? f_out + (size_t)f0 * n_dv * xs : nullptr;
+    double* e = e_out ? e_out + (size_t)f0 * n_dv * 2 : nullptr;
+    int r = mixed ? enqueue_batch<float>(c, nf, xyz + f0 * xs, n_dv, q, f, e)
+                  : enqueue_batch<double>(c, nf, xyz + f0 * xs, n_dv, q, f, e);
+    if (r) return r;
+  }
+  return check_launch(c);
 }
 
 int cpm_grad(cpm_ctx* c, const double* xyz, double dv, const double* q_target, double* loss_out, double* dl_dxyz,
              double* dl_ddv, double* q_out) {
   if (!c) return CPM_EINVAL;
-  return fail(c, CPM_EINVAL, "cpm_grad: not available in this build");
+  if (!c->built) return fail(c, CPM_ESTATE, "cpm_grad before cpm_build_elastance");
+  if (!xyz || !q_target || !loss_out || !dl_dxyz || !dl_ddv) return fail(c, CPM_EINVAL, "null argument");
+  if (!std::isfinite(dv)) return fail(c, CPM_ENONFINITE, "non-finite dV");
+  int r = c->precision == CPM_MIXED ? enqueue_grad<float>(c, xyz, dv, q_target, loss_out, dl_dxyz, dl_ddv, q_out)
+                                    : enqueue_grad<double>(c, xyz, dv, q_target, loss_out, dl_dxyz, dl_ddv, q_out);
+  if (r) return r;
+  return check_launch(c);
 }
 
 int cpm_get_matrix(cpm_ctx* c, int which, double* host_out) {
@@ -891,6 +1088,14 @@ long long cpm_get_buffer(cpm_ctx* c, int which, void* host_out) {
     HIP_TRY(c, hipMemcpy(host_out, src, count * elt, hipMemcpyDeviceToHost));
   }
   return (long long)count;
+}
+
+int cpm_replay_kernel(cpm_ctx* c, int kernel, int reps) {
+  if (!c) return CPM_EINVAL;
+  if (kernel < 0 || kernel >= CPM_KERNEL_COUNT || reps < 0) return fail(c, CPM_EINVAL, "bad kernel id or count");
+  if (!c->last_launch[kernel]) return fail(c, CPM_ESTATE, "kernel %d has not run yet", kernel);
+  for (int i = 0; i < reps; ++i) c->last_launch[kernel]();
+  return check_launch(c);
 }
 
 int cpm_sync_status(cpm_ctx* c) {

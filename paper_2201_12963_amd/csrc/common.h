@@ -48,6 +48,15 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// sum over a 256-thread workgroup (red: 4 doubles of LDS); every thread gets the total
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
 __device__ __forceinline__ double wrap01(double t) { return t - floor(t); }
 
 // cell index of a coordinate along one axis, bit-identical to the integer
@@ -232,5 +241,19 @@ void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const d
 void launch_energy(hipStream_t s, int n_frames, const EnergyArgs& ea);
 void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
                            const double* Sc, double* q);
+
+void launch_adjoint_rhs(hipStream_t s, int n, const double* q, const double* t, const double* c, double dv, double* g);
+void launch_sub(hipStream_t s, int n, const double* a, const double* b, double* out);
+void launch_grad_finish(hipStream_t s, int n, const double* q, const double* t, const double* lam, const double* c,
+                        const double* energy, double* loss, double* dldv);
+
+// mixed precision (k_mixed.hip)
+void launch_split_matrix(hipStream_t s, int n, int n_pad, const double* S, float* Sf, unsigned short* split);
+void launch_split_b(hipStream_t s, int n_frames, int n, int n_pad, const double* b, unsigned short* split);
+void launch_charges_f32(hipStream_t s, int n_frames, int n, const float* Sf, const double* b, double* Q0);
+void launch_reproject(hipStream_t s, int n_frames, int n, const unsigned char* sub1, double* Q0);
+void launch_gemm_bf16x6(hipStream_t s, int M, int N, int K, const unsigned short* A, size_t a_plane,
+                        const unsigned short* B, size_t b_plane, double* D, int ldd);
+void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out);
 
 }  // namespace cpm

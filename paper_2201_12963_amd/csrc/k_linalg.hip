@@ -333,7 +333,54 @@ __global__ __launch_bounds__(256) void k_expand_charges(int n_elec, int n_dv, co
   q[((size_t)f * n_dv + v) * n_elec + i] = Q0[(size_t)f * n_elec + i] + dv[v] * Sc[i];
 }
 
+// ------------------------------------------------------------ adjoint
+
+// g = 2 (q - t) + dv c   (the right-hand side of lambda = S g)
+__global__ __launch_bounds__(256) void k_adjoint_rhs(int n, const double* __restrict__ q, const double* __restrict__ t,
+                                                     const double* __restrict__ c, double dv, double* __restrict__ g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = 2.0 * (q[i] - t[i]) + dv * c[i];
+}
+
+// qa = q - lambda  (electrode charges of the adjoint force pass)
+__global__ __launch_bounds__(256) void k_sub(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                             double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+// loss = sum (q - t)^2 + U_coul;  dL/ddV = lambda . c   (one workgroup)
+__global__ __launch_bounds__(256) void k_grad_finish(int n, const double* __restrict__ q, const double* __restrict__ t,
+                                                     const double* __restrict__ lam, const double* __restrict__ c,
+                                                     const double* __restrict__ energy, double* __restrict__ loss,
+                                                     double* __restrict__ dldv) {
+  __shared__ double red[4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double d = q[i] - t[i];
+    a += d * d;
+    b += lam[i] * c[i];
+  }
+  double A = block_sum(a, red);
+  double B = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    loss[0] = A + energy[0];
+    dldv[0] = B;
+  }
+}
+
 // ------------------------------------------------------------ launchers
+
+void launch_adjoint_rhs(hipStream_t s, int n, const double* q, const double* t, const double* c, double dv, double* g) {
+  hipLaunchKernelGGL(k_adjoint_rhs, dim3((n + 255) / 256), dim3(256), 0, s, n, q, t, c, dv, g);
+}
+void launch_sub(hipStream_t s, int n, const double* a, const double* b, double* out) {
+  hipLaunchKernelGGL(k_sub, dim3((n + 255) / 256), dim3(256), 0, s, n, a, b, out);
+}
+void launch_grad_finish(hipStream_t s, int n, const double* q, const double* t, const double* lam, const double* c,
+                        const double* energy, double* loss, double* dldv) {
+  hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(256), 0, s, n, q, t, lam, c, energy, loss, dldv);
+}
 
 void launch_elastance_real(hipStream_t s, int n, const double* ex, const double* ey, const double* ez,
                            const Cell& cell, double alpha, double eta, double rcut, double self_term, double* A) {
