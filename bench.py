@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # FP64 vector (and FP64 matrix) peak
 BF16_PEAK_TFLOPS = 2500.0      # dense bf16 matrix peak
-REPLAYS = 200
+REPLAYS = int(os.environ.get("CPM_BENCH_REPLAYS", "200"))
 
 # Algorithmic FP64 operation counts of the per-pair formulas (erfc ~ 20 and
 # exp ~ 10 operations as polynomial/rational evaluations, plus the arithmetic

@@ -69,7 +69,9 @@ struct cpm_ctx {
 
   // ---- per-step buffers (capacity cap_frames)
   int cap_frames = 0;
-  int *d_cell_start = nullptr, *d_order = nullptr, *d_status = nullptr;
+  int *d_cell_start = nullptr, *d_order = nullptr, *d_status = nullptr, *d_wfirst = nullptr;
+  double* d_sw = nullptr;
+  float* d_swf = nullptr;
   double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
   float *d_fx = nullptr, *d_fy = nullptr, *d_fz = nullptr, *d_fq = nullptr;
   double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
@@ -275,6 +277,11 @@ int alloc_frames(cpm_ctx* c, int nf) {
   }
   TRY(dalloc(c, &c->d_phir, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_zdip, (size_t)nf));
+  if (c->kspace == CPM_KSPACE_PPPM) {
+    TRY(dalloc(c, &c->d_wfirst, (size_t)nf * 3 * ns));
+    if (mixed) TRY(dalloc(c, &c->d_swf, (size_t)nf * 3 * c->order * ns));
+    else TRY(dalloc(c, &c->d_sw, (size_t)nf * 3 * c->order * ns));
+  }
   TRY(dalloc(c, &c->d_b, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_Q0, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_qint, (size_t)nf * ne));
@@ -333,7 +340,8 @@ template <typename T> struct Bufs;
 template <> struct Bufs<double> {
   using T2 = double2;
   static SiteSet<double> sites(cpm_ctx* c) {
-    return SiteSet<double>{c->d_sx, c->d_sy, c->d_sz, c->d_sq, c->d_order, c->d_cell_start, c->n_site};
+    return SiteSet<double>{c->d_sx, c->d_sy, c->d_sz, c->d_sq, c->d_order, c->d_cell_start, c->n_site,
+                           c->d_wfirst, c->d_sw};
   }
   static const ElecSet<double>& elec(cpm_ctx* c) { return c->el; }
   static double* phir(cpm_ctx* c) { return c->d_phir; }
@@ -347,11 +355,13 @@ template <> struct Bufs<double> {
   static const double* G(cpm_ctx* c) { return c->d_G; }
   static const double* gw(cpm_ctx* c) { return c->d_gw; }
   static const double* val(cpm_ctx* c) { return c->d_val; }
+  static double* sw(cpm_ctx* c) { return c->d_sw; }
 };
 template <> struct Bufs<float> {
   using T2 = float2;
   static SiteSet<float> sites(cpm_ctx* c) {
-    return SiteSet<float>{c->d_fx, c->d_fy, c->d_fz, c->d_fq, c->d_order, c->d_cell_start, c->n_site};
+    return SiteSet<float>{c->d_fx, c->d_fy, c->d_fz, c->d_fq, c->d_order, c->d_cell_start, c->n_site,
+                          c->d_wfirst, c->d_swf};
   }
   static const ElecSet<float>& elec(cpm_ctx* c) { return c->elf; }
   static float* phir(cpm_ctx* c) { return c->d_phirf; }
@@ -365,6 +375,7 @@ template <> struct Bufs<float> {
   static const float* G(cpm_ctx* c) { return c->d_Gf; }
   static const float* gw(cpm_ctx* c) { return c->d_gwf; }
   static const float* val(cpm_ctx* c) { return c->d_valf; }
+  static float* sw(cpm_ctx* c) { return c->d_swf; }
 };
 
 // Stage 1: positions -> binned sites -> b (frames 0..nf-1)
@@ -378,11 +389,17 @@ void enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool keep_spectrum) {
     launch_bin_sites(s, nf, c->n_site, xyz, (size_t)3 * c->n_site, c->d_site_q, c->cell, c->d_cell_start,
                      c->d_order, c->d_sx, c->d_sy, c->d_sz, c->d_sq, mixed ? c->d_fx : nullptr,
                      mixed ? c->d_fy : nullptr, mixed ? c->d_fz : nullptr, mixed ? c->d_fq : nullptr, c->d_zdip,
-                     c->d_status, (c->kspace == CPM_KSPACE_PPPM && !mixed) ? c->d_rho : nullptr, c->mi.M,
-                     (c->kspace == CPM_KSPACE_PPPM && mixed) ? c->d_rhof : nullptr);
+                     c->d_status, nullptr, c->mi.M, nullptr);
   });
   SiteSet<T> st = B::sites(c);
-  rec(c, CPM_KERNEL_REAL_B, [=] { launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c)); });
+  // the real-space kernel also clears the site charge mesh the spread accumulates
+  // into and computes the sites' B-spline weights
+  rec(c, CPM_KERNEL_REAL_B, [=] {
+    const bool pppm = c->kspace == CPM_KSPACE_PPPM;
+    launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c),
+                       pppm ? B::rho(c) : nullptr, c->mi, pppm ? c->d_wfirst : nullptr,
+                       pppm ? B::sw(c) : nullptr);
+  });
   if (c->kspace == CPM_KSPACE_PPPM) {
     rec(c, CPM_KERNEL_SPREAD_SITES, [=] { launch_spread_sites_t<T>(s, nf, c->mi, st, B::rho(c)); });
     rec(c, CPM_KERNEL_FFT_XY_FWD, [=] {
@@ -612,6 +629,8 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     return fail(nullptr, CPM_EINVAL, "alpha must be below eta/sqrt(2) (A would not be positive definite)");
   if (!(d->alpha_build > 0) || !(d->rcut_build > 0) || !(d->kcut_build > 0))
     return fail(nullptr, CPM_EINVAL, "elastance build parameters must be positive");
+  if (d->alpha * d->rcut > 8.0)
+    return fail(nullptr, CPM_EINVAL, "alpha * rcut must not exceed 8 (the real-space sums are converged long before)");
   if (d->n_elec < 2 || !d->elec_xyz || !d->elec_side) return fail(nullptr, CPM_EINVAL, "need >= 2 electrode atoms");
   if (d->n_site < 0 || (d->n_site > 0 && !d->site_q)) return fail(nullptr, CPM_EINVAL, "bad site charges");
   if (d->kspace == CPM_KSPACE_EWALD && !(d->kcut > 0)) return fail(nullptr, CPM_EINVAL, "EWALD needs kcut > 0");

@@ -123,6 +123,9 @@ struct SiteSet {       // cell-sorted sites of frame 0 (add frame * n to index)
   const T* x; const T* y; const T* z; const T* q;
   const int* order; const int* cell_start;
   int n;
+  // B-spline assignment of every site (PPPM only): first mesh index per
+  // axis, wrapped into [0, K), [frame][3][n]; weights [frame][3][P][n]
+  const int* wfirst; const T* w;
 };
 
 template <typename T>
@@ -176,6 +179,31 @@ struct EnergyArgs {
   double* out;                                   // [frame][n_dv][2]
 };
 
+// Same weights with the order P known at compile time (unrolled).
+template <int P, typename T>
+__device__ __forceinline__ int spline_weights_p(T u, T* w) {
+  T s = u - (T)P * (T)0.5;
+  T fl = floor(s);
+  T f = s - fl;
+  T B[P];
+  B[0] = (T)1;
+#pragma unroll
+  for (int j = 1; j < P; ++j) B[j] = (T)0;
+#pragma unroll
+  for (int n = 2; n <= P; ++n) {
+    const T inv = (T)1 / (T)(n - 1);
+#pragma unroll
+    for (int j = n - 1; j >= 0; --j) {
+      T x = f + (T)j;
+      T prev = (j > 0) ? B[j - 1] : (T)0;
+      B[j] = (x * B[j] + ((T)n - x) * prev) * inv;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < P; ++t) w[t] = B[P - 1 - t];
+  return (int)fl + 1;
+}
+
 // --------------------------------------------------------------- launchers
 
 // cell binning (k_bin.hip)
@@ -188,7 +216,8 @@ void launch_bin_sites(hipStream_t s, int n_frames, int n_site, const double* xyz
 // real-space sums (k_realspace.hip)
 template <typename T>
 void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
-                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out);
+                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out,
+                     T* zero_mesh, const MeshInfo& mi, int* wfirst_out, T* w_out);
 template <typename T>
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
                           const SiteSet<T>& st, const ForceArgs<T>& fa);

@@ -35,19 +35,20 @@ template <typename T2> __device__ __forceinline__ T2 cmul_si(T2 a, int sigma) {
   return sigma > 0 ? T2{-a.y, a.x} : T2{a.y, -a.x};
 }
 
-// X[m] = sum_r v[r] exp(sigma 2 pi i r m / R), R in {2,3,4,5}
-template <typename T2>
-__device__ __forceinline__ void small_dft(T2* v, int R, int sigma) {
+// X[m] = sum_r v[r] exp(sigma 2 pi i r m / R), R in {2,3,4,5}; R is a
+// compile-time constant so v stays in registers
+template <int R, typename T2>
+__device__ __forceinline__ void small_dft(T2* v, int sigma) {
   using Rl = typename CT<T2>::R;
-  if (R == 2) {
+  if constexpr (R == 2) {
     T2 a = cadd(v[0], v[1]), b = csub(v[0], v[1]);
     v[0] = a; v[1] = b;
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     T2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
     T2 s13 = cadd(v[1], v[3]), d13 = cmul_si(csub(v[1], v[3]), sigma);
     v[0] = cadd(s02, s13); v[2] = csub(s02, s13);
     v[1] = cadd(d02, d13); v[3] = csub(d02, d13);
-  } else if (R == 3) {
+  } else if constexpr (R == 3) {
     const Rl h = (Rl)0.86602540378443865;    // sqrt(3)/2
     T2 s = cadd(v[1], v[2]);
     T2 d = cmul_si(cscale(csub(v[1], v[2]), h), sigma);
@@ -75,37 +76,59 @@ template <> __device__ __forceinline__ const double2* twiddles<double2>(const FF
 template <> __device__ __forceinline__ const float2* twiddles<float2>(const FFTPlan1D& p) { return p.twf; }
 
 // Transform nlines lines of length p.n held in LDS buffer a (element stride
-// es, line stride ls), ping-ponging with b.  Returns the buffer holding the
-// result.  sigma = -1 forward, +1 inverse (unnormalised).
+// es, line stride ls), ping-ponging with b; tw is the plan's twiddle table
+// staged in LDS.  Returns the buffer holding the result.  sigma = -1
+// forward, +1 inverse (unnormalised).
+// Copy the twiddle table of plan p into LDS (the caller synchronises).
 template <typename T2>
-__device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, int nlines, int es, int ls, int sigma) {
+__device__ __forceinline__ void load_twiddles(const FFTPlan1D& p, T2* dst) {
+  const T2* src = twiddles<T2>(p);
+  for (int i = threadIdx.x; i < p.n; i += blockDim.x) dst[i] = src[i];
+}
+
+// One Stockham stage of radix R over nlines lines (see the file comment).
+template <int R, typename T2>
+__device__ __forceinline__ void fft_stage(const T2* src, T2* dst, int N, int Ns, int nlines, int es, int ls,
+                                          const T2* tw, int sigma) {
+  const int nb = N / R;
+  const int tstep = N / (Ns * R);
+  for (int u = threadIdx.x; u < nlines * nb; u += blockDim.x) {
+    const int line = u / nb;
+    const int j = u - line * nb;
+    const T2* in = src + line * ls;
+    T2* out = dst + line * ls;
+    T2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[(j + r * nb) * es];
+    const int k = j % Ns;
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        T2 w = tw[r * k * tstep];
+        if (sigma > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    small_dft<R>(v, sigma);
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(base + r * Ns) * es] = v[r];
+  }
+}
+
+template <typename T2>
+__device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nlines, int es, int ls, int sigma) {
   const int N = p.n;
-  const T2* tw = twiddles<T2>(p);
   T2* src = a;
   T2* dst = b;
   int Ns = 1;
   for (int f = 0; f < p.nfac; ++f) {
     const int R = p.fac[f];
-    const int nb = N / R;
-    const int tstep = N / (Ns * R);
-    for (int u = threadIdx.x; u < nlines * nb; u += blockDim.x) {
-      const int line = u / nb;
-      const int j = u - line * nb;
-      const T2* in = src + line * ls;
-      T2* out = dst + line * ls;
-      T2 v[5];
-      for (int r = 0; r < R; ++r) v[r] = in[(j + r * nb) * es];
-      const int k = j % Ns;
-      if (Ns > 1) {
-        for (int r = 1; r < R; ++r) {
-          T2 w = tw[r * k * tstep];
-          if (sigma > 0) w.y = -w.y;
-          v[r] = cmul(v[r], w);
-        }
-      }
-      small_dft(v, R, sigma);
-      const int base = (j / Ns) * Ns * R + k;
-      for (int r = 0; r < R; ++r) out[(base + r * Ns) * es] = v[r];
+    switch (R) {
+      case 2: fft_stage<2>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
+      case 3: fft_stage<3>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
+      case 4: fft_stage<4>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
+      default: fft_stage<5>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
     }
     __syncthreads();
     T2* t = src; src = dst; dst = t;
@@ -127,6 +150,10 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
   T2* B = A + NP;
+  T2* twx = B + NP;
+  T2* twy = twx + Kx;
+  load_twiddles(px, twx);
+  load_twiddles(py, twy);
   const int z = blockIdx.x;
   const size_t off = ((size_t)blockIdx.y * Kz + z) * NP;
   if (mode == 0) {
@@ -136,9 +163,9 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
   }
   __syncthreads();
   const int sigma = mode == 0 ? -1 : 1;
-  T2* r1 = fft_lines(A, B, px, Ky, 1, Kx, sigma);          // along x
+  T2* r1 = fft_lines(A, B, px, twx, Ky, 1, Kx, sigma);          // along x
   T2* o1 = (r1 == A) ? B : A;
-  T2* r2 = fft_lines(r1, o1, py, Kx, Kx, 1, sigma);        // along y
+  T2* r2 = fft_lines(r1, o1, py, twy, Kx, Kx, 1, sigma);        // along y
   if (mode == 0) {
     for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2[i];
   } else {
@@ -178,6 +205,8 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
   T2* A = reinterpret_cast<T2*>(smem);
   T2* B = A + za.nxc * Kz;
   T2* C = B + za.nxc * Kz;
+  T2* twz = C + za.nxc * Kz;
+  load_twiddles(pz, twz);
   const size_t fo = (size_t)blockIdx.y * Kx * Ky * Kz;
   // LDS layout [z][c]: lines along z have element stride nc, line stride 1
   for (int i = threadIdx.x; i < NL; i += blockDim.x) {
@@ -185,7 +214,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
     A[i] = data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c];
   }
   __syncthreads();
-  T2* X = fft_lines(A, B, pz, nc, nc, 1, -1);
+  T2* X = fft_lines(A, B, pz, twz, nc, nc, 1, -1);
   T2* F1 = (X == A) ? B : A;
   if (za.mode == 0) {
     double e = 0.0;
@@ -208,7 +237,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
       energy_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.5 * s;
     }
-    T2* Y = fft_lines(X, F1, pz, nc, nc, 1, +1);
+    T2* Y = fft_lines(X, F1, pz, twz, nc, nc, 1, +1);
     for (int i = threadIdx.x; i < NL; i += blockDim.x) {
       int zz = i / nc, c = i - zz * nc;
       data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Y[i];
@@ -229,7 +258,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
       F1[i] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};     // (-i kx + ky) v
     }
     __syncthreads();
-    T2* Y = fft_lines(F1, X, pz, nc, nc, 1, +1);
+    T2* Y = fft_lines(F1, X, pz, twz, nc, nc, 1, +1);
     for (int i = threadIdx.x; i < NL; i += blockDim.x) {
       int zz = i / nc, c = i - zz * nc;
       data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Y[i];
@@ -242,7 +271,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
       A[i] = T2{kz * v.y, -kz * v.x};                            // -i kz v
     }
     __syncthreads();
-    T2* Z = fft_lines(A, B, pz, nc, nc, 1, +1);
+    T2* Z = fft_lines(A, B, pz, twz, nc, nc, 1, +1);
     for (int i = threadIdx.x; i < NL; i += blockDim.x) {
       int zz = i / nc, c = i - zz * nc;
       data2[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Z[i];
@@ -256,7 +285,7 @@ template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                      int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
                      size_t out_re_stride) {
-  size_t lds = 2 * (size_t)px.n * py.n * sizeof(T2);
+  size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
   hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, n_frames), dim3(256), lds, s, px, py, Kz, mode, in_re,
                      in_c, out_c, out_re, out_im, out_re_stride);
@@ -265,7 +294,7 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part) {
-  size_t lds = 3 * (size_t)za.nxc * za.Kz * sizeof(T2);
+  size_t lds = (3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2);
   hipLaunchKernelGGL((k_fft_z<T, T2>), dim3(za.Ky * za.nchunk, n_frames), dim3(256), lds, s, pz, za, G,
                      data1, data2, save, add_saved, energy_part);
 }

@@ -289,24 +289,27 @@ __device__ double block_sum(double v, double* red) {
 }
 
 __global__ __launch_bounds__(256) void k_energy(EnergyArgs ea) {
-  __shared__ double red[4];
+  // ten partial sums reduced together: 8 dot products over the electrodes,
+  // the site real-space energies and the k-space energy parts
+  __shared__ double red[4][10];
   const int frame = blockIdx.x;
   const size_t fe = (size_t)frame * ea.n_elec;
-  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = threadIdx.x; i < ea.n_elec; i += blockDim.x) {
     double Q = ea.Q0[fe + i], bb = ea.b[fe + i], sc = ea.Sc[i], c = ea.c[i], d = ea.d[i], z = ea.ze[i];
     s[0] += Q * bb; s[1] += sc * bb; s[2] += Q * c; s[3] += sc * c;
     s[4] += d * Q; s[5] += d * sc; s[6] += z * Q; s[7] += z * sc;
   }
-  double u = 0.0;
-  for (int j = threadIdx.x; j < ea.n_site; j += blockDim.x) u += ea.u_site[(size_t)frame * ea.n_site + j];
-  double k = 0.0;
-  for (int j = threadIdx.x; j < ea.n_ek; j += blockDim.x) k += ea.ek[(size_t)frame * ea.n_ek + j];
-  double S[8];
-  for (int t = 0; t < 8; ++t) S[t] = block_sum(s[t], red);
-  double U = block_sum(u, red);
-  double K = block_sum(k, red);
-  double u_elyt = U + K - ea.self_energy;
+  for (int j = threadIdx.x; j < ea.n_site; j += blockDim.x) s[8] += ea.u_site[(size_t)frame * ea.n_site + j];
+  for (int j = threadIdx.x; j < ea.n_ek; j += blockDim.x) s[9] += ea.ek[(size_t)frame * ea.n_ek + j];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) s[t] = wave_sum(s[t]);
+  if ((threadIdx.x & 63) == 0)
+    for (int t = 0; t < 10; ++t) red[threadIdx.x >> 6][t] = s[t];
+  __syncthreads();
+  double S[10];
+  for (int t = 0; t < 10; ++t) S[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  double u_elyt = S[8] + S[9] - ea.self_energy;
   double zdip = ea.zdip ? ea.zdip[frame] : 0.0;
   for (int v = threadIdx.x; v < ea.n_dv; v += blockDim.x) {
     double dv = ea.dv ? ea.dv[v] : ea.dv_single;

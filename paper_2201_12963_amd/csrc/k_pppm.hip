@@ -10,8 +10,10 @@
 // Electrode spreading and gathering: the electrodes never move, so their
 // stencils (mesh index and weight of every (atom, point) pair) are tables
 // built once; the spread is then a deterministic sparse gather per touched
-// mesh point, and the potential at an atom is one wavefront-reduced dot
-// product over its P^3 points.
+// mesh point (16 lanes each), and the potential at an atom is one
+// wavefront-reduced dot product over its P^3 points.
+#include <type_traits>
+
 #include "common.h"
 
 namespace cpm {
@@ -25,38 +27,44 @@ __global__ __launch_bounds__(256) void k_spread_sites(MeshInfo mi, SiteSet<T> st
   if (j >= st.n) return;
   const int r = gid - j * P2;
   const int ry = r % P, rz = r / P;
-  const size_t fo = (size_t)frame * st.n;
-  const T x = st.x[fo + j], y = st.y[fo + j], z = st.z[fo + j], q = st.q[fo + j];
-  T wx[MAX_ORDER], wy[MAX_ORDER], wz[MAX_ORDER];
-  int fx = spline_weights<T>(x * (T)mi.invh[0], P, wx);
-  int fy = spline_weights<T>(y * (T)mi.invh[1], P, wy);
-  int fz = spline_weights<T>(z * (T)mi.invh[2], P, wz);
+  const size_t n = st.n, fo = (size_t)frame * st.n;
   const int Kx = mi.K[0], Ky = mi.K[1], Kz = mi.K[2];
-  int iy = fy + ry; iy = (iy % Ky + Ky) % Ky;
-  int iz = fz + rz; iz = (iz % Kz + Kz) % Kz;
-  T qw = q * wy[ry] * wz[rz];
+  const int fx = st.wfirst[(frame * 3 + 0) * n + j];
+  int iy = st.wfirst[(frame * 3 + 1) * n + j] + ry; iy -= (iy >= Ky) ? Ky : 0;
+  int iz = st.wfirst[(frame * 3 + 2) * n + j] + rz; iz -= (iz >= Kz) ? Kz : 0;
+  const T qw = st.q[fo + j] * st.w[((frame * 3 + 1) * P + ry) * n + j] * st.w[((frame * 3 + 2) * P + rz) * n + j];
   T* row = rho_all + (size_t)frame * mi.M + ((size_t)iz * Ky + iy) * Kx;
   for (int t = 0; t < P; ++t) {
-    int ix = fx + t; ix = (ix % Kx + Kx) % Kx;
-    atomicAdd(row + ix, qw * wx[t]);
+    int ix = fx + t; ix -= (ix >= Kx) ? Kx : 0;
+    atomicAdd(row + ix, qw * st.w[((frame * 3 + 0) * P + t) * n + j]);
   }
 }
 
-// rho[touch[t]] = sum_k val[k] q[col[k]] over rowptr[t] <= k < rowptr[t+1]
-template <typename T>
+// rho[touch[t]] = sum_k val[k] q[col[k]] over rowptr[t] <= k < rowptr[t+1];
+// 16 lanes per touched mesh point, reduced with shuffles
 __global__ __launch_bounds__(256) void k_spread_elec(int n_touch, const int* __restrict__ touch,
                                                      const int* __restrict__ rowptr,
                                                      const int* __restrict__ col,
-                                                     const T* __restrict__ val,
+                                                     const double* __restrict__ val_d,
+                                                     const float* __restrict__ val_f,
                                                      const double* __restrict__ q_all, size_t q_stride,
-                                                     T* __restrict__ rho_all, int M) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+                                                     double* __restrict__ rho_d, float* __restrict__ rho_f, int M) {
+  const int sub = threadIdx.x & 15;
+  const int t = blockIdx.x * (blockDim.x / 16) + (threadIdx.x >> 4);
   const int frame = blockIdx.y;
-  if (t >= n_touch) return;
+  const bool ok = t < n_touch;
   const double* q = q_all + (size_t)frame * q_stride;
-  T acc = 0;
-  for (int k = rowptr[t]; k < rowptr[t + 1]; ++k) acc += val[k] * (T)q[col[k]];
-  rho_all[(size_t)frame * M + touch[t]] = acc;
+  double acc = 0.0;
+  if (ok) {
+    const int k1 = rowptr[t + 1];
+    for (int k = rowptr[t] + sub; k < k1; k += 16) acc += (val_d ? val_d[k] : (double)val_f[k]) * q[col[k]];
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+  if (ok && sub == 0) {
+    if (rho_d) rho_d[(size_t)frame * M + touch[t]] = acc;
+    else rho_f[(size_t)frame * M + touch[t]] = (float)acc;
+  }
 }
 
 // b_i = -(phi_real_i + sum_t gw[i][t] phi[gidx[i][t]]): one wavefront per atom
@@ -89,9 +97,11 @@ void launch_spread_sites_t(hipStream_t s, int n_frames, const MeshInfo& mi, cons
 template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
                           const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M) {
-  dim3 grid((n_touch + 255) / 256, n_frames);
-  hipLaunchKernelGGL(k_spread_elec<T>, grid, dim3(256), 0, s, n_touch, touch, rowptr, col, val, q,
-                     q_stride, rho, M);
+  dim3 grid((n_touch + 15) / 16, n_frames);
+  const bool dbl = std::is_same<T, double>::value;
+  hipLaunchKernelGGL(k_spread_elec, grid, dim3(256), 0, s, n_touch, touch, rowptr, col,
+                     dbl ? (const double*)val : nullptr, dbl ? nullptr : (const float*)val, q, q_stride,
+                     dbl ? (double*)rho : nullptr, dbl ? nullptr : (float*)rho, M);
 }
 
 template <typename T>
