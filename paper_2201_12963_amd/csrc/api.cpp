@@ -389,21 +389,19 @@ void enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool keep_spectrum) {
     launch_bin_sites(s, nf, c->n_site, xyz, (size_t)3 * c->n_site, c->d_site_q, c->cell, c->d_cell_start,
                      c->d_order, c->d_sx, c->d_sy, c->d_sz, c->d_sq, mixed ? c->d_fx : nullptr,
                      mixed ? c->d_fy : nullptr, mixed ? c->d_fz : nullptr, mixed ? c->d_fq : nullptr, c->d_zdip,
-                     c->d_status, nullptr, c->mi.M, nullptr);
+                     c->d_status);
   });
   SiteSet<T> st = B::sites(c);
-  // the real-space kernel also clears the site charge mesh the spread accumulates
-  // into and computes the sites' B-spline weights
+  // the real-space kernel also computes the sites' B-spline weights
   rec(c, CPM_KERNEL_REAL_B, [=] {
     const bool pppm = c->kspace == CPM_KSPACE_PPPM;
-    launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c),
-                       pppm ? B::rho(c) : nullptr, c->mi, pppm ? c->d_wfirst : nullptr,
-                       pppm ? B::sw(c) : nullptr);
+    launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c), c->mi,
+                       pppm ? c->d_wfirst : nullptr, pppm ? B::sw(c) : nullptr);
   });
   if (c->kspace == CPM_KSPACE_PPPM) {
-    rec(c, CPM_KERNEL_SPREAD_SITES, [=] { launch_spread_sites_t<T>(s, nf, c->mi, st, B::rho(c)); });
+    // site spread fused with the forward x-y transform, plane by plane
     rec(c, CPM_KERNEL_FFT_XY_FWD, [=] {
-      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho(c), nullptr, B::c1(c), nullptr, nullptr);
+      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, c->cell, st, B::rho(c), B::c1(c));
     });
     rec(c, CPM_KERNEL_FFT_Z_POT, [=] {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
@@ -437,6 +435,9 @@ void enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Forc
   fa.qa_frame_stride = qa_stride;
   fa.mi = c->mi;
   if (c->kspace == CPM_KSPACE_PPPM) {
+    // the electrode spread stays a kernel of its own: only the few planes
+    // near the electrodes hold charge, and a per-plane fusion would leave
+    // that work to a handful of workgroups
     rec(c, CPM_KERNEL_SPREAD_ELEC, [=] {
       launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
                               B::rho_e(c), c->mi.M);
@@ -843,6 +844,14 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
         fillp[sl]++;
       }
     c->n_touch = (int)touch.size();
+    {
+      const size_t need = c->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns))
+                                                    : fft_xy_spread_lds<double, double2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns));
+      if (need > 150 * 1024) {
+        fail(c, CPM_EINVAL, "mesh plane and site staging area (%zu bytes) exceed LDS", need);
+        return bad(CPM_EINVAL);
+      }
+    }
     std::vector<float> gwf(gw.begin(), gw.end()), valf(val.begin(), val.end());
     if ((r = upload(c, &c->d_gidx, gidx)) || (r = upload(c, &c->d_gw, gw)) || (r = upload(c, &c->d_gwf, gwf)) ||
         (r = upload(c, &c->d_touch, touch)) || (r = upload(c, &c->d_rowptr, rowptr)) || (r = upload(c, &c->d_col, col)) ||

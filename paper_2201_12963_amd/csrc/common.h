@@ -204,28 +204,26 @@ __device__ __forceinline__ int spline_weights_p(T u, T* w) {
   return (int)fl + 1;
 }
 
+
 // --------------------------------------------------------------- launchers
 
 // cell binning (k_bin.hip)
 void launch_bin_sites(hipStream_t s, int n_frames, int n_site, const double* xyz, size_t frame_stride,
                       const double* site_q, Cell cell, int* cell_start, int* site_order,
                       double* sx, double* sy, double* sz, double* sq, float* fx, float* fy, float* fz,
-                      float* fq, double* zdip, int* status, double* zero_mesh, int mesh_M,
-                      float* zero_meshf);
+                      float* fq, double* zdip, int* status);
 
 // real-space sums (k_realspace.hip)
 template <typename T>
 void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
                      double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out,
-                     T* zero_mesh, const MeshInfo& mi, int* wfirst_out, T* w_out);
+                     const MeshInfo& mi, int* wfirst_out, T* w_out);
 template <typename T>
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
                           const SiteSet<T>& st, const ForceArgs<T>& fa);
 size_t bin_lds_bytes(int n_site, int n_cells);
 
 // particle-mesh steps (k_pppm.hip)
-template <typename T>
-void launch_spread_sites_t(hipStream_t s, int n_frames, const MeshInfo& mi, const SiteSet<T>& st, T* rho);
 template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
                           const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M);
@@ -241,6 +239,12 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part);
+template <typename T, typename T2>
+size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap);
+int fft_xy_spread_stage_cap(int n_site);
+template <typename T, typename T2>
+void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
+                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c);
 
 // explicit Ewald (k_ewald.hip)
 void launch_ewald_sf(hipStream_t s, int n_frames, int nk, const double* kv, const double* ew,

@@ -28,9 +28,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_sites(
     int* __restrict__ order_all, double* __restrict__ sx_all, double* __restrict__ sy_all,
     double* __restrict__ sz_all, double* __restrict__ sq_all, float* __restrict__ fx_all,
     float* __restrict__ fy_all, float* __restrict__ fz_all, float* __restrict__ fq_all,
-    double* __restrict__ zdip_all, int* __restrict__ status, double* __restrict__ mesh_all,
-    float* __restrict__ meshf_all, int mesh_M) {
-  extern __shared__ int lds[];
+    double* __restrict__ zdip_all, int* __restrict__ status) {
+  extern __shared__ __align__(16) int lds[];
   const int n_cells = cell.n_cells;
   int* cid = lds;                              // [n_site]
   int* hist = lds + n_site;                    // [BIN_WAVES][n_cells]
@@ -48,15 +47,6 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_sites(
   int* cell_start = cell_start_all + (size_t)frame * (n_cells + 1);
   int* order = order_all + (size_t)frame * n_site;
 
-  // clear this frame's charge mesh (spread accumulates into it)
-  if (mesh_all) {
-    double* m = mesh_all + (size_t)frame * mesh_M;
-    for (int i = tid; i < mesh_M; i += BIN_THREADS) m[i] = 0.0;
-  }
-  if (meshf_all) {
-    float* m = meshf_all + (size_t)frame * mesh_M;
-    for (int i = tid; i < mesh_M; i += BIN_THREADS) m[i] = 0.0f;
-  }
 
   // 1. cell ids
   double zd = 0.0;
@@ -178,12 +168,11 @@ size_t bin_lds_bytes(int n_site, int n_cells) {
 void launch_bin_sites(hipStream_t s, int n_frames, int n_site, const double* xyz, size_t frame_stride,
                       const double* site_q, Cell cell, int* cell_start, int* site_order,
                       double* sx, double* sy, double* sz, double* sq, float* fx, float* fy, float* fz,
-                      float* fq, double* zdip, int* status, double* zero_mesh, int mesh_M,
-                      float* zero_meshf) {
+                      float* fq, double* zdip, int* status) {
   size_t lds = bin_lds_bytes(n_site, cell.n_cells);
   hipLaunchKernelGGL(k_bin_sites, dim3(n_frames), dim3(BIN_THREADS), lds, s, n_site, xyz,
                      frame_stride, site_q, cell, cell_start, site_order, sx, sy, sz, sq, fx, fy, fz, fq,
-                     zdip, status, zero_mesh, zero_meshf, mesh_M);
+                     zdip, status);
 }
 
 }  // namespace cpm

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
                                                 const T* __restrict__ in_re, const T2* __restrict__ in_c,
                                                 T2* __restrict__ out_c, T* __restrict__ out_re,
                                                 T* __restrict__ out_im, size_t out_re_stride) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
   T2* B = A + NP;
@@ -177,6 +177,105 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
   }
 }
 
+// ------------------------------------------------- spread fused with x-y
+
+// Forward x-y transform of one z-plane of the electrolyte charge mesh, whose
+// real values are first assembled in LDS: the sites whose B-spline stencil
+// reaches the plane are found in the contiguous cell-sorted ranges of the
+// cell layers around it, staged (stage_cap entries at most, flushed when
+// the next block-wide chunk could overflow it), and add their P x P in-plane
+// contributions with LDS atomics.  The assembled plane is also written to rho_out (the
+// charge mesh, for inspection), then transformed as in k_fft_xy.
+template <typename T, typename T2>
+__global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
+                                                       Cell cl, SiteSet<T> st, int stage_cap,
+                                                       T* __restrict__ rho_out, T2* __restrict__ out_c) {
+  // 16-byte alignment keeps the dynamic area (after the static counter)
+  // aligned for the complex values and the FP64 LDS atomics
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int nvalid;
+  const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
+  T2* A = reinterpret_cast<T2*>(smem);
+  T2* B = A + NP;
+  T2* twx = B + NP;
+  T2* twy = twx + Kx;
+  T* acc = reinterpret_cast<T*>(twy + Ky);                 // NP values
+  int* list = reinterpret_cast<int*>(acc + NP);            // staged (site, z slot) entries
+  load_twiddles(px, twx);
+  load_twiddles(py, twy);
+  const int iz = blockIdx.x;
+  const int frame = blockIdx.y;
+  for (int i = threadIdx.x; i < NP; i += blockDim.x) acc[i] = (T)0;
+  if (threadIdx.x == 0) nvalid = 0;
+  __syncthreads();
+  const int P = mi.order;
+  const size_t n = st.n;
+  const int* wfx = st.wfirst + (frame * 3 + 0) * n;
+  const int* wfy = st.wfirst + (frame * 3 + 1) * n;
+  const int* wfz = st.wfirst + (frame * 3 + 2) * n;
+  const T* q = st.q + (size_t)frame * n;
+  // (site, y-row) tasks of the staged entries: P atomic adds along x each
+  auto flush = [&](int nv) {
+    for (int t = threadIdx.x; t < nv * P; t += blockDim.x) {
+      const int e = list[t / P], ry = t % P;
+      const int j = e >> 3, tz = e & 7;
+      int iy = wfy[j] + ry; iy -= (iy >= Ky) ? Ky : 0;
+      const T qw = q[j] * st.w[((frame * 3 + 1) * P + ry) * n + j] * st.w[((frame * 3 + 2) * P + tz) * n + j];
+      const int fx = wfx[j];
+      T* row = acc + iy * Kx;
+      for (int tx = 0; tx < P; ++tx) {
+        int ix = fx + tx; ix -= (ix >= Kx) ? Kx : 0;
+        atomicAdd(row + ix, qw * st.w[((frame * 3 + 0) * P + tx) * n + j]);
+      }
+    }
+  };
+  // cell layers whose sites can reach this plane (one layer of margin on each side)
+  const double cwz = cl.L[2] / cl.nc[2];
+  const double hz = mi.h[2];
+  const double zlo = (iz - 0.5 * P - 1.0) * hz, zhi = (iz + 0.5 * P + 1.0) * hz;
+  int c0 = (int)floor(zlo / cwz), c1 = (int)floor(zhi / cwz);
+  if (c1 - c0 + 1 > cl.nc[2]) { c0 = 0; c1 = cl.nc[2] - 1; }
+  const int per_layer = cl.nc[0] * cl.nc[1];
+  const int* cs = st.cell_start + (size_t)frame * (cl.n_cells + 1);
+  for (int cz = c0; cz <= c1; ++cz) {
+    const int czw = ((cz % cl.nc[2]) + cl.nc[2]) % cl.nc[2];
+    const int j0 = cs[czw * per_layer], j1 = cs[(czw + 1) * per_layer];
+    // block-wide chunks, so that the list is flushed before it can overflow
+    for (int base = j0; base < j1; base += blockDim.x) {
+      const int j = base + threadIdx.x;
+      if (j < j1) {
+        int tz = iz - wfz[j];
+        tz += (tz < 0) ? Kz : 0;
+        if (tz < P) {
+          int slot = atomicAdd(&nvalid, 1);
+          list[slot] = j * 8 + tz;                      // site index and its z weight slot
+        }
+      }
+      __syncthreads();
+      const int nv = nvalid;
+      __syncthreads();                                  // all have read the count before it changes again
+      if (nv > stage_cap - (int)blockDim.x) {
+        flush(nv);
+        __syncthreads();
+        if (threadIdx.x == 0) nvalid = 0;
+        __syncthreads();
+      }
+    }
+  }
+  flush(nvalid);
+  __syncthreads();
+  const size_t off = ((size_t)frame * Kz + iz) * NP;
+  for (int i = threadIdx.x; i < NP; i += blockDim.x) {
+    if (rho_out) rho_out[off + i] = acc[i];
+    A[i] = T2{acc[i], (T)0};
+  }
+  __syncthreads();
+  T2* r1p = fft_lines(A, B, px, twx, Ky, 1, Kx, -1);
+  T2* o1 = (r1p == A) ? B : A;
+  T2* r2p = fft_lines(r1p, o1, py, twy, Kx, Kx, 1, -1);
+  for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2p[i];
+}
+
 // ------------------------------------------------------------------- z pass
 
 template <typename T> __device__ __forceinline__ T mode_k(int i, int K, T twopi_L) {
@@ -195,7 +294,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
                                                T2* __restrict__ data1, T2* __restrict__ data2,
                                                T2* __restrict__ save, int add_saved,
                                                double* __restrict__ energy_part) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   const int Kx = za.Kx, Ky = za.Ky, Kz = za.Kz;
   const int y = blockIdx.x / za.nchunk;
@@ -280,6 +379,33 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
 }
 
 // ------------------------------------------------------------------ launchers
+
+// dynamic LDS of k_fft_xy_spread: two complex planes, twiddles, the real
+// plane and the site staging list
+template <typename T, typename T2>
+size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap) {
+  return (2 * (size_t)Kx * Ky + Kx + Ky) * sizeof(T2) + (size_t)Kx * Ky * sizeof(T) + (size_t)stage_cap * sizeof(int);
+}
+
+int fft_xy_spread_stage_cap(int n_site) { return std::max(512, std::min(n_site, 4096)); }
+
+template <typename T, typename T2>
+void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
+                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c) {
+  const int cap = fft_xy_spread_stage_cap(st.n);
+  size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n, cap);
+  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), dim3(Kz, n_frames), dim3(256), lds, s, px, py, Kz, mi, cell, st,
+                     cap, rho_out, out_c);
+}
+
+template size_t fft_xy_spread_lds<double, double2>(int, int, int);
+template size_t fft_xy_spread_lds<float, float2>(int, int, int);
+template void launch_fft_xy_spread_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
+                                                      const MeshInfo&, const Cell&, const SiteSet<double>&, double*,
+                                                      double2*);
+template void launch_fft_xy_spread_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
+                                                    const MeshInfo&, const Cell&, const SiteSet<float>&, float*,
+                                                    float2*);
 
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,

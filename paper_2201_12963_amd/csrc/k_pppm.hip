@@ -3,10 +3,8 @@
 // electrolyte sites and of the electrode charges, and interpolation of the
 // mesh potential at the electrode atoms, which gives the k-space part of b.
 //
-// Electrolyte spreading: one thread per (site, y-row, z-row) of the P x P x P
-// stencil; each thread adds P weighted charges along x to contiguous mesh
-// points with hardware FP64/FP32 atomics (the sites of a wavefront are
-// cell-sorted, so their rows overlap in the same cache lines).
+// (The electrolyte sites are spread plane by plane inside the forward x-y
+// transform, k_fft_xy_spread.)
 // Electrode spreading and gathering: the electrodes never move, so their
 // stencils (mesh index and weight of every (atom, point) pair) are tables
 // built once; the spread is then a deterministic sparse gather per touched
@@ -17,28 +15,6 @@
 #include "common.h"
 
 namespace cpm {
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_spread_sites(MeshInfo mi, SiteSet<T> st, T* __restrict__ rho_all) {
-  const int P = mi.order, P2 = P * P;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int frame = blockIdx.y;
-  const int j = gid / P2;
-  if (j >= st.n) return;
-  const int r = gid - j * P2;
-  const int ry = r % P, rz = r / P;
-  const size_t n = st.n, fo = (size_t)frame * st.n;
-  const int Kx = mi.K[0], Ky = mi.K[1], Kz = mi.K[2];
-  const int fx = st.wfirst[(frame * 3 + 0) * n + j];
-  int iy = st.wfirst[(frame * 3 + 1) * n + j] + ry; iy -= (iy >= Ky) ? Ky : 0;
-  int iz = st.wfirst[(frame * 3 + 2) * n + j] + rz; iz -= (iz >= Kz) ? Kz : 0;
-  const T qw = st.q[fo + j] * st.w[((frame * 3 + 1) * P + ry) * n + j] * st.w[((frame * 3 + 2) * P + rz) * n + j];
-  T* row = rho_all + (size_t)frame * mi.M + ((size_t)iz * Ky + iy) * Kx;
-  for (int t = 0; t < P; ++t) {
-    int ix = fx + t; ix -= (ix >= Kx) ? Kx : 0;
-    atomicAdd(row + ix, qw * st.w[((frame * 3 + 0) * P + t) * n + j]);
-  }
-}
 
 // rho[touch[t]] = sum_k val[k] q[col[k]] over rowptr[t] <= k < rowptr[t+1];
 // 16 lanes per touched mesh point, reduced with shuffles
@@ -88,13 +64,6 @@ __global__ __launch_bounds__(256) void k_gather_b(int n_elec, int P3, const int*
 }
 
 template <typename T>
-void launch_spread_sites_t(hipStream_t s, int n_frames, const MeshInfo& mi, const SiteSet<T>& st, T* rho) {
-  int n = st.n * mi.order * mi.order;
-  dim3 grid((n + 255) / 256, n_frames);
-  hipLaunchKernelGGL(k_spread_sites<T>, grid, dim3(256), 0, s, mi, st, rho);
-}
-
-template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
                           const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M) {
   dim3 grid((n_touch + 15) / 16, n_frames);
@@ -111,8 +80,6 @@ void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const in
   hipLaunchKernelGGL(k_gather_b<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b);
 }
 
-template void launch_spread_sites_t<double>(hipStream_t, int, const MeshInfo&, const SiteSet<double>&, double*);
-template void launch_spread_sites_t<float>(hipStream_t, int, const MeshInfo&, const SiteSet<float>&, float*);
 template void launch_spread_elec_t<double>(hipStream_t, int, int, const int*, const int*, const int*,
                                            const double*, const double*, size_t, double*, int);
 template void launch_spread_elec_t<float>(hipStream_t, int, int, const int*, const int*, const int*,

@@ -133,13 +133,12 @@ __device__ __forceinline__ void site_spline(const MeshInfo& mi, T u, int axis, s
   for (int t = 0; t < mi.order; ++t) w[((frame * 3 + axis) * mi.order + t) * n + site] = wt[t];
 }
 
-// One wavefront per electrode atom.  The workgroups also (i) clear the
-// frame's site charge mesh and (ii) compute the B-spline assignment of the
-// sites for the mesh steps that follow, each workgroup taking a slice.
+// One wavefront per electrode atom.  The workgroups also compute the
+// B-spline assignment of the sites for the mesh steps that follow, each
+// workgroup taking a slice.
 template <typename T>
 __global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, T rc2, ElecSet<T> el,
-                                                SiteSet<T> st, T* __restrict__ phi_out,
-                                                T* __restrict__ zero_mesh, MeshInfo mi,
+                                                SiteSet<T> st, T* __restrict__ phi_out, MeshInfo mi,
                                                 int* __restrict__ wfirst_out, T* __restrict__ w_out) {
   __shared__ T qbuf[4][5 * WaveQueue<T>::CAP];
   const int lane = threadIdx.x & (WAVE - 1);
@@ -147,11 +146,6 @@ __global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, T rc2
   const int frame = blockIdx.y;
   const size_t fo = (size_t)frame * st.n;
   const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
-  if (zero_mesh) {
-    const int per = (mi.M + gridDim.x - 1) / gridDim.x;
-    T* m = zero_mesh + (size_t)frame * mi.M;
-    for (int i = blockIdx.x * per + threadIdx.x; i < min(mi.M, (blockIdx.x + 1) * per); i += blockDim.x) m[i] = 0;
-  }
   if (w_out) {
     const int per = (st.n + gridDim.x - 1) / gridDim.x;
     const int lo = blockIdx.x * per, hi = min(st.n, lo + per);
@@ -212,11 +206,11 @@ __global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, T rc2
 
 template <typename T>
 void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
-                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out, T* zero_mesh,
+                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out,
                      const MeshInfo& mi, int* wfirst_out, T* w_out) {
   dim3 grid((el.n + 3) / 4, n_frames);
   hipLaunchKernelGGL(k_real_b<T>, grid, dim3(256), 0, s, cell, (T)alpha, (T)eta, (T)(rcut * rcut),
-                     el, st, phi_out, zero_mesh, mi, wfirst_out, w_out);
+                     el, st, phi_out, mi, wfirst_out, w_out);
 }
 
 // ------------------------------------------------------------ site forces
@@ -423,10 +417,10 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
 
 // explicit instantiations used by api.cpp
 template void launch_real_b_t<double>(hipStream_t, int, const Cell&, double, double, double,
-                                      const ElecSet<double>&, const SiteSet<double>&, double*, double*,
+                                      const ElecSet<double>&, const SiteSet<double>&, double*,
                                       const MeshInfo&, int*, double*);
 template void launch_real_b_t<float>(hipStream_t, int, const Cell&, double, double, double,
-                                     const ElecSet<float>&, const SiteSet<float>&, float*, float*,
+                                     const ElecSet<float>&, const SiteSet<float>&, float*,
                                      const MeshInfo&, int*, float*);
 template void launch_site_forces_t<double>(hipStream_t, int, const Cell&, const ElecSet<double>&,
                                            const SiteSet<double>&, const ForceArgs<double>&);
