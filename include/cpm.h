@@ -163,7 +163,7 @@ long long cpm_get_buffer(cpm_ctx* ctx, int which, void* host_out);
  * overwrites internal buffers only; outputs of the last step stay valid.
  * CPM_ESTATE if that kernel has not run yet. */
 enum {
-  CPM_KERNEL_BIN = 0, CPM_KERNEL_REAL_B, CPM_KERNEL_SPREAD_SITES, CPM_KERNEL_FFT_XY_FWD,
+  CPM_KERNEL_BIN = 0, CPM_KERNEL_REAL_B, CPM_KERNEL_SITE_PAIRS, CPM_KERNEL_FFT_XY_FWD,
   CPM_KERNEL_FFT_Z_POT, CPM_KERNEL_FFT_XY_INV, CPM_KERNEL_GATHER_B, CPM_KERNEL_CHARGES,
   CPM_KERNEL_SPREAD_ELEC, CPM_KERNEL_FFT_XY_FWD_E, CPM_KERNEL_FFT_Z_FIELD, CPM_KERNEL_FFT_XY_INV_E,
   CPM_KERNEL_SITE_FORCES, CPM_KERNEL_ENERGY, CPM_KERNEL_COUNT

@@ -22,7 +22,7 @@ FINITE_FIELD, DOUBLED_CELL = 0, 1
 KSPACE_EWALD, KSPACE_PPPM = 0, 1
 FP64, MIXED = 0, 1
 BUF_CELL_START, BUF_SITE_ORDER, BUF_PHI_REAL, BUF_B, BUF_RHO_MESH, BUF_PHI_MESH, BUF_FIELD_MESH, BUF_NCELL = range(8)
-KERNELS = ("bin", "real_b", "spread_sites", "fft_xy_fwd", "fft_z_pot", "fft_xy_inv", "gather_b", "charges",
+KERNELS = ("bin", "real_b", "site_pairs", "fft_xy_fwd", "fft_z_pot", "fft_xy_inv", "gather_b", "charges",
            "spread_elec", "fft_xy_fwd_e", "fft_z_field", "fft_xy_inv_e", "site_forces", "energy")
 
 _STATUS_NAMES = {0: "CPM_OK", -1: "CPM_EINVAL", -2: "CPM_ESTATE", -3: "CPM_ENOTSPD", -4: "CPM_EDEVICE",

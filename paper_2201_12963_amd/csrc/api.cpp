@@ -69,9 +69,8 @@ struct cpm_ctx {
 
   // ---- per-step buffers (capacity cap_frames)
   int cap_frames = 0;
-  int *d_cell_start = nullptr, *d_order = nullptr, *d_status = nullptr, *d_wfirst = nullptr;
-  double* d_sw = nullptr;
-  float* d_swf = nullptr;
+  int *d_cell_start = nullptr, *d_order = nullptr, *d_status = nullptr;
+  double* d_fpair = nullptr;      // site-site force sums [frame][3][n_site]
   double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
   float *d_fx = nullptr, *d_fy = nullptr, *d_fz = nullptr, *d_fq = nullptr;
   double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
@@ -277,11 +276,7 @@ int alloc_frames(cpm_ctx* c, int nf) {
   }
   TRY(dalloc(c, &c->d_phir, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_zdip, (size_t)nf));
-  if (c->kspace == CPM_KSPACE_PPPM) {
-    TRY(dalloc(c, &c->d_wfirst, (size_t)nf * 3 * ns));
-    if (mixed) TRY(dalloc(c, &c->d_swf, (size_t)nf * 3 * c->order * ns));
-    else TRY(dalloc(c, &c->d_sw, (size_t)nf * 3 * c->order * ns));
-  }
+  TRY(dalloc(c, &c->d_fpair, (size_t)nf * 3 * ns));
   TRY(dalloc(c, &c->d_b, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_Q0, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_qint, (size_t)nf * ne));
@@ -329,19 +324,26 @@ int alloc_frames(cpm_ctx* c, int nf) {
 
 // ------------------------------------------------------------ the step
 
-// launch now and remember the launch (arguments by value) for cpm_replay_kernel
+// launch on stream s now and remember the launch (arguments by value) for
+// cpm_replay_kernel, which re-runs it on the context's stream
 template <typename F>
-void rec(cpm_ctx* c, int id, F&& f) {
-  c->last_launch[id] = std::function<void()>(f);
-  f();
+void rec(cpm_ctx* c, int id, hipStream_t s, F f) {
+  c->last_launch[id] = [c, f]() { f(c->stream); };
+  f(s);
+}
+
+// remember a launch for cpm_replay_kernel without running it now (a part of
+// a launch that hosts several kernels' workgroups, timed on its own)
+template <typename F>
+void keep(cpm_ctx* c, int id, F f) {
+  c->last_launch[id] = [c, f]() { f(c->stream); };
 }
 
 template <typename T> struct Bufs;
 template <> struct Bufs<double> {
   using T2 = double2;
   static SiteSet<double> sites(cpm_ctx* c) {
-    return SiteSet<double>{c->d_sx, c->d_sy, c->d_sz, c->d_sq, c->d_order, c->d_cell_start, c->n_site,
-                           c->d_wfirst, c->d_sw};
+    return SiteSet<double>{c->d_sx, c->d_sy, c->d_sz, c->d_sq, c->d_order, c->d_cell_start, c->n_site};
   }
   static const ElecSet<double>& elec(cpm_ctx* c) { return c->el; }
   static double* phir(cpm_ctx* c) { return c->d_phir; }
@@ -355,13 +357,11 @@ template <> struct Bufs<double> {
   static const double* G(cpm_ctx* c) { return c->d_G; }
   static const double* gw(cpm_ctx* c) { return c->d_gw; }
   static const double* val(cpm_ctx* c) { return c->d_val; }
-  static double* sw(cpm_ctx* c) { return c->d_sw; }
 };
 template <> struct Bufs<float> {
   using T2 = float2;
   static SiteSet<float> sites(cpm_ctx* c) {
-    return SiteSet<float>{c->d_fx, c->d_fy, c->d_fz, c->d_fq, c->d_order, c->d_cell_start, c->n_site,
-                          c->d_wfirst, c->d_swf};
+    return SiteSet<float>{c->d_fx, c->d_fy, c->d_fz, c->d_fq, c->d_order, c->d_cell_start, c->n_site};
   }
   static const ElecSet<float>& elec(cpm_ctx* c) { return c->elf; }
   static float* phir(cpm_ctx* c) { return c->d_phirf; }
@@ -375,55 +375,71 @@ template <> struct Bufs<float> {
   static const float* G(cpm_ctx* c) { return c->d_Gf; }
   static const float* gw(cpm_ctx* c) { return c->d_gwf; }
   static const float* val(cpm_ctx* c) { return c->d_valf; }
-  static float* sw(cpm_ctx* c) { return c->d_swf; }
 };
 
-// Stage 1: positions -> binned sites -> b (frames 0..nf-1)
+// Stage 1: positions -> binned sites -> b (frames 0..nf-1).  With PPPM the
+// real-space part of b runs as extra workgroups of the first mesh launch
+// (both need only the binned sites).
 template <typename T>
-void enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool keep_spectrum) {
+int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
   using B = Bufs<T>;
   using T2 = typename B::T2;
   hipStream_t s = c->stream;
   const bool mixed = std::is_same<T, float>::value;
-  rec(c, CPM_KERNEL_BIN, [=] {
+  rec(c, CPM_KERNEL_BIN, s, [=](hipStream_t s) {
     launch_bin_sites(s, nf, c->n_site, xyz, (size_t)3 * c->n_site, c->d_site_q, c->cell, c->d_cell_start,
                      c->d_order, c->d_sx, c->d_sy, c->d_sz, c->d_sq, mixed ? c->d_fx : nullptr,
                      mixed ? c->d_fy : nullptr, mixed ? c->d_fz : nullptr, mixed ? c->d_fq : nullptr, c->d_zdip,
                      c->d_status);
   });
   SiteSet<T> st = B::sites(c);
-  // the real-space kernel also computes the sites' B-spline weights
-  rec(c, CPM_KERNEL_REAL_B, [=] {
-    const bool pppm = c->kspace == CPM_KSPACE_PPPM;
-    launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c), c->mi,
-                       pppm ? c->d_wfirst : nullptr, pppm ? B::sw(c) : nullptr);
-  });
   if (c->kspace == CPM_KSPACE_PPPM) {
-    // site spread fused with the forward x-y transform, plane by plane
-    rec(c, CPM_KERNEL_FFT_XY_FWD, [=] {
-      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, c->cell, st, B::rho(c), B::c1(c));
+    RealBArgs<T> rb{};
+    rb.n_blocks = (c->n_elec + 3) / 4;
+    rb.alpha = (T)c->alpha;
+    rb.eta = (T)c->eta;
+    rb.rc2 = (T)(c->rcut * c->rcut);
+    rb.el = B::elec(c);
+    rb.phi_out = B::phir(c);
+    // site spread fused with the forward x-y transform, plane by plane, and
+    // the real-space part of b
+    rec(c, CPM_KERNEL_FFT_XY_FWD, s, [=](hipStream_t s) {
+      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, c->cell, st, B::rho(c), B::c1(c),
+                                    true, &rb);
     });
-    rec(c, CPM_KERNEL_FFT_Z_POT, [=] {
+    keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) {
+      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, c->cell, st, B::rho(c), B::c1(c),
+                                    false, &rb);
+    });
+    rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
-                            keep_spectrum ? B::save(c) : nullptr, 0, c->d_ek);
+                            forces ? B::save(c) : nullptr, 0, c->d_ek);
     });
-    rec(c, CPM_KERNEL_FFT_XY_INV, [=] {
+    rec(c, CPM_KERNEL_FFT_XY_INV, s, [=](hipStream_t s) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
     });
-    rec(c, CPM_KERNEL_GATHER_B, [=] {
+    rec(c, CPM_KERNEL_GATHER_B, s, [=](hipStream_t s) {
       launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b);
     });
   } else {
+    rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) {
+      launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c));
+    });
     SiteSet<double> sd = Bufs<double>::sites(c);
     launch_ewald_sf(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok, c->d_ek);
     launch_ewald_phi(s, nf, c->nk, c->n_elec, c->d_ew, c->d_eph, c->d_rhok, c->d_phir, c->d_b);
   }
+  return CPM_OK;
 }
 
 // Stage 3: Coulomb forces on the sites for electrode charges qa (+ optional
-// second set qb on a shared field mesh Eb), plus real-space energies
+// second set qb on a shared field mesh Eb) and, if ea is given, the
+// energies.  The site-site forces (independent of the charges) run as extra
+// workgroups of the z pass of the field, the energies as extra workgroups
+// of the site-force launch.
 template <typename T>
-void enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, ForceArgs<T> fa) {
+int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, ForceArgs<T> fa,
+                   const EnergyArgs* ea) {
   using B = Bufs<T>;
   using T2 = typename B::T2;
   hipStream_t s = c->stream;
@@ -434,56 +450,88 @@ void enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Forc
   fa.qa = qa;
   fa.qa_frame_stride = qa_stride;
   fa.mi = c->mi;
+  fa.f_pair = c->d_fpair;
+  PairArgs<T> pa{};
+  pa.n_blocks = (c->n_site + 3) / 4;
+  pa.cell = c->cell;
+  pa.st = st;
+  pa.alpha = fa.alpha;
+  pa.rc2 = fa.rc2;
+  pa.f_pair = c->d_fpair;
+  pa.u_site = c->d_usite;
   if (c->kspace == CPM_KSPACE_PPPM) {
     // the electrode spread stays a kernel of its own: only the few planes
     // near the electrodes hold charge, and a per-plane fusion would leave
     // that work to a handful of workgroups
-    rec(c, CPM_KERNEL_SPREAD_ELEC, [=] {
+    rec(c, CPM_KERNEL_SPREAD_ELEC, s, [=](hipStream_t s) {
       launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
                               B::rho_e(c), c->mi.M);
     });
-    rec(c, CPM_KERNEL_FFT_XY_FWD_E, [=] {
+    rec(c, CPM_KERNEL_FFT_XY_FWD_E, s, [=](hipStream_t s) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
     });
-    rec(c, CPM_KERNEL_FFT_Z_FIELD, [=] {
-      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr);
+    rec(c, CPM_KERNEL_FFT_Z_FIELD, s, [=](hipStream_t s) {
+      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, true,
+                            &pa);
     });
-    // c1 -> Ex (re), Ey (im); c2 -> Ez
+    keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) {
+      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, false,
+                            &pa);
+    });
+    // c1 -> Ex (re), Ey (im); c2 -> Ez; field meshes are [frame][3][M]
     T* E = B::E(c);
     const size_t M = c->mi.M;
-    // field meshes are [frame][3][M]
-    rec(c, CPM_KERNEL_FFT_XY_INV_E, [=] {
-      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, E, E + M, 3 * M);
-      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c2(c), nullptr, E + 2 * M, nullptr,
-                             3 * M);
+    rec(c, CPM_KERNEL_FFT_XY_INV_E, s, [=](hipStream_t s) {
+      launch_fft_xy_field_inv_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], B::c1(c), B::c2(c), E, 3 * M);
     });
     fa.Ea = E;
     fa.Ea_frame_stride = 3 * M;
     fa.Esite = nullptr;
   } else {
+    rec(c, CPM_KERNEL_SITE_PAIRS, s, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, c->cell, st, fa); });
     SiteSet<double> sd = Bufs<double>::sites(c);
     launch_ewald_rho_all(s, nf, c->nk, c->n_elec, c->d_eph, qa, qa_stride, c->d_rhok, c->d_rhok_all);
     launch_ewald_field(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok_all, c->d_Esite);
     fa.Ea = nullptr;
     fa.Esite = c->d_Esite;
   }
-  rec(c, CPM_KERNEL_SITE_FORCES, [=] { launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa); });
+  const bool with_e = ea != nullptr;
+  const EnergyArgs e = with_e ? *ea : EnergyArgs{};
+  rec(c, CPM_KERNEL_SITE_FORCES, s, [=](hipStream_t s) {
+    launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa, true, with_e ? &e : nullptr);
+  });
+  if (with_e)
+    keep(c, CPM_KERNEL_ENERGY, [=](hipStream_t s) {
+      launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa, false, &e);
+    });
+  return CPM_OK;
+}
+
+// energy reduction of the step: dV sweep of n_dv values (dv) or one (dv_single)
+EnergyArgs energy_args(cpm_ctx* c, int n_dv, const double* dv, double dv_single, double* out) {
+  EnergyArgs ea{};
+  ea.n_elec = c->n_elec; ea.n_site = c->n_site; ea.n_ek = c->n_ek;
+  ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
+  ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
+  ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
+  ea.n_dv = n_dv; ea.dv = dv; ea.dv_single = dv_single; ea.out = out;
+  return ea;
 }
 
 template <typename T>
 int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, double* f_out, double* e_out) {
   hipStream_t s = c->stream;
   const bool need_forces = f_out || e_out;
-  enqueue_b<T>(c, 1, xyz, need_forces);
+  TRY(enqueue_b<T>(c, 1, xyz, need_forces));
   if (std::is_same<T, float>::value) {
     // FP32 GEMV on centred b, FP64 re-projection, then q = Q0 + dV S c
-    rec(c, CPM_KERNEL_CHARGES, [=] {
+    rec(c, CPM_KERNEL_CHARGES, s, [=](hipStream_t s) {
       launch_charges_f32(s, 1, c->n_elec, c->d_Sf, c->d_b, c->d_Q0);
       launch_reproject(s, 1, c->n_elec, c->d_sub1, c->d_Q0);
       launch_axpy(s, c->n_elec, c->d_Q0, c->d_Sc, dv, q_out);
     });
   } else {
-    rec(c, CPM_KERNEL_CHARGES, [=] { launch_charges(s, 1, c->n_elec, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q_out); });
+    rec(c, CPM_KERNEL_CHARGES, s, [=](hipStream_t s) { launch_charges(s, 1, c->n_elec, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q_out); });
   }
   if (need_forces) {
     ForceArgs<T> fa{};
@@ -494,16 +542,8 @@ int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, doubl
     fa.n_dv = 1;
     fa.dv = nullptr;
     fa.u_site = c->d_usite;
-    enqueue_forces<T>(c, 1, q_out, c->n_elec, fa);
-  }
-  if (e_out) {
-    EnergyArgs ea{};
-    ea.n_elec = c->n_elec; ea.n_site = c->n_site; ea.n_ek = c->n_ek;
-    ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
-    ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
-    ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
-    ea.n_dv = 1; ea.dv = nullptr; ea.dv_single = dv; ea.out = e_out;
-    rec(c, CPM_KERNEL_ENERGY, [=] { launch_energy(s, 1, ea); });
+    const EnergyArgs ea = energy_args(c, 1, nullptr, dv, e_out);
+    TRY(enqueue_forces<T>(c, 1, q_out, c->n_elec, fa, e_out ? &ea : nullptr));
   }
   return CPM_OK;
 }
@@ -515,7 +555,7 @@ int enqueue_grad(cpm_ctx* c, const double* xyz, double dv, const double* t, doub
   hipStream_t s = c->stream;
   const int n = c->n_elec;
   double* q = q_out ? q_out : c->d_qint;
-  enqueue_b<T>(c, 1, xyz, true);
+  TRY(enqueue_b<T>(c, 1, xyz, true));
   launch_charges(s, 1, n, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q);
   launch_adjoint_rhs(s, n, q, t, c->d_c, dv, c->d_g);
   launch_charges(s, 1, n, c->d_S, c->d_g, c->d_Sc, 0.0, c->d_lam, nullptr);    // lambda = S g
@@ -527,14 +567,8 @@ int enqueue_grad(cpm_ctx* c, const double* xyz, double dv, const double* t, doub
   fa.f_frame_stride = 3 * (size_t)c->n_site;
   fa.n_dv = 1;
   fa.u_site = c->d_usite;
-  enqueue_forces<T>(c, 1, c->d_qa, n, fa);
-  EnergyArgs ea{};
-  ea.n_elec = n; ea.n_site = c->n_site; ea.n_ek = c->n_ek;
-  ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
-  ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
-  ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
-  ea.n_dv = 1; ea.dv = nullptr; ea.dv_single = dv; ea.out = c->d_energy_tmp;
-  launch_energy(s, 1, ea);
+  const EnergyArgs ea = energy_args(c, 1, nullptr, dv, c->d_energy_tmp);
+  TRY(enqueue_forces<T>(c, 1, c->d_qa, n, fa, &ea));
   launch_grad_finish(s, n, q, t, c->d_lam, c->d_c, c->d_energy_tmp, loss, dldv);
   return CPM_OK;
 }
@@ -550,8 +584,7 @@ void enqueue_esc_mesh(cpm_ctx* c, T* out) {
                           B::rho_e(c), c->mi.M);
   launch_fft_xy_t<T, T2>(s, 1, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
   launch_fft_z_t<T, T2>(s, 1, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), nullptr, 0, nullptr);
-  launch_fft_xy_t<T, T2>(s, 1, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, out, out + M, 3 * M);
-  launch_fft_xy_t<T, T2>(s, 1, c->px, c->py, c->mi.K[2], 1, nullptr, B::c2(c), nullptr, out + 2 * M, nullptr, 3 * M);
+  launch_fft_xy_field_inv_t<T, T2>(s, 1, c->px, c->py, c->mi.K[2], B::c1(c), B::c2(c), out, 3 * M);
 }
 
 // Frames [0, nf) of a batch: b for every frame, Q0 = S B in one GEMM, the
@@ -562,7 +595,7 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
   hipStream_t s = c->stream;
   const int n = c->n_elec;
   const bool need_forces = f_out || e_out;
-  enqueue_b<T>(c, nf, xyz, need_forces);
+  TRY(enqueue_b<T>(c, nf, xyz, need_forces));
   // Q0[f][i] = sum_j B[f][j] S[i][j]
   if (std::is_same<T, float>::value) {
     launch_split_b(s, nf, n, c->n_pad, c->d_b, c->d_bsplit);
@@ -585,16 +618,8 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
     fa.n_dv = f_out ? n_dv : 0;
     fa.dv = c->d_dv;
     fa.u_site = c->d_usite;
-    enqueue_forces<T>(c, nf, c->d_Q0, n, fa);
-  }
-  if (e_out) {
-    EnergyArgs ea{};
-    ea.n_elec = n; ea.n_site = c->n_site; ea.n_ek = c->n_ek;
-    ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
-    ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
-    ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
-    ea.n_dv = n_dv; ea.dv = c->d_dv; ea.dv_single = 0.0; ea.out = e_out;
-    launch_energy(s, nf, ea);
+    const EnergyArgs ea = energy_args(c, n_dv, c->d_dv, 0.0, e_out);
+    TRY(enqueue_forces<T>(c, nf, c->d_Q0, n, fa, e_out ? &ea : nullptr));
   }
   return CPM_OK;
 }
@@ -637,6 +662,11 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   if (d->kspace == CPM_KSPACE_EWALD && !(d->kcut > 0)) return fail(nullptr, CPM_EINVAL, "EWALD needs kcut > 0");
   if (d->kspace == CPM_KSPACE_PPPM && (d->order < 2 || d->order > MAX_ORDER))
     return fail(nullptr, CPM_EINVAL, "PPPM order must be 2..%d", MAX_ORDER);
+  if (d->kspace == CPM_KSPACE_PPPM)
+    for (int k = 0; k < 3; ++k)
+      if (d->mesh[k] < d->order)
+        return fail(nullptr, CPM_EINVAL, "PPPM mesh needs at least `order` points per axis (axis %d has %d)", k,
+                    d->mesh[k]);
   if (d->geometry == CPM_DOUBLED_CELL && !d->elec_sub) return fail(nullptr, CPM_EINVAL, "doubled cell needs elec_sub");
   double qsum = 0.0, qabs = 0.0;
   for (int j = 0; j < d->n_site; ++j) {

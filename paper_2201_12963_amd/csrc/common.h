@@ -123,9 +123,6 @@ struct SiteSet {       // cell-sorted sites of frame 0 (add frame * n to index)
   const T* x; const T* y; const T* z; const T* q;
   const int* order; const int* cell_start;
   int n;
-  // B-spline assignment of every site (PPPM only): first mesh index per
-  // axis, wrapped into [0, K), [frame][3][n]; weights [frame][3][P][n]
-  const int* wfirst; const T* w;
 };
 
 template <typename T>
@@ -156,6 +153,37 @@ struct ForceArgs {
   double* f_out; size_t f_frame_stride;   // [frame][n_dv][3][n_site] original order
   int n_dv; const double* dv;             // dV values of the sweep (n_dv == 1: dv may be nullptr)
   double* u_site;                          // [frame][n_site] 1/2 Q_j sum Q_j' g0 (sorted order), or nullptr
+  // site-site real-space sum of every site, sum_j' Q_j' g0(r) r_vec without
+  // k_e and Q_j, [frame][3][n_site] sorted order: written by the site-pair
+  // kernel, read by the site-force kernel
+  double* f_pair;
+};
+
+// LDS of the pair queues of one 256-thread workgroup (four wavefronts,
+// 5 x 128 values each)
+template <typename T>
+constexpr size_t pair_queue_lds() { return 4 * 5 * 128 * sizeof(T); }
+
+// real-space part of b hosted as extra workgroups of another launch
+// (one wavefront per electrode atom, four per workgroup)
+template <typename T>
+struct RealBArgs {
+  int n_blocks;                // workgroups per frame, 0: none
+  T alpha, eta, rc2;
+  ElecSet<T> el;
+  T* phi_out;                  // [frame][n_elec] original order
+};
+
+// site-site forces hosted as extra workgroups of another launch (one
+// wavefront per site, four per workgroup)
+template <typename T>
+struct PairArgs {
+  int n_blocks;                // workgroups per frame, 0: none
+  Cell cell;
+  SiteSet<T> st;
+  T alpha, rc2;
+  double* f_pair;              // [frame][3][n_site] sorted order
+  double* u_site;              // [frame][n_site] sorted order, or nullptr
 };
 
 struct ZPassArgs {
@@ -204,6 +232,38 @@ __device__ __forceinline__ int spline_weights_p(T u, T* w) {
   return (int)fl + 1;
 }
 
+// The same Cox-de Boor triangle for an order P (<= MAX_ORDER) known only at
+// run time, fully unrolled so that it stays in registers: B[j] (j < P) is the
+// weight of mesh point first + P - 1 - j.  Returns first (not wrapped).
+template <typename T>
+__device__ __forceinline__ int spline_triangle(T u, int P, T (&B)[MAX_ORDER]) {
+  T s = u - (T)P * (T)0.5;
+  T fl = floor(s);
+  T f = s - fl;
+  B[0] = (T)1;
+#pragma unroll
+  for (int j = 1; j < MAX_ORDER; ++j) B[j] = (T)0;
+#pragma unroll
+  for (int n = 2; n <= MAX_ORDER; ++n) {
+    if (n <= P) {
+      const T inv = (T)1 / (T)(n - 1);
+#pragma unroll
+      for (int j = n - 1; j >= 0; --j) {
+        T x = f + (T)j;
+        T prev = (j > 0) ? B[j - 1] : (T)0;
+        B[j] = (x * B[j] + ((T)n - x) * prev) * inv;
+      }
+    }
+  }
+  return (int)fl + 1;
+}
+
+// first mesh point of the stencil of scaled coordinate u, as spline_triangle
+template <typename T>
+__device__ __forceinline__ int spline_first(T u, int P) {
+  return (int)floor(u - (T)P * (T)0.5) + 1;
+}
+
 
 // --------------------------------------------------------------- launchers
 
@@ -216,11 +276,15 @@ void launch_bin_sites(hipStream_t s, int n_frames, int n_site, const double* xyz
 // real-space sums (k_realspace.hip)
 template <typename T>
 void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
-                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out,
-                     const MeshInfo& mi, int* wfirst_out, T* w_out);
+                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out);
+template <typename T>
+void launch_site_pairs_t(hipStream_t s, int n_frames, const Cell& cell, const SiteSet<T>& st,
+                         const ForceArgs<T>& fa);
+// forces: the site-force workgroups; ea (or nullptr): one more workgroup per
+// frame that reduces the energies
 template <typename T>
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
-                          const SiteSet<T>& st, const ForceArgs<T>& fa);
+                          const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea);
 size_t bin_lds_bytes(int n_site, int n_cells);
 
 // particle-mesh steps (k_pppm.hip)
@@ -236,15 +300,23 @@ template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                      int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
                      size_t out_re_stride = 0);
+// inverse x-y pass of the field: c1 -> E[0] (re), E[1] (im); c2 -> E[2];
+// both in one launch; E frames frame_stride apart, components M apart
+template <typename T, typename T2>
+void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
+                               const T2* c1, const T2* c2, T* E, size_t frame_stride);
+// z pass; z_pass false launches only the workgroups of pa (if any)
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
-                    T2* data1, T2* data2, T2* save, int add_saved, double* energy_part);
+                    T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass = true,
+                    const PairArgs<T>* pa = nullptr);
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap);
 int fft_xy_spread_stage_cap(int n_site);
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
-                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c);
+                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c,
+                            bool planes = true, const RealBArgs<T>* rb = nullptr);
 
 // explicit Ewald (k_ewald.hip)
 void launch_ewald_sf(hipStream_t s, int n_frames, int nk, const double* kv, const double* ew,
@@ -271,7 +343,6 @@ void launch_dot(hipStream_t s, int n, const double* a, const double* b, double* 
 void launch_rank1(hipStream_t s, int n, double* S, const double* u, const double* sc);
 void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const double* b, const double* Sc, double dv,
                     double* Q0, double* q);
-void launch_energy(hipStream_t s, int n_frames, const EnergyArgs& ea);
 void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
                            const double* Sc, double* q);
 

@@ -17,6 +17,7 @@
 // A round trip real mesh -> potential (or field) mesh is therefore
 // fft_xy(forward) -> fft_z -> fft_xy(inverse).  Mesh layout [z][y][x].
 #include "common.h"
+#include "pairs.h"
 
 namespace cpm {
 
@@ -141,11 +142,14 @@ __device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nli
 
 // mode 0: forward, real input -> complex output
 // mode 1: inverse, complex input -> real part to out_re (and imaginary part to out_im if given)
+// split (mode 1 only): blockIdx.y = 2 frame + part; part 1 transforms in_c2
+// into out_re2 (real part only), part 0 in_c as above
 template <typename T, typename T2>
 __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
                                                 const T* __restrict__ in_re, const T2* __restrict__ in_c,
                                                 T2* __restrict__ out_c, T* __restrict__ out_re,
-                                                T* __restrict__ out_im, size_t out_re_stride) {
+                                                T* __restrict__ out_im, size_t out_re_stride, int split,
+                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
@@ -155,7 +159,10 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
   load_twiddles(px, twx);
   load_twiddles(py, twy);
   const int z = blockIdx.x;
-  const size_t off = ((size_t)blockIdx.y * Kz + z) * NP;
+  const int part = split ? (int)(blockIdx.y & 1) : 0;
+  const int frame = split ? (int)(blockIdx.y >> 1) : (int)blockIdx.y;
+  if (part) { in_c = in_c2; out_re = out_re2; out_im = nullptr; }
+  const size_t off = ((size_t)frame * Kz + z) * NP;
   if (mode == 0) {
     for (int i = threadIdx.x; i < NP; i += blockDim.x) A[i] = T2{in_re[off + i], (T)0};
   } else {
@@ -169,7 +176,7 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
   if (mode == 0) {
     for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2[i];
   } else {
-    const size_t ro = (size_t)blockIdx.y * out_re_stride + (size_t)z * NP;
+    const size_t ro = (size_t)frame * out_re_stride + (size_t)z * NP;
     for (int i = threadIdx.x; i < NP; i += blockDim.x) {
       out_re[ro + i] = r2[i].x;
       if (out_im) out_im[ro + i] = r2[i].y;
@@ -184,16 +191,27 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
 // reaches the plane are found in the contiguous cell-sorted ranges of the
 // cell layers around it, staged (stage_cap entries at most, flushed when
 // the next block-wide chunk could overflow it), and add their P x P in-plane
-// contributions with LDS atomics.  The assembled plane is also written to rho_out (the
+// contributions with LDS atomics, their B-spline weights computed on the spot.  The assembled plane is also written to rho_out (the
 // charge mesh, for inspection), then transformed as in k_fft_xy.
+//
+// Workgroups from n_planes on compute the real-space part of b instead (they
+// need only the binned sites, as the planes do).
 template <typename T, typename T2>
 __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
                                                        Cell cl, SiteSet<T> st, int stage_cap,
-                                                       T* __restrict__ rho_out, T2* __restrict__ out_c) {
+                                                       T* __restrict__ rho_out, T2* __restrict__ out_c,
+                                                       int n_planes, RealBArgs<T> rb) {
   // 16-byte alignment keeps the dynamic area (after the static counter)
   // aligned for the complex values and the FP64 LDS atomics
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int nvalid;
+  if ((int)blockIdx.x >= n_planes) {
+    const int g = ((int)blockIdx.x - n_planes) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+    if (g < rb.el.n)
+      real_b_wave(cl, rb.alpha, rb.eta, rb.rc2, rb.el, st, rb.phi_out, g, blockIdx.y,
+                  reinterpret_cast<T*>(smem) + (threadIdx.x >> 6) * 5 * WaveQueue<T>::CAP);
+    return;
+  }
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
   T2* B = A + NP;
@@ -210,22 +228,41 @@ __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D p
   __syncthreads();
   const int P = mi.order;
   const size_t n = st.n;
-  const int* wfx = st.wfirst + (frame * 3 + 0) * n;
-  const int* wfy = st.wfirst + (frame * 3 + 1) * n;
-  const int* wfz = st.wfirst + (frame * 3 + 2) * n;
+  const T* sx = st.x + (size_t)frame * n;
+  const T* sy = st.y + (size_t)frame * n;
+  const T* sz = st.z + (size_t)frame * n;
   const T* q = st.q + (size_t)frame * n;
-  // (site, y-row) tasks of the staged entries: P atomic adds along x each
+  const T ihx = (T)mi.invh[0], ihy = (T)mi.invh[1], ihz = (T)mi.invh[2];
+  // one task per staged (site, z slot): the site's B-spline weights, then its
+  // P x P in-plane contributions added with LDS atomics
   auto flush = [&](int nv) {
-    for (int t = threadIdx.x; t < nv * P; t += blockDim.x) {
-      const int e = list[t / P], ry = t % P;
+    for (int e_i = threadIdx.x; e_i < nv; e_i += blockDim.x) {
+      const int e = list[e_i];
       const int j = e >> 3, tz = e & 7;
-      int iy = wfy[j] + ry; iy -= (iy >= Ky) ? Ky : 0;
-      const T qw = q[j] * st.w[((frame * 3 + 1) * P + ry) * n + j] * st.w[((frame * 3 + 2) * P + tz) * n + j];
-      const int fx = wfx[j];
-      T* row = acc + iy * Kx;
-      for (int tx = 0; tx < P; ++tx) {
-        int ix = fx + tx; ix -= (ix >= Kx) ? Kx : 0;
-        atomicAdd(row + ix, qw * st.w[((frame * 3 + 0) * P + tx) * n + j]);
+      T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
+      int fx = spline_triangle(sx[j] * ihx, P, Bx);
+      int fy = spline_triangle(sy[j] * ihy, P, By);
+      spline_triangle(sz[j] * ihz, P, Bz);
+      fx = ((fx % Kx) + Kx) % Kx;
+      fy = ((fy % Ky) + Ky) % Ky;
+      T wz = 0;
+#pragma unroll
+      for (int b = 0; b < MAX_ORDER; ++b) wz = (b == P - 1 - tz) ? Bz[b] : wz;
+      const T qz = q[j] * wz;
+#pragma unroll
+      for (int by = 0; by < MAX_ORDER; ++by) {
+        if (by < P) {
+          int iy = fy + (P - 1 - by); iy -= (iy >= Ky) ? Ky : 0;
+          const T qyz = qz * By[by];
+          T* row = acc + iy * Kx;
+#pragma unroll
+          for (int bx = 0; bx < MAX_ORDER; ++bx) {
+            if (bx < P) {
+              int ix = fx + (P - 1 - bx); ix -= (ix >= Kx) ? Kx : 0;
+              atomicAdd(row + ix, qyz * Bx[bx]);
+            }
+          }
+        }
       }
     }
   };
@@ -244,7 +281,9 @@ __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D p
     for (int base = j0; base < j1; base += blockDim.x) {
       const int j = base + threadIdx.x;
       if (j < j1) {
-        int tz = iz - wfz[j];
+        int fz = spline_first(sz[j] * ihz, P);
+        fz = ((fz % Kz) + Kz) % Kz;
+        int tz = iz - fz;
         tz += (tz < 0) ? Kz : 0;
         if (tz < P) {
           int slot = atomicAdd(&nvalid, 1);
@@ -293,9 +332,18 @@ template <typename T, typename T2>
 __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
                                                T2* __restrict__ data1, T2* __restrict__ data2,
                                                T2* __restrict__ save, int add_saved,
-                                               double* __restrict__ energy_part) {
+                                               double* __restrict__ energy_part, int n_z_blocks,
+                                               PairArgs<T> pa) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
+  if ((int)blockIdx.x >= n_z_blocks) {
+    // hosted: site-site forces, one wavefront per site
+    const int j = ((int)blockIdx.x - n_z_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+    if (j < pa.st.n)
+      site_pairs_wave(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, j, blockIdx.y,
+                      reinterpret_cast<T*>(smem) + (threadIdx.x >> 6) * 5 * WaveQueue<T>::CAP);
+    return;
+  }
   const int Kx = za.Kx, Ky = za.Ky, Kz = za.Kz;
   const int y = blockIdx.x / za.nchunk;
   const int x0 = (blockIdx.x - y * za.nchunk) * za.nxc;
@@ -334,7 +382,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
     if (energy_part && threadIdx.x == 0) {
       double s = 0.0;
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-      energy_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.5 * s;
+      energy_part[(size_t)blockIdx.y * n_z_blocks + blockIdx.x] = 0.5 * s;
     }
     T2* Y = fft_lines(X, F1, pz, twz, nc, nc, 1, +1);
     for (int i = threadIdx.x; i < NL; i += blockDim.x) {
@@ -391,21 +439,26 @@ int fft_xy_spread_stage_cap(int n_site) { return std::max(512, std::min(n_site, 
 
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
-                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c) {
+                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c,
+                            bool planes, const RealBArgs<T>* rb) {
   const int cap = fft_xy_spread_stage_cap(st.n);
-  size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n, cap);
-  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), dim3(Kz, n_frames), dim3(256), lds, s, px, py, Kz, mi, cell, st,
-                     cap, rho_out, out_c);
+  const int np = planes ? Kz : 0;
+  const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
+  size_t lds = std::max(fft_xy_spread_lds<T, T2>(px.n, py.n, cap), pair_queue_lds<T>());
+  dim3 grid(np + r.n_blocks, n_frames);
+  if (grid.x == 0) return;
+  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), grid, dim3(256), lds, s, px, py, Kz, mi, cell, st, cap, rho_out,
+                     out_c, np, r);
 }
 
 template size_t fft_xy_spread_lds<double, double2>(int, int, int);
 template size_t fft_xy_spread_lds<float, float2>(int, int, int);
 template void launch_fft_xy_spread_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
                                                       const MeshInfo&, const Cell&, const SiteSet<double>&, double*,
-                                                      double2*);
+                                                      double2*, bool, const RealBArgs<double>*);
 template void launch_fft_xy_spread_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
                                                     const MeshInfo&, const Cell&, const SiteSet<float>&, float*,
-                                                    float2*);
+                                                    float2*, bool, const RealBArgs<float>*);
 
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
@@ -414,15 +467,29 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
   size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
   hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, n_frames), dim3(256), lds, s, px, py, Kz, mode, in_re,
-                     in_c, out_c, out_re, out_im, out_re_stride);
+                     in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
+}
+
+template <typename T, typename T2>
+void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
+                               const T2* c1, const T2* c2, T* E, size_t frame_stride) {
+  const size_t M = (size_t)px.n * py.n * Kz;
+  size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
+  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, 2 * n_frames), dim3(256), lds, s, px, py, Kz, 1,
+                     (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
 }
 
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
-                    T2* data1, T2* data2, T2* save, int add_saved, double* energy_part) {
-  size_t lds = (3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2);
-  hipLaunchKernelGGL((k_fft_z<T, T2>), dim3(za.Ky * za.nchunk, n_frames), dim3(256), lds, s, pz, za, G,
-                     data1, data2, save, add_saved, energy_part);
+                    T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass,
+                    const PairArgs<T>* pa) {
+  const int nzb = z_pass ? za.Ky * za.nchunk : 0;
+  const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
+  size_t lds = std::max((3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2), pair_queue_lds<T>());
+  dim3 grid(nzb + p.n_blocks, n_frames);
+  if (grid.x == 0) return;
+  hipLaunchKernelGGL((k_fft_z<T, T2>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
+                     energy_part, nzb, p);
 }
 
 template void launch_fft_xy_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
@@ -431,8 +498,14 @@ template void launch_fft_xy_t<double, double2>(hipStream_t, int, const FFTPlan1D
 template void launch_fft_xy_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int, int,
                                              const float*, const float2*, float2*, float*, float*, size_t);
 template void launch_fft_z_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
-                                              const double*, double2*, double2*, double2*, int, double*);
+                                              const double*, double2*, double2*, double2*, int, double*, bool,
+                                              const PairArgs<double>*);
 template void launch_fft_z_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
-                                            const float*, float2*, float2*, float2*, int, double*);
+                                            const float*, float2*, float2*, float2*, int, double*, bool,
+                                            const PairArgs<float>*);
+template void launch_fft_xy_field_inv_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&,
+                                                         int, const double2*, const double2*, double*, size_t);
+template void launch_fft_xy_field_inv_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
+                                                       const float2*, const float2*, float*, size_t);
 
 }  // namespace cpm

@@ -288,43 +288,6 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_energy(EnergyArgs ea) {
-  // ten partial sums reduced together: 8 dot products over the electrodes,
-  // the site real-space energies and the k-space energy parts
-  __shared__ double red[4][10];
-  const int frame = blockIdx.x;
-  const size_t fe = (size_t)frame * ea.n_elec;
-  double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < ea.n_elec; i += blockDim.x) {
-    double Q = ea.Q0[fe + i], bb = ea.b[fe + i], sc = ea.Sc[i], c = ea.c[i], d = ea.d[i], z = ea.ze[i];
-    s[0] += Q * bb; s[1] += sc * bb; s[2] += Q * c; s[3] += sc * c;
-    s[4] += d * Q; s[5] += d * sc; s[6] += z * Q; s[7] += z * sc;
-  }
-  for (int j = threadIdx.x; j < ea.n_site; j += blockDim.x) s[8] += ea.u_site[(size_t)frame * ea.n_site + j];
-  for (int j = threadIdx.x; j < ea.n_ek; j += blockDim.x) s[9] += ea.ek[(size_t)frame * ea.n_ek + j];
-#pragma unroll
-  for (int t = 0; t < 10; ++t) s[t] = wave_sum(s[t]);
-  if ((threadIdx.x & 63) == 0)
-    for (int t = 0; t < 10; ++t) red[threadIdx.x >> 6][t] = s[t];
-  __syncthreads();
-  double S[10];
-  for (int t = 0; t < 10; ++t) S[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-  double u_elyt = S[8] + S[9] - ea.self_energy;
-  double zdip = ea.zdip ? ea.zdip[frame] : 0.0;
-  for (int v = threadIdx.x; v < ea.n_dv; v += blockDim.x) {
-    double dv = ea.dv ? ea.dv[v] : ea.dv_single;
-    double qb = S[0] + dv * S[1];
-    double qv = S[0] + dv * (S[2] + S[1]) + dv * dv * S[3];
-    double dq = S[4] + dv * S[5];
-    double zq = S[6] + dv * S[7];
-    double uc = u_elyt - qb + 0.5 * qv;
-    double ecp = uc - dv * dq;
-    if (ea.ff) ecp += dv / ea.Lz * (zq + zdip);
-    double* o = ea.out + ((size_t)frame * ea.n_dv + v) * 2;
-    o[0] = uc;
-    o[1] = ecp;
-  }
-}
 
 // q[f][v][i] = Q0[f][i] + dv[v] Sc[i]
 __global__ __launch_bounds__(256) void k_expand_charges(int n_elec, int n_dv, const double* __restrict__ dv,
@@ -424,9 +387,6 @@ void launch_rank1(hipStream_t s, int n, double* S, const double* u, const double
 void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const double* b, const double* Sc, double dv,
                     double* Q0, double* q) {
   hipLaunchKernelGGL(k_charges, dim3((n + 3) / 4, n_frames), dim3(256), 0, s, n, S, b, Sc, dv, Q0, q);
-}
-void launch_energy(hipStream_t s, int n_frames, const EnergyArgs& ea) {
-  hipLaunchKernelGGL(k_energy, dim3(n_frames), dim3(256), 0, s, ea);
 }
 void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
                            const double* Sc, double* q) {

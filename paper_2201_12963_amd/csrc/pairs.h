@@ -1,0 +1,306 @@
+// Pair machinery of the real-space (short-range) Ewald sums with Gaussian
+// electrode charges (Eq. 1-3), shared by the stand-alone real-space kernels
+// and the kernels that host them as extra workgroups:
+//   electrolyte potential at electrode i:  k_e sum_j Q_j g1(r),
+//       g1(r) = [erfc(alpha r) - erfc(eta r)]/r;
+//   site-site forces through g0(r) = erfc(alpha r)/r.
+//
+// Layout: one 64-wide wavefront per target (an electrode, or a site), lanes
+// test the candidate partners of the neighbouring cells and queue those
+// inside the cutoff (pair compaction below).  Partners are read from the
+// cell-sorted SoA copies, so a wavefront's loads of one cell are contiguous;
+// the 27 (or fewer, for cells that wrap onto themselves) neighbour cells
+// cover every partner within rcut because cells are at least rcut wide.
+// Extra periodic images are looped over when the cell is shorter than
+// 2 rcut.  Results are reduced across the wavefront with butterfly shuffles;
+// no atomics, so every run sums in the same order.
+#pragma once
+#include "common.h"
+#include "erfcx_cheb.h"
+
+namespace cpm {
+
+// erfcx(x) = exp(x^2) erfc(x) for 0 <= x <= ERFCX_XMAX: Clenshaw sum of the
+// Chebyshev series in u(t), t = 2/(2 + x) (coefficients in erfcx_cheb.h)
+__device__ __forceinline__ double erfcx_cheb(double x) {
+  const double t = 2.0 / (2.0 + x);
+  const double u = (t - ERFCX_TMIN) * (2.0 / (1.0 - ERFCX_TMIN)) - 1.0;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = ERFCX_DEG; k > 0; --k) {
+    double b0 = fma(2.0 * u, b1, ERFCX_CHEB[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(u, b1, ERFCX_CHEB[0] - b2);
+}
+
+// erfc(x) given e = exp(-x^2), 0 <= x <= ERFCX_XMAX (alpha rcut is checked
+// against this bound when a context is created); float: the library erfcf
+__device__ __forceinline__ double erfc_from_exp(double x, double e) { return e * erfcx_cheb(x); }
+__device__ __forceinline__ float erfc_from_exp(float x, float) { return erfcf(x); }
+
+__device__ __forceinline__ double t_exp(double x) { return exp(x); }
+__device__ __forceinline__ float t_exp(float x) { return expf(x); }
+__device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }
+
+// ------------------------------------------------------- pair compaction
+//
+// Lanes first test candidates for r < rcut (cheap); the pairs inside the
+// cutoff are appended to a per-wavefront LDS queue (ballot + popcount gives
+// each lane its slot), and the transcendental pair terms are evaluated 64
+// queued pairs at a time, so every lane of that pass does useful work.
+
+template <typename T>
+struct WaveQueue {
+  static constexpr int CAP = 2 * WAVE;
+  T* x; T* y; T* z; T* a; T* b;
+  __device__ __forceinline__ void bind(T* base) {
+    x = base; y = base + CAP; z = base + 2 * CAP; a = base + 3 * CAP; b = base + 4 * CAP;
+  }
+};
+static_assert(pair_queue_lds<double>() == 4 * 5 * WaveQueue<double>::CAP * sizeof(double),
+              "LDS reserved for hosted pair workgroups must hold four wavefront queues");
+
+// append this lane's pair if `in`; returns the new queue length (< 2 * WAVE
+// when called with fewer than WAVE entries queued)
+template <typename T>
+__device__ __forceinline__ int queue_push(WaveQueue<T>& q, int n, bool in, T dx, T dy, T dz, T a, T b) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const unsigned long long m = __ballot(in);
+  if (in) {
+    const int pos = n + __popcll(m & ((1ull << lane) - 1ull));
+    q.x[pos] = dx; q.y[pos] = dy; q.z[pos] = dz; q.a[pos] = a; q.b[pos] = b;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return n + __popcll(m);
+}
+
+// drop the first WAVE entries (already consumed), moving the rest down
+template <typename T>
+__device__ __forceinline__ int queue_pop(WaveQueue<T>& q, int n) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int rest = n - WAVE;
+  T x = 0, y = 0, z = 0, a = 0, b = 0;
+  if (lane < rest) { x = q.x[WAVE + lane]; y = q.y[WAVE + lane]; z = q.z[WAVE + lane]; a = q.a[WAVE + lane]; b = q.b[WAVE + lane]; }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rest) { q.x[lane] = x; q.y[lane] = y; q.z[lane] = z; q.a[lane] = a; q.b[lane] = b; }
+  __builtin_amdgcn_wave_barrier();
+  return rest;
+}
+
+// ------------------------------------------------------------------ b real
+
+// erfc(eta r) and exp(-eta^2 r^2) are below 1e-18 for eta r > 6.5, far under
+// FP64 resolution of the alpha terms they are added to, so they are skipped
+// there (always the case for sites at least 0.33 nm from an electrode atom)
+constexpr double ETA_R_SKIP = 6.5;
+
+template <typename T>
+__device__ __forceinline__ T g1_potential(T dx, T dy, T dz, T q, T alpha, T eta) {
+  T r2 = dx * dx + dy * dy + dz * dz;
+  T r = t_sqrt(r2);
+  T e = erfc_from_exp(alpha * r, t_exp(-alpha * alpha * r2));
+  if (eta * r < (T)ETA_R_SKIP) e -= erfc_from_exp(eta * r, t_exp(-eta * eta * r2));
+  return q * e / r;
+}
+
+// Stencil cell number s of cell (cx, cy, cz): s enumerates the deduplicated
+// neighbour offsets (z slowest).
+__device__ __forceinline__ int stencil_linear(const Cell& cell, int cx, int cy, int cz, int s) {
+  const int nsx = stencil_count(cell.nc[0]), nsy = stencil_count(cell.nc[1]);
+  const int d = s % nsx, b = (s / nsx) % nsy, a = s / (nsx * nsy);
+  const int xc = stencil_cell(cx, d, cell.nc[0]);
+  const int yc = stencil_cell(cy, b, cell.nc[1]);
+  const int zc = stencil_cell(cz, a, cell.nc[2]);
+  return (zc * cell.nc[1] + yc) * cell.nc[0] + xc;
+}
+
+
+// Real-space electrolyte potential at electrode atom g of a frame, one
+// wavefront: k_e sum_j Q_j g1(r) over the sites of the stencil cells.
+// qbuf: this wavefront's queue storage (5 WaveQueue<T>::CAP values of T).
+template <typename T>
+__device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, T rc2, const ElecSet<T>& el,
+                                            const SiteSet<T>& st, T* __restrict__ phi_out, int g, int frame,
+                                            T* qbuf) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const size_t fo = (size_t)frame * st.n;
+  const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
+  if (g >= el.n) return;
+  WaveQueue<T> Q;
+  Q.bind(qbuf);
+  const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
+  const T ex = el.x[g], ey = el.y[g], ez = el.z[g];
+  const int c = el.cell[g];
+  const int cx = c % cell.nc[0], cy = (c / cell.nc[0]) % cell.nc[1], cz = c / (cell.nc[0] * cell.nc[1]);
+  const T L0 = (T)cell.L[0], L1 = (T)cell.L[1], L2 = (T)cell.L[2];
+  const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
+  const int nst = stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
+  // site ranges of all stencil cells, loaded in parallel (lane t: cell t)
+  int my_lo = 0, my_hi = 0;
+  if (lane < nst) {
+    int nc = stencil_linear(cell, cx, cy, cz, lane);
+    my_lo = cs[nc];
+    my_hi = cs[nc + 1];
+  }
+  T acc = 0;
+  int n = 0;
+  for (int t = 0; t < nst; ++t) {
+    const int j0 = __shfl(my_lo, t, WAVE), j1 = __shfl(my_hi, t, WAVE);
+    for (int base = j0; base < j1; base += WAVE) {
+      const int j = base + lane;
+      const bool valid = j < j1;
+      T dx0 = 0, dy0 = 0, dz0 = 0, qj = 0;
+      if (valid) {
+        dx0 = min_image(ex - sx[j], L0, i0);
+        dy0 = min_image(ey - sy[j], L1, i1);
+        dz0 = min_image(ez - sz[j], L2, i2);
+        qj = sq[j];
+      }
+      for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
+        for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
+          for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
+            T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
+            bool in = valid && (dx * dx + dy * dy + dz * dz < rc2);
+            n = queue_push(Q, n, in, dx, dy, dz, qj, (T)0);
+            if (n >= WAVE) {
+              acc += g1_potential(Q.x[lane], Q.y[lane], Q.z[lane], Q.a[lane], alpha, eta);
+              n = queue_pop(Q, n);
+            }
+          }
+    }
+  }
+  if (lane < n) acc += g1_potential(Q.x[lane], Q.y[lane], Q.z[lane], Q.a[lane], alpha, eta);
+  acc = wave_sum(acc);
+  if (lane == 0) phi_out[(size_t)frame * el.n + el.orig[g]] = (T)KE * acc;
+}
+
+// ------------------------------------------------------------ site forces
+
+// radial force factor g(r) = -(d kernel/dr)/r of a site pair (g0) and of a
+// site-Gaussian pair (g1), and the site-pair potential erfc(alpha r)/r
+template <typename T>
+__device__ __forceinline__ void g0_terms(T r2, T alpha, T& g, T& pot) {
+  const T two_over_sqrtpi = (T)1.1283791670955126;
+  T r = t_sqrt(r2);
+  T ir = (T)1 / r;
+  T ex = t_exp(-alpha * alpha * r2);
+  T ec = erfc_from_exp(alpha * r, ex);
+  g = (ec * ir + two_over_sqrtpi * alpha * ex) * ir * ir;
+  pot = ec * ir;
+}
+template <typename T>
+__device__ __forceinline__ T g1_force(T r2, T alpha, T eta) {
+  const T two_over_sqrtpi = (T)1.1283791670955126;
+  T r = t_sqrt(r2);
+  T ir = (T)1 / r;
+  T ex = t_exp(-alpha * alpha * r2);
+  T e = erfc_from_exp(alpha * r, ex);
+  T x = alpha * ex;
+  if (eta * r < (T)ETA_R_SKIP) {
+    T exn = t_exp(-eta * eta * r2);
+    e -= erfc_from_exp(eta * r, exn);
+    x -= eta * exn;
+  }
+  return (e * ir + two_over_sqrtpi * x) * ir * ir;
+}
+
+// queued site pairs: force factor and pair potential (g0)
+template <typename T>
+__device__ __forceinline__ void eval_g0(const WaveQueue<T>& Q, int lane, T alpha, T* fr, T& u) {
+  const T qx = Q.x[lane], qy = Q.y[lane], qz = Q.z[lane];
+  T g, pot;
+  g0_terms(qx * qx + qy * qy + qz * qz, alpha, g, pot);
+  const T w = Q.a[lane] * g;
+  fr[0] += w * qx; fr[1] += w * qy; fr[2] += w * qz;
+  u += Q.a[lane] * pot;
+}
+
+// queued site-Gaussian pairs: force factor (g1) for the charges a (and b)
+template <typename T, bool TWO>
+__device__ __forceinline__ void eval_g1(const WaveQueue<T>& Q, int lane, T alpha, T eta, T* fr, T* frb) {
+  const T qx = Q.x[lane], qy = Q.y[lane], qz = Q.z[lane];
+  const T g = g1_force(qx * qx + qy * qy + qz * qz, alpha, eta);
+  const T w = Q.a[lane] * g;
+  fr[0] += w * qx; fr[1] += w * qy; fr[2] += w * qz;
+  if (TWO) { const T wb = Q.b[lane] * g; frb[0] += wb * qx; frb[1] += wb * qy; frb[2] += wb * qz; }
+}
+
+// cell of a site and the number of stencil cells
+__device__ __forceinline__ int site_cell(const Cell& cell, double x, double y, double z, int& cx, int& cy, int& cz) {
+  cx = cell_coord(x, cell.L[0], cell.nc[0]);
+  cy = cell_coord(y, cell.L[1], cell.nc[1]);
+  cz = cell_coord(z, cell.L[2], cell.nc[2]);
+  return stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
+}
+
+// Site-site part of the force on site j of a frame, one wavefront (it does
+// not depend on the electrode charges): f_pair gets sum_j' Q_j' g0(r) r_vec
+// (without k_e and Q_j), u_site the pair energy
+// 1/2 k_e Q_j sum_j' Q_j' erfc(alpha r)/r.  The cell ranges of the stencil
+// are loaded in parallel up front.  qbuf: as for real_b_wave.
+template <typename T>
+__device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<T>& st, T alpha, T rc2,
+                                                double* __restrict__ f_pair, double* __restrict__ u_site,
+                                                int j, int frame, T* qbuf) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  WaveQueue<T> Q;
+  Q.bind(qbuf);
+  const size_t fo = (size_t)frame * st.n;
+  const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
+  const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
+  const T xj = sx[j], yj = sy[j], zj = sz[j];
+  const T L0 = (T)cell.L[0], L1 = (T)cell.L[1], L2 = (T)cell.L[2];
+  const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
+  int cx, cy, cz;
+  const int nst = site_cell(cell, (double)xj, (double)yj, (double)zj, cx, cy, cz);
+  int s_lo = 0, s_hi = 0;
+  if (lane < nst) {
+    const int nc = stencil_linear(cell, cx, cy, cz, lane);
+    s_lo = cs[nc];
+    s_hi = cs[nc + 1];
+  }
+  T fr[3] = {0, 0, 0};
+  T u = 0;
+  int n = 0;
+  for (int t = 0; t < nst; ++t) {
+    const int k0 = __shfl(s_lo, t, WAVE), k1 = __shfl(s_hi, t, WAVE);
+    for (int base = k0; base < k1; base += WAVE) {
+      const int k = base + lane;
+      const bool valid = k < k1;
+      T dx0 = 0, dy0 = 0, dz0 = 0, ca = 0;
+      if (valid) {
+        dx0 = min_image(xj - sx[k], L0, i0);
+        dy0 = min_image(yj - sy[k], L1, i1);
+        dz0 = min_image(zj - sz[k], L2, i2);
+        ca = sq[k];
+      }
+      for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
+        for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
+          for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
+            const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
+            const bool self = k == j && ix == 0 && iy == 0 && iz == 0;
+            const bool in = valid && !self && (dx * dx + dy * dy + dz * dz < rc2);
+            n = queue_push(Q, n, in, dx, dy, dz, ca, (T)0);
+            if (n >= WAVE) {
+              eval_g0(Q, lane, alpha, fr, u);
+              n = queue_pop(Q, n);
+            }
+          }
+    }
+  }
+  if (lane < n) eval_g0(Q, lane, alpha, fr, u);
+  double e[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) e[d] = (double)wave_sum(fr[d]);
+  const double us = (double)wave_sum(u);
+  if (lane == 0) {
+    double* o = f_pair + (size_t)frame * 3 * st.n;
+    o[j] = e[0]; o[st.n + j] = e[1]; o[2 * st.n + j] = e[2];
+    if (u_site) u_site[fo + j] = 0.5 * KE * (double)sq[j] * us;
+  }
+}
+
+}  // namespace cpm

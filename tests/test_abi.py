@@ -50,9 +50,10 @@ def test_create_rejects_bad_descriptors_without_gpu():
         dict(site_q=w.site_q + 0.01),                        # not neutral
         dict(elec_side=np.zeros(w.n_elec, np.int8)),
         dict(geometry=1),                                    # doubled cell without elec_sub
+        dict(kspace=1, mesh=(16, 4, 64), order=5),           # fewer mesh points than the stencil
         dict(kspace=1, mesh=(7, 16, 64)),                    # 7 is not 2^a 3^b 5^c ... rejected before GPU
     ]
-    for over in cases[:5]:
+    for over in cases[:6]:
         with pytest.raises(binding.CpmError) as ei:
             binding.Context(**{**base, **over})
         assert ei.value.code == binding.CPM_EINVAL

@@ -185,6 +185,29 @@ def test_graph_replay_matches_eager(torch_dev):
     ctx.close()
 
 
+def test_set_matrix_restores_a_built_context(torch_dev):
+    """A context given S from a host copy (checkpoint resume) steps like the one that built it.
+
+    Equal to rounding, not bit for bit: the charge spread adds with LDS
+    atomics, whose order varies from run to run."""
+    torch = torch_dev
+    from paper_2201_12963_amd import Context
+    _say("[gpu] set_matrix paper dc")
+    w, A, S = built("paper", "dc")
+    ctx1, stream = gpu_context(torch, w)
+    ctx2 = Context.from_workload(w, stream=stream)
+    ctx2.set_matrix(ctx1.get_matrix(1))
+    xyz = torch.tensor(w.site_xyz, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        r1 = ctx1.solve(xyz, w.dv)
+        r2 = ctx2.solve(xyz, w.dv)
+    stream.synchronize()
+    for a, b in zip(r1, r2):
+        assert torch.allclose(a, b, rtol=0, atol=1e-12 * float(b.abs().max()))
+    ctx1.close()
+    ctx2.close()
+
+
 def test_nonfinite_positions_are_reported(torch_dev):
     torch = torch_dev
     w, A, S = built("tiny", "ff")
