@@ -73,7 +73,17 @@ typedef struct {
   const unsigned char* elec_sub; /* host [n_elec]: doubled cell, 1 = first sub-cell (e1); NULL for finite field */
   int n_site;           /* number of electrolyte point charges */
   const double* site_q; /* host [n_site] charges (e); must sum to zero within 1e-9 */
+  int flags;            /* CPM_FLAG_* bits, 0 for none */
 } cpm_desc;
+
+/* descriptor flags */
+enum {
+  /* capture each solve in a HIP graph on first use (per set of pointer
+   * arguments and dv, 16 kept) and replay it afterwards; needs a non-null
+   * stream.  Without it every call launches its kernels directly, which is
+   * also what a caller capturing its own graph around the call needs. */
+  CPM_FLAG_GRAPH = 1
+};
 
 /* Create a context: validates the descriptor (alpha < eta/sqrt2, positive
  * box and cutoffs, mesh factorable, neutral electrolyte, sides +-1,
@@ -105,8 +115,9 @@ int cpm_build_elastance(cpm_ctx* ctx);
  *               U_elyt - q.b + 1/2 q.A q; E_cp = U_coul - dV d.q
  *               (+ dV/Lz (z.q + sum Q_j Z_j) for the finite field), whose
  *               negative position gradient is f_out.
- * Repeated calls with identical pointer arguments and dv replay a HIP
- * graph of the step.  CPM_ESTATE before cpm_build_elastance. */
+ * With CPM_FLAG_GRAPH, repeated calls with identical pointer arguments and
+ * dv replay a HIP graph of the step.  CPM_ESTATE before
+ * cpm_build_elastance. */
 int cpm_solve(cpm_ctx* ctx, const double* site_xyz, double dv,
               double* q_out, double* f_out, double* energy_out);
 

@@ -21,6 +21,7 @@ CPM_OK, CPM_EINVAL, CPM_ESTATE, CPM_ENOTSPD, CPM_EDEVICE, CPM_ENOMEM, CPM_ENONFI
 FINITE_FIELD, DOUBLED_CELL = 0, 1
 KSPACE_EWALD, KSPACE_PPPM = 0, 1
 FP64, MIXED = 0, 1
+FLAG_GRAPH = 1
 BUF_CELL_START, BUF_SITE_ORDER, BUF_PHI_REAL, BUF_B, BUF_RHO_MESH, BUF_PHI_MESH, BUF_FIELD_MESH, BUF_NCELL = range(8)
 KERNELS = ("bin", "real_b", "site_pairs", "fft_xy_fwd", "fft_z_pot", "fft_xy_inv", "gather_b", "charges",
            "spread_elec", "fft_xy_fwd_e", "fft_z_field", "fft_xy_inv_e", "site_forces", "energy")
@@ -52,6 +53,7 @@ class CpmDesc(ctypes.Structure):
         ("elec_sub", ctypes.POINTER(ctypes.c_uint8)),
         ("n_site", ctypes.c_int),
         ("site_q", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.c_int),
     ]
 
 
@@ -110,7 +112,7 @@ class Context:
 
     def __init__(self, *, box, geometry, kspace, precision, eta, alpha, rcut, kcut, mesh, order,
                  alpha_build, rcut_build, kcut_build, elec_xyz, elec_side, elec_sub, site_q,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, graph: bool = False):
         self._lib = load_library()
         self._ctx = ctypes.c_void_p()
         self._keep = []
@@ -121,6 +123,7 @@ class Context:
         d.mesh[:] = [int(m) for m in mesh]
         d.order = int(order)
         d.alpha_build, d.rcut_build, d.kcut_build = float(alpha_build), float(rcut_build), float(kcut_build)
+        d.flags = FLAG_GRAPH if graph else 0
         ex = np.ascontiguousarray(elec_xyz, dtype=np.float64)
         es = np.ascontiguousarray(elec_side, dtype=np.int8)
         sq = np.ascontiguousarray(site_q, dtype=np.float64)
@@ -142,14 +145,14 @@ class Context:
             raise CpmError(r, self._lib.cpm_last_error(None).decode())
 
     @classmethod
-    def from_workload(cls, w, precision=FP64, stream=None):
+    def from_workload(cls, w, precision=FP64, stream=None, graph=False):
         """Context for a workloads.Workload."""
         return cls(box=w.box, geometry=DOUBLED_CELL if w.geometry == "dc" else FINITE_FIELD,
                    kspace=KSPACE_PPPM if w.kspace == "pppm" else KSPACE_EWALD, precision=precision,
                    eta=w.eta, alpha=w.alpha, rcut=w.rcut, kcut=w.kcut, mesh=w.mesh, order=w.order,
                    alpha_build=w.alpha_exact, rcut_build=w.rcut_exact, kcut_build=w.kcut_exact,
                    elec_xyz=w.elec_xyz, elec_side=w.elec_side, elec_sub=w.elec_sub, site_q=w.site_q,
-                   stream=stream)
+                   stream=stream, graph=graph)
 
     # ---------------------------------------------------------------- calls
     def _check(self, r):

@@ -43,7 +43,8 @@ struct cpm_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool built = false;
-  bool use_graph = true;
+  bool graph_flag = false;   // CPM_FLAG_GRAPH
+  bool use_graph = false;    // graph_flag and a non-null stream
 
   std::vector<double> hx, hy, hz;          // electrodes (host)
   std::vector<signed char> side;
@@ -378,42 +379,51 @@ template <> struct Bufs<float> {
 };
 
 // Stage 1: positions -> binned sites -> b (frames 0..nf-1).  With PPPM the
-// real-space part of b runs as extra workgroups of the first mesh launch
-// (both need only the binned sites).
+// binning runs as one more workgroup per frame of the first mesh launch (the
+// spread scans the raw positions and needs no cell list), and the real-space
+// part of b as extra workgroups of the z pass that follows.
 template <typename T>
 int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
   using B = Bufs<T>;
   using T2 = typename B::T2;
   hipStream_t s = c->stream;
   const bool mixed = std::is_same<T, float>::value;
-  rec(c, CPM_KERNEL_BIN, s, [=](hipStream_t s) {
-    launch_bin_sites(s, nf, c->n_site, xyz, (size_t)3 * c->n_site, c->d_site_q, c->cell, c->d_cell_start,
-                     c->d_order, c->d_sx, c->d_sy, c->d_sz, c->d_sq, mixed ? c->d_fx : nullptr,
-                     mixed ? c->d_fy : nullptr, mixed ? c->d_fz : nullptr, mixed ? c->d_fq : nullptr, c->d_zdip,
-                     c->d_status);
-  });
+  BinArgs ba{};
+  ba.n_site = c->n_site;
+  ba.xyz_all = xyz;
+  ba.frame_stride = (size_t)3 * c->n_site;
+  ba.site_q = c->d_site_q;
+  ba.cell = c->cell;
+  ba.cell_start_all = c->d_cell_start;
+  ba.order_all = c->d_order;
+  ba.sx_all = c->d_sx; ba.sy_all = c->d_sy; ba.sz_all = c->d_sz; ba.sq_all = c->d_sq;
+  if (mixed) { ba.fx_all = c->d_fx; ba.fy_all = c->d_fy; ba.fz_all = c->d_fz; ba.fq_all = c->d_fq; }
+  ba.zdip_all = c->d_zdip;
+  ba.status = c->d_status;
   SiteSet<T> st = B::sites(c);
   if (c->kspace == CPM_KSPACE_PPPM) {
+    rec(c, CPM_KERNEL_FFT_XY_FWD, s, [=](hipStream_t s) {
+      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, B::rho(c), B::c1(c), true, true);
+    });
+    keep(c, CPM_KERNEL_BIN, [=](hipStream_t s) {
+      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, B::rho(c), B::c1(c), false, true);
+    });
     RealBArgs<T> rb{};
     rb.n_blocks = (c->n_elec + 3) / 4;
+    rb.cell = c->cell;
+    rb.st = st;
     rb.alpha = (T)c->alpha;
     rb.eta = (T)c->eta;
     rb.rc2 = (T)(c->rcut * c->rcut);
     rb.el = B::elec(c);
     rb.phi_out = B::phir(c);
-    // site spread fused with the forward x-y transform, plane by plane, and
-    // the real-space part of b
-    rec(c, CPM_KERNEL_FFT_XY_FWD, s, [=](hipStream_t s) {
-      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, c->cell, st, B::rho(c), B::c1(c),
-                                    true, &rb);
-    });
-    keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) {
-      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, c->cell, st, B::rho(c), B::c1(c),
-                                    false, &rb);
-    });
     rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
-                            forces ? B::save(c) : nullptr, 0, c->d_ek);
+                            forces ? B::save(c) : nullptr, 0, c->d_ek, true, &rb, nullptr);
+    });
+    keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) {
+      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
+                            forces ? B::save(c) : nullptr, 0, c->d_ek, false, &rb, nullptr);
     });
     rec(c, CPM_KERNEL_FFT_XY_INV, s, [=](hipStream_t s) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
@@ -422,6 +432,7 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
       launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b);
     });
   } else {
+    rec(c, CPM_KERNEL_BIN, s, [=](hipStream_t s) { launch_bin_sites(s, nf, ba); });
     rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) {
       launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c));
     });
@@ -472,11 +483,11 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
     });
     rec(c, CPM_KERNEL_FFT_Z_FIELD, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, true,
-                            &pa);
+                            nullptr, &pa);
     });
     keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, false,
-                            &pa);
+                            nullptr, &pa);
     });
     // c1 -> Ex (re), Ey (im); c2 -> Ez; field meshes are [frame][3][M]
     T* E = B::E(c);
@@ -668,6 +679,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
         return fail(nullptr, CPM_EINVAL, "PPPM mesh needs at least `order` points per axis (axis %d has %d)", k,
                     d->mesh[k]);
   if (d->geometry == CPM_DOUBLED_CELL && !d->elec_sub) return fail(nullptr, CPM_EINVAL, "doubled cell needs elec_sub");
+  if (d->flags & ~CPM_FLAG_GRAPH) return fail(nullptr, CPM_EINVAL, "unknown descriptor flags 0x%x", d->flags);
   double qsum = 0.0, qabs = 0.0;
   for (int j = 0; j < d->n_site; ++j) {
     if (!std::isfinite(d->site_q[j])) return fail(nullptr, CPM_ENONFINITE, "non-finite site charge");
@@ -695,7 +707,8 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   c->order = d->order;
   c->n_elec = d->n_elec; c->n_site = d->n_site;
   c->stream = (hipStream_t)hip_stream;
-  c->use_graph = hip_stream != nullptr && std::getenv("CPM_NO_GRAPH") == nullptr;
+  c->graph_flag = (d->flags & CPM_FLAG_GRAPH) != 0;
+  c->use_graph = hip_stream != nullptr && c->graph_flag;
   const int ne = c->n_elec, ns = c->n_site;
   c->hx.assign(d->elec_xyz, d->elec_xyz + ne);
   c->hy.assign(d->elec_xyz + ne, d->elec_xyz + 2 * ne);
@@ -813,9 +826,15 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       fail(c, CPM_EINVAL, "x-y mesh plane too large for LDS");
       return bad(CPM_EINVAL);
     }
-    // z pass: columns per workgroup bounded by LDS (3 buffers) and chosen so
+    // z pass: columns per workgroup bounded by LDS (3 buffers) and by the
+    // register prefetch of the multiplier (ZPASS_MAX_POINTS), and chosen so
     // that there are at least ~64 workgroups per frame
+    if (mi.K[2] > ZPASS_MAX_POINTS) {
+      fail(c, CPM_EINVAL, "mesh has more than %d points along z", ZPASS_MAX_POINTS);
+      return bad(CPM_EINVAL);
+    }
     int maxc = (int)std::max<size_t>(1, (96 * 1024) / (3 * mi.K[2] * elt));
+    maxc = std::min(maxc, ZPASS_MAX_POINTS / mi.K[2]);
     int nchunk = std::max((mi.K[0] + maxc - 1) / maxc, (64 + mi.K[1] - 1) / mi.K[1]);
     nchunk = std::min(nchunk, mi.K[0]);
     int nxc = (mi.K[0] + nchunk - 1) / nchunk;
@@ -875,8 +894,10 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       }
     c->n_touch = (int)touch.size();
     {
-      const size_t need = c->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns))
-                                                    : fft_xy_spread_lds<double, double2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns));
+      const size_t need =
+          std::max(c->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns))
+                                             : fft_xy_spread_lds<double, double2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns)),
+                   bin_lds_256(ns, cl.n_cells));
       if (need > 150 * 1024) {
         fail(c, CPM_EINVAL, "mesh plane and site staging area (%zu bytes) exceed LDS", need);
         return bad(CPM_EINVAL);
@@ -916,7 +937,7 @@ int cpm_set_stream(cpm_ctx* c, void* hip_stream) {
   if (!c) return CPM_EINVAL;
   if ((hipStream_t)hip_stream != c->stream) free_graphs(c);
   c->stream = (hipStream_t)hip_stream;
-  c->use_graph = hip_stream != nullptr && std::getenv("CPM_NO_GRAPH") == nullptr;
+  c->use_graph = hip_stream != nullptr && c->graph_flag;
   return CPM_OK;
 }
 

@@ -169,6 +169,8 @@ constexpr size_t pair_queue_lds() { return 4 * 5 * 128 * sizeof(T); }
 template <typename T>
 struct RealBArgs {
   int n_blocks;                // workgroups per frame, 0: none
+  Cell cell;
+  SiteSet<T> st;               // cell-sorted sites
   T alpha, eta, rc2;
   ElecSet<T> el;
   T* phi_out;                  // [frame][n_elec] original order
@@ -185,6 +187,11 @@ struct PairArgs {
   double* f_pair;              // [frame][3][n_site] sorted order
   double* u_site;              // [frame][n_site] sorted order, or nullptr
 };
+
+// points (columns x Kz) of one z-pass workgroup: 256 threads hold up to 8
+// values each of the prefetched multiplier
+constexpr int ZPASS_PREFETCH = 8;
+constexpr int ZPASS_MAX_POINTS = 256 * ZPASS_PREFETCH;
 
 struct ZPassArgs {
   int Kx, Ky, Kz;
@@ -267,11 +274,21 @@ __device__ __forceinline__ int spline_first(T u, int P) {
 
 // --------------------------------------------------------------- launchers
 
-// cell binning (k_bin.hip)
-void launch_bin_sites(hipStream_t s, int n_frames, int n_site, const double* xyz, size_t frame_stride,
-                      const double* site_q, Cell cell, int* cell_start, int* site_order,
-                      double* sx, double* sy, double* sz, double* sq, float* fx, float* fy, float* fz,
-                      float* fq, double* zdip, int* status);
+// cell binning (bin.h, k_bin.hip)
+struct BinArgs {
+  int n_site;
+  const double* xyz_all;       // [frame][3][n_site], frame_stride apart
+  size_t frame_stride;
+  const double* site_q;        // [n_site]
+  Cell cell;
+  int* cell_start_all;         // [frame][n_cells + 1]
+  int* order_all;              // [frame][n_site]
+  double *sx_all, *sy_all, *sz_all, *sq_all;   // [frame][n_site] (or nullptr)
+  float *fx_all, *fy_all, *fz_all, *fq_all;    // FP32 copies (or nullptr)
+  double* zdip_all;            // [frame]
+  int* status;
+};
+void launch_bin_sites(hipStream_t s, int n_frames, const BinArgs& a);
 
 // real-space sums (k_realspace.hip)
 template <typename T>
@@ -309,14 +326,16 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass = true,
-                    const PairArgs<T>* pa = nullptr);
+                    const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr);
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap);
 int fft_xy_spread_stage_cap(int n_site);
+// LDS of a 256-thread workgroup running the binning body
+size_t bin_lds_256(int n_site, int n_cells);
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
-                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c,
-                            bool planes = true, const RealBArgs<T>* rb = nullptr);
+                            const MeshInfo& mi, const BinArgs& ba, T* rho_out, T2* out_c, bool planes = true,
+                            bool bin = false);
 
 // explicit Ewald (k_ewald.hip)
 void launch_ewald_sf(hipStream_t s, int n_frames, int nk, const double* kv, const double* ew,

@@ -17,6 +17,7 @@
 // A round trip real mesh -> potential (or field) mesh is therefore
 // fft_xy(forward) -> fft_z -> fft_xy(inverse).  Mesh layout [z][y][x].
 #include "common.h"
+#include "bin.h"
 #include "pairs.h"
 
 namespace cpm {
@@ -187,29 +188,25 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
 // ------------------------------------------------- spread fused with x-y
 
 // Forward x-y transform of one z-plane of the electrolyte charge mesh, whose
-// real values are first assembled in LDS: the sites whose B-spline stencil
-// reaches the plane are found in the contiguous cell-sorted ranges of the
-// cell layers around it, staged (stage_cap entries at most, flushed when
-// the next block-wide chunk could overflow it), and add their P x P in-plane
-// contributions with LDS atomics, their B-spline weights computed on the spot.  The assembled plane is also written to rho_out (the
-// charge mesh, for inspection), then transformed as in k_fft_xy.
-//
-// Workgroups from n_planes on compute the real-space part of b instead (they
-// need only the binned sites, as the planes do).
+// real values are first assembled in LDS.  The plane's workgroup scans every
+// site (wrapped into the box as the binning does), stages those whose
+// B-spline stencil reaches the plane (stage_cap entries at most, flushed
+// when the next block-wide chunk could overflow it), and each staged site
+// adds its P x P in-plane contributions with LDS atomics, its weights
+// computed on the spot.  The scan needs no cell list, so the binning of the
+// same frame runs as one more workgroup of this launch (index n_planes).
+// The assembled plane is also written to rho_out (the charge mesh, for
+// inspection), then transformed as in k_fft_xy.
 template <typename T, typename T2>
 __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
-                                                       Cell cl, SiteSet<T> st, int stage_cap,
-                                                       T* __restrict__ rho_out, T2* __restrict__ out_c,
-                                                       int n_planes, RealBArgs<T> rb) {
+                                                       BinArgs ba, int stage_cap, T* __restrict__ rho_out,
+                                                       T2* __restrict__ out_c, int n_planes) {
   // 16-byte alignment keeps the dynamic area (after the static counter)
   // aligned for the complex values and the FP64 LDS atomics
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int nvalid;
   if ((int)blockIdx.x >= n_planes) {
-    const int g = ((int)blockIdx.x - n_planes) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
-    if (g < rb.el.n)
-      real_b_wave(cl, rb.alpha, rb.eta, rb.rc2, rb.el, st, rb.phi_out, g, blockIdx.y,
-                  reinterpret_cast<T*>(smem) + (threadIdx.x >> 6) * 5 * WaveQueue<T>::CAP);
+    bin_block<256>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
     return;
   }
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
@@ -227,11 +224,12 @@ __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D p
   if (threadIdx.x == 0) nvalid = 0;
   __syncthreads();
   const int P = mi.order;
-  const size_t n = st.n;
-  const T* sx = st.x + (size_t)frame * n;
-  const T* sy = st.y + (size_t)frame * n;
-  const T* sz = st.z + (size_t)frame * n;
-  const T* q = st.q + (size_t)frame * n;
+  const int n = ba.n_site;
+  const double* sx = ba.xyz_all + frame * ba.frame_stride;
+  const double* sy = sx + n;
+  const double* sz = sy + n;
+  const double* q = ba.site_q;
+  const double Lx = ba.cell.L[0], Ly = ba.cell.L[1], Lz = ba.cell.L[2];
   const T ihx = (T)mi.invh[0], ihy = (T)mi.invh[1], ihz = (T)mi.invh[2];
   // one task per staged (site, z slot): the site's B-spline weights, then its
   // P x P in-plane contributions added with LDS atomics
@@ -239,16 +237,21 @@ __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D p
     for (int e_i = threadIdx.x; e_i < nv; e_i += blockDim.x) {
       const int e = list[e_i];
       const int j = e >> 3, tz = e & 7;
+      double xj = sx[j], yj = sy[j];
+      if (!isfinite(xj)) xj = 0.0;
+      if (!isfinite(yj)) yj = 0.0;
+      double zj = sz[j];
+      if (!isfinite(zj)) zj = 0.0;
       T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
-      int fx = spline_triangle(sx[j] * ihx, P, Bx);
-      int fy = spline_triangle(sy[j] * ihy, P, By);
-      spline_triangle(sz[j] * ihz, P, Bz);
+      int fx = spline_triangle((T)wrap_coord(xj, Lx) * ihx, P, Bx);
+      int fy = spline_triangle((T)wrap_coord(yj, Ly) * ihy, P, By);
+      spline_triangle((T)wrap_coord(zj, Lz) * ihz, P, Bz);
       fx = ((fx % Kx) + Kx) % Kx;
       fy = ((fy % Ky) + Ky) % Ky;
       T wz = 0;
 #pragma unroll
       for (int b = 0; b < MAX_ORDER; ++b) wz = (b == P - 1 - tz) ? Bz[b] : wz;
-      const T qz = q[j] * wz;
+      const T qz = (T)q[j] * wz;
 #pragma unroll
       for (int by = 0; by < MAX_ORDER; ++by) {
         if (by < P) {
@@ -266,39 +269,30 @@ __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D p
       }
     }
   };
-  // cell layers whose sites can reach this plane (one layer of margin on each side)
-  const double cwz = cl.L[2] / cl.nc[2];
-  const double hz = mi.h[2];
-  const double zlo = (iz - 0.5 * P - 1.0) * hz, zhi = (iz + 0.5 * P + 1.0) * hz;
-  int c0 = (int)floor(zlo / cwz), c1 = (int)floor(zhi / cwz);
-  if (c1 - c0 + 1 > cl.nc[2]) { c0 = 0; c1 = cl.nc[2] - 1; }
-  const int per_layer = cl.nc[0] * cl.nc[1];
-  const int* cs = st.cell_start + (size_t)frame * (cl.n_cells + 1);
-  for (int cz = c0; cz <= c1; ++cz) {
-    const int czw = ((cz % cl.nc[2]) + cl.nc[2]) % cl.nc[2];
-    const int j0 = cs[czw * per_layer], j1 = cs[(czw + 1) * per_layer];
-    // block-wide chunks, so that the list is flushed before it can overflow
-    for (int base = j0; base < j1; base += blockDim.x) {
-      const int j = base + threadIdx.x;
-      if (j < j1) {
-        int fz = spline_first(sz[j] * ihz, P);
-        fz = ((fz % Kz) + Kz) % Kz;
-        int tz = iz - fz;
-        tz += (tz < 0) ? Kz : 0;
-        if (tz < P) {
-          int slot = atomicAdd(&nvalid, 1);
-          list[slot] = j * 8 + tz;                      // site index and its z weight slot
-        }
+  // block-wide chunks over all sites, so that the list is flushed before it
+  // can overflow
+  for (int base = 0; base < n; base += blockDim.x) {
+    const int j = base + threadIdx.x;
+    if (j < n) {
+      double zj = sz[j];
+      if (!isfinite(zj)) zj = 0.0;
+      int fz = spline_first((T)wrap_coord(zj, Lz) * ihz, P);
+      fz = ((fz % Kz) + Kz) % Kz;
+      int tz = iz - fz;
+      tz += (tz < 0) ? Kz : 0;
+      if (tz < P) {
+        int slot = atomicAdd(&nvalid, 1);
+        list[slot] = j * 8 + tz;                        // site index and its z weight slot
       }
+    }
+    __syncthreads();
+    const int nv = nvalid;
+    __syncthreads();                                    // all have read the count before it changes again
+    if (nv > stage_cap - (int)blockDim.x) {
+      flush(nv);
       __syncthreads();
-      const int nv = nvalid;
-      __syncthreads();                                  // all have read the count before it changes again
-      if (nv > stage_cap - (int)blockDim.x) {
-        flush(nv);
-        __syncthreads();
-        if (threadIdx.x == 0) nvalid = 0;
-        __syncthreads();
-      }
+      if (threadIdx.x == 0) nvalid = 0;
+      __syncthreads();
     }
   }
   flush(nvalid);
@@ -333,15 +327,21 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
                                                T2* __restrict__ data1, T2* __restrict__ data2,
                                                T2* __restrict__ save, int add_saved,
                                                double* __restrict__ energy_part, int n_z_blocks,
-                                               PairArgs<T> pa) {
+                                               RealBArgs<T> rb, PairArgs<T> pa) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   if ((int)blockIdx.x >= n_z_blocks) {
-    // hosted: site-site forces, one wavefront per site
-    const int j = ((int)blockIdx.x - n_z_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
-    if (j < pa.st.n)
-      site_pairs_wave(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, j, blockIdx.y,
-                      reinterpret_cast<T*>(smem) + (threadIdx.x >> 6) * 5 * WaveQueue<T>::CAP);
+    // hosted work, one wavefront per target: the real-space part of b
+    // (electrode atoms), then the site-site forces (sites)
+    T* qbuf = reinterpret_cast<T*>(smem) + (threadIdx.x >> 6) * 5 * WaveQueue<T>::CAP;
+    const int hb = (int)blockIdx.x - n_z_blocks;
+    if (hb < rb.n_blocks) {
+      const int g = hb * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+      if (g < rb.el.n) real_b_wave(rb.cell, rb.alpha, rb.eta, rb.rc2, rb.el, rb.st, rb.phi_out, g, blockIdx.y, qbuf);
+    } else {
+      const int j = (hb - rb.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+      if (j < pa.st.n) site_pairs_wave(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, j, blockIdx.y, qbuf);
+    }
     return;
   }
   const int Kx = za.Kx, Ky = za.Ky, Kz = za.Kz;
@@ -355,24 +355,44 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
   T2* twz = C + za.nxc * Kz;
   load_twiddles(pz, twz);
   const size_t fo = (size_t)blockIdx.y * Kx * Ky * Kz;
-  // LDS layout [z][c]: lines along z have element stride nc, line stride 1
+  // LDS layout [z][c]: lines along z have element stride nc, line stride 1;
+  // point i of the workgroup is handled by thread i mod 256 (slot i / 256)
   for (int i = threadIdx.x; i < NL; i += blockDim.x) {
     int zz = i / nc, c = i - zz * nc;
     A[i] = data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c];
+  }
+  // the multiplier (and the saved spectrum) of this thread's points, loaded
+  // now so that their latency overlaps the forward transform
+  T gk[ZPASS_PREFETCH];
+  T2 sv[ZPASS_PREFETCH];
+#pragma unroll
+  for (int u = 0; u < ZPASS_PREFETCH; ++u) {
+    const int i = threadIdx.x + u * 256;
+    gk[u] = (T)0;
+    sv[u] = T2{(T)0, (T)0};
+    if (i < NL) {
+      const int zz = i / nc, c = i - zz * nc;
+      const size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
+      gk[u] = G[g];
+      if (za.mode == 1 && add_saved) sv[u] = save[fo + g];
+    }
   }
   __syncthreads();
   T2* X = fft_lines(A, B, pz, twz, nc, nc, 1, -1);
   T2* F1 = (X == A) ? B : A;
   if (za.mode == 0) {
     double e = 0.0;
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-      int zz = i / nc, c = i - zz * nc;
-      size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
-      T2 v = X[i];
-      if (save) save[fo + g] = v;
-      T gk = G[g];
-      e += (double)gk * ((double)v.x * v.x + (double)v.y * v.y);
-      X[i] = T2{v.x * gk, v.y * gk};
+#pragma unroll
+    for (int u = 0; u < ZPASS_PREFETCH; ++u) {
+      const int i = threadIdx.x + u * 256;
+      if (i < NL) {
+        const int zz = i / nc, c = i - zz * nc;
+        const size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
+        const T2 v = X[i];
+        if (save) save[fo + g] = v;
+        e += (double)gk[u] * ((double)v.x * v.x + (double)v.y * v.y);
+        X[i] = T2{v.x * gk[u], v.y * gk[u]};
+      }
     }
     if (energy_part) {
       e = wave_sum(e);
@@ -393,16 +413,18 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
     // C keeps the spectrum G X; F1 and X serve as the ping-pong pair of
     // the first inverse, A and B of the second
     const T ky = mode_k<T>(y, Ky, (T)za.twopi_L[1]);
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-      int zz = i / nc, c = i - zz * nc;
-      size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
-      T2 v = X[i];
-      if (add_saved) { T2 sv = save[fo + g]; v.x += sv.x; v.y += sv.y; }
-      T gk = G[g];
-      v = T2{v.x * gk, v.y * gk};
-      C[i] = v;
-      T kx = mode_k<T>(x0 + c, Kx, (T)za.twopi_L[0]);
-      F1[i] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};     // (-i kx + ky) v
+#pragma unroll
+    for (int u = 0; u < ZPASS_PREFETCH; ++u) {
+      const int i = threadIdx.x + u * 256;
+      if (i < NL) {
+        const int c = i % nc;
+        T2 v = X[i];
+        if (add_saved) { v.x += sv[u].x; v.y += sv[u].y; }
+        v = T2{v.x * gk[u], v.y * gk[u]};
+        C[i] = v;
+        const T kx = mode_k<T>(x0 + c, Kx, (T)za.twopi_L[0]);
+        F1[i] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};   // (-i kx + ky) v
+      }
     }
     __syncthreads();
     T2* Y = fft_lines(F1, X, pz, twz, nc, nc, 1, +1);
@@ -439,26 +461,25 @@ int fft_xy_spread_stage_cap(int n_site) { return std::max(512, std::min(n_site, 
 
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
-                            const MeshInfo& mi, const Cell& cell, const SiteSet<T>& st, T* rho_out, T2* out_c,
-                            bool planes, const RealBArgs<T>* rb) {
-  const int cap = fft_xy_spread_stage_cap(st.n);
+                            const MeshInfo& mi, const BinArgs& ba, T* rho_out, T2* out_c, bool planes, bool bin) {
+  const int cap = fft_xy_spread_stage_cap(ba.n_site);
   const int np = planes ? Kz : 0;
-  const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
-  size_t lds = std::max(fft_xy_spread_lds<T, T2>(px.n, py.n, cap), pair_queue_lds<T>());
-  dim3 grid(np + r.n_blocks, n_frames);
+  size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n, cap);
+  if (bin) lds = std::max(lds, bin_lds_256(ba.n_site, ba.cell.n_cells));
+  dim3 grid(np + (bin ? 1 : 0), n_frames);
   if (grid.x == 0) return;
-  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), grid, dim3(256), lds, s, px, py, Kz, mi, cell, st, cap, rho_out,
-                     out_c, np, r);
+  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), grid, dim3(256), lds, s, px, py, Kz, mi, ba, cap, rho_out, out_c,
+                     np);
 }
+
+size_t bin_lds_256(int n_site, int n_cells) { return bin_body_lds<256>(n_site, n_cells); }
 
 template size_t fft_xy_spread_lds<double, double2>(int, int, int);
 template size_t fft_xy_spread_lds<float, float2>(int, int, int);
 template void launch_fft_xy_spread_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
-                                                      const MeshInfo&, const Cell&, const SiteSet<double>&, double*,
-                                                      double2*, bool, const RealBArgs<double>*);
+                                                      const MeshInfo&, const BinArgs&, double*, double2*, bool, bool);
 template void launch_fft_xy_spread_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
-                                                    const MeshInfo&, const Cell&, const SiteSet<float>&, float*,
-                                                    float2*, bool, const RealBArgs<float>*);
+                                                    const MeshInfo&, const BinArgs&, float*, float2*, bool, bool);
 
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
@@ -482,14 +503,16 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass,
-                    const PairArgs<T>* pa) {
+                    const RealBArgs<T>* rb, const PairArgs<T>* pa) {
   const int nzb = z_pass ? za.Ky * za.nchunk : 0;
+  const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
-  size_t lds = std::max((3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2), pair_queue_lds<T>());
-  dim3 grid(nzb + p.n_blocks, n_frames);
+  size_t lds = (3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2);
+  if (r.n_blocks + p.n_blocks > 0) lds = std::max(lds, pair_queue_lds<T>());
+  dim3 grid(nzb + r.n_blocks + p.n_blocks, n_frames);
   if (grid.x == 0) return;
   hipLaunchKernelGGL((k_fft_z<T, T2>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
-                     energy_part, nzb, p);
+                     energy_part, nzb, r, p);
 }
 
 template void launch_fft_xy_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
@@ -499,10 +522,10 @@ template void launch_fft_xy_t<float, float2>(hipStream_t, int, const FFTPlan1D&,
                                              const float*, const float2*, float2*, float*, float*, size_t);
 template void launch_fft_z_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                               const double*, double2*, double2*, double2*, int, double*, bool,
-                                              const PairArgs<double>*);
+                                              const RealBArgs<double>*, const PairArgs<double>*);
 template void launch_fft_z_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                             const float*, float2*, float2*, float2*, int, double*, bool,
-                                            const PairArgs<float>*);
+                                            const RealBArgs<float>*, const PairArgs<float>*);
 template void launch_fft_xy_field_inv_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&,
                                                          int, const double2*, const double2*, double*, size_t);
 template void launch_fft_xy_field_inv_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
