@@ -72,6 +72,7 @@ struct cpm_ctx {
   int cap_frames = 0;
   int *d_cell_start = nullptr, *d_order = nullptr, *d_status = nullptr;
   double* d_fpair = nullptr;      // site-site force sums [frame][3][n_site]
+  double* d_wrap = nullptr;       // binning scratch: wrapped coordinates [frame][3][n_site]
   double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
   float *d_fx = nullptr, *d_fy = nullptr, *d_fz = nullptr, *d_fq = nullptr;
   double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
@@ -278,6 +279,7 @@ int alloc_frames(cpm_ctx* c, int nf) {
   TRY(dalloc(c, &c->d_phir, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_zdip, (size_t)nf));
   TRY(dalloc(c, &c->d_fpair, (size_t)nf * 3 * ns));
+  TRY(dalloc(c, &c->d_wrap, (size_t)nf * 3 * ns));
   TRY(dalloc(c, &c->d_b, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_Q0, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_qint, (size_t)nf * ne));
@@ -400,6 +402,7 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
   if (mixed) { ba.fx_all = c->d_fx; ba.fy_all = c->d_fy; ba.fz_all = c->d_fz; ba.fq_all = c->d_fq; }
   ba.zdip_all = c->d_zdip;
   ba.status = c->d_status;
+  ba.wrap_all = c->d_wrap;
   SiteSet<T> st = B::sites(c);
   if (c->kspace == CPM_KSPACE_PPPM) {
     rec(c, CPM_KERNEL_FFT_XY_FWD, s, [=](hipStream_t s) {
@@ -897,7 +900,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       const size_t need =
           std::max(c->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns))
                                              : fft_xy_spread_lds<double, double2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns)),
-                   bin_lds_256(ns, cl.n_cells));
+                   bin_lds_spread(ns, cl.n_cells));
       if (need > 150 * 1024) {
         fail(c, CPM_EINVAL, "mesh plane and site staging area (%zu bytes) exceed LDS", need);
         return bad(CPM_EINVAL);

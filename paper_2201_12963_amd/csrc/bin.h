@@ -13,6 +13,8 @@
 //      the cell_start array;
 //   4. every site goes to offset + rank, all sites in parallel, so the sites
 //      of a cell appear in increasing original index (a stable counting sort).
+// The wrapped coordinates come from the same quotient x/L as the cell index
+// (computed once, in step 1, and parked in a scratch array until step 4).
 // The sorted SoA copies (wrapped x, y, z and the charge) are what the later
 // kernels stream; the body also sums Q_j Z_j for the finite-field energy.
 #pragma once
@@ -22,7 +24,7 @@ namespace cpm {
 
 
 // sites per thread whose loads are issued together
-constexpr int BIN_BATCH = 4;
+constexpr int BIN_BATCH = 6;
 
 // LDS of the body (ints): cell ids, ranks, per-wave histograms, cell totals
 template <int NT>
@@ -31,6 +33,17 @@ size_t bin_body_lds(int n_site, int n_cells) {
 }
 
 __device__ __forceinline__ double wrap_coord(double x, double L) { return x - L * floor(x / L); }
+
+// wrapped coordinate x - L floor(x/L) and cell index min(floor(f n), n - 1),
+// f = x/L - floor(x/L), from one quotient (the same operations as
+// cell_coord and wrap_coord)
+__device__ __forceinline__ double wrap_and_cell(double x, double L, int n, int& c) {
+  const double t = x / L;
+  const double fl = floor(t);
+  const int ci = (int)floor((t - fl) * (double)n);
+  c = ci < n - 1 ? ci : n - 1;
+  return x - L * fl;
+}
 
 template <int NT>
 __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds) {
@@ -53,7 +66,12 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   int* cell_start = a.cell_start_all + (size_t)frame * (n_cells + 1);
   int* order = a.order_all + (size_t)frame * n_site;
 
-  // 1. cell ids; the loads of BIN_BATCH sites per thread are issued together
+  double* wx = a.wrap_all + (size_t)frame * 3 * n_site;
+  double* wy = wx + n_site;
+  double* wz = wy + n_site;
+
+  // 1. cell ids and wrapped coordinates; the loads of BIN_BATCH sites per
+  // thread are issued together
   double zd = 0.0;
   int bad = 0;
   for (int i0 = tid; i0 < n_site; i0 += BIN_BATCH * NT) {
@@ -70,11 +88,13 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
       if (i < n_site) {
         double xi = xv[u], yi = yv[u], zi = zv[u];
         if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) { bad = 1; xi = yi = zi = 0.0; }
-        const int cx = cell_coord(xi, cell.L[0], cell.nc[0]);
-        const int cy = cell_coord(yi, cell.L[1], cell.nc[1]);
-        const int cz = cell_coord(zi, cell.L[2], cell.nc[2]);
+        int cx, cy, cz;
+        const double ax = wrap_and_cell(xi, cell.L[0], cell.nc[0], cx);
+        const double ay = wrap_and_cell(yi, cell.L[1], cell.nc[1], cy);
+        const double az = wrap_and_cell(zi, cell.L[2], cell.nc[2], cz);
         cid[i] = (cz * cell.nc[1] + cy) * cell.nc[0] + cx;
-        zd += qv[u] * wrap_coord(zi, cell.L[2]);
+        wx[i] = ax; wy[i] = ay; wz[i] = az;
+        zd += qv[u] * az;
       }
     }
   }
@@ -105,7 +125,8 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
       eq &= ((key >> b) & 1) ? bb : ~bb;
     }
     const int r = __popcll(eq & lt);
-    if (key < n_cells) rnk[i] = hist[wave * n_cells + key] + r;
+    // rank in the low 24 bits, owning wave above (no division by per_wave later)
+    if (key < n_cells) rnk[i] = (wave << 24) | (hist[wave * n_cells + key] + r);
     // every lane has read the count; the group leader advances it
     __builtin_amdgcn_wave_barrier();
     if (key < n_cells && r == 0) hist[wave * n_cells + key] += __popcll(eq);
@@ -166,19 +187,16 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
       xv[u] = yv[u] = zv[u] = qv[u] = 0.0;
       pv[u] = 0;
       if (i < n_site) {
-        xv[u] = x[i]; yv[u] = y[i]; zv[u] = z[i]; qv[u] = a.site_q[i];
-        pv[u] = hist[(i / per_wave) * n_cells + cid[i]] + rnk[i];
+        xv[u] = wx[i]; yv[u] = wy[i]; zv[u] = wz[i]; qv[u] = a.site_q[i];
+        const int rw = rnk[i];
+        pv[u] = hist[(rw >> 24) * n_cells + cid[i]] + (rw & 0xffffff);
       }
     }
 #pragma unroll
     for (int u = 0; u < BIN_BATCH; ++u) {
       const int i = i0 + u * NT;
       if (i < n_site) {
-        double xi = xv[u], yi = yv[u], zi = zv[u];
-        if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) xi = yi = zi = 0.0;
-        xi = wrap_coord(xi, cell.L[0]);
-        yi = wrap_coord(yi, cell.L[1]);
-        zi = wrap_coord(zi, cell.L[2]);
+        const double xi = xv[u], yi = yv[u], zi = zv[u];
         const int pos = pv[u];
         order[pos] = i;
         if (sx) { sx[pos] = xi; sy[pos] = yi; sz[pos] = zi; sq[pos] = qv[u]; }

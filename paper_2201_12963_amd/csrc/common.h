@@ -287,6 +287,7 @@ struct BinArgs {
   float *fx_all, *fy_all, *fz_all, *fq_all;    // FP32 copies (or nullptr)
   double* zdip_all;            // [frame]
   int* status;
+  double* wrap_all;            // scratch [frame][3][n_site]: wrapped coordinates, original order
 };
 void launch_bin_sites(hipStream_t s, int n_frames, const BinArgs& a);
 
@@ -330,8 +331,10 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap);
 int fft_xy_spread_stage_cap(int n_site);
-// LDS of a 256-thread workgroup running the binning body
-size_t bin_lds_256(int n_site, int n_cells);
+// threads of the spread + x-y transform workgroups (which also run the binning)
+constexpr int SPREAD_THREADS = 512;
+// LDS of such a workgroup running the binning body
+size_t bin_lds_spread(int n_site, int n_cells);
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                             const MeshInfo& mi, const BinArgs& ba, T* rho_out, T2* out_c, bool planes = true,

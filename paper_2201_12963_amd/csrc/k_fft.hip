@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
 // The assembled plane is also written to rho_out (the charge mesh, for
 // inspection), then transformed as in k_fft_xy.
 template <typename T, typename T2>
-__global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
+__global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
                                                        BinArgs ba, int stage_cap, T* __restrict__ rho_out,
                                                        T2* __restrict__ out_c, int n_planes) {
   // 16-byte alignment keeps the dynamic area (after the static counter)
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D p
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int nvalid;
   if ((int)blockIdx.x >= n_planes) {
-    bin_block<256>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
+    bin_block<SPREAD_THREADS>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
     return;
   }
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
@@ -457,7 +457,7 @@ size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap) {
   return (2 * (size_t)Kx * Ky + Kx + Ky) * sizeof(T2) + (size_t)Kx * Ky * sizeof(T) + (size_t)stage_cap * sizeof(int);
 }
 
-int fft_xy_spread_stage_cap(int n_site) { return std::max(512, std::min(n_site, 4096)); }
+int fft_xy_spread_stage_cap(int n_site) { return std::max(2 * SPREAD_THREADS, std::min(n_site, 4096)); }
 
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
@@ -465,14 +465,14 @@ void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, co
   const int cap = fft_xy_spread_stage_cap(ba.n_site);
   const int np = planes ? Kz : 0;
   size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n, cap);
-  if (bin) lds = std::max(lds, bin_lds_256(ba.n_site, ba.cell.n_cells));
+  if (bin) lds = std::max(lds, bin_lds_spread(ba.n_site, ba.cell.n_cells));
   dim3 grid(np + (bin ? 1 : 0), n_frames);
   if (grid.x == 0) return;
-  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), grid, dim3(256), lds, s, px, py, Kz, mi, ba, cap, rho_out, out_c,
+  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, cap, rho_out, out_c,
                      np);
 }
 
-size_t bin_lds_256(int n_site, int n_cells) { return bin_body_lds<256>(n_site, n_cells); }
+size_t bin_lds_spread(int n_site, int n_cells) { return bin_body_lds<SPREAD_THREADS>(n_site, n_cells); }
 
 template size_t fft_xy_spread_lds<double, double2>(int, int, int);
 template size_t fft_xy_spread_lds<float, float2>(int, int, int);

@@ -97,8 +97,9 @@ def test_step_parity_sites_crowded_into_one_layer(torch_dev):
     per_plane = np.zeros(w.mesh[2], int)
     for t in range(w.order):
         np.add.at(per_plane, (first + t) % w.mesh[2], 1)
-    cap = max(512, min(w.n_site, 4096))
-    assert per_plane.max() > cap - 256
+    threads = 512                      # workgroup size of the spread
+    cap = max(2 * threads, min(w.n_site, 4096))
+    assert per_plane.max() > cap - threads
     check_step(torch_dev, wc, A, S)
 
 
