@@ -159,10 +159,10 @@ struct ForceArgs {
   double* f_pair;
 };
 
-// LDS of the pair queues of one 256-thread workgroup (four wavefronts,
-// 5 x 128 values each)
+// LDS of the pair scratch of one 256-thread workgroup: four wavefronts,
+// each with a queue of 5 x 128 values and 64 ints of partner runs
 template <typename T>
-constexpr size_t pair_queue_lds() { return 4 * 5 * 128 * sizeof(T); }
+constexpr size_t pair_queue_lds() { return 4 * (5 * 128 * sizeof(T) + 64 * sizeof(int)); }
 
 // real-space part of b hosted as extra workgroups of another launch
 // (one wavefront per electrode atom, four per workgroup)

@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
   if ((int)blockIdx.x >= n_z_blocks) {
     // hosted work, one wavefront per target: the real-space part of b
     // (electrode atoms), then the site-site forces (sites)
-    T* qbuf = reinterpret_cast<T*>(smem) + (threadIdx.x >> 6) * 5 * WaveQueue<T>::CAP;
+    T* qbuf = reinterpret_cast<T*>(smem + (threadIdx.x >> 6) * wave_scratch_bytes<T>());
     const int hb = (int)blockIdx.x - n_z_blocks;
     if (hb < rb.n_blocks) {
       const int g = hb * (blockDim.x / WAVE) + (threadIdx.x >> 6);

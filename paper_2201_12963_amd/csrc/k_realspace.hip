@@ -10,10 +10,11 @@ namespace cpm {
 template <typename T>
 __global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, T rc2, ElecSet<T> el,
                                                 SiteSet<T> st, T* __restrict__ phi_out) {
-  __shared__ T qbuf[4][5 * WaveQueue<T>::CAP];
+  __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
   const int g = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   if (g >= el.n) return;
-  real_b_wave(cell, alpha, eta, rc2, el, st, phi_out, g, blockIdx.y, qbuf[threadIdx.x >> 6]);
+  real_b_wave(cell, alpha, eta, rc2, el, st, phi_out, g, blockIdx.y,
+              reinterpret_cast<T*>(scratch + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
 }
 
 template <typename T>
@@ -27,10 +28,11 @@ void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha
 template <typename T>
 __global__ __launch_bounds__(256) void k_site_pairs(Cell cell, SiteSet<T> st, T alpha, T rc2,
                                                     double* __restrict__ f_pair, double* __restrict__ u_site) {
-  __shared__ T qbuf[4][5 * WaveQueue<T>::CAP];
+  __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
   const int j = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   if (j >= st.n) return;
-  site_pairs_wave(cell, st, alpha, rc2, f_pair, u_site, j, blockIdx.y, qbuf[threadIdx.x >> 6]);
+  site_pairs_wave(cell, st, alpha, rc2, f_pair, u_site, j, blockIdx.y,
+                  reinterpret_cast<T*>(scratch + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
 }
 
 
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
     energy_block(en, blockIdx.y);
     return;
   }
-  __shared__ T qbuf[4][5 * WaveQueue<T>::CAP];
+  __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
   __shared__ T wsp[4][3][MAX_ORDER];
   __shared__ int fsp[4][3];
   const int lane = threadIdx.x & (WAVE - 1);
@@ -57,8 +59,11 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   const int j = blockIdx.x * (blockDim.x / WAVE) + wv;
   const int frame = blockIdx.y;
   if (j >= st.n) return;
+  T* ws = reinterpret_cast<T*>(scratch + wv * wave_scratch_bytes<T>());
   WaveQueue<T> Q;
-  Q.bind(qbuf[wv]);
+  Q.bind(ws);
+  int* rlo = reinterpret_cast<int*>(ws + 5 * WaveQueue<T>::CAP);
+  int* rhi = rlo + 32;
   const size_t fo = (size_t)frame * st.n;
   const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
   const T xj = sx[j], yj = sy[j], zj = sz[j], qj = sq[j];
@@ -66,11 +71,11 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
   int cx, cy, cz;
   const int nst = site_cell(cell, (double)xj, (double)yj, (double)zj, cx, cy, cz);
-  int e_lo = 0, e_hi = 0;
+  int e_lo = 0, e_hi = 0, e_c = 0;
   if (lane < nst) {
-    const int nc = stencil_linear(cell, cx, cy, cz, lane);
-    e_lo = el.cell_start[nc];
-    e_hi = el.cell_start[nc + 1];
+    e_c = stencil_linear(cell, cx, cy, cz, lane);
+    e_lo = el.cell_start[e_c];
+    e_hi = el.cell_start[e_c + 1];
   }
 
   // ---- k-space field at the site
@@ -112,34 +117,35 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   T fr[3] = {0, 0, 0};
   T frb[3] = {0, 0, 0};
   const double* qa = fa.qa + (size_t)frame * fa.qa_frame_stride;
+  const int nruns = merge_runs(e_lo, e_hi, e_c, nst, rlo, rhi);
   int n = 0;
-  for (int t = 0; t < nst; ++t) {
-    const int k0 = __shfl(e_lo, t, WAVE), k1 = __shfl(e_hi, t, WAVE);
-    for (int base = k0; base < k1; base += WAVE) {
-      const int k = base + lane;
-      const bool valid = k < k1;
-      T dx0 = 0, dy0 = 0, dz0 = 0, ca = 0, cb = 0;
-      if (valid) {
-        dx0 = min_image(xj - el.x[k], L0, i0);
-        dy0 = min_image(yj - el.y[k], L1, i1);
-        dz0 = min_image(zj - el.z[k], L2, i2);
-        const int o = el.orig[k];
-        ca = (T)qa[o];
-        if (TWO) cb = (T)fa.qb[o];
-      }
-      for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
-        for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
-          for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
-            const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
-            const bool in = valid && (dx * dx + dy * dy + dz * dz < fa.rc2);
-            n = queue_push(Q, n, in, dx, dy, dz, ca, cb);
-            if (n >= WAVE) {
-              eval_g1<T, TWO>(Q, lane, fa.alpha, fa.eta, fr, frb);
-              n = queue_pop(Q, n);
-            }
-          }
-    }
-  }
+  walk_runs(rlo, rhi, nruns,
+            [&](int k, bool v) {
+              ElecPartner<T> p{0, 0, 0, 0};
+              if (v) { p.x = el.x[k]; p.y = el.y[k]; p.z = el.z[k]; p.o = el.orig[k]; }
+              return p;
+            },
+            [&](const ElecPartner<T>& p, int k, bool valid) {
+              T ca = 0, cb = 0;
+              if (valid) {
+                ca = (T)qa[p.o];
+                if (TWO) cb = (T)fa.qb[p.o];
+              }
+              const T dx0 = min_image(xj - p.x, L0, i0);
+              const T dy0 = min_image(yj - p.y, L1, i1);
+              const T dz0 = min_image(zj - p.z, L2, i2);
+              for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
+                for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
+                  for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
+                    const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
+                    const bool in = valid && (dx * dx + dy * dy + dz * dz < fa.rc2);
+                    n = queue_push(Q, n, in, dx, dy, dz, ca, cb);
+                    if (n >= WAVE) {
+                      eval_g1<T, TWO>(Q, lane, fa.alpha, fa.eta, fr, frb);
+                      n = queue_pop(Q, n);
+                    }
+                  }
+            });
   if (lane < n) eval_g1<T, TWO>(Q, lane, fa.alpha, fa.eta, fr, frb);
 
   // ---- reduce and write

@@ -60,8 +60,6 @@ struct WaveQueue {
     x = base; y = base + CAP; z = base + 2 * CAP; a = base + 3 * CAP; b = base + 4 * CAP;
   }
 };
-static_assert(pair_queue_lds<double>() == 4 * 5 * WaveQueue<double>::CAP * sizeof(double),
-              "LDS reserved for hosted pair workgroups must hold four wavefront queues");
 
 // append this lane's pair if `in`; returns the new queue length (< 2 * WAVE
 // when called with fewer than WAVE entries queued)
@@ -89,6 +87,94 @@ __device__ __forceinline__ int queue_pop(WaveQueue<T>& q, int n) {
   __builtin_amdgcn_wave_barrier();
   return rest;
 }
+
+// ------------------------------------------------- candidate walking
+//
+// Each wavefront keeps, next to its queue, a list of at most 32 runs of
+// partner indices.  The stencil cells' ranges are ordered by cell index (so
+// by position in the cell-sorted arrays) and adjacent ranges are joined, so
+// that the partners are walked in full chunks of 64; the partner data of the
+// next chunk is loaded while the current one is tested and queued.
+
+// LDS of one wavefront: its queue (5 CAP values of T) and the runs (2 x 32 ints)
+template <typename T>
+constexpr size_t wave_scratch_bytes() { return 5 * WaveQueue<T>::CAP * sizeof(T) + 64 * sizeof(int); }
+static_assert(pair_queue_lds<double>() == 4 * wave_scratch_bytes<double>(),
+              "LDS reserved for hosted pair workgroups must hold four wavefront scratch areas");
+static_assert(pair_queue_lds<float>() == 4 * wave_scratch_bytes<float>(),
+              "LDS reserved for hosted pair workgroups must hold four wavefront scratch areas");
+
+// Lanes t < nst hold the range [lo, hi) of stencil cell ci (distinct cells).
+// Writes the merged runs to rlo/rhi and returns their number.
+__device__ __forceinline__ int merge_runs(int lo, int hi, int ci, int nst, int* rlo, int* rhi) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const bool act = lane < nst;
+  int r = 0;
+  for (int u = 0; u < nst; ++u) {
+    const int cu = __shfl(ci, u, WAVE);
+    r += (act && cu < ci) ? 1 : 0;
+  }
+  if (act) { rlo[r] = lo; rhi[r] = hi; }
+  __builtin_amdgcn_wave_barrier();
+  const int l2 = act ? rlo[lane] : 0, h2 = act ? rhi[lane] : 0;
+  __builtin_amdgcn_wave_barrier();
+  const int hprev = __shfl_up(h2, 1, WAVE);
+  const bool start = act && (lane == 0 || l2 != hprev);
+  const unsigned long long sm = __ballot(start);
+  const int run = __popcll(sm & ((2ull << lane) - 1ull)) - 1;      // run holding this lane's range
+  const bool last = act && (lane + 1 == nst || ((sm >> (lane + 1)) & 1ull));
+  if (start) rlo[run] = l2;
+  if (last) rhi[run] = h2;
+  __builtin_amdgcn_wave_barrier();
+  return __popcll(sm);
+}
+
+// Walks the partners listed by the runs 64 at a time: load(k, valid)
+// returns the data of partner k (lane's index in the chunk), body(data, k,
+// valid) consumes it.  The loads of the next chunk are issued before the
+// body of the current one runs.
+template <typename Load, typename Body>
+__device__ __forceinline__ void walk_runs(const int* rlo, const int* rhi, int nruns, Load load, Body body) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  int r = 0, base = 0, end = 0;
+  if (nruns > 0) { base = rlo[0]; end = rhi[0]; }
+  while (r < nruns && base >= end) {
+    ++r;
+    if (r < nruns) { base = rlo[r]; end = rhi[r]; }
+  }
+  if (r >= nruns) return;
+  int ck = base + lane;
+  bool cv = ck < end;
+  auto cur = load(ck, cv);
+  for (;;) {
+    base += WAVE;
+    while (r < nruns && base >= end) {
+      ++r;
+      if (r < nruns) { base = rlo[r]; end = rhi[r]; }
+    }
+    const bool more = r < nruns;
+    const int nk = base + lane;
+    const bool nv = more && nk < end;
+    auto nxt = load(nk, nv);
+    body(cur, ck, cv);
+    if (!more) break;
+    cur = nxt;
+    ck = nk;
+    cv = nv;
+  }
+}
+
+template <typename T>
+struct Partner {
+  T x, y, z, a;
+};
+
+// an electrode atom: position and original index (its charge is per step)
+template <typename T>
+struct ElecPartner {
+  T x, y, z;
+  int o;
+};
 
 // ------------------------------------------------------------------ b real
 
@@ -120,17 +206,18 @@ __device__ __forceinline__ int stencil_linear(const Cell& cell, int cx, int cy, 
 
 // Real-space electrolyte potential at electrode atom g of a frame, one
 // wavefront: k_e sum_j Q_j g1(r) over the sites of the stencil cells.
-// qbuf: this wavefront's queue storage (5 WaveQueue<T>::CAP values of T).
+// scratch: this wavefront's LDS (wave_scratch_bytes<T>()).
 template <typename T>
 __device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, T rc2, const ElecSet<T>& el,
                                             const SiteSet<T>& st, T* __restrict__ phi_out, int g, int frame,
-                                            T* qbuf) {
+                                            T* scratch) {
   const int lane = threadIdx.x & (WAVE - 1);
   const size_t fo = (size_t)frame * st.n;
   const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
-  if (g >= el.n) return;
   WaveQueue<T> Q;
-  Q.bind(qbuf);
+  Q.bind(scratch);
+  int* rlo = reinterpret_cast<int*>(scratch + 5 * WaveQueue<T>::CAP);
+  int* rhi = rlo + 32;
   const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
   const T ex = el.x[g], ey = el.y[g], ez = el.z[g];
   const int c = el.cell[g];
@@ -138,40 +225,38 @@ __device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, T 
   const T L0 = (T)cell.L[0], L1 = (T)cell.L[1], L2 = (T)cell.L[2];
   const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
   const int nst = stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
-  // site ranges of all stencil cells, loaded in parallel (lane t: cell t)
-  int my_lo = 0, my_hi = 0;
+  // site ranges of all stencil cells, loaded in parallel (lane t: cell t), merged into runs
+  int my_lo = 0, my_hi = 0, my_c = 0;
   if (lane < nst) {
-    int nc = stencil_linear(cell, cx, cy, cz, lane);
-    my_lo = cs[nc];
-    my_hi = cs[nc + 1];
+    my_c = stencil_linear(cell, cx, cy, cz, lane);
+    my_lo = cs[my_c];
+    my_hi = cs[my_c + 1];
   }
+  const int nruns = merge_runs(my_lo, my_hi, my_c, nst, rlo, rhi);
   T acc = 0;
   int n = 0;
-  for (int t = 0; t < nst; ++t) {
-    const int j0 = __shfl(my_lo, t, WAVE), j1 = __shfl(my_hi, t, WAVE);
-    for (int base = j0; base < j1; base += WAVE) {
-      const int j = base + lane;
-      const bool valid = j < j1;
-      T dx0 = 0, dy0 = 0, dz0 = 0, qj = 0;
-      if (valid) {
-        dx0 = min_image(ex - sx[j], L0, i0);
-        dy0 = min_image(ey - sy[j], L1, i1);
-        dz0 = min_image(ez - sz[j], L2, i2);
-        qj = sq[j];
-      }
-      for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
-        for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
-          for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
-            T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
-            bool in = valid && (dx * dx + dy * dy + dz * dz < rc2);
-            n = queue_push(Q, n, in, dx, dy, dz, qj, (T)0);
-            if (n >= WAVE) {
-              acc += g1_potential(Q.x[lane], Q.y[lane], Q.z[lane], Q.a[lane], alpha, eta);
-              n = queue_pop(Q, n);
-            }
-          }
-    }
-  }
+  walk_runs(rlo, rhi, nruns,
+            [&](int k, bool v) {
+              Partner<T> p{0, 0, 0, 0};
+              if (v) { p.x = sx[k]; p.y = sy[k]; p.z = sz[k]; p.a = sq[k]; }
+              return p;
+            },
+            [&](const Partner<T>& p, int k, bool valid) {
+              const T dx0 = min_image(ex - p.x, L0, i0);
+              const T dy0 = min_image(ey - p.y, L1, i1);
+              const T dz0 = min_image(ez - p.z, L2, i2);
+              for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
+                for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
+                  for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
+                    const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
+                    const bool in = valid && (dx * dx + dy * dy + dz * dz < rc2);
+                    n = queue_push(Q, n, in, dx, dy, dz, p.a, (T)0);
+                    if (n >= WAVE) {
+                      acc += g1_potential(Q.x[lane], Q.y[lane], Q.z[lane], Q.a[lane], alpha, eta);
+                      n = queue_pop(Q, n);
+                    }
+                  }
+            });
   if (lane < n) acc += g1_potential(Q.x[lane], Q.y[lane], Q.z[lane], Q.a[lane], alpha, eta);
   acc = wave_sum(acc);
   if (lane == 0) phi_out[(size_t)frame * el.n + el.orig[g]] = (T)KE * acc;
@@ -239,15 +324,16 @@ __device__ __forceinline__ int site_cell(const Cell& cell, double x, double y, d
 // Site-site part of the force on site j of a frame, one wavefront (it does
 // not depend on the electrode charges): f_pair gets sum_j' Q_j' g0(r) r_vec
 // (without k_e and Q_j), u_site the pair energy
-// 1/2 k_e Q_j sum_j' Q_j' erfc(alpha r)/r.  The cell ranges of the stencil
-// are loaded in parallel up front.  qbuf: as for real_b_wave.
+// 1/2 k_e Q_j sum_j' Q_j' erfc(alpha r)/r.  scratch: as for real_b_wave.
 template <typename T>
 __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<T>& st, T alpha, T rc2,
                                                 double* __restrict__ f_pair, double* __restrict__ u_site,
-                                                int j, int frame, T* qbuf) {
+                                                int j, int frame, T* scratch) {
   const int lane = threadIdx.x & (WAVE - 1);
   WaveQueue<T> Q;
-  Q.bind(qbuf);
+  Q.bind(scratch);
+  int* rlo = reinterpret_cast<int*>(scratch + 5 * WaveQueue<T>::CAP);
+  int* rhi = rlo + 32;
   const size_t fo = (size_t)frame * st.n;
   const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
   const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
@@ -256,41 +342,39 @@ __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<
   const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
   int cx, cy, cz;
   const int nst = site_cell(cell, (double)xj, (double)yj, (double)zj, cx, cy, cz);
-  int s_lo = 0, s_hi = 0;
+  int s_lo = 0, s_hi = 0, s_c = 0;
   if (lane < nst) {
-    const int nc = stencil_linear(cell, cx, cy, cz, lane);
-    s_lo = cs[nc];
-    s_hi = cs[nc + 1];
+    s_c = stencil_linear(cell, cx, cy, cz, lane);
+    s_lo = cs[s_c];
+    s_hi = cs[s_c + 1];
   }
+  const int nruns = merge_runs(s_lo, s_hi, s_c, nst, rlo, rhi);
   T fr[3] = {0, 0, 0};
   T u = 0;
   int n = 0;
-  for (int t = 0; t < nst; ++t) {
-    const int k0 = __shfl(s_lo, t, WAVE), k1 = __shfl(s_hi, t, WAVE);
-    for (int base = k0; base < k1; base += WAVE) {
-      const int k = base + lane;
-      const bool valid = k < k1;
-      T dx0 = 0, dy0 = 0, dz0 = 0, ca = 0;
-      if (valid) {
-        dx0 = min_image(xj - sx[k], L0, i0);
-        dy0 = min_image(yj - sy[k], L1, i1);
-        dz0 = min_image(zj - sz[k], L2, i2);
-        ca = sq[k];
-      }
-      for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
-        for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
-          for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
-            const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
-            const bool self = k == j && ix == 0 && iy == 0 && iz == 0;
-            const bool in = valid && !self && (dx * dx + dy * dy + dz * dz < rc2);
-            n = queue_push(Q, n, in, dx, dy, dz, ca, (T)0);
-            if (n >= WAVE) {
-              eval_g0(Q, lane, alpha, fr, u);
-              n = queue_pop(Q, n);
-            }
-          }
-    }
-  }
+  walk_runs(rlo, rhi, nruns,
+            [&](int k, bool v) {
+              Partner<T> p{0, 0, 0, 0};
+              if (v) { p.x = sx[k]; p.y = sy[k]; p.z = sz[k]; p.a = sq[k]; }
+              return p;
+            },
+            [&](const Partner<T>& p, int k, bool valid) {
+              const T dx0 = min_image(xj - p.x, L0, i0);
+              const T dy0 = min_image(yj - p.y, L1, i1);
+              const T dz0 = min_image(zj - p.z, L2, i2);
+              for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
+                for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
+                  for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
+                    const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
+                    const bool self = k == j && ix == 0 && iy == 0 && iz == 0;
+                    const bool in = valid && !self && (dx * dx + dy * dy + dz * dz < rc2);
+                    n = queue_push(Q, n, in, dx, dy, dz, p.a, (T)0);
+                    if (n >= WAVE) {
+                      eval_g0(Q, lane, alpha, fr, u);
+                      n = queue_pop(Q, n);
+                    }
+                  }
+            });
   if (lane < n) eval_g0(Q, lane, alpha, fr, u);
   double e[3];
 #pragma unroll
