@@ -74,7 +74,6 @@ struct cpm_ctx {
   double* d_fpair = nullptr;      // site-site force sums [frame][3][n_site]
   double* d_wrap = nullptr;       // binning scratch: wrapped coordinates [frame][3][n_site]
   double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
-  float *d_fx = nullptr, *d_fy = nullptr, *d_fz = nullptr, *d_fq = nullptr;
   double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
   double *d_ek = nullptr, *d_ftmp = nullptr, *d_energy_tmp = nullptr, *d_lam = nullptr, *d_scalar = nullptr;
   double *d_g = nullptr, *d_qa = nullptr, *d_dv = nullptr;
@@ -270,10 +269,6 @@ int alloc_frames(cpm_ctx* c, int nf) {
   TRY(dalloc(c, &c->d_sz, (size_t)nf * ns));
   TRY(dalloc(c, &c->d_sq, (size_t)nf * ns));
   if (mixed) {
-    TRY(dalloc(c, &c->d_fx, (size_t)nf * ns));
-    TRY(dalloc(c, &c->d_fy, (size_t)nf * ns));
-    TRY(dalloc(c, &c->d_fz, (size_t)nf * ns));
-    TRY(dalloc(c, &c->d_fq, (size_t)nf * ns));
     TRY(dalloc(c, &c->d_phirf, (size_t)nf * ne));
   }
   TRY(dalloc(c, &c->d_phir, (size_t)nf * ne));
@@ -364,7 +359,7 @@ template <> struct Bufs<double> {
 template <> struct Bufs<float> {
   using T2 = float2;
   static SiteSet<float> sites(cpm_ctx* c) {
-    return SiteSet<float>{c->d_fx, c->d_fy, c->d_fz, c->d_fq, c->d_order, c->d_cell_start, c->n_site};
+    return SiteSet<float>{c->d_sx, c->d_sy, c->d_sz, c->d_sq, c->d_order, c->d_cell_start, c->n_site};
   }
   static const ElecSet<float>& elec(cpm_ctx* c) { return c->elf; }
   static float* phir(cpm_ctx* c) { return c->d_phirf; }
@@ -399,7 +394,6 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
   ba.cell_start_all = c->d_cell_start;
   ba.order_all = c->d_order;
   ba.sx_all = c->d_sx; ba.sy_all = c->d_sy; ba.sz_all = c->d_sz; ba.sq_all = c->d_sq;
-  if (mixed) { ba.fx_all = c->d_fx; ba.fy_all = c->d_fy; ba.fz_all = c->d_fz; ba.fq_all = c->d_fq; }
   ba.zdip_all = c->d_zdip;
   ba.status = c->d_status;
   ba.wrap_all = c->d_wrap;
@@ -417,7 +411,7 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
     rb.st = st;
     rb.alpha = (T)c->alpha;
     rb.eta = (T)c->eta;
-    rb.rc2 = (T)(c->rcut * c->rcut);
+    rb.rc2 = c->rcut * c->rcut;
     rb.el = B::elec(c);
     rb.phi_out = B::phir(c);
     rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
@@ -460,7 +454,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
   SiteSet<T> st = B::sites(c);
   fa.alpha = (T)c->alpha;
   fa.eta = (T)c->eta;
-  fa.rc2 = (T)(c->rcut * c->rcut);
+  fa.rc2 = c->rcut * c->rcut;
   fa.qa = qa;
   fa.qa_frame_stride = qa_stride;
   fa.mi = c->mi;
@@ -759,7 +753,6 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   std::stable_sort(eorder.begin(), eorder.end(), [&](int a, int b) { return ecell[a] < ecell[b]; });
   std::vector<int> ecs(cl.n_cells + 1, 0), ecell_sorted(ne);
   std::vector<double> sxe(ne), sye(ne), sze(ne);
-  std::vector<float> sxf(ne), syf(ne), szf(ne);
   for (int k = 0; k < ne; ++k) {
     int i = eorder[k];
     ecs[ecell[i] + 1]++;
@@ -767,7 +760,6 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     sxe[k] = wrap_host(c->hx[i], c->box[0]);
     sye[k] = wrap_host(c->hy[i], c->box[1]);
     sze[k] = wrap_host(c->hz[i], c->box[2]);
-    sxf[k] = (float)sxe[k]; syf[k] = (float)sye[k]; szf[k] = (float)sze[k];
   }
   for (int k = 0; k < cl.n_cells; ++k) ecs[k + 1] += ecs[k];
   if ((r = upload(c, &c->d_ex, c->hx)) || (r = upload(c, &c->d_ey, c->hy)) || (r = upload(c, &c->d_ez, c->hz)) ||
@@ -775,13 +767,12 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       (r = upload(c, &c->d_e1, e1)) || (r = upload(c, &c->d_site_q, c->hq)))
     return bad(r);
   {
-    double *x, *y, *z; float *xf, *yf, *zf; int *o, *ce, *cs;
+    double *x, *y, *z; int *o, *ce, *cs;
     if ((r = upload(c, &x, sxe)) || (r = upload(c, &y, sye)) || (r = upload(c, &z, sze)) ||
-        (r = upload(c, &xf, sxf)) || (r = upload(c, &yf, syf)) || (r = upload(c, &zf, szf)) ||
         (r = upload(c, &o, eorder)) || (r = upload(c, &ce, ecell_sorted)) || (r = upload(c, &cs, ecs)))
       return bad(r);
     c->el = ElecSet<double>{x, y, z, o, ce, cs, ne};
-    c->elf = ElecSet<float>{xf, yf, zf, o, ce, cs, ne};
+    c->elf = ElecSet<float>{x, y, z, o, ce, cs, ne};
   }
   if ((r = dalloc(c, &c->d_A, (size_t)ne * ne)) || (r = dalloc(c, &c->d_S, (size_t)ne * ne)) ||
       (r = dalloc(c, &c->d_Sc, ne)) || (r = dalloc(c, &c->d_status, 4)) || (r = dalloc(c, &c->d_scalar, 8)))

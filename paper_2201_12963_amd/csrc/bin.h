@@ -15,8 +15,8 @@
 //      of a cell appear in increasing original index (a stable counting sort).
 // The wrapped coordinates come from the same quotient x/L as the cell index
 // (computed once, in step 1, and parked in a scratch array until step 4).
-// The sorted SoA copies (wrapped x, y, z and the charge) are what the later
-// kernels stream; the body also sums Q_j Z_j for the finite-field energy.
+// The sorted FP64 SoA copies (wrapped x, y, z and the charge) are what the
+// later kernels stream; the body also sums Q_j Z_j for the finite-field energy.
 #pragma once
 #include "common.h"
 
@@ -168,14 +168,10 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   __syncthreads();
 
   // 4. placement, every site independently
-  double* sx = a.sx_all ? a.sx_all + (size_t)frame * n_site : nullptr;
-  double* sy = a.sy_all ? a.sy_all + (size_t)frame * n_site : nullptr;
-  double* sz = a.sz_all ? a.sz_all + (size_t)frame * n_site : nullptr;
-  double* sq = a.sq_all ? a.sq_all + (size_t)frame * n_site : nullptr;
-  float* fx = a.fx_all ? a.fx_all + (size_t)frame * n_site : nullptr;
-  float* fy = a.fy_all ? a.fy_all + (size_t)frame * n_site : nullptr;
-  float* fz = a.fz_all ? a.fz_all + (size_t)frame * n_site : nullptr;
-  float* fq = a.fq_all ? a.fq_all + (size_t)frame * n_site : nullptr;
+  double* sx = a.sx_all + (size_t)frame * n_site;
+  double* sy = a.sy_all + (size_t)frame * n_site;
+  double* sz = a.sz_all + (size_t)frame * n_site;
+  double* sq = a.sq_all + (size_t)frame * n_site;
   // (all loads of a batch before any store: the output may not be assumed
   // apart from the input)
   for (int i0 = tid; i0 < n_site; i0 += BIN_BATCH * NT) {
@@ -199,8 +195,7 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
         const double xi = xv[u], yi = yv[u], zi = zv[u];
         const int pos = pv[u];
         order[pos] = i;
-        if (sx) { sx[pos] = xi; sy[pos] = yi; sz[pos] = zi; sq[pos] = qv[u]; }
-        if (fx) { fx[pos] = (float)xi; fy[pos] = (float)yi; fz[pos] = (float)zi; fq[pos] = (float)qv[u]; }
+        sx[pos] = xi; sy[pos] = yi; sz[pos] = zi; sq[pos] = qv[u];
       }
     }
   }

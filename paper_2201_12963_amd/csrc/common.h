@@ -120,21 +120,24 @@ __device__ __forceinline__ int spline_weights(T u, int P, T* w) {
 
 template <typename T>
 struct SiteSet {       // cell-sorted sites of frame 0 (add frame * n to index)
-  const T* x; const T* y; const T* z; const T* q;
+  // positions and charges stay FP64 in every precision: displacements are
+  // formed in FP64 and only the pair arithmetic runs in T
+  const double* x; const double* y; const double* z; const double* q;
   const int* order; const int* cell_start;
   int n;
 };
 
 template <typename T>
-struct ElecSet {       // cell-sorted electrode atoms (static)
-  const T* x; const T* y; const T* z;
+struct ElecSet {       // cell-sorted electrode atoms (static), FP64 positions
+  const double* x; const double* y; const double* z;
   const int* orig; const int* cell; const int* cell_start;
   int n;
 };
 
 template <typename T>
 struct ForceArgs {
-  T alpha, eta, rc2;
+  T alpha, eta;
+  double rc2;                  // squared cutoff (the cutoff test is FP64 in every precision)
   // k-space field meshes (V/nm, k_e included), [frame][3][M] and a shared
   // second set (or nullptr); mesh geometry for the spline gather
   const T* Ea; size_t Ea_frame_stride;
@@ -171,7 +174,8 @@ struct RealBArgs {
   int n_blocks;                // workgroups per frame, 0: none
   Cell cell;
   SiteSet<T> st;               // cell-sorted sites
-  T alpha, eta, rc2;
+  T alpha, eta;
+  double rc2;
   ElecSet<T> el;
   T* phi_out;                  // [frame][n_elec] original order
 };
@@ -183,7 +187,8 @@ struct PairArgs {
   int n_blocks;                // workgroups per frame, 0: none
   Cell cell;
   SiteSet<T> st;
-  T alpha, rc2;
+  T alpha;
+  double rc2;
   double* f_pair;              // [frame][3][n_site] sorted order
   double* u_site;              // [frame][n_site] sorted order, or nullptr
 };
@@ -265,6 +270,31 @@ __device__ __forceinline__ int spline_triangle(T u, int P, T (&B)[MAX_ORDER]) {
   return (int)fl + 1;
 }
 
+// The same for a scaled coordinate given in FP64 (u up to K): the stencil
+// start and the fractional offset are taken in FP64, the triangle in T.
+template <typename T>
+__device__ __forceinline__ int spline_triangle_d(double u, int P, T (&B)[MAX_ORDER]) {
+  const double s = u - (double)P * 0.5;
+  const double fl = floor(s);
+  const T f = (T)(s - fl);
+  B[0] = (T)1;
+#pragma unroll
+  for (int j = 1; j < MAX_ORDER; ++j) B[j] = (T)0;
+#pragma unroll
+  for (int n = 2; n <= MAX_ORDER; ++n) {
+    if (n <= P) {
+      const T inv = (T)1 / (T)(n - 1);
+#pragma unroll
+      for (int j = n - 1; j >= 0; --j) {
+        T x = f + (T)j;
+        T prev = (j > 0) ? B[j - 1] : (T)0;
+        B[j] = (x * B[j] + ((T)n - x) * prev) * inv;
+      }
+    }
+  }
+  return (int)fl + 1;
+}
+
 // first mesh point of the stencil of scaled coordinate u, as spline_triangle
 template <typename T>
 __device__ __forceinline__ int spline_first(T u, int P) {
@@ -283,8 +313,7 @@ struct BinArgs {
   Cell cell;
   int* cell_start_all;         // [frame][n_cells + 1]
   int* order_all;              // [frame][n_site]
-  double *sx_all, *sy_all, *sz_all, *sq_all;   // [frame][n_site] (or nullptr)
-  float *fx_all, *fy_all, *fz_all, *fq_all;    // FP32 copies (or nullptr)
+  double *sx_all, *sy_all, *sz_all, *sq_all;   // [frame][n_site]
   double* zdip_all;            // [frame]
   int* status;
   double* wrap_all;            // scratch [frame][3][n_site]: wrapped coordinates, original order

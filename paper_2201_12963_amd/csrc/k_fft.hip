@@ -230,7 +230,7 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
   const double* sz = sy + n;
   const double* q = ba.site_q;
   const double Lx = ba.cell.L[0], Ly = ba.cell.L[1], Lz = ba.cell.L[2];
-  const T ihx = (T)mi.invh[0], ihy = (T)mi.invh[1], ihz = (T)mi.invh[2];
+  const double ihx = mi.invh[0], ihy = mi.invh[1], ihz = mi.invh[2];
   // one task per staged (site, z slot): the site's B-spline weights, then its
   // P x P in-plane contributions added with LDS atomics
   auto flush = [&](int nv) {
@@ -243,9 +243,9 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
       double zj = sz[j];
       if (!isfinite(zj)) zj = 0.0;
       T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
-      int fx = spline_triangle((T)wrap_coord(xj, Lx) * ihx, P, Bx);
-      int fy = spline_triangle((T)wrap_coord(yj, Ly) * ihy, P, By);
-      spline_triangle((T)wrap_coord(zj, Lz) * ihz, P, Bz);
+      int fx = spline_triangle_d<T>(wrap_coord(xj, Lx) * ihx, P, Bx);
+      int fy = spline_triangle_d<T>(wrap_coord(yj, Ly) * ihy, P, By);
+      spline_triangle_d<T>(wrap_coord(zj, Lz) * ihz, P, Bz);
       fx = ((fx % Kx) + Kx) % Kx;
       fy = ((fy % Ky) + Ky) % Ky;
       T wz = 0;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
     if (j < n) {
       double zj = sz[j];
       if (!isfinite(zj)) zj = 0.0;
-      int fz = spline_first((T)wrap_coord(zj, Lz) * ihz, P);
+      int fz = spline_first(wrap_coord(zj, Lz) * ihz, P);
       fz = ((fz % Kz) + Kz) % Kz;
       int tz = iz - fz;
       tz += (tz < 0) ? Kz : 0;

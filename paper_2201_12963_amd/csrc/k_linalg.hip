@@ -246,7 +246,8 @@ __global__ void k_rank1(int n, double* __restrict__ S, const double* __restrict_
 
 // ------------------------------------------------------------ charge solve
 
-// Q0 = S b (per frame), q = Q0 + dv Sc; one wavefront per row
+// Q0 = S b (per frame), q = Q0 + dv Sc; one wavefront per row, four
+// independent accumulators so that four row loads per lane are in flight
 __global__ __launch_bounds__(256) void k_charges(int n, const double* __restrict__ S, const double* __restrict__ b_all,
                                                  const double* __restrict__ Sc, double dv,
                                                  double* __restrict__ Q0_all, double* __restrict__ q_all) {
@@ -255,22 +256,31 @@ __global__ __launch_bounds__(256) void k_charges(int n, const double* __restrict
   const int frame = blockIdx.y;
   if (i >= n) return;
   const double* b = b_all + (size_t)frame * n;
-  double acc = 0.0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if ((n & 1) == 0) {       // rows are 16-byte aligned: stream them as double2
     const double2* row = reinterpret_cast<const double2*>(S + (size_t)i * n);
+    const double2* b2 = reinterpret_cast<const double2*>(b);
     const int n2 = n >> 1;
-    for (int j = lane; j < n2; j += WAVE) {
-      double2 s = row[j];
-      acc = fma(s.x, b[2 * j], acc);
-      acc = fma(s.y, b[2 * j + 1], acc);
+    int j = lane;
+    for (; j + 3 * WAVE < n2; j += 4 * WAVE) {
+      const double2 s0 = row[j], s1 = row[j + WAVE], s2 = row[j + 2 * WAVE], s3 = row[j + 3 * WAVE];
+      const double2 v0 = b2[j], v1 = b2[j + WAVE], v2 = b2[j + 2 * WAVE], v3 = b2[j + 3 * WAVE];
+      a0 = fma(s0.x, v0.x, fma(s0.y, v0.y, a0));
+      a1 = fma(s1.x, v1.x, fma(s1.y, v1.y, a1));
+      a2 = fma(s2.x, v2.x, fma(s2.y, v2.y, a2));
+      a3 = fma(s3.x, v3.x, fma(s3.y, v3.y, a3));
+    }
+    for (; j < n2; j += WAVE) {
+      const double2 s0 = row[j], v0 = b2[j];
+      a0 = fma(s0.x, v0.x, fma(s0.y, v0.y, a0));
     }
   } else {
     const double* row = S + (size_t)i * n;
-    for (int j = lane; j < n; j += WAVE) acc = fma(row[j], b[j], acc);
+    for (int j = lane; j < n; j += WAVE) a0 = fma(row[j], b[j], a0);
   }
-  acc = wave_sum(acc);
+  const double acc = wave_sum((a0 + a1) + (a2 + a3));
   if (lane == 0) {
-    size_t o = (size_t)frame * n + i;
+    const size_t o = (size_t)frame * n + i;
     if (Q0_all) Q0_all[o] = acc;
     if (q_all) q_all[o] = acc + dv * Sc[i];
   }

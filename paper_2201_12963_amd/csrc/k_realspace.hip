@@ -8,7 +8,7 @@
 namespace cpm {
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, T rc2, ElecSet<T> el,
+__global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, double rc2, ElecSet<T> el,
                                                 SiteSet<T> st, T* __restrict__ phi_out) {
   __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
   const int g = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
@@ -21,12 +21,12 @@ template <typename T>
 void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
                      double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out) {
   dim3 grid((el.n + 3) / 4, n_frames);
-  hipLaunchKernelGGL(k_real_b<T>, grid, dim3(256), 0, s, cell, (T)alpha, (T)eta, (T)(rcut * rcut),
+  hipLaunchKernelGGL(k_real_b<T>, grid, dim3(256), 0, s, cell, (T)alpha, (T)eta, rcut * rcut,
                      el, st, phi_out);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_site_pairs(Cell cell, SiteSet<T> st, T alpha, T rc2,
+__global__ __launch_bounds__(256) void k_site_pairs(Cell cell, SiteSet<T> st, T alpha, double rc2,
                                                     double* __restrict__ f_pair, double* __restrict__ u_site) {
   __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
   const int j = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
@@ -65,12 +65,10 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   int* rlo = reinterpret_cast<int*>(ws + 5 * WaveQueue<T>::CAP);
   int* rhi = rlo + 32;
   const size_t fo = (size_t)frame * st.n;
-  const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
-  const T xj = sx[j], yj = sy[j], zj = sz[j], qj = sq[j];
-  const T L0 = (T)cell.L[0], L1 = (T)cell.L[1], L2 = (T)cell.L[2];
-  const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
+  const double xj = st.x[fo + j], yj = st.y[fo + j], zj = st.z[fo + j];
+  const double qj = st.q[fo + j];
   int cx, cy, cz;
-  const int nst = site_cell(cell, (double)xj, (double)yj, (double)zj, cx, cy, cz);
+  const int nst = site_cell(cell, xj, yj, zj, cx, cy, cz);
   int e_lo = 0, e_hi = 0, e_c = 0;
   if (lane < nst) {
     e_c = stencil_linear(cell, cx, cy, cz, lane);
@@ -84,11 +82,11 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
     const int P = fa.mi.order;
     const int Kx = fa.mi.K[0], Ky = fa.mi.K[1], Kz = fa.mi.K[2], M = fa.mi.M;
     if (lane < 3) {
-      const T xa = lane == 0 ? xj : (lane == 1 ? yj : zj);
-      const T ih = (T)(lane == 0 ? fa.mi.invh[0] : (lane == 1 ? fa.mi.invh[1] : fa.mi.invh[2]));
+      const double xa = lane == 0 ? xj : (lane == 1 ? yj : zj);
+      const double ih = lane == 0 ? fa.mi.invh[0] : (lane == 1 ? fa.mi.invh[1] : fa.mi.invh[2]);
       const int K = lane == 0 ? Kx : (lane == 1 ? Ky : Kz);
       T B[MAX_ORDER];
-      int first = spline_triangle(xa * ih, P, B);
+      int first = spline_triangle_d<T>(xa * ih, P, B);
       fsp[wv][lane] = ((first % K) + K) % K;
 #pragma unroll
       for (int b = 0; b < MAX_ORDER; ++b)
@@ -121,24 +119,22 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   int n = 0;
   walk_runs(rlo, rhi, nruns,
             [&](int k, bool v) {
-              ElecPartner<T> p{0, 0, 0, 0};
+              ElecPartner p{0, 0, 0, 0};
               if (v) { p.x = el.x[k]; p.y = el.y[k]; p.z = el.z[k]; p.o = el.orig[k]; }
               return p;
             },
-            [&](const ElecPartner<T>& p, int k, bool valid) {
+            [&](const ElecPartner& p, int k, bool valid) {
               T ca = 0, cb = 0;
               if (valid) {
                 ca = (T)qa[p.o];
                 if (TWO) cb = (T)fa.qb[p.o];
               }
-              const T dx0 = min_image(xj - p.x, L0, i0);
-              const T dy0 = min_image(yj - p.y, L1, i1);
-              const T dz0 = min_image(zj - p.z, L2, i2);
+              const Disp d = min_disp(cell, xj, yj, zj, p.x, p.y, p.z);
               for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
                 for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
                   for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
-                    const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
-                    const bool in = valid && (dx * dx + dy * dy + dz * dz < fa.rc2);
+                    T dx, dy, dz;
+                    const bool in = image_pair(cell, d, ix, iy, iz, fa.rc2, dx, dy, dz) && valid;
                     n = queue_push(Q, n, in, dx, dy, dz, ca, cb);
                     if (n >= WAVE) {
                       eval_g1<T, TWO>(Q, lane, fa.alpha, fa.eta, fr, frb);
@@ -155,17 +151,17 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   for (int d = 0; d < 3; ++d) {
     const double e_k = (double)wave_sum(ea[d]);
     const double e_r = (double)wave_sum(fr[d]) + fp[(size_t)d * st.n + j];
-    F[d] = fa.out_scale * (double)qj * (e_k + KE * e_r);
+    F[d] = fa.out_scale * qj * (e_k + KE * e_r);
     if (TWO) {
       const double eb_k = (double)wave_sum(eb[d]);
       const double eb_r = (double)wave_sum(frb[d]);
-      FB[d] = fa.out_scale * (double)qj * (eb_k + KE * eb_r);
+      FB[d] = fa.out_scale * qj * (eb_k + KE * eb_r);
     } else {
       FB[d] = 0.0;
     }
   }
-  F[2] += (double)qj * fa.field;
-  FB[2] += (double)qj * fa.fieldb;
+  F[2] += qj * fa.field;
+  FB[2] += qj * fa.fieldb;
   const int orig = st.order[fo + j];
   double* fout = fa.f_out + (size_t)frame * fa.f_frame_stride;
   for (int v = lane; v < fa.n_dv; v += WAVE) {

@@ -164,17 +164,43 @@ __device__ __forceinline__ void walk_runs(const int* rlo, const int* rhi, int nr
   }
 }
 
+// a partner site: FP64 position (displacements are formed in FP64) and charge
 template <typename T>
 struct Partner {
-  T x, y, z, a;
+  double x, y, z;
+  T a;
 };
 
-// an electrode atom: position and original index (its charge is per step)
-template <typename T>
+// an electrode atom: FP64 position and original index (its charge is per step)
 struct ElecPartner {
-  T x, y, z;
+  double x, y, z;
   int o;
 };
+
+// Minimum-image displacement from a partner to the target, in FP64; the
+// periodic images add (ix, iy, iz) cell lengths, still in FP64, and only the
+// result is rounded to the pair arithmetic's type (two ~10 nm coordinates
+// differenced in FP32 would lose ~1e-6 nm).
+struct Disp {
+  double d0, d1, d2;
+};
+__device__ __forceinline__ Disp min_disp(const Cell& cell, double tx, double ty, double tz, double px, double py,
+                                         double pz) {
+  return Disp{min_image(tx - px, cell.L[0], cell.invL[0]), min_image(ty - py, cell.L[1], cell.invL[1]),
+              min_image(tz - pz, cell.L[2], cell.invL[2])};
+}
+// The displacement to periodic image (ix, iy, iz), rounded to T, and whether
+// the pair lies inside the cutoff: that decision is taken in FP64 in every
+// precision, so that all paths keep the same pairs.
+template <typename T>
+__device__ __forceinline__ bool image_pair(const Cell& cell, const Disp& d, int ix, int iy, int iz, double rc2, T& dx,
+                                           T& dy, T& dz) {
+  const double x = d.d0 + ix * cell.L[0];
+  const double y = d.d1 + iy * cell.L[1];
+  const double z = d.d2 + iz * cell.L[2];
+  dx = (T)x; dy = (T)y; dz = (T)z;
+  return x * x + y * y + z * z < rc2;
+}
 
 // ------------------------------------------------------------------ b real
 
@@ -208,22 +234,21 @@ __device__ __forceinline__ int stencil_linear(const Cell& cell, int cx, int cy, 
 // wavefront: k_e sum_j Q_j g1(r) over the sites of the stencil cells.
 // scratch: this wavefront's LDS (wave_scratch_bytes<T>()).
 template <typename T>
-__device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, T rc2, const ElecSet<T>& el,
+__device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, double rc2, const ElecSet<T>& el,
                                             const SiteSet<T>& st, T* __restrict__ phi_out, int g, int frame,
                                             T* scratch) {
   const int lane = threadIdx.x & (WAVE - 1);
   const size_t fo = (size_t)frame * st.n;
-  const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
+  const double* sx = st.x + fo; const double* sy = st.y + fo; const double* sz = st.z + fo;
+  const double* sq = st.q + fo;
   WaveQueue<T> Q;
   Q.bind(scratch);
   int* rlo = reinterpret_cast<int*>(scratch + 5 * WaveQueue<T>::CAP);
   int* rhi = rlo + 32;
   const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
-  const T ex = el.x[g], ey = el.y[g], ez = el.z[g];
+  const double ex = el.x[g], ey = el.y[g], ez = el.z[g];
   const int c = el.cell[g];
   const int cx = c % cell.nc[0], cy = (c / cell.nc[0]) % cell.nc[1], cz = c / (cell.nc[0] * cell.nc[1]);
-  const T L0 = (T)cell.L[0], L1 = (T)cell.L[1], L2 = (T)cell.L[2];
-  const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
   const int nst = stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
   // site ranges of all stencil cells, loaded in parallel (lane t: cell t), merged into runs
   int my_lo = 0, my_hi = 0, my_c = 0;
@@ -237,19 +262,17 @@ __device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, T 
   int n = 0;
   walk_runs(rlo, rhi, nruns,
             [&](int k, bool v) {
-              Partner<T> p{0, 0, 0, 0};
-              if (v) { p.x = sx[k]; p.y = sy[k]; p.z = sz[k]; p.a = sq[k]; }
+              Partner<T> p{0, 0, 0, (T)0};
+              if (v) { p.x = sx[k]; p.y = sy[k]; p.z = sz[k]; p.a = (T)sq[k]; }
               return p;
             },
             [&](const Partner<T>& p, int k, bool valid) {
-              const T dx0 = min_image(ex - p.x, L0, i0);
-              const T dy0 = min_image(ey - p.y, L1, i1);
-              const T dz0 = min_image(ez - p.z, L2, i2);
+              const Disp d = min_disp(cell, ex, ey, ez, p.x, p.y, p.z);
               for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
                 for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
                   for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
-                    const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
-                    const bool in = valid && (dx * dx + dy * dy + dz * dz < rc2);
+                    T dx, dy, dz;
+                    const bool in = image_pair(cell, d, ix, iy, iz, rc2, dx, dy, dz) && valid;
                     n = queue_push(Q, n, in, dx, dy, dz, p.a, (T)0);
                     if (n >= WAVE) {
                       acc += g1_potential(Q.x[lane], Q.y[lane], Q.z[lane], Q.a[lane], alpha, eta);
@@ -326,7 +349,7 @@ __device__ __forceinline__ int site_cell(const Cell& cell, double x, double y, d
 // (without k_e and Q_j), u_site the pair energy
 // 1/2 k_e Q_j sum_j' Q_j' erfc(alpha r)/r.  scratch: as for real_b_wave.
 template <typename T>
-__device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<T>& st, T alpha, T rc2,
+__device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<T>& st, T alpha, double rc2,
                                                 double* __restrict__ f_pair, double* __restrict__ u_site,
                                                 int j, int frame, T* scratch) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -336,12 +359,11 @@ __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<
   int* rhi = rlo + 32;
   const size_t fo = (size_t)frame * st.n;
   const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
-  const T* sx = st.x + fo; const T* sy = st.y + fo; const T* sz = st.z + fo; const T* sq = st.q + fo;
-  const T xj = sx[j], yj = sy[j], zj = sz[j];
-  const T L0 = (T)cell.L[0], L1 = (T)cell.L[1], L2 = (T)cell.L[2];
-  const T i0 = (T)cell.invL[0], i1 = (T)cell.invL[1], i2 = (T)cell.invL[2];
+  const double* sx = st.x + fo; const double* sy = st.y + fo; const double* sz = st.z + fo;
+  const double* sq = st.q + fo;
+  const double xj = sx[j], yj = sy[j], zj = sz[j];
   int cx, cy, cz;
-  const int nst = site_cell(cell, (double)xj, (double)yj, (double)zj, cx, cy, cz);
+  const int nst = site_cell(cell, xj, yj, zj, cx, cy, cz);
   int s_lo = 0, s_hi = 0, s_c = 0;
   if (lane < nst) {
     s_c = stencil_linear(cell, cx, cy, cz, lane);
@@ -354,20 +376,18 @@ __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<
   int n = 0;
   walk_runs(rlo, rhi, nruns,
             [&](int k, bool v) {
-              Partner<T> p{0, 0, 0, 0};
-              if (v) { p.x = sx[k]; p.y = sy[k]; p.z = sz[k]; p.a = sq[k]; }
+              Partner<T> p{0, 0, 0, (T)0};
+              if (v) { p.x = sx[k]; p.y = sy[k]; p.z = sz[k]; p.a = (T)sq[k]; }
               return p;
             },
             [&](const Partner<T>& p, int k, bool valid) {
-              const T dx0 = min_image(xj - p.x, L0, i0);
-              const T dy0 = min_image(yj - p.y, L1, i1);
-              const T dz0 = min_image(zj - p.z, L2, i2);
+              const Disp d = min_disp(cell, xj, yj, zj, p.x, p.y, p.z);
               for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
                 for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
                   for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
-                    const T dx = dx0 + (T)ix * L0, dy = dy0 + (T)iy * L1, dz = dz0 + (T)iz * L2;
+                    T dx, dy, dz;
                     const bool self = k == j && ix == 0 && iy == 0 && iz == 0;
-                    const bool in = valid && !self && (dx * dx + dy * dy + dz * dz < rc2);
+                    const bool in = image_pair(cell, d, ix, iy, iz, rc2, dx, dy, dz) && valid && !self;
                     n = queue_push(Q, n, in, dx, dy, dz, p.a, (T)0);
                     if (n >= WAVE) {
                       eval_g0(Q, lane, alpha, fr, u);

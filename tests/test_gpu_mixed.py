@@ -123,3 +123,20 @@ def test_large_cell_fp64_against_oracle(torch_dev):
     assert rel_rms(dldx.cpu().numpy(), g["dl_dx"]) < 1e-9
     assert abs(dldv.item() - g["dl_ddv"]) < 1e-8 * abs(g["dl_ddv"])
     ctx.close()
+
+
+def test_mixed_batch_many_frames_within_bar(torch_dev):
+    """4096 perturbed frames: every mixed-precision charge within 1e-6 e of FP64.
+
+    Guards the two places where FP32 would otherwise cross the bar on a few
+    frames: displacements of ~10 nm coordinates (formed in FP64) and the
+    real-space cutoff test (taken in FP64, so both paths keep the same pairs)."""
+    from workloads import perturbed_frames
+    _say("[gpu] mixed batch, 4096 frames paper ff")
+    w = workload("paper", "ff")
+    frames = perturbed_frames(w, 4096)
+    dvs = np.array([0.0, 4.0])
+    (q64, _, _), (q32, _, _) = solve_both(torch_dev, w, frames, dvs)
+    per_frame = np.abs(q32 - q64).max(axis=(1, 2))
+    _say(f"    max {per_frame.max():.3e} e, frames above 1e-6: {int((per_frame > Q_TOL).sum())}")
+    assert per_frame.max() < Q_TOL
