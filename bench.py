@@ -121,6 +121,15 @@ def gpu_steps(torch, w, traj, steps, warmup, precision=0, profile_kernels=False)
     if ctx.sync_status() != 0:
         raise RuntimeError("kernel status flag raised during the timed loop")
     if profile_kernels:
+        if os.environ.get("CPM_BENCH_COPY_CALIBRATION"):
+            # a plain device copy of known size (256 MiB read, 256 MiB
+            # written), for scaling the HBM byte counters of a --pmc run
+            src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)          # the same bytes through an elementwise kernel
+            torch.cuda.synchronize()
+            del src, dst
         # per-kernel average duration: replay the last launch of each kernel,
         # bracketed by events on the context's stream
         times = {}
@@ -142,17 +151,41 @@ def gpu_steps(torch, w, traj, steps, warmup, precision=0, profile_kernels=False)
     return out
 
 
-# launches that also carry another kernel's workgroups (real_b in fft_xy_fwd,
-# site_pairs in fft_z_field): their time mixes memory-bound and ALU-bound
-# work, so the hosted kernels are replayed on their own and the roofline is
-# taken over the kernels that run alone
-HOSTS = ("fft_xy_fwd", "fft_z_field")
+# The roofline kernel: the site-site pair forces, the step's largest
+# arithmetic workload (k_e Q Q' g0 over every site pair within r_c).  In the
+# step its workgroups ride in the field's z-pass launch; it is timed alone
+# through the stand-alone kernel with the same body (k_site_pairs), which
+# the step never launches, so its rocprofv3 average is its own.
+ROOFLINE_KERNEL = "site_pairs"
+
+# HBM traffic of one k_site_pairs launch (doubled paper cell), from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
+# scaled by the same counter's reading for a 256 MiB device copy; valid
+# only while the kernel's sources are the ones measured (hash below).
+TRAFFIC = {"site_pairs": {"bytes": 866230, "sources_sha256": "8441cb53647d0e70e291389d8276166ada8b6e5f85f51c24054049809d77ccb7"}}
+TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    pkg = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2201_12963_amd")
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(pkg, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(name):
+    t = TRAFFIC.get(name)
+    if not t or t["bytes"] is None or t["sources_sha256"] != sources_sha256():
+        return None
+    return t["bytes"]
 
 
 def roofline(w, kernel_ms):
-    """Roofline entry for the longest kernel among those timed alone."""
-    cand = {k: v for k, v in kernel_ms.items() if k not in HOSTS and k != "energy"}
-    name = max(cand, key=lambda k: cand[k])
+    """Roofline entry for the site-site pair kernel, timed alone."""
+    name = ROOFLINE_KERNEL
     ms = kernel_ms[name]
     bound, work, unit = kernel_work(w, name)
     if bound == "hbm":
@@ -162,7 +195,7 @@ def roofline(w, kernel_ms):
         achieved = work / (ms * 1e-3) / 1e12
         peak = FP64_PEAK_TFLOPS
     return dict(kernel=name, bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
-                traffic=None, avg_us=ms * 1e3, work_per_launch=work,
+                traffic=measured_traffic(name), avg_us=ms * 1e3, work_per_launch=work,
                 per_kernel_us={k: round(v * 1e3, 2) for k, v in kernel_ms.items()})
 
 

@@ -418,9 +418,9 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
                             forces ? B::save(c) : nullptr, 0, c->d_ek, true, &rb, nullptr);
     });
+    // timed alone through the stand-alone kernel with the same body
     keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) {
-      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
-                            forces ? B::save(c) : nullptr, 0, c->d_ek, false, &rb, nullptr);
+      launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c));
     });
     rec(c, CPM_KERNEL_FFT_XY_INV, s, [=](hipStream_t s) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
@@ -482,10 +482,8 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, true,
                             nullptr, &pa);
     });
-    keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) {
-      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, false,
-                            nullptr, &pa);
-    });
+    // timed alone through the stand-alone kernel with the same body
+    keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, c->cell, st, fa); });
     // c1 -> Ex (re), Ey (im); c2 -> Ez; field meshes are [frame][3][M]
     T* E = B::E(c);
     const size_t M = c->mi.M;
