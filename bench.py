@@ -162,7 +162,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 866230, "sources_sha256": "8441cb53647d0e70e291389d8276166ada8b6e5f85f51c24054049809d77ccb7"}}
+TRAFFIC = {"site_pairs": {"bytes": 404448, "sources_sha256": "8db19d257e2174c2ed492f636619aa26fc04c39959400242eb6387c4487134b0"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 

@@ -84,6 +84,18 @@ __device__ __forceinline__ int stencil_cell(int c, int s, int n) {
   return (c + s) % n;
 }
 
+// Workgroups of a launch are dispatched to the 8 XCDs in turn (block b to
+// XCD b mod 8).  Mapping dispatch index b of nb blocks to the logical index
+// returned here gives each XCD one contiguous range of logical blocks, so a
+// kernel whose neighbouring logical blocks share data (cell-sorted targets)
+// keeps that data in one XCD's L2.  A bijection on [0, nb) whatever the
+// actual placement.  Worth it only where every target costs about the same:
+// contiguous ranges put unequal targets on unequal XCDs.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <typename T> struct Real2;
 template <> struct Real2<double> { using type = double2; };
 template <> struct Real2<float> { using type = float2; };

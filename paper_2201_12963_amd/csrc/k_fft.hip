@@ -336,10 +336,10 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
     T* qbuf = reinterpret_cast<T*>(smem + (threadIdx.x >> 6) * wave_scratch_bytes<T>());
     const int hb = (int)blockIdx.x - n_z_blocks;
     if (hb < rb.n_blocks) {
-      const int g = hb * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+      const int g = xcd_block(hb, rb.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
       if (g < rb.el.n) real_b_wave(rb.cell, rb.alpha, rb.eta, rb.rc2, rb.el, rb.st, rb.phi_out, g, blockIdx.y, qbuf);
     } else {
-      const int j = (hb - rb.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+      const int j = xcd_block(hb - rb.n_blocks, pa.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
       if (j < pa.st.n) site_pairs_wave(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, j, blockIdx.y, qbuf);
     }
     return;

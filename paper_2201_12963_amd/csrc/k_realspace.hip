@@ -11,7 +11,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, double rc2, ElecSet<T> el,
                                                 SiteSet<T> st, T* __restrict__ phi_out) {
   __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
-  const int g = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+  const int g = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   if (g >= el.n) return;
   real_b_wave(cell, alpha, eta, rc2, el, st, phi_out, g, blockIdx.y,
               reinterpret_cast<T*>(scratch + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
@@ -29,7 +29,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_site_pairs(Cell cell, SiteSet<T> st, T alpha, double rc2,
                                                     double* __restrict__ f_pair, double* __restrict__ u_site) {
   __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
-  const int j = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+  const int j = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   if (j >= st.n) return;
   site_pairs_wave(cell, st, alpha, rc2, f_pair, u_site, j, blockIdx.y,
                   reinterpret_cast<T*>(scratch + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
