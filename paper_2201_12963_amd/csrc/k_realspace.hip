@@ -67,6 +67,10 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   const size_t fo = (size_t)frame * st.n;
   const double xj = st.x[fo + j], yj = st.y[fo + j], zj = st.z[fo + j];
   const double qj = st.q[fo + j];
+  // read now, used at the end: their latency overlaps the work in between
+  const int orig = st.order[fo + j];
+  const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
+  const double fp0 = fp[j], fp1 = fp[st.n + j], fp2 = fp[2 * (size_t)st.n + j];
   int cx, cy, cz;
   const int nst = site_cell(cell, xj, yj, zj, cx, cy, cz);
   int e_lo = 0, e_hi = 0, e_c = 0;
@@ -145,12 +149,12 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   if (lane < n) eval_g1<T, TWO>(Q, lane, fa.alpha, fa.eta, fr, frb);
 
   // ---- reduce and write
-  const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
+  const double fpd[3] = {fp0, fp1, fp2};
   double F[3], FB[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double e_k = (double)wave_sum(ea[d]);
-    const double e_r = (double)wave_sum(fr[d]) + fp[(size_t)d * st.n + j];
+    const double e_r = (double)wave_sum(fr[d]) + fpd[d];
     F[d] = fa.out_scale * qj * (e_k + KE * e_r);
     if (TWO) {
       const double eb_k = (double)wave_sum(eb[d]);
@@ -162,7 +166,6 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   }
   F[2] += qj * fa.field;
   FB[2] += qj * fa.fieldb;
-  const int orig = st.order[fo + j];
   double* fout = fa.f_out + (size_t)frame * fa.f_frame_stride;
   for (int v = lane; v < fa.n_dv; v += WAVE) {
     const double dv = fa.dv ? fa.dv[v] : 0.0;

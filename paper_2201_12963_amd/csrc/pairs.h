@@ -248,6 +248,7 @@ __device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, do
   const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
   const double ex = el.x[g], ey = el.y[g], ez = el.z[g];
   const int c = el.cell[g];
+  const int og = el.orig[g];                   // read now, used at the end
   const int cx = c % cell.nc[0], cy = (c / cell.nc[0]) % cell.nc[1], cz = c / (cell.nc[0] * cell.nc[1]);
   const int nst = stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
   // site ranges of all stencil cells, loaded in parallel (lane t: cell t), merged into runs
@@ -282,7 +283,7 @@ __device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, do
             });
   if (lane < n) acc += g1_potential(Q.x[lane], Q.y[lane], Q.z[lane], Q.a[lane], alpha, eta);
   acc = wave_sum(acc);
-  if (lane == 0) phi_out[(size_t)frame * el.n + el.orig[g]] = (T)KE * acc;
+  if (lane == 0) phi_out[(size_t)frame * el.n + og] = (T)KE * acc;
 }
 
 // ------------------------------------------------------------ site forces
@@ -361,7 +362,7 @@ __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<
   const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
   const double* sx = st.x + fo; const double* sy = st.y + fo; const double* sz = st.z + fo;
   const double* sq = st.q + fo;
-  const double xj = sx[j], yj = sy[j], zj = sz[j];
+  const double xj = sx[j], yj = sy[j], zj = sz[j], qj = sq[j];
   int cx, cy, cz;
   const int nst = site_cell(cell, xj, yj, zj, cx, cy, cz);
   int s_lo = 0, s_hi = 0, s_c = 0;
@@ -403,7 +404,7 @@ __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<
   if (lane == 0) {
     double* o = f_pair + (size_t)frame * 3 * st.n;
     o[j] = e[0]; o[st.n + j] = e[1]; o[2 * st.n + j] = e[2];
-    if (u_site) u_site[fo + j] = 0.5 * KE * (double)sq[j] * us;
+    if (u_site) u_site[fo + j] = 0.5 * KE * qj * us;
   }
 }
 
