@@ -10,6 +10,7 @@ cell (N_e = 1760, N_l = 2560); the finite-field cell (N_e = 880, N_l = 1280),
 the precision form, the batched form and the gradient are reported beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
+    python bench.py --only {precision,batched,gradient}     (one form alone)
 
 Prints one JSON line.
 """
@@ -304,6 +305,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--only", choices=("precision", "batched", "gradient"),
+                    help="run only this form and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this path runs on a single MI355X "
@@ -312,6 +315,11 @@ def main():
 
     import torch
     from workloads import make_workload, random_walk
+
+    if args.only:
+        form = {"precision": precision_form, "batched": batched_form, "gradient": gradient_form}[args.only]
+        print(json.dumps({args.only: form(torch)}), flush=True)
+        return
 
     n_traj = min(max(args.steps, 1), 1000)
     wd = make_workload("paper", "dc")

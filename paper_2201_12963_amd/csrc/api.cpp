@@ -75,7 +75,7 @@ struct cpm_ctx {
   double* d_wrap = nullptr;       // binning scratch: wrapped coordinates [frame][3][n_site]
   double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
   double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
-  double *d_ek = nullptr, *d_ftmp = nullptr, *d_energy_tmp = nullptr, *d_lam = nullptr, *d_scalar = nullptr;
+  double *d_ek = nullptr, *d_ftmp = nullptr, *d_fcomp = nullptr, *d_energy_tmp = nullptr, *d_lam = nullptr, *d_scalar = nullptr;
   double *d_g = nullptr, *d_qa = nullptr, *d_dv = nullptr;
   int cap_dv = 0;
   // k-space field mesh of the electrode charges S c alone (batched dV sweep)
@@ -284,6 +284,7 @@ int alloc_frames(cpm_ctx* c, int nf) {
   if (mixed) TRY(dalloc(c, &c->d_bsplit, (size_t)3 * nf * c->n_pad));
   TRY(dalloc(c, &c->d_usite, (size_t)nf * ns));
   TRY(dalloc(c, &c->d_ftmp, (size_t)nf * 3 * ns));
+  TRY(dalloc(c, &c->d_fcomp, (size_t)nf * 6 * ns));
   TRY(dalloc(c, &c->d_energy_tmp, (size_t)nf * 2));
   if (c->kspace == CPM_KSPACE_PPPM) {
     const size_t M = c->mi.M;
@@ -460,7 +461,10 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
   fa.mi = c->mi;
   fa.f_pair = c->d_fpair;
   PairArgs<T> pa{};
-  pa.n_blocks = (c->n_site + 3) / 4;
+  // one frame: a wavefront per site (short chains, all in flight at once);
+  // many frames: cell tiles
+  pa.tsplit = nf == 1 ? 0 : 1;
+  pa.n_blocks = c->n_site == 0 ? 0 : pa.tsplit > 0 ? c->cell.n_cells * pa.tsplit : (c->n_site + 3) / 4;
   pa.cell = c->cell;
   pa.st = st;
   pa.alpha = fa.alpha;
@@ -478,12 +482,18 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
     rec(c, CPM_KERNEL_FFT_XY_FWD_E, s, [=](hipStream_t s) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
     });
+    // one frame: the site-pair workgroups ride in the z pass (latency);
+    // many frames: a launch of their own, so that the z pass keeps its small
+    // LDS footprint and occupancy (throughput)
+    const bool host_pairs = nf == 1;
     rec(c, CPM_KERNEL_FFT_Z_FIELD, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, true,
-                            nullptr, &pa);
+                            nullptr, host_pairs ? &pa : nullptr);
     });
-    // timed alone through the stand-alone kernel with the same body
-    keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, c->cell, st, fa); });
+    if (host_pairs)   // timed alone through the stand-alone kernel with the same body
+      keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
+    else
+      rec(c, CPM_KERNEL_SITE_PAIRS, s, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
     // c1 -> Ex (re), Ey (im); c2 -> Ez; field meshes are [frame][3][M]
     T* E = B::E(c);
     const size_t M = c->mi.M;
@@ -494,7 +504,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
     fa.Ea_frame_stride = 3 * M;
     fa.Esite = nullptr;
   } else {
-    rec(c, CPM_KERNEL_SITE_PAIRS, s, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, c->cell, st, fa); });
+    rec(c, CPM_KERNEL_SITE_PAIRS, s, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
     SiteSet<double> sd = Bufs<double>::sites(c);
     launch_ewald_rho_all(s, nf, c->nk, c->n_elec, c->d_eph, qa, qa_stride, c->d_rhok, c->d_rhok_all);
     launch_ewald_field(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok_all, c->d_Esite);
@@ -619,13 +629,15 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
     fa.fieldb = (c->geometry == CPM_FINITE_FIELD) ? -1.0 / c->box[2] : 0.0;
     fa.qb = c->d_Sc;
     if (c->kspace == CPM_KSPACE_PPPM) fa.Eb = std::is_same<T, float>::value ? (const T*)c->d_EScf : (const T*)c->d_ESc;
-    fa.f_out = f_out ? f_out : c->d_ftmp;
-    fa.f_frame_stride = f_out ? (size_t)n_dv * 3 * c->n_site : 0;
-    fa.n_dv = f_out ? n_dv : 0;
+    // forces at dV = 0 and per unit dV, then the sweep in a streaming pass
+    fa.f_out = c->d_ftmp;
+    fa.f_comp = f_out ? c->d_fcomp : nullptr;
+    fa.n_dv = 0;
     fa.dv = c->d_dv;
     fa.u_site = c->d_usite;
     const EnergyArgs ea = energy_args(c, n_dv, c->d_dv, 0.0, e_out);
     TRY(enqueue_forces<T>(c, nf, c->d_Q0, n, fa, e_out ? &ea : nullptr));
+    if (f_out) launch_expand_forces(s, nf, c->n_site, n_dv, c->d_dv, c->d_fcomp, f_out);
   }
   return CPM_OK;
 }

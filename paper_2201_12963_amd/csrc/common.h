@@ -48,6 +48,43 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Sums of eight values over the wavefront in 10 exchanges instead of 8 x 6:
+// each exchange step halves the values a lane keeps (it sends the half its
+// partner keeps), down to one, then the last three steps sum that one.
+// Afterwards lane l holds the total of value l >> 3.
+template <typename T>
+__device__ __forceinline__ T wave_sum8(const T (&v)[8]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  T a[4], b[2];
+  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T keep = h32 ? v[i + 4] : v[i], send = h32 ? v[i] : v[i + 4];
+    a[i] = keep + __shfl_xor(send, 32, WAVE);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const T keep = h16 ? a[i + 2] : a[i], send = h16 ? a[i] : a[i + 2];
+    b[i] = keep + __shfl_xor(send, 16, WAVE);
+  }
+  T c = (h8 ? b[1] : b[0]) + __shfl_xor(h8 ? b[0] : b[1], 8, WAVE);
+  c += __shfl_xor(c, 4, WAVE);
+  c += __shfl_xor(c, 2, WAVE);
+  c += __shfl_xor(c, 1, WAVE);
+  return c;
+}
+
+// value of v in lane l (l uniform), for every lane
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // sum over a 256-thread workgroup (red: 4 doubles of LDS); every thread gets the total
 __device__ __forceinline__ double block_sum_d(double v, double* red) {
   v = wave_sum(v);
@@ -166,6 +203,10 @@ struct ForceArgs {
   double fieldb;             // same for the second set (per unit dV)
   // outputs
   double* f_out; size_t f_frame_stride;   // [frame][n_dv][3][n_site] original order
+  // instead of f_out (if non-null): [frame][2][3][n_site] original order,
+  // the force at dV = 0 and its derivative by dV, expanded over the sweep
+  // by launch_expand_forces
+  double* f_comp;
   int n_dv; const double* dv;             // dV values of the sweep (n_dv == 1: dv may be nullptr)
   double* u_site;                          // [frame][n_site] 1/2 Q_j sum Q_j' g0 (sorted order), or nullptr
   // site-site real-space sum of every site, sum_j' Q_j' g0(r) r_vec without
@@ -192,11 +233,14 @@ struct RealBArgs {
   T* phi_out;                  // [frame][n_elec] original order
 };
 
-// site-site forces hosted as extra workgroups of another launch (one
-// wavefront per site, four per workgroup)
+// site-site forces hosted as extra workgroups of another launch: cell tiles
+// (tsplit > 0 workgroups per cell, each a contiguous share of its sites;
+// for many frames) or one wavefront per site (tsplit == 0; for one frame,
+// where the shorter per-wavefront chains win)
 template <typename T>
 struct PairArgs {
-  int n_blocks;                // workgroups per frame, 0: none
+  int n_blocks;                // workgroups per frame (n_cells * tsplit, or ceil(n_site / 4)), 0: none
+  int tsplit;
   Cell cell;
   SiteSet<T> st;
   T alpha;
@@ -337,8 +381,10 @@ template <typename T>
 void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
                      double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out);
 template <typename T>
-void launch_site_pairs_t(hipStream_t s, int n_frames, const Cell& cell, const SiteSet<T>& st,
-                         const ForceArgs<T>& fa);
+void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa);
+// LDS of a site-pair workgroup (tsplit > 0: tile form)
+template <typename T>
+size_t site_pairs_lds(int tsplit);
 // forces: the site-force workgroups; ea (or nullptr): one more workgroup per
 // frame that reduces the energies
 template <typename T>
@@ -408,6 +454,10 @@ void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const d
                     double* Q0, double* q);
 void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
                            const double* Sc, double* q);
+// out[f][v][k] = comp[f][0][k] + dv[v] comp[f][1][k] over the 3 n_site
+// values k of every frame f and dV v
+void launch_expand_forces(hipStream_t s, int n_frames, int n_site, int n_dv, const double* dv, const double* comp,
+                          double* out);
 
 void launch_adjoint_rhs(hipStream_t s, int n, const double* q, const double* t, const double* c, double dv, double* g);
 void launch_sub(hipStream_t s, int n, const double* a, const double* b, double* out);

@@ -20,10 +20,14 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& ea, int frame) {
   }
   for (int j = threadIdx.x; j < ea.n_site; j += blockDim.x) s[8] += ea.u_site[(size_t)frame * ea.n_site + j];
   for (int j = threadIdx.x; j < ea.n_ek; j += blockDim.x) s[9] += ea.ek[(size_t)frame * ea.n_ek + j];
-#pragma unroll
-  for (int t = 0; t < 10; ++t) s[t] = wave_sum(s[t]);
-  if ((threadIdx.x & 63) == 0)
-    for (int t = 0; t < 10; ++t) red[threadIdx.x >> 6][t] = s[t];
+  const double v0[8] = {s[0], s[1], s[2], s[3], s[4], s[5], s[6], s[7]};
+  const double v1[8] = {s[8], s[9], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const double t0 = wave_sum8(v0), t1 = wave_sum8(v1);     // lane 8k: total of value k
+  const int lane = threadIdx.x & 63;
+  if ((lane & 7) == 0) {
+    red[threadIdx.x >> 6][lane >> 3] = t0;
+    if (lane < 16) red[threadIdx.x >> 6][8 + (lane >> 3)] = t1;
+  }
   __syncthreads();
   double S[10];
   for (int t = 0; t < 10; ++t) S[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];

@@ -19,6 +19,7 @@
 #include "common.h"
 #include "bin.h"
 #include "pairs.h"
+#include "tiles.h"
 
 namespace cpm {
 
@@ -339,8 +340,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
       const int g = xcd_block(hb, rb.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
       if (g < rb.el.n) real_b_wave(rb.cell, rb.alpha, rb.eta, rb.rc2, rb.el, rb.st, rb.phi_out, g, blockIdx.y, qbuf);
     } else {
-      const int j = xcd_block(hb - rb.n_blocks, pa.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
-      if (j < pa.st.n) site_pairs_wave(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, j, blockIdx.y, qbuf);
+      site_pairs_block(pa, xcd_block(hb - rb.n_blocks, pa.n_blocks), blockIdx.y, smem);
     }
     return;
   }
@@ -508,7 +508,8 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
   const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
   size_t lds = (3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2);
-  if (r.n_blocks + p.n_blocks > 0) lds = std::max(lds, pair_queue_lds<T>());
+  if (r.n_blocks > 0) lds = std::max(lds, pair_queue_lds<T>());
+  if (p.n_blocks > 0) lds = std::max(lds, p.tsplit > 0 ? TileLds<T, 1, 4, 4>::total : pair_queue_lds<T>());
   dim3 grid(nzb + r.n_blocks + p.n_blocks, n_frames);
   if (grid.x == 0) return;
   hipLaunchKernelGGL((k_fft_z<T, T2>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,

@@ -309,6 +309,20 @@ __global__ __launch_bounds__(256) void k_expand_charges(int n_elec, int n_dv, co
   q[((size_t)f * n_dv + v) * n_elec + i] = Q0[(size_t)f * n_elec + i] + dv[v] * Sc[i];
 }
 
+// out[f][v][k] = comp[f][0][k] + dv[v] comp[f][1][k], k < n3: the forces are
+// affine in dV, so the sweep is written from two vectors per frame, every
+// store a full run of consecutive values
+__global__ __launch_bounds__(256) void k_expand_forces(int n3, int n_dv, const double* __restrict__ dv,
+                                                       const double* __restrict__ comp, double* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (k >= n3) return;
+  const double a = comp[(size_t)f * 2 * n3 + k];
+  const double b = comp[(size_t)f * 2 * n3 + n3 + k];
+  double* o = out + (size_t)f * n_dv * n3 + k;
+  for (int v = 0; v < n_dv; ++v) o[(size_t)v * n3] = a + dv[v] * b;
+}
+
 // ------------------------------------------------------------ adjoint
 
 // g = 2 (q - t) + dv c   (the right-hand side of lambda = S g)
@@ -397,6 +411,12 @@ void launch_rank1(hipStream_t s, int n, double* S, const double* u, const double
 void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const double* b, const double* Sc, double dv,
                     double* Q0, double* q) {
   hipLaunchKernelGGL(k_charges, dim3((n + 3) / 4, n_frames), dim3(256), 0, s, n, S, b, Sc, dv, Q0, q);
+}
+void launch_expand_forces(hipStream_t s, int n_frames, int n_site, int n_dv, const double* dv, const double* comp,
+                          double* out) {
+  const int n3 = 3 * n_site;
+  if (n3 == 0 || n_frames == 0) return;
+  hipLaunchKernelGGL(k_expand_forces, dim3((n3 + 255) / 256, n_frames), dim3(256), 0, s, n3, n_dv, dv, comp, out);
 }
 void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
                            const double* Sc, double* q) {

@@ -3,6 +3,7 @@
 // wavefront per site) and the rest of the force on every site once the
 // electrode charges are known; the pair machinery is in pairs.h.
 #include "pairs.h"
+#include "tiles.h"
 #include "energy.h"
 
 namespace cpm {
@@ -26,14 +27,13 @@ void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_site_pairs(Cell cell, SiteSet<T> st, T alpha, double rc2,
-                                                    double* __restrict__ f_pair, double* __restrict__ u_site) {
-  __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
-  const int j = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
-  if (j >= st.n) return;
-  site_pairs_wave(cell, st, alpha, rc2, f_pair, u_site, j, blockIdx.y,
-                  reinterpret_cast<T*>(scratch + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
+__global__ __launch_bounds__(TILE_THREADS) void k_site_pairs(PairArgs<T> pa) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  site_pairs_block(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }
+
+template <typename T>
+size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? TileLds<T, 1, 4, 4>::total : 4 * wave_scratch_bytes<T>(); }
 
 
 // The rest of the force on every site, once the electrode charges are known:
@@ -47,8 +47,18 @@ __global__ __launch_bounds__(256) void k_site_pairs(Cell cell, SiteSet<T> st, T 
 template <typename T, bool TWO>
 __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, SiteSet<T> st,
                                                      ForceArgs<T> fa, int n_force_blocks, EnergyArgs en) {
-  if ((int)blockIdx.x >= n_force_blocks) {
-    energy_block(en, blockIdx.y);
+  int bx = blockIdx.x, frame = blockIdx.y;
+  if (gridDim.y > 1) {
+    // many frames: each XCD takes a contiguous range of whole frames, so a
+    // frame's field meshes are fetched into one L2 and its output lines are
+    // filled there (one frame keeps the plain order: its targets differ in
+    // cost, and contiguous ranges would load the XCDs unevenly)
+    const int L = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    frame = L / gridDim.x;
+    bx = L - frame * gridDim.x;
+  }
+  if (bx >= n_force_blocks) {
+    energy_block(en, frame);
     return;
   }
   __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
@@ -56,8 +66,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   __shared__ int fsp[4][3];
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
-  const int j = blockIdx.x * (blockDim.x / WAVE) + wv;
-  const int frame = blockIdx.y;
+  const int j = bx * (blockDim.x / WAVE) + wv;
   if (j >= st.n) return;
   T* ws = reinterpret_cast<T*>(scratch + wv * wave_scratch_bytes<T>());
   WaveQueue<T> Q;
@@ -151,21 +160,30 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   // ---- reduce and write
   const double fpd[3] = {fp0, fp1, fp2};
   double F[3], FB[3];
+  const T va[8] = {ea[0], ea[1], ea[2], fr[0], fr[1], fr[2], (T)0, (T)0};
+  const T sa = wave_sum8(va);                 // lane 8k: total of va[k]
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double e_k = (double)wave_sum(ea[d]);
-    const double e_r = (double)wave_sum(fr[d]) + fpd[d];
-    F[d] = fa.out_scale * qj * (e_k + KE * e_r);
-    if (TWO) {
-      const double eb_k = (double)wave_sum(eb[d]);
-      const double eb_r = (double)wave_sum(frb[d]);
-      FB[d] = fa.out_scale * qj * (eb_k + KE * eb_r);
-    } else {
-      FB[d] = 0.0;
-    }
+  for (int d = 0; d < 3; ++d)
+    F[d] = fa.out_scale * qj * ((double)read_lane(sa, 8 * d) + KE * ((double)read_lane(sa, 24 + 8 * d) + fpd[d]));
+  if (TWO) {
+    const T vb[8] = {eb[0], eb[1], eb[2], frb[0], frb[1], frb[2], (T)0, (T)0};
+    const T sb = wave_sum8(vb);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      FB[d] = fa.out_scale * qj * ((double)read_lane(sb, 8 * d) + KE * (double)read_lane(sb, 24 + 8 * d));
+  } else {
+    FB[0] = FB[1] = FB[2] = 0.0;
   }
   F[2] += qj * fa.field;
   FB[2] += qj * fa.fieldb;
+  if (fa.f_comp) {
+    if (lane < 6) {
+      const double val = lane == 0 ? F[0] : lane == 1 ? F[1] : lane == 2 ? F[2]
+                       : lane == 3 ? FB[0] : lane == 4 ? FB[1] : FB[2];
+      fa.f_comp[((size_t)frame * 6 + lane) * st.n + orig] = val;
+    }
+    return;
+  }
   double* fout = fa.f_out + (size_t)frame * fa.f_frame_stride;
   for (int v = lane; v < fa.n_dv; v += WAVE) {
     const double dv = fa.dv ? fa.dv[v] : 0.0;
@@ -177,10 +195,10 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
 }
 
 template <typename T>
-void launch_site_pairs_t(hipStream_t s, int n_frames, const Cell& cell, const SiteSet<T>& st,
-                         const ForceArgs<T>& fa) {
-  dim3 grid((st.n + 3) / 4, n_frames);
-  hipLaunchKernelGGL(k_site_pairs<T>, grid, dim3(256), 0, s, cell, st, fa.alpha, fa.rc2, fa.f_pair, fa.u_site);
+void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
+  if (pa.n_blocks == 0 || n_frames == 0) return;
+  hipLaunchKernelGGL(k_site_pairs<T>, dim3(pa.n_blocks, n_frames), dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit), s,
+                     pa);
 }
 
 template <typename T>
@@ -201,10 +219,10 @@ template void launch_real_b_t<double>(hipStream_t, int, const Cell&, double, dou
                                       const ElecSet<double>&, const SiteSet<double>&, double*);
 template void launch_real_b_t<float>(hipStream_t, int, const Cell&, double, double, double,
                                      const ElecSet<float>&, const SiteSet<float>&, float*);
-template void launch_site_pairs_t<double>(hipStream_t, int, const Cell&, const SiteSet<double>&,
-                                          const ForceArgs<double>&);
-template void launch_site_pairs_t<float>(hipStream_t, int, const Cell&, const SiteSet<float>&,
-                                         const ForceArgs<float>&);
+template void launch_site_pairs_t<double>(hipStream_t, int, const PairArgs<double>&);
+template void launch_site_pairs_t<float>(hipStream_t, int, const PairArgs<float>&);
+template size_t site_pairs_lds<double>(int);
+template size_t site_pairs_lds<float>(int);
 template void launch_site_forces_t<double>(hipStream_t, int, const Cell&, const ElecSet<double>&,
                                            const SiteSet<double>&, const ForceArgs<double>&, bool,
                                            const EnergyArgs*);

@@ -397,10 +397,12 @@ __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<
                   }
             });
   if (lane < n) eval_g0(Q, lane, alpha, fr, u);
+  const T v8[8] = {fr[0], fr[1], fr[2], u, (T)0, (T)0, (T)0, (T)0};
+  const T s8 = wave_sum8(v8);                 // lane 8k: total of v8[k]
   double e[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) e[d] = (double)wave_sum(fr[d]);
-  const double us = (double)wave_sum(u);
+  for (int d = 0; d < 3; ++d) e[d] = (double)read_lane(s8, 8 * d);
+  const double us = (double)read_lane(s8, 24);
   if (lane == 0) {
     double* o = f_pair + (size_t)frame * 3 * st.n;
     o[j] = e[0]; o[st.n + j] = e[1]; o[2 * st.n + j] = e[2];
