@@ -176,6 +176,35 @@ int cell_coord_host(double x, double L, int n) {
 
 double wrap_host(double x, double L) { return x - L * std::floor(x / L); }
 
+// Stencil groups of every cell of the grid: the distinct neighbour cells
+// (offsets -1, 0, 1 per axis, fewer where the axis has under 3 cells),
+// sorted and joined into runs of consecutive cell indices [lo, hi).
+void stencil_groups(const Cell& cl, std::vector<int>& ptr, std::vector<int>& lo, std::vector<int>& hi) {
+  ptr.assign(1, 0);
+  lo.clear();
+  hi.clear();
+  auto count = [](int n) { return n >= 3 ? 3 : n; };
+  auto nb = [](int c, int s, int n) {
+    if (n >= 3) { int v = c + s - 1; return v < 0 ? v + n : (v >= n ? v - n : v); }
+    return (c + s) % n;
+  };
+  for (int c = 0; c < cl.n_cells; ++c) {
+    const int cx = c % cl.nc[0], cy = (c / cl.nc[0]) % cl.nc[1], cz = c / (cl.nc[0] * cl.nc[1]);
+    std::vector<int> cells;
+    for (int a = 0; a < count(cl.nc[2]); ++a)
+      for (int b = 0; b < count(cl.nc[1]); ++b)
+        for (int d = 0; d < count(cl.nc[0]); ++d)
+          cells.push_back((nb(cz, a, cl.nc[2]) * cl.nc[1] + nb(cy, b, cl.nc[1])) * cl.nc[0] + nb(cx, d, cl.nc[0]));
+    std::sort(cells.begin(), cells.end());
+    cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+    for (size_t k = 0; k < cells.size(); ++k) {
+      if (k == 0 || cells[k] != cells[k - 1] + 1) { lo.push_back(cells[k]); hi.push_back(cells[k] + 1); }
+      else hi.back() = cells[k] + 1;
+    }
+    ptr.push_back((int)lo.size());
+  }
+}
+
 // half-space k-vectors with 0 < |k| <= kcut: (n1 > 0) or (n1 == 0, n2 > 0) or (n1 == n2 == 0, n3 > 0)
 void half_kvectors(const double* box, double kcut, std::vector<double>& kx, std::vector<double>& ky,
                    std::vector<double>& kz) {
@@ -737,6 +766,13 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     cl.img[k] = (int)std::floor(c->rcut / c->box[k] + 0.5);
     cl.n_cells *= cl.nc[k];
   }
+  std::vector<int> gptr, glo, ghi;
+  stencil_groups(cl, gptr, glo, ghi);
+  {
+    int *dp, *dl, *dh;
+    if ((r = upload(c, &dp, gptr)) || (r = upload(c, &dl, glo)) || (r = upload(c, &dh, ghi))) return bad(r);
+    cl.grp_ptr = dp; cl.grp_lo = dl; cl.grp_hi = dh;
+  }
   c->cell_b = cl;
   for (int k = 0; k < 3; ++k) c->cell_b.img[k] = (int)std::floor(c->rcut_b / c->box[k] + 0.5);
   if (bin_lds_bytes(ns, cl.n_cells) > 150 * 1024) {
@@ -776,13 +812,27 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       (r = upload(c, &c->d_c, cc)) || (r = upload(c, &c->d_d, dd)) || (r = upload(c, &c->d_ze, ze)) ||
       (r = upload(c, &c->d_e1, e1)) || (r = upload(c, &c->d_site_q, c->hq)))
     return bad(r);
+  // electrode atoms in reach of every cell: the stencil groups' ranges of
+  // the sorted atoms, empty ones dropped and adjacent ones joined
+  std::vector<int> rptr(1, 0), rlo, rhi;
+  for (int cc2 = 0; cc2 < cl.n_cells; ++cc2) {
+    const size_t first = rlo.size();
+    for (int g = gptr[cc2]; g < gptr[cc2 + 1]; ++g) {
+      const int lo = ecs[glo[g]], hi = ecs[ghi[g]];
+      if (hi <= lo) continue;
+      if (rlo.size() > first && rhi.back() == lo) rhi.back() = hi;
+      else { rlo.push_back(lo); rhi.push_back(hi); }
+    }
+    rptr.push_back((int)rlo.size());
+  }
   {
-    double *x, *y, *z; int *o, *ce, *cs;
+    double *x, *y, *z; int *o, *ce, *cs, *rp, *rl, *rh;
     if ((r = upload(c, &x, sxe)) || (r = upload(c, &y, sye)) || (r = upload(c, &z, sze)) ||
-        (r = upload(c, &o, eorder)) || (r = upload(c, &ce, ecell_sorted)) || (r = upload(c, &cs, ecs)))
+        (r = upload(c, &o, eorder)) || (r = upload(c, &ce, ecell_sorted)) || (r = upload(c, &cs, ecs)) ||
+        (r = upload(c, &rp, rptr)) || (r = upload(c, &rl, rlo)) || (r = upload(c, &rh, rhi)))
       return bad(r);
-    c->el = ElecSet<double>{x, y, z, o, ce, cs, ne};
-    c->elf = ElecSet<float>{x, y, z, o, ce, cs, ne};
+    c->el = ElecSet<double>{x, y, z, o, ce, cs, ne, rp, rl, rh};
+    c->elf = ElecSet<float>{x, y, z, o, ce, cs, ne, rp, rl, rh};
   }
   if ((r = dalloc(c, &c->d_A, (size_t)ne * ne)) || (r = dalloc(c, &c->d_S, (size_t)ne * ne)) ||
       (r = dalloc(c, &c->d_Sc, ne)) || (r = dalloc(c, &c->d_status, 4)) || (r = dalloc(c, &c->d_scalar, 8)))

@@ -21,6 +21,14 @@ struct Cell {          // periodic orthorhombic cell and its cell-list grid
   int nc[3];           // cells per axis, n_d = max(1, floor(L_d / rcut))
   int img[3];          // extra images per axis: floor(rcut/L + 1/2)
   int n_cells;
+  // stencil of every cell (device tables, fixed by the grid): the distinct
+  // neighbour cells sorted and joined into groups of consecutive cell
+  // indices [grp_lo, grp_hi); groups grp_ptr[c] .. grp_ptr[c+1]-1 (at most
+  // 27) belong to cell c.  A group's members are one contiguous index range
+  // [cs[grp_lo], cs[grp_hi]) of any cell-sorted array with cell_start cs.
+  const int* grp_ptr;
+  const int* grp_lo;
+  const int* grp_hi;
 };
 
 struct FFTPlan1D {     // mixed-radix Stockham plan for one axis
@@ -181,6 +189,9 @@ struct ElecSet {       // cell-sorted electrode atoms (static), FP64 positions
   const double* x; const double* y; const double* z;
   const int* orig; const int* cell; const int* cell_start;
   int n;
+  // electrode atoms in reach of every cell: index runs [run_lo, run_hi) of
+  // the sorted atoms, runs run_ptr[c] .. run_ptr[c+1]-1 (non-empty only)
+  const int* run_ptr; const int* run_lo; const int* run_hi;
 };
 
 template <typename T>

@@ -80,14 +80,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   const int orig = st.order[fo + j];
   const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
   const double fp0 = fp[j], fp1 = fp[st.n + j], fp2 = fp[2 * (size_t)st.n + j];
-  int cx, cy, cz;
-  const int nst = site_cell(cell, xj, yj, zj, cx, cy, cz);
-  int e_lo = 0, e_hi = 0, e_c = 0;
-  if (lane < nst) {
-    e_c = stencil_linear(cell, cx, cy, cz, lane);
-    e_lo = el.cell_start[e_c];
-    e_hi = el.cell_start[e_c + 1];
-  }
+  const int cj = site_cell(cell, xj, yj, zj);
 
   // ---- k-space field at the site
   T ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0};
@@ -108,8 +101,14 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
     __builtin_amdgcn_wave_barrier();
     const int fx = fsp[wv][0], fy = fsp[wv][1], fz = fsp[wv][2];
     const T* Ef = fa.Ea + (size_t)frame * fa.Ea_frame_stride;
+    // point t = (tz P + ty) P + tx: quotients through a float reciprocal,
+    // exact for t < 7^3 (the fractions stay >= 1/98 away from integers)
+    const float invP = 1.0f / (float)P, invP2 = 1.0f / (float)(P * P);
     for (int t = lane; t < P * P * P; t += WAVE) {
-      const int tx = t % P, ty = (t / P) % P, tz = t / (P * P);
+      const int tz = (int)(((float)t + 0.5f) * invP2);
+      const int rz = t - tz * P * P;
+      const int ty = (int)(((float)rz + 0.5f) * invP);
+      const int tx = rz - ty * P;
       int ix = fx + tx; ix -= (ix >= Kx) ? Kx : 0;
       int iy = fy + ty; iy -= (iy >= Ky) ? Ky : 0;
       int iz = fz + tz; iz -= (iz >= Kz) ? Kz : 0;
@@ -128,7 +127,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   T fr[3] = {0, 0, 0};
   T frb[3] = {0, 0, 0};
   const double* qa = fa.qa + (size_t)frame * fa.qa_frame_stride;
-  const int nruns = merge_runs(e_lo, e_hi, e_c, nst, rlo, rhi);
+  const int nruns = elec_runs(el, cj, rlo, rhi);
   int n = 0;
   walk_runs(rlo, rhi, nruns,
             [&](int k, bool v) {

@@ -91,10 +91,10 @@ __device__ __forceinline__ int queue_pop(WaveQueue<T>& q, int n) {
 // ------------------------------------------------- candidate walking
 //
 // Each wavefront keeps, next to its queue, a list of at most 32 runs of
-// partner indices.  The stencil cells' ranges are ordered by cell index (so
-// by position in the cell-sorted arrays) and adjacent ranges are joined, so
-// that the partners are walked in full chunks of 64; the partner data of the
-// next chunk is loaded while the current one is tested and queued.
+// partner indices: the stencil's cells grouped into runs of consecutive cell
+// indices (a table fixed by the grid), so that the partners are walked in
+// full chunks of 64; the partner data of the next chunk is loaded while the
+// current one is tested and queued.
 
 // LDS of one wavefront: its queue (5 CAP values of T) and the runs (2 x 32 ints)
 template <typename T>
@@ -104,29 +104,40 @@ static_assert(pair_queue_lds<double>() == 4 * wave_scratch_bytes<double>(),
 static_assert(pair_queue_lds<float>() == 4 * wave_scratch_bytes<float>(),
               "LDS reserved for hosted pair workgroups must hold four wavefront scratch areas");
 
-// Lanes t < nst hold the range [lo, hi) of stencil cell ci (distinct cells).
-// Writes the merged runs to rlo/rhi and returns their number.
-__device__ __forceinline__ int merge_runs(int lo, int hi, int ci, int nst, int* rlo, int* rhi) {
+// Runs of the stencil of cell c in a cell-sorted array with cell_start cs
+// (one per stencil group, in increasing index order): lanes below the
+// returned count write [rlo, rhi).
+__device__ __forceinline__ int stencil_runs(const Cell& cell, int c, const int* cs, int* rlo, int* rhi) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const bool act = lane < nst;
-  int r = 0;
-  for (int u = 0; u < nst; ++u) {
-    const int cu = __shfl(ci, u, WAVE);
-    r += (act && cu < ci) ? 1 : 0;
+  const int g0 = cell.grp_ptr[c], ng = cell.grp_ptr[c + 1] - g0;
+  if (lane < ng) {
+    rlo[lane] = cs[cell.grp_lo[g0 + lane]];
+    rhi[lane] = cs[cell.grp_hi[g0 + lane]];
   }
-  if (act) { rlo[r] = lo; rhi[r] = hi; }
   __builtin_amdgcn_wave_barrier();
-  const int l2 = act ? rlo[lane] : 0, h2 = act ? rhi[lane] : 0;
+  return ng;
+}
+
+// Cell of a wrapped position (the binning's arithmetic on the wrapped
+// coordinate; where the two could differ in the last bit the position lies
+// on a cell face, and the stencils of both cells hold every partner within
+// the cutoff, cells being at least rcut wide)
+__device__ __forceinline__ int site_cell(const Cell& cell, double x, double y, double z) {
+  return (cell_coord(z, cell.L[2], cell.nc[2]) * cell.nc[1] + cell_coord(y, cell.L[1], cell.nc[1])) * cell.nc[0] +
+         cell_coord(x, cell.L[0], cell.nc[0]);
+}
+
+// Runs of the electrode atoms in reach of cell c (a fixed table)
+template <typename T>
+__device__ __forceinline__ int elec_runs(const ElecSet<T>& el, int c, int* rlo, int* rhi) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int r0 = el.run_ptr[c], nr = el.run_ptr[c + 1] - r0;
+  if (lane < nr) {
+    rlo[lane] = el.run_lo[r0 + lane];
+    rhi[lane] = el.run_hi[r0 + lane];
+  }
   __builtin_amdgcn_wave_barrier();
-  const int hprev = __shfl_up(h2, 1, WAVE);
-  const bool start = act && (lane == 0 || l2 != hprev);
-  const unsigned long long sm = __ballot(start);
-  const int run = __popcll(sm & ((2ull << lane) - 1ull)) - 1;      // run holding this lane's range
-  const bool last = act && (lane + 1 == nst || ((sm >> (lane + 1)) & 1ull));
-  if (start) rlo[run] = l2;
-  if (last) rhi[run] = h2;
-  __builtin_amdgcn_wave_barrier();
-  return __popcll(sm);
+  return nr;
 }
 
 // Walks the partners listed by the runs 64 at a time: load(k, valid)
@@ -218,18 +229,6 @@ __device__ __forceinline__ T g1_potential(T dx, T dy, T dz, T q, T alpha, T eta)
   return q * e / r;
 }
 
-// Stencil cell number s of cell (cx, cy, cz): s enumerates the deduplicated
-// neighbour offsets (z slowest).
-__device__ __forceinline__ int stencil_linear(const Cell& cell, int cx, int cy, int cz, int s) {
-  const int nsx = stencil_count(cell.nc[0]), nsy = stencil_count(cell.nc[1]);
-  const int d = s % nsx, b = (s / nsx) % nsy, a = s / (nsx * nsy);
-  const int xc = stencil_cell(cx, d, cell.nc[0]);
-  const int yc = stencil_cell(cy, b, cell.nc[1]);
-  const int zc = stencil_cell(cz, a, cell.nc[2]);
-  return (zc * cell.nc[1] + yc) * cell.nc[0] + xc;
-}
-
-
 // Real-space electrolyte potential at electrode atom g of a frame, one
 // wavefront: k_e sum_j Q_j g1(r) over the sites of the stencil cells.
 // scratch: this wavefront's LDS (wave_scratch_bytes<T>()).
@@ -249,16 +248,7 @@ __device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, do
   const double ex = el.x[g], ey = el.y[g], ez = el.z[g];
   const int c = el.cell[g];
   const int og = el.orig[g];                   // read now, used at the end
-  const int cx = c % cell.nc[0], cy = (c / cell.nc[0]) % cell.nc[1], cz = c / (cell.nc[0] * cell.nc[1]);
-  const int nst = stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
-  // site ranges of all stencil cells, loaded in parallel (lane t: cell t), merged into runs
-  int my_lo = 0, my_hi = 0, my_c = 0;
-  if (lane < nst) {
-    my_c = stencil_linear(cell, cx, cy, cz, lane);
-    my_lo = cs[my_c];
-    my_hi = cs[my_c + 1];
-  }
-  const int nruns = merge_runs(my_lo, my_hi, my_c, nst, rlo, rhi);
+  const int nruns = stencil_runs(cell, c, cs, rlo, rhi);
   T acc = 0;
   int n = 0;
   walk_runs(rlo, rhi, nruns,
@@ -337,14 +327,6 @@ __device__ __forceinline__ void eval_g1(const WaveQueue<T>& Q, int lane, T alpha
   if (TWO) { const T wb = Q.b[lane] * g; frb[0] += wb * qx; frb[1] += wb * qy; frb[2] += wb * qz; }
 }
 
-// cell of a site and the number of stencil cells
-__device__ __forceinline__ int site_cell(const Cell& cell, double x, double y, double z, int& cx, int& cy, int& cz) {
-  cx = cell_coord(x, cell.L[0], cell.nc[0]);
-  cy = cell_coord(y, cell.L[1], cell.nc[1]);
-  cz = cell_coord(z, cell.L[2], cell.nc[2]);
-  return stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
-}
-
 // Site-site part of the force on site j of a frame, one wavefront (it does
 // not depend on the electrode charges): f_pair gets sum_j' Q_j' g0(r) r_vec
 // (without k_e and Q_j), u_site the pair energy
@@ -363,15 +345,7 @@ __device__ __forceinline__ void site_pairs_wave(const Cell& cell, const SiteSet<
   const double* sx = st.x + fo; const double* sy = st.y + fo; const double* sz = st.z + fo;
   const double* sq = st.q + fo;
   const double xj = sx[j], yj = sy[j], zj = sz[j], qj = sq[j];
-  int cx, cy, cz;
-  const int nst = site_cell(cell, xj, yj, zj, cx, cy, cz);
-  int s_lo = 0, s_hi = 0, s_c = 0;
-  if (lane < nst) {
-    s_c = stencil_linear(cell, cx, cy, cz, lane);
-    s_lo = cs[s_c];
-    s_hi = cs[s_c + 1];
-  }
-  const int nruns = merge_runs(s_lo, s_hi, s_c, nst, rlo, rhi);
+  const int nruns = stencil_runs(cell, site_cell(cell, xj, yj, zj), cs, rlo, rhi);
   T fr[3] = {0, 0, 0};
   T u = 0;
   int n = 0;

@@ -2,8 +2,9 @@
 // 256 threads takes the targets of one cell (a chunk of at most TILE_TGT of
 // them) against every candidate of the cell's stencil.
 //
-//   * the stencil's candidates are index runs of a cell-sorted array (merged
-//     as in the wavefront walker); they are staged in LDS, TILE_CAND at a time;
+//   * the stencil's candidates are index runs of a cell-sorted array (one per
+//     stencil group, as in the wavefront walker), staged in LDS, TILE_CAND at
+//     a time;
 //   * thread (ti, sl) keeps target ti of the chunk in registers and tests
 //     candidates sl, sl + nsl, ... (nsl = 256 / chunk size): the lanes of a
 //     wavefront read few distinct candidates, which LDS broadcasts;
@@ -32,20 +33,11 @@ struct TileRuns {
   int n, total;
 };
 
-// Wavefront 0 of the workgroup: runs of the stencil cells of cell c in the
-// cell_start array cs.
+// Wavefront 0 of the workgroup: runs of the stencil of cell c in the
+// cell_start array cs, with offsets and total.
 __device__ __forceinline__ void tile_runs(const Cell& cell, int c, const int* cs, TileRuns* R) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int nx = cell.nc[0], ny = cell.nc[1];
-  const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
-  const int nst = stencil_count(cell.nc[0]) * stencil_count(cell.nc[1]) * stencil_count(cell.nc[2]);
-  int lo = 0, hi = 0, ci = 0;
-  if (lane < nst) {
-    ci = stencil_linear(cell, cx, cy, cz, lane);
-    lo = cs[ci];
-    hi = cs[ci + 1];
-  }
-  const int nr = merge_runs(lo, hi, ci, nst, R->lo, R->hi);
+  const int nr = stencil_runs(cell, c, cs, R->lo, R->hi);
   const int len = lane < nr ? R->hi[lane] - R->lo[lane] : 0;
   int incl = len;
   for (int o = 1; o < 32; o <<= 1) {
