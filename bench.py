@@ -91,7 +91,6 @@ def make_ctx(torch, w, precision=0):
 
 def gpu_steps(torch, w, traj, steps, warmup, precision=0, profile_kernels=False):
     """Time `steps` steps of the trajectory (inputs resident on the GPU)."""
-    from paper_2201_12963_amd.binding import KERNELS
     ctx, stream = make_ctx(torch, w, precision)
     frames = torch.tensor(traj, dtype=torch.float64, device="cuda")
     xyz = torch.empty((3, w.n_site), dtype=torch.float64, device="cuda")
@@ -131,24 +130,45 @@ def gpu_steps(torch, w, traj, steps, warmup, precision=0, profile_kernels=False)
             torch.mul(src, 1.0, out=dst)          # the same bytes through an elementwise kernel
             torch.cuda.synchronize()
             del src, dst
-        # per-kernel average duration: replay the last launch of each kernel,
-        # bracketed by events on the context's stream
-        times = {}
-        for kid, name in enumerate(KERNELS):
-            try:
-                with torch.cuda.stream(stream):
-                    ctx.replay_kernel(kid, 5)
-                    a = torch.cuda.Event(enable_timing=True)
-                    b = torch.cuda.Event(enable_timing=True)
-                    a.record(stream)
-                    ctx.replay_kernel(kid, REPLAYS)
-                    b.record(stream)
-                stream.synchronize()
-                times[name] = a.elapsed_time(b) / REPLAYS
-            except Exception:
-                continue
-        out["kernel_ms"] = times
+        out["kernel_ms"] = kernel_times(torch, ctx, stream, REPLAYS)
     ctx.close()
+    return out
+
+
+def kernel_times(torch, ctx, stream, reps, warm=5):
+    """Average duration (ms) of the last launch of every step kernel: each is
+    replayed `reps` times, bracketed by events on the context's stream."""
+    from paper_2201_12963_amd.binding import KERNELS
+    times = {}
+    for kid, name in enumerate(KERNELS):
+        try:
+            with torch.cuda.stream(stream):
+                ctx.replay_kernel(kid, warm)
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                ctx.replay_kernel(kid, reps)
+                b.record(stream)
+            stream.synchronize()
+            times[name] = a.elapsed_time(b) / reps
+        except Exception:
+            continue
+    return times
+
+
+def per_kernel_roofline(w, kernel_ms, n_frames=1):
+    """Achieved rate and roofline fraction of every timed kernel (algorithmic
+    work of its own body x n_frames over its average duration)."""
+    out = {}
+    for name, ms in kernel_ms.items():
+        bound, work, unit = kernel_work(w, name)
+        work *= n_frames
+        if bound == "hbm":
+            achieved, peak = work / (ms * 1e-3) / 1e9, HBM_PEAK_GBS
+        else:
+            achieved, peak = work / (ms * 1e-3) / 1e12, FP64_PEAK_TFLOPS
+        out[name] = dict(us=round(ms * 1e3, 2), bound=bound, achieved=round(achieved, 4), unit=unit,
+                         frac=round(achieved / peak, 5))
     return out
 
 
@@ -164,7 +184,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
 TRAFFIC = {"site_pairs": {"bytes": 404448, "sources_sha256": "8db19d257e2174c2ed492f636619aa26fc04c39959400242eb6387c4487134b0"}}
-TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
+TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
 def sources_sha256():
@@ -197,7 +217,7 @@ def roofline(w, kernel_ms):
         peak = FP64_PEAK_TFLOPS
     return dict(kernel=name, bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
                 traffic=measured_traffic(name), avg_us=ms * 1e3, work_per_launch=work,
-                per_kernel_us={k: round(v * 1e3, 2) for k, v in kernel_ms.items()})
+                per_kernel=per_kernel_roofline(w, kernel_ms))
 
 
 def cpu_baseline(w, traj, budget_s=20.0):
@@ -264,8 +284,14 @@ def batched_form(torch, n_frames=4096, n_dv=32, reps=3):
             b.record(stream)
         stream.synchronize()
         ms = a.elapsed_time(b) / reps
-        out[label] = dict(frames_per_s=n_frames * n_dv / (ms * 1e-3), ms_per_batch=ms)
+        from paper_2201_12963_amd.binding import BUF_BATCH_CHUNK
+        out[label] = dict(frames_per_s=n_frames * n_dv / (ms * 1e-3), ms_per_batch=ms,
+                          frames_per_launch=int(ctx.get_buffer(BUF_BATCH_CHUNK)[0]))
         out[label + "_q"] = q[:, 7].cpu().numpy()
+        # every kernel of the batch timed alone (the last launch of each, over
+        # frames_per_launch frames)
+        out[label + "_kernels"] = per_kernel_roofline(w, kernel_times(torch, ctx, stream, 3, warm=1),
+                                                      out[label]["frames_per_launch"] or n_frames)
         ctx.close()
         del q, f, e
         torch.cuda.empty_cache()
@@ -274,7 +300,10 @@ def batched_form(torch, n_frames=4096, n_dv=32, reps=3):
                          "finite-field paper cell; a unit is one (frame, dV) pair with q, F and U",
                 fp64_frames_per_s=out["fp64"]["frames_per_s"], fp64_ms_per_batch=out["fp64"]["ms_per_batch"],
                 mixed_frames_per_s=out["mixed"]["frames_per_s"], mixed_ms_per_batch=out["mixed"]["ms_per_batch"],
-                mixed_vs_fp64_q_max_err_e=dq)
+                mixed_vs_fp64_q_max_err_e=dq,
+                frames_per_launch={"fp64": out["fp64"]["frames_per_launch"], "mixed": out["mixed"]["frames_per_launch"]},
+                fp64_per_kernel=out["fp64_kernels"],
+                mixed_per_kernel=out["mixed_kernels"])
 
 
 def gradient_form(torch, reps=50):

@@ -129,7 +129,11 @@ int cpm_solve(cpm_ctx* ctx, const double* site_xyz, double dv,
  *   energy_out device [n_frames][n_dv][2] or NULL
  * The charges of all frames come from one GEMM Q = S B; q and the forces
  * are affine in dV, so each frame is solved once and the dV sweep is a
- * rank-one update.  CPM_ENOMEM if the scratch for n_frames does not fit. */
+ * rank-one update.  Frames go through in launches of up to 4096: the first
+ * call with at least 128 frames times launches of 64, 128, ... frames on its
+ * own first frames and keeps the fastest size for the context (it
+ * synchronises the stream once; setting CPM_BATCH_CHUNK in the environment
+ * fixes the size and skips this).  CPM_ENOMEM if the scratch does not fit. */
 int cpm_solve_batch(cpm_ctx* ctx, int n_frames, const double* site_xyz,
                     int n_dv, const double* dv_host,
                     double* q_out, double* f_out, double* energy_out);
@@ -161,10 +165,12 @@ int cpm_set_matrix(cpm_ctx* ctx, const double* host_S);
  *   CPM_BUF_RHO_MESH  double [Kz][Ky][Kx] electrolyte charge mesh
  *   CPM_BUF_PHI_MESH  double [Kz][Ky][Kx] electrolyte potential mesh (V)
  *   CPM_BUF_FIELD_MESH double [3][Kz][Ky][Kx] field of all charges (V/nm)
- *   CPM_BUF_NCELL     int32 [3]  cells per axis */
+ *   CPM_BUF_NCELL     int32 [3]  cells per axis
+ *   CPM_BUF_BATCH_CHUNK int32 [1] frames per launch chosen for cpm_solve_batch (0: not yet) */
 enum {
   CPM_BUF_CELL_START = 0, CPM_BUF_SITE_ORDER = 1, CPM_BUF_PHI_REAL = 2, CPM_BUF_B = 3,
-  CPM_BUF_RHO_MESH = 4, CPM_BUF_PHI_MESH = 5, CPM_BUF_FIELD_MESH = 6, CPM_BUF_NCELL = 7
+  CPM_BUF_RHO_MESH = 4, CPM_BUF_PHI_MESH = 5, CPM_BUF_FIELD_MESH = 6, CPM_BUF_NCELL = 7,
+  CPM_BUF_BATCH_CHUNK = 8
 };
 long long cpm_get_buffer(cpm_ctx* ctx, int which, void* host_out);
 

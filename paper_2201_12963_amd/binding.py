@@ -22,7 +22,8 @@ FINITE_FIELD, DOUBLED_CELL = 0, 1
 KSPACE_EWALD, KSPACE_PPPM = 0, 1
 FP64, MIXED = 0, 1
 FLAG_GRAPH = 1
-BUF_CELL_START, BUF_SITE_ORDER, BUF_PHI_REAL, BUF_B, BUF_RHO_MESH, BUF_PHI_MESH, BUF_FIELD_MESH, BUF_NCELL = range(8)
+(BUF_CELL_START, BUF_SITE_ORDER, BUF_PHI_REAL, BUF_B, BUF_RHO_MESH, BUF_PHI_MESH, BUF_FIELD_MESH, BUF_NCELL,
+ BUF_BATCH_CHUNK) = range(9)
 KERNELS = ("bin", "real_b", "site_pairs", "fft_xy_fwd", "fft_z_pot", "fft_xy_inv", "gather_b", "charges",
            "spread_elec", "fft_xy_fwd_e", "fft_z_field", "fft_xy_inv_e", "site_forces", "energy")
 
@@ -216,7 +217,7 @@ class Context:
         n = self._lib.cpm_get_buffer(self._ctx, which, None)
         if n < 0:
             self._check(int(n))
-        is_int = which in (BUF_CELL_START, BUF_SITE_ORDER, BUF_NCELL)
+        is_int = which in (BUF_CELL_START, BUF_SITE_ORDER, BUF_NCELL, BUF_BATCH_CHUNK)
         out = np.empty(int(n), dtype=np.int32 if is_int else np.float64)
         r = self._lib.cpm_get_buffer(self._ctx, which, out.ctypes.data_as(ctypes.c_void_p))
         if r < 0:

@@ -60,6 +60,12 @@ struct cpm_ctx {
   double *d_ex = nullptr, *d_ey = nullptr, *d_ez = nullptr;
   double *d_c = nullptr, *d_d = nullptr, *d_ze = nullptr, *d_e1 = nullptr;
   double *d_A = nullptr, *d_S = nullptr, *d_Sc = nullptr;
+  double* d_Sc_s = nullptr;                // S c in the electrodes' cell-sorted order
+  int* d_epos = nullptr;                   // cell-sorted position of every electrode atom
+  double* d_qs = nullptr;                  // [frame][n_elec] charges of the force pass, cell-sorted
+  // work items of the real-space b tiles: at most TILE_TGT atoms of one cell
+  int n_items = 0;
+  int *d_item_c = nullptr, *d_item_lo = nullptr, *d_item_hi = nullptr;
   float* d_Sf = nullptr;
   unsigned short *d_Ssplit = nullptr, *d_bsplit = nullptr;   // three bf16 terms each
   unsigned char* d_sub1 = nullptr;
@@ -75,9 +81,10 @@ struct cpm_ctx {
   double* d_wrap = nullptr;       // binning scratch: wrapped coordinates [frame][3][n_site]
   double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
   double *d_zdip = nullptr, *d_b = nullptr, *d_Q0 = nullptr, *d_qint = nullptr, *d_usite = nullptr;
-  double *d_ek = nullptr, *d_ftmp = nullptr, *d_fcomp = nullptr, *d_energy_tmp = nullptr, *d_lam = nullptr, *d_scalar = nullptr;
+  double *d_ek = nullptr, *d_ftmp = nullptr, *d_fcomp = nullptr, *d_felec = nullptr, *d_energy_tmp = nullptr, *d_lam = nullptr, *d_scalar = nullptr;
   double *d_g = nullptr, *d_qa = nullptr, *d_dv = nullptr;
   int cap_dv = 0;
+  int batch_chunk = 0;                     // frames per batched launch chosen by the tuner (0: not yet)
   // k-space field mesh of the electrode charges S c alone (batched dV sweep)
   double* d_ESc = nullptr;
   float* d_EScf = nullptr;
@@ -310,10 +317,12 @@ int alloc_frames(cpm_ctx* c, int nf) {
   TRY(dalloc(c, &c->d_lam, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_g, (size_t)nf * ne));
   TRY(dalloc(c, &c->d_qa, (size_t)nf * ne));
+  TRY(dalloc(c, &c->d_qs, (size_t)nf * ne));
   if (mixed) TRY(dalloc(c, &c->d_bsplit, (size_t)3 * nf * c->n_pad));
   TRY(dalloc(c, &c->d_usite, (size_t)nf * ns));
   TRY(dalloc(c, &c->d_ftmp, (size_t)nf * 3 * ns));
   TRY(dalloc(c, &c->d_fcomp, (size_t)nf * 6 * ns));
+  TRY(dalloc(c, &c->d_felec, (size_t)nf * 6 * ns));
   TRY(dalloc(c, &c->d_energy_tmp, (size_t)nf * 2));
   if (c->kspace == CPM_KSPACE_PPPM) {
     const size_t M = c->mi.M;
@@ -428,6 +437,21 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
   ba.status = c->d_status;
   ba.wrap_all = c->d_wrap;
   SiteSet<T> st = B::sites(c);
+  // real-space b: one frame, a wavefront per electrode atom (hosted in the
+  // potential's z pass); many frames, cell tiles in a launch of their own
+  RealBArgs<T> rb{};
+  rb.tiles = nf > 1;
+  rb.n_blocks = rb.tiles ? c->n_items : (c->n_elec + 3) / 4;
+  rb.cell = c->cell;
+  rb.st = st;
+  rb.alpha = (T)c->alpha;
+  rb.eta = (T)c->eta;
+  rb.rc2 = c->rcut * c->rcut;
+  rb.el = B::elec(c);
+  rb.phi_out = B::phir(c);
+  rb.item_c = c->d_item_c;
+  rb.item_lo = c->d_item_lo;
+  rb.item_hi = c->d_item_hi;
   if (c->kspace == CPM_KSPACE_PPPM) {
     rec(c, CPM_KERNEL_FFT_XY_FWD, s, [=](hipStream_t s) {
       launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, B::rho(c), B::c1(c), true, true);
@@ -435,23 +459,13 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
     keep(c, CPM_KERNEL_BIN, [=](hipStream_t s) {
       launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, B::rho(c), B::c1(c), false, true);
     });
-    RealBArgs<T> rb{};
-    rb.n_blocks = (c->n_elec + 3) / 4;
-    rb.cell = c->cell;
-    rb.st = st;
-    rb.alpha = (T)c->alpha;
-    rb.eta = (T)c->eta;
-    rb.rc2 = c->rcut * c->rcut;
-    rb.el = B::elec(c);
-    rb.phi_out = B::phir(c);
+    if (rb.tiles) rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
-                            forces ? B::save(c) : nullptr, 0, c->d_ek, true, &rb, nullptr);
+                            forces ? B::save(c) : nullptr, 0, c->d_ek, true, rb.tiles ? nullptr : &rb, nullptr);
     });
     // timed alone through the stand-alone kernel with the same body
-    keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) {
-      launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c));
-    });
+    if (!rb.tiles) keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     rec(c, CPM_KERNEL_FFT_XY_INV, s, [=](hipStream_t s) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
     });
@@ -460,9 +474,7 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
     });
   } else {
     rec(c, CPM_KERNEL_BIN, s, [=](hipStream_t s) { launch_bin_sites(s, nf, ba); });
-    rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) {
-      launch_real_b_t<T>(s, nf, c->cell, c->alpha, c->eta, c->rcut, B::elec(c), st, B::phir(c));
-    });
+    rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     SiteSet<double> sd = Bufs<double>::sites(c);
     launch_ewald_sf(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok, c->d_ek);
     launch_ewald_phi(s, nf, c->nk, c->n_elec, c->d_ew, c->d_eph, c->d_rhok, c->d_phir, c->d_b);
@@ -471,12 +483,12 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
 }
 
 // Stage 3: Coulomb forces on the sites for electrode charges qa (+ optional
-// second set qb on a shared field mesh Eb) and, if ea is given, the
-// energies.  The site-site forces (independent of the charges) run as extra
+// second set qb on a shared field mesh Eb; qa_s: qa in the electrodes'
+// cell-sorted order, same frame stride) and, if ea is given, the energies.  The site-site forces (independent of the charges) run as extra
 // workgroups of the z pass of the field, the energies as extra workgroups
 // of the site-force launch.
 template <typename T>
-int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, ForceArgs<T> fa,
+int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const double* qa_s, ForceArgs<T> fa,
                    const EnergyArgs* ea) {
   using B = Bufs<T>;
   using T2 = typename B::T2;
@@ -487,6 +499,8 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
   fa.rc2 = c->rcut * c->rcut;
   fa.qa = qa;
   fa.qa_frame_stride = qa_stride;
+  fa.qa_s = qa_s;
+  fa.qb_s = fa.qb ? c->d_Sc_s : nullptr;     // the only second set is S c
   fa.mi = c->mi;
   fa.f_pair = c->d_fpair;
   PairArgs<T> pa{};
@@ -500,6 +514,17 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, Force
   pa.rc2 = fa.rc2;
   pa.f_pair = c->d_fpair;
   pa.u_site = c->d_usite;
+  if (pa.tsplit > 0) {
+    // tiles run after the charge solve: they take the site-electrode pairs
+    // too, and the site-force kernel then skips its own electrode walk
+    pa.el = B::elec(c);
+    pa.eta = fa.eta;
+    pa.qa_s = qa_s;
+    pa.qa_stride = qa_stride;
+    pa.qb_s = fa.qb_s;
+    pa.f_elec = c->d_felec;
+    fa.f_elec = c->d_felec;
+  }
   if (c->kspace == CPM_KSPACE_PPPM) {
     // the electrode spread stays a kernel of its own: only the few planes
     // near the electrodes hold charge, and a per-plane fusion would leave
@@ -573,10 +598,12 @@ int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, doubl
     rec(c, CPM_KERNEL_CHARGES, s, [=](hipStream_t s) {
       launch_charges_f32(s, 1, c->n_elec, c->d_Sf, c->d_b, c->d_Q0);
       launch_reproject(s, 1, c->n_elec, c->d_sub1, c->d_Q0);
-      launch_axpy(s, c->n_elec, c->d_Q0, c->d_Sc, dv, q_out);
+      launch_axpy(s, c->n_elec, c->d_Q0, c->d_Sc, dv, q_out, c->d_epos, c->d_qs);
     });
   } else {
-    rec(c, CPM_KERNEL_CHARGES, s, [=](hipStream_t s) { launch_charges(s, 1, c->n_elec, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q_out); });
+    rec(c, CPM_KERNEL_CHARGES, s, [=](hipStream_t s) {
+      launch_charges(s, 1, c->n_elec, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q_out, c->d_epos, c->d_qs);
+    });
   }
   if (need_forces) {
     ForceArgs<T> fa{};
@@ -588,7 +615,7 @@ int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, doubl
     fa.dv = nullptr;
     fa.u_site = c->d_usite;
     const EnergyArgs ea = energy_args(c, 1, nullptr, dv, e_out);
-    TRY(enqueue_forces<T>(c, 1, q_out, c->n_elec, fa, e_out ? &ea : nullptr));
+    TRY(enqueue_forces<T>(c, 1, q_out, c->n_elec, c->d_qs, fa, e_out ? &ea : nullptr));
   }
   return CPM_OK;
 }
@@ -604,7 +631,7 @@ int enqueue_grad(cpm_ctx* c, const double* xyz, double dv, const double* t, doub
   launch_charges(s, 1, n, c->d_S, c->d_b, c->d_Sc, dv, c->d_Q0, q);
   launch_adjoint_rhs(s, n, q, t, c->d_c, dv, c->d_g);
   launch_charges(s, 1, n, c->d_S, c->d_g, c->d_Sc, 0.0, c->d_lam, nullptr);    // lambda = S g
-  launch_sub(s, n, q, c->d_lam, c->d_qa);
+  launch_sub(s, n, q, c->d_lam, c->d_qa, c->d_epos, c->d_qs);
   ForceArgs<T> fa{};
   fa.out_scale = -1.0;
   fa.field = 0.0;
@@ -613,7 +640,7 @@ int enqueue_grad(cpm_ctx* c, const double* xyz, double dv, const double* t, doub
   fa.n_dv = 1;
   fa.u_site = c->d_usite;
   const EnergyArgs ea = energy_args(c, 1, nullptr, dv, c->d_energy_tmp);
-  TRY(enqueue_forces<T>(c, 1, c->d_qa, n, fa, &ea));
+  TRY(enqueue_forces<T>(c, 1, c->d_qa, n, c->d_qs, fa, &ea));
   launch_grad_finish(s, n, q, t, c->d_lam, c->d_c, c->d_energy_tmp, loss, dldv);
   return CPM_OK;
 }
@@ -651,6 +678,7 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
     launch_gemm_nt(s, nf, n, n, 1.0, c->d_b, n, c->d_S, n, 0.0, c->d_Q0, n);
   }
   launch_expand_charges(s, nf, n, n_dv, c->d_dv, c->d_Q0, c->d_Sc, q_out);
+  if (f_out || e_out) launch_permute(s, nf, n, c->d_epos, c->d_Q0, c->d_qs);
   if (need_forces) {
     ForceArgs<T> fa{};
     fa.out_scale = 1.0;
@@ -665,10 +693,59 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
     fa.dv = c->d_dv;
     fa.u_site = c->d_usite;
     const EnergyArgs ea = energy_args(c, n_dv, c->d_dv, 0.0, e_out);
-    TRY(enqueue_forces<T>(c, nf, c->d_Q0, n, fa, e_out ? &ea : nullptr));
+    TRY(enqueue_forces<T>(c, nf, c->d_Q0, n, c->d_qs, fa, e_out ? &ea : nullptr));
     if (f_out) launch_expand_forces(s, nf, c->n_site, n_dv, c->d_dv, c->d_fcomp, f_out);
   }
   return CPM_OK;
+}
+
+// Frames per batched launch.  Many frames per launch amortise launch costs;
+// fewer keep a launch's intermediate meshes (~2 MB per frame of the paper
+// cell) within the last-level cache for the next kernel.  The tuner times
+// each candidate size on the caller's first frames (second of two runs,
+// HIP events on the context's stream, so it synchronises once) and keeps
+// the fastest per frame.  Its runs write outputs that the real run
+// overwrites.
+constexpr int BATCH_CHUNK_MAX = 4096;
+constexpr int BATCH_TUNE_MIN = 64;
+
+template <typename Run>
+int tune_batch_chunk(cpm_ctx* c, int n_frames, Run run) {
+  std::vector<int> cand;
+  for (int k = BATCH_TUNE_MIN; k <= std::min(n_frames, BATCH_CHUNK_MAX); k *= 2) cand.push_back(k);
+  if (cand.empty()) return CPM_OK;
+  if (c->cap_frames < cand.back()) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int r = alloc_frames(c, cand.back());
+    if (r) return r;
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, CPM_EDEVICE, "hipEventCreate failed");
+  }
+  int best = cand.back();
+  float best_t = 0.0f;
+  int rc = CPM_OK;
+  for (int k : cand) {
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2 && rc == CPM_OK; ++rep) {
+      if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(c, CPM_EDEVICE, "hipEventRecord failed"); break; }
+      rc = run(k, 0);
+      if (rc) break;
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        rc = fail(c, CPM_EDEVICE, "timing a batch size failed");
+    }
+    if (rc) break;
+    const float per_frame = ms / (float)k;
+    if (k == cand.front() || per_frame < best_t) { best_t = per_frame; best = k; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == CPM_OK) c->batch_chunk = best;
+  return rc;
 }
 
 int check_launch(cpm_ctx* c) {
@@ -808,6 +885,25 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     sze[k] = wrap_host(c->hz[i], c->box[2]);
   }
   for (int k = 0; k < cl.n_cells; ++k) ecs[k + 1] += ecs[k];
+  std::vector<int> epos(ne);
+  for (int k = 0; k < ne; ++k) epos[eorder[k]] = k;
+  if ((r = upload(c, &c->d_epos, epos))) return bad(r);
+  {
+    // each cell's atoms in equal chunks of at most TILE_TGT
+    std::vector<int> ic, il, ih;
+    for (int cc2 = 0; cc2 < cl.n_cells; ++cc2) {
+      const int lo = ecs[cc2], n = ecs[cc2 + 1] - lo;
+      const int nch = (n + TILE_TGT - 1) / TILE_TGT;
+      for (int k = 0; k < nch; ++k) {
+        ic.push_back(cc2);
+        il.push_back(lo + (int)((long long)n * k / nch));
+        ih.push_back(lo + (int)((long long)n * (k + 1) / nch));
+      }
+    }
+    c->n_items = (int)ic.size();
+    if ((r = upload(c, &c->d_item_c, ic)) || (r = upload(c, &c->d_item_lo, il)) || (r = upload(c, &c->d_item_hi, ih)))
+      return bad(r);
+  }
   if ((r = upload(c, &c->d_ex, c->hx)) || (r = upload(c, &c->d_ey, c->hy)) || (r = upload(c, &c->d_ez, c->hz)) ||
       (r = upload(c, &c->d_c, cc)) || (r = upload(c, &c->d_d, dd)) || (r = upload(c, &c->d_ze, ze)) ||
       (r = upload(c, &c->d_e1, e1)) || (r = upload(c, &c->d_site_q, c->hq)))
@@ -835,7 +931,8 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     c->elf = ElecSet<float>{x, y, z, o, ce, cs, ne, rp, rl, rh};
   }
   if ((r = dalloc(c, &c->d_A, (size_t)ne * ne)) || (r = dalloc(c, &c->d_S, (size_t)ne * ne)) ||
-      (r = dalloc(c, &c->d_Sc, ne)) || (r = dalloc(c, &c->d_status, 4)) || (r = dalloc(c, &c->d_scalar, 8)))
+      (r = dalloc(c, &c->d_Sc, ne)) || (r = dalloc(c, &c->d_Sc_s, ne)) || (r = dalloc(c, &c->d_status, 4)) ||
+      (r = dalloc(c, &c->d_scalar, 8)))
     return bad(r);
   c->n_pad = (ne + 15) / 16 * 16;
   if (c->precision == CPM_MIXED) {
@@ -1046,6 +1143,7 @@ int cpm_build_elastance(cpm_ctx* c) {
     launch_rank1(s, n, c->d_S, u, c->d_scalar);             // S -= w w^T / e1.w
   }
   launch_matvec(s, n, c->d_S, c->d_c, c->d_Sc);            // S c
+  launch_permute(s, 1, n, c->d_epos, c->d_Sc, c->d_Sc_s);
   if (c->precision == CPM_MIXED) launch_split_matrix(s, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
   TRY(check_launch(c));
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -1065,6 +1163,7 @@ int cpm_set_matrix(cpm_ctx* c, const double* host_S) {
   const int n = c->n_elec;
   HIP_TRY(c, hipMemcpy(c->d_S, host_S, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice));
   launch_matvec(c->stream, n, c->d_S, c->d_c, c->d_Sc);
+  launch_permute(c->stream, 1, n, c->d_epos, c->d_Sc, c->d_Sc_s);
   if (c->precision == CPM_MIXED) launch_split_matrix(c->stream, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->built = true;
@@ -1129,14 +1228,6 @@ int cpm_solve_batch(cpm_ctx* c, int n_frames, const double* xyz, int n_dv, const
   if (n_frames == 0) return CPM_OK;
   for (int v = 0; v < n_dv; ++v)
     if (!std::isfinite(dv_host[v])) return fail(c, CPM_ENONFINITE, "non-finite dV");
-  // frames go through in chunks that fit the per-frame scratch
-  const int chunk_max = std::max(1, std::min(n_frames, (int)std::max<long>(1, std::atol(
-      std::getenv("CPM_BATCH_CHUNK") ? std::getenv("CPM_BATCH_CHUNK") : "4096"))));
-  if (c->cap_frames < chunk_max) {
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    int r = alloc_frames(c, chunk_max);
-    if (r) return r;
-  }
   if (c->cap_dv < n_dv) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     int r = dalloc(c, &c->d_dv, n_dv);
@@ -1152,14 +1243,34 @@ int cpm_solve_batch(cpm_ctx* c, int n_frames, const double* xyz, int n_dv, const
     else enqueue_esc_mesh<double>(c, c->d_ESc);
     c->esc_ready = true;
   }
-  const size_t xs = (size_t)3 * c->n_site;
-  for (int f0 = 0; f0 < n_frames; f0 += chunk_max) {
-    int nf = std::min(chunk_max, n_frames - f0);
+  auto run = [&](int nf, int f0) {
+    const size_t xs3 = (size_t)3 * c->n_site;
     double* q = q_out + (size_t)f0 * n_dv * c->n_elec;
-    double* f = f_out ? f_out + (size_t)f0 * n_dv * xs : nullptr;
+    double* f = f_out ? f_out + (size_t)f0 * n_dv * xs3 : nullptr;
     double* e = e_out ? e_out + (size_t)f0 * n_dv * 2 : nullptr;
-    int r = mixed ? enqueue_batch<float>(c, nf, xyz + f0 * xs, n_dv, q, f, e)
-                  : enqueue_batch<double>(c, nf, xyz + f0 * xs, n_dv, q, f, e);
+    return mixed ? enqueue_batch<float>(c, nf, xyz + f0 * xs3, n_dv, q, f, e)
+                 : enqueue_batch<double>(c, nf, xyz + f0 * xs3, n_dv, q, f, e);
+  };
+  // frames per launch: set by CPM_BATCH_CHUNK, else tuned on the first call
+  // with enough frames, else all of them (at most BATCH_CHUNK_MAX)
+  int chunk_max;
+  if (const char* env = std::getenv("CPM_BATCH_CHUNK")) {
+    chunk_max = (int)std::max<long>(1, std::atol(env));
+  } else {
+    if (c->batch_chunk == 0 && n_frames >= 2 * BATCH_TUNE_MIN) {
+      int r = tune_batch_chunk(c, n_frames, run);
+      if (r) return r;
+    }
+    chunk_max = c->batch_chunk > 0 ? c->batch_chunk : BATCH_CHUNK_MAX;
+  }
+  chunk_max = std::max(1, std::min(chunk_max, n_frames));
+  if (c->cap_frames < chunk_max) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int r = alloc_frames(c, chunk_max);
+    if (r) return r;
+  }
+  for (int f0 = 0; f0 < n_frames; f0 += chunk_max) {
+    int r = run(std::min(chunk_max, n_frames - f0), f0);
     if (r) return r;
   }
   return check_launch(c);
@@ -1208,6 +1319,9 @@ long long cpm_get_buffer(cpm_ctx* c, int which, void* host_out) {
     case CPM_BUF_NCELL:
       if (host_out) std::memcpy(host_out, c->cell.nc, 3 * sizeof(int));
       return 3;
+    case CPM_BUF_BATCH_CHUNK:
+      if (host_out) std::memcpy(host_out, &c->batch_chunk, sizeof(int));
+      return 1;
     default: return fail(c, CPM_EINVAL, "unknown buffer %d", which);
   }
   if (!host_out) return (long long)count;

@@ -12,6 +12,11 @@ constexpr double KE = 1.43996454784;   // eV nm / e^2
 constexpr int WAVE = 64;
 constexpr int MAX_FFT_FACTORS = 12;
 constexpr int MAX_ORDER = 7;
+// cell tiles of the real-space sums: workgroup size, candidates staged in
+// LDS per pass, targets per chunk
+constexpr int TILE_THREADS = 256;
+constexpr int TILE_CAND = 512;
+constexpr int TILE_TGT = 64;
 
 // ---------------------------------------------------------------- geometry
 
@@ -206,9 +211,12 @@ struct ForceArgs {
   // explicit-Ewald path instead of a mesh: k-space field at the sites,
   // [frame][3][n_site] in cell-sorted order (V/nm), or nullptr
   const double* Esite;
-  // electrode charges, original order: qa per frame (stride n_elec), qb shared
+  // electrode charges, original order: qa per frame (stride n_elec), qb shared;
+  // the same in the electrodes' cell-sorted order (what the pair walk reads)
   const double* qa; size_t qa_frame_stride;
   const double* qb;
+  const double* qa_s;
+  const double* qb_s;
   double out_scale;          // multiplies the Coulomb force (e.g. -1 for a gradient)
   double field;              // -dV/Lz for the finite field (0 otherwise), added along z
   double fieldb;             // same for the second set (per unit dV)
@@ -220,6 +228,10 @@ struct ForceArgs {
   double* f_comp;
   int n_dv; const double* dv;             // dV values of the sweep (n_dv == 1: dv may be nullptr)
   double* u_site;                          // [frame][n_site] 1/2 Q_j sum Q_j' g0 (sorted order), or nullptr
+  // site-electrode sums already made by the pair tiles, [frame][6][n_site]
+  // sorted order (charges a, then b), or nullptr: the site-force kernel
+  // then walks the electrode atoms itself
+  const double* f_elec;
   // site-site real-space sum of every site, sum_j' Q_j' g0(r) r_vec without
   // k_e and Q_j, [frame][3][n_site] sorted order: written by the site-pair
   // kernel, read by the site-force kernel
@@ -231,17 +243,23 @@ struct ForceArgs {
 template <typename T>
 constexpr size_t pair_queue_lds() { return 4 * (5 * 128 * sizeof(T) + 64 * sizeof(int)); }
 
-// real-space part of b hosted as extra workgroups of another launch
-// (one wavefront per electrode atom, four per workgroup)
+// real-space part of b: one wavefront per electrode atom, four per
+// workgroup (tiles == 0; hosted as extra workgroups of another launch for
+// one frame), or cell tiles over fixed work items of at most TILE_TGT atoms
+// of one cell (tiles != 0; many frames)
 template <typename T>
 struct RealBArgs {
-  int n_blocks;                // workgroups per frame, 0: none
+  int n_blocks;                // workgroups per frame (ceil(n_elec / 4), or the item count), 0: none
   Cell cell;
   SiteSet<T> st;               // cell-sorted sites
   T alpha, eta;
   double rc2;
   ElecSet<T> el;
   T* phi_out;                  // [frame][n_elec] original order
+  int tiles;
+  const int* item_c;           // cell of item b
+  const int* item_lo;          // its atoms [item_lo, item_hi) of the sorted electrode arrays
+  const int* item_hi;
 };
 
 // site-site forces hosted as extra workgroups of another launch: cell tiles
@@ -258,6 +276,15 @@ struct PairArgs {
   double rc2;
   double* f_pair;              // [frame][3][n_site] sorted order
   double* u_site;              // [frame][n_site] sorted order, or nullptr
+  // tiles only, once the electrode charges are known (batched form): the
+  // site-electrode sums as well, for the charges qa_s (per frame, stride
+  // qa_stride) and qb_s (shared, or nullptr), in the atoms' sorted order;
+  // f_elec [frame][6][n_site] sorted order, or nullptr for none
+  ElecSet<T> el;
+  T eta;
+  const double* qa_s; size_t qa_stride;
+  const double* qb_s;
+  double* f_elec;
 };
 
 // points (columns x Kz) of one z-pass workgroup: 256 threads hold up to 8
@@ -389,8 +416,7 @@ void launch_bin_sites(hipStream_t s, int n_frames, const BinArgs& a);
 
 // real-space sums (k_realspace.hip)
 template <typename T>
-void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
-                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out);
+void launch_real_b_t(hipStream_t s, int n_frames, const RealBArgs<T>& rb);
 template <typename T>
 void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa);
 // LDS of a site-pair workgroup (tsplit > 0: tile form)
@@ -462,7 +488,9 @@ void launch_matvec(hipStream_t s, int n, const double* Mx, const double* x, doub
 void launch_dot(hipStream_t s, int n, const double* a, const double* b, double* out);
 void launch_rank1(hipStream_t s, int n, double* S, const double* u, const double* sc);
 void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const double* b, const double* Sc, double dv,
-                    double* Q0, double* q);
+                    double* Q0, double* q, const int* epos = nullptr, double* qs = nullptr);
+// dst[f][epos[i]] = src[f][i] for n values of n_frames frames
+void launch_permute(hipStream_t s, int n_frames, int n, const int* epos, const double* src, double* dst);
 void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
                            const double* Sc, double* q);
 // out[f][v][k] = comp[f][0][k] + dv[v] comp[f][1][k] over the 3 n_site
@@ -471,7 +499,8 @@ void launch_expand_forces(hipStream_t s, int n_frames, int n_site, int n_dv, con
                           double* out);
 
 void launch_adjoint_rhs(hipStream_t s, int n, const double* q, const double* t, const double* c, double dv, double* g);
-void launch_sub(hipStream_t s, int n, const double* a, const double* b, double* out);
+void launch_sub(hipStream_t s, int n, const double* a, const double* b, double* out, const int* epos = nullptr,
+                double* out_s = nullptr);
 void launch_grad_finish(hipStream_t s, int n, const double* q, const double* t, const double* lam, const double* c,
                         const double* energy, double* loss, double* dldv);
 
@@ -482,6 +511,7 @@ void launch_charges_f32(hipStream_t s, int n_frames, int n, const float* Sf, con
 void launch_reproject(hipStream_t s, int n_frames, int n, const unsigned char* sub1, double* Q0);
 void launch_gemm_bf16x6(hipStream_t s, int M, int N, int K, const unsigned short* A, size_t a_plane,
                         const unsigned short* B, size_t b_plane, double* D, int ldd);
-void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out);
+void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out,
+                 const int* epos = nullptr, double* out_s = nullptr);
 
 }  // namespace cpm

@@ -334,11 +334,9 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
   if ((int)blockIdx.x >= n_z_blocks) {
     // hosted work, one wavefront per target: the real-space part of b
     // (electrode atoms), then the site-site forces (sites)
-    T* qbuf = reinterpret_cast<T*>(smem + (threadIdx.x >> 6) * wave_scratch_bytes<T>());
     const int hb = (int)blockIdx.x - n_z_blocks;
     if (hb < rb.n_blocks) {
-      const int g = xcd_block(hb, rb.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
-      if (g < rb.el.n) real_b_wave(rb.cell, rb.alpha, rb.eta, rb.rc2, rb.el, rb.st, rb.phi_out, g, blockIdx.y, qbuf);
+      real_b_block(rb, xcd_block(hb, rb.n_blocks), blockIdx.y, smem);
     } else {
       site_pairs_block(pa, xcd_block(hb - rb.n_blocks, pa.n_blocks), blockIdx.y, smem);
     }
@@ -508,8 +506,8 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
   const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
   size_t lds = (3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2);
-  if (r.n_blocks > 0) lds = std::max(lds, pair_queue_lds<T>());
-  if (p.n_blocks > 0) lds = std::max(lds, p.tsplit > 0 ? TileLds<T, 1, 4, 4>::total : pair_queue_lds<T>());
+  if (r.n_blocks > 0) lds = std::max(lds, r.tiles ? PairLds<T>::total : pair_queue_lds<T>());
+  if (p.n_blocks > 0) lds = std::max(lds, p.tsplit > 0 ? PairLds<T>::total : pair_queue_lds<T>());
   dim3 grid(nzb + r.n_blocks + p.n_blocks, n_frames);
   if (grid.x == 0) return;
   hipLaunchKernelGGL((k_fft_z<T, T2>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,

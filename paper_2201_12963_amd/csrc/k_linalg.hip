@@ -250,7 +250,8 @@ __global__ void k_rank1(int n, double* __restrict__ S, const double* __restrict_
 // independent accumulators so that four row loads per lane are in flight
 __global__ __launch_bounds__(256) void k_charges(int n, const double* __restrict__ S, const double* __restrict__ b_all,
                                                  const double* __restrict__ Sc, double dv,
-                                                 double* __restrict__ Q0_all, double* __restrict__ q_all) {
+                                                 double* __restrict__ Q0_all, double* __restrict__ q_all,
+                                                 const int* __restrict__ epos, double* __restrict__ qs_all) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   const int frame = blockIdx.y;
@@ -281,9 +282,20 @@ __global__ __launch_bounds__(256) void k_charges(int n, const double* __restrict
   const double acc = wave_sum((a0 + a1) + (a2 + a3));
   if (lane == 0) {
     const size_t o = (size_t)frame * n + i;
+    const double qv = acc + dv * Sc[i];
     if (Q0_all) Q0_all[o] = acc;
-    if (q_all) q_all[o] = acc + dv * Sc[i];
+    if (q_all) q_all[o] = qv;
+    if (qs_all) qs_all[(size_t)frame * n + epos[i]] = qv;      // cell-sorted copy
   }
+}
+
+// dst[f][epos[i]] = src[f][i]: charges of every frame in the electrodes'
+// cell-sorted order (what the pair walkers stream)
+__global__ __launch_bounds__(256) void k_permute(int n, const int* __restrict__ epos, const double* __restrict__ src,
+                                                 double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t f = blockIdx.y;
+  if (i < n) dst[f * n + epos[i]] = src[f * n + i];
 }
 
 // ------------------------------------------------------------ energies
@@ -333,10 +345,16 @@ __global__ __launch_bounds__(256) void k_adjoint_rhs(int n, const double* __rest
 }
 
 // qa = q - lambda  (electrode charges of the adjoint force pass)
+// (and its cell-sorted copy out_s[epos[i]])
 __global__ __launch_bounds__(256) void k_sub(int n, const double* __restrict__ a, const double* __restrict__ b,
-                                             double* __restrict__ out) {
+                                             double* __restrict__ out, const int* __restrict__ epos,
+                                             double* __restrict__ out_s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a[i] - b[i];
+  if (i < n) {
+    const double v = a[i] - b[i];
+    out[i] = v;
+    if (out_s) out_s[epos[i]] = v;
+  }
 }
 
 // loss = sum (q - t)^2 + U_coul;  dL/ddV = lambda . c   (one workgroup)
@@ -364,8 +382,8 @@ __global__ __launch_bounds__(256) void k_grad_finish(int n, const double* __rest
 void launch_adjoint_rhs(hipStream_t s, int n, const double* q, const double* t, const double* c, double dv, double* g) {
   hipLaunchKernelGGL(k_adjoint_rhs, dim3((n + 255) / 256), dim3(256), 0, s, n, q, t, c, dv, g);
 }
-void launch_sub(hipStream_t s, int n, const double* a, const double* b, double* out) {
-  hipLaunchKernelGGL(k_sub, dim3((n + 255) / 256), dim3(256), 0, s, n, a, b, out);
+void launch_sub(hipStream_t s, int n, const double* a, const double* b, double* out, const int* epos, double* out_s) {
+  hipLaunchKernelGGL(k_sub, dim3((n + 255) / 256), dim3(256), 0, s, n, a, b, out, epos, out_s);
 }
 void launch_grad_finish(hipStream_t s, int n, const double* q, const double* t, const double* lam, const double* c,
                         const double* energy, double* loss, double* dldv) {
@@ -409,8 +427,12 @@ void launch_rank1(hipStream_t s, int n, double* S, const double* u, const double
   hipLaunchKernelGGL(k_rank1, dim3((n + 15) / 16, (n + 15) / 16), dim3(256), 0, s, n, S, u, sc);
 }
 void launch_charges(hipStream_t s, int n_frames, int n, const double* S, const double* b, const double* Sc, double dv,
-                    double* Q0, double* q) {
-  hipLaunchKernelGGL(k_charges, dim3((n + 3) / 4, n_frames), dim3(256), 0, s, n, S, b, Sc, dv, Q0, q);
+                    double* Q0, double* q, const int* epos, double* qs) {
+  hipLaunchKernelGGL(k_charges, dim3((n + 3) / 4, n_frames), dim3(256), 0, s, n, S, b, Sc, dv, Q0, q, epos, qs);
+}
+void launch_permute(hipStream_t s, int n_frames, int n, const int* epos, const double* src, double* dst) {
+  if (n == 0 || n_frames == 0) return;
+  hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256, n_frames), dim3(256), 0, s, n, epos, src, dst);
 }
 void launch_expand_forces(hipStream_t s, int n_frames, int n_site, int n_dv, const double* dv, const double* comp,
                           double* out) {

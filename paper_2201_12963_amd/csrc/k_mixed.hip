@@ -53,11 +53,16 @@ __global__ __launch_bounds__(256) void k_split_matrix(int n, int n_pad, const do
   for (int k = 0; k < 3; ++k) split[k * plane + (size_t)row * n_pad + col] = t[k];
 }
 
-// out = x + a y
+// out = x + a y (and its cell-sorted copy out_s[epos[i]], if given)
 __global__ __launch_bounds__(256) void k_axpy(int n, const double* __restrict__ x, const double* __restrict__ y,
-                                              double a, double* __restrict__ out) {
+                                              double a, double* __restrict__ out, const int* __restrict__ epos,
+                                              double* __restrict__ out_s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = x[i] + a * y[i];
+  if (i < n) {
+    const double v = x[i] + a * y[i];
+    out[i] = v;
+    if (out_s) out_s[epos[i]] = v;
+  }
 }
 
 // mean-centred b of each frame, split into three bf16 terms, rows [frame][n_pad]
@@ -185,8 +190,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x6(int M, int N, int K, const 
 void launch_split_matrix(hipStream_t s, int n, int n_pad, const double* S, float* Sf, unsigned short* split) {
   hipLaunchKernelGGL(k_split_matrix, dim3((n_pad + 255) / 256, n), dim3(256), 0, s, n, n_pad, S, Sf, split);
 }
-void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out) {
-  hipLaunchKernelGGL(k_axpy, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y, a, out);
+void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out, const int* epos,
+                 double* out_s) {
+  hipLaunchKernelGGL(k_axpy, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y, a, out, epos, out_s);
 }
 void launch_split_b(hipStream_t s, int n_frames, int n, int n_pad, const double* b, unsigned short* split) {
   hipLaunchKernelGGL(k_split_b, dim3(n_frames), dim3(256), 0, s, n, n_pad, b, split);

@@ -9,21 +9,16 @@
 namespace cpm {
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_real_b(Cell cell, T alpha, T eta, double rc2, ElecSet<T> el,
-                                                SiteSet<T> st, T* __restrict__ phi_out) {
-  __shared__ __align__(16) unsigned char scratch[4 * wave_scratch_bytes<T>()];
-  const int g = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
-  if (g >= el.n) return;
-  real_b_wave(cell, alpha, eta, rc2, el, st, phi_out, g, blockIdx.y,
-              reinterpret_cast<T*>(scratch + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
+__global__ __launch_bounds__(TILE_THREADS) void k_real_b(RealBArgs<T> rb) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  real_b_block(rb, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }
 
 template <typename T>
-void launch_real_b_t(hipStream_t s, int n_frames, const Cell& cell, double alpha, double eta,
-                     double rcut, const ElecSet<T>& el, const SiteSet<T>& st, T* phi_out) {
-  dim3 grid((el.n + 3) / 4, n_frames);
-  hipLaunchKernelGGL(k_real_b<T>, grid, dim3(256), 0, s, cell, (T)alpha, (T)eta, rcut * rcut,
-                     el, st, phi_out);
+void launch_real_b_t(hipStream_t s, int n_frames, const RealBArgs<T>& rb) {
+  if (rb.n_blocks == 0 || n_frames == 0) return;
+  const size_t lds = rb.tiles ? PairLds<T>::total : 4 * wave_scratch_bytes<T>();
+  hipLaunchKernelGGL(k_real_b<T>, dim3(rb.n_blocks, n_frames), dim3(TILE_THREADS), lds, s, rb);
 }
 
 template <typename T>
@@ -33,7 +28,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_site_pairs(PairArgs<T> pa) {
 }
 
 template <typename T>
-size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? TileLds<T, 1, 4, 4>::total : 4 * wave_scratch_bytes<T>(); }
+size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? PairLds<T>::total : 4 * wave_scratch_bytes<T>(); }
 
 
 // The rest of the force on every site, once the electrode charges are known:
@@ -44,7 +39,7 @@ size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? TileLds<T, 1, 4, 4>::tot
 // the applied field.  One wavefront per site.  Workgroups from
 // n_force_blocks on reduce the energies of their frame instead (they read
 // nothing this kernel writes, so they run beside the force workgroups).
-template <typename T, bool TWO>
+template <typename T, bool TWO, bool WALK>
 __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, SiteSet<T> st,
                                                      ForceArgs<T> fa, int n_force_blocks, EnergyArgs en) {
   int bx = blockIdx.x, frame = blockIdx.y;
@@ -80,6 +75,13 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   const int orig = st.order[fo + j];
   const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
   const double fp0 = fp[j], fp1 = fp[st.n + j], fp2 = fp[2 * (size_t)st.n + j];
+  // site-electrode sums made by the pair tiles (WALK == false)
+  double fe[6] = {0, 0, 0, 0, 0, 0};
+  if (!WALK) {
+    const double* fep = fa.f_elec + (size_t)frame * 6 * st.n;
+#pragma unroll
+    for (int u = 0; u < 6; ++u) fe[u] = fep[(size_t)u * st.n + j];
+  }
   const int cj = site_cell(cell, xj, yj, zj);
 
   // ---- k-space field at the site
@@ -126,21 +128,23 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   // ---- real space: electrode Gaussians (g1)
   T fr[3] = {0, 0, 0};
   T frb[3] = {0, 0, 0};
-  const double* qa = fa.qa + (size_t)frame * fa.qa_frame_stride;
+  if (WALK) {
+  // the charges in the atoms' sorted order, loaded with their positions
+  const double* qa = fa.qa_s + (size_t)frame * fa.qa_frame_stride;
   const int nruns = elec_runs(el, cj, rlo, rhi);
   int n = 0;
   walk_runs(rlo, rhi, nruns,
             [&](int k, bool v) {
-              ElecPartner p{0, 0, 0, 0};
-              if (v) { p.x = el.x[k]; p.y = el.y[k]; p.z = el.z[k]; p.o = el.orig[k]; }
+              ElecPartner<T> p{0, 0, 0, (T)0, (T)0};
+              if (v) {
+                p.x = el.x[k]; p.y = el.y[k]; p.z = el.z[k];
+                p.a = (T)qa[k];
+                if (TWO) p.b = (T)fa.qb_s[k];
+              }
               return p;
             },
-            [&](const ElecPartner& p, int k, bool valid) {
-              T ca = 0, cb = 0;
-              if (valid) {
-                ca = (T)qa[p.o];
-                if (TWO) cb = (T)fa.qb[p.o];
-              }
+            [&](const ElecPartner<T>& p, int k, bool valid) {
+              const T ca = p.a, cb = p.b;
               const Disp d = min_disp(cell, xj, yj, zj, p.x, p.y, p.z);
               for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
                 for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
@@ -155,9 +159,10 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
                   }
             });
   if (lane < n) eval_g1<T, TWO>(Q, lane, fa.alpha, fa.eta, fr, frb);
+  }
 
   // ---- reduce and write
-  const double fpd[3] = {fp0, fp1, fp2};
+  const double fpd[3] = {fp0 + fe[0], fp1 + fe[1], fp2 + fe[2]};
   double F[3], FB[3];
   const T va[8] = {ea[0], ea[1], ea[2], fr[0], fr[1], fr[2], (T)0, (T)0};
   const T sa = wave_sum8(va);                 // lane 8k: total of va[k]
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
     const T sb = wave_sum8(vb);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      FB[d] = fa.out_scale * qj * ((double)read_lane(sb, 8 * d) + KE * (double)read_lane(sb, 24 + 8 * d));
+      FB[d] = fa.out_scale * qj * ((double)read_lane(sb, 8 * d) + KE * ((double)read_lane(sb, 24 + 8 * d) + fe[3 + d]));
   } else {
     FB[0] = FB[1] = FB[2] = 0.0;
   }
@@ -207,17 +212,22 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
   dim3 grid(nfb + (ea ? 1 : 0), n_frames);
   if (grid.x == 0) return;
   const EnergyArgs e = ea ? *ea : EnergyArgs{};
-  if (fa.Eb || fa.qb)
-    hipLaunchKernelGGL((k_site_forces<T, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+  // TWO: a second charge set; WALK: the kernel walks the electrode atoms
+  // itself (no site-electrode sums from the pair tiles)
+  const bool two = fa.Eb || fa.qb, walk = fa.f_elec == nullptr;
+  if (two && walk)
+    hipLaunchKernelGGL((k_site_forces<T, true, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+  else if (two)
+    hipLaunchKernelGGL((k_site_forces<T, true, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+  else if (walk)
+    hipLaunchKernelGGL((k_site_forces<T, false, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
   else
-    hipLaunchKernelGGL((k_site_forces<T, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+    hipLaunchKernelGGL((k_site_forces<T, false, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
 }
 
 // explicit instantiations used by api.cpp
-template void launch_real_b_t<double>(hipStream_t, int, const Cell&, double, double, double,
-                                      const ElecSet<double>&, const SiteSet<double>&, double*);
-template void launch_real_b_t<float>(hipStream_t, int, const Cell&, double, double, double,
-                                     const ElecSet<float>&, const SiteSet<float>&, float*);
+template void launch_real_b_t<double>(hipStream_t, int, const RealBArgs<double>&);
+template void launch_real_b_t<float>(hipStream_t, int, const RealBArgs<float>&);
 template void launch_site_pairs_t<double>(hipStream_t, int, const PairArgs<double>&);
 template void launch_site_pairs_t<float>(hipStream_t, int, const PairArgs<float>&);
 template size_t site_pairs_lds<double>(int);

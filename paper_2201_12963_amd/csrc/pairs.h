@@ -182,10 +182,11 @@ struct Partner {
   T a;
 };
 
-// an electrode atom: FP64 position and original index (its charge is per step)
+// an electrode atom: FP64 position and its charge(s) of this step
+template <typename T>
 struct ElecPartner {
   double x, y, z;
-  int o;
+  T a, b;
 };
 
 // Minimum-image displacement from a partner to the target, in FP64; the

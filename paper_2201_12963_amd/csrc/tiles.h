@@ -22,9 +22,6 @@
 
 namespace cpm {
 
-constexpr int TILE_THREADS = 256;
-constexpr int TILE_CAND = 512;   // candidates staged in LDS per pass
-constexpr int TILE_TGT = 64;     // targets per chunk
 
 // merged candidate runs of a stencil: [lo, hi) of the source array, with
 // exclusive offsets into the flattened candidate list
@@ -33,12 +30,12 @@ struct TileRuns {
   int n, total;
 };
 
-// Wavefront 0 of the workgroup: runs of the stencil of cell c in the
-// cell_start array cs, with offsets and total.
-__device__ __forceinline__ void tile_runs(const Cell& cell, int c, const int* cs, TileRuns* R) {
+// One wavefront: lanes below nr hold run [lo, hi); R gets the runs, their
+// exclusive offsets and the total.
+__device__ __forceinline__ void tile_scan_runs(int nr, int lo, int hi, TileRuns* R) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int nr = stencil_runs(cell, c, cs, R->lo, R->hi);
-  const int len = lane < nr ? R->hi[lane] - R->lo[lane] : 0;
+  const int len = lane < nr ? hi - lo : 0;
+  if (lane < nr) { R->lo[lane] = lo; R->hi[lane] = hi; }
   int incl = len;
   for (int o = 1; o < 32; o <<= 1) {
     const int t = __shfl_up(incl, o, WAVE);
@@ -47,6 +44,25 @@ __device__ __forceinline__ void tile_runs(const Cell& cell, int c, const int* cs
   if (lane < nr) R->off[lane] = incl - len;
   const int total = __shfl(incl, 31, WAVE);
   if (lane == 0) { R->n = nr; R->total = total; }
+}
+
+// runs of the stencil of cell c in the cell_start array cs
+__device__ __forceinline__ void tile_runs(const Cell& cell, int c, const int* cs, TileRuns* R) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int g0 = cell.grp_ptr[c], ng = cell.grp_ptr[c + 1] - g0;
+  int lo = 0, hi = 0;
+  if (lane < ng) { lo = cs[cell.grp_lo[g0 + lane]]; hi = cs[cell.grp_hi[g0 + lane]]; }
+  tile_scan_runs(ng, lo, hi, R);
+}
+
+// runs of the electrode atoms in reach of cell c (a fixed table)
+template <typename T>
+__device__ __forceinline__ void tile_elec_runs(const ElecSet<T>& el, int c, TileRuns* R) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int r0 = el.run_ptr[c], nr = el.run_ptr[c + 1] - r0;
+  int lo = 0, hi = 0;
+  if (lane < nr) { lo = el.run_lo[r0 + lane]; hi = el.run_hi[r0 + lane]; }
+  tile_scan_runs(nr, lo, hi, R);
 }
 
 // source index of flattened candidate k
@@ -111,8 +127,8 @@ __device__ __forceinline__ int tq_pop(const TileQ<T, NV>& q, int n) {
 // several times slower here)
 template <typename T, int NQ, int NV, int NACC>
 struct TileLds {
-  static constexpr size_t runs = 0;
-  static constexpr size_t cand = (sizeof(TileRuns) + 15) / 16 * 16;
+  static constexpr size_t runs = 0;           // two run lists (sites, electrodes)
+  static constexpr size_t cand = (2 * sizeof(TileRuns) + 15) / 16 * 16;
   static constexpr size_t cand_bytes = (size_t)TILE_CAND * (3 * sizeof(double) + NQ * sizeof(T) + sizeof(int));
   static constexpr size_t queue = cand + (cand_bytes + 15) / 16 * 16;
   static constexpr size_t queue_bytes = (TileQ<T, NV>::bytes() + 15) / 16 * 16;
@@ -151,107 +167,207 @@ struct TileMap {
 
 // ------------------------------------------------------------ site pairs
 
-// queued site pair of this lane: g0 force factor and pair potential added
-// to its target's accumulators
-template <typename T>
-__device__ __forceinline__ void tile_eval_g0(const TileQ<T, 4>& Q, int lane, T alpha, double* acc) {
-  constexpr int CAP = TileQ<T, 4>::CAP;
-  const T qx = Q.v[lane], qy = Q.v[CAP + lane], qz = Q.v[2 * CAP + lane], qa = Q.v[3 * CAP + lane];
-  const int tt = Q.t[lane];
-  T g, pot;
-  g0_terms(qx * qx + qy * qy + qz * qz, alpha, g, pot);
-  const T w = qa * g;
-  atomicAdd(acc + tt, (double)(w * qx));
-  atomicAdd(acc + TILE_TGT + tt, (double)(w * qy));
-  atomicAdd(acc + 2 * TILE_TGT + tt, (double)(w * qz));
-  atomicAdd(acc + 3 * TILE_TGT + tt, (double)(qa * pot));
+// queue entries: displacement (3), charge a, charge b
+template <typename T> using TileQ5 = TileQ<T, 5>;
+template <typename T> using PairLds = TileLds<T, 2, 5, 10>;
+// accumulators per target: 0-2 site-site force sum, 3 site-site potential,
+// 4-6 site-electrode force sum with charges a, 7-9 with charges b
+
+// One candidate phase of a target chunk: the candidates listed by R, staged
+// into C by stage(slot, source index), tested against the chunk's targets
+// (self pairs excluded when self_excl), pairs inside the cutoff evaluated by
+// eval(lane) 64 at a time.
+template <typename T, typename Stage, typename Eval>
+__device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const TileRuns* R, const TileMap& m, int j,
+                                           double xt, double yt, double zt, bool self_excl, const TileCand<T, 2>& C,
+                                           const TileQ5<T>& Q, Stage stage, Eval eval) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const bool no_img = (cell.img[0] | cell.img[1] | cell.img[2]) == 0;
+  for (int c0 = 0;; c0 += TILE_CAND) {
+    __syncthreads();
+    const int total = R->total;
+    const int nck = min(TILE_CAND, total - c0);
+    for (int k = threadIdx.x; k < nck; k += TILE_THREADS) stage(k, tile_src(R, c0 + k));
+    __syncthreads();
+    const int n_iter = nck > 0 ? (nck + m.nsl - 1) / m.nsl : 0;
+    int n = 0;
+    for (int it = 0; it < n_iter; ++it) {
+      const int k = m.sl + it * m.nsl;
+      const bool valid = m.act && k < nck;
+      double px = xt, py = yt, pz = zt;
+      T qa = 0, qb = 0;
+      int pk = -1;
+      if (valid) { px = C.x[k]; py = C.y[k]; pz = C.z[k]; qa = C.q[0][k]; qb = C.q[1][k]; pk = C.k[k]; }
+      const bool self_pk = self_excl && pk == j;
+      const Disp d = min_disp(cell, xt, yt, zt, px, py, pz);
+      if (no_img) {
+        T dx, dy, dz;
+        const bool in = image_pair(cell, d, 0, 0, 0, rc2, dx, dy, dz) && valid && !self_pk;
+        const T val[5] = {dx, dy, dz, qa, qb};
+        n = tq_push(Q, n, in, val, m.ti);
+        if (n >= WAVE) {
+          eval(lane);
+          n = tq_pop(Q, n);
+        }
+        continue;
+      }
+      for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
+        for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
+          for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
+            T dx, dy, dz;
+            const bool self = self_pk && ix == 0 && iy == 0 && iz == 0;
+            const bool in = image_pair(cell, d, ix, iy, iz, rc2, dx, dy, dz) && valid && !self;
+            const T val[5] = {dx, dy, dz, qa, qb};
+            n = tq_push(Q, n, in, val, m.ti);
+            if (n >= WAVE) {
+              eval(lane);
+              n = tq_pop(Q, n);
+            }
+          }
+    }
+    if (lane < n) eval(lane);
+    if (c0 + TILE_CAND >= total) break;
+  }
 }
 
-// Site-site sums of the targets [t_lo, t_hi) of cell c (a frame's sorted
+// Real-space sums of the targets [t_lo, t_hi) of cell c (a frame's sorted
 // sites): f_pair gets sum_j' Q_j' g0(r) r_vec (without k_e and Q_j), u_site
-// 1/2 k_e Q_j sum_j' Q_j' erfc(alpha r)/r.  lds: TileLds<T, 1, 4, 4>::total bytes.
+// 1/2 k_e Q_j sum_j' Q_j' erfc(alpha r)/r; with pa.f_elec also the
+// site-electrode sums sum_i q_i g1(r) r_vec for the charges qa and qb
+// (without k_e and Q_j).  lds: PairLds<T>::total bytes.
 template <typename T>
-__device__ __forceinline__ void site_pairs_tile(const Cell& cell, const SiteSet<T>& st, T alpha, double rc2,
-                                                double* __restrict__ f_pair, double* __restrict__ u_site, int c,
-                                                int t_lo, int t_hi, int frame, unsigned char* lds) {
-  using L = TileLds<T, 1, 4, 4>;
+__device__ __forceinline__ void site_pairs_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
+                                                unsigned char* lds) {
+  using L = PairLds<T>;
+  constexpr int CAP = TileQ5<T>::CAP;
+  const Cell& cell = pa.cell;
+  const SiteSet<T>& st = pa.st;
   TileRuns* R = reinterpret_cast<TileRuns*>(lds + L::runs);
-  TileCand<T, 1> C;
+  TileRuns* RE = R + 1;
+  TileCand<T, 2> C;
   C.bind(lds + L::cand);
-  TileQ<T, 4> Q;
+  TileQ5<T> Q;
   Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
-  double* acc = reinterpret_cast<double*>(lds + L::acc);     // [4][TILE_TGT]
-  const int lane = threadIdx.x & (WAVE - 1);
+  double* acc = reinterpret_cast<double*>(lds + L::acc);     // [10][TILE_TGT]
   const size_t fo = (size_t)frame * st.n;
   const int* cs = st.cell_start + (size_t)frame * (cell.n_cells + 1);
   const double* sx = st.x + fo; const double* sy = st.y + fo; const double* sz = st.z + fo;
   const double* sq = st.q + fo;
+  const bool elec = pa.f_elec != nullptr;
   if (threadIdx.x < WAVE) tile_runs(cell, c, cs, R);
-  const bool no_img = (cell.img[0] | cell.img[1] | cell.img[2]) == 0;
+  else if (elec && threadIdx.x < 2 * WAVE) tile_elec_runs(pa.el, c, RE);
+  const double* qa_e = elec ? pa.qa_s + (size_t)frame * pa.qa_stride : nullptr;
   for (int t0 = t_lo; t0 < t_hi; t0 += TILE_TGT) {
     const TileMap m(min(TILE_TGT, t_hi - t0));
     const int j = t0 + m.ti;
     const double xt = sx[j], yt = sy[j], zt = sz[j];
-    for (int i = threadIdx.x; i < 4 * TILE_TGT; i += TILE_THREADS) acc[i] = 0.0;
-    for (int c0 = 0;; c0 += TILE_CAND) {
-      __syncthreads();
-      const int total = R->total;
-      if (c0 >= total && c0 > 0) break;
-      const int nck = min(TILE_CAND, total - c0);
-      for (int k = threadIdx.x; k < nck; k += TILE_THREADS) {
-        const int s = tile_src(R, c0 + k);
-        C.x[k] = sx[s]; C.y[k] = sy[s]; C.z[k] = sz[s]; C.q[0][k] = (T)sq[s]; C.k[k] = s;
-      }
-      __syncthreads();
-      const int n_iter = (nck + m.nsl - 1) / m.nsl;
-      int n = 0;
-      for (int it = 0; it < n_iter; ++it) {
-        const int k = m.sl + it * m.nsl;
-        const bool valid = m.act && k < nck;
-        double px = xt, py = yt, pz = zt;
-        T pq = 0;
-        int pk = j;
-        if (valid) { px = C.x[k]; py = C.y[k]; pz = C.z[k]; pq = C.q[0][k]; pk = C.k[k]; }
-        const Disp d = min_disp(cell, xt, yt, zt, px, py, pz);
-        if (no_img) {
-          T dx, dy, dz;
-          const bool in = image_pair(cell, d, 0, 0, 0, rc2, dx, dy, dz) && valid && pk != j;
-          const T val[4] = {dx, dy, dz, pq};
-          n = tq_push(Q, n, in, val, m.ti);
-          if (n >= WAVE) {
-            tile_eval_g0(Q, lane, alpha, acc);
-            n = tq_pop(Q, n);
-          }
-          continue;
-        }
-        for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
-          for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
-            for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
-              T dx, dy, dz;
-              const bool self = pk == j && ix == 0 && iy == 0 && iz == 0;
-              const bool in = image_pair(cell, d, ix, iy, iz, rc2, dx, dy, dz) && valid && !self;
-              const T val[4] = {dx, dy, dz, pq};
-              n = tq_push(Q, n, in, val, m.ti);
-              if (n >= WAVE) {
-                tile_eval_g0(Q, lane, alpha, acc);
-                n = tq_pop(Q, n);
-              }
-            }
-      }
-      if (lane < n) tile_eval_g0(Q, lane, alpha, acc);
-      if (c0 + TILE_CAND >= total) break;
-    }
+    for (int i = threadIdx.x; i < 10 * TILE_TGT; i += TILE_THREADS) acc[i] = 0.0;
+    // sites: g0 force factor and pair potential
+    tile_phase<T>(cell, pa.rc2, R, m, j, xt, yt, zt, true, C, Q,
+                  [&](int k, int s) {
+                    C.x[k] = sx[s]; C.y[k] = sy[s]; C.z[k] = sz[s];
+                    C.q[0][k] = (T)sq[s]; C.q[1][k] = (T)0; C.k[k] = s;
+                  },
+                  [&](int l) {
+                    const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l], qa = Q.v[3 * CAP + l];
+                    const int tt = Q.t[l];
+                    T g, pot;
+                    g0_terms(qx * qx + qy * qy + qz * qz, pa.alpha, g, pot);
+                    const T w = qa * g;
+                    atomicAdd(acc + tt, (double)(w * qx));
+                    atomicAdd(acc + TILE_TGT + tt, (double)(w * qy));
+                    atomicAdd(acc + 2 * TILE_TGT + tt, (double)(w * qz));
+                    atomicAdd(acc + 3 * TILE_TGT + tt, (double)(qa * pot));
+                  });
+    // electrode atoms: g1 force factor for both charge sets
+    if (elec)
+      tile_phase<T>(cell, pa.rc2, RE, m, j, xt, yt, zt, false, C, Q,
+                    [&](int k, int s) {
+                      C.x[k] = pa.el.x[s]; C.y[k] = pa.el.y[s]; C.z[k] = pa.el.z[s];
+                      C.q[0][k] = (T)qa_e[s]; C.q[1][k] = pa.qb_s ? (T)pa.qb_s[s] : (T)0; C.k[k] = -1;
+                    },
+                    [&](int l) {
+                      const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l];
+                      const T qa = Q.v[3 * CAP + l], qb = Q.v[4 * CAP + l];
+                      const int tt = Q.t[l];
+                      const T g = g1_force(qx * qx + qy * qy + qz * qz, pa.alpha, pa.eta);
+                      const T wa = qa * g, wb = qb * g;
+                      atomicAdd(acc + 4 * TILE_TGT + tt, (double)(wa * qx));
+                      atomicAdd(acc + 5 * TILE_TGT + tt, (double)(wa * qy));
+                      atomicAdd(acc + 6 * TILE_TGT + tt, (double)(wa * qz));
+                      atomicAdd(acc + 7 * TILE_TGT + tt, (double)(wb * qx));
+                      atomicAdd(acc + 8 * TILE_TGT + tt, (double)(wb * qy));
+                      atomicAdd(acc + 9 * TILE_TGT + tt, (double)(wb * qz));
+                    });
     __syncthreads();
     if ((int)threadIdx.x < m.ntc) {
       const int jj = t0 + threadIdx.x;
-      double* o = f_pair + (size_t)frame * 3 * st.n;
+      double* o = pa.f_pair + (size_t)frame * 3 * st.n;
       o[jj] = acc[threadIdx.x];
       o[st.n + jj] = acc[TILE_TGT + threadIdx.x];
       o[2 * (size_t)st.n + jj] = acc[2 * TILE_TGT + threadIdx.x];
-      if (u_site) u_site[fo + jj] = 0.5 * KE * sq[jj] * acc[3 * TILE_TGT + threadIdx.x];
+      if (pa.u_site) pa.u_site[fo + jj] = 0.5 * KE * sq[jj] * acc[3 * TILE_TGT + threadIdx.x];
+      if (elec) {
+        double* e = pa.f_elec + (size_t)frame * 6 * st.n;
+#pragma unroll
+        for (int u = 0; u < 6; ++u) e[(size_t)u * st.n + jj] = acc[(4 + u) * TILE_TGT + threadIdx.x];
+      }
     }
     __syncthreads();
   }
+}
+
+// Real-space electrolyte potential at the electrode atoms of one work item
+// (atoms [t_lo, t_hi) of cell c, t_hi - t_lo <= TILE_TGT):
+// k_e sum_j Q_j g1(r) over the sites of the stencil.  lds: PairLds<T>::total.
+template <typename T>
+__device__ __forceinline__ void real_b_tile(const RealBArgs<T>& rb, int c, int t_lo, int t_hi, int frame,
+                                            unsigned char* lds) {
+  using L = PairLds<T>;
+  constexpr int CAP = TileQ5<T>::CAP;
+  const SiteSet<T>& st = rb.st;
+  TileRuns* R = reinterpret_cast<TileRuns*>(lds + L::runs);
+  TileCand<T, 2> C;
+  C.bind(lds + L::cand);
+  TileQ5<T> Q;
+  Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
+  double* acc = reinterpret_cast<double*>(lds + L::acc);
+  const size_t fo = (size_t)frame * st.n;
+  const int* cs = st.cell_start + (size_t)frame * (rb.cell.n_cells + 1);
+  const double* sx = st.x + fo; const double* sy = st.y + fo; const double* sz = st.z + fo;
+  const double* sq = st.q + fo;
+  if (threadIdx.x < WAVE) tile_runs(rb.cell, c, cs, R);
+  const TileMap m(t_hi - t_lo);
+  const int g = t_lo + m.ti;
+  const double xt = rb.el.x[g], yt = rb.el.y[g], zt = rb.el.z[g];
+  for (int i = threadIdx.x; i < TILE_TGT; i += TILE_THREADS) acc[i] = 0.0;
+  tile_phase<T>(rb.cell, rb.rc2, R, m, -1, xt, yt, zt, false, C, Q,
+                [&](int k, int s) {
+                  C.x[k] = sx[s]; C.y[k] = sy[s]; C.z[k] = sz[s];
+                  C.q[0][k] = (T)sq[s]; C.q[1][k] = (T)0; C.k[k] = s;
+                },
+                [&](int l) {
+                  atomicAdd(acc + Q.t[l], (double)g1_potential(Q.v[l], Q.v[CAP + l], Q.v[2 * CAP + l],
+                                                               Q.v[3 * CAP + l], rb.alpha, rb.eta));
+                });
+  __syncthreads();
+  if ((int)threadIdx.x < m.ntc) {
+    const int gg = t_lo + threadIdx.x;
+    rb.phi_out[(size_t)frame * rb.el.n + rb.el.orig[gg]] = (T)(KE * acc[threadIdx.x]);
+  }
+}
+
+// workgroup b of a frame's real-space b work
+template <typename T>
+__device__ __forceinline__ void real_b_block(const RealBArgs<T>& rb, int b, int frame, unsigned char* lds) {
+  if (!rb.tiles) {
+    const int g = b * (TILE_THREADS / WAVE) + (threadIdx.x >> 6);
+    if (g < rb.el.n)
+      real_b_wave(rb.cell, rb.alpha, rb.eta, rb.rc2, rb.el, rb.st, rb.phi_out, g, frame,
+                  reinterpret_cast<T*>(lds + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
+    return;
+  }
+  real_b_tile(rb, rb.item_c[b], rb.item_lo[b], rb.item_hi[b], frame, lds);
 }
 
 // workgroup b of a frame's site-pair work: with tsplit > 0, share b mod
@@ -272,7 +388,7 @@ __device__ __forceinline__ void site_pairs_block(const PairArgs<T>& pa, int b, i
   const int lo = cs[c], n = cs[c + 1] - lo;
   const int t_lo = lo + (int)(((long long)n * s) / pa.tsplit);
   const int t_hi = lo + (int)(((long long)n * (s + 1)) / pa.tsplit);
-  site_pairs_tile(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, c, t_lo, t_hi, frame, lds);
+  site_pairs_tile(pa, c, t_lo, t_hi, frame, lds);
 }
 
 }  // namespace cpm

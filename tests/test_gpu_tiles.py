@@ -5,7 +5,9 @@ path (one wavefront per target):
   * sites crowded into one slab: a cell holds more targets than one tile
     chunk (64) and a stencil more candidates than one LDS pass (512);
   * the tiny cell run with PPPM: cells narrower than 2 rcut, so every pair
-    test loops over periodic images.
+    test loops over periodic images;
+  * a batch large enough for the frames-per-launch tuner, whose frames land
+    in several launches.
 
 Bars: charges within 1e-6 e, forces within 1e-4 relative RMS of the oracle;
 batched and single-frame GPU results within rounding of each other.
@@ -122,3 +124,41 @@ def test_batch_tiles_with_periodic_images(torch_dev, geometry):
     from workloads import perturbed_frames
     frames = perturbed_frames(w, 4, sigma=0.05, seed=8)
     run_batch_case(torch_dev, w, A, S, frames, np.array([0.0, 1.0, 2.0]), ((0, 2), (3, 1)))
+
+
+def test_batch_size_tuner_keeps_results(torch_dev):
+    """A batch large enough to tune the frames per launch: the chosen size is
+    one of the candidates, and frames that fall in different launches match
+    the single-frame path."""
+    torch = torch_dev
+    from paper_2201_12963_amd import Context
+    from paper_2201_12963_amd.binding import BUF_BATCH_CHUNK
+    from workloads import perturbed_frames
+    _say("[gpu] batch size tuner: paper ff, 200 frames")
+    w, A, S = built("paper", "ff")
+    frames = perturbed_frames(w, 200, sigma=0.05, seed=13)
+    dvs = np.array([0.0, 2.0])
+    stream = torch.cuda.Stream()
+    ctx = Context.from_workload(w, stream=stream)
+    ctx.build_elastance()
+    assert int(ctx.get_buffer(BUF_BATCH_CHUNK)[0]) == 0
+    X = torch.tensor(frames, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        Qb, Fb, Eb = ctx.solve_batch(X, dvs)
+    stream.synchronize()
+    assert ctx.sync_status() == 0
+    chunk = int(ctx.get_buffer(BUF_BATCH_CHUNK)[0])
+    _say(f"    frames per launch {chunk}")
+    assert chunk in (64, 128)
+    Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
+    for fi in (0, chunk - 1, chunk, 199):
+        x = torch.tensor(frames[fi], dtype=torch.float64, device="cuda")
+        for vi, dv in enumerate(dvs):
+            with torch.cuda.stream(stream):
+                q, f, e = ctx.solve(x, float(dv))
+            stream.synchronize()
+            q, f, e = q.cpu().numpy(), f.cpu().numpy(), e.cpu().numpy()
+            assert np.abs(Qb[fi, vi] - q).max() < 1e-11
+            assert rel_rms(Fb[fi, vi], f) < 1e-10
+            assert np.abs(Eb[fi, vi] - e).max() < 1e-9 * np.abs(e).max()
+    ctx.close()
