@@ -52,33 +52,37 @@ def count_pairs(a, b, box, rcut, same=False):
     return n
 
 
-def kernel_work(w, name):
-    """(bound, algorithmic work per launch, unit) of one step kernel for workload w."""
+def kernel_work(w, name, n_frames=1):
+    """(bound, algorithmic work of one launch over n_frames frames, unit) of a
+    step kernel.  Bytes count frame-independent tables (S, S c, electrode
+    stencils, the influence function) once per launch and per-frame data
+    once per frame; FLOP counts are per frame."""
     P3 = w.order ** 3
     M = int(np.prod(w.mesh))
     ne, nl = w.n_elec, w.n_site
     if name == "site_pairs":
         pg0 = count_pairs(w.site_xyz, w.site_xyz, w.box, w.rcut, same=True)
-        return "alu", pg0 * FLOPS_PAIR_G0, "TFLOP/s"
+        return "alu", n_frames * pg0 * FLOPS_PAIR_G0, "TFLOP/s"
     if name == "site_forces":
         pg1 = count_pairs(w.site_xyz, w.elec_xyz, w.box, w.rcut)
-        return "alu", pg1 * FLOPS_PAIR_G1 + nl * P3 * 6, "TFLOP/s"
+        return "alu", n_frames * (pg1 * FLOPS_PAIR_G1 + nl * P3 * 6), "TFLOP/s"
     if name == "real_b":
-        return "alu", count_pairs(w.elec_xyz, w.site_xyz, w.box, w.rcut) * FLOPS_PAIR_B, "TFLOP/s"
-    if name == "charges":
-        return "hbm", 8 * ne * ne + 8 * 3 * ne, "GB/s"
-    if name.startswith("fft_z"):
-        # complex mesh read and written once (+ influence function read)
-        return "hbm", M * (16 * 2 + 8), "GB/s"
-    if name.startswith("fft_xy"):
-        return "hbm", M * (8 + 16), "GB/s"
-    if name == "spread_elec":
-        return "hbm", ne * 8 + ne * P3 * 12 + M * 8, "GB/s"
-    if name == "gather_b":
-        return "hbm", ne * P3 * 12 + M * 8 + ne * 16, "GB/s"
-    if name == "bin":
-        return "hbm", nl * (24 + 8) + nl * (32 + 4) + M * 8, "GB/s"
-    return "hbm", ne * 8 * 6 + nl * 8, "GB/s"
+        return "alu", n_frames * count_pairs(w.elec_xyz, w.site_xyz, w.box, w.rcut) * FLOPS_PAIR_B, "TFLOP/s"
+    if name == "charges":           # S streamed once; b read, Q0 and q written per frame
+        return "hbm", 8 * ne * ne + n_frames * 8 * 3 * ne, "GB/s"
+    if name.startswith("fft_z"):    # complex mesh read and written (+ G once)
+        return "hbm", M * 8 + n_frames * M * 16 * 2, "GB/s"
+    if name.startswith("fft_xy"):   # real plane in, complex plane out (or back)
+        return "hbm", n_frames * M * (8 + 16), "GB/s"
+    if name == "spread_elec":       # stencil table once; q read, mesh written per frame
+        return "hbm", ne * P3 * 12 + n_frames * (ne * 8 + M * 8), "GB/s"
+    if name == "gather_b":          # stencil table once; mesh read, b written per frame
+        return "hbm", ne * P3 * 12 + n_frames * (M * 8 + ne * 16), "GB/s"
+    if name == "bin":               # positions and charges in; sorted copies, order and the
+        #                             wrapped-coordinate scratch (written and read back) out
+        return "hbm", n_frames * nl * (32 + 36 + 48), "GB/s"
+    # energy: S c, c, d, z once; Q0 and b per frame, the site energies per frame
+    return "hbm", ne * 8 * 4 + n_frames * (ne * 16 + nl * 8), "GB/s"
 
 
 def make_ctx(torch, w, precision=0):
@@ -161,8 +165,7 @@ def per_kernel_roofline(w, kernel_ms, n_frames=1):
     work of its own body x n_frames over its average duration)."""
     out = {}
     for name, ms in kernel_ms.items():
-        bound, work, unit = kernel_work(w, name)
-        work *= n_frames
+        bound, work, unit = kernel_work(w, name, n_frames)
         if bound == "hbm":
             achieved, peak = work / (ms * 1e-3) / 1e9, HBM_PEAK_GBS
         else:
@@ -183,7 +186,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 404448, "sources_sha256": "8db19d257e2174c2ed492f636619aa26fc04c39959400242eb6387c4487134b0"}}
+TRAFFIC = {"site_pairs": {"bytes": 445696, "sources_sha256": "56774de942c99d45a2067028abeb1afa2eddf4e5be5b0f2177ae1e5e1c57b1e1"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 

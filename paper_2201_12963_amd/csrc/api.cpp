@@ -185,15 +185,16 @@ double wrap_host(double x, double L) { return x - L * std::floor(x / L); }
 
 // Stencil groups of every cell of the grid: the distinct neighbour cells
 // (offsets -1, 0, 1 per axis, fewer where the axis has under 3 cells),
-// sorted and joined into runs of consecutive cell indices [lo, hi).
-void stencil_groups(const Cell& cl, std::vector<int>& ptr, std::vector<int>& lo, std::vector<int>& hi) {
-  ptr.assign(1, 0);
-  lo.clear();
-  hi.clear();
-  auto count = [](int n) { return n >= 3 ? 3 : n; };
-  auto nb = [](int c, int s, int n) {
-    if (n >= 3) { int v = c + s - 1; return v < 0 ? v + n : (v >= n ? v - n : v); }
-    return (c + s) % n;
+// sorted and joined into runs of consecutive cell indices [lo, hi); n[c]
+// groups per cell at [c * STENCIL_MAX + k] (unused entries 0).
+void stencil_groups(const Cell& cl, std::vector<int>& n, std::vector<int>& lo, std::vector<int>& hi) {
+  n.assign(cl.n_cells, 0);
+  lo.assign((size_t)cl.n_cells * STENCIL_MAX, 0);
+  hi.assign((size_t)cl.n_cells * STENCIL_MAX, 0);
+  auto count = [](int m) { return m >= 3 ? 3 : m; };
+  auto nb = [](int c, int s, int m) {
+    if (m >= 3) { int v = c + s - 1; return v < 0 ? v + m : (v >= m ? v - m : v); }
+    return (c + s) % m;
   };
   for (int c = 0; c < cl.n_cells; ++c) {
     const int cx = c % cl.nc[0], cy = (c / cl.nc[0]) % cl.nc[1], cz = c / (cl.nc[0] * cl.nc[1]);
@@ -204,11 +205,15 @@ void stencil_groups(const Cell& cl, std::vector<int>& ptr, std::vector<int>& lo,
           cells.push_back((nb(cz, a, cl.nc[2]) * cl.nc[1] + nb(cy, b, cl.nc[1])) * cl.nc[0] + nb(cx, d, cl.nc[0]));
     std::sort(cells.begin(), cells.end());
     cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
-    for (size_t k = 0; k < cells.size(); ++k) {
-      if (k == 0 || cells[k] != cells[k - 1] + 1) { lo.push_back(cells[k]); hi.push_back(cells[k] + 1); }
-      else hi.back() = cells[k] + 1;
+    int k = -1;
+    for (size_t t = 0; t < cells.size(); ++t) {
+      if (t == 0 || cells[t] != cells[t - 1] + 1) {
+        ++k;
+        lo[(size_t)c * STENCIL_MAX + k] = cells[t];
+      }
+      hi[(size_t)c * STENCIL_MAX + k] = cells[t] + 1;
     }
-    ptr.push_back((int)lo.size());
+    n[c] = k + 1;
   }
 }
 
@@ -843,12 +848,12 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     cl.img[k] = (int)std::floor(c->rcut / c->box[k] + 0.5);
     cl.n_cells *= cl.nc[k];
   }
-  std::vector<int> gptr, glo, ghi;
-  stencil_groups(cl, gptr, glo, ghi);
+  std::vector<int> gn, glo, ghi;
+  stencil_groups(cl, gn, glo, ghi);
   {
-    int *dp, *dl, *dh;
-    if ((r = upload(c, &dp, gptr)) || (r = upload(c, &dl, glo)) || (r = upload(c, &dh, ghi))) return bad(r);
-    cl.grp_ptr = dp; cl.grp_lo = dl; cl.grp_hi = dh;
+    int *dn, *dl, *dh;
+    if ((r = upload(c, &dn, gn)) || (r = upload(c, &dl, glo)) || (r = upload(c, &dh, ghi))) return bad(r);
+    cl.grp_n = dn; cl.grp_lo = dl; cl.grp_hi = dh;
   }
   c->cell_b = cl;
   for (int k = 0; k < 3; ++k) c->cell_b.img[k] = (int)std::floor(c->rcut_b / c->box[k] + 0.5);
@@ -910,22 +915,23 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     return bad(r);
   // electrode atoms in reach of every cell: the stencil groups' ranges of
   // the sorted atoms, empty ones dropped and adjacent ones joined
-  std::vector<int> rptr(1, 0), rlo, rhi;
+  std::vector<int> rn(cl.n_cells, 0), rlo((size_t)cl.n_cells * STENCIL_MAX, 0), rhi((size_t)cl.n_cells * STENCIL_MAX, 0);
   for (int cc2 = 0; cc2 < cl.n_cells; ++cc2) {
-    const size_t first = rlo.size();
-    for (int g = gptr[cc2]; g < gptr[cc2 + 1]; ++g) {
-      const int lo = ecs[glo[g]], hi = ecs[ghi[g]];
+    int k = 0;
+    const size_t base = (size_t)cc2 * STENCIL_MAX;
+    for (int g = 0; g < gn[cc2]; ++g) {
+      const int lo = ecs[glo[base + g]], hi = ecs[ghi[base + g]];
       if (hi <= lo) continue;
-      if (rlo.size() > first && rhi.back() == lo) rhi.back() = hi;
-      else { rlo.push_back(lo); rhi.push_back(hi); }
+      if (k > 0 && rhi[base + k - 1] == lo) rhi[base + k - 1] = hi;
+      else { rlo[base + k] = lo; rhi[base + k] = hi; ++k; }
     }
-    rptr.push_back((int)rlo.size());
+    rn[cc2] = k;
   }
   {
     double *x, *y, *z; int *o, *ce, *cs, *rp, *rl, *rh;
     if ((r = upload(c, &x, sxe)) || (r = upload(c, &y, sye)) || (r = upload(c, &z, sze)) ||
         (r = upload(c, &o, eorder)) || (r = upload(c, &ce, ecell_sorted)) || (r = upload(c, &cs, ecs)) ||
-        (r = upload(c, &rp, rptr)) || (r = upload(c, &rl, rlo)) || (r = upload(c, &rh, rhi)))
+        (r = upload(c, &rp, rn)) || (r = upload(c, &rl, rlo)) || (r = upload(c, &rh, rhi)))
       return bad(r);
     c->el = ElecSet<double>{x, y, z, o, ce, cs, ne, rp, rl, rh};
     c->elf = ElecSet<float>{x, y, z, o, ce, cs, ne, rp, rl, rh};

@@ -12,6 +12,7 @@ constexpr double KE = 1.43996454784;   // eV nm / e^2
 constexpr int WAVE = 64;
 constexpr int MAX_FFT_FACTORS = 12;
 constexpr int MAX_ORDER = 7;
+constexpr int STENCIL_MAX = 27;   // neighbour cells of a cell, itself included
 // cell tiles of the real-space sums: workgroup size, candidates staged in
 // LDS per pass, targets per chunk
 constexpr int TILE_THREADS = 256;
@@ -28,10 +29,11 @@ struct Cell {          // periodic orthorhombic cell and its cell-list grid
   int n_cells;
   // stencil of every cell (device tables, fixed by the grid): the distinct
   // neighbour cells sorted and joined into groups of consecutive cell
-  // indices [grp_lo, grp_hi); groups grp_ptr[c] .. grp_ptr[c+1]-1 (at most
-  // 27) belong to cell c.  A group's members are one contiguous index range
-  // [cs[grp_lo], cs[grp_hi]) of any cell-sorted array with cell_start cs.
-  const int* grp_ptr;
+  // indices [lo, hi); cell c has grp_n[c] <= STENCIL_MAX groups, at
+  // grp_lo/grp_hi[c * STENCIL_MAX + k] (a fixed stride, so the groups are read
+  // in the same step as their count).  A group's members are one contiguous
+  // index range [cs[lo], cs[hi]) of any cell-sorted array with cell_start cs.
+  const int* grp_n;
   const int* grp_lo;
   const int* grp_hi;
 };
@@ -194,9 +196,10 @@ struct ElecSet {       // cell-sorted electrode atoms (static), FP64 positions
   const double* x; const double* y; const double* z;
   const int* orig; const int* cell; const int* cell_start;
   int n;
-  // electrode atoms in reach of every cell: index runs [run_lo, run_hi) of
-  // the sorted atoms, runs run_ptr[c] .. run_ptr[c+1]-1 (non-empty only)
-  const int* run_ptr; const int* run_lo; const int* run_hi;
+  // electrode atoms in reach of every cell: run_n[c] <= STENCIL_MAX index
+  // runs [run_lo, run_hi) of the sorted atoms at [c * STENCIL_MAX + k]
+  // (non-empty only)
+  const int* run_n; const int* run_lo; const int* run_hi;
 };
 
 template <typename T>

@@ -257,6 +257,7 @@ __global__ __launch_bounds__(256) void k_charges(int n, const double* __restrict
   const int frame = blockIdx.y;
   if (i >= n) return;
   const double* b = b_all + (size_t)frame * n;
+  const int ep = qs_all ? epos[i] : 0;      // read now, used at the end
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if ((n & 1) == 0) {       // rows are 16-byte aligned: stream them as double2
     const double2* row = reinterpret_cast<const double2*>(S + (size_t)i * n);
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(256) void k_charges(int n, const double* __restrict
     const double qv = acc + dv * Sc[i];
     if (Q0_all) Q0_all[o] = acc;
     if (q_all) q_all[o] = qv;
-    if (qs_all) qs_all[(size_t)frame * n + epos[i]] = qv;      // cell-sorted copy
+    if (qs_all) qs_all[(size_t)frame * n + ep] = qv;      // cell-sorted copy
   }
 }
 

@@ -109,10 +109,12 @@ static_assert(pair_queue_lds<float>() == 4 * wave_scratch_bytes<float>(),
 // returned count write [rlo, rhi).
 __device__ __forceinline__ int stencil_runs(const Cell& cell, int c, const int* cs, int* rlo, int* rhi) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int g0 = cell.grp_ptr[c], ng = cell.grp_ptr[c + 1] - g0;
+  const int ng = cell.grp_n[c];
+  int glo = 0, ghi = 0;
+  if (lane < STENCIL_MAX) { glo = cell.grp_lo[c * STENCIL_MAX + lane]; ghi = cell.grp_hi[c * STENCIL_MAX + lane]; }
   if (lane < ng) {
-    rlo[lane] = cs[cell.grp_lo[g0 + lane]];
-    rhi[lane] = cs[cell.grp_hi[g0 + lane]];
+    rlo[lane] = cs[glo];
+    rhi[lane] = cs[ghi];
   }
   __builtin_amdgcn_wave_barrier();
   return ng;
@@ -131,10 +133,12 @@ __device__ __forceinline__ int site_cell(const Cell& cell, double x, double y, d
 template <typename T>
 __device__ __forceinline__ int elec_runs(const ElecSet<T>& el, int c, int* rlo, int* rhi) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int r0 = el.run_ptr[c], nr = el.run_ptr[c + 1] - r0;
+  const int nr = el.run_n[c];
+  int lo = 0, hi = 0;
+  if (lane < STENCIL_MAX) { lo = el.run_lo[c * STENCIL_MAX + lane]; hi = el.run_hi[c * STENCIL_MAX + lane]; }
   if (lane < nr) {
-    rlo[lane] = el.run_lo[r0 + lane];
-    rhi[lane] = el.run_hi[r0 + lane];
+    rlo[lane] = lo;
+    rhi[lane] = hi;
   }
   __builtin_amdgcn_wave_barrier();
   return nr;

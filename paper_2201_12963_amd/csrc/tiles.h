@@ -49,9 +49,9 @@ __device__ __forceinline__ void tile_scan_runs(int nr, int lo, int hi, TileRuns*
 // runs of the stencil of cell c in the cell_start array cs
 __device__ __forceinline__ void tile_runs(const Cell& cell, int c, const int* cs, TileRuns* R) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int g0 = cell.grp_ptr[c], ng = cell.grp_ptr[c + 1] - g0;
+  const int ng = cell.grp_n[c];
   int lo = 0, hi = 0;
-  if (lane < ng) { lo = cs[cell.grp_lo[g0 + lane]]; hi = cs[cell.grp_hi[g0 + lane]]; }
+  if (lane < ng) { lo = cs[cell.grp_lo[c * STENCIL_MAX + lane]]; hi = cs[cell.grp_hi[c * STENCIL_MAX + lane]]; }
   tile_scan_runs(ng, lo, hi, R);
 }
 
@@ -59,9 +59,9 @@ __device__ __forceinline__ void tile_runs(const Cell& cell, int c, const int* cs
 template <typename T>
 __device__ __forceinline__ void tile_elec_runs(const ElecSet<T>& el, int c, TileRuns* R) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int r0 = el.run_ptr[c], nr = el.run_ptr[c + 1] - r0;
+  const int nr = el.run_n[c];
   int lo = 0, hi = 0;
-  if (lane < nr) { lo = el.run_lo[r0 + lane]; hi = el.run_hi[r0 + lane]; }
+  if (lane < nr) { lo = el.run_lo[c * STENCIL_MAX + lane]; hi = el.run_hi[c * STENCIL_MAX + lane]; }
   tile_scan_runs(nr, lo, hi, R);
 }
 
