@@ -331,7 +331,7 @@ int alloc_frames(cpm_ctx* c, int nf) {
   TRY(dalloc(c, &c->d_energy_tmp, (size_t)nf * 2));
   if (c->kspace == CPM_KSPACE_PPPM) {
     const size_t M = c->mi.M;
-    c->n_ek = c->za_pot.Ky * c->za_pot.nchunk;
+    c->n_ek = c->za_pot.n_blocks;
     TRY(dalloc(c, &c->d_ek, (size_t)nf * c->n_ek));
     if (!mixed) {
       TRY(dalloc(c, &c->d_rho, nf * M));
@@ -983,22 +983,17 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       fail(c, CPM_EINVAL, "x-y mesh plane too large for LDS");
       return bad(CPM_EINVAL);
     }
-    // z pass: columns per workgroup bounded by LDS (3 buffers) and by the
-    // register prefetch of the multiplier (ZPASS_MAX_POINTS), and chosen so
-    // that there are at least ~64 workgroups per frame
+    // z pass: one wavefront per (x, y) column, up to 4 per workgroup, each
+    // with three lines of Kz points in LDS (plus the shared twiddles)
     if (mi.K[2] > ZPASS_MAX_POINTS) {
       fail(c, CPM_EINVAL, "mesh has more than %d points along z", ZPASS_MAX_POINTS);
       return bad(CPM_EINVAL);
     }
-    int maxc = (int)std::max<size_t>(1, (96 * 1024) / (3 * mi.K[2] * elt));
-    maxc = std::min(maxc, ZPASS_MAX_POINTS / mi.K[2]);
-    int nchunk = std::max((mi.K[0] + maxc - 1) / maxc, (64 + mi.K[1] - 1) / mi.K[1]);
-    nchunk = std::min(nchunk, mi.K[0]);
-    int nxc = (mi.K[0] + nchunk - 1) / nchunk;
-    nchunk = (mi.K[0] + nxc - 1) / nxc;
+    const int cpw = (int)std::max<size_t>(1, std::min<size_t>(4, ((150 * 1024) / elt - mi.K[2]) / (3 * (size_t)mi.K[2])));
     ZPassArgs za{};
     za.Kx = mi.K[0]; za.Ky = mi.K[1]; za.Kz = mi.K[2];
-    za.nxc = nxc; za.nchunk = nchunk;
+    za.cpw = cpw;
+    za.n_blocks = (mi.K[0] * mi.K[1] + cpw - 1) / cpw;
     for (int k = 0; k < 3; ++k) za.twopi_L[k] = 2 * M_PI / c->box[k];
     za.mode = 0;
     c->za_pot = za;

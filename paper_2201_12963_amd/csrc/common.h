@@ -290,15 +290,16 @@ struct PairArgs {
   double* f_elec;
 };
 
-// points (columns x Kz) of one z-pass workgroup: 256 threads hold up to 8
-// values each of the prefetched multiplier
+// z pass: a lane prefetches the multiplier (and saved spectrum) of the
+// first ZPASS_PREFETCH of its column's points into registers, the rest is
+// read when used; columns of at most ZPASS_MAX_POINTS points
 constexpr int ZPASS_PREFETCH = 8;
-constexpr int ZPASS_MAX_POINTS = 256 * ZPASS_PREFETCH;
+constexpr int ZPASS_MAX_POINTS = 2048;
 
 struct ZPassArgs {
   int Kx, Ky, Kz;
-  int nxc;                 // columns per workgroup
-  int nchunk;              // x chunks per y row
+  int cpw;                 // (x, y) columns per workgroup, one wavefront each (<= 4)
+  int n_blocks;            // workgroups per frame: ceil(Kx Ky / cpw)
   int mode;                // 0: potential, 1: field (ik)
   double twopi_L[3];       // 2 pi / L_d
 };

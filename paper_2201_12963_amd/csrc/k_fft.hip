@@ -16,10 +16,12 @@
 //     ik differentiation), transforms back along z, and writes in place.
 // A round trip real mesh -> potential (or field) mesh is therefore
 // fft_xy(forward) -> fft_z -> fft_xy(inverse).  Mesh layout [z][y][x].
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 #include "bin.h"
 #include "pairs.h"
-#include "tiles.h"
 
 namespace cpm {
 
@@ -134,6 +136,59 @@ __device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nli
       default: fft_stage<5>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
     }
     __syncthreads();
+    T2* t = src; src = dst; dst = t;
+    Ns *= R;
+  }
+  return src;
+}
+
+// One Stockham stage of radix R over one contiguous line, by the lanes of
+// one wavefront (no workgroup barrier; the caller orders the stages)
+template <int R, typename T2>
+__device__ __forceinline__ void fft_stage_w(const T2* src, T2* dst, int N, int Ns, const T2* tw, int sigma) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int nb = N / R;
+  const int tstep = N / (Ns * R);
+  for (int j = lane; j < nb; j += WAVE) {
+    T2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+    const int k = j % Ns;
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        T2 w = tw[r * k * tstep];
+        if (sigma > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    small_dft<R>(v, sigma);
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+  }
+}
+
+// Transform one line of p.n points held in a wavefront's own LDS buffer a,
+// ping-ponging with b; the stages are ordered by wavefront barriers only
+// (a wavefront's LDS operations complete in order).  Returns the buffer
+// holding the result.
+template <typename T2>
+__device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int sigma) {
+  const int N = p.n;
+  T2* src = a;
+  T2* dst = b;
+  int Ns = 1;
+  __builtin_amdgcn_wave_barrier();
+  for (int f = 0; f < p.nfac; ++f) {
+    const int R = p.fac[f];
+    switch (R) {
+      case 2: fft_stage_w<2>(src, dst, N, Ns, tw, sigma); break;
+      case 3: fft_stage_w<3>(src, dst, N, Ns, tw, sigma); break;
+      case 4: fft_stage_w<4>(src, dst, N, Ns, tw, sigma); break;
+      default: fft_stage_w<5>(src, dst, N, Ns, tw, sigma); break;
+    }
+    __builtin_amdgcn_wave_barrier();
     T2* t = src; src = dst; dst = t;
     Ns *= R;
   }
@@ -334,114 +389,109 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
   if ((int)blockIdx.x >= n_z_blocks) {
     // hosted work, one wavefront per target: the real-space part of b
     // (electrode atoms), then the site-site forces (sites)
+    // (hosted work is always the one-wavefront-per-target form; the launcher
+    // checks that)
     const int hb = (int)blockIdx.x - n_z_blocks;
+    T* qbuf = reinterpret_cast<T*>(smem + (threadIdx.x >> 6) * wave_scratch_bytes<T>());
     if (hb < rb.n_blocks) {
-      real_b_block(rb, xcd_block(hb, rb.n_blocks), blockIdx.y, smem);
+      const int g = xcd_block(hb, rb.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+      if (g < rb.el.n) real_b_wave(rb.cell, rb.alpha, rb.eta, rb.rc2, rb.el, rb.st, rb.phi_out, g, blockIdx.y, qbuf);
     } else {
-      site_pairs_block(pa, xcd_block(hb - rb.n_blocks, pa.n_blocks), blockIdx.y, smem);
+      const int j = xcd_block(hb - rb.n_blocks, pa.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
+      if (j < pa.st.n) site_pairs_wave(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, j, blockIdx.y, qbuf);
     }
     return;
   }
+  // one wavefront per (x, y) column of Kz points, za.cpw columns per
+  // workgroup; each wavefront has its own three LDS lines and synchronises
+  // only with itself
   const int Kx = za.Kx, Ky = za.Ky, Kz = za.Kz;
-  const int y = blockIdx.x / za.nchunk;
-  const int x0 = (blockIdx.x - y * za.nchunk) * za.nxc;
-  const int nc = min(za.nxc, Kx - x0);
-  const int NL = nc * Kz;
-  T2* A = reinterpret_cast<T2*>(smem);
-  T2* B = A + za.nxc * Kz;
-  T2* C = B + za.nxc * Kz;
-  T2* twz = C + za.nxc * Kz;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+  T2* twz = reinterpret_cast<T2*>(smem);
+  T2* A = twz + Kz + (size_t)wv * 3 * Kz;
+  T2* B = A + Kz;
+  T2* C = B + Kz;
   load_twiddles(pz, twz);
+  const int col = blockIdx.x * za.cpw + wv;
+  const bool active = wv < za.cpw && col < Kx * Ky;
+  const int y = active ? col / Kx : 0, x = active ? col - y * Kx : 0;
   const size_t fo = (size_t)blockIdx.y * Kx * Ky * Kz;
-  // LDS layout [z][c]: lines along z have element stride nc, line stride 1;
-  // point i of the workgroup is handled by thread i mod 256 (slot i / 256)
-  for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-    int zz = i / nc, c = i - zz * nc;
-    A[i] = data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c];
-  }
-  // the multiplier (and the saved spectrum) of this thread's points, loaded
-  // now so that their latency overlaps the forward transform
+  const size_t plane = (size_t)Kx * Ky;
+  const size_t cxy = (size_t)y * Kx + x;                   // point z of the column: z * plane + cxy
+  // the column, and the multiplier (and saved spectrum) of this lane's
+  // points, loaded together so that their latencies overlap
   T gk[ZPASS_PREFETCH];
   T2 sv[ZPASS_PREFETCH];
 #pragma unroll
   for (int u = 0; u < ZPASS_PREFETCH; ++u) {
-    const int i = threadIdx.x + u * 256;
+    const int z = lane + u * WAVE;
     gk[u] = (T)0;
     sv[u] = T2{(T)0, (T)0};
-    if (i < NL) {
-      const int zz = i / nc, c = i - zz * nc;
-      const size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
-      gk[u] = G[g];
-      if (za.mode == 1 && add_saved) sv[u] = save[fo + g];
+    if (active && z < Kz) {
+      A[z] = data1[fo + z * plane + cxy];
+      gk[u] = G[z * plane + cxy];
+      if (za.mode == 1 && add_saved) sv[u] = save[fo + z * plane + cxy];
     }
   }
-  __syncthreads();
-  T2* X = fft_lines(A, B, pz, twz, nc, nc, 1, -1);
-  T2* F1 = (X == A) ? B : A;
-  if (za.mode == 0) {
-    double e = 0.0;
+  if (active)
+    for (int z = lane + ZPASS_PREFETCH * WAVE; z < Kz; z += WAVE) A[z] = data1[fo + z * plane + cxy];
+  __syncthreads();                                         // twiddles
+  double e = 0.0;
+  if (active) {
+    T2* X = fft_line_w(A, B, pz, twz, -1);
+    T2* F1 = (X == A) ? B : A;
+    if (za.mode == 0) {
+      // X <- G X (energy partial 1/2 sum G |X|^2; X saved for the field pass)
+      auto mul = [&](int z, T g) {
+        const T2 v = X[z];
+        if (save) save[fo + z * plane + cxy] = v;
+        e += (double)g * ((double)v.x * v.x + (double)v.y * v.y);
+        X[z] = T2{v.x * g, v.y * g};
+      };
 #pragma unroll
-    for (int u = 0; u < ZPASS_PREFETCH; ++u) {
-      const int i = threadIdx.x + u * 256;
-      if (i < NL) {
-        const int zz = i / nc, c = i - zz * nc;
-        const size_t g = ((size_t)zz * Ky + y) * Kx + x0 + c;
-        const T2 v = X[i];
-        if (save) save[fo + g] = v;
-        e += (double)gk[u] * ((double)v.x * v.x + (double)v.y * v.y);
-        X[i] = T2{v.x * gk[u], v.y * gk[u]};
+      for (int u = 0; u < ZPASS_PREFETCH; ++u)
+        if (lane + u * WAVE < Kz) mul(lane + u * WAVE, gk[u]);
+      for (int z = lane + ZPASS_PREFETCH * WAVE; z < Kz; z += WAVE) mul(z, G[z * plane + cxy]);
+      T2* Y = fft_line_w(X, F1, pz, twz, +1);
+      for (int z = lane; z < Kz; z += WAVE) data1[fo + z * plane + cxy] = Y[z];
+    } else {
+      // C keeps G X; the first inverse transforms (-i kx + ky) G X (Ex + i Ey
+      // after the x-y inverse), the second -i kz G X (Ez)
+      const T kx = mode_k<T>(x, Kx, (T)za.twopi_L[0]);
+      const T ky = mode_k<T>(y, Ky, (T)za.twopi_L[1]);
+      auto mul = [&](int z, T g, T2 w) {
+        T2 v = X[z];
+        if (add_saved) { v.x += w.x; v.y += w.y; }
+        v = T2{v.x * g, v.y * g};
+        C[z] = v;
+        F1[z] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};
+      };
+#pragma unroll
+      for (int u = 0; u < ZPASS_PREFETCH; ++u)
+        if (lane + u * WAVE < Kz) mul(lane + u * WAVE, gk[u], sv[u]);
+      for (int z = lane + ZPASS_PREFETCH * WAVE; z < Kz; z += WAVE)
+        mul(z, G[z * plane + cxy], add_saved ? save[fo + z * plane + cxy] : T2{(T)0, (T)0});
+      T2* Y = fft_line_w(F1, X, pz, twz, +1);
+      for (int z = lane; z < Kz; z += WAVE) data1[fo + z * plane + cxy] = Y[z];
+      T2* W = (Y == F1) ? X : F1;                           // free after the store above
+      __builtin_amdgcn_wave_barrier();
+      for (int z = lane; z < Kz; z += WAVE) {
+        const T kz = mode_k<T>(z, Kz, (T)za.twopi_L[2]);
+        const T2 v = C[z];
+        C[z] = T2{kz * v.y, -kz * v.x};
       }
+      T2* Z = fft_line_w(C, W, pz, twz, +1);
+      for (int z = lane; z < Kz; z += WAVE) data2[fo + z * plane + cxy] = Z[z];
     }
-    if (energy_part) {
-      e = wave_sum(e);
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
-    }
+  }
+  if (za.mode == 0 && energy_part) {
+    e = wave_sum(e);
+    if (lane == 0) red[wv] = e;
     __syncthreads();
-    if (energy_part && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
       double s = 0.0;
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
       energy_part[(size_t)blockIdx.y * n_z_blocks + blockIdx.x] = 0.5 * s;
-    }
-    T2* Y = fft_lines(X, F1, pz, twz, nc, nc, 1, +1);
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-      int zz = i / nc, c = i - zz * nc;
-      data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Y[i];
-    }
-  } else {
-    // C keeps the spectrum G X; F1 and X serve as the ping-pong pair of
-    // the first inverse, A and B of the second
-    const T ky = mode_k<T>(y, Ky, (T)za.twopi_L[1]);
-#pragma unroll
-    for (int u = 0; u < ZPASS_PREFETCH; ++u) {
-      const int i = threadIdx.x + u * 256;
-      if (i < NL) {
-        const int c = i % nc;
-        T2 v = X[i];
-        if (add_saved) { v.x += sv[u].x; v.y += sv[u].y; }
-        v = T2{v.x * gk[u], v.y * gk[u]};
-        C[i] = v;
-        const T kx = mode_k<T>(x0 + c, Kx, (T)za.twopi_L[0]);
-        F1[i] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};   // (-i kx + ky) v
-      }
-    }
-    __syncthreads();
-    T2* Y = fft_lines(F1, X, pz, twz, nc, nc, 1, +1);
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-      int zz = i / nc, c = i - zz * nc;
-      data1[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Y[i];
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-      int zz = i / nc;
-      T kz = mode_k<T>(zz, Kz, (T)za.twopi_L[2]);
-      T2 v = C[i];
-      A[i] = T2{kz * v.y, -kz * v.x};                            // -i kz v
-    }
-    __syncthreads();
-    T2* Z = fft_lines(A, B, pz, twz, nc, nc, 1, +1);
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-      int zz = i / nc, c = i - zz * nc;
-      data2[fo + ((size_t)zz * Ky + y) * Kx + x0 + c] = Z[i];
     }
   }
 }
@@ -502,12 +552,15 @@ template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass,
                     const RealBArgs<T>* rb, const PairArgs<T>* pa) {
-  const int nzb = z_pass ? za.Ky * za.nchunk : 0;
+  const int nzb = z_pass ? za.n_blocks : 0;
   const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
-  size_t lds = (3 * (size_t)za.nxc * za.Kz + za.Kz) * sizeof(T2);
-  if (r.n_blocks > 0) lds = std::max(lds, r.tiles ? PairLds<T>::total : pair_queue_lds<T>());
-  if (p.n_blocks > 0) lds = std::max(lds, p.tsplit > 0 ? PairLds<T>::total : pair_queue_lds<T>());
+  size_t lds = (3 * (size_t)za.cpw * za.Kz + za.Kz) * sizeof(T2);
+  if (r.n_blocks + p.n_blocks > 0) lds = std::max(lds, pair_queue_lds<T>());
+  if ((r.n_blocks > 0 && r.tiles) || (p.n_blocks > 0 && p.tsplit > 0)) {
+    std::fprintf(stderr, "cpm: only the one-wavefront-per-target pair forms ride in the z pass\n");
+    std::abort();
+  }
   dim3 grid(nzb + r.n_blocks + p.n_blocks, n_frames);
   if (grid.x == 0) return;
   hipLaunchKernelGGL((k_fft_z<T, T2>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
