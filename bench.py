@@ -186,7 +186,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 445696, "sources_sha256": "56774de942c99d45a2067028abeb1afa2eddf4e5be5b0f2177ae1e5e1c57b1e1"}}
+TRAFFIC = {"site_pairs": {"bytes": 445696, "sources_sha256": "a65e9c8adf692828f882ca9756fce9cc7e85457026cbdc21216b9c5d9ebc97f0"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
