@@ -103,6 +103,17 @@ def test_step_parity_sites_crowded_into_one_layer(torch_dev):
     check_step(torch_dev, wc, A, S)
 
 
+@pytest.mark.parametrize("kz", [600, 2048])
+def test_step_parity_long_z_columns(torch_dev, kz):
+    """Meshes with more points along z than the z pass prefetches per lane
+    (512), and at 2048 points so long that a workgroup holds one column."""
+    import dataclasses
+    _say(f"[gpu] step tiny ff with PPPM, mesh 16x16x{kz}")
+    w0, A, S = built("tiny", "ff")
+    w = dataclasses.replace(w0, kspace="pppm", mesh=(16, 16, kz))
+    check_step(torch_dev, w, A, S)
+
+
 def check_step(torch, w, A, S):
     es = cpm.Electrostatics(w, oracle_method(w))
     ref = cpm.step(w, A, S, es)
