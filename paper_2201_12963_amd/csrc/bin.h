@@ -13,8 +13,15 @@
 //      the cell_start array;
 //   4. every site goes to offset + rank, all sites in parallel, so the sites
 //      of a cell appear in increasing original index (a stable counting sort).
-// The wrapped coordinates come from the same quotient x/L as the cell index
-// (computed once, in step 1, and parked in a scratch array until step 4).
+// The wrapped coordinates come from the same quotient x/L as the cell index,
+// computed once in step 1 and carried to step 4 in one of two ways:
+//   KEEP: every thread holds those of its first BIN_BATCH sites (and their
+//     charges) in registers; sites beyond BIN_BATCH x NT are read and wrapped
+//     again in step 4 (the same operations, so the same bits).  No scratch
+//     round trip, for the one-frame launch, where the workgroup's latency
+//     is the step's;
+//   otherwise: a scratch array in global memory, which keeps the register
+//     count (and the occupancy of the many-frame launches) down.
 // The sorted FP64 SoA copies (wrapped x, y, z and the charge) are what the
 // later kernels stream; the body also sums Q_j Z_j for the finite-field energy.
 #pragma once
@@ -45,7 +52,7 @@ __device__ __forceinline__ double wrap_and_cell(double x, double L, int n, int& 
   return x - L * fl;
 }
 
-template <int NT>
+template <int NT, bool KEEP>
 __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds) {
   constexpr int NW = NT / WAVE;
   const int n_site = a.n_site;
@@ -66,6 +73,9 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   int* cell_start = a.cell_start_all + (size_t)frame * (n_cells + 1);
   int* order = a.order_all + (size_t)frame * n_site;
 
+  // KEEP: the first batch of every thread (wrapped coordinates and charges)
+  double kx[BIN_BATCH], ky[BIN_BATCH], kz[BIN_BATCH], kq[BIN_BATCH];
+  // otherwise: the scratch array
   double* wx = a.wrap_all + (size_t)frame * 3 * n_site;
   double* wy = wx + n_site;
   double* wz = wy + n_site;
@@ -85,17 +95,19 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
 #pragma unroll
     for (int u = 0; u < BIN_BATCH; ++u) {
       const int i = i0 + u * NT;
+      double ax = 0.0, ay = 0.0, az = 0.0;
       if (i < n_site) {
         double xi = xv[u], yi = yv[u], zi = zv[u];
         if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) { bad = 1; xi = yi = zi = 0.0; }
         int cx, cy, cz;
-        const double ax = wrap_and_cell(xi, cell.L[0], cell.nc[0], cx);
-        const double ay = wrap_and_cell(yi, cell.L[1], cell.nc[1], cy);
-        const double az = wrap_and_cell(zi, cell.L[2], cell.nc[2], cz);
+        ax = wrap_and_cell(xi, cell.L[0], cell.nc[0], cx);
+        ay = wrap_and_cell(yi, cell.L[1], cell.nc[1], cy);
+        az = wrap_and_cell(zi, cell.L[2], cell.nc[2], cz);
         cid[i] = (cz * cell.nc[1] + cy) * cell.nc[0] + cx;
-        wx[i] = ax; wy[i] = ay; wz[i] = az;
+        if (!KEEP) { wx[i] = ax; wy[i] = ay; wz[i] = az; }
         zd += qv[u] * az;
       }
+      if (KEEP && i0 == tid) { kx[u] = ax; ky[u] = ay; kz[u] = az; kq[u] = qv[u]; }
     }
   }
   if (bad) atomicOr(a.status, 1);
@@ -177,13 +189,16 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   for (int i0 = tid; i0 < n_site; i0 += BIN_BATCH * NT) {
     double xv[BIN_BATCH], yv[BIN_BATCH], zv[BIN_BATCH], qv[BIN_BATCH];
     int pv[BIN_BATCH];
+    const bool first = KEEP && i0 == tid;
 #pragma unroll
     for (int u = 0; u < BIN_BATCH; ++u) {
       const int i = i0 + u * NT;
-      xv[u] = yv[u] = zv[u] = qv[u] = 0.0;
+      if (KEEP) { xv[u] = kx[u]; yv[u] = ky[u]; zv[u] = kz[u]; qv[u] = kq[u]; }
+      else { xv[u] = yv[u] = zv[u] = qv[u] = 0.0; }
       pv[u] = 0;
       if (i < n_site) {
-        xv[u] = wx[i]; yv[u] = wy[i]; zv[u] = wz[i]; qv[u] = a.site_q[i];
+        if (!KEEP) { xv[u] = wx[i]; yv[u] = wy[i]; zv[u] = wz[i]; qv[u] = a.site_q[i]; }
+        else if (!first) { xv[u] = x[i]; yv[u] = y[i]; zv[u] = z[i]; qv[u] = a.site_q[i]; }
         const int rw = rnk[i];
         pv[u] = hist[(rw >> 24) * n_cells + cid[i]] + (rw & 0xffffff);
       }
@@ -192,7 +207,14 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
     for (int u = 0; u < BIN_BATCH; ++u) {
       const int i = i0 + u * NT;
       if (i < n_site) {
-        const double xi = xv[u], yi = yv[u], zi = zv[u];
+        double xi = xv[u], yi = yv[u], zi = zv[u];
+        if (KEEP && !first) {
+          if (!isfinite(xi) || !isfinite(yi) || !isfinite(zi)) xi = yi = zi = 0.0;
+          int c;
+          xi = wrap_and_cell(xi, cell.L[0], cell.nc[0], c);
+          yi = wrap_and_cell(yi, cell.L[1], cell.nc[1], c);
+          zi = wrap_and_cell(zi, cell.L[2], cell.nc[2], c);
+        }
         const int pos = pv[u];
         order[pos] = i;
         sx[pos] = xi; sy[pos] = yi; sz[pos] = zi; sq[pos] = qv[u];

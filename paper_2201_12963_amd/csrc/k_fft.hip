@@ -142,6 +142,72 @@ __device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nli
   return src;
 }
 
+// Lines of at most DFT_DIRECT_MAX points: the plane transforms are bound
+// by the latency of their dependent stages (a thread's butterfly of one
+// stage is a chain of index arithmetic, two LDS reads, the twiddle products
+// and the writes, then a barrier), so short lines are summed directly
+// instead: thread (line, k) forms X_k = sum_n x_n e^{-+2 pi i n k / N} from
+// the same twiddle table, its index advanced by k modulo N.  One pass and
+// one barrier per direction; the result lands in b in natural order.  Taken
+// only while every output of the plane has a thread of its own (a second
+// round of N-term sums costs more than the stages it saves, as at 36 x 36).
+constexpr int DFT_DIRECT_MAX = 32;
+
+// threads of a plane workgroup: one-frame launches use XY_THREADS (an
+// 18 x 18 plane is then one direct-sum output per thread), many-frame
+// launches XY_THREADS_MANY (more workgroups per CU for the Stockham stages)
+constexpr int XY_THREADS = 512;
+constexpr int XY_THREADS_MANY = 256;
+
+template <typename T2>
+__device__ T2* dft_lines(const T2* a, T2* b, int N, const T2* tw, int nlines, int es, int ls, int sigma) {
+  using T = typename CT<T2>::R;
+  const T sg = sigma > 0 ? (T)-1 : (T)1;             // conjugate the table for the inverse
+  for (int u = threadIdx.x; u < nlines * N; u += blockDim.x) {
+    const int line = u / N;
+    const int k = u - line * N;
+    const T2* in = a + line * ls;
+    // two partial sums (even and odd n) shorten the dependent chain
+    T sr0 = 0, si0 = 0, sr1 = 0, si1 = 0;
+    int t = 0;
+    int n = 0;
+    for (; n + 1 < N; n += 2) {
+      const T2 x0 = in[n * es];
+      const T2 x1 = in[(n + 1) * es];
+      const T2 w0 = tw[t];
+      t += k; t -= (t >= N) ? N : 0;
+      const T2 w1 = tw[t];
+      t += k; t -= (t >= N) ? N : 0;
+      const T wy0 = sg * w0.y, wy1 = sg * w1.y;
+      sr0 += x0.x * w0.x - x0.y * wy0;
+      si0 += x0.x * wy0 + x0.y * w0.x;
+      sr1 += x1.x * w1.x - x1.y * wy1;
+      si1 += x1.x * wy1 + x1.y * w1.x;
+    }
+    if (n < N) {
+      const T2 x0 = in[n * es];
+      const T2 w0 = tw[t];
+      const T wy0 = sg * w0.y;
+      sr0 += x0.x * w0.x - x0.y * wy0;
+      si0 += x0.x * wy0 + x0.y * w0.x;
+    }
+    b[line * ls + k * es] = T2{sr0 + sr1, si0 + si1};
+  }
+  __syncthreads();
+  return b;
+}
+
+// One direction of a plane: the direct sum for short lines in the one-frame
+// launches (direct), else the Stockham stages, which do fewer operations and
+// serve the many-frame launches better, where throughput counts
+template <typename T2>
+__device__ T2* plane_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nlines, int es, int ls, int sigma,
+                           bool direct) {
+  if (direct && p.n <= DFT_DIRECT_MAX && nlines * p.n <= (int)blockDim.x)
+    return dft_lines(a, b, p.n, tw, nlines, es, ls, sigma);
+  return fft_lines(a, b, p, tw, nlines, es, ls, sigma);
+}
+
 // One Stockham stage of radix R over one contiguous line, by the lanes of
 // one wavefront (no workgroup barrier; the caller orders the stages)
 template <int R, typename T2>
@@ -201,12 +267,13 @@ __device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int si
 // mode 1: inverse, complex input -> real part to out_re (and imaginary part to out_im if given)
 // split (mode 1 only): blockIdx.y = 2 frame + part; part 1 transforms in_c2
 // into out_re2 (real part only), part 0 in_c as above
+// direct: a one-frame launch (the lines are summed directly, see dft_lines)
 template <typename T, typename T2>
-__global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
+__global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
                                                 const T* __restrict__ in_re, const T2* __restrict__ in_c,
                                                 T2* __restrict__ out_c, T* __restrict__ out_re,
                                                 T* __restrict__ out_im, size_t out_re_stride, int split,
-                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
+                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2, bool direct) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
@@ -227,9 +294,9 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
   }
   __syncthreads();
   const int sigma = mode == 0 ? -1 : 1;
-  T2* r1 = fft_lines(A, B, px, twx, Ky, 1, Kx, sigma);          // along x
+  T2* r1 = plane_lines(A, B, px, twx, Ky, 1, Kx, sigma, direct);        // along x
   T2* o1 = (r1 == A) ? B : A;
-  T2* r2 = fft_lines(r1, o1, py, twy, Kx, Kx, 1, sigma);        // along y
+  T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, direct);      // along y
   if (mode == 0) {
     for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2[i];
   } else {
@@ -252,8 +319,9 @@ __global__ __launch_bounds__(256) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int 
 // computed on the spot.  The scan needs no cell list, so the binning of the
 // same frame runs as one more workgroup of this launch (index n_planes).
 // The assembled plane is also written to rho_out (the charge mesh, for
-// inspection), then transformed as in k_fft_xy.
-template <typename T, typename T2>
+// inspection), then transformed as in k_fft_xy.  ONE: a one-frame launch
+// (the binning keeps its sites in registers, the planes use the direct sum).
+template <typename T, typename T2, bool ONE>
 __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
                                                        BinArgs ba, int stage_cap, T* __restrict__ rho_out,
                                                        T2* __restrict__ out_c, int n_planes) {
@@ -262,7 +330,7 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int nvalid;
   if ((int)blockIdx.x >= n_planes) {
-    bin_block<SPREAD_THREADS>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
+    bin_block<SPREAD_THREADS, ONE>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
     return;
   }
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
@@ -359,9 +427,9 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
     A[i] = T2{acc[i], (T)0};
   }
   __syncthreads();
-  T2* r1p = fft_lines(A, B, px, twx, Ky, 1, Kx, -1);
+  T2* r1p = plane_lines(A, B, px, twx, Ky, 1, Kx, -1, ONE);
   T2* o1 = (r1p == A) ? B : A;
-  T2* r2p = fft_lines(r1p, o1, py, twy, Kx, Kx, 1, -1);
+  T2* r2p = plane_lines(r1p, o1, py, twy, Kx, Kx, 1, -1, ONE);
   for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2p[i];
 }
 
@@ -516,8 +584,12 @@ void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, co
   if (bin) lds = std::max(lds, bin_lds_spread(ba.n_site, ba.cell.n_cells));
   dim3 grid(np + (bin ? 1 : 0), n_frames);
   if (grid.x == 0) return;
-  hipLaunchKernelGGL((k_fft_xy_spread<T, T2>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, cap, rho_out, out_c,
-                     np);
+  if (n_frames == 1)
+    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, true>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, cap, rho_out,
+                       out_c, np);
+  else
+    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, false>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, cap, rho_out,
+                       out_c, np);
 }
 
 size_t bin_lds_spread(int n_site, int n_cells) { return bin_body_lds<SPREAD_THREADS>(n_site, n_cells); }
@@ -535,8 +607,8 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
                      size_t out_re_stride) {
   size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
-  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, n_frames), dim3(256), lds, s, px, py, Kz, mode, in_re,
-                     in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
+  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, n_frames), dim3(n_frames == 1 ? XY_THREADS : XY_THREADS_MANY), lds, s, px, py, Kz, mode, in_re,
+                     in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr, n_frames == 1);
 }
 
 template <typename T, typename T2>
@@ -544,8 +616,8 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
                                const T2* c1, const T2* c2, T* E, size_t frame_stride) {
   const size_t M = (size_t)px.n * py.n * Kz;
   size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
-  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, 2 * n_frames), dim3(256), lds, s, px, py, Kz, 1,
-                     (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
+  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, 2 * n_frames), dim3(n_frames == 1 ? XY_THREADS : XY_THREADS_MANY), lds, s, px, py, Kz, 1,
+                     (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M, n_frames == 1);
 }
 
 template <typename T, typename T2>

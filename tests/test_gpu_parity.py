@@ -114,6 +114,19 @@ def test_step_parity_long_z_columns(torch_dev, kz):
     check_step(torch_dev, w, A, S)
 
 
+@pytest.mark.parametrize("kx,ky", [(15, 20), (30, 16), (32, 20), (25, 24)])
+def test_step_parity_plane_shapes(torch_dev, kx, ky):
+    """Odd and non-square x-y planes.  A one-frame step sums lines of up to 32
+    points directly while every output of the plane has a thread of its own
+    (15 x 20, 30 x 16); larger planes (32 x 20, 25 x 24) take the radix
+    stages."""
+    import dataclasses
+    _say(f"[gpu] step tiny ff with PPPM, mesh {kx}x{ky}x64")
+    w0, A, S = built("tiny", "ff")
+    w = dataclasses.replace(w0, kspace="pppm", mesh=(kx, ky, 64))
+    check_step(torch_dev, w, A, S)
+
+
 def check_step(torch, w, A, S):
     es = cpm.Electrostatics(w, oracle_method(w))
     ref = cpm.step(w, A, S, es)
