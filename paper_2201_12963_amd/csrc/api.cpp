@@ -1047,8 +1047,8 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     c->n_touch = (int)touch.size();
     {
       const size_t need =
-          std::max(c->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns))
-                                             : fft_xy_spread_lds<double, double2>(mi.K[0], mi.K[1], fft_xy_spread_stage_cap(ns)),
+          std::max(c->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(mi.K[0], mi.K[1])
+                                             : fft_xy_spread_lds<double, double2>(mi.K[0], mi.K[1]),
                    bin_lds_spread(ns, cl.n_cells));
       if (need > 150 * 1024) {
         fail(c, CPM_EINVAL, "mesh plane and site staging area (%zu bytes) exceed LDS", need);

@@ -457,10 +457,12 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass = true,
                     const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr);
 template <typename T, typename T2>
-size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap);
-int fft_xy_spread_stage_cap(int n_site);
+size_t fft_xy_spread_lds(int Kx, int Ky);
 // threads of the spread + x-y transform workgroups (which also run the binning)
 constexpr int SPREAD_THREADS = 512;
+// sites per thread whose z is read together by the spread's staging (the
+// per-wavefront lists hold SPREAD_BATCH x 64 entries)
+constexpr int SPREAD_BATCH = 8;
 // LDS of such a workgroup running the binning body
 size_t bin_lds_spread(int n_site, int n_cells);
 template <typename T, typename T2>

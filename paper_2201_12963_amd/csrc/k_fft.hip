@@ -313,9 +313,8 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
 // Forward x-y transform of one z-plane of the electrolyte charge mesh, whose
 // real values are first assembled in LDS.  The plane's workgroup scans every
 // site (wrapped into the box as the binning does), stages those whose
-// B-spline stencil reaches the plane (stage_cap entries at most, flushed
-// when the next block-wide chunk could overflow it), and each staged site
-// adds its P x P in-plane contributions with LDS atomics, its weights
+// B-spline stencil reaches the plane in per-wavefront lists, and each staged
+// site adds its P x P in-plane contributions with LDS atomics, its weights
 // computed on the spot.  The scan needs no cell list, so the binning of the
 // same frame runs as one more workgroup of this launch (index n_planes).
 // The assembled plane is also written to rho_out (the charge mesh, for
@@ -323,12 +322,10 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
 // (the binning keeps its sites in registers, the planes use the direct sum).
 template <typename T, typename T2, bool ONE>
 __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
-                                                       BinArgs ba, int stage_cap, T* __restrict__ rho_out,
+                                                       BinArgs ba, T* __restrict__ rho_out,
                                                        T2* __restrict__ out_c, int n_planes) {
-  // 16-byte alignment keeps the dynamic area (after the static counter)
-  // aligned for the complex values and the FP64 LDS atomics
+  // 16-byte alignment for the complex values and the FP64 LDS atomics
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int nvalid;
   if ((int)blockIdx.x >= n_planes) {
     bin_block<SPREAD_THREADS, ONE>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
     return;
@@ -345,7 +342,6 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
   const int iz = blockIdx.x;
   const int frame = blockIdx.y;
   for (int i = threadIdx.x; i < NP; i += blockDim.x) acc[i] = (T)0;
-  if (threadIdx.x == 0) nvalid = 0;
   __syncthreads();
   const int P = mi.order;
   const int n = ba.n_site;
@@ -355,71 +351,79 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
   const double* q = ba.site_q;
   const double Lx = ba.cell.L[0], Ly = ba.cell.L[1], Lz = ba.cell.L[2];
   const double ihx = mi.invh[0], ihy = mi.invh[1], ihz = mi.invh[2];
-  // one task per staged (site, z slot): the site's B-spline weights, then its
+  // one staged (site, z slot) entry: the site's B-spline weights, then its
   // P x P in-plane contributions added with LDS atomics
-  auto flush = [&](int nv) {
-    for (int e_i = threadIdx.x; e_i < nv; e_i += blockDim.x) {
-      const int e = list[e_i];
-      const int j = e >> 3, tz = e & 7;
-      double xj = sx[j], yj = sy[j];
-      if (!isfinite(xj)) xj = 0.0;
-      if (!isfinite(yj)) yj = 0.0;
-      double zj = sz[j];
-      if (!isfinite(zj)) zj = 0.0;
-      T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
-      int fx = spline_triangle_d<T>(wrap_coord(xj, Lx) * ihx, P, Bx);
-      int fy = spline_triangle_d<T>(wrap_coord(yj, Ly) * ihy, P, By);
-      spline_triangle_d<T>(wrap_coord(zj, Lz) * ihz, P, Bz);
-      fx = ((fx % Kx) + Kx) % Kx;
-      fy = ((fy % Ky) + Ky) % Ky;
-      T wz = 0;
+  auto add_site = [&](int e) {
+    const int j = e >> 3, tz = e & 7;
+    double xj = sx[j], yj = sy[j];
+    if (!isfinite(xj)) xj = 0.0;
+    if (!isfinite(yj)) yj = 0.0;
+    double zj = sz[j];
+    if (!isfinite(zj)) zj = 0.0;
+    T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
+    int fx = spline_triangle_d<T>(wrap_coord(xj, Lx) * ihx, P, Bx);
+    int fy = spline_triangle_d<T>(wrap_coord(yj, Ly) * ihy, P, By);
+    spline_triangle_d<T>(wrap_coord(zj, Lz) * ihz, P, Bz);
+    fx = ((fx % Kx) + Kx) % Kx;
+    fy = ((fy % Ky) + Ky) % Ky;
+    T wz = 0;
 #pragma unroll
-      for (int b = 0; b < MAX_ORDER; ++b) wz = (b == P - 1 - tz) ? Bz[b] : wz;
-      const T qz = (T)q[j] * wz;
+    for (int b = 0; b < MAX_ORDER; ++b) wz = (b == P - 1 - tz) ? Bz[b] : wz;
+    const T qz = (T)q[j] * wz;
 #pragma unroll
-      for (int by = 0; by < MAX_ORDER; ++by) {
-        if (by < P) {
-          int iy = fy + (P - 1 - by); iy -= (iy >= Ky) ? Ky : 0;
-          const T qyz = qz * By[by];
-          T* row = acc + iy * Kx;
+    for (int by = 0; by < MAX_ORDER; ++by) {
+      if (by < P) {
+        int iy = fy + (P - 1 - by); iy -= (iy >= Ky) ? Ky : 0;
+        const T qyz = qz * By[by];
+        T* row = acc + iy * Kx;
 #pragma unroll
-          for (int bx = 0; bx < MAX_ORDER; ++bx) {
-            if (bx < P) {
-              int ix = fx + (P - 1 - bx); ix -= (ix >= Kx) ? Kx : 0;
-              atomicAdd(row + ix, qyz * Bx[bx]);
-            }
+        for (int bx = 0; bx < MAX_ORDER; ++bx) {
+          if (bx < P) {
+            int ix = fx + (P - 1 - bx); ix -= (ix >= Kx) ? Kx : 0;
+            atomicAdd(row + ix, qyz * Bx[bx]);
           }
         }
       }
     }
   };
-  // block-wide chunks over all sites, so that the list is flushed before it
-  // can overflow
-  for (int base = 0; base < n; base += blockDim.x) {
-    const int j = base + threadIdx.x;
-    if (j < n) {
-      double zj = sz[j];
-      if (!isfinite(zj)) zj = 0.0;
-      int fz = spline_first(wrap_coord(zj, Lz) * ihz, P);
-      fz = ((fz % Kz) + Kz) % Kz;
-      int tz = iz - fz;
-      tz += (tz < 0) ? Kz : 0;
-      if (tz < P) {
-        int slot = atomicAdd(&nvalid, 1);
-        list[slot] = j * 8 + tz;                        // site index and its z weight slot
+  // Staging, wavefront by wavefront: a thread reads the z of SPREAD_BATCH
+  // sites (the loads issued together); those whose stencil reaches the plane
+  // go to the wavefront's own list (ballot and prefix count: no atomics and
+  // no workgroup barrier), which the wavefront then works through with all
+  // its lanes, so that every wavefront shares the weights and the atomics.
+  const int lane = threadIdx.x & (WAVE - 1);
+  int* wl = list + (threadIdx.x / WAVE) * (SPREAD_BATCH * WAVE);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int base = 0; base < n; base += SPREAD_BATCH * SPREAD_THREADS) {
+    double zv[SPREAD_BATCH];
+#pragma unroll
+    for (int u = 0; u < SPREAD_BATCH; ++u) {
+      const int j = base + u * SPREAD_THREADS + (int)threadIdx.x;
+      zv[u] = j < n ? sz[j] : 0.0;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < SPREAD_BATCH; ++u) {
+      const int j = base + u * SPREAD_THREADS + (int)threadIdx.x;
+      int tz = P;
+      if (j < n) {
+        double zj = zv[u];
+        if (!isfinite(zj)) zj = 0.0;
+        int fz = spline_first(wrap_coord(zj, Lz) * ihz, P);
+        fz = ((fz % Kz) + Kz) % Kz;
+        tz = iz - fz;
+        tz += (tz < 0) ? Kz : 0;
       }
+      const bool hit = tz < P;
+      const unsigned long long m = __ballot(hit);
+      if (hit) wl[cnt + __popcll(m & lt)] = j * 8 + tz;   // site index and its z weight slot
+      cnt += __popcll(m);
     }
-    __syncthreads();
-    const int nv = nvalid;
-    __syncthreads();                                    // all have read the count before it changes again
-    if (nv > stage_cap - (int)blockDim.x) {
-      flush(nv);
-      __syncthreads();
-      if (threadIdx.x == 0) nvalid = 0;
-      __syncthreads();
-    }
+    // a wavefront's LDS operations complete in order: its lanes see the list
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < cnt; e += WAVE) add_site(wl[e]);
+    __builtin_amdgcn_wave_barrier();                      // list read before the next batch writes it
   }
-  flush(nvalid);
   __syncthreads();
   const size_t off = ((size_t)frame * Kz + iz) * NP;
   for (int i = threadIdx.x; i < NP; i += blockDim.x) {
@@ -569,33 +573,32 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
 // dynamic LDS of k_fft_xy_spread: two complex planes, twiddles, the real
 // plane and the site staging list
 template <typename T, typename T2>
-size_t fft_xy_spread_lds(int Kx, int Ky, int stage_cap) {
-  return (2 * (size_t)Kx * Ky + Kx + Ky) * sizeof(T2) + (size_t)Kx * Ky * sizeof(T) + (size_t)stage_cap * sizeof(int);
+size_t fft_xy_spread_lds(int Kx, int Ky) {
+  return (2 * (size_t)Kx * Ky + Kx + Ky) * sizeof(T2) + (size_t)Kx * Ky * sizeof(T) +
+         (size_t)SPREAD_BATCH * SPREAD_THREADS * sizeof(int);
 }
 
-int fft_xy_spread_stage_cap(int n_site) { return std::max(2 * SPREAD_THREADS, std::min(n_site, 4096)); }
 
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                             const MeshInfo& mi, const BinArgs& ba, T* rho_out, T2* out_c, bool planes, bool bin) {
-  const int cap = fft_xy_spread_stage_cap(ba.n_site);
   const int np = planes ? Kz : 0;
-  size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n, cap);
+  size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n);
   if (bin) lds = std::max(lds, bin_lds_spread(ba.n_site, ba.cell.n_cells));
   dim3 grid(np + (bin ? 1 : 0), n_frames);
   if (grid.x == 0) return;
   if (n_frames == 1)
-    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, true>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, cap, rho_out,
+    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, true>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, rho_out,
                        out_c, np);
   else
-    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, false>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, cap, rho_out,
+    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, false>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, rho_out,
                        out_c, np);
 }
 
 size_t bin_lds_spread(int n_site, int n_cells) { return bin_body_lds<SPREAD_THREADS>(n_site, n_cells); }
 
-template size_t fft_xy_spread_lds<double, double2>(int, int, int);
-template size_t fft_xy_spread_lds<float, float2>(int, int, int);
+template size_t fft_xy_spread_lds<double, double2>(int, int);
+template size_t fft_xy_spread_lds<float, float2>(int, int);
 template void launch_fft_xy_spread_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
                                                       const MeshInfo&, const BinArgs&, double*, double2*, bool, bool);
 template void launch_fft_xy_spread_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,

@@ -79,9 +79,9 @@ def test_step_parity(torch_dev, name, geometry):
 
 
 def test_step_parity_sites_crowded_into_one_layer(torch_dev):
-    """All sites in a 0.2 nm slab: the planes beside it see more candidate sites
-    than the spread's staging list holds in one go, so the list is flushed
-    part-way through the plane (the path an ordinary cell never takes)."""
+    """All sites in a 0.2 nm slab: on the planes beside it a wavefront of the
+    spread stages more sites than it has lanes (its list takes several
+    rounds), the path an ordinary cell never takes."""
     import dataclasses
     _say("[gpu] step paper ff, sites crowded into one slab")
     w, A, S = built("paper", "ff")
@@ -91,15 +91,17 @@ def test_step_parity_sites_crowded_into_one_layer(torch_dev):
     x[1] = rng.uniform(0.0, w.box[1], w.n_site)
     x[2] = rng.uniform(6.2, 6.4, w.n_site)
     wc = dataclasses.replace(w, site_xyz=x)
-    # sites whose z stencil reaches each plane, against the staging threshold
+    # sites whose z stencil reaches each plane, per staging wavefront: the
+    # spread's 512 threads read sites u * 512 + thread (u < 8), so site j
+    # belongs to wavefront (j mod 512) // 64 of batch j // 4096
     u = x[2] / (w.box[2] / w.mesh[2])
     first = (np.floor(u - w.order / 2.0).astype(int) + 1) % w.mesh[2]
-    per_plane = np.zeros(w.mesh[2], int)
+    j = np.arange(w.n_site)
+    group = (j // 4096) * 8 + (j % 512) // 64
+    per_wave = np.zeros((w.mesh[2], group.max() + 1), int)
     for t in range(w.order):
-        np.add.at(per_plane, (first + t) % w.mesh[2], 1)
-    threads = 512                      # workgroup size of the spread
-    cap = max(2 * threads, min(w.n_site, 4096))
-    assert per_plane.max() > cap - threads
+        np.add.at(per_wave, ((first + t) % w.mesh[2], group), 1)
+    assert per_wave.max() > 64
     check_step(torch_dev, wc, A, S)
 
 
