@@ -91,21 +91,30 @@ __device__ __forceinline__ void load_twiddles(const FFTPlan1D& p, T2* dst) {
   for (int i = threadIdx.x; i < p.n; i += blockDim.x) dst[i] = src[i];
 }
 
+// floor(u / d) for small non-negative u and d (u + d below 2^21) from a
+// single-precision reciprocal rd = 1/d: (u + 1/2) / d lies at least 1/(2d)
+// from an integer, farther than the product's rounding error can move it.
+// Three operations instead of an integer division's twenty on the
+// dependent chain of a stage.
+__device__ __forceinline__ int div_small(int u, float rd) { return (int)(((float)u + 0.5f) * rd); }
+
 // One Stockham stage of radix R over nlines lines (see the file comment).
 template <int R, typename T2>
 __device__ __forceinline__ void fft_stage(const T2* src, T2* dst, int N, int Ns, int nlines, int es, int ls,
                                           const T2* tw, int sigma) {
   const int nb = N / R;
   const int tstep = N / (Ns * R);
+  const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
   for (int u = threadIdx.x; u < nlines * nb; u += blockDim.x) {
-    const int line = u / nb;
+    const int line = div_small(u, rnb);
     const int j = u - line * nb;
     const T2* in = src + line * ls;
     T2* out = dst + line * ls;
     T2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = in[(j + r * nb) * es];
-    const int k = j % Ns;
+    const int jq = div_small(j, rns);
+    const int k = j - jq * Ns;
     if (Ns > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -115,7 +124,7 @@ __device__ __forceinline__ void fft_stage(const T2* src, T2* dst, int N, int Ns,
       }
     }
     small_dft<R>(v, sigma);
-    const int base = (j / Ns) * Ns * R + k;
+    const int base = jq * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[(base + r * Ns) * es] = v[r];
   }
@@ -149,12 +158,14 @@ __device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nli
 // instead: thread (line, k) forms X_k = sum_n x_n e^{-+2 pi i n k / N} from
 // the same twiddle table, its index advanced by k modulo N.  One pass and
 // one barrier per direction; the result lands in b in natural order.  Taken
-// only while every output of the plane has a thread of its own (a second
-// round of N-term sums costs more than the stages it saves, as at 36 x 36).
+// only while every thread of the plane has a single task (a second round of
+// N-term sums costs more than the stages it saves, as at 36 x 36).
 constexpr int DFT_DIRECT_MAX = 32;
+// points per LDS round trip of the direct sum (even)
+constexpr int DFT_CHUNK = 6;
 
 // threads of a plane workgroup: one-frame launches use XY_THREADS (an
-// 18 x 18 plane is then one direct-sum output per thread), many-frame
+// 18 x 18 plane is then one direct-sum task per thread), many-frame
 // launches XY_THREADS_MANY (more workgroups per CU for the Stockham stages)
 constexpr int XY_THREADS = 512;
 constexpr int XY_THREADS_MANY = 256;
@@ -163,35 +174,45 @@ template <typename T2>
 __device__ T2* dft_lines(const T2* a, T2* b, int N, const T2* tw, int nlines, int es, int ls, int sigma) {
   using T = typename CT<T2>::R;
   const T sg = sigma > 0 ? (T)-1 : (T)1;             // conjugate the table for the inverse
-  for (int u = threadIdx.x; u < nlines * N; u += blockDim.x) {
-    const int line = u / N;
-    const int k = u - line * N;
+  // even N: a thread gives X_k and X_{k+N/2} (k < N/2) from the sums E and O
+  // over even and odd n, as e^{-+2 pi i n (k + N/2) / N} = (-1)^n e^{-+2 pi i n k / N}:
+  // X_k = E + O, X_{k+N/2} = E - O, every point and twiddle read serving two
+  // outputs; odd N: one output per thread
+  const int half = (N & 1) ? N : N / 2;
+  const float rh = 1.0f / (float)half;
+  for (int u = threadIdx.x; u < nlines * half; u += blockDim.x) {
+    const int line = div_small(u, rh);
+    const int k = u - line * half;
     const T2* in = a + line * ls;
-    // two partial sums (even and odd n) shorten the dependent chain
-    T sr0 = 0, si0 = 0, sr1 = 0, si1 = 0;
+    // DFT_CHUNK points and their twiddles are read together (one LDS round
+    // trip per chunk); the chunk starts at an even n, so its even entries
+    // go to E and its odd ones to O
+    T er = 0, ei = 0, orr = 0, oi = 0;
     int t = 0;
-    int n = 0;
-    for (; n + 1 < N; n += 2) {
-      const T2 x0 = in[n * es];
-      const T2 x1 = in[(n + 1) * es];
-      const T2 w0 = tw[t];
-      t += k; t -= (t >= N) ? N : 0;
-      const T2 w1 = tw[t];
-      t += k; t -= (t >= N) ? N : 0;
-      const T wy0 = sg * w0.y, wy1 = sg * w1.y;
-      sr0 += x0.x * w0.x - x0.y * wy0;
-      si0 += x0.x * wy0 + x0.y * w0.x;
-      sr1 += x1.x * w1.x - x1.y * wy1;
-      si1 += x1.x * wy1 + x1.y * w1.x;
+    for (int n0 = 0; n0 < N; n0 += DFT_CHUNK) {
+      T2 xv[DFT_CHUNK], wv[DFT_CHUNK];
+#pragma unroll
+      for (int c = 0; c < DFT_CHUNK; ++c) {
+        xv[c] = T2{0, 0};
+        wv[c] = T2{0, 0};
+        if (n0 + c < N) {
+          xv[c] = in[(n0 + c) * es];
+          wv[c] = tw[t];
+          t += k; t -= (t >= N) ? N : 0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < DFT_CHUNK; c += 2) {
+        const T wy0 = sg * wv[c].y, wy1 = sg * wv[c + 1].y;
+        er += xv[c].x * wv[c].x - xv[c].y * wy0;
+        ei += xv[c].x * wy0 + xv[c].y * wv[c].x;
+        orr += xv[c + 1].x * wv[c + 1].x - xv[c + 1].y * wy1;
+        oi += xv[c + 1].x * wy1 + xv[c + 1].y * wv[c + 1].x;
+      }
     }
-    if (n < N) {
-      const T2 x0 = in[n * es];
-      const T2 w0 = tw[t];
-      const T wy0 = sg * w0.y;
-      sr0 += x0.x * w0.x - x0.y * wy0;
-      si0 += x0.x * wy0 + x0.y * w0.x;
-    }
-    b[line * ls + k * es] = T2{sr0 + sr1, si0 + si1};
+    T2* out = b + line * ls;
+    out[k * es] = T2{er + orr, ei + oi};
+    if (half != N) out[(k + half) * es] = T2{er - orr, ei - oi};
   }
   __syncthreads();
   return b;
@@ -203,7 +224,7 @@ __device__ T2* dft_lines(const T2* a, T2* b, int N, const T2* tw, int nlines, in
 template <typename T2>
 __device__ T2* plane_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nlines, int es, int ls, int sigma,
                            bool direct) {
-  if (direct && p.n <= DFT_DIRECT_MAX && nlines * p.n <= (int)blockDim.x)
+  if (direct && p.n <= DFT_DIRECT_MAX && nlines * ((p.n & 1) ? p.n : p.n / 2) <= (int)blockDim.x)
     return dft_lines(a, b, p.n, tw, nlines, es, ls, sigma);
   return fft_lines(a, b, p, tw, nlines, es, ls, sigma);
 }
@@ -215,11 +236,13 @@ __device__ __forceinline__ void fft_stage_w(const T2* src, T2* dst, int N, int N
   const int lane = threadIdx.x & (WAVE - 1);
   const int nb = N / R;
   const int tstep = N / (Ns * R);
+  const float rns = 1.0f / (float)Ns;
   for (int j = lane; j < nb; j += WAVE) {
     T2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
-    const int k = j % Ns;
+    const int jq = div_small(j, rns);
+    const int k = j - jq * Ns;
     if (Ns > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
@@ -229,7 +252,7 @@ __device__ __forceinline__ void fft_stage_w(const T2* src, T2* dst, int N, int N
       }
     }
     small_dft<R>(v, sigma);
-    const int base = (j / Ns) * Ns * R + k;
+    const int base = jq * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
   }
@@ -267,13 +290,13 @@ __device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int si
 // mode 1: inverse, complex input -> real part to out_re (and imaginary part to out_im if given)
 // split (mode 1 only): blockIdx.y = 2 frame + part; part 1 transforms in_c2
 // into out_re2 (real part only), part 0 in_c as above
-// direct: a one-frame launch (the lines are summed directly, see dft_lines)
-template <typename T, typename T2>
+// DIRECT: a one-frame launch (short lines are summed directly, see dft_lines)
+template <typename T, typename T2, bool DIRECT>
 __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
                                                 const T* __restrict__ in_re, const T2* __restrict__ in_c,
                                                 T2* __restrict__ out_c, T* __restrict__ out_re,
                                                 T* __restrict__ out_im, size_t out_re_stride, int split,
-                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2, bool direct) {
+                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
@@ -294,9 +317,9 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
   }
   __syncthreads();
   const int sigma = mode == 0 ? -1 : 1;
-  T2* r1 = plane_lines(A, B, px, twx, Ky, 1, Kx, sigma, direct);        // along x
+  T2* r1 = plane_lines(A, B, px, twx, Ky, 1, Kx, sigma, DIRECT);        // along x
   T2* o1 = (r1 == A) ? B : A;
-  T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, direct);      // along y
+  T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, DIRECT);      // along y
   if (mode == 0) {
     for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2[i];
   } else {
@@ -610,8 +633,12 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
                      size_t out_re_stride) {
   size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
-  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, n_frames), dim3(n_frames == 1 ? XY_THREADS : XY_THREADS_MANY), lds, s, px, py, Kz, mode, in_re,
-                     in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr, n_frames == 1);
+  if (n_frames == 1)
+    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 1), dim3(XY_THREADS), lds, s, px, py, Kz, mode, in_re, in_c,
+                       out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
+  else
+    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3(Kz, n_frames), dim3(XY_THREADS_MANY), lds, s, px, py, Kz, mode,
+                       in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
 }
 
 template <typename T, typename T2>
@@ -619,8 +646,12 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
                                const T2* c1, const T2* c2, T* E, size_t frame_stride) {
   const size_t M = (size_t)px.n * py.n * Kz;
   size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
-  hipLaunchKernelGGL((k_fft_xy<T, T2>), dim3(Kz, 2 * n_frames), dim3(n_frames == 1 ? XY_THREADS : XY_THREADS_MANY), lds, s, px, py, Kz, 1,
-                     (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M, n_frames == 1);
+  if (n_frames == 1)
+    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 2), dim3(XY_THREADS), lds, s, px, py, Kz, 1, (const T*)nullptr,
+                       c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
+  else
+    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3(Kz, 2 * n_frames), dim3(XY_THREADS_MANY), lds, s, px, py, Kz, 1,
+                       (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
 }
 
 template <typename T, typename T2>
