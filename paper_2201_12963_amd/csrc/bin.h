@@ -15,8 +15,8 @@
 //      of a cell appear in increasing original index (a stable counting sort).
 // The wrapped coordinates come from the same quotient x/L as the cell index,
 // computed once in step 1 and carried to step 4 in one of two ways:
-//   KEEP: every thread holds those of its first BIN_BATCH sites (and their
-//     charges) in registers; sites beyond BIN_BATCH x NT are read and wrapped
+//   KEEP: every thread holds those of its first BATCH sites (and their
+//     charges) in registers; sites beyond BATCH x NT are read and wrapped
 //     again in step 4 (the same operations, so the same bits).  No scratch
 //     round trip, for the one-frame launch, where the workgroup's latency
 //     is the step's;
@@ -30,8 +30,10 @@
 namespace cpm {
 
 
-// sites per thread whose loads are issued together
+// sites per thread whose loads are issued together (KEEP: held in
+// registers, 3 x 1024 sites for the one-frame workgroup)
 constexpr int BIN_BATCH = 6;
+constexpr int BIN_BATCH_KEEP = 3;
 
 // LDS of the body (ints): cell ids, ranks, per-wave histograms, cell totals
 template <int NT>
@@ -39,11 +41,9 @@ size_t bin_body_lds(int n_site, int n_cells) {
   return sizeof(int) * (2 * (size_t)n_site + (size_t)(NT / WAVE + 1) * n_cells);
 }
 
-__device__ __forceinline__ double wrap_coord(double x, double L) { return x - L * floor(x / L); }
-
 // wrapped coordinate x - L floor(x/L) and cell index min(floor(f n), n - 1),
 // f = x/L - floor(x/L), from one quotient (the same operations as
-// cell_coord and wrap_coord)
+// cell_coord)
 __device__ __forceinline__ double wrap_and_cell(double x, double L, int n, int& c) {
   const double t = x / L;
   const double fl = floor(t);
@@ -52,7 +52,7 @@ __device__ __forceinline__ double wrap_and_cell(double x, double L, int n, int& 
   return x - L * fl;
 }
 
-template <int NT, bool KEEP>
+template <int NT, bool KEEP, int BATCH>
 __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds) {
   constexpr int NW = NT / WAVE;
   const int n_site = a.n_site;
@@ -74,26 +74,26 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   int* order = a.order_all + (size_t)frame * n_site;
 
   // KEEP: the first batch of every thread (wrapped coordinates and charges)
-  double kx[BIN_BATCH], ky[BIN_BATCH], kz[BIN_BATCH], kq[BIN_BATCH];
+  double kx[BATCH], ky[BATCH], kz[BATCH], kq[BATCH];
   // otherwise: the scratch array
   double* wx = a.wrap_all + (size_t)frame * 3 * n_site;
   double* wy = wx + n_site;
   double* wz = wy + n_site;
 
-  // 1. cell ids and wrapped coordinates; the loads of BIN_BATCH sites per
+  // 1. cell ids and wrapped coordinates; the loads of BATCH sites per
   // thread are issued together
   double zd = 0.0;
   int bad = 0;
-  for (int i0 = tid; i0 < n_site; i0 += BIN_BATCH * NT) {
-    double xv[BIN_BATCH], yv[BIN_BATCH], zv[BIN_BATCH], qv[BIN_BATCH];
+  for (int i0 = tid; i0 < n_site; i0 += BATCH * NT) {
+    double xv[BATCH], yv[BATCH], zv[BATCH], qv[BATCH];
 #pragma unroll
-    for (int u = 0; u < BIN_BATCH; ++u) {
+    for (int u = 0; u < BATCH; ++u) {
       const int i = i0 + u * NT;
       xv[u] = yv[u] = zv[u] = qv[u] = 0.0;
       if (i < n_site) { xv[u] = x[i]; yv[u] = y[i]; zv[u] = z[i]; qv[u] = a.site_q[i]; }
     }
 #pragma unroll
-    for (int u = 0; u < BIN_BATCH; ++u) {
+    for (int u = 0; u < BATCH; ++u) {
       const int i = i0 + u * NT;
       double ax = 0.0, ay = 0.0, az = 0.0;
       if (i < n_site) {
@@ -186,12 +186,12 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   double* sq = a.sq_all + (size_t)frame * n_site;
   // (all loads of a batch before any store: the output may not be assumed
   // apart from the input)
-  for (int i0 = tid; i0 < n_site; i0 += BIN_BATCH * NT) {
-    double xv[BIN_BATCH], yv[BIN_BATCH], zv[BIN_BATCH], qv[BIN_BATCH];
-    int pv[BIN_BATCH];
+  for (int i0 = tid; i0 < n_site; i0 += BATCH * NT) {
+    double xv[BATCH], yv[BATCH], zv[BATCH], qv[BATCH];
+    int pv[BATCH];
     const bool first = KEEP && i0 == tid;
 #pragma unroll
-    for (int u = 0; u < BIN_BATCH; ++u) {
+    for (int u = 0; u < BATCH; ++u) {
       const int i = i0 + u * NT;
       if (KEEP) { xv[u] = kx[u]; yv[u] = ky[u]; zv[u] = kz[u]; qv[u] = kq[u]; }
       else { xv[u] = yv[u] = zv[u] = qv[u] = 0.0; }
@@ -204,7 +204,7 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
       }
     }
 #pragma unroll
-    for (int u = 0; u < BIN_BATCH; ++u) {
+    for (int u = 0; u < BATCH; ++u) {
       const int i = i0 + u * NT;
       if (i < n_site) {
         double xi = xv[u], yi = yv[u], zi = zv[u];

@@ -152,33 +152,6 @@ template <typename T> struct Real2;
 template <> struct Real2<double> { using type = double2; };
 template <> struct Real2<float> { using type = float2; };
 
-// Centred cardinal B-spline weights along one axis.  A particle at scaled
-// coordinate u (mesh units) touches the P mesh points m = first + t,
-// t = 0..P-1, first = floor(u - P/2) + 1, with weight M_P(u - m + P/2).
-// Writing s = u - P/2 and f = s - floor(s), the argument for point t is
-// f + (P - 1 - t).  The values B[j] = M_n(f + j), j = 0..P-1, follow from
-// the Cox-de Boor recursion M_n(x) = [x M_{n-1}(x) + (n - x) M_{n-1}(x-1)]/(n-1)
-// starting at M_1(f + j) = [j == 0].
-template <typename T>
-__device__ __forceinline__ int spline_weights(T u, int P, T* w) {
-  T s = u - (T)P * (T)0.5;
-  T fl = floor(s);
-  T f = s - fl;
-  T B[MAX_ORDER];
-  B[0] = (T)1;
-#pragma unroll
-  for (int j = 1; j < MAX_ORDER; ++j) B[j] = (T)0;
-  for (int n = 2; n <= P; ++n) {
-    T inv = (T)1 / (T)(n - 1);
-    for (int j = n - 1; j >= 0; --j) {
-      T x = f + (T)j;
-      T prev = (j > 0) ? B[j - 1] : (T)0;
-      B[j] = (x * B[j] + ((T)n - x) * prev) * inv;
-    }
-  }
-  for (int t = 0; t < P; ++t) w[t] = B[P - 1 - t];
-  return (int)fl + 1;
-}
 
 // ------------------------------------------------------ kernel arguments
 
@@ -317,64 +290,43 @@ struct EnergyArgs {
   double* out;                                   // [frame][n_dv][2]
 };
 
-// Same weights with the order P known at compile time (unrolled).
-template <int P, typename T>
-__device__ __forceinline__ int spline_weights_p(T u, T* w) {
-  T s = u - (T)P * (T)0.5;
-  T fl = floor(s);
-  T f = s - fl;
-  T B[P];
-  B[0] = (T)1;
-#pragma unroll
-  for (int j = 1; j < P; ++j) B[j] = (T)0;
-#pragma unroll
-  for (int n = 2; n <= P; ++n) {
-    const T inv = (T)1 / (T)(n - 1);
-#pragma unroll
-    for (int j = n - 1; j >= 0; --j) {
-      T x = f + (T)j;
-      T prev = (j > 0) ? B[j - 1] : (T)0;
-      B[j] = (x * B[j] + ((T)n - x) * prev) * inv;
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < P; ++t) w[t] = B[P - 1 - t];
-  return (int)fl + 1;
-}
-
-// The same Cox-de Boor triangle for an order P (<= MAX_ORDER) known only at
-// run time, fully unrolled so that it stays in registers: B[j] (j < P) is the
-// weight of mesh point first + P - 1 - j.  Returns first (not wrapped).
-template <typename T>
-__device__ __forceinline__ int spline_triangle(T u, int P, T (&B)[MAX_ORDER]) {
-  T s = u - (T)P * (T)0.5;
-  T fl = floor(s);
-  T f = s - fl;
-  B[0] = (T)1;
-#pragma unroll
-  for (int j = 1; j < MAX_ORDER; ++j) B[j] = (T)0;
-#pragma unroll
-  for (int n = 2; n <= MAX_ORDER; ++n) {
-    if (n <= P) {
-      const T inv = (T)1 / (T)(n - 1);
-#pragma unroll
-      for (int j = n - 1; j >= 0; --j) {
-        T x = f + (T)j;
-        T prev = (j > 0) ? B[j - 1] : (T)0;
-        B[j] = (x * B[j] + ((T)n - x) * prev) * inv;
-      }
-    }
-  }
-  return (int)fl + 1;
-}
-
-// The same for a scaled coordinate given in FP64 (u up to K): the stencil
-// start and the fractional offset are taken in FP64, the triangle in T.
-template <typename T>
+// Centred cardinal B-spline weights along one axis.  A particle at scaled
+// coordinate u (mesh units) touches the P mesh points m = first + t,
+// t = 0..P-1, first = floor(u - P/2) + 1, with weight M_P(u - m + P/2).
+// Writing s = u - P/2 and f = s - floor(s), the argument for point t is
+// f + (P - 1 - t).  The values B[j] = M_n(f + j), j = 0..P-1, follow from
+// the Cox-de Boor recursion M_n(x) = [x M_{n-1}(x) + (n - x) M_{n-1}(x-1)]/(n-1)
+// starting at M_1(f + j) = [j == 0].
+// The recursion is evaluated as a triangle for an order P (<= MAX_ORDER)
+// known only at run time, fully unrolled so that it stays in registers:
+// B[j] (j < P) is the weight of mesh point first + P - 1 - j; returns first
+// (not wrapped).  The scaled coordinate u (up to K) is given in FP64: the
+// stencil start and the fractional offset are taken in FP64, the weights in T.
+// ORD = 5: the order is known to be 5; ORD = -1: it is known not to be
+// (either keeps only one of the two evaluations below in the kernel, which
+// saves registers); ORD = 0: decided at run time.
+template <typename T, int ORD = 0>
 __device__ __forceinline__ int spline_triangle_d(double u, int P, T (&B)[MAX_ORDER]) {
+  if (ORD == 5) P = 5;
   const double s = u - (double)P * 0.5;
   const double fl = floor(s);
   const T f = (T)(s - fl);
+  if (ORD == 5 || (ORD == 0 && P == 5)) {
+    // order 5 (the quartic B-spline): the triangle below written out as
+    // polynomials in f, 24 B_j = f^4, 1 + 4f + 6f^2 + 4f^3 - 4f^4,
+    // 11 + 12f - 6f^2 - 12f^3 + 6f^4, 11 - 12f - 6f^2 + 12f^3 - 4f^4,
+    // (1 - f)^4 (Horner: a short dependent chain instead of ten steps)
+    const T c = (T)(1.0 / 24.0);
+    const T f2 = f * f, g = (T)1 - f, g2 = g * g;
+    B[0] = c * (f2 * f2);
+    B[1] = c * ((T)1 + f * ((T)4 + f * ((T)6 + f * ((T)4 - (T)4 * f))));
+    B[2] = c * ((T)11 + f * ((T)12 + f * ((T)-6 + f * ((T)-12 + (T)6 * f))));
+    B[3] = c * ((T)11 + f * ((T)-12 + f * ((T)-6 + f * ((T)12 - (T)4 * f))));
+    B[4] = c * (g2 * g2);
+#pragma unroll
+    for (int j = 5; j < MAX_ORDER; ++j) B[j] = (T)0;
+    return (int)fl + 1;
+  }
   B[0] = (T)1;
 #pragma unroll
   for (int j = 1; j < MAX_ORDER; ++j) B[j] = (T)0;
@@ -393,7 +345,7 @@ __device__ __forceinline__ int spline_triangle_d(double u, int P, T (&B)[MAX_ORD
   return (int)fl + 1;
 }
 
-// first mesh point of the stencil of scaled coordinate u, as spline_triangle
+// first mesh point of the stencil of scaled coordinate u, as spline_triangle_d
 template <typename T>
 __device__ __forceinline__ int spline_first(T u, int P) {
   return (int)floor(u - (T)P * (T)0.5) + 1;
@@ -458,11 +410,16 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
                     const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr);
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky);
-// threads of the spread + x-y transform workgroups (which also run the binning)
+// threads of the spread + x-y transform workgroups (which also run the
+// binning): many-frame launches SPREAD_THREADS, one-frame launches
+// SPREAD_THREADS_ONE (four wavefronts per SIMD for the binning workgroup,
+// which is then on the step's critical path)
 constexpr int SPREAD_THREADS = 512;
+constexpr int SPREAD_THREADS_ONE = 1024;
 // sites per thread whose z is read together by the spread's staging (the
-// per-wavefront lists hold SPREAD_BATCH x 64 entries)
-constexpr int SPREAD_BATCH = 8;
+// per-wavefront lists hold SPREAD_LIST / 64 entries per wavefront, SPREAD_LIST
+// entries per workgroup in either configuration)
+constexpr int SPREAD_LIST = 4096;
 // LDS of such a workgroup running the binning body
 size_t bin_lds_spread(int n_site, int n_cells);
 template <typename T, typename T2>

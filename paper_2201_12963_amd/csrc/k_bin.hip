@@ -9,7 +9,7 @@ constexpr int BIN_THREADS = 1024;
 
 __global__ __launch_bounds__(BIN_THREADS) void k_bin_sites(BinArgs a) {
   extern __shared__ __align__(16) int lds[];
-  bin_block<BIN_THREADS, false>(a, blockIdx.x, lds);
+  bin_block<BIN_THREADS, false, BIN_BATCH>(a, blockIdx.x, lds);
 }
 
 size_t bin_lds_bytes(int n_site, int n_cells) { return bin_body_lds<BIN_THREADS>(n_site, n_cells); }

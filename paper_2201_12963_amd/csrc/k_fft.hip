@@ -342,15 +342,19 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
 // same frame runs as one more workgroup of this launch (index n_planes).
 // The assembled plane is also written to rho_out (the charge mesh, for
 // inspection), then transformed as in k_fft_xy.  ONE: a one-frame launch
-// (the binning keeps its sites in registers, the planes use the direct sum).
-template <typename T, typename T2, bool ONE>
-__global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
+// (1024 threads; the binning keeps its sites in registers, the planes use
+// the direct sum).  P5: B-splines of order 5 (else any other order).
+template <typename T, typename T2, bool ONE, bool P5>
+__global__ __launch_bounds__(ONE ? SPREAD_THREADS_ONE : SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
                                                        BinArgs ba, T* __restrict__ rho_out,
                                                        T2* __restrict__ out_c, int n_planes) {
   // 16-byte alignment for the complex values and the FP64 LDS atomics
   extern __shared__ __align__(16) unsigned char smem[];
   if ((int)blockIdx.x >= n_planes) {
-    bin_block<SPREAD_THREADS, ONE>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
+    if constexpr (ONE)
+      bin_block<SPREAD_THREADS_ONE, true, BIN_BATCH_KEEP>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
+    else
+      bin_block<SPREAD_THREADS, false, BIN_BATCH>(ba, blockIdx.y, reinterpret_cast<int*>(smem));
     return;
   }
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
@@ -374,6 +378,12 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
   const double* q = ba.site_q;
   const double Lx = ba.cell.L[0], Ly = ba.cell.L[1], Lz = ba.cell.L[2];
   const double ihx = mi.invh[0], ihy = mi.invh[1], ihz = mi.invh[2];
+  // wrapped into the box through the reciprocal box lengths (the spread's
+  // weights vanish continuously at the stencil ends, so a last-bit
+  // difference from the binning's quotient is immaterial; the staging and
+  // the weights below use the same function, so they agree on the stencil)
+  const double rLx = 1.0 / Lx, rLy = 1.0 / Ly, rLz = 1.0 / Lz;
+  auto wrap = [](double x, double L, double rL) { return x - L * floor(x * rL); };
   // one staged (site, z slot) entry: the site's B-spline weights, then its
   // P x P in-plane contributions added with LDS atomics
   auto add_site = [&](int e) {
@@ -384,9 +394,10 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
     double zj = sz[j];
     if (!isfinite(zj)) zj = 0.0;
     T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
-    int fx = spline_triangle_d<T>(wrap_coord(xj, Lx) * ihx, P, Bx);
-    int fy = spline_triangle_d<T>(wrap_coord(yj, Ly) * ihy, P, By);
-    spline_triangle_d<T>(wrap_coord(zj, Lz) * ihz, P, Bz);
+    constexpr int ORD = P5 ? 5 : -1;
+    int fx = spline_triangle_d<T, ORD>(wrap(xj, Lx, rLx) * ihx, P, Bx);
+    int fy = spline_triangle_d<T, ORD>(wrap(yj, Ly, rLy) * ihy, P, By);
+    spline_triangle_d<T, ORD>(wrap(zj, Lz, rLz) * ihz, P, Bz);
     fx = ((fx % Kx) + Kx) % Kx;
     fy = ((fy % Ky) + Ky) % Ky;
     T wz = 0;
@@ -409,30 +420,35 @@ __global__ __launch_bounds__(SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, 
       }
     }
   };
-  // Staging, wavefront by wavefront: a thread reads the z of SPREAD_BATCH
-  // sites (the loads issued together); those whose stencil reaches the plane
-  // go to the wavefront's own list (ballot and prefix count: no atomics and
-  // no workgroup barrier), which the wavefront then works through with all
-  // its lanes, so that every wavefront shares the weights and the atomics.
+  // Staging, wavefront by wavefront, by the first SPREAD_THREADS threads
+  // (in a one-frame workgroup the others wait at the barrier: more
+  // wavefronts only thin out the lists): a thread reads the z of SB sites
+  // (the loads issued together); those whose stencil reaches the plane go to
+  // the wavefront's own list (ballot and prefix count: no atomics and no
+  // workgroup barrier), which the wavefront then works through with all its
+  // lanes, so that every wavefront shares the weights and the atomics.
   const int lane = threadIdx.x & (WAVE - 1);
-  int* wl = list + (threadIdx.x / WAVE) * (SPREAD_BATCH * WAVE);
+  constexpr int NT = SPREAD_THREADS;
+  constexpr int SB = SPREAD_LIST / NT;
+  int* wl = list + (threadIdx.x / WAVE) * (SB * WAVE);
   const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int base = 0; base < n; base += SPREAD_BATCH * SPREAD_THREADS) {
-    double zv[SPREAD_BATCH];
+  if (threadIdx.x < NT)
+  for (int base = 0; base < n; base += SPREAD_LIST) {
+    double zv[SB];
 #pragma unroll
-    for (int u = 0; u < SPREAD_BATCH; ++u) {
-      const int j = base + u * SPREAD_THREADS + (int)threadIdx.x;
+    for (int u = 0; u < SB; ++u) {
+      const int j = base + u * NT + (int)threadIdx.x;
       zv[u] = j < n ? sz[j] : 0.0;
     }
     int cnt = 0;
 #pragma unroll
-    for (int u = 0; u < SPREAD_BATCH; ++u) {
-      const int j = base + u * SPREAD_THREADS + (int)threadIdx.x;
+    for (int u = 0; u < SB; ++u) {
+      const int j = base + u * NT + (int)threadIdx.x;
       int tz = P;
       if (j < n) {
         double zj = zv[u];
         if (!isfinite(zj)) zj = 0.0;
-        int fz = spline_first(wrap_coord(zj, Lz) * ihz, P);
+        int fz = spline_first(wrap(zj, Lz, rLz) * ihz, P);
         fz = ((fz % Kz) + Kz) % Kz;
         tz = iz - fz;
         tz += (tz < 0) ? Kz : 0;
@@ -598,7 +614,7 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky) {
   return (2 * (size_t)Kx * Ky + Kx + Ky) * sizeof(T2) + (size_t)Kx * Ky * sizeof(T) +
-         (size_t)SPREAD_BATCH * SPREAD_THREADS * sizeof(int);
+         (size_t)SPREAD_LIST * sizeof(int);
 }
 
 
@@ -610,15 +626,15 @@ void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, co
   if (bin) lds = std::max(lds, bin_lds_spread(ba.n_site, ba.cell.n_cells));
   dim3 grid(np + (bin ? 1 : 0), n_frames);
   if (grid.x == 0) return;
-  if (n_frames == 1)
-    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, true>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, rho_out,
-                       out_c, np);
-  else
-    hipLaunchKernelGGL((k_fft_xy_spread<T, T2, false>), grid, dim3(SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, rho_out,
-                       out_c, np);
+  auto* k = n_frames == 1 ? (mi.order == 5 ? k_fft_xy_spread<T, T2, true, true> : k_fft_xy_spread<T, T2, true, false>)
+                          : (mi.order == 5 ? k_fft_xy_spread<T, T2, false, true> : k_fft_xy_spread<T, T2, false, false>);
+  hipLaunchKernelGGL(k, grid, dim3(n_frames == 1 ? SPREAD_THREADS_ONE : SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, rho_out,
+                     out_c, np);
 }
 
-size_t bin_lds_spread(int n_site, int n_cells) { return bin_body_lds<SPREAD_THREADS>(n_site, n_cells); }
+size_t bin_lds_spread(int n_site, int n_cells) {
+  return std::max(bin_body_lds<SPREAD_THREADS>(n_site, n_cells), bin_body_lds<SPREAD_THREADS_ONE>(n_site, n_cells));
+}
 
 template size_t fft_xy_spread_lds<double, double2>(int, int);
 template size_t fft_xy_spread_lds<float, float2>(int, int);

@@ -92,8 +92,8 @@ def test_step_parity_sites_crowded_into_one_layer(torch_dev):
     x[2] = rng.uniform(6.2, 6.4, w.n_site)
     wc = dataclasses.replace(w, site_xyz=x)
     # sites whose z stencil reaches each plane, per staging wavefront: the
-    # spread's 512 threads read sites u * 512 + thread (u < 8), so site j
-    # belongs to wavefront (j mod 512) // 64 of batch j // 4096
+    # spread's first 512 threads read sites u * 512 + thread (u < 8), so
+    # site j belongs to wavefront (j mod 512) // 64 of batch j // 4096
     u = x[2] / (w.box[2] / w.mesh[2])
     first = (np.floor(u - w.order / 2.0).astype(int) + 1) % w.mesh[2]
     j = np.arange(w.n_site)
@@ -126,6 +126,17 @@ def test_step_parity_plane_shapes(torch_dev, kx, ky):
     _say(f"[gpu] step tiny ff with PPPM, mesh {kx}x{ky}x64")
     w0, A, S = built("tiny", "ff")
     w = dataclasses.replace(w0, kspace="pppm", mesh=(kx, ky, 64))
+    check_step(torch_dev, w, A, S)
+
+
+@pytest.mark.parametrize("order", [3, 4, 6, 7])
+def test_step_parity_spline_orders(torch_dev, order):
+    """B-spline orders other than 5: the kernels evaluate the weights by the
+    Cox-de Boor triangle there and by closed-form quartics at order 5."""
+    import dataclasses
+    _say(f"[gpu] step tiny ff with PPPM, order {order}")
+    w0, A, S = built("tiny", "ff")
+    w = dataclasses.replace(w0, kspace="pppm", mesh=(16, 16, 64), order=order)
     check_step(torch_dev, w, A, S)
 
 
