@@ -41,7 +41,8 @@ size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? PairLds<T>::total : 4 * 
 // nothing this kernel writes, so they run beside the force workgroups).
 template <typename T, bool TWO, bool WALK>
 __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, SiteSet<T> st,
-                                                     ForceArgs<T> fa, int n_force_blocks, EnergyArgs en) {
+                                                     ForceArgs<T> fa, int n_force_blocks, EnergyArgs en,
+                                                     int walk_parts) {
   int bx = blockIdx.x, frame = blockIdx.y;
   if (gridDim.y > 1) {
     // many frames: each XCD takes a contiguous range of whole frames, so a
@@ -61,8 +62,16 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   __shared__ int fsp[4][3];
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
-  const int j = bx * (blockDim.x / WAVE) + wv;
-  if (j >= st.n) return;
+  // WALK with parts == 2: two wavefronts per site, each walking half of the
+  // site's electrode candidates (the walk is the kernel's longest chain); the
+  // second hands its sums to the first through LDS.  A wavefront past the
+  // last site mirrors it, writes nothing and still meets the barrier.
+  const int parts = WALK ? walk_parts : 1;
+  const int part = parts == 2 ? (wv & 1) : 0;
+  const int jw = parts == 2 ? bx * 2 + (wv >> 1) : bx * 4 + wv;
+  if (parts == 1 && jw >= st.n) return;
+  const bool live = jw < st.n;
+  const int j = live ? jw : st.n - 1;
   T* ws = reinterpret_cast<T*>(scratch + wv * wave_scratch_bytes<T>());
   WaveQueue<T> Q;
   Q.bind(ws);
@@ -83,10 +92,14 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
     for (int u = 0; u < 6; ++u) fe[u] = fep[(size_t)u * st.n + j];
   }
   const int cj = site_cell(cell, xj, yj, zj);
+  // the electrode runs of the site's cell, read before the k-space part so
+  // that their latency overlaps it
+  const int nruns = WALK ? elec_runs(el, cj, rlo, rhi) : 0;
+  if (WALK && parts == 2) split_runs(rlo, rhi, nruns, part, 2);
 
   // ---- k-space field at the site
   T ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0};
-  if (fa.Ea) {
+  if (fa.Ea && part == 0) {
     const int P = fa.mi.order;
     const int Kx = fa.mi.K[0], Ky = fa.mi.K[1], Kz = fa.mi.K[2], M = fa.mi.M;
     if (lane < 3) {
@@ -120,7 +133,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
       if (TWO) { eb[0] += w * fa.Eb[m]; eb[1] += w * fa.Eb[M + m]; eb[2] += w * fa.Eb[2 * M + m]; }
     }
   }
-  if (fa.Esite && lane == 0) {
+  if (fa.Esite && lane == 0 && part == 0) {
     const double* E = fa.Esite + (size_t)frame * 3 * st.n;
     ea[0] = (T)E[j]; ea[1] = (T)E[st.n + j]; ea[2] = (T)E[2 * st.n + j];
   }
@@ -131,7 +144,6 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   if (WALK) {
   // the charges in the atoms' sorted order, loaded with their positions
   const double* qa = fa.qa_s + (size_t)frame * fa.qa_frame_stride;
-  const int nruns = elec_runs(el, cj, rlo, rhi);
   int n = 0;
   walk_runs(rlo, rhi, nruns,
             [&](int k, bool v) {
@@ -166,15 +178,37 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   double F[3], FB[3];
   const T va[8] = {ea[0], ea[1], ea[2], fr[0], fr[1], fr[2], (T)0, (T)0};
   const T sa = wave_sum8(va);                 // lane 8k: total of va[k]
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-    F[d] = fa.out_scale * qj * ((double)read_lane(sa, 8 * d) + KE * ((double)read_lane(sa, 24 + 8 * d) + fpd[d]));
+  T sb = (T)0;
   if (TWO) {
     const T vb[8] = {eb[0], eb[1], eb[2], frb[0], frb[1], frb[2], (T)0, (T)0};
-    const T sb = wave_sum8(vb);
+    sb = wave_sum8(vb);
+  }
+  // walk sums of the site (both halves under WALK)
+  double wa[3], wb[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    wa[d] = (double)read_lane(sa, 24 + 8 * d);
+    wb[d] = TWO ? (double)read_lane(sb, 24 + 8 * d) : 0.0;
+  }
+  if (WALK && parts == 2) {
+    __shared__ double half[2][6];
+    const int sl = wv >> 1;
+    if (part == 1 && lane == 0) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) { half[sl][d] = wa[d]; half[sl][3 + d] = wb[d]; }
+    }
+    __syncthreads();
+    if (part == 1 || !live) return;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { wa[d] += half[sl][d]; wb[d] += half[sl][3 + d]; }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    F[d] = fa.out_scale * qj * ((double)read_lane(sa, 8 * d) + KE * (wa[d] + fpd[d]));
+  if (TWO) {
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      FB[d] = fa.out_scale * qj * ((double)read_lane(sb, 8 * d) + KE * ((double)read_lane(sb, 24 + 8 * d) + fe[3 + d]));
+      FB[d] = fa.out_scale * qj * ((double)read_lane(sb, 8 * d) + KE * (wb[d] + fe[3 + d]));
   } else {
     FB[0] = FB[1] = FB[2] = 0.0;
   }
@@ -208,21 +242,40 @@ void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
 template <typename T>
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
                           const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea) {
-  const int nfb = forces ? (st.n + 3) / 4 : 0;
-  dim3 grid(nfb + (ea ? 1 : 0), n_frames);
-  if (grid.x == 0) return;
-  const EnergyArgs e = ea ? *ea : EnergyArgs{};
   // TWO: a second charge set; WALK: the kernel walks the electrode atoms
   // itself (no site-electrode sums from the pair tiles)
   const bool two = fa.Eb || fa.qb, walk = fa.f_elec == nullptr;
+  // walking sites take two wavefronts each when all of them can be resident
+  // at once (otherwise the second half of the sites would wait for slots
+  // held by the first, whose halves wait for each other at a barrier)
+  int parts = 1;
+  if (walk && forces) {
+    static int resident[2] = {-1, -1};          // wavefronts of the walking kernel the device holds
+    int& r = resident[two ? 1 : 0];
+    if (r < 0) {
+      int dev = 0, cus = 0, blocks = 0;
+      hipGetDevice(&dev);
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (two)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, true, true>, 256, 0);
+      else
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, false, true>, 256, 0);
+      r = cus * blocks * 4;
+    }
+    parts = 2 * st.n * n_frames <= r ? 2 : 1;
+  }
+  const int nfb = forces ? (parts == 2 ? (st.n + 1) / 2 : (st.n + 3) / 4) : 0;
+  dim3 grid(nfb + (ea ? 1 : 0), n_frames);
+  if (grid.x == 0) return;
+  const EnergyArgs e = ea ? *ea : EnergyArgs{};
   if (two && walk)
-    hipLaunchKernelGGL((k_site_forces<T, true, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+    hipLaunchKernelGGL((k_site_forces<T, true, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
   else if (two)
-    hipLaunchKernelGGL((k_site_forces<T, true, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+    hipLaunchKernelGGL((k_site_forces<T, true, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
   else if (walk)
-    hipLaunchKernelGGL((k_site_forces<T, false, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+    hipLaunchKernelGGL((k_site_forces<T, false, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
   else
-    hipLaunchKernelGGL((k_site_forces<T, false, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e);
+    hipLaunchKernelGGL((k_site_forces<T, false, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
 }
 
 // explicit instantiations used by api.cpp

@@ -144,6 +144,31 @@ __device__ __forceinline__ int elec_runs(const ElecSet<T>& el, int c, int* rlo, 
   return nr;
 }
 
+// Keeps part `part` of `parts` of the candidates listed by the wavefront's
+// runs (the candidates counted in run order and cut into equal shares),
+// rewriting the run table in place; runs may come out empty.
+__device__ __forceinline__ void split_runs(int* rlo, int* rhi, int nruns, int part, int parts) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  int lo = 0, hi = 0;
+  if (lane < nruns) { lo = rlo[lane]; hi = rhi[lane]; }
+  const int len = hi - lo;
+  int incl = len;                               // inclusive prefix over the (at most 32) runs
+#pragma unroll
+  for (int off = 1; off < 32; off <<= 1) {
+    const int t = __shfl_up(incl, off, WAVE);
+    if (lane >= off) incl += t;
+  }
+  const int total = __shfl(incl, 31, WAVE);
+  const int a = (int)((long long)total * part / parts);
+  const int b = (int)((long long)total * (part + 1) / parts);
+  const int start = incl - len;
+  const int nlo = lo + max(0, min(len, a - start));
+  const int nhi = max(nlo, lo + max(0, min(len, b - start)));
+  __builtin_amdgcn_wave_barrier();
+  if (lane < nruns) { rlo[lane] = nlo; rhi[lane] = nhi; }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Walks the partners listed by the runs 64 at a time: load(k, valid)
 // returns the data of partner k (lane's index in the chunk), body(data, k,
 // valid) consumes it.  The loads of the next chunk are issued before the

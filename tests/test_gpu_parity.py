@@ -140,6 +140,20 @@ def test_step_parity_spline_orders(torch_dev, order):
     check_step(torch_dev, w, A, S)
 
 
+def test_step_parity_odd_site_count(torch_dev):
+    """99 sites: the one-frame site-force kernel pairs two wavefronts per
+    site when all of them fit on the device, and the last workgroup then
+    holds a single site (its second pair mirrors the last site and writes
+    nothing)."""
+    import dataclasses
+    _say("[gpu] step tiny ff with PPPM, 99 sites")
+    w0, A, S = built("tiny", "ff")
+    q = w0.site_q[:99].copy()
+    q[0] = 0.0                                   # keeps the electrolyte neutral
+    w = dataclasses.replace(w0, kspace="pppm", site_xyz=w0.site_xyz[:, :99].copy(), site_q=q)
+    check_step(torch_dev, w, A, S)
+
+
 def check_step(torch, w, A, S):
     es = cpm.Electrostatics(w, oracle_method(w))
     ref = cpm.step(w, A, S, es)
