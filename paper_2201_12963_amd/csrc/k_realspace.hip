@@ -232,6 +232,118 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   }
 }
 
+// The same when the pair tiles have already made the site-electrode sums
+// (many frames): no walk is left, only the interpolation, so 16 lanes take a
+// site and a wavefront four.  Every lane evaluates the site's three weight
+// sets itself and gathers the points t = sub, sub + 16, ... of the P^3
+// stencil; the 16 lanes then sum by butterfly shuffles.  A group past the
+// last site mirrors it and writes nothing.
+template <typename T, bool TWO>
+__global__ __launch_bounds__(256) void k_site_forces_g16(SiteSet<T> st, ForceArgs<T> fa, int n_force_blocks,
+                                                         EnergyArgs en) {
+  int bx = blockIdx.x, frame = blockIdx.y;
+  if (gridDim.y > 1) {
+    // each XCD takes a contiguous range of whole frames (as k_site_forces)
+    const int L = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    frame = L / gridDim.x;
+    bx = L - frame * gridDim.x;
+  }
+  if (bx >= n_force_blocks) {
+    energy_block(en, frame);
+    return;
+  }
+  const int sub = threadIdx.x & 15;
+  const int jw = bx * (blockDim.x / 16) + (threadIdx.x >> 4);
+  const bool live = jw < st.n;
+  const int j = live ? jw : st.n - 1;
+  const size_t fo = (size_t)frame * st.n;
+  const double xj = st.x[fo + j], yj = st.y[fo + j], zj = st.z[fo + j];
+  const double qj = st.q[fo + j];
+  const int orig = st.order[fo + j];
+  const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
+  const double* fep = fa.f_elec + (size_t)frame * 6 * st.n;
+  double fpd[3], fe[6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) fpd[d] = fp[(size_t)d * st.n + j];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) fe[u] = fep[(size_t)u * st.n + j];
+
+  T ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0};
+  if (fa.Ea) {
+    const int P = fa.mi.order;
+    const int Kx = fa.mi.K[0], Ky = fa.mi.K[1], Kz = fa.mi.K[2], M = fa.mi.M;
+    T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
+    int fx = spline_triangle_d<T>(xj * fa.mi.invh[0], P, Bx);
+    int fy = spline_triangle_d<T>(yj * fa.mi.invh[1], P, By);
+    int fz = spline_triangle_d<T>(zj * fa.mi.invh[2], P, Bz);
+    fx = ((fx % Kx) + Kx) % Kx;
+    fy = ((fy % Ky) + Ky) % Ky;
+    fz = ((fz % Kz) + Kz) % Kz;
+    const T* Ef = fa.Ea + (size_t)frame * fa.Ea_frame_stride;
+    // point t = (tz P + ty) P + tx: quotients through a float reciprocal,
+    // exact for t < 7^3 (the fractions stay >= 1/98 away from integers)
+    const float invP = 1.0f / (float)P, invP2 = 1.0f / (float)(P * P);
+    for (int t = sub; t < P * P * P; t += 16) {
+      const int tz = (int)(((float)t + 0.5f) * invP2);
+      const int rz = t - tz * P * P;
+      const int ty = (int)(((float)rz + 0.5f) * invP);
+      const int tx = rz - ty * P;
+      // weight of stencil offset o along an axis: B[P - 1 - o] (selected,
+      // not indexed, so that the weights stay in registers)
+      T wx = 0, wy = 0, wz = 0;
+#pragma unroll
+      for (int b = 0; b < MAX_ORDER; ++b) {
+        wx = (b == P - 1 - tx) ? Bx[b] : wx;
+        wy = (b == P - 1 - ty) ? By[b] : wy;
+        wz = (b == P - 1 - tz) ? Bz[b] : wz;
+      }
+      int ix = fx + tx; ix -= (ix >= Kx) ? Kx : 0;
+      int iy = fy + ty; iy -= (iy >= Ky) ? Ky : 0;
+      int iz = fz + tz; iz -= (iz >= Kz) ? Kz : 0;
+      const int m = (iz * Ky + iy) * Kx + ix;
+      const T w = wx * wy * wz;
+      ea[0] += w * Ef[m]; ea[1] += w * Ef[M + m]; ea[2] += w * Ef[2 * M + m];
+      if (TWO) { eb[0] += w * fa.Eb[m]; eb[1] += w * fa.Eb[M + m]; eb[2] += w * fa.Eb[2 * M + m]; }
+    }
+  } else if (fa.Esite && sub == 0) {
+    const double* E = fa.Esite + (size_t)frame * 3 * st.n;
+    ea[0] = (T)E[j]; ea[1] = (T)E[st.n + j]; ea[2] = (T)E[2 * st.n + j];
+  }
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      ea[d] += __shfl_xor(ea[d], off, 16);
+      if (TWO) eb[d] += __shfl_xor(eb[d], off, 16);
+    }
+  }
+  double F[3], FB[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    F[d] = fa.out_scale * qj * ((double)ea[d] + KE * (fpd[d] + fe[d]));
+    FB[d] = TWO ? fa.out_scale * qj * ((double)eb[d] + KE * fe[3 + d]) : 0.0;
+  }
+  F[2] += qj * fa.field;
+  FB[2] += qj * fa.fieldb;
+  if (!live) return;
+  if (fa.f_comp) {
+    if (sub < 6) {
+      const double val = sub == 0 ? F[0] : sub == 1 ? F[1] : sub == 2 ? F[2]
+                       : sub == 3 ? FB[0] : sub == 4 ? FB[1] : FB[2];
+      fa.f_comp[((size_t)frame * 6 + sub) * st.n + orig] = val;
+    }
+    return;
+  }
+  double* fout = fa.f_out + (size_t)frame * fa.f_frame_stride;
+  for (int v = sub; v < fa.n_dv; v += 16) {
+    const double dv = fa.dv ? fa.dv[v] : 0.0;
+    double* o = fout + (size_t)v * 3 * st.n;
+    o[orig] = F[0] + dv * FB[0];
+    o[st.n + orig] = F[1] + dv * FB[1];
+    o[2 * st.n + orig] = F[2] + dv * FB[2];
+  }
+}
+
 template <typename T>
 void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
   if (pa.n_blocks == 0 || n_frames == 0) return;
@@ -264,18 +376,25 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
     }
     parts = 2 * st.n * n_frames <= r ? 2 : 1;
   }
+  const EnergyArgs e = ea ? *ea : EnergyArgs{};
+  if (!walk) {
+    // sixteen lanes per site
+    const int nfb = forces ? (st.n + 15) / 16 : 0;
+    dim3 grid(nfb + (ea ? 1 : 0), n_frames);
+    if (grid.x == 0) return;
+    if (two)
+      hipLaunchKernelGGL((k_site_forces_g16<T, true>), grid, dim3(256), 0, s, st, fa, nfb, e);
+    else
+      hipLaunchKernelGGL((k_site_forces_g16<T, false>), grid, dim3(256), 0, s, st, fa, nfb, e);
+    return;
+  }
   const int nfb = forces ? (parts == 2 ? (st.n + 1) / 2 : (st.n + 3) / 4) : 0;
   dim3 grid(nfb + (ea ? 1 : 0), n_frames);
   if (grid.x == 0) return;
-  const EnergyArgs e = ea ? *ea : EnergyArgs{};
-  if (two && walk)
+  if (two)
     hipLaunchKernelGGL((k_site_forces<T, true, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
-  else if (two)
-    hipLaunchKernelGGL((k_site_forces<T, true, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
-  else if (walk)
-    hipLaunchKernelGGL((k_site_forces<T, false, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
   else
-    hipLaunchKernelGGL((k_site_forces<T, false, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
+    hipLaunchKernelGGL((k_site_forces<T, false, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
 }
 
 // explicit instantiations used by api.cpp
