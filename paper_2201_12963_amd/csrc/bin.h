@@ -128,9 +128,13 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   const int per_wave = ((n_site + NW - 1) / NW + WAVE - 1) / WAVE * WAVE;
   const int lo = wave * per_wave;
   const int hi = min(n_site, lo + per_wave);
+  // (the next batch's keys are read before this batch's ballots, so that
+  // their LDS latency overlaps them)
+  int key_next = (lo + lane < hi) ? cid[lo + lane] : n_cells;
   for (int base = lo; base < hi; base += WAVE) {
     const int i = base + lane;
-    const int key = (i < hi) ? cid[i] : n_cells;
+    const int key = key_next;
+    key_next = (i + WAVE < hi) ? cid[i + WAVE] : n_cells;
     unsigned long long eq = ~0ull;
     for (int b = 0; b < nbits; ++b) {
       const unsigned long long bb = __ballot((key >> b) & 1);
@@ -146,7 +150,8 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
   }
   __syncthreads();
 
-  // 3. offsets: per cell, exclusive over waves; then exclusive scan over cells
+  // 3. offsets: per cell, exclusive over waves (hist); then exclusive scan
+  // over cells (tot); a site goes to tot + hist + rank
   for (int c = tid; c < n_cells; c += NT) {
     int run = 0;
     for (int w = 0; w < NW; ++w) {
@@ -176,8 +181,6 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
     if (lane == 0) cell_start[n_cells] = carry;
   }
   __syncthreads();
-  for (int i = tid; i < NW * n_cells; i += NT) hist[i] += tot[i % n_cells];
-  __syncthreads();
 
   // 4. placement, every site independently
   double* sx = a.sx_all + (size_t)frame * n_site;
@@ -200,7 +203,8 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
         if (!KEEP) { xv[u] = wx[i]; yv[u] = wy[i]; zv[u] = wz[i]; qv[u] = a.site_q[i]; }
         else if (!first) { xv[u] = x[i]; yv[u] = y[i]; zv[u] = z[i]; qv[u] = a.site_q[i]; }
         const int rw = rnk[i];
-        pv[u] = hist[(rw >> 24) * n_cells + cid[i]] + (rw & 0xffffff);
+        const int c = cid[i];
+        pv[u] = tot[c] + hist[(rw >> 24) * n_cells + c] + (rw & 0xffffff);
       }
     }
 #pragma unroll
