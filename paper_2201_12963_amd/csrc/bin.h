@@ -181,6 +181,12 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
     if (lane == 0) cell_start[n_cells] = carry;
   }
   __syncthreads();
+  if (!KEEP) {
+    // (many frames: the cell starts folded into the offsets here, one
+    // register fewer in step 4, which keeps the spread's occupancy)
+    for (int i = tid; i < NW * n_cells; i += NT) hist[i] += tot[i % n_cells];
+    __syncthreads();
+  }
 
   // 4. placement, every site independently
   double* sx = a.sx_all + (size_t)frame * n_site;
@@ -204,7 +210,7 @@ __device__ __forceinline__ void bin_block(const BinArgs& a, int frame, int* lds)
         else if (!first) { xv[u] = x[i]; yv[u] = y[i]; zv[u] = z[i]; qv[u] = a.site_q[i]; }
         const int rw = rnk[i];
         const int c = cid[i];
-        pv[u] = tot[c] + hist[(rw >> 24) * n_cells + c] + (rw & 0xffffff);
+        pv[u] = (KEEP ? tot[c] : 0) + hist[(rw >> 24) * n_cells + c] + (rw & 0xffffff);
       }
     }
 #pragma unroll
