@@ -42,8 +42,17 @@ __device__ __forceinline__ float erfc_from_exp(float x, float) { return erfcf(x)
 
 __device__ __forceinline__ double t_exp(double x) { return exp(x); }
 __device__ __forceinline__ float t_exp(float x) { return expf(x); }
-__device__ __forceinline__ double t_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float t_sqrt(float x) { return sqrtf(x); }
+// 1/sqrt(x), x > 0: the hardware estimate refined by two Newton steps
+// y <- y (3 - x y^2) / 2 (each squares the relative error, so the estimate's
+// ~1e-7 falls below FP64 rounding); float: 1/sqrtf
+__device__ __forceinline__ double t_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ float t_rsqrt(float x) { return 1.0f / sqrtf(x); }
 
 // ------------------------------------------------------- pair compaction
 //
@@ -253,10 +262,11 @@ constexpr double ETA_R_SKIP = 6.5;
 template <typename T>
 __device__ __forceinline__ T g1_potential(T dx, T dy, T dz, T q, T alpha, T eta) {
   T r2 = dx * dx + dy * dy + dz * dz;
-  T r = t_sqrt(r2);
+  const T ir = t_rsqrt(r2);
+  const T r = r2 * ir;
   T e = erfc_from_exp(alpha * r, t_exp(-alpha * alpha * r2));
   if (eta * r < (T)ETA_R_SKIP) e -= erfc_from_exp(eta * r, t_exp(-eta * eta * r2));
-  return q * e / r;
+  return q * e * ir;
 }
 
 // Real-space electrolyte potential at electrode atom g of a frame, one
@@ -313,8 +323,8 @@ __device__ __forceinline__ void real_b_wave(const Cell& cell, T alpha, T eta, do
 template <typename T>
 __device__ __forceinline__ void g0_terms(T r2, T alpha, T& g, T& pot) {
   const T two_over_sqrtpi = (T)1.1283791670955126;
-  T r = t_sqrt(r2);
-  T ir = (T)1 / r;
+  const T ir = t_rsqrt(r2);
+  const T r = r2 * ir;
   T ex = t_exp(-alpha * alpha * r2);
   T ec = erfc_from_exp(alpha * r, ex);
   g = (ec * ir + two_over_sqrtpi * alpha * ex) * ir * ir;
@@ -323,8 +333,8 @@ __device__ __forceinline__ void g0_terms(T r2, T alpha, T& g, T& pot) {
 template <typename T>
 __device__ __forceinline__ T g1_force(T r2, T alpha, T eta) {
   const T two_over_sqrtpi = (T)1.1283791670955126;
-  T r = t_sqrt(r2);
-  T ir = (T)1 / r;
+  const T ir = t_rsqrt(r2);
+  const T r = r2 * ir;
   T ex = t_exp(-alpha * alpha * r2);
   T e = erfc_from_exp(alpha * r, ex);
   T x = alpha * ex;
