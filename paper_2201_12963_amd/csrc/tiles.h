@@ -191,6 +191,43 @@ __device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const T
     __syncthreads();
     const int n_iter = nck > 0 ? (nck + m.nsl - 1) / m.nsl : 0;
     int n = 0;
+    if (no_img) {
+      // two candidates per step: their tests are independent chains that
+      // the compiler interleaves (three wavefronts per SIMD hide little)
+      for (int it = 0; it < n_iter; it += 2) {
+        double px[2], py[2], pz[2];
+        T qa[2], qb[2];
+        bool in[2];
+        T dx[2], dy[2], dz[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = m.sl + (it + h) * m.nsl;
+          const bool valid = m.act && it + h < n_iter && k < nck;
+          px[h] = xt; py[h] = yt; pz[h] = zt;
+          qa[h] = 0; qb[h] = 0;
+          int pk = -1;
+          if (valid) {
+            px[h] = C.x[k]; py[h] = C.y[k]; pz[h] = C.z[k];
+            qa[h] = C.q[0][k]; qb[h] = C.q[1][k]; pk = C.k[k];
+          }
+          const Disp d = min_disp(cell, xt, yt, zt, px[h], py[h], pz[h]);
+          dx[h] = (T)d.d0; dy[h] = (T)d.d1; dz[h] = (T)d.d2;
+          in[h] = d.d0 * d.d0 + d.d1 * d.d1 + d.d2 * d.d2 < rc2 && valid && !(self_excl && pk == j);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const T val[5] = {dx[h], dy[h], dz[h], qa[h], qb[h]};
+          n = tq_push(Q, n, in[h], val, m.ti);
+          if (n >= WAVE) {
+            eval(lane);
+            n = tq_pop(Q, n);
+          }
+        }
+      }
+      if (lane < n) eval(lane);
+      if (c0 + TILE_CAND >= total) break;
+      continue;
+    }
     for (int it = 0; it < n_iter; ++it) {
       const int k = m.sl + it * m.nsl;
       const bool valid = m.act && k < nck;
@@ -200,17 +237,6 @@ __device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const T
       if (valid) { px = C.x[k]; py = C.y[k]; pz = C.z[k]; qa = C.q[0][k]; qb = C.q[1][k]; pk = C.k[k]; }
       const bool self_pk = self_excl && pk == j;
       const Disp d = min_disp(cell, xt, yt, zt, px, py, pz);
-      if (no_img) {
-        T dx, dy, dz;
-        const bool in = image_pair(cell, d, 0, 0, 0, rc2, dx, dy, dz) && valid && !self_pk;
-        const T val[5] = {dx, dy, dz, qa, qb};
-        n = tq_push(Q, n, in, val, m.ti);
-        if (n >= WAVE) {
-          eval(lane);
-          n = tq_pop(Q, n);
-        }
-        continue;
-      }
       for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
         for (int iy = -cell.img[1]; iy <= cell.img[1]; ++iy)
           for (int iz = -cell.img[2]; iz <= cell.img[2]; ++iz) {
