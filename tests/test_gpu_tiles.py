@@ -3,7 +3,7 @@ take their less common branches, against the oracle and the single-frame
 path (one wavefront per target):
 
   * sites crowded into one slab: a cell holds more targets than one tile
-    chunk (64) and a stencil more candidates than one LDS pass (512);
+    chunk (64) and a stencil more candidates than two LDS passes (2 x 256);
   * the tiny cell run with PPPM: cells narrower than 2 rcut, so every pair
     test loops over periodic images;
   * a batch large enough for the frames-per-launch tuner, whose frames land
