@@ -186,7 +186,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 431360, "sources_sha256": "0d12469061c8c328790741ba36abb88e5cbe53f794053541dcb869e8415c8a05"}}
+TRAFFIC = {"site_pairs": {"bytes": 423168, "sources_sha256": "aa369475a3320ef38780c913fff79a4001e9b2f71dc49011b570074429c13ff6"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
