@@ -31,15 +31,17 @@ template <typename T>
 size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? PairLds<T>::total : 4 * wave_scratch_bytes<T>(); }
 
 
-// The rest of the force on every site, once the electrode charges are known:
-// pairs with the electrode Gaussians (g1); the k-space field, interpolated
-// from the mesh with the site's B-spline weights (three lanes build the
-// weights of one axis each in LDS, then the lanes run over the P^3 points)
-// or taken from the explicit Ewald sum; the site-site sum of k_site_pairs;
-// the applied field.  One wavefront per site.  Workgroups from
-// n_force_blocks on reduce the energies of their frame instead (they read
-// nothing this kernel writes, so they run beside the force workgroups).
-template <typename T, bool TWO, bool WALK>
+// The rest of the force on every site, once the electrode charges are known
+// (one-frame launches; many-frame ones take k_site_forces_g16 below): pairs
+// with the electrode Gaussians (g1), walked here; the k-space field,
+// interpolated from the mesh with the site's B-spline weights (three lanes
+// build the weights of one axis each in LDS, then the lanes run over the P^3
+// points) or taken from the explicit Ewald sum; the site-site sum of
+// k_site_pairs; the applied field.  One wavefront per site (or two, see
+// below).  Workgroups from n_force_blocks on reduce the energies of their
+// frame instead (they read nothing this kernel writes, so they run beside
+// the force workgroups).
+template <typename T, bool TWO>
 __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, SiteSet<T> st,
                                                      ForceArgs<T> fa, int n_force_blocks, EnergyArgs en,
                                                      int walk_parts) {
@@ -62,11 +64,11 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   __shared__ int fsp[4][3];
   const int lane = threadIdx.x & (WAVE - 1);
   const int wv = threadIdx.x >> 6;
-  // WALK with parts == 2: two wavefronts per site, each walking half of the
-  // site's electrode candidates (the walk is the kernel's longest chain); the
+  // parts == 2: two wavefronts per site, each walking half of the site's
+  // electrode candidates (the walk is the kernel's longest chain); the
   // second hands its sums to the first through LDS.  A wavefront past the
   // last site mirrors it, writes nothing and still meets the barrier.
-  const int parts = WALK ? walk_parts : 1;
+  const int parts = walk_parts;
   const int part = parts == 2 ? (wv & 1) : 0;
   const int jw = parts == 2 ? bx * 2 + (wv >> 1) : bx * 4 + wv;
   if (parts == 1 && jw >= st.n) return;
@@ -84,18 +86,11 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   const int orig = st.order[fo + j];
   const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
   const double fp0 = fp[j], fp1 = fp[st.n + j], fp2 = fp[2 * (size_t)st.n + j];
-  // site-electrode sums made by the pair tiles (WALK == false)
-  double fe[6] = {0, 0, 0, 0, 0, 0};
-  if (!WALK) {
-    const double* fep = fa.f_elec + (size_t)frame * 6 * st.n;
-#pragma unroll
-    for (int u = 0; u < 6; ++u) fe[u] = fep[(size_t)u * st.n + j];
-  }
   const int cj = site_cell(cell, xj, yj, zj);
   // the electrode runs of the site's cell, read before the k-space part so
   // that their latency overlaps it
-  const int nruns = WALK ? elec_runs(el, cj, rlo, rhi) : 0;
-  if (WALK && parts == 2) split_runs(rlo, rhi, nruns, part, 2);
+  const int nruns = elec_runs(el, cj, rlo, rhi);
+  if (parts == 2) split_runs(rlo, rhi, nruns, part, 2);
 
   // ---- k-space field at the site
   T ea[3] = {0, 0, 0}, eb[3] = {0, 0, 0};
@@ -141,7 +136,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   // ---- real space: electrode Gaussians (g1)
   T fr[3] = {0, 0, 0};
   T frb[3] = {0, 0, 0};
-  if (WALK) {
+  {
   // the charges in the atoms' sorted order, loaded with their positions
   const double* qa = fa.qa_s + (size_t)frame * fa.qa_frame_stride;
   int n = 0;
@@ -174,7 +169,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   }
 
   // ---- reduce and write
-  const double fpd[3] = {fp0 + fe[0], fp1 + fe[1], fp2 + fe[2]};
+  const double fpd[3] = {fp0, fp1, fp2};
   double F[3], FB[3];
   const T va[8] = {ea[0], ea[1], ea[2], fr[0], fr[1], fr[2], (T)0, (T)0};
   const T sa = wave_sum8(va);                 // lane 8k: total of va[k]
@@ -183,14 +178,14 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
     const T vb[8] = {eb[0], eb[1], eb[2], frb[0], frb[1], frb[2], (T)0, (T)0};
     sb = wave_sum8(vb);
   }
-  // walk sums of the site (both halves under WALK)
+  // walk sums of the site (both halves when split)
   double wa[3], wb[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     wa[d] = (double)read_lane(sa, 24 + 8 * d);
     wb[d] = TWO ? (double)read_lane(sb, 24 + 8 * d) : 0.0;
   }
-  if (WALK && parts == 2) {
+  if (parts == 2) {
     __shared__ double half[2][6];
     const int sl = wv >> 1;
     if (part == 1 && lane == 0) {
@@ -208,7 +203,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   if (TWO) {
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      FB[d] = fa.out_scale * qj * ((double)read_lane(sb, 8 * d) + KE * (wb[d] + fe[3 + d]));
+      FB[d] = fa.out_scale * qj * ((double)read_lane(sb, 8 * d) + KE * wb[d]);
   } else {
     FB[0] = FB[1] = FB[2] = 0.0;
   }
@@ -354,24 +349,26 @@ void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
 template <typename T>
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
                           const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea) {
-  // TWO: a second charge set; WALK: the kernel walks the electrode atoms
-  // itself (no site-electrode sums from the pair tiles)
+  // TWO: a second charge set; walk: the kernel walks the electrode atoms
+  // itself (no site-electrode sums from the pair tiles; else k_site_forces_g16)
   const bool two = fa.Eb || fa.qb, walk = fa.f_elec == nullptr;
   // walking sites take two wavefronts each when all of them can be resident
   // at once (otherwise the second half of the sites would wait for slots
   // held by the first, whose halves wait for each other at a barrier)
   int parts = 1;
   if (walk && forces) {
-    static int resident[2] = {-1, -1};          // wavefronts of the walking kernel the device holds
-    int& r = resident[two ? 1 : 0];
-    if (r < 0) {
-      int dev = 0, cus = 0, blocks = 0;
-      hipGetDevice(&dev);
+    // wavefronts of the walking kernel a device holds, per device (up to 16)
+    static int resident[16][2] = {};
+    int dev = 0;
+    hipGetDevice(&dev);
+    int& r = resident[dev & 15][two ? 1 : 0];
+    if (r <= 0) {
+      int cus = 0, blocks = 0;
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       if (two)
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, true, true>, 256, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, true>, 256, 0);
       else
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, false, true>, 256, 0);
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, false>, 256, 0);
       r = cus * blocks * 4;
     }
     parts = 2 * st.n * n_frames <= r ? 2 : 1;
@@ -392,9 +389,9 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
   dim3 grid(nfb + (ea ? 1 : 0), n_frames);
   if (grid.x == 0) return;
   if (two)
-    hipLaunchKernelGGL((k_site_forces<T, true, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
+    hipLaunchKernelGGL((k_site_forces<T, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
   else
-    hipLaunchKernelGGL((k_site_forces<T, false, true>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
+    hipLaunchKernelGGL((k_site_forces<T, false>), grid, dim3(256), 0, s, cell, el, st, fa, nfb, e, parts);
 }
 
 // explicit instantiations used by api.cpp
