@@ -232,12 +232,17 @@ __device__ T2* plane_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int n
 // One Stockham stage of radix R over one contiguous line, by the lanes of
 // one wavefront (no workgroup barrier; the caller orders the stages)
 template <int R, typename T2>
-__device__ __forceinline__ void fft_stage_w(const T2* src, T2* dst, int N, int Ns, const T2* tw, int sigma) {
+__device__ __forceinline__ void fft_stage_w(const T2* src0, T2* dst0, int N, int Ns, const T2* tw, int sigma, int nl,
+                                            int lstride) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int nb = N / R;
   const int tstep = N / (Ns * R);
-  const float rns = 1.0f / (float)Ns;
-  for (int j = lane; j < nb; j += WAVE) {
+  const float rns = 1.0f / (float)Ns, rnb = 1.0f / (float)nb;
+  for (int u = lane; u < nl * nb; u += WAVE) {
+    const int l = nl > 1 ? div_small(u, rnb) : 0;
+    const int j = u - l * nb;
+    const T2* src = src0 + l * lstride;
+    T2* dst = dst0 + l * lstride;
     T2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
@@ -258,12 +263,12 @@ __device__ __forceinline__ void fft_stage_w(const T2* src, T2* dst, int N, int N
   }
 }
 
-// Transform one line of p.n points held in a wavefront's own LDS buffer a,
-// ping-ponging with b; the stages are ordered by wavefront barriers only
-// (a wavefront's LDS operations complete in order).  Returns the buffer
-// holding the result.
+// Transform nl lines of p.n points (lstride apart) held in a wavefront's own
+// LDS buffer a, ping-ponging with b; the stages are ordered by wavefront
+// barriers only (a wavefront's LDS operations complete in order).  Returns
+// the buffer holding the result.
 template <typename T2>
-__device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int sigma) {
+__device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int sigma, int nl = 1, int lstride = 0) {
   const int N = p.n;
   T2* src = a;
   T2* dst = b;
@@ -272,10 +277,10 @@ __device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int si
   for (int f = 0; f < p.nfac; ++f) {
     const int R = p.fac[f];
     switch (R) {
-      case 2: fft_stage_w<2>(src, dst, N, Ns, tw, sigma); break;
-      case 3: fft_stage_w<3>(src, dst, N, Ns, tw, sigma); break;
-      case 4: fft_stage_w<4>(src, dst, N, Ns, tw, sigma); break;
-      default: fft_stage_w<5>(src, dst, N, Ns, tw, sigma); break;
+      case 2: fft_stage_w<2>(src, dst, N, Ns, tw, sigma, nl, lstride); break;
+      case 3: fft_stage_w<3>(src, dst, N, Ns, tw, sigma, nl, lstride); break;
+      case 4: fft_stage_w<4>(src, dst, N, Ns, tw, sigma, nl, lstride); break;
+      default: fft_stage_w<5>(src, dst, N, Ns, tw, sigma, nl, lstride); break;
     }
     __builtin_amdgcn_wave_barrier();
     T2* t = src; src = dst; dst = t;
@@ -491,15 +496,16 @@ template <typename T> __device__ __forceinline__ T mode_k(int i, int K, T twopi_
 // mode 1 (field):     X = FFT_z(data1) (+ save if add_saved);
 //          data1 = IFFT_z((-i kx + ky) G X)  [Ex + i Ey after the x-y inverse]
 //          data2 = IFFT_z(-i kz G X)         [Ez]
-template <typename T, typename T2>
+// MULTI: many frames, lpw columns per wavefront (else one, and hosted work)
+template <typename T, typename T2, bool MULTI>
 __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
                                                T2* __restrict__ data1, T2* __restrict__ data2,
                                                T2* __restrict__ save, int add_saved,
                                                double* __restrict__ energy_part, int n_z_blocks,
-                                               RealBArgs<T> rb, PairArgs<T> pa) {
+                                               RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
-  if ((int)blockIdx.x >= n_z_blocks) {
+  if (!MULTI && (int)blockIdx.x >= n_z_blocks) {
     // hosted work, one wavefront per target: the real-space part of b
     // (electrode atoms), then the site-site forces (sites)
     // (hosted work is always the one-wavefront-per-target form; the launcher
@@ -515,99 +521,123 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
     }
     return;
   }
-  // one wavefront per (x, y) column of Kz points, za.cpw columns per
-  // workgroup; each wavefront has its own three LDS lines and synchronises
-  // only with itself
+  // one wavefront per lpw (x, y) columns of Kz points (lpw = 1 for one
+  // frame; many frames put up to four short columns in a wavefront, so that
+  // the stages fill its lanes), za.cpw wavefronts per workgroup; each
+  // wavefront has its own three LDS buffers of lpw lines and synchronises
+  // only with itself.  Lane l always takes column l mod lpw, points
+  // l / lpw + u 64 / lpw of it.
   const int Kx = za.Kx, Ky = za.Ky, Kz = za.Kz;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+  const int L = MULTI ? lpw : 1, zs = WAVE / L;            // lpw divides 64
   T2* twz = reinterpret_cast<T2*>(smem);
-  T2* A = twz + Kz + (size_t)wv * 3 * Kz;
-  T2* B = A + Kz;
-  T2* C = B + Kz;
+  T2* A = twz + Kz + (size_t)wv * 3 * L * Kz;
+  T2* B = A + L * Kz;
+  T2* C = B + L * Kz;
   load_twiddles(pz, twz);
-  const int col = blockIdx.x * za.cpw + wv;
-  const bool active = wv < za.cpw && col < Kx * Ky;
+  const int c = lane & (L - 1);                            // this lane's column of the wavefront
+  const int z0 = lane / L;
+  const int col = (blockIdx.x * za.cpw + wv) * L + c;
+  const bool wave_on = wv < za.cpw && (blockIdx.x * za.cpw + wv) * L < Kx * Ky;
+  const bool active = wave_on && col < Kx * Ky;            // this lane's column exists
   const int y = active ? col / Kx : 0, x = active ? col - y * Kx : 0;
   const size_t fo = (size_t)blockIdx.y * Kx * Ky * Kz;
   const size_t plane = (size_t)Kx * Ky;
   const size_t cxy = (size_t)y * Kx + x;                   // point z of the column: z * plane + cxy
-  // the column, and the multiplier (and saved spectrum) of this lane's
+  T2* Al = A + c * Kz;
+  // the columns, and the multiplier (and saved spectrum) of this lane's
   // points, loaded together so that their latencies overlap
   T gk[ZPASS_PREFETCH];
   T2 sv[ZPASS_PREFETCH];
 #pragma unroll
   for (int u = 0; u < ZPASS_PREFETCH; ++u) {
-    const int z = lane + u * WAVE;
+    const int z = z0 + u * zs;
     gk[u] = (T)0;
     sv[u] = T2{(T)0, (T)0};
     if (active && z < Kz) {
-      A[z] = data1[fo + z * plane + cxy];
+      Al[z] = data1[fo + z * plane + cxy];
       gk[u] = G[z * plane + cxy];
       if (za.mode == 1 && add_saved) sv[u] = save[fo + z * plane + cxy];
     }
   }
   if (active)
-    for (int z = lane + ZPASS_PREFETCH * WAVE; z < Kz; z += WAVE) A[z] = data1[fo + z * plane + cxy];
+    for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs) Al[z] = data1[fo + z * plane + cxy];
   __syncthreads();                                         // twiddles
   double e = 0.0;
-  if (active) {
-    T2* X = fft_line_w(A, B, pz, twz, -1);
+  if (wave_on) {
+    T2* X = fft_line_w(A, B, pz, twz, -1, L, Kz);
     T2* F1 = (X == A) ? B : A;
+    T2* Xl = X + c * Kz;
+    T2* F1l = F1 + c * Kz;
     if (za.mode == 0) {
       // X <- G X (energy partial 1/2 sum G |X|^2; X saved for the field pass)
       auto mul = [&](int z, T g) {
-        const T2 v = X[z];
+        const T2 v = Xl[z];
         if (save) save[fo + z * plane + cxy] = v;
         e += (double)g * ((double)v.x * v.x + (double)v.y * v.y);
-        X[z] = T2{v.x * g, v.y * g};
+        Xl[z] = T2{v.x * g, v.y * g};
       };
+      if (active) {
 #pragma unroll
-      for (int u = 0; u < ZPASS_PREFETCH; ++u)
-        if (lane + u * WAVE < Kz) mul(lane + u * WAVE, gk[u]);
-      for (int z = lane + ZPASS_PREFETCH * WAVE; z < Kz; z += WAVE) mul(z, G[z * plane + cxy]);
-      T2* Y = fft_line_w(X, F1, pz, twz, +1);
-      for (int z = lane; z < Kz; z += WAVE) data1[fo + z * plane + cxy] = Y[z];
+        for (int u = 0; u < ZPASS_PREFETCH; ++u)
+          if (z0 + u * zs < Kz) mul(z0 + u * zs, gk[u]);
+        for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs) mul(z, G[z * plane + cxy]);
+      }
+      T2* Y = fft_line_w(X, F1, pz, twz, +1, L, Kz);
+      if (active)
+        for (int z = z0; z < Kz; z += zs) data1[fo + z * plane + cxy] = Y[c * Kz + z];
     } else {
       // C keeps G X; the first inverse transforms (-i kx + ky) G X (Ex + i Ey
       // after the x-y inverse), the second -i kz G X (Ez)
       const T kx = mode_k<T>(x, Kx, (T)za.twopi_L[0]);
       const T ky = mode_k<T>(y, Ky, (T)za.twopi_L[1]);
+      T2* Cl = C + c * Kz;
       auto mul = [&](int z, T g, T2 w) {
-        T2 v = X[z];
+        T2 v = Xl[z];
         if (add_saved) { v.x += w.x; v.y += w.y; }
         v = T2{v.x * g, v.y * g};
-        C[z] = v;
-        F1[z] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};
+        Cl[z] = v;
+        F1l[z] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};
       };
+      if (active) {
 #pragma unroll
-      for (int u = 0; u < ZPASS_PREFETCH; ++u)
-        if (lane + u * WAVE < Kz) mul(lane + u * WAVE, gk[u], sv[u]);
-      for (int z = lane + ZPASS_PREFETCH * WAVE; z < Kz; z += WAVE)
-        mul(z, G[z * plane + cxy], add_saved ? save[fo + z * plane + cxy] : T2{(T)0, (T)0});
-      T2* Y = fft_line_w(F1, X, pz, twz, +1);
-      for (int z = lane; z < Kz; z += WAVE) data1[fo + z * plane + cxy] = Y[z];
+        for (int u = 0; u < ZPASS_PREFETCH; ++u)
+          if (z0 + u * zs < Kz) mul(z0 + u * zs, gk[u], sv[u]);
+        for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs)
+          mul(z, G[z * plane + cxy], add_saved ? save[fo + z * plane + cxy] : T2{(T)0, (T)0});
+      }
+      T2* Y = fft_line_w(F1, X, pz, twz, +1, L, Kz);
+      if (active)
+        for (int z = z0; z < Kz; z += zs) data1[fo + z * plane + cxy] = Y[c * Kz + z];
       T2* W = (Y == F1) ? X : F1;                           // free after the store above
       __builtin_amdgcn_wave_barrier();
-      for (int z = lane; z < Kz; z += WAVE) {
+      for (int z = z0; z < Kz; z += zs) {
         const T kz = mode_k<T>(z, Kz, (T)za.twopi_L[2]);
-        const T2 v = C[z];
-        C[z] = T2{kz * v.y, -kz * v.x};
+        const T2 v = Cl[z];
+        Cl[z] = T2{kz * v.y, -kz * v.x};
       }
-      T2* Z = fft_line_w(C, W, pz, twz, +1);
-      for (int z = lane; z < Kz; z += WAVE) data2[fo + z * plane + cxy] = Z[z];
+      T2* Z = fft_line_w(C, W, pz, twz, +1, L, Kz);
+      if (active)
+        for (int z = z0; z < Kz; z += zs) data2[fo + z * plane + cxy] = Z[c * Kz + z];
     }
   }
   if (za.mode == 0 && energy_part) {
     e = wave_sum(e);
     if (lane == 0) red[wv] = e;
     __syncthreads();
+    double* ep = energy_part + (size_t)blockIdx.y * ek_stride;
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-      energy_part[(size_t)blockIdx.y * n_z_blocks + blockIdx.x] = 0.5 * s;
+      ep[blockIdx.x] = 0.5 * s;
     }
+    // a frame's partials are ek_stride apart; with fewer workgroups than
+    // that (several columns per wavefront) the first clears the rest
+    if (blockIdx.x == 0)
+      for (int b = n_z_blocks + (int)threadIdx.x; b < ek_stride; b += blockDim.x) ep[b] = 0.0;
   }
 }
+
 
 // ------------------------------------------------------------------ launchers
 
@@ -676,10 +706,20 @@ template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass,
                     const RealBArgs<T>* rb, const PairArgs<T>* pa) {
-  const int nzb = z_pass ? za.n_blocks : 0;
   const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
-  size_t lds = (3 * (size_t)za.cpw * za.Kz + za.Kz) * sizeof(T2);
+  // columns per wavefront: one for one frame (the chain of a column is the
+  // latency); many frames put up to four short columns in a wavefront
+  // (Kz = 64: a radix-4 stage has 16 butterflies per column), while the
+  // workgroup's LDS stays within 64 KiB
+  int lpw = 1;
+  if (n_frames > 1)
+    while (lpw < 4 && 2 * lpw * za.Kz <= 4 * WAVE &&
+           (3 * (size_t)za.cpw * 2 * lpw * za.Kz + za.Kz) * sizeof(T2) <= 64 * 1024)
+      lpw *= 2;
+  const int per_block = za.cpw * lpw;
+  const int nzb = z_pass ? (za.Kx * za.Ky + per_block - 1) / per_block : 0;
+  size_t lds = (3 * (size_t)za.cpw * lpw * za.Kz + za.Kz) * sizeof(T2);
   if (r.n_blocks + p.n_blocks > 0) lds = std::max(lds, pair_queue_lds<T>());
   if ((r.n_blocks > 0 && r.tiles) || (p.n_blocks > 0 && p.tsplit > 0)) {
     std::fprintf(stderr, "cpm: only the one-wavefront-per-target pair forms ride in the z pass\n");
@@ -687,8 +727,18 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
   }
   dim3 grid(nzb + r.n_blocks + p.n_blocks, n_frames);
   if (grid.x == 0) return;
-  hipLaunchKernelGGL((k_fft_z<T, T2>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
-                     energy_part, nzb, r, p);
+  // energy partials: za.n_blocks per frame (the one-column-per-wavefront
+  // count the buffers are sized for)
+  if (lpw > 1 && r.n_blocks + p.n_blocks > 0) {
+    std::fprintf(stderr, "cpm: no hosted work in a z pass of several columns per wavefront\n");
+    std::abort();
+  }
+  if (lpw > 1)
+    hipLaunchKernelGGL((k_fft_z<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
+                       energy_part, nzb, r, p, lpw, za.n_blocks);
+  else
+    hipLaunchKernelGGL((k_fft_z<T, T2, false>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
+                       energy_part, nzb, r, p, 1, za.n_blocks);
 }
 
 template void launch_fft_xy_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
