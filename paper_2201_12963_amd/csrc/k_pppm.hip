@@ -63,6 +63,29 @@ __global__ __launch_bounds__(256) void k_gather_b(int n_elec, int P3, const int*
   }
 }
 
+// The same with 16 lanes per atom, four atoms per wavefront (many frames:
+// four times fewer wavefronts for the same loads)
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_b16(int n_elec, int P3, const int* __restrict__ gidx,
+                                                    const T* __restrict__ gw, const T* __restrict__ phi_all,
+                                                    int M, const T* __restrict__ phi_real_all,
+                                                    double* __restrict__ b_all) {
+  const int sub = threadIdx.x & 15;
+  const int i = blockIdx.x * (blockDim.x / 16) + (threadIdx.x >> 4);
+  const int frame = blockIdx.y;
+  const bool live = i < n_elec;
+  const int ii = live ? i : n_elec - 1;
+  const T* phi = phi_all + (size_t)frame * M;
+  T acc = 0;
+  for (int t = sub; t < P3; t += 16) acc += gw[(size_t)ii * P3 + t] * phi[gidx[(size_t)ii * P3 + t]];
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+  if (live && sub == 0) {
+    size_t o = (size_t)frame * n_elec + i;
+    b_all[o] = -((double)phi_real_all[o] + (double)acc);
+  }
+}
+
 template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
                           const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M) {
@@ -76,8 +99,13 @@ void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* t
 template <typename T>
 void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const int* gidx, const T* gw,
                        const T* phi, int M, const T* phi_real, double* b) {
-  dim3 grid((n_elec + 3) / 4, n_frames);
-  hipLaunchKernelGGL(k_gather_b<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b);
+  if (n_frames == 1) {
+    dim3 grid((n_elec + 3) / 4, 1);
+    hipLaunchKernelGGL(k_gather_b<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b);
+  } else {
+    dim3 grid((n_elec + 15) / 16, n_frames);
+    hipLaunchKernelGGL(k_gather_b16<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b);
+  }
 }
 
 template void launch_spread_elec_t<double>(hipStream_t, int, int, const int*, const int*, const int*,
