@@ -98,18 +98,22 @@ __device__ __forceinline__ void load_twiddles(const FFTPlan1D& p, T2* dst) {
 // dependent chain of a stage.
 __device__ __forceinline__ int div_small(int u, float rd) { return (int)(((float)u + 0.5f) * rd); }
 
-// One Stockham stage of radix R over nlines lines (see the file comment).
+// One Stockham stage of radix R over nlines lines (see the file comment) of
+// each of nplanes planes pstride apart.
 template <int R, typename T2>
 __device__ __forceinline__ void fft_stage(const T2* src, T2* dst, int N, int Ns, int nlines, int es, int ls,
-                                          const T2* tw, int sigma) {
+                                          const T2* tw, int sigma, int nplanes, int pstride) {
   const int nb = N / R;
   const int tstep = N / (Ns * R);
-  const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
-  for (int u = threadIdx.x; u < nlines * nb; u += blockDim.x) {
-    const int line = div_small(u, rnb);
-    const int j = u - line * nb;
-    const T2* in = src + line * ls;
-    T2* out = dst + line * ls;
+  const int lnb = nlines * nb;
+  const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns, rlnb = 1.0f / (float)lnb;
+  for (int u = threadIdx.x; u < nplanes * lnb; u += blockDim.x) {
+    const int pl = nplanes > 1 ? div_small(u, rlnb) : 0;
+    const int ul = u - pl * lnb;
+    const int line = div_small(ul, rnb);
+    const int j = ul - line * nb;
+    const T2* in = src + pl * pstride + line * ls;
+    T2* out = dst + pl * pstride + line * ls;
     T2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = in[(j + r * nb) * es];
@@ -131,7 +135,8 @@ __device__ __forceinline__ void fft_stage(const T2* src, T2* dst, int N, int Ns,
 }
 
 template <typename T2>
-__device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nlines, int es, int ls, int sigma) {
+__device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nlines, int es, int ls, int sigma,
+                         int nplanes = 1, int pstride = 0) {
   const int N = p.n;
   T2* src = a;
   T2* dst = b;
@@ -139,10 +144,10 @@ __device__ T2* fft_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nli
   for (int f = 0; f < p.nfac; ++f) {
     const int R = p.fac[f];
     switch (R) {
-      case 2: fft_stage<2>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
-      case 3: fft_stage<3>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
-      case 4: fft_stage<4>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
-      default: fft_stage<5>(src, dst, N, Ns, nlines, es, ls, tw, sigma); break;
+      case 2: fft_stage<2>(src, dst, N, Ns, nlines, es, ls, tw, sigma, nplanes, pstride); break;
+      case 3: fft_stage<3>(src, dst, N, Ns, nlines, es, ls, tw, sigma, nplanes, pstride); break;
+      case 4: fft_stage<4>(src, dst, N, Ns, nlines, es, ls, tw, sigma, nplanes, pstride); break;
+      default: fft_stage<5>(src, dst, N, Ns, nlines, es, ls, tw, sigma, nplanes, pstride); break;
     }
     __syncthreads();
     T2* t = src; src = dst; dst = t;
@@ -169,6 +174,8 @@ constexpr int DFT_CHUNK = 6;
 // launches XY_THREADS_MANY (more workgroups per CU for the Stockham stages)
 constexpr int XY_THREADS = 512;
 constexpr int XY_THREADS_MANY = 256;
+// planes per workgroup of many-frame x-y launches
+constexpr int XY_PLANES_MANY = 2;
 
 template <typename T2>
 __device__ T2* dft_lines(const T2* a, T2* b, int N, const T2* tw, int nlines, int es, int ls, int sigma) {
@@ -223,10 +230,10 @@ __device__ T2* dft_lines(const T2* a, T2* b, int N, const T2* tw, int nlines, in
 // serve the many-frame launches better, where throughput counts
 template <typename T2>
 __device__ T2* plane_lines(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int nlines, int es, int ls, int sigma,
-                           bool direct) {
-  if (direct && p.n <= DFT_DIRECT_MAX && nlines * ((p.n & 1) ? p.n : p.n / 2) <= (int)blockDim.x)
+                           bool direct, int nplanes = 1, int pstride = 0) {
+  if (direct && nplanes == 1 && p.n <= DFT_DIRECT_MAX && nlines * ((p.n & 1) ? p.n : p.n / 2) <= (int)blockDim.x)
     return dft_lines(a, b, p.n, tw, nlines, es, ls, sigma);
-  return fft_lines(a, b, p, tw, nlines, es, ls, sigma);
+  return fft_lines(a, b, p, tw, nlines, es, ls, sigma, nplanes, pstride);
 }
 
 // One Stockham stage of radix R over one contiguous line, by the lanes of
@@ -303,33 +310,38 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
                                                 T* __restrict__ out_im, size_t out_re_stride, int split,
                                                 const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // PL consecutive planes per workgroup (many frames: the stages of two
+  // 18-point planes fill a 256-thread workgroup better than one), held one
+  // after the other in A and in B
+  constexpr int PL = DIRECT ? 1 : XY_PLANES_MANY;
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
-  T2* B = A + NP;
-  T2* twx = B + NP;
+  T2* B = A + PL * NP;
+  T2* twx = B + PL * NP;
   T2* twy = twx + Kx;
   load_twiddles(px, twx);
   load_twiddles(py, twy);
-  const int z = blockIdx.x;
+  const int z = blockIdx.x * PL;
+  const int np = min(PL, Kz - z);
   const int part = split ? (int)(blockIdx.y & 1) : 0;
   const int frame = split ? (int)(blockIdx.y >> 1) : (int)blockIdx.y;
   if (part) { in_c = in_c2; out_re = out_re2; out_im = nullptr; }
-  const size_t off = ((size_t)frame * Kz + z) * NP;
+  const size_t off = ((size_t)frame * Kz + z) * NP;         // the workgroup's planes are contiguous
   if (mode == 0) {
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) A[i] = T2{in_re[off + i], (T)0};
+    for (int i = threadIdx.x; i < np * NP; i += blockDim.x) A[i] = T2{in_re[off + i], (T)0};
   } else {
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) A[i] = in_c[off + i];
+    for (int i = threadIdx.x; i < np * NP; i += blockDim.x) A[i] = in_c[off + i];
   }
   __syncthreads();
   const int sigma = mode == 0 ? -1 : 1;
-  T2* r1 = plane_lines(A, B, px, twx, Ky, 1, Kx, sigma, DIRECT);        // along x
+  T2* r1 = plane_lines(A, B, px, twx, Ky, 1, Kx, sigma, DIRECT, np, NP);        // along x
   T2* o1 = (r1 == A) ? B : A;
-  T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, DIRECT);      // along y
+  T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, DIRECT, np, NP);      // along y
   if (mode == 0) {
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2[i];
+    for (int i = threadIdx.x; i < np * NP; i += blockDim.x) out_c[off + i] = r2[i];
   } else {
     const size_t ro = (size_t)frame * out_re_stride + (size_t)z * NP;
-    for (int i = threadIdx.x; i < NP; i += blockDim.x) {
+    for (int i = threadIdx.x; i < np * NP; i += blockDim.x) {
       out_re[ro + i] = r2[i].x;
       if (out_im) out_im[ro + i] = r2[i].y;
     }
@@ -675,30 +687,36 @@ template void launch_fft_xy_spread_t<double, double2>(hipStream_t, int, const FF
 template void launch_fft_xy_spread_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
                                                     const MeshInfo&, const BinArgs&, float*, float2*, bool, bool);
 
+// dynamic LDS of k_fft_xy: pl planes twice (ping-pong) and the twiddles
+template <typename T2>
+size_t fft_xy_lds(const FFTPlan1D& px, const FFTPlan1D& py, int pl) {
+  return (2 * (size_t)pl * px.n * py.n + px.n + py.n) * sizeof(T2);
+}
+
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                      int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
                      size_t out_re_stride) {
-  size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
   if (n_frames == 1)
-    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 1), dim3(XY_THREADS), lds, s, px, py, Kz, mode, in_re, in_c,
-                       out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
+    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 1), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
+                       Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
   else
-    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3(Kz, n_frames), dim3(XY_THREADS_MANY), lds, s, px, py, Kz, mode,
-                       in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
+    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + XY_PLANES_MANY - 1) / XY_PLANES_MANY, n_frames),
+                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, XY_PLANES_MANY), s, px, py, Kz, mode, in_re, in_c,
+                       out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
 }
 
 template <typename T, typename T2>
 void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                                const T2* c1, const T2* c2, T* E, size_t frame_stride) {
   const size_t M = (size_t)px.n * py.n * Kz;
-  size_t lds = (2 * (size_t)px.n * py.n + px.n + py.n) * sizeof(T2);
   if (n_frames == 1)
-    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 2), dim3(XY_THREADS), lds, s, px, py, Kz, 1, (const T*)nullptr,
-                       c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
+    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 2), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
+                       Kz, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
   else
-    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3(Kz, 2 * n_frames), dim3(XY_THREADS_MANY), lds, s, px, py, Kz, 1,
+    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + XY_PLANES_MANY - 1) / XY_PLANES_MANY, 2 * n_frames),
+                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, XY_PLANES_MANY), s, px, py, Kz, 1,
                        (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
 }
 
