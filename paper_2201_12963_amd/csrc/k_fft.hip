@@ -174,8 +174,9 @@ constexpr int DFT_CHUNK = 6;
 // launches XY_THREADS_MANY (more workgroups per CU for the Stockham stages)
 constexpr int XY_THREADS = 512;
 constexpr int XY_THREADS_MANY = 256;
-// planes per workgroup of many-frame x-y launches
-constexpr int XY_PLANES_MANY = 2;
+// planes per workgroup of many-frame x-y launches (measured over 2, 3 and 4
+// at 18 x 18: FP64 best at 3, FP32 at 4)
+template <typename T2> constexpr int xy_planes_many() { return sizeof(T2) == 16 ? 3 : 4; }
 
 template <typename T2>
 __device__ T2* dft_lines(const T2* a, T2* b, int N, const T2* tw, int nlines, int es, int ls, int sigma) {
@@ -310,10 +311,10 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
                                                 T* __restrict__ out_im, size_t out_re_stride, int split,
                                                 const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // PL consecutive planes per workgroup (many frames: the stages of two
+  // PL consecutive planes per workgroup (many frames: the stages of several
   // 18-point planes fill a 256-thread workgroup better than one), held one
   // after the other in A and in B
-  constexpr int PL = DIRECT ? 1 : XY_PLANES_MANY;
+  constexpr int PL = DIRECT ? 1 : xy_planes_many<T2>();
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
   T2* B = A + PL * NP;
@@ -702,8 +703,8 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
     hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 1), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
                        Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
   else
-    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + XY_PLANES_MANY - 1) / XY_PLANES_MANY, n_frames),
-                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, XY_PLANES_MANY), s, px, py, Kz, mode, in_re, in_c,
+    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + xy_planes_many<T2>() - 1) / xy_planes_many<T2>(), n_frames),
+                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, xy_planes_many<T2>()), s, px, py, Kz, mode, in_re, in_c,
                        out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
 }
 
@@ -715,8 +716,8 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
     hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 2), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
                        Kz, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
   else
-    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + XY_PLANES_MANY - 1) / XY_PLANES_MANY, 2 * n_frames),
-                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, XY_PLANES_MANY), s, px, py, Kz, 1,
+    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + xy_planes_many<T2>() - 1) / xy_planes_many<T2>(), 2 * n_frames),
+                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, xy_planes_many<T2>()), s, px, py, Kz, 1,
                        (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
 }
 
