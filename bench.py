@@ -186,7 +186,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 423168, "sources_sha256": "aa369475a3320ef38780c913fff79a4001e9b2f71dc49011b570074429c13ff6"}}
+TRAFFIC = {"site_pairs": {"bytes": 431360, "sources_sha256": "cef4656a75034d9f168cfc30d6ada7bbbd27a99d4e86d824fbcb2647df5c38dd"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
