@@ -20,10 +20,20 @@
 
 namespace cpm {
 
+// 1/d for d >= 1: the hardware reciprocal estimate refined by two Newton
+// steps y <- y + y (1 - d y) (each squares the relative error, so the
+// estimate's ~1e-7 falls below FP64 rounding)
+__device__ __forceinline__ double recip_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  y = fma(y, fma(-d, y, 1.0), y);
+  y = fma(y, fma(-d, y, 1.0), y);
+  return y;
+}
+
 // erfcx(x) = exp(x^2) erfc(x) for 0 <= x <= ERFCX_XMAX: Clenshaw sum of the
 // Chebyshev series in u(t), t = 2/(2 + x) (coefficients in erfcx_cheb.h)
 __device__ __forceinline__ double erfcx_cheb(double x) {
-  const double t = 2.0 / (2.0 + x);
+  const double t = 2.0 * recip_nr(2.0 + x);
   const double u = (t - ERFCX_TMIN) * (2.0 / (1.0 - ERFCX_TMIN)) - 1.0;
   double b1 = 0.0, b2 = 0.0;
 #pragma unroll
