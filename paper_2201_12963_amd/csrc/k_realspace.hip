@@ -27,6 +27,16 @@ __global__ __launch_bounds__(TILE_THREADS) void k_site_pairs(PairArgs<T> pa) {
   site_pairs_block(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }
 
+// The cell-tile form (many frames) as a kernel of its own, held to five
+// wavefronts per SIMD (its ~32 KB of LDS allow five workgroups per CU; the
+// few registers it then spills cost less than the fifth workgroup gains:
+// 12.3 -> 11.6 ms per 4096 frames)
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS, 5) void k_site_pairs_tiles(PairArgs<T> pa) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  site_pairs_block(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
+}
+
 template <typename T>
 size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? PairLds<T>::total : 4 * wave_scratch_bytes<T>(); }
 
@@ -342,8 +352,12 @@ __global__ __launch_bounds__(256) void k_site_forces_g16(SiteSet<T> st, ForceArg
 template <typename T>
 void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
   if (pa.n_blocks == 0 || n_frames == 0) return;
-  hipLaunchKernelGGL(k_site_pairs<T>, dim3(pa.n_blocks, n_frames), dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit), s,
-                     pa);
+  if (pa.tsplit > 0)
+    hipLaunchKernelGGL(k_site_pairs_tiles<T>, dim3(pa.n_blocks, n_frames), dim3(TILE_THREADS),
+                       site_pairs_lds<T>(pa.tsplit), s, pa);
+  else
+    hipLaunchKernelGGL(k_site_pairs<T>, dim3(pa.n_blocks, n_frames), dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit),
+                       s, pa);
 }
 
 template <typename T>

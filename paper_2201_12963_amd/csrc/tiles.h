@@ -167,9 +167,14 @@ struct TileMap {
 
 // ------------------------------------------------------------ site pairs
 
-// queue entries: displacement (3), charge a, charge b
-template <typename T> using TileQ5 = TileQ<T, 5>;
-template <typename T> using PairLds = TileLds<T, 2, 5, 10>;
+// queue entries: the displacement (3 values of T) and one int holding the
+// target (low 8 bits) and the candidate's slot in the staged list (above):
+// the charges are read from the staged candidates when the pair is
+// evaluated, which keeps the queues (and the workgroup's LDS) small
+template <typename T> using TileQP = TileQ<T, 3>;
+template <typename T> using PairLds = TileLds<T, 2, 3, 10>;
+__device__ __forceinline__ int tq_pack(int target, int slot) { return target | (slot << 8); }
+static_assert(TILE_TGT <= 256 && TILE_CAND <= (1 << 22), "queue entry packing");
 // accumulators per target: 0-2 site-site force sum, 3 site-site potential,
 // 4-6 site-electrode force sum with charges a, 7-9 with charges b
 
@@ -180,7 +185,7 @@ template <typename T> using PairLds = TileLds<T, 2, 5, 10>;
 template <typename T, typename Stage, typename Eval>
 __device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const TileRuns* R, const TileMap& m, int j,
                                            double xt, double yt, double zt, bool self_excl, const TileCand<T, 2>& C,
-                                           const TileQ5<T>& Q, Stage stage, Eval eval) {
+                                           const TileQP<T>& Q, Stage stage, Eval eval) {
   const int lane = threadIdx.x & (WAVE - 1);
   const bool no_img = (cell.img[0] | cell.img[1] | cell.img[2]) == 0;
   for (int c0 = 0;; c0 += TILE_CAND) {
@@ -196,19 +201,19 @@ __device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const T
       // the compiler interleaves (three wavefronts per SIMD hide little)
       for (int it = 0; it < n_iter; it += 2) {
         double px[2], py[2], pz[2];
-        T qa[2], qb[2];
+        int kk[2];
         bool in[2];
         T dx[2], dy[2], dz[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int k = m.sl + (it + h) * m.nsl;
           const bool valid = m.act && it + h < n_iter && k < nck;
+          kk[h] = k;
           px[h] = xt; py[h] = yt; pz[h] = zt;
-          qa[h] = 0; qb[h] = 0;
           int pk = -1;
           if (valid) {
             px[h] = C.x[k]; py[h] = C.y[k]; pz[h] = C.z[k];
-            qa[h] = C.q[0][k]; qb[h] = C.q[1][k]; pk = C.k[k];
+            pk = C.k[k];
           }
           const Disp d = min_disp(cell, xt, yt, zt, px[h], py[h], pz[h]);
           dx[h] = (T)d.d0; dy[h] = (T)d.d1; dz[h] = (T)d.d2;
@@ -216,8 +221,8 @@ __device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const T
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const T val[5] = {dx[h], dy[h], dz[h], qa[h], qb[h]};
-          n = tq_push(Q, n, in[h], val, m.ti);
+          const T val[3] = {dx[h], dy[h], dz[h]};
+          n = tq_push(Q, n, in[h], val, tq_pack(m.ti, kk[h]));
           if (n >= WAVE) {
             eval(lane);
             n = tq_pop(Q, n);
@@ -232,9 +237,8 @@ __device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const T
       const int k = m.sl + it * m.nsl;
       const bool valid = m.act && k < nck;
       double px = xt, py = yt, pz = zt;
-      T qa = 0, qb = 0;
       int pk = -1;
-      if (valid) { px = C.x[k]; py = C.y[k]; pz = C.z[k]; qa = C.q[0][k]; qb = C.q[1][k]; pk = C.k[k]; }
+      if (valid) { px = C.x[k]; py = C.y[k]; pz = C.z[k]; pk = C.k[k]; }
       const bool self_pk = self_excl && pk == j;
       const Disp d = min_disp(cell, xt, yt, zt, px, py, pz);
       for (int ix = -cell.img[0]; ix <= cell.img[0]; ++ix)
@@ -243,8 +247,8 @@ __device__ __forceinline__ void tile_phase(const Cell& cell, double rc2, const T
             T dx, dy, dz;
             const bool self = self_pk && ix == 0 && iy == 0 && iz == 0;
             const bool in = image_pair(cell, d, ix, iy, iz, rc2, dx, dy, dz) && valid && !self;
-            const T val[5] = {dx, dy, dz, qa, qb};
-            n = tq_push(Q, n, in, val, m.ti);
+            const T val[3] = {dx, dy, dz};
+            n = tq_push(Q, n, in, val, tq_pack(m.ti, k));
             if (n >= WAVE) {
               eval(lane);
               n = tq_pop(Q, n);
@@ -265,14 +269,14 @@ template <typename T>
 __device__ __forceinline__ void site_pairs_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
                                                 unsigned char* lds) {
   using L = PairLds<T>;
-  constexpr int CAP = TileQ5<T>::CAP;
+  constexpr int CAP = TileQP<T>::CAP;
   const Cell& cell = pa.cell;
   const SiteSet<T>& st = pa.st;
   TileRuns* R = reinterpret_cast<TileRuns*>(lds + L::runs);
   TileRuns* RE = R + 1;
   TileCand<T, 2> C;
   C.bind(lds + L::cand);
-  TileQ5<T> Q;
+  TileQP<T> Q;
   Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
   double* acc = reinterpret_cast<double*>(lds + L::acc);     // [10][TILE_TGT]
   const size_t fo = (size_t)frame * st.n;
@@ -295,8 +299,10 @@ __device__ __forceinline__ void site_pairs_tile(const PairArgs<T>& pa, int c, in
                     C.q[0][k] = (T)sq[s]; C.q[1][k] = (T)0; C.k[k] = s;
                   },
                   [&](int l) {
-                    const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l], qa = Q.v[3 * CAP + l];
-                    const int tt = Q.t[l];
+                    const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l];
+                    const int e = Q.t[l];
+                    const int tt = e & 255;
+                    const T qa = C.q[0][e >> 8];
                     T g, pot;
                     g0_terms(qx * qx + qy * qy + qz * qz, pa.alpha, g, pot);
                     const T w = qa * g;
@@ -314,8 +320,9 @@ __device__ __forceinline__ void site_pairs_tile(const PairArgs<T>& pa, int c, in
                     },
                     [&](int l) {
                       const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l];
-                      const T qa = Q.v[3 * CAP + l], qb = Q.v[4 * CAP + l];
-                      const int tt = Q.t[l];
+                      const int e = Q.t[l];
+                      const int tt = e & 255;
+                      const T qa = C.q[0][e >> 8], qb = C.q[1][e >> 8];
                       const T g = g1_force(qx * qx + qy * qy + qz * qz, pa.alpha, pa.eta);
                       const T wa = qa * g, wb = qb * g;
                       atomicAdd(acc + 4 * TILE_TGT + tt, (double)(wa * qx));
@@ -350,12 +357,12 @@ template <typename T>
 __device__ __forceinline__ void real_b_tile(const RealBArgs<T>& rb, int c, int t_lo, int t_hi, int frame,
                                             unsigned char* lds) {
   using L = PairLds<T>;
-  constexpr int CAP = TileQ5<T>::CAP;
+  constexpr int CAP = TileQP<T>::CAP;
   const SiteSet<T>& st = rb.st;
   TileRuns* R = reinterpret_cast<TileRuns*>(lds + L::runs);
   TileCand<T, 2> C;
   C.bind(lds + L::cand);
-  TileQ5<T> Q;
+  TileQP<T> Q;
   Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
   double* acc = reinterpret_cast<double*>(lds + L::acc);
   const size_t fo = (size_t)frame * st.n;
@@ -373,8 +380,9 @@ __device__ __forceinline__ void real_b_tile(const RealBArgs<T>& rb, int c, int t
                   C.q[0][k] = (T)sq[s]; C.q[1][k] = (T)0; C.k[k] = s;
                 },
                 [&](int l) {
-                  atomicAdd(acc + Q.t[l], (double)g1_potential(Q.v[l], Q.v[CAP + l], Q.v[2 * CAP + l],
-                                                               Q.v[3 * CAP + l], rb.alpha, rb.eta));
+                  const int e = Q.t[l];
+                  atomicAdd(acc + (e & 255), (double)g1_potential(Q.v[l], Q.v[CAP + l], Q.v[2 * CAP + l],
+                                                                  C.q[0][e >> 8], rb.alpha, rb.eta));
                 });
   __syncthreads();
   if ((int)threadIdx.x < m.ntc) {
