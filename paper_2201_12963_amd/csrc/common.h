@@ -14,7 +14,7 @@ constexpr int MAX_FFT_FACTORS = 12;
 constexpr int MAX_ORDER = 7;
 constexpr int STENCIL_MAX = 27;   // neighbour cells of a cell, itself included
 // cell tiles of the real-space sums: workgroup size, candidates staged in
-// LDS per pass (256: ~40 KB of LDS per workgroup, four per CU; 512 left
+// LDS per pass (256: ~32 KB of LDS per workgroup, five per CU; 512 left
 // three and measured 8% slower), targets per chunk
 constexpr int TILE_THREADS = 256;
 constexpr int TILE_CAND = 256;
