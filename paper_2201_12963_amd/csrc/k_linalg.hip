@@ -316,10 +316,14 @@ __device__ double block_sum(double v, double* red) {
 __global__ __launch_bounds__(256) void k_expand_charges(int n_elec, int n_dv, const double* __restrict__ dv,
                                                         const double* __restrict__ Q0, const double* __restrict__ Sc,
                                                         double* __restrict__ q) {
+  // a thread takes atom i of frame f over the whole sweep (its two inputs
+  // read once, every store a run of consecutive atoms)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y, f = blockIdx.z;
+  const int f = blockIdx.y;
   if (i >= n_elec) return;
-  q[((size_t)f * n_dv + v) * n_elec + i] = Q0[(size_t)f * n_elec + i] + dv[v] * Sc[i];
+  const double a = Q0[(size_t)f * n_elec + i], b = Sc[i];
+  double* o = q + (size_t)f * n_dv * n_elec + i;
+  for (int v = 0; v < n_dv; ++v) o[(size_t)v * n_elec] = a + dv[v] * b;
 }
 
 // out[f][v][k] = comp[f][0][k] + dv[v] comp[f][1][k], k < n3: the forces are
@@ -443,8 +447,8 @@ void launch_expand_forces(hipStream_t s, int n_frames, int n_site, int n_dv, con
 }
 void launch_expand_charges(hipStream_t s, int n_frames, int n_elec, int n_dv, const double* dv, const double* Q0,
                            const double* Sc, double* q) {
-  hipLaunchKernelGGL(k_expand_charges, dim3((n_elec + 255) / 256, n_dv, n_frames), dim3(256), 0, s, n_elec, n_dv, dv,
-                     Q0, Sc, q);
+  hipLaunchKernelGGL(k_expand_charges, dim3((n_elec + 255) / 256, n_frames), dim3(256), 0, s, n_elec, n_dv, dv, Q0, Sc,
+                     q);
 }
 
 }  // namespace cpm
