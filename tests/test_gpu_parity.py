@@ -92,12 +92,12 @@ def test_step_parity_sites_crowded_into_one_layer(torch_dev):
     x[2] = rng.uniform(6.2, 6.4, w.n_site)
     wc = dataclasses.replace(w, site_xyz=x)
     # sites whose z stencil reaches each plane, per staging wavefront: the
-    # spread's first 512 threads read sites u * 512 + thread (u < 8), so
-    # site j belongs to wavefront (j mod 512) // 64 of batch j // 4096
+    # spread's first 256 threads read sites u * 256 + thread (u < 16), so
+    # site j belongs to wavefront (j mod 256) // 64 of batch j // 4096
     u = x[2] / (w.box[2] / w.mesh[2])
     first = (np.floor(u - w.order / 2.0).astype(int) + 1) % w.mesh[2]
     j = np.arange(w.n_site)
-    group = (j // 4096) * 8 + (j % 512) // 64
+    group = (j // 4096) * 4 + (j % 256) // 64
     per_wave = np.zeros((w.mesh[2], group.max() + 1), int)
     for t in range(w.order):
         np.add.at(per_wave, ((first + t) % w.mesh[2], group), 1)
