@@ -1,5 +1,5 @@
 // Energies of the step (Eq. 3 and its constant-potential counterpart), as
-// one 256-thread workgroup per frame: ten sums over the electrodes, the
+// one workgroup per frame (any whole number of wavefronts up to 1024 threads): ten sums over the electrodes, the
 // sites and the k-space parts, reduced together, then U_coul and E_cp for
 // every dV of the frame.
 #pragma once
@@ -10,7 +10,7 @@ namespace cpm {
 __device__ __forceinline__ void energy_block(const EnergyArgs& ea, int frame) {
   // ten partial sums reduced together: 8 dot products over the electrodes,
   // the site real-space energies and the k-space energy parts
-  __shared__ double red[4][10];
+  __shared__ double red[16][10];
   const size_t fe = (size_t)frame * ea.n_elec;
   double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = threadIdx.x; i < ea.n_elec; i += blockDim.x) {
@@ -30,7 +30,11 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& ea, int frame) {
   }
   __syncthreads();
   double S[10];
-  for (int t = 0; t < 10; ++t) S[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  const int nw = blockDim.x >> 6;
+  for (int t = 0; t < 10; ++t) {
+    S[t] = red[0][t];
+    for (int w = 1; w < nw; ++w) S[t] += red[w][t];
+  }
   double u_elyt = S[8] + S[9] - ea.self_energy;
   double zdip = ea.zdip ? ea.zdip[frame] : 0.0;
   for (int v = threadIdx.x; v < ea.n_dv; v += blockDim.x) {

@@ -239,12 +239,14 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
 
 // The same when the pair tiles have already made the site-electrode sums
 // (many frames): no walk is left, only the interpolation, so 16 lanes take a
-// site and a wavefront four.  Every lane evaluates the site's three weight
-// sets itself and gathers the points t = sub, sub + 16, ... of the P^3
-// stencil; the 16 lanes then sum by butterfly shuffles.  A group past the
-// last site mirrors it and writes nothing.
+// site, a wavefront four and a workgroup of G16_THREADS lanes 32 (larger
+// workgroups measured faster than 256 lanes here).  Every lane evaluates the
+// site's three weight sets itself and gathers the points t = sub, sub + 16,
+// ... of the P^3 stencil; the 16 lanes then sum by butterfly shuffles.  A
+// group past the last site mirrors it and writes nothing.
+constexpr int G16_THREADS = 512;
 template <typename T, bool TWO>
-__global__ __launch_bounds__(256) void k_site_forces_g16(SiteSet<T> st, ForceArgs<T> fa, int n_force_blocks,
+__global__ __launch_bounds__(G16_THREADS) void k_site_forces_g16(SiteSet<T> st, ForceArgs<T> fa, int n_force_blocks,
                                                          EnergyArgs en) {
   int bx = blockIdx.x, frame = blockIdx.y;
   if (gridDim.y > 1) {
@@ -390,13 +392,15 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
   const EnergyArgs e = ea ? *ea : EnergyArgs{};
   if (!walk) {
     // sixteen lanes per site
-    const int nfb = forces ? (st.n + 15) / 16 : 0;
+    const int nfb = forces ? (st.n + G16_THREADS / 16 - 1) / (G16_THREADS / 16) : 0;
     dim3 grid(nfb + (ea ? 1 : 0), n_frames);
     if (grid.x == 0) return;
+    // energies alone: one frame's sums are short, 256 lanes reduce them sooner
+    const dim3 block(nfb ? G16_THREADS : 256);
     if (two)
-      hipLaunchKernelGGL((k_site_forces_g16<T, true>), grid, dim3(256), 0, s, st, fa, nfb, e);
+      hipLaunchKernelGGL((k_site_forces_g16<T, true>), grid, block, 0, s, st, fa, nfb, e);
     else
-      hipLaunchKernelGGL((k_site_forces_g16<T, false>), grid, dim3(256), 0, s, st, fa, nfb, e);
+      hipLaunchKernelGGL((k_site_forces_g16<T, false>), grid, block, 0, s, st, fa, nfb, e);
     return;
   }
   const int nfb = forces ? (parts == 2 ? (st.n + 1) / 2 : (st.n + 3) / 4) : 0;
