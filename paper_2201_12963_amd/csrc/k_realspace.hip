@@ -239,12 +239,12 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
 
 // The same when the pair tiles have already made the site-electrode sums
 // (many frames): no walk is left, only the interpolation, so 16 lanes take a
-// site, a wavefront four and a workgroup of G16_THREADS lanes 32 (larger
-// workgroups measured faster than 256 lanes here).  Every lane evaluates the
+// site, a wavefront four and a workgroup of G16_THREADS lanes 64 (larger
+// workgroups measured faster than 256 or 512 lanes here).  Every lane evaluates the
 // site's three weight sets itself and gathers the points t = sub, sub + 16,
 // ... of the P^3 stencil; the 16 lanes then sum by butterfly shuffles.  A
 // group past the last site mirrors it and writes nothing.
-constexpr int G16_THREADS = 512;
+constexpr int G16_THREADS = 1024;
 template <typename T, bool TWO>
 __global__ __launch_bounds__(G16_THREADS) void k_site_forces_g16(SiteSet<T> st, ForceArgs<T> fa, int n_force_blocks,
                                                          EnergyArgs en) {
