@@ -186,7 +186,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 444672, "sources_sha256": "ebca1e0e18a58bb5c191bc3a3f7d19fafff22a27a505eccf40f2359094213cd1"}}
+TRAFFIC = {"site_pairs": {"bytes": 444672, "sources_sha256": "ec136434e70f5d904e41b49d233d30faa9aa639183e5d39585246f019f949cb6"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
