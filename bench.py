@@ -40,7 +40,8 @@ FLOPS_PAIR_B, FLOPS_PAIR_G0, FLOPS_PAIR_G1 = 50, 50, 80
 
 
 def count_pairs(a, b, box, rcut, same=False):
-    """Number of (a, b) pairs within rcut (minimum image; the cells used here are >= 2 rcut)."""
+    """Number of (a, b) pairs within rcut (minimum image; the cells used here
+    are >= 2 rcut).  same=True counts the unordered pairs of one set once."""
     n = 0
     for i0 in range(0, a.shape[1], 512):
         d = a[:, i0:i0 + 512, None] - b[:, None, :]
@@ -48,26 +49,49 @@ def count_pairs(a, b, box, rcut, same=False):
         r2 = np.einsum("kab,kab->ab", d, d)
         n += int(np.count_nonzero(r2 < rcut * rcut))
     if same:
-        n -= a.shape[1]
+        n = (n - a.shape[1]) // 2
     return n
 
 
-def kernel_work(w, name, n_frames=1):
+_PAIRS = {}
+
+
+def pair_counts(w):
+    """(unordered site-site pairs, site-electrode pairs) within r_c, cached per workload."""
+    key = (w.name, w.geometry, w.n_elec, w.n_site)
+    if key not in _PAIRS:
+        _PAIRS[key] = (count_pairs(w.site_xyz, w.site_xyz, w.box, w.rcut, same=True),
+                       count_pairs(w.site_xyz, w.elec_xyz, w.box, w.rcut))
+    return _PAIRS[key]
+
+
+def kernel_work(w, name, n_frames=1, n_dv=1, mixed=False):
     """(bound, algorithmic work of one launch over n_frames frames, unit) of a
     step kernel.  Bytes count frame-independent tables (S, S c, electrode
     stencils, the influence function) once per launch and per-frame data
-    once per frame; FLOP counts are per frame."""
+    once per frame; FLOP counts are per frame.  Site pairs are the unordered
+    pairs within r_c (each is one evaluation of the method).  In batches the
+    cell tiles take the site-electrode (g1) pairs as well, and the site-force
+    kernel only interpolates the mesh field."""
     P3 = w.order ** 3
     M = int(np.prod(w.mesh))
     ne, nl = w.n_elec, w.n_site
+    pg0, pg1 = pair_counts(w)
+    batched = n_frames > 1
     if name == "site_pairs":
-        pg0 = count_pairs(w.site_xyz, w.site_xyz, w.box, w.rcut, same=True)
-        return "alu", n_frames * pg0 * FLOPS_PAIR_G0, "TFLOP/s"
+        flop = pg0 * FLOPS_PAIR_G0 + (pg1 * FLOPS_PAIR_G1 if batched else 0)
+        return "alu", n_frames * flop, "TFLOP/s"
     if name == "site_forces":
-        pg1 = count_pairs(w.site_xyz, w.elec_xyz, w.box, w.rcut)
-        return "alu", n_frames * (pg1 * FLOPS_PAIR_G1 + nl * P3 * 6), "TFLOP/s"
+        flop = nl * P3 * 6 + (0 if batched else pg1 * FLOPS_PAIR_G1)
+        return "alu", n_frames * flop, "TFLOP/s"
     if name == "real_b":
-        return "alu", n_frames * count_pairs(w.elec_xyz, w.site_xyz, w.box, w.rcut) * FLOPS_PAIR_B, "TFLOP/s"
+        return "alu", n_frames * pg1 * FLOPS_PAIR_B, "TFLOP/s"
+    if name == "gemm":              # Q0 = S B: 2 N_e^2 FLOP per frame (the method's contraction)
+        return "mfma" if mixed else "alu", n_frames * 2.0 * ne * ne, "TFLOP/s"
+    if name == "expand_q":          # Q0 read, q written for every dV; S c once
+        return "hbm", ne * 8 + n_frames * ne * 8 * (1 + n_dv), "GB/s"
+    if name == "expand_f":          # two force vectors read, F written for every dV
+        return "hbm", n_frames * 3 * nl * 8 * (2 + n_dv), "GB/s"
     if name == "charges":           # S streamed once; b read, Q0 and q written per frame
         return "hbm", 8 * ne * ne + n_frames * 8 * 3 * ne, "GB/s"
     if name.startswith("fft_z"):    # complex mesh read and written (+ G once)
@@ -160,19 +184,37 @@ def kernel_times(torch, ctx, stream, reps, warm=5):
     return times
 
 
-def per_kernel_roofline(w, kernel_ms, n_frames=1):
+def peak_of(bound, mixed=False):
+    if bound == "hbm":
+        return HBM_PEAK_GBS
+    if bound == "mfma":
+        return BF16_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    return FP64_PEAK_TFLOPS
+
+
+def per_kernel_roofline(w, kernel_ms, n_frames=1, n_dv=1, mixed=False):
     """Achieved rate and roofline fraction of every timed kernel (algorithmic
     work of its own body x n_frames over its average duration)."""
     out = {}
     for name, ms in kernel_ms.items():
-        bound, work, unit = kernel_work(w, name, n_frames)
-        if bound == "hbm":
-            achieved, peak = work / (ms * 1e-3) / 1e9, HBM_PEAK_GBS
-        else:
-            achieved, peak = work / (ms * 1e-3) / 1e12, FP64_PEAK_TFLOPS
+        bound, work, unit = kernel_work(w, name, n_frames, n_dv, mixed)
+        scale = 1e9 if bound == "hbm" else 1e12
+        achieved = work / (ms * 1e-3) / scale
+        peak = peak_of(bound, mixed)
         out[name] = dict(us=round(ms * 1e3, 2), bound=bound, achieved=round(achieved, 4), unit=unit,
-                         frac=round(achieved / peak, 5))
+                         frac=round(achieved / peak, 5), roof_us=round(work / scale / peak * 1e6, 4))
     return out
+
+
+def step_fraction(w, kernel_ms, ms_step):
+    """Whole one-frame step: the sum over the step's kernel bodies of the time
+    each would take at its roofline, divided by the measured step time."""
+    roof_s = 0.0
+    for name in kernel_ms:
+        bound, work, _ = kernel_work(w, name)
+        roof_s += work / (1e9 if bound == "hbm" else 1e12) / peak_of(bound)
+    return dict(roofline_us=roof_s * 1e6, measured_us=ms_step * 1e3, frac=roof_s / (ms_step * 1e-3),
+                kernels=sorted(kernel_ms))
 
 
 # The roofline kernel: the site-site pair forces, the step's largest
@@ -207,48 +249,86 @@ def measured_traffic(name):
     return t["bytes"]
 
 
-def roofline(w, kernel_ms):
-    """Roofline entry for the site-site pair kernel, timed alone."""
+def roofline(w, kernel_ms, ms_step):
+    """Roofline entry for the site-site pair kernel, timed alone, plus the
+    whole-step fraction and every kernel's own fraction."""
     name = ROOFLINE_KERNEL
     ms = kernel_ms[name]
     bound, work, unit = kernel_work(w, name)
-    if bound == "hbm":
-        achieved = work / (ms * 1e-3) / 1e9
-        peak = HBM_PEAK_GBS
-    else:
-        achieved = work / (ms * 1e-3) / 1e12
-        peak = FP64_PEAK_TFLOPS
+    scale = 1e9 if bound == "hbm" else 1e12
+    achieved = work / (ms * 1e-3) / scale
+    peak = peak_of(bound)
+    pg0, pg1 = pair_counts(w)
     return dict(kernel=name, bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak,
                 traffic=measured_traffic(name), avg_us=ms * 1e3, work_per_launch=work,
+                work_basis=f"{pg0} unordered site pairs within r_c x {FLOPS_PAIR_G0} FLOP",
+                step=step_fraction(w, kernel_ms, ms_step),
                 per_kernel=per_kernel_roofline(w, kernel_ms))
 
 
-def cpu_baseline(w, traj, budget_s=20.0):
-    """The oracle (FP64 NumPy/SciPy, PPPM) on a bounded sample of the same loop."""
-    from oracle import cpm
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _time_steps(cpm, w, A, S, es, traj, start, n):
+    t0 = time.perf_counter()
+    for k in range(n):
+        cpm.step(w, A, S, es, site_xyz=traj[(start + k) % traj.shape[0]])
+    return (time.perf_counter() - t0) / n
+
+
+def cpu_baseline(w, traj, steps_per_rep=2, reps=5, parity=None):
+    """The oracle (FP64 NumPy/SciPy, PPPM) on a bounded sample of the same
+    loop: the median of `reps` repeats of `steps_per_rep` consecutive steps
+    on all the host's BLAS threads, and the same with one thread.  With
+    `parity` (a dict of GPU results of the precision form), the oracle also
+    computes that step and the GPU's per-result error against it is returned."""
+    from oracle import cpm
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     A, S = cpm.build(w)
     es = cpm.Electrostatics(w, "pppm")
     cpm.step(w, A, S, es, site_xyz=traj[0])          # warm-up
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        cpm.step(w, A, S, es, site_xyz=traj[(n + 1) % traj.shape[0]])
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or n >= 50:
-            break
-    return dict(value=n / el, unit="steps/s", cores=threads, kind="oracle",
-                sample=f"{n} consecutive steps of the same random-walk loop ({w.geometry}, "
-                       f"N_e={w.n_elec}, N_l={w.n_site}), A and S precomputed outside the timing")
+    per_step = [_time_steps(cpm, w, A, S, es, traj, 1 + r * steps_per_rep, steps_per_rep) for r in range(reps)]
+    with threadpool_limits(limits=1):
+        one = [_time_steps(cpm, w, A, S, es, traj, 1 + r, 1) for r in range(reps)]
+    out = dict(value=1.0 / float(np.median(per_step)), unit="steps/s", cores=threads, kind="oracle",
+               cpu_model=cpu_model(), os_cpu_count=os.cpu_count(),
+               single_core_steps_per_s=1.0 / float(np.median(one)),
+               sample=f"median of {reps} repeats of {steps_per_rep} consecutive steps of the same random-walk "
+                      f"loop ({w.geometry}, N_e={w.n_elec}, N_l={w.n_site}) on {threads} BLAS threads; "
+                      f"single core: median of {reps} single steps; A and S precomputed outside the timing")
+    if parity is not None:
+        out["precision_form_vs_oracle"] = precision_parity(cpm, parity)
+    return out
+
+
+def precision_parity(cpm, g):
+    """Per-result error of the precision form's last GPU step against the oracle."""
+    w, x = g["workload"], g["site_xyz"]
+    A, S = cpm.build(w)
+    ref = cpm.step(w, A, S, cpm.Electrostatics(w, "pppm"), site_xyz=x)
+    out = {}
+    for label in ("fp64", "mixed"):
+        r = g[label]
+        out[label] = dict(
+            q_max_err_e=float(np.abs(r["q"] - ref["q"]).max()),
+            f_rel_rms=float(np.sqrt(np.mean((r["f"] - ref["f"]) ** 2) / np.mean(ref["f"] ** 2))),
+            u_coul_err_ev=float(abs(r["e"][0] - ref["u_coul"])),
+            e_cp_err_ev=float(abs(r["e"][1] - ref["e_cp"])))
+    return out
 
 
 def precision_form(torch, steps=200, warmup=20):
-    """Large cell (N_e = 3520, N_l = 5120): FP64 and mixed steps/s and the mixed errors."""
+    """Large cell (N_e = 3520, N_l = 5120): FP64 and mixed steps/s and the mixed errors
+    against FP64 on the GPU (the errors against the oracle are taken in the CPU leg)."""
     from workloads import make_workload, random_walk
     w = make_workload("large", "ff")
     traj = random_walk(w, 200)
@@ -256,11 +336,14 @@ def precision_form(torch, steps=200, warmup=20):
     r32 = gpu_steps(torch, w, traj, steps, warmup, precision=1)
     dq = float(np.abs(r32["q"] - r64["q"]).max())
     df = float(np.sqrt(np.mean((r32["f"] - r64["f"]) ** 2) / np.mean(r64["f"] ** 2)))
+    last = traj[(steps - 1) % traj.shape[0]]
+    state = dict(workload=w, site_xyz=last,
+                 fp64={k: r64[k] for k in ("q", "f", "e")}, mixed={k: r32[k] for k in ("q", "f", "e")})
     return dict(workload="6.8x6.8x12.625 nm finite field, N_e=3520, N_l=5120, PPPM 36x36x64",
                 fp64_steps_per_s=1000.0 * steps / r64["ms_total"],
                 mixed_steps_per_s=1000.0 * steps / r32["ms_total"],
                 mixed_vs_fp64_q_max_err_e=dq, mixed_vs_fp64_f_rel_rms=df,
-                mixed_vs_fp64_u_err_ev=float(abs(r32["e"][0] - r64["e"][0])))
+                mixed_vs_fp64_u_err_ev=float(abs(r32["e"][0] - r64["e"][0]))), state
 
 
 def batched_form(torch, n_frames=4096, n_dv=32, reps=3):
@@ -294,7 +377,8 @@ def batched_form(torch, n_frames=4096, n_dv=32, reps=3):
         # every kernel of the batch timed alone (the last launch of each, over
         # frames_per_launch frames)
         out[label + "_kernels"] = per_kernel_roofline(w, kernel_times(torch, ctx, stream, 3, warm=1),
-                                                      out[label]["frames_per_launch"] or n_frames)
+                                                      out[label]["frames_per_launch"] or n_frames, n_dv,
+                                                      mixed=prec == 1)
         ctx.close()
         del q, f, e
         torch.cuda.empty_cache()
@@ -349,7 +433,8 @@ def main():
     from workloads import make_workload, random_walk
 
     if args.only:
-        form = {"precision": precision_form, "batched": batched_form, "gradient": gradient_form}[args.only]
+        form = {"precision": lambda t: precision_form(t)[0], "batched": batched_form,
+                "gradient": gradient_form}[args.only]
         print(json.dumps({args.only: form(torch)}), flush=True)
         return
 
@@ -383,16 +468,18 @@ def main():
             "finite_field_workload": "same cell, finite field: 3.4x3.4x12.625 nm, N_e=880, N_l=1280, "
                                      "PPPM 18x18x64",
         },
-        "roofline": roofline(wd, rd["kernel_ms"]),
+        "roofline": roofline(wd, rd["kernel_ms"], ms_step),
     }
+    precision_state = None
     if not args.no_forms:
+        prec, precision_state = precision_form(torch)
         line["forms"] = {
-            "precision": precision_form(torch),
+            "precision": prec,
             "batched": batched_form(torch),
             "gradient": gradient_form(torch),
         }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wd, trajd)
+        line["cpu_baseline"] = cpu_baseline(wd, trajd, parity=precision_state)
     print(json.dumps(line), flush=True)
 
 

@@ -183,7 +183,12 @@ enum {
   CPM_KERNEL_BIN = 0, CPM_KERNEL_REAL_B, CPM_KERNEL_SITE_PAIRS, CPM_KERNEL_FFT_XY_FWD,
   CPM_KERNEL_FFT_Z_POT, CPM_KERNEL_FFT_XY_INV, CPM_KERNEL_GATHER_B, CPM_KERNEL_CHARGES,
   CPM_KERNEL_SPREAD_ELEC, CPM_KERNEL_FFT_XY_FWD_E, CPM_KERNEL_FFT_Z_FIELD, CPM_KERNEL_FFT_XY_INV_E,
-  CPM_KERNEL_SITE_FORCES, CPM_KERNEL_ENERGY, CPM_KERNEL_COUNT
+  CPM_KERNEL_SITE_FORCES, CPM_KERNEL_ENERGY,
+  /* batched form only: the charge GEMM Q0 = S B (FP64, or the bf16 split
+   * products in MIXED), the expansion of q over the dV sweep, and that of
+   * the forces */
+  CPM_KERNEL_GEMM, CPM_KERNEL_EXPAND_Q, CPM_KERNEL_EXPAND_F,
+  CPM_KERNEL_COUNT
 };
 int cpm_replay_kernel(cpm_ctx* ctx, int kernel, int reps);
 

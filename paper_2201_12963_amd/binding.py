@@ -25,7 +25,8 @@ FLAG_GRAPH = 1
 (BUF_CELL_START, BUF_SITE_ORDER, BUF_PHI_REAL, BUF_B, BUF_RHO_MESH, BUF_PHI_MESH, BUF_FIELD_MESH, BUF_NCELL,
  BUF_BATCH_CHUNK) = range(9)
 KERNELS = ("bin", "real_b", "site_pairs", "fft_xy_fwd", "fft_z_pot", "fft_xy_inv", "gather_b", "charges",
-           "spread_elec", "fft_xy_fwd_e", "fft_z_field", "fft_xy_inv_e", "site_forces", "energy")
+           "spread_elec", "fft_xy_fwd_e", "fft_z_field", "fft_xy_inv_e", "site_forces", "energy",
+           "gemm", "expand_q", "expand_f")
 
 _STATUS_NAMES = {0: "CPM_OK", -1: "CPM_EINVAL", -2: "CPM_ESTATE", -3: "CPM_ENOTSPD", -4: "CPM_EDEVICE",
                  -5: "CPM_ENOMEM", -6: "CPM_ENONFINITE"}
@@ -139,11 +140,18 @@ class Context:
         d.n_site = sq.shape[0]
         d.site_q = sq.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.n_elec, self.n_site = d.n_elec, d.n_site
-        self.stream = stream
+        # the library always works on a real stream (torch's current one if
+        # none is given, set once the descriptor has passed validation); every
+        # call orders it after the caller's current stream and the caller's
+        # current stream after it (_call)
         handle = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
         r = self._lib.cpm_create(ctypes.byref(d), handle, ctypes.byref(self._ctx))
         if r != CPM_OK:
             raise CpmError(r, self._lib.cpm_last_error(None).decode())
+        if stream is None:
+            stream = torch.cuda.current_stream()
+            self._check(self._lib.cpm_set_stream(self._ctx, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     @classmethod
     def from_workload(cls, w, precision=FP64, stream=None, graph=False):
@@ -160,6 +168,24 @@ class Context:
         if r != CPM_OK:
             raise CpmError(r, self._lib.cpm_last_error(self._ctx).decode())
 
+    def _call(self, fn, *args):
+        """Run one library call with its stream ordered against the caller's.
+
+        Inputs and outputs are tensors made or last touched on the caller's
+        current stream; the library enqueues on the context's stream.  The
+        context's stream first waits for the caller's stream (inputs ready,
+        output memory no longer in use), and afterwards the caller's stream
+        waits for the context's (results ready before the caller reads them
+        or the caching allocator hands their memory out again)."""
+        cur = torch.cuda.current_stream(self.stream.device)
+        other = cur.cuda_stream != self.stream.cuda_stream
+        if other:
+            self.stream.wait_stream(cur)
+        r = fn(self._ctx, *args)
+        if other:
+            cur.wait_stream(self.stream)
+        self._check(r)
+
     def build_elastance(self):
         self._check(self._lib.cpm_build_elastance(self._ctx))
 
@@ -173,8 +199,7 @@ class Context:
             f_out = torch.empty((3, self.n_site), dtype=torch.float64, device=dev)
         if energy and energy_out is None:
             energy_out = torch.empty(2, dtype=torch.float64, device=dev)
-        self._check(self._lib.cpm_solve(self._ctx, _ptr(site_xyz), float(dv), _ptr(q_out), _ptr(f_out),
-                                        _ptr(energy_out)))
+        self._call(self._lib.cpm_solve, _ptr(site_xyz), float(dv), _ptr(q_out), _ptr(f_out), _ptr(energy_out))
         return q_out, f_out, energy_out
 
     def solve_batch(self, site_xyz: torch.Tensor, dvs, q_out=None, f_out=None, energy_out=None,
@@ -188,9 +213,8 @@ class Context:
             f_out = torch.empty((n_frames, dv.size, 3, self.n_site), dtype=torch.float64, device=dev)
         if energy and energy_out is None:
             energy_out = torch.empty((n_frames, dv.size, 2), dtype=torch.float64, device=dev)
-        self._check(self._lib.cpm_solve_batch(self._ctx, n_frames, _ptr(site_xyz), dv.size,
-                                              dv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                              _ptr(q_out), _ptr(f_out), _ptr(energy_out)))
+        self._call(self._lib.cpm_solve_batch, n_frames, _ptr(site_xyz), dv.size,
+                   dv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(q_out), _ptr(f_out), _ptr(energy_out))
         return q_out, f_out, energy_out
 
     def grad(self, site_xyz: torch.Tensor, dv: float, q_target: torch.Tensor):
@@ -199,8 +223,8 @@ class Context:
         dldx = torch.empty((3, self.n_site), dtype=torch.float64, device=dev)
         dldv = torch.empty(1, dtype=torch.float64, device=dev)
         q = torch.empty(self.n_elec, dtype=torch.float64, device=dev)
-        self._check(self._lib.cpm_grad(self._ctx, _ptr(site_xyz), float(dv), _ptr(q_target), _ptr(loss),
-                                       _ptr(dldx), _ptr(dldv), _ptr(q)))
+        self._call(self._lib.cpm_grad, _ptr(site_xyz), float(dv), _ptr(q_target), _ptr(loss), _ptr(dldx),
+                   _ptr(dldv), _ptr(q))
         return loss, dldx, dldv, q
 
     def get_matrix(self, which: int) -> np.ndarray:
@@ -226,7 +250,7 @@ class Context:
 
     def replay_kernel(self, kernel: int, reps: int):
         """Re-enqueue the last launch of one step kernel `reps` times (timing hook)."""
-        self._check(self._lib.cpm_replay_kernel(self._ctx, int(kernel), int(reps)))
+        self._call(self._lib.cpm_replay_kernel, int(kernel), int(reps))
 
     def sync_status(self) -> int:
         return int(self._lib.cpm_sync_status(self._ctx))

@@ -676,13 +676,19 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
   // Q0[f][i] = sum_j B[f][j] S[i][j]
   if (std::is_same<T, float>::value) {
     launch_split_b(s, nf, n, c->n_pad, c->d_b, c->d_bsplit);
-    launch_gemm_bf16x6(s, nf, n, c->n_pad, c->d_bsplit, (size_t)nf * c->n_pad, c->d_Ssplit, (size_t)n * c->n_pad,
-                       c->d_Q0, n);
+    rec(c, CPM_KERNEL_GEMM, s, [=](hipStream_t s) {
+      launch_gemm_bf16x6(s, nf, n, c->n_pad, c->d_bsplit, (size_t)nf * c->n_pad, c->d_Ssplit, (size_t)n * c->n_pad,
+                         c->d_Q0, n);
+    });
     launch_reproject(s, nf, n, c->d_sub1, c->d_Q0);
   } else {
-    launch_gemm_nt(s, nf, n, n, 1.0, c->d_b, n, c->d_S, n, 0.0, c->d_Q0, n);
+    rec(c, CPM_KERNEL_GEMM, s, [=](hipStream_t s) {
+      launch_gemm_nt(s, nf, n, n, 1.0, c->d_b, n, c->d_S, n, 0.0, c->d_Q0, n);
+    });
   }
-  launch_expand_charges(s, nf, n, n_dv, c->d_dv, c->d_Q0, c->d_Sc, q_out);
+  rec(c, CPM_KERNEL_EXPAND_Q, s, [=](hipStream_t s) {
+    launch_expand_charges(s, nf, n, n_dv, c->d_dv, c->d_Q0, c->d_Sc, q_out);
+  });
   if (f_out || e_out) launch_permute(s, nf, n, c->d_epos, c->d_Q0, c->d_qs);
   if (need_forces) {
     ForceArgs<T> fa{};
@@ -699,7 +705,10 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
     fa.u_site = c->d_usite;
     const EnergyArgs ea = energy_args(c, n_dv, c->d_dv, 0.0, e_out);
     TRY(enqueue_forces<T>(c, nf, c->d_Q0, n, c->d_qs, fa, e_out ? &ea : nullptr));
-    if (f_out) launch_expand_forces(s, nf, c->n_site, n_dv, c->d_dv, c->d_fcomp, f_out);
+    if (f_out)
+      rec(c, CPM_KERNEL_EXPAND_F, s, [=](hipStream_t s) {
+        launch_expand_forces(s, nf, c->n_site, n_dv, c->d_dv, c->d_fcomp, f_out);
+      });
   }
   return CPM_OK;
 }
@@ -796,6 +805,26 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       if (d->mesh[k] < d->order)
         return fail(nullptr, CPM_EINVAL, "PPPM mesh needs at least `order` points per axis (axis %d has %d)", k,
                     d->mesh[k]);
+  if (d->kspace == CPM_KSPACE_PPPM) {
+    // everything about the mesh that needs no device: factorable axes, the
+    // z-column limit and the LDS of the x-y planes (one-frame launches hold
+    // one plane; many-frame launches fall back to one plane per workgroup
+    // when several do not fit)
+    const int elt = d->precision == CPM_MIXED ? (int)sizeof(float2) : (int)sizeof(double2);
+    for (int k = 0; k < 3; ++k) {
+      FFTPlan1D p{};
+      if (!factorize(d->mesh[k], p))
+        return fail(nullptr, CPM_EINVAL, "mesh size %d is not a product of 2, 3 and 5", d->mesh[k]);
+    }
+    if (d->mesh[2] > ZPASS_MAX_POINTS)
+      return fail(nullptr, CPM_EINVAL, "mesh has more than %d points along z", ZPASS_MAX_POINTS);
+    if (fft_xy_lds_bytes(d->mesh[0], d->mesh[1], elt, 1) > LDS_LIMIT)
+      return fail(nullptr, CPM_EINVAL, "x-y mesh plane too large for LDS");
+    const size_t spread = d->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(d->mesh[0], d->mesh[1])
+                                                    : fft_xy_spread_lds<double, double2>(d->mesh[0], d->mesh[1]);
+    if (spread > LDS_LIMIT)
+      return fail(nullptr, CPM_EINVAL, "mesh plane and site staging area (%zu bytes) exceed LDS", spread);
+  }
   if (d->geometry == CPM_DOUBLED_CELL && !d->elec_sub) return fail(nullptr, CPM_EINVAL, "doubled cell needs elec_sub");
   if (d->flags & ~CPM_FLAG_GRAPH) return fail(nullptr, CPM_EINVAL, "unknown descriptor flags 0x%x", d->flags);
   double qsum = 0.0, qabs = 0.0;
@@ -857,7 +886,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   }
   c->cell_b = cl;
   for (int k = 0; k < 3; ++k) c->cell_b.img[k] = (int)std::floor(c->rcut_b / c->box[k] + 0.5);
-  if (bin_lds_bytes(ns, cl.n_cells) > 150 * 1024) {
+  if (bin_lds_bytes(ns, cl.n_cells) > LDS_LIMIT) {
     fail(c, CPM_EINVAL, "%d sites in %d cells exceed the single-workgroup binning limit", ns, cl.n_cells);
     return bad(CPM_EINVAL);
   }
@@ -979,17 +1008,9 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       plans[k]->twf = dtf;
     }
     const size_t elt = c->precision == CPM_MIXED ? sizeof(float2) : sizeof(double2);
-    if ((size_t)2 * mi.K[0] * mi.K[1] * elt > 150 * 1024) {
-      fail(c, CPM_EINVAL, "x-y mesh plane too large for LDS");
-      return bad(CPM_EINVAL);
-    }
     // z pass: one wavefront per (x, y) column, up to 4 per workgroup, each
     // with three lines of Kz points in LDS (plus the shared twiddles)
-    if (mi.K[2] > ZPASS_MAX_POINTS) {
-      fail(c, CPM_EINVAL, "mesh has more than %d points along z", ZPASS_MAX_POINTS);
-      return bad(CPM_EINVAL);
-    }
-    const int cpw = (int)std::max<size_t>(1, std::min<size_t>(4, ((150 * 1024) / elt - mi.K[2]) / (3 * (size_t)mi.K[2])));
+    const int cpw = (int)std::max<size_t>(1, std::min<size_t>(4, (LDS_LIMIT / elt - mi.K[2]) / (3 * (size_t)mi.K[2])));
     ZPassArgs za{};
     za.Kx = mi.K[0]; za.Ky = mi.K[1]; za.Kz = mi.K[2];
     za.cpw = cpw;
@@ -1045,15 +1066,9 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
         fillp[sl]++;
       }
     c->n_touch = (int)touch.size();
-    {
-      const size_t need =
-          std::max(c->precision == CPM_MIXED ? fft_xy_spread_lds<float, float2>(mi.K[0], mi.K[1])
-                                             : fft_xy_spread_lds<double, double2>(mi.K[0], mi.K[1]),
-                   bin_lds_spread(ns, cl.n_cells));
-      if (need > 150 * 1024) {
-        fail(c, CPM_EINVAL, "mesh plane and site staging area (%zu bytes) exceed LDS", need);
-        return bad(CPM_EINVAL);
-      }
+    if (bin_lds_spread(ns, cl.n_cells) > LDS_LIMIT) {
+      fail(c, CPM_EINVAL, "%d sites in %d cells exceed the binning workgroup's LDS", ns, cl.n_cells);
+      return bad(CPM_EINVAL);
     }
     std::vector<float> gwf(gw.begin(), gw.end()), valf(val.begin(), val.end());
     if ((r = upload(c, &c->d_gidx, gidx)) || (r = upload(c, &c->d_gw, gw)) || (r = upload(c, &c->d_gwf, gwf)) ||

@@ -13,6 +13,8 @@ constexpr int WAVE = 64;
 constexpr int MAX_FFT_FACTORS = 12;
 constexpr int MAX_ORDER = 7;
 constexpr int STENCIL_MAX = 27;   // neighbour cells of a cell, itself included
+// dynamic LDS a launch may ask for (of the 160 KiB of a gfx950 CU)
+constexpr size_t LDS_LIMIT = 150 * 1024;
 // cell tiles of the real-space sums: workgroup size, candidates staged in
 // LDS per pass (256: ~32 KB of LDS per workgroup, five per CU; 512 left
 // three and measured 8% slower), targets per chunk
@@ -411,6 +413,8 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
                     const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr);
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky);
+// dynamic LDS of an x-y launch holding `planes` planes of elt_bytes complex values
+size_t fft_xy_lds_bytes(int Kx, int Ky, int elt_bytes, int planes);
 // threads of the spread + x-y transform workgroups (which also run the
 // binning): many-frame launches SPREAD_THREADS (256 measured faster than
 // 512 there: 3.7 -> 2.5 ms per 4096 frames), one-frame launches

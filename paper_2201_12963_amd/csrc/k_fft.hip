@@ -304,7 +304,7 @@ __device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int si
 // split (mode 1 only): blockIdx.y = 2 frame + part; part 1 transforms in_c2
 // into out_re2 (real part only), part 0 in_c as above
 // DIRECT: a one-frame launch (short lines are summed directly, see dft_lines)
-template <typename T, typename T2, bool DIRECT>
+template <typename T, typename T2, bool DIRECT, int PL>
 __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
                                                 const T* __restrict__ in_re, const T2* __restrict__ in_c,
                                                 T2* __restrict__ out_c, T* __restrict__ out_re,
@@ -312,9 +312,9 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
                                                 const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
   extern __shared__ __align__(16) unsigned char smem[];
   // PL consecutive planes per workgroup (many frames: the stages of several
-  // 18-point planes fill a 256-thread workgroup better than one), held one
-  // after the other in A and in B
-  constexpr int PL = DIRECT ? 1 : xy_planes_many<T2>();
+  // 18-point planes fill a 256-thread workgroup better than one; one plane
+  // where that many do not fit in LDS), held one after the other in A and in B
+  static_assert(!DIRECT || PL == 1, "a one-frame launch takes one plane per workgroup");
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
   T2* B = A + PL * NP;
@@ -694,18 +694,40 @@ size_t fft_xy_lds(const FFTPlan1D& px, const FFTPlan1D& py, int pl) {
   return (2 * (size_t)pl * px.n * py.n + px.n + py.n) * sizeof(T2);
 }
 
+// planes per workgroup of a many-frame x-y launch: xy_planes_many() where
+// they fit in LDS, else one
+template <typename T2>
+int xy_planes_fit(const FFTPlan1D& px, const FFTPlan1D& py) {
+  return fft_xy_lds<T2>(px, py, xy_planes_many<T2>()) <= LDS_LIMIT ? xy_planes_many<T2>() : 1;
+}
+
+size_t fft_xy_lds_bytes(int Kx, int Ky, int elt_bytes, int planes) {
+  return (2 * (size_t)planes * Kx * Ky + Kx + Ky) * (size_t)elt_bytes;
+}
+
+// many-frame x-y launch with pl planes per workgroup; grid.y = ny (frames,
+// or frames x 2 parts for the split field transform)
+template <typename T, typename T2>
+void launch_xy_many(hipStream_t s, const FFTPlan1D& px, const FFTPlan1D& py, int Kz, int ny, int mode,
+                    const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im, size_t out_re_stride, int split,
+                    const T2* in_c2, T* out_re2) {
+  const int pl = xy_planes_fit<T2>(px, py);
+  auto* k = pl == 1 ? k_fft_xy<T, T2, false, 1> : k_fft_xy<T, T2, false, xy_planes_many<T2>()>;
+  hipLaunchKernelGGL(k, dim3((Kz + pl - 1) / pl, ny), dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, pl), s, px, py, Kz,
+                     mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, split, in_c2, out_re2);
+}
+
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                      int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
                      size_t out_re_stride) {
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
   if (n_frames == 1)
-    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 1), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
+    hipLaunchKernelGGL((k_fft_xy<T, T2, true, 1>), dim3(Kz, 1), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
                        Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
   else
-    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + xy_planes_many<T2>() - 1) / xy_planes_many<T2>(), n_frames),
-                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, xy_planes_many<T2>()), s, px, py, Kz, mode, in_re, in_c,
-                       out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
+    launch_xy_many<T, T2>(s, px, py, Kz, n_frames, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0,
+                          (const T2*)nullptr, (T*)nullptr);
 }
 
 template <typename T, typename T2>
@@ -713,12 +735,11 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
                                const T2* c1, const T2* c2, T* E, size_t frame_stride) {
   const size_t M = (size_t)px.n * py.n * Kz;
   if (n_frames == 1)
-    hipLaunchKernelGGL((k_fft_xy<T, T2, true>), dim3(Kz, 2), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
+    hipLaunchKernelGGL((k_fft_xy<T, T2, true, 1>), dim3(Kz, 2), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
                        Kz, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
   else
-    hipLaunchKernelGGL((k_fft_xy<T, T2, false>), dim3((Kz + xy_planes_many<T2>() - 1) / xy_planes_many<T2>(), 2 * n_frames),
-                       dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, xy_planes_many<T2>()), s, px, py, Kz, 1,
-                       (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
+    launch_xy_many<T, T2>(s, px, py, Kz, 2 * n_frames, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride,
+                          1, c2, E + 2 * M);
 }
 
 template <typename T, typename T2>

@@ -35,7 +35,8 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libcpm.so not built")
 def test_create_rejects_bad_descriptors_without_gpu():
-    """Descriptor validation happens before any device call."""
+    """Descriptor validation, mesh factorisation and LDS sizing included,
+    happens before any device call."""
     import numpy as np
     from paper_2201_12963_amd import binding
     from workloads import make_workload
@@ -51,9 +52,12 @@ def test_create_rejects_bad_descriptors_without_gpu():
         dict(elec_side=np.zeros(w.n_elec, np.int8)),
         dict(geometry=1),                                    # doubled cell without elec_sub
         dict(kspace=1, mesh=(16, 4, 64), order=5),           # fewer mesh points than the stencil
-        dict(kspace=1, mesh=(7, 16, 64)),                    # 7 is not 2^a 3^b 5^c ... rejected before GPU
+        dict(kspace=1, mesh=(7, 16, 64)),                    # 7 is not a product of 2, 3 and 5
+        dict(kspace=1, mesh=(16, 16, 4096)),                 # longer z columns than the z pass takes
+        dict(kspace=1, mesh=(64, 64, 64)),                   # FP64 plane + staging list exceed LDS
+        dict(kspace=0, precision=1),                         # mixed precision needs PPPM
     ]
-    for over in cases[:6]:
+    for over in cases:
         with pytest.raises(binding.CpmError) as ei:
             binding.Context(**{**base, **over})
         assert ei.value.code == binding.CPM_EINVAL

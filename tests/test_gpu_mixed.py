@@ -2,10 +2,11 @@
 
 The mixed path (FP32 mesh, FFT and real space, FP32 GEMV on centred b or the
 bf16x3 split GEMM for batches, FP64 re-projection and energy sums) is
-compared with the FP64 GPU path on the same inputs, per result, and held to
-the method's bars (1e-6 e per charge, 1e-4 relative RMS force).  The FP64
-path at the largest cell (6.8 x 6.8 nm, 3520 electrode atoms, 5120 sites)
-is compared with the oracle.
+compared per result (charges, forces, U_coul, E_cp) with the FP64 oracle on
+the same inputs and held to the method's bars (1e-6 e per charge, 1e-4
+relative RMS force); its distance from the FP64 GPU path is printed beside
+it.  The FP64 path at the largest cell (6.8 x 6.8 nm, 3520 electrode atoms,
+5120 sites) is compared with the oracle.
 """
 
 import sys
@@ -60,33 +61,45 @@ def solve_both(torch, w, frames=None, dvs=None):
 @pytest.mark.parametrize("name,geometry", [("paper", "ff"), ("paper", "dc"), ("large", "ff")])
 def test_mixed_single_frame(torch_dev, name, geometry):
     _say(f"[gpu] mixed {name} {geometry}")
-    w = workload(name, geometry)
+    w, A, S = built(name, geometry)
+    ref = cpm.step(w, A, S, cpm.Electrostatics(w, "pppm"))
     (q64, f64, e64), (q32, f32, e32) = solve_both(torch_dev, w)
-    dq = np.abs(q32 - q64).max()
-    df = rel_rms(f32, f64)
-    de = np.abs(e32 - e64)
-    _say(f"    mixed vs fp64: q max {dq:.3e} e (|q| max {np.abs(q64).max():.3e}), F rel rms {df:.3e}, "
-         f"U_coul {de[0]:.3e} eV, E_cp {de[1]:.3e} eV")
+    dq = np.abs(q32 - ref["q"]).max()
+    df = rel_rms(f32, ref["f"])
+    du = abs(e32[0] - ref["u_coul"])
+    de = abs(e32[1] - ref["e_cp"])
+    _say(f"    mixed vs oracle: q max {dq:.3e} e (|q| max {np.abs(ref['q']).max():.3e}), F rel rms {df:.3e}, "
+         f"U_coul {du:.3e} eV of {abs(ref['u_coul']):.3e}, E_cp {de:.3e} eV")
+    _say(f"    mixed vs fp64 GPU: q max {np.abs(q32 - q64).max():.3e} e, F rel rms {rel_rms(f32, f64):.3e}")
     assert dq < Q_TOL
     assert df < F_RTOL
     assert abs(q32.sum()) < 1e-12
-    assert de[0] < 1e-5 * abs(e64[0]) + 1e-6
+    assert du < 1e-5 * abs(ref["u_coul"]) + 1e-6
+    assert de < 1e-5 * abs(ref["e_cp"]) + 1e-6
+    if geometry == "dc":
+        assert abs(q32[w.elec_sub.astype(bool)].sum()) < 1e-12
 
 
 @pytest.mark.parametrize("geometry", ["ff", "dc"])
 def test_mixed_batch(torch_dev, geometry):
     from workloads import perturbed_frames
     _say(f"[gpu] mixed batch paper {geometry}")
-    w = workload("paper", geometry)
+    w, A, S = built("paper", geometry)
     frames = perturbed_frames(w, 8, sigma=0.05, seed=4)
     dvs = np.linspace(0.0, 4.0, 5)
     (q64, f64, e64), (q32, f32, e32) = solve_both(torch_dev, w, frames, dvs)
-    dq = np.abs(q32 - q64).max()
-    df = rel_rms(f32, f64)
-    _say(f"    bf16x3 batch vs fp64: q max {dq:.3e} e, F rel rms {df:.3e}, "
-         f"U max {np.abs(e32[..., 0] - e64[..., 0]).max():.3e} eV")
-    assert dq < Q_TOL
-    assert df < F_RTOL
+    _say(f"    bf16x3 batch vs fp64 GPU: q max {np.abs(q32 - q64).max():.3e} e, F rel rms {rel_rms(f32, f64):.3e}")
+    es = cpm.Electrostatics(w, "pppm")
+    for fi, vi in ((0, 0), (3, 2), (7, 4)):
+        ref = cpm.step(w, A, S, es, site_xyz=frames[fi], dv=dvs[vi])
+        dq = np.abs(q32[fi, vi] - ref["q"]).max()
+        df = rel_rms(f32[fi, vi], ref["f"])
+        du = abs(e32[fi, vi, 0] - ref["u_coul"])
+        _say(f"    frame {fi} dV {dvs[vi]}: mixed vs oracle q max {dq:.3e} e, F rel rms {df:.3e}, U_coul {du:.3e} eV")
+        assert dq < Q_TOL
+        assert df < F_RTOL
+        assert du < 1e-5 * abs(ref["u_coul"]) + 1e-6
+        assert abs(e32[fi, vi, 1] - ref["e_cp"]) < 1e-5 * abs(ref["e_cp"]) + 1e-6
     if geometry == "dc":
         sub = w.elec_sub.astype(bool)
         assert np.abs(q32[..., sub].sum(-1)).max() < 1e-12
@@ -126,17 +139,27 @@ def test_large_cell_fp64_against_oracle(torch_dev):
 
 
 def test_mixed_batch_many_frames_within_bar(torch_dev):
-    """4096 perturbed frames: every mixed-precision charge within 1e-6 e of FP64.
+    """4096 perturbed frames: every mixed-precision charge within 1e-6 e of FP64,
+    and sampled frames within the bars of the oracle.
 
     Guards the two places where FP32 would otherwise cross the bar on a few
     frames: displacements of ~10 nm coordinates (formed in FP64) and the
     real-space cutoff test (taken in FP64, so both paths keep the same pairs)."""
     from workloads import perturbed_frames
     _say("[gpu] mixed batch, 4096 frames paper ff")
-    w = workload("paper", "ff")
+    w, A, S = built("paper", "ff")
     frames = perturbed_frames(w, 4096)
     dvs = np.array([0.0, 4.0])
-    (q64, _, _), (q32, _, _) = solve_both(torch_dev, w, frames, dvs)
+    (q64, _, _), (q32, f32, e32) = solve_both(torch_dev, w, frames, dvs)
     per_frame = np.abs(q32 - q64).max(axis=(1, 2))
     _say(f"    max {per_frame.max():.3e} e, frames above 1e-6: {int((per_frame > Q_TOL).sum())}")
     assert per_frame.max() < Q_TOL
+    es = cpm.Electrostatics(w, "pppm")
+    for fi, vi in ((int(np.argmax(per_frame)), 1), (4095, 0)):
+        ref = cpm.step(w, A, S, es, site_xyz=frames[fi], dv=dvs[vi])
+        dq = np.abs(q32[fi, vi] - ref["q"]).max()
+        df = rel_rms(f32[fi, vi], ref["f"])
+        _say(f"    frame {fi} dV {dvs[vi]}: mixed vs oracle q max {dq:.3e} e, F rel rms {df:.3e}")
+        assert dq < Q_TOL
+        assert df < F_RTOL
+        assert abs(e32[fi, vi, 0] - ref["u_coul"]) < 1e-5 * abs(ref["u_coul"]) + 1e-6

@@ -162,3 +162,106 @@ def test_batch_size_tuner_keeps_results(torch_dev):
             assert rel_rms(Fb[fi, vi], f) < 1e-10
             assert np.abs(Eb[fi, vi] - e).max() < 1e-9 * np.abs(e).max()
     ctx.close()
+
+
+@pytest.mark.parametrize("chunk", [4096, 2048])
+def test_fp64_batch_at_full_launch_size(torch_dev, chunk, monkeypatch):
+    """The FP64 batch in the launch configuration the throughput figure uses:
+    4096 perturbed frames x 2 dV in launches of `chunk` frames.  Frames at
+    both ends of each launch are compared with the single-frame path and two
+    of them with the oracle."""
+    torch = torch_dev
+    from paper_2201_12963_amd import Context
+    from paper_2201_12963_amd.binding import BUF_BATCH_CHUNK
+    from workloads import perturbed_frames
+    _say(f"[gpu] fp64 batch paper ff, 4096 frames in launches of {chunk}")
+    monkeypatch.setenv("CPM_BATCH_CHUNK", str(chunk))
+    w, A, S = built("paper", "ff")
+    frames = perturbed_frames(w, 4096)
+    dvs = np.array([0.0, 4.0])
+    stream = torch.cuda.Stream()
+    ctx = Context.from_workload(w, stream=stream)
+    ctx.build_elastance()
+    X = torch.tensor(frames, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        Qb, Fb, Eb = ctx.solve_batch(X, dvs)
+    stream.synchronize()
+    assert ctx.sync_status() == 0
+    Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
+    for fi in (0, 2047, 2048, 4095):
+        x = torch.tensor(frames[fi], dtype=torch.float64, device="cuda")
+        for vi, dv in enumerate(dvs):
+            with torch.cuda.stream(stream):
+                q, f, e = ctx.solve(x, float(dv))
+            stream.synchronize()
+            q, f, e = q.cpu().numpy(), f.cpu().numpy(), e.cpu().numpy()
+            assert np.abs(Qb[fi, vi] - q).max() < 1e-11
+            assert rel_rms(Fb[fi, vi], f) < 1e-10
+            assert np.abs(Eb[fi, vi] - e).max() < 1e-9 * np.abs(e).max()
+    es = cpm.Electrostatics(w, "pppm")
+    for fi, vi in ((2047, 1), (4095, 0)):
+        ref = cpm.step(w, A, S, es, site_xyz=frames[fi], dv=dvs[vi])
+        qerr = np.abs(Qb[fi, vi] - ref["q"]).max()
+        fr = rel_rms(Fb[fi, vi], ref["f"])
+        _say(f"    frame {fi} dV {dvs[vi]}: q err {qerr:.2e} e, F rel rms {fr:.2e}")
+        assert qerr < 1e-8 * np.abs(ref["q"]).max() + 1e-12
+        assert fr < 1e-9
+        assert abs(Eb[fi, vi, 0] - ref["u_coul"]) < 1e-9 * abs(ref["u_coul"])
+        assert abs(Eb[fi, vi, 1] - ref["e_cp"]) < 1e-9 * abs(ref["e_cp"])
+    ctx.close()
+
+
+def test_batch_with_planes_too_large_for_three_per_workgroup(torch_dev):
+    """FP64 x-y planes of 48 x 45 points: three of them (with the ping-pong
+    copies) exceed the LDS of a workgroup, so the many-frame x-y launches take
+    one plane per workgroup; the batch must still match the single frames."""
+    _say("[gpu] batch tiles: tiny ff with PPPM mesh 48x45x64, 3 frames")
+    w0, A, S = built("tiny", "ff")
+    w = dataclasses.replace(w0, kspace="pppm", mesh=(48, 45, 64))
+    assert (2 * 3 * 48 * 45 + 48 + 45) * 16 > 150 * 1024
+    from workloads import perturbed_frames
+    frames = perturbed_frames(w, 3, sigma=0.05, seed=9)
+    run_batch_case(torch_dev, w, A, S, frames, np.array([0.0, 2.0]), ((1, 1),))
+
+
+def test_calls_outside_the_context_stream(torch_dev):
+    """solve, solve_batch, grad and the autograd loss called on torch's current
+    stream (not inside `with torch.cuda.stream(ctx.stream)`) give the same
+    results as calls inside it: the binding orders the two streams."""
+    torch = torch_dev
+    from paper_2201_12963_amd import Context
+    from paper_2201_12963_amd.autograd import cpm_loss
+    from workloads import perturbed_frames
+    _say("[gpu] calls outside the context stream, paper ff")
+    w, A, S = built("paper", "ff")
+    stream = torch.cuda.Stream()
+    ctx = Context.from_workload(w, stream=stream)
+    ctx.build_elastance()
+    frames = perturbed_frames(w, 4, sigma=0.05, seed=3)
+    dvs = np.array([0.0, 2.0])
+    t = torch.tensor(np.random.default_rng(2).normal(0, 0.01, w.n_elec), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        X = torch.tensor(frames, dtype=torch.float64, device="cuda")
+        ref_solve = [a.clone() for a in ctx.solve(X[1].contiguous(), 2.0)]
+        ref_batch = [a.clone() for a in ctx.solve_batch(X, dvs)]
+        ref_grad = [a.clone() for a in ctx.grad(X[2].contiguous(), 2.0, t)]
+    stream.synchronize()
+    for rep in range(3):
+        # inputs made on the current stream right before the call, outputs read right after
+        X2 = torch.tensor(frames, dtype=torch.float64, device="cuda") * 1.0
+        got = ctx.solve(X2[1].contiguous(), 2.0)
+        for a, b in zip(got, ref_solve):
+            assert torch.allclose(a, b, rtol=0, atol=1e-12 * float(b.abs().max()))
+        got = ctx.solve_batch(X2, dvs)
+        for a, b in zip(got, ref_batch):
+            assert torch.allclose(a, b, rtol=0, atol=1e-12 * float(b.abs().max()))
+        got = ctx.grad(X2[2].contiguous(), 2.0, t)
+        for a, b in zip(got, ref_grad):
+            assert torch.allclose(a, b, rtol=0, atol=1e-11 * float(b.abs().max()))
+        x = X2[2].clone().requires_grad_(True)
+        dv = torch.tensor(2.0, dtype=torch.float64, device="cuda", requires_grad=True)
+        loss, q = cpm_loss(ctx, x, dv, t)
+        loss.backward()
+        assert abs(loss.item() - ref_grad[0].item()) < 1e-11 * abs(ref_grad[0].item())
+        assert torch.allclose(x.grad, ref_grad[1], rtol=0, atol=1e-11 * float(ref_grad[1].abs().max()))
+    ctx.close()

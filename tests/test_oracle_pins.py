@@ -101,6 +101,43 @@ def test_ff_dc_mismatch_shrinks_with_lz():
         prev = mismatch
 
 
+def test_ff_dc_agreement_with_electrolyte():
+    """Filled cell: finite field against the first sub-cell of the doubled cell.
+
+    * The net charge of each electrode is set by the laterally averaged
+      (one-dimensional) part of the electrostatics, where the empty-capacitor
+      ratio (g - s)/(g - s Lz/(Lz - g)) applies to the electrolyte-induced
+      charge as well; the two geometries' net charges stand in that ratio at
+      dpsi = 0 and 2 V.
+    * The in-plane charge pattern (charges minus their electrode's mean) is
+      the same in both up to the small influence of the second sub-cell
+      through the electrodes (screening, Doubled Cell Method subsection).
+    * The doubled cell is mirror-symmetric about the plane between the
+      sub-cells (electrolyte mirrored, polarity reversed), so each atom of the
+      second sub-cell carries the charge of its mirror atom in the first.
+    """
+    wf, Af, Sf = built("tiny", "ff")
+    wd, Ad, Sd = built("tiny", "dc")
+    n = wf.n_elec
+    seff = honeycomb_seff(wf.box[0] / 6, wf.box[1] / 3, wf.eta)
+    g, lz = 4.34, wf.box[2]
+    ratio = (g - seff) / (g - seff * lz / (lz - g))
+    up = wf.elec_side > 0
+    half = n // 2
+    for dv in (0.0, 2.0):
+        qf = cpm.step(wf, Af, Sf, cpm.Electrostatics(wf, "exact"), dv=dv, with_forces=False)["q"]
+        qd = cpm.step(wd, Ad, Sd, cpm.Electrostatics(wd, "exact"), dv=dv, with_forces=False)["q"]
+        q1, q2 = qd[:n], qd[n:]
+        assert abs(qf[up].sum() / q1[up].sum() - ratio) < 5e-5
+        assert abs(qf[~up].sum() / q1[~up].sum() - ratio) < 5e-5
+        for m in (up, ~up):
+            a, b = qf[m] - qf[m].mean(), q1[m] - q1[m].mean()
+            assert np.abs(a - b).max() < 1e-3 * np.abs(a).max()
+        # mirror: sub-cell 1 upper layer <-> sub-cell 2 lower layer (same x, y)
+        assert np.abs(q2[:half] - q1[half:]).max() < 1e-12
+        assert np.abs(q2[half:] - q1[:half]).max() < 1e-12
+
+
 # --------------------------------------------------------------------------
 # P1 / P2 / P7: constraint algebra
 # --------------------------------------------------------------------------
@@ -240,14 +277,19 @@ def test_bruteforce_reciprocal_tiny_cell():
 # P8 / P12: forces and gradient against finite differences
 # --------------------------------------------------------------------------
 
-def test_forces_match_energy_derivative():
-    """F_j = -dE_cp/dR_j along q*(R) (exact Ewald, central differences, h = 1e-5 nm)."""
-    w, A, S = built("tiny", "ff")
+@pytest.mark.parametrize("geometry", ["ff", "dc"])
+def test_forces_match_energy_derivative(geometry):
+    """F_j = -dE_cp/dR_j along q*(R) (exact Ewald, central differences, h = 1e-5 nm).
+
+    Finite field: E_cp = U_coul - dpsi d.q + dpsi/Lz (z.q + sum Q_j Z_j);
+    doubled cell: E_cp = U_coul - dpsi d.q.  A slip in either branch (a sign,
+    a dropped field term) moves the derivative away from the force."""
+    w, A, S = built("tiny", geometry)
     es = cpm.Electrostatics(w, "exact")
     r = cpm.step(w, A, S, es)
     h = 1e-5
     fmax = np.abs(r["f"]).max()
-    for j in (0, 17, 63, 99):
+    for j in (0, 17, 63, w.n_site - 1):
         for d in range(3):
             xp = w.site_xyz.copy(); xp[d, j] += h
             xm = w.site_xyz.copy(); xm[d, j] -= h
@@ -264,9 +306,10 @@ def test_internal_forces_sum_to_zero():
     assert np.abs(f.sum(axis=1)).max() < 1e-10 * np.abs(f).max()
 
 
-def test_gradient_matches_finite_differences():
+@pytest.mark.parametrize("geometry", ["ff", "dc"])
+def test_gradient_matches_finite_differences(geometry):
     """d/dR and d/ddpsi of L = sum (q - t)^2 + U_coul by the adjoint (exact Ewald)."""
-    w, A, S = built("tiny", "ff")
+    w, A, S = built("tiny", geometry)
     es = cpm.Electrostatics(w, "exact")
     t = np.random.default_rng(5).normal(0.0, 0.01, w.n_elec)
     g = cpm.loss_gradient(w, A, S, es, t)
@@ -277,7 +320,7 @@ def test_gradient_matches_finite_differences():
 
     h = 1e-5
     gmax = np.abs(g["dl_dx"]).max()
-    for j in (3, 50, 91):
+    for j in (3, 50, w.n_site - 9):
         for d in range(3):
             xp = w.site_xyz.copy(); xp[d, j] += h
             xm = w.site_xyz.copy(); xm[d, j] -= h
@@ -366,6 +409,32 @@ def test_pppm_against_exact_ewald():
     frms = np.sqrt(np.mean((r1["f"] - r2["f"]) ** 2))
     assert frms / (KE / 0.01) < 1e-5
     assert abs(r1["u_coul"] - r2["u_coul"]) < 1e-3 * abs(r1["u_coul"])
+
+
+# converged Ewald parameters for the accuracy checks of the working meshes:
+# erfc(alpha rc) and exp(-kc^2/4alpha^2) are both ~1e-8 (alpha rc = kc/2alpha = 4.16)
+REF_ALPHA, REF_RCUT, REF_KCUT = 1.6, 2.6, 13.4
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,geometry", [("paper", "ff"), ("paper", "dc"), ("large", "ff")])
+def test_working_mesh_meets_force_accuracy(name, geometry):
+    """The meshes the GPU path runs (paper cell 18x18x64, doubled 18x18x128,
+    large cell 36x36x64; order 5, alpha = 2.21/nm, rc = 1.2 nm) meet the
+    relative force accuracy 1e-5: RMS force error against converged Ewald,
+    at the same electrode charges, divided by the force between two unit
+    charges 0.1 nm apart (k_e / 0.01 nm^2 = 144 eV/nm).  The charge error of
+    the PPPM b against the converged b is ~1e-5 e (the discretisation budget),
+    which is why the GPU's 1e-6 e bar is taken against the PPPM oracle."""
+    w, A, S = built(name, geometry)
+    r = cpm.step(w, A, S, cpm.Electrostatics(w, "pppm"))
+    f_ref = ewald.coulomb_forces(w.site_xyz, w.site_q, w.elec_xyz, r["q"], w.box, w.eta,
+                                 REF_ALPHA, REF_RCUT, REF_KCUT) + cpm.field_force(w, w.dv)
+    frms = np.sqrt(np.mean((f_ref - r["f"]) ** 2)) / (KE / 0.01)
+    assert frms < 1e-5
+    b_ref = ewald.b_vector(w.elec_xyz, w.site_xyz, w.site_q, w.box, w.eta, REF_ALPHA, REF_RCUT, REF_KCUT)
+    q_ref = S @ (b_ref + w.dv * cpm.drive_vector(w))
+    assert np.abs(q_ref - r["q"]).max() < 1e-4
 
 
 def test_pppm_converges_to_ewald_on_fine_mesh():
