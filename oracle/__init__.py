@@ -16,6 +16,7 @@ ewald   exact Ewald sums with Gaussian electrode charges (Eq. 1-3)
 pppm    particle-particle particle-mesh sums with the same splitting
 cpm     the electroneutral constant-potential solve (Eq. 4-15), energy,
         forces and the adjoint gradient
+slab    the charged-sheet correction of the slab geometry (Fig. 2b)
 cells   cell binning of electrolyte sites (integer reference)
 
 Parity status: every function here is pinned by the CPU tests in

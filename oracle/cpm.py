@@ -29,7 +29,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg
 
-from . import ewald, pppm
+from . import ewald, pppm, slab
 
 
 def inverse_elastance(A):
@@ -53,11 +53,20 @@ def projected_inverse(A, e1=None):
 
 
 def drive_vector(w):
-    """c with v = b + dpsi c: d for the doubled cell, d - z/Lz for the finite field."""
+    """c with v = b + dpsi c: d for the doubled cell, d - z/Lz for the finite field.
+
+    The finite-field form takes z wrapped into [0, Lz); it is Eq. (11) with
+    the lower electrode's z taken one period up only if neither electrode
+    crosses the cell boundary z = 0 (the ramp potential must be continuous
+    inside each electrode), which is asserted here."""
     d = 0.5 * w.elec_side.astype(np.float64)
-    if w.geometry == "dc":
+    if w.geometry in ("dc", "slab"):
         return d
     z = w.elec_xyz[2] - w.box[2] * np.floor(w.elec_xyz[2] / w.box[2])
+    for side in (-1, 1):
+        zs = z[w.elec_side == side]
+        if zs.max() - zs.min() > 0.5 * w.box[2]:
+            raise ValueError("a finite-field electrode crosses the cell boundary z = 0")
     return d - z / w.box[2]
 
 
@@ -78,8 +87,12 @@ def sub_cell_vector(w):
 # --------------------------------------------------------------------------
 
 def elastance(w):
-    """A for the workload's electrodes with its converged Ewald parameters."""
-    return ewald.elastance(w.elec_xyz, w.box, w.eta, w.alpha_exact, w.rcut_exact, w.kcut_exact)
+    """A for the workload's electrodes with its converged Ewald parameters
+    (plus the slab correction's z z^T block in slab geometry)."""
+    A = ewald.elastance(w.elec_xyz, w.box, w.eta, w.alpha_exact, w.rcut_exact, w.kcut_exact)
+    if w.geometry == "slab":
+        A = A + slab.elastance_term(w.elec_xyz, w.box)
+    return A
 
 
 def build(w, A=None):
@@ -104,6 +117,24 @@ class Electrostatics:
             self.G = pppm.influence(w.box, w.mesh, w.order, w.alpha)
 
     def b(self, site_xyz):
+        b = self._b(site_xyz)
+        if self.w.geometry == "slab":
+            b = b + slab.b_term(self.w.elec_xyz, site_xyz, self.w.site_q, self.w.box)
+        return b
+
+    def u_elyt(self, site_xyz):
+        u = self._u_elyt(site_xyz)
+        if self.w.geometry == "slab":
+            u = u + slab.energy_term(site_xyz, self.w.site_q, self.w.box)
+        return u
+
+    def forces(self, site_xyz, elec_q):
+        f = self._forces(site_xyz, elec_q)
+        if self.w.geometry == "slab":
+            f = f + slab.force_term(site_xyz, self.w.site_q, self.w.elec_xyz, elec_q, self.w.box)
+        return f
+
+    def _b(self, site_xyz):
         w = self.w
         if self.method == "exact":
             return ewald.b_vector(w.elec_xyz, site_xyz, w.site_q, w.box, w.eta,
@@ -114,7 +145,7 @@ class Electrostatics:
         return pppm.b_vector(w.elec_xyz, site_xyz, w.site_q, w.box, w.eta, w.alpha, w.rcut,
                              w.mesh, w.order, G=self.G)
 
-    def u_elyt(self, site_xyz):
+    def _u_elyt(self, site_xyz):
         w = self.w
         if self.method == "exact":
             return ewald.electrolyte_energy(site_xyz, w.site_q, w.box, w.alpha_exact,
@@ -124,7 +155,7 @@ class Electrostatics:
         return pppm.electrolyte_energy(site_xyz, w.site_q, w.box, w.alpha, w.rcut,
                                        w.mesh, w.order, G=self.G)
 
-    def forces(self, site_xyz, elec_q):
+    def _forces(self, site_xyz, elec_q):
         w = self.w
         if self.method == "exact":
             return ewald.coulomb_forces(site_xyz, w.site_q, w.elec_xyz, elec_q, w.box, w.eta,
@@ -148,7 +179,7 @@ def energies(w, A, q, b, u_elyt, site_xyz, dv):
     """U_coul of Eq. (3) at q and the constant-potential energy E_cp.
 
     U_coul = U_elyt - q.b + 1/2 q.A q.
-    E_cp   = U_coul - dpsi d.q                       (doubled cell)
+    E_cp   = U_coul - dpsi d.q                       (doubled cell, slab)
            = U_coul - dpsi d.q + dpsi/Lz (z.q + sum_j Q_j Z_j)   (finite field)
     E_cp is stationary in q on the neutral subspace at q*, so its negative
     gradient in the site positions at fixed q is the force on the sites.

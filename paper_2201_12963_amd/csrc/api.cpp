@@ -843,6 +843,23 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     if (d->geometry == CPM_DOUBLED_CELL) n1 += d->elec_sub[i] != 0;
   }
   if (npos == 0 || npos == d->n_elec) return fail(nullptr, CPM_EINVAL, "need atoms on both electrodes");
+  if (d->geometry == CPM_FINITE_FIELD) {
+    // the drive d - z/Lz uses z wrapped into [0, Lz): the applied ramp must
+    // not jump inside an electrode, so neither may cross z = 0
+    for (int side = -1; side <= 1; side += 2) {
+      double lo = 1e300, hi = -1e300;
+      for (int i = 0; i < d->n_elec; ++i) {
+        if (d->elec_side[i] != side) continue;
+        const double z = d->elec_xyz[2 * d->n_elec + i];
+        const double zw = z - d->box[2] * std::floor(z / d->box[2]);
+        lo = std::min(lo, zw);
+        hi = std::max(hi, zw);
+      }
+      if (hi - lo > 0.5 * d->box[2])
+        return fail(nullptr, CPM_EINVAL, "finite field: an electrode crosses the cell boundary z = 0 "
+                                         "(place the boundary behind the electrodes)");
+    }
+  }
   if (d->geometry == CPM_DOUBLED_CELL && (n1 == 0 || n1 == d->n_elec))
     return fail(nullptr, CPM_EINVAL, "doubled cell needs atoms in both sub-cells");
 

@@ -6,13 +6,14 @@ must have, finite differences and a textbook lattice constant.
 """
 
 import dataclasses
+import functools
 import math
 
 import numpy as np
 import pytest
 
 from conftest import built, workload
-from oracle import KE, cells, cpm, ewald, pppm
+from oracle import KE, cells, cpm, ewald, pppm, slab
 
 EPS0 = 1.0 / (4.0 * math.pi * KE)
 
@@ -467,3 +468,190 @@ def test_cell_binning_is_a_valid_stable_partition():
         lo = cc * w.box[d] / n[d]
         hi = (cc + 1) * w.box[d] / n[d]
         assert np.all(x >= lo - 1e-12) and np.all(x < hi + 1e-12)
+
+
+# --------------------------------------------------------------------------
+# three charged sheets per electrode (snapshot re-solves)
+# --------------------------------------------------------------------------
+
+def test_three_layer_nearest_sheet_share():
+    """With all three sheets of each electrode charged, more than 90% of each
+    electrode's net charge sits on the sheet nearest the electrolyte
+    (Electrolyte and Charge Densities); the next sheet carries a small charge
+    of the opposite sign (the Gaussian smearing of the nearest sheet lets a
+    little of the field through), and the sheets stay neutral in sum with
+    their counter-electrode (e.q* = 0)."""
+    from workloads import make_workload
+    w = make_workload("tiny", "ff", layers=3)
+    A, S = cpm.build(w)
+    q = cpm.step(w, A, S, cpm.Electrostatics(w, "ewald"), dv=2.0, with_forces=False)["q"]
+    assert abs(q.sum()) < 1e-12
+    for side in (-1, 1):
+        m = w.elec_side == side
+        tot = q[m].sum()
+        share = [q[m & (w.elec_layer == k)].sum() / tot for k in range(3)]
+        assert share[0] > 0.9
+        assert share[1] < 0 and abs(share[1]) < 0.1
+        assert abs(share[2]) < abs(share[1])
+
+
+def _layer_lattice_potential(dxy, dz, cx, cy, eta, nmax=40):
+    """Potential (V per e on each atom of the lattice, k_e included) at a
+    Gaussian charge from a rectangular cx x cy lattice of Gaussian charges of
+    one basis site, offset in-plane by dxy and vertically by dz from it.
+
+    Written from the 2D Fourier series of the interaction erf(beta r)/r,
+    beta = eta/sqrt2 (two Gaussians of Eq. 2), of a lattice with cell area a:
+      (2 pi k_e / a) { -[dz erf(beta dz) + exp(-beta^2 dz^2)/(beta sqrt(pi))]
+        + sum_{G != 0} cos(G.dxy) [e^{G dz} erfc(G/2beta + beta dz)
+                                   + e^{-G dz} erfc(G/2beta - beta dz)] / (2G) }
+    (the G = 0 term up to a constant that cancels for a neutral system).  The
+    self-interaction of a Gaussian is the dxy = dz = 0 term of its own lattice."""
+    from scipy.special import erf, erfc
+    beta = eta / math.sqrt(2.0)
+    i, j = np.meshgrid(np.arange(-nmax, nmax + 1), np.arange(-nmax, nmax + 1), indexing="ij")
+    G = np.stack([2 * math.pi * i / cx, 2 * math.pi * j / cy], -1).reshape(-1, 2)
+    g = np.linalg.norm(G, axis=1)
+    keep = g > 0
+    G, g = G[keep], g[keep]
+    z = abs(dz)
+    # e^{Gz} erfc(G/2b + b z) written as erfcx-stable products
+    t1 = np.exp(g * z - (g / (2 * beta) + beta * z) ** 2) * _erfcx(g / (2 * beta) + beta * z)
+    t2 = np.exp(-g * z) * erfc(g / (2 * beta) - beta * z)
+    s = np.sum(np.cos(G @ np.asarray(dxy)) * (t1 + t2) / (2 * g))
+    g0 = -(z * erf(beta * z) + math.exp(-(beta * z) ** 2) / (beta * math.sqrt(math.pi)))
+    return 2 * math.pi * KE / (cx * cy) * (g0 + s)
+
+
+def _erfcx(x):
+    from scipy.special import erfcx
+    return erfcx(x)
+
+
+def test_three_layer_empty_capacitor_lattice_sums():
+    """Empty capacitor with three charged sheets per electrode (A-B-A), doubled
+    cell with a wide back region: the charge of every atom class (sheet,
+    basis site) from a small linear system built on 2D lattice sums (each
+    class's potential equals its electrode's potential, total charge zero),
+    against the oracle's 3D Ewald solve.  The A-B stacking makes the atoms of
+    a B sheet inequivalent (above an atom or a hexagon centre of the next
+    sheet), so each of the 4 basis sites of a sheet is its own class."""
+    from workloads import make_workload
+    w0 = make_workload("tiny", "dc", layers=3)
+    n1 = w0.n_elec // 2                             # first sub-cell
+    lz = 10.0                                       # back regions of ~4.3 nm
+    ex = w0.elec_xyz.copy()
+    ex[2, n1:] = w0.elec_xyz[2, :n1] + lz           # second sub-cell one period up
+    w = dataclasses.replace(w0, box=np.array([w0.box[0], w0.box[1], 2 * lz]), elec_xyz=ex).empty()
+    A, S = cpm.build(w)
+    dv = 2.0
+    q = S @ (dv * cpm.drive_vector(w))
+    cx, cy = w.box[0] / 6, w.box[1] / 3
+    # classes of the first sub-cell: atoms are generated sheet by sheet, cell
+    # by cell, 4 basis sites per cell
+    idx = np.arange(n1)
+    per_sheet = 6 * 3 * 4
+    sheet = idx // per_sheet
+    basis = idx % 4
+    first = {}
+    for k in range(n1):
+        first.setdefault((sheet[k], basis[k]), k)
+    classes = sorted(first)
+    nc = len(classes)
+    M = np.zeros((nc + 1, nc + 1))
+    rhs = np.zeros(nc + 1)
+    for r, (sk, ak) in enumerate(classes):
+        i = first[(sk, ak)]
+        for c, (sm, bm) in enumerate(classes):
+            j = first[(sm, bm)]
+            M[r, c] = _layer_lattice_potential(ex[:2, i] - ex[:2, j], ex[2, i] - ex[2, j], cx, cy, w.eta)
+        M[r, nc] = -1.0                             # minus the common offset psibar
+        rhs[r] = dv * 0.5 * w.elec_side[i]
+    M[nc, :nc] = 1.0                                # neutral
+    sol = np.linalg.solve(M, rhs)
+    for c, key in enumerate(classes):
+        members = [k for k in range(n1) if (sheet[k], basis[k]) == key]
+        assert np.abs(q[members] - sol[c]).max() < 1e-10 * np.abs(sol[:nc]).max()
+
+
+# --------------------------------------------------------------------------
+# slab geometry with the charged-sheet (dipole) correction
+# --------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=None)
+def slab_built(factor=3.0, empty=False):
+    from workloads import make_workload
+    w = make_workload("tiny", "slab", slab_factor=factor)
+    if empty:
+        w = w.empty()
+    A, S = cpm.build(w)
+    return w, A, S
+
+
+def test_slab_empty_capacitor_closed_form():
+    """The corrected slab is an isolated capacitor in z, like each sub-cell of
+    the doubled cell: Q+ = eps0 A dpsi / (g - s_eff), every atom of a layer equal."""
+    w, A, S = slab_built(3.0, True)
+    seff = honeycomb_seff(w.box[0] / 6, w.box[1] / 3, w.eta)
+    g = 4.34
+    q = S @ (2.0 * cpm.drive_vector(w))
+    up = w.elec_side > 0
+    qdc = EPS0 * w.box[0] * w.box[1] * 2.0 / (g - seff)
+    assert abs(q[up].sum() - qdc) < 1e-10 * qdc
+    assert abs(q[~up].sum() + qdc) < 1e-10 * qdc
+    assert np.ptp(q[up]) < 1e-12 * qdc
+
+
+def test_slab_result_independent_of_the_empty_space():
+    """With the correction the charges, forces and energies do not depend on
+    how much empty space is added (without it they would, through the
+    spurious dipole interaction of the copies)."""
+    res = []
+    for factor in (3.0, 4.5):
+        w, A, S = slab_built(factor)
+        res.append(cpm.step(w, A, S, cpm.Electrostatics(w, "exact")))
+    r1, r2 = res
+    assert np.abs(r1["q"] - r2["q"]).max() < 1e-10
+    assert np.abs(r1["f"] - r2["f"]).max() < 1e-9 * np.abs(r1["f"]).max()
+    assert abs(r1["u_coul"] - r2["u_coul"]) < 1e-10 * abs(r1["u_coul"])
+    assert abs(r1["e_cp"] - r2["e_cp"]) < 1e-10 * abs(r1["e_cp"])
+    # and the uncorrected sums would not be: the correction's share of q is large
+    w, A, S = slab_built(3.0)
+    es = cpm.Electrostatics(w, "exact")
+    b_raw = es._b(w.site_xyz)
+    A_raw = A - slab.elastance_term(w.elec_xyz, w.box)
+    q_raw = cpm.projected_inverse(A_raw) @ (b_raw + w.dv * cpm.drive_vector(w))
+    assert np.abs(q_raw - r1["q"]).max() > 1e-3 * np.abs(r1["q"]).max()
+
+
+def test_slab_forces_match_energy_derivative():
+    """F_j = -dE_cp/dR_j with E_cp = U_coul - dpsi d.q and the correction in U_coul."""
+    w, A, S = slab_built(3.0)
+    es = cpm.Electrostatics(w, "exact")
+    r = cpm.step(w, A, S, es)
+    h = 1e-5
+    fmax = np.abs(r["f"]).max()
+    for j in (2, 40, 77):
+        for d in range(3):
+            xp = w.site_xyz.copy(); xp[d, j] += h
+            xm = w.site_xyz.copy(); xm[d, j] -= h
+            ep = cpm.step(w, A, S, es, site_xyz=xp, with_forces=False)["e_cp"]
+            em = cpm.step(w, A, S, es, site_xyz=xm, with_forces=False)["e_cp"]
+            assert abs(-(ep - em) / (2 * h) - r["f"][d, j]) < 1e-7 * fmax
+
+
+def test_slab_agrees_with_doubled_cell():
+    """Filled cell: the slab and the first sub-cell of the doubled cell are both
+    isolated capacitors in z, so their net electrode charges agree to rounding;
+    atom by atom they differ only by the small in-plane coupling of the
+    doubled cell's two electrolytes through the electrodes (~1e-4)."""
+    w, A, S = slab_built(3.0)
+    wd, Ad, Sd = built("tiny", "dc")
+    n = w.n_elec
+    up = w.elec_side > 0
+    for dv in (0.0, 2.0):
+        qs = cpm.step(w, A, S, cpm.Electrostatics(w, "exact"), dv=dv, with_forces=False)["q"]
+        qd = cpm.step(wd, Ad, Sd, cpm.Electrostatics(wd, "exact"), dv=dv, with_forces=False)["q"][:n]
+        for m in (up, ~up):
+            assert abs(qs[m].sum() / qd[m].sum() - 1.0) < 1e-10
+        assert np.abs(qs - qd).max() < 2e-4 * np.abs(qs).max()

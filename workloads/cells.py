@@ -46,7 +46,7 @@ class Workload:
     """
 
     name: str
-    geometry: str                  # "ff" (finite field) or "dc" (doubled cell)
+    geometry: str                  # "ff" (finite field), "dc" (doubled cell) or "slab"
     box: np.ndarray                # (3,) nm
     eta: float                     # Gaussian width of electrode charges, 1/nm
     # run-time splitting of the electrolyte sums
@@ -63,6 +63,7 @@ class Workload:
     elec_xyz: np.ndarray
     elec_side: np.ndarray          # int8, +1 positive / -1 negative electrode
     elec_sub: Optional[np.ndarray]  # uint8, 1 = first sub-cell (dc only)
+    elec_layer: Optional[np.ndarray]  # int8 graphene layer of each atom, 0 = nearest the electrolyte
     site_xyz: np.ndarray
     site_q: np.ndarray
     site_zmin: np.ndarray          # per-site z window used by the random walk
@@ -88,15 +89,36 @@ class Workload:
                                    site_zmin=np.zeros(0), site_zmax=np.zeros(0))
 
 
-def graphene_layer(ncell_x: int, ncell_y: int, lx: float, ly: float, z: float) -> np.ndarray:
-    """Honeycomb layer of 4 * ncell_x * ncell_y atoms filling lx x ly at height z."""
+INTERLAYER = 0.335     # nm, graphite interlayer spacing
+
+
+def graphene_layer(ncell_x: int, ncell_y: int, lx: float, ly: float, z: float,
+                   shifted: bool = False) -> np.ndarray:
+    """Honeycomb layer of 4 * ncell_x * ncell_y atoms filling lx x ly at height z.
+
+    shifted=True gives the B layer of A-B stacking: the lattice moved by one
+    bond along the armchair direction (a third of the rectangular cell in y),
+    which puts half of its atoms over hexagon centres of the A layer."""
     cx, cy = lx / ncell_x, ly / ncell_y
+    dy = 1.0 / 3.0 if shifted else 0.0
     pts = []
     for iy in range(ncell_y):
         for ix in range(ncell_x):
             for fx, fy in _HONEYCOMB_FRAC:
-                pts.append(((ix + fx) * cx, (iy + fy) * cy, z))
+                pts.append(((ix + fx) * cx, ((iy + fy + dy) * cy) % ly, z))
     return np.array(pts, dtype=np.float64).T.copy()
+
+
+def electrode(ncell_x, ncell_y, lx, ly, z_proximal, outward, layers):
+    """An electrode of `layers` graphene sheets in A-B-A stacking: the first at
+    z_proximal (facing the electrolyte), the others INTERLAYER apart going
+    `outward` (-1: down, +1: up).  Returns (xyz, layer index per atom)."""
+    xyz, lay = [], []
+    for k in range(layers):
+        xyz.append(graphene_layer(ncell_x, ncell_y, lx, ly, z_proximal + outward * k * INTERLAYER,
+                                  shifted=(k % 2 == 1)))
+        lay.append(np.full(xyz[-1].shape[1], k, np.int8))
+    return np.concatenate(xyz, axis=1), np.concatenate(lay)
 
 
 def _random_unit(rng: np.random.Generator) -> np.ndarray:
@@ -175,6 +197,7 @@ def _double(w: Workload, z_lo: float, z_hi: float) -> Workload:
         elec_xyz=np.concatenate([w.elec_xyz, e2], axis=1),
         elec_side=np.concatenate([w.elec_side, -w.elec_side]).astype(np.int8),
         elec_sub=np.concatenate([np.ones(w.n_elec, np.uint8), np.zeros(w.n_elec, np.uint8)]),
+        elec_layer=np.concatenate([w.elec_layer, w.elec_layer]),
         site_xyz=np.concatenate([w.site_xyz, s2], axis=1),
         site_q=np.concatenate([w.site_q, w.site_q]),
         site_zmin=np.concatenate([w.site_zmin, zmin2]),
@@ -182,17 +205,46 @@ def _double(w: Workload, z_lo: float, z_hi: float) -> Workload:
     )
 
 
-def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None) -> Workload:
-    """Build one of the named workloads ('tiny', 'paper', 'large') in 'ff' or 'dc'."""
-    if geometry not in ("ff", "dc"):
-        raise ValueError("geometry must be 'ff' or 'dc'")
+SLAB_FACTOR = 3.0   # periodic length over the cell's length in slab geometry
+
+
+def _slab(w: Workload, factor: float) -> Workload:
+    """Slab geometry: the same cell inside a z-period `factor` times as long,
+    the rest empty, and the mesh lengthened in z in proportion (same spacing)."""
+    box = w.box.copy()
+    box[2] = factor * w.box[2]
+    kz = int(round(factor * w.mesh[2]))
+    return dataclasses.replace(w, geometry="slab", box=box, mesh=(w.mesh[0], w.mesh[1], kz))
+
+
+def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None, layers: int = 1,
+                  slab_factor: float = SLAB_FACTOR) -> Workload:
+    """Build one of the named workloads ('tiny', 'paper', 'large') in 'ff', 'dc' or 'slab'.
+
+    Slab geometry (the non-periodic setting the paper compares against) keeps
+    the finite-field cell's contents and puts them in a z-period slab_factor
+    times as long (vacuum above the upper electrode), as the slab correction
+    needs.
+
+    layers = 1 charges only the graphene sheet of each electrode nearest the
+    electrolyte (the production setting of the paper); layers = 3 charges all
+    three sheets (A-B-A stacking, 0.335 nm apart), as in the paper's re-runs
+    of snapshots.  The electrolyte is the same in both."""
+    if geometry not in ("ff", "dc", "slab"):
+        raise ValueError("geometry must be 'ff', 'dc' or 'slab'")
+    if layers not in (1, 3):
+        raise ValueError("layers must be 1 or 3")
     eta = 19.79
     if name == "tiny":
         a = 0.246
         lx, ly, lz = 6 * a, 1.27824, 6.0
-        z_lo, z_hi = 0.0, 4.34
-        lo = graphene_layer(6, 3, lx, ly, z_lo)
-        hi = graphene_layer(6, 3, lx, ly, z_hi)
+        # with three sheets the whole system moves up by two spacings, so the
+        # cell boundary z = 0 stays behind the lower electrode (a finite-field
+        # electrode must not cross it)
+        z_lo = 2 * INTERLAYER if layers == 3 else 0.0
+        z_hi = z_lo + 4.34
+        lo, lo_l = electrode(6, 3, lx, ly, z_lo, -1, layers)
+        hi, hi_l = electrode(6, 3, lx, ly, z_hi, +1, layers)
         seed = 1 if seed is None else seed
         rng = np.random.default_rng(seed)
         sxyz, sq = random_electrolyte(rng, 50, lx, ly, z_lo + MIN_SEP, z_hi - MIN_SEP, 1)
@@ -203,8 +255,8 @@ def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None) -
         lx = ly = 3.4 * reps
         lz = 12.625
         z_lo, z_hi = 1.3125, 11.3125
-        lo = graphene_layer(11 * reps, 10 * reps, lx, ly, z_lo)
-        hi = graphene_layer(11 * reps, 10 * reps, lx, ly, z_hi)
+        lo, lo_l = electrode(11 * reps, 10 * reps, lx, ly, z_lo, -1, layers)
+        hi, hi_l = electrode(11 * reps, 10 * reps, lx, ly, z_hi, +1, layers)
         seed = (2 if name == "paper" else 3) if seed is None else seed
         rng = np.random.default_rng(seed)
         sxyz, sq = random_electrolyte(rng, 320 * reps * reps, lx, ly,
@@ -222,11 +274,13 @@ def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None) -
         name=name, geometry="ff", box=np.array([lx, ly, lz]), eta=eta,
         elec_xyz=np.concatenate([lo, hi], axis=1),
         elec_side=np.concatenate([-np.ones(n_half, np.int8), np.ones(n_half, np.int8)]),
-        elec_sub=None, site_xyz=sxyz, site_q=sq,
+        elec_sub=None, elec_layer=np.concatenate([lo_l, hi_l]), site_xyz=sxyz, site_q=sq,
         site_zmin=np.full(sq.shape, z_lo + MIN_SEP), site_zmax=np.full(sq.shape, z_hi - MIN_SEP),
         seed=seed, **params)
     if geometry == "dc":
         w = _double(w, z_lo, z_hi)
+    elif geometry == "slab":
+        w = _slab(w, slab_factor)
     return w
 
 
