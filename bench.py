@@ -393,6 +393,67 @@ def batched_form(torch, n_frames=4096, n_dv=32, reps=3):
                 mixed_per_kernel=out["mixed_kernels"])
 
 
+def geometry_form(torch, ff_steps_per_s, dc_steps_per_s, steps=400, warmup=40):
+    """The paper's cost comparison on one GPU: the slab geometry (z period 3x
+    the cell, charged-sheet correction, mesh 18 x 18 x 192 at the finite-field
+    spacing) against the fully periodic finite field and doubled cell.  The
+    doubled cell holds two independent cells, so its steps count twice per
+    simulated cell (as the paper counts its nanoseconds)."""
+    from workloads import make_workload, random_walk
+    w = make_workload("paper", "slab")
+    traj = random_walk(w, 200)
+    r = gpu_steps(torch, w, traj, steps, warmup)
+    slab = 1000.0 * steps / r["ms_total"]
+    return dict(workload="paper-shaped cell in slab geometry: 3.4x3.4x37.875 nm period (cell 12.625 nm + "
+                         "empty space), N_e=880, N_l=1280, PPPM 18x18x192 order 5, dipole correction",
+                slab_steps_per_s=slab, finite_field_steps_per_s=ff_steps_per_s,
+                doubled_cell_cell_steps_per_s=2.0 * dc_steps_per_s,
+                finite_field_over_slab=ff_steps_per_s / slab, doubled_cell_over_slab=2.0 * dc_steps_per_s / slab)
+
+
+def three_layer_form(torch, n_frames=4096, n_dv=32, reps=3):
+    """Re-solving snapshots with all three graphene sheets charged (N_e = 2640,
+    finite field), batched: (frame, dV) pairs per second, and the share of
+    each electrode's net charge on its nearest sheet at the largest dV."""
+    from workloads import make_workload, perturbed_frames
+    w = make_workload("paper", "ff", layers=3)
+    frames = torch.tensor(perturbed_frames(w, n_frames), dtype=torch.float64, device="cuda")
+    dvs = np.linspace(0.0, 4.0, n_dv)
+    ctx, stream = make_ctx(torch, w)
+    q = torch.empty((n_frames, n_dv, w.n_elec), dtype=torch.float64, device="cuda")
+    f = torch.empty((n_frames, n_dv, 3, w.n_site), dtype=torch.float64, device="cuda")
+    e = torch.empty((n_frames, n_dv, 2), dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        ctx.solve_batch(frames, dvs, q, f, e)
+    stream.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        for _ in range(reps):
+            ctx.solve_batch(frames, dvs, q, f, e)
+        b.record(stream)
+    stream.synchronize()
+    ms = a.elapsed_time(b) / reps
+    qh = q[:, -1].cpu().numpy()
+    share = []
+    for side in (-1, 1):
+        m = w.elec_side == side
+        share.append(qh[:, m & (w.elec_layer == 0)].sum(-1) / qh[:, m].sum(-1))
+    share = np.concatenate(share)
+    from paper_2201_12963_amd.binding import BUF_BATCH_CHUNK
+    chunk = int(ctx.get_buffer(BUF_BATCH_CHUNK)[0]) or n_frames
+    kern = per_kernel_roofline(w, kernel_times(torch, ctx, stream, 3, warm=1), chunk, n_dv)
+    ctx.close()
+    del q, f, e
+    torch.cuda.empty_cache()
+    return dict(workload=f"{n_frames} frames x {n_dv} dV of the finite-field paper cell with all three sheets of "
+                         "each electrode charged (N_e=2640, N_l=1280)",
+                fp64_frames_per_s=n_frames * n_dv / (ms * 1e-3), fp64_ms_per_batch=ms, frames_per_launch=chunk,
+                nearest_sheet_share_at_4V={"min": float(share.min()), "mean": float(share.mean())},
+                fp64_per_kernel=kern)
+
+
 def gradient_form(torch, reps=50):
     from workloads import make_workload
     w = make_workload("large", "ff")
@@ -421,7 +482,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--only", choices=("precision", "batched", "gradient"),
+    ap.add_argument("--only", choices=("precision", "batched", "gradient", "three_layer"),
                     help="run only this form and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -434,7 +495,7 @@ def main():
 
     if args.only:
         form = {"precision": lambda t: precision_form(t)[0], "batched": batched_form,
-                "gradient": gradient_form}[args.only]
+                "gradient": gradient_form, "three_layer": three_layer_form}[args.only]
         print(json.dumps({args.only: form(torch)}), flush=True)
         return
 
@@ -477,6 +538,8 @@ def main():
             "precision": prec,
             "batched": batched_form(torch),
             "gradient": gradient_form(torch),
+            "geometries": geometry_form(torch, line["config"]["finite_field_steps_per_s"], line["value"]),
+            "three_layer": three_layer_form(torch),
         }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wd, trajd, parity=precision_state)

@@ -43,8 +43,15 @@ enum {
   CPM_ENONFINITE = -6  /* non-finite input or result */
 };
 
-/* geometry (Sec. II.B of the paper) */
-enum { CPM_FINITE_FIELD = 0, CPM_DOUBLED_CELL = 1 };
+/* geometry (Sec. II.B of the paper).  CPM_SLAB is the mixed-periodicity
+ * setting the paper compares against (Fig. 2b): box[2] is the lengthened
+ * z period, the electrodes and electrolyte occupy at most half of it with the
+ * empty space across z = 0, and the charged-sheet (dipole) correction
+ * k_e 2 pi / V M_z^2, M_z = sum q z over all charges, enters A (k_e 4 pi/V
+ * z z^T), b (-k_e 4 pi/V z sum_j Q_j Z_j), the electrolyte energy and the
+ * site forces (-k_e 4 pi/V Q_j M_z along z); the electrode potentials are
+ * psibar e + dV d with one neutrality constraint. */
+enum { CPM_FINITE_FIELD = 0, CPM_DOUBLED_CELL = 1, CPM_SLAB = 2 };
 /* reciprocal-space method for the electrolyte sums */
 enum { CPM_KSPACE_EWALD = 0, CPM_KSPACE_PPPM = 1 };
 /* arithmetic of the per-step path: FP64 throughout, or FP32 mesh / FFT /
@@ -55,8 +62,8 @@ enum { CPM_FP64 = 0, CPM_MIXED = 1 };
 typedef struct cpm_ctx cpm_ctx;
 
 typedef struct {
-  double box[3];        /* Lx, Ly, Lz of the fully periodic cell (nm); doubled cell: the doubled Lz */
-  int geometry;         /* CPM_FINITE_FIELD or CPM_DOUBLED_CELL */
+  double box[3];        /* Lx, Ly, Lz of the periodic cell (nm); doubled cell: the doubled Lz; slab: the lengthened Lz */
+  int geometry;         /* CPM_FINITE_FIELD, CPM_DOUBLED_CELL or CPM_SLAB */
   int kspace;           /* CPM_KSPACE_EWALD or CPM_KSPACE_PPPM */
   int precision;        /* CPM_FP64 or CPM_MIXED */
   double eta;           /* Gaussian width of electrode charges (Eq. 2), 1/nm */
@@ -86,8 +93,10 @@ enum {
 };
 
 /* Create a context: validates the descriptor (alpha < eta/sqrt2, positive
- * box and cutoffs, mesh factorable, neutral electrolyte, sides +-1,
- * doubled cell needs elec_sub with both sub-cells non-empty), uploads the
+ * box and cutoffs, mesh factorable and its planes within LDS, neutral
+ * electrolyte, sides +-1, doubled cell needs elec_sub with both sub-cells
+ * non-empty, finite-field electrodes may not cross z = 0, slab electrodes
+ * within half of the z period; all before any device call), uploads the
  * electrodes and prepares the per-step tables (k-vectors or influence
  * function, electrode spline weights, FFT twiddles, cell lists).
  * hip_stream may be NULL (the null stream).  *out is NULL on error. */
@@ -98,7 +107,8 @@ int cpm_set_stream(cpm_ctx* ctx, void* hip_stream);
 
 /* Once per electrode geometry (Eq. 3, 8-9, 14-15; "precomputed" in
  * Sec. II.A): builds A in FP64 (Gaussian real-space pairs, k-space as
- * 2 C C^T with C the sqrt(w)-weighted cos/sin factors, self term), inverts
+ * 2 C C^T with C the sqrt(w)-weighted cos/sin factors, self term, and in
+ * slab geometry the dipole correction's k_e 4 pi / V z z^T), inverts
  * it, projects S = O A^-1 (and O1 for the doubled cell) and forms S c.
  * Synchronises the stream.  CPM_ENOTSPD if A is not positive definite. */
 int cpm_build_elastance(cpm_ctx* ctx);
@@ -113,7 +123,8 @@ int cpm_build_elastance(cpm_ctx* ctx);
  *   f_out       device [3][n_site] or NULL  forces on the sites (eV/nm)
  *   energy_out  device [2] or NULL          {U_coul, E_cp} (eV): U_coul =
  *               U_elyt - q.b + 1/2 q.A q; E_cp = U_coul - dV d.q
- *               (+ dV/Lz (z.q + sum Q_j Z_j) for the finite field), whose
+ *               (+ dV/Lz (z.q + sum Q_j Z_j) for the finite field; the slab
+ *               correction is part of U_elyt, b and A), whose
  *               negative position gradient is f_out.
  * With CPM_FLAG_GRAPH, repeated calls with identical pointer arguments and
  * dv replay a HIP graph of the step.  CPM_ESTATE before
@@ -146,6 +157,29 @@ int cpm_solve_batch(cpm_ctx* ctx, int n_frames, const double* site_xyz,
  *   q_out     device [n_elec] or NULL (q* of the forward pass) */
 int cpm_grad(cpm_ctx* ctx, const double* site_xyz, double dv, const double* q_target,
              double* loss_out, double* dl_dxyz, double* dl_ddv, double* q_out);
+
+/* Laterally averaged charge density and electrostatic potential profile
+ * across the cell (Eq. 16; potential-profile subsection and post-analysis
+ * paragraph of the appendix), averaged over frames.  Grid: n_bins bins of
+ * width h = Lz/n_bins, bin k = [k h, (k+1) h), values at the bin centres.
+ * rho: the sites' point charges counted in the bin of their wrapped z, each
+ * electrode atom's charge spread as its Gaussian (Eq. 2) integrated over
+ * the bins (nearest periodic images included), divided by Lx Ly h and by
+ * n_frames.  psi: the second-difference equations
+ * (psi_{k+1} - 2 psi_k + psi_{k-1}) / h^2 = -rho_k / eps0 with, per geometry,
+ * a rise of dv over one period (finite field), continuity (doubled cell) or
+ * zero field at z = 0 (slab), solved exactly; the mean of psi over the bins
+ * centred in [bulk_lo, bulk_hi) is subtracted.
+ *   site_xyz  device [n_frames][3][n_site]
+ *   q         device, frame f's electrode charges at q + f * q_stride
+ *             (q_stride >= n_elec; n_dv * n_elec to read one dV of a batch)
+ *   rho_out   device [n_bins] (e/nm^3); psi_out device [n_bins] (V)
+ * CPM_EINVAL for n_bins outside 2..2048, an empty bulk window or more than
+ * 2048 distinct electrode heights.  The scratch (n_part x (n_bins + heights)
+ * doubles, n_part <= 128) is allocated by the context and grows on demand
+ * (that call synchronises the stream). */
+int cpm_profile(cpm_ctx* ctx, int n_frames, const double* site_xyz, const double* q, long long q_stride,
+                double dv, int n_bins, double bulk_lo, double bulk_hi, double* rho_out, double* psi_out);
 
 /* Copies of internal matrices for tests and checkpoints (synchronises):
  * which = 0: A, 1: S (projected inverse), 2: S c (n_elec values).

@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpm.so")
 
 CPM_OK, CPM_EINVAL, CPM_ESTATE, CPM_ENOTSPD, CPM_EDEVICE, CPM_ENOMEM, CPM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
-FINITE_FIELD, DOUBLED_CELL = 0, 1
+FINITE_FIELD, DOUBLED_CELL, SLAB = 0, 1, 2
+GEOMETRY = {"ff": FINITE_FIELD, "dc": DOUBLED_CELL, "slab": SLAB}
 KSPACE_EWALD, KSPACE_PPPM = 0, 1
 FP64, MIXED = 0, 1
 FLAG_GRAPH = 1
@@ -33,7 +34,7 @@ _STATUS_NAMES = {0: "CPM_OK", -1: "CPM_EINVAL", -2: "CPM_ESTATE", -3: "CPM_ENOTS
 
 EXPORTED = ("cpm_create", "cpm_set_stream", "cpm_build_elastance", "cpm_solve", "cpm_solve_batch",
             "cpm_grad", "cpm_get_matrix", "cpm_set_matrix", "cpm_get_buffer", "cpm_sync_status",
-            "cpm_last_error", "cpm_destroy", "cpm_replay_kernel")
+            "cpm_last_error", "cpm_destroy", "cpm_replay_kernel", "cpm_profile")
 
 
 class CpmError(RuntimeError):
@@ -89,6 +90,9 @@ def load_library():
     lib.cpm_set_matrix.restype = ip
     lib.cpm_get_buffer.argtypes = [vp, ip, vp]
     lib.cpm_get_buffer.restype = ctypes.c_longlong
+    lib.cpm_profile.argtypes = [vp, ip, vp, vp, ctypes.c_longlong, ctypes.c_double, ip, ctypes.c_double,
+                                ctypes.c_double, vp, vp]
+    lib.cpm_profile.restype = ip
     lib.cpm_replay_kernel.argtypes = [vp, ip, ip]
     lib.cpm_replay_kernel.restype = ip
     lib.cpm_sync_status.argtypes = [vp]
@@ -156,7 +160,7 @@ class Context:
     @classmethod
     def from_workload(cls, w, precision=FP64, stream=None, graph=False):
         """Context for a workloads.Workload."""
-        return cls(box=w.box, geometry=DOUBLED_CELL if w.geometry == "dc" else FINITE_FIELD,
+        return cls(box=w.box, geometry=GEOMETRY[w.geometry],
                    kspace=KSPACE_PPPM if w.kspace == "pppm" else KSPACE_EWALD, precision=precision,
                    eta=w.eta, alpha=w.alpha, rcut=w.rcut, kcut=w.kcut, mesh=w.mesh, order=w.order,
                    alpha_build=w.alpha_exact, rcut_build=w.rcut_exact, kcut_build=w.kcut_exact,
@@ -226,6 +230,27 @@ class Context:
         self._call(self._lib.cpm_grad, _ptr(site_xyz), float(dv), _ptr(q_target), _ptr(loss), _ptr(dldx),
                    _ptr(dldv), _ptr(q))
         return loss, dldx, dldv, q
+
+    def profile(self, site_xyz: torch.Tensor, q: torch.Tensor, dv: float, n_bins: int, bulk, rho_out=None,
+                psi_out=None):
+        """Frame-averaged charge density and potential profile along z.
+
+        site_xyz [F][3][n_site]; q [F][..., n_elec] (the last axis the atoms;
+        a batch's q[:, v] view for one dV is accepted as it is); bulk = (z_lo,
+        z_hi) window whose mean potential is zero.  Returns (rho, psi)."""
+        n_frames = site_xyz.shape[0]
+        if q.shape[0] != n_frames or q.shape[-1] != self.n_elec or q.stride(-1) != 1:
+            raise ValueError("q must be [n_frames][..., n_elec] with contiguous atoms")
+        if q.dtype != torch.float64 or not q.is_cuda:
+            raise ValueError("q must be a float64 GPU tensor")
+        dev = site_xyz.device
+        if rho_out is None:
+            rho_out = torch.empty(n_bins, dtype=torch.float64, device=dev)
+        if psi_out is None:
+            psi_out = torch.empty(n_bins, dtype=torch.float64, device=dev)
+        self._call(self._lib.cpm_profile, n_frames, _ptr(site_xyz), ctypes.c_void_p(q.data_ptr()), q.stride(0),
+                   float(dv), int(n_bins), float(bulk[0]), float(bulk[1]), _ptr(rho_out), _ptr(psi_out))
+        return rho_out, psi_out
 
     def get_matrix(self, which: int) -> np.ndarray:
         n = self.n_elec

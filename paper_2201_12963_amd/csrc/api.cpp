@@ -92,6 +92,16 @@ struct cpm_ctx {
   double* d_phir = nullptr;
   float* d_phirf = nullptr;
   int n_ek = 0;
+  // slab geometry: k_e 4 pi / V, z.(S c) and the per-frame field of the dipole correction
+  double slab_kappa = 0.0, slab_zSc = 0.0;
+  double* d_slabfield = nullptr;
+
+  // ---- potential profile: distinct electrode heights and the histogram scratch
+  int n_heights = 0;
+  int* d_height_of = nullptr;
+  double* d_heights = nullptr;
+  double* d_prof = nullptr;
+  size_t cap_prof = 0;
 
   // ---- PPPM
   MeshInfo mi{};
@@ -293,6 +303,18 @@ void free_graphs(cpm_ctx* c) {
   c->graphs.clear();
 }
 
+// slab geometry's dipole-correction terms (kappa == 0: none)
+SlabTerms slab_terms(const cpm_ctx* c) {
+  SlabTerms sl{};
+  if (c->geometry == CPM_SLAB) {
+    sl.kappa = c->slab_kappa;
+    sl.ze = c->d_ze;
+    sl.zdip = c->d_zdip;
+    sl.n_elec = c->n_elec;
+  }
+  return sl;
+}
+
 // --------------------------------------------------------------- buffers
 
 int alloc_frames(cpm_ctx* c, int nf) {
@@ -329,6 +351,7 @@ int alloc_frames(cpm_ctx* c, int nf) {
   TRY(dalloc(c, &c->d_fcomp, (size_t)nf * 6 * ns));
   TRY(dalloc(c, &c->d_felec, (size_t)nf * 6 * ns));
   TRY(dalloc(c, &c->d_energy_tmp, (size_t)nf * 2));
+  TRY(dalloc(c, &c->d_slabfield, (size_t)nf));
   if (c->kspace == CPM_KSPACE_PPPM) {
     const size_t M = c->mi.M;
     c->n_ek = c->za_pot.n_blocks;
@@ -475,14 +498,15 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
     });
     rec(c, CPM_KERNEL_GATHER_B, s, [=](hipStream_t s) {
-      launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b);
+      launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b,
+                           slab_terms(c));
     });
   } else {
     rec(c, CPM_KERNEL_BIN, s, [=](hipStream_t s) { launch_bin_sites(s, nf, ba); });
     rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     SiteSet<double> sd = Bufs<double>::sites(c);
     launch_ewald_sf(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok, c->d_ek);
-    launch_ewald_phi(s, nf, c->nk, c->n_elec, c->d_ew, c->d_eph, c->d_rhok, c->d_phir, c->d_b);
+    launch_ewald_phi(s, nf, c->nk, c->n_elec, c->d_ew, c->d_eph, c->d_rhok, c->d_phir, c->d_b, slab_terms(c));
   }
   return CPM_OK;
 }
@@ -508,6 +532,11 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
   fa.qb_s = fa.qb ? c->d_Sc_s : nullptr;     // the only second set is S c
   fa.mi = c->mi;
   fa.f_pair = c->d_fpair;
+  // slab: the uniform field of the dipole correction for the charges qa,
+  // made by one more workgroup per frame of the electrode spread (PPPM) or
+  // by a launch of its own (explicit Ewald)
+  const SlabTerms sl = slab_terms(c);
+  fa.field_frame = c->geometry == CPM_SLAB ? c->d_slabfield : nullptr;
   PairArgs<T> pa{};
   // one frame: a wavefront per site (short chains, all in flight at once);
   // many frames: cell tiles
@@ -536,7 +565,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     // that work to a handful of workgroups
     rec(c, CPM_KERNEL_SPREAD_ELEC, s, [=](hipStream_t s) {
       launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
-                              B::rho_e(c), c->mi.M);
+                              B::rho_e(c), c->mi.M, sl, fa.field_frame ? c->d_slabfield : nullptr);
     });
     rec(c, CPM_KERNEL_FFT_XY_FWD_E, s, [=](hipStream_t s) {
       launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
@@ -564,6 +593,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     fa.Esite = nullptr;
   } else {
     rec(c, CPM_KERNEL_SITE_PAIRS, s, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
+    if (fa.field_frame) launch_slab_field(s, nf, sl, qa, qa_stride, c->d_slabfield);
     SiteSet<double> sd = Bufs<double>::sites(c);
     launch_ewald_rho_all(s, nf, c->nk, c->n_elec, c->d_eph, qa, qa_stride, c->d_rhok, c->d_rhok_all);
     launch_ewald_field(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok_all, c->d_Esite);
@@ -589,6 +619,7 @@ EnergyArgs energy_args(cpm_ctx* c, int n_dv, const double* dv, double dv_single,
   ea.Q0 = c->d_Q0; ea.b = c->d_b; ea.Sc = c->d_Sc; ea.c = c->d_c; ea.d = c->d_d; ea.ze = c->d_ze;
   ea.u_site = c->d_usite; ea.ek = c->d_ek; ea.zdip = c->d_zdip; ea.self_energy = c->self_energy;
   ea.ff = c->geometry == CPM_FINITE_FIELD; ea.Lz = c->box[2];
+  ea.slab_kappa = c->geometry == CPM_SLAB ? c->slab_kappa : 0.0;
   ea.n_dv = n_dv; ea.dv = dv; ea.dv_single = dv_single; ea.out = out;
   return ea;
 }
@@ -694,7 +725,10 @@ int enqueue_batch(cpm_ctx* c, int nf, const double* xyz, int n_dv, double* q_out
     ForceArgs<T> fa{};
     fa.out_scale = 1.0;
     fa.field = 0.0;
-    fa.fieldb = (c->geometry == CPM_FINITE_FIELD) ? -1.0 / c->box[2] : 0.0;
+    // the applied field per unit dV (finite field), or the dipole
+    // correction's field from the charges dV S c (slab)
+    fa.fieldb = c->geometry == CPM_FINITE_FIELD ? -1.0 / c->box[2]
+              : c->geometry == CPM_SLAB ? -c->slab_kappa * c->slab_zSc : 0.0;
     fa.qb = c->d_Sc;
     if (c->kspace == CPM_KSPACE_PPPM) fa.Eb = std::is_same<T, float>::value ? (const T*)c->d_EScf : (const T*)c->d_ESc;
     // forces at dV = 0 and per unit dV, then the sweep in a streaming pass
@@ -762,6 +796,17 @@ int tune_batch_chunk(cpm_ctx* c, int n_frames, Run run) {
   return rc;
 }
 
+// z.(S c) for the slab's batched dV sweep (host copy of S c; the stream is idle)
+int slab_zsc(cpm_ctx* c) {
+  if (c->geometry != CPM_SLAB) return CPM_OK;
+  std::vector<double> sc(c->n_elec);
+  HIP_TRY(c, hipMemcpy(sc.data(), c->d_Sc, sc.size() * sizeof(double), hipMemcpyDeviceToHost));
+  double t = 0.0;
+  for (int i = 0; i < c->n_elec; ++i) t += wrap_host(c->hz[i], c->box[2]) * sc[i];
+  c->slab_zSc = t;
+  return CPM_OK;
+}
+
 int check_launch(cpm_ctx* c) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, CPM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -779,7 +824,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   if (!d || !out) return fail(nullptr, CPM_EINVAL, "null descriptor or output pointer");
   for (int k = 0; k < 3; ++k)
     if (!(d->box[k] > 0.0) || !std::isfinite(d->box[k])) return fail(nullptr, CPM_EINVAL, "box lengths must be positive");
-  if (d->geometry != CPM_FINITE_FIELD && d->geometry != CPM_DOUBLED_CELL)
+  if (d->geometry != CPM_FINITE_FIELD && d->geometry != CPM_DOUBLED_CELL && d->geometry != CPM_SLAB)
     return fail(nullptr, CPM_EINVAL, "unknown geometry %d", d->geometry);
   if (d->kspace != CPM_KSPACE_EWALD && d->kspace != CPM_KSPACE_PPPM)
     return fail(nullptr, CPM_EINVAL, "unknown kspace %d", d->kspace);
@@ -860,6 +905,21 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
                                          "(place the boundary behind the electrodes)");
     }
   }
+  if (d->geometry == CPM_SLAB) {
+    // the dipole correction needs the electrodes (and the electrolyte between
+    // them) inside one period with empty space across z = 0: the electrodes'
+    // wrapped heights may span at most half the period
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < d->n_elec; ++i) {
+      const double z = d->elec_xyz[2 * d->n_elec + i];
+      const double zw = z - d->box[2] * std::floor(z / d->box[2]);
+      lo = std::min(lo, zw);
+      hi = std::max(hi, zw);
+    }
+    if (hi - lo > 0.5 * d->box[2])
+      return fail(nullptr, CPM_EINVAL, "slab: the electrodes must lie within half of the z period, with the empty "
+                                       "space across z = 0");
+  }
   if (d->geometry == CPM_DOUBLED_CELL && (n1 == 0 || n1 == d->n_elec))
     return fail(nullptr, CPM_EINVAL, "doubled cell needs atoms in both sub-cells");
 
@@ -907,6 +967,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     fail(c, CPM_EINVAL, "%d sites in %d cells exceed the single-workgroup binning limit", ns, cl.n_cells);
     return bad(CPM_EINVAL);
   }
+  c->slab_kappa = KE * 4.0 * M_PI / (c->box[0] * c->box[1] * c->box[2]);
   double q2 = 0.0;
   for (double q : c->hq) q2 += q * q;
   c->self_energy = KE * c->alpha / std::sqrt(M_PI) * q2;
@@ -916,7 +977,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   for (int i = 0; i < ne; ++i) {
     dd[i] = 0.5 * c->side[i];
     ze[i] = wrap_host(c->hz[i], c->box[2]);
-    cc[i] = (c->geometry == CPM_DOUBLED_CELL) ? dd[i] : dd[i] - ze[i] / c->box[2];
+    cc[i] = (c->geometry == CPM_FINITE_FIELD) ? dd[i] - ze[i] / c->box[2] : dd[i];
     if (c->geometry == CPM_DOUBLED_CELL) e1[i] = c->sub[i] ? 1.0 : 0.0;
   }
   std::vector<int> ecell(ne), eorder(ne);
@@ -959,6 +1020,18 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       (r = upload(c, &c->d_c, cc)) || (r = upload(c, &c->d_d, dd)) || (r = upload(c, &c->d_ze, ze)) ||
       (r = upload(c, &c->d_e1, e1)) || (r = upload(c, &c->d_site_q, c->hq)))
     return bad(r);
+  {
+    // distinct wrapped electrode heights (the potential profile adds each
+    // height's Gaussian once with the summed charge of its atoms)
+    std::vector<double> hs;
+    std::vector<int> hof(ne);
+    for (int i = 0; i < ne; ++i) hs.push_back(ze[i]);
+    std::sort(hs.begin(), hs.end());
+    hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
+    for (int i = 0; i < ne; ++i) hof[i] = (int)(std::lower_bound(hs.begin(), hs.end(), ze[i]) - hs.begin());
+    c->n_heights = (int)hs.size();
+    if ((r = upload(c, &c->d_height_of, hof)) || (r = upload(c, &c->d_heights, hs))) return bad(r);
+  }
   // electrode atoms in reach of every cell: the stencil groups' ranges of
   // the sorted atoms, empty ones dropped and adjacent ones joined
   std::vector<int> rn(cl.n_cells, 0), rlo((size_t)cl.n_cells * STENCIL_MAX, 0), rhi((size_t)cl.n_cells * STENCIL_MAX, 0);
@@ -1154,6 +1227,14 @@ int cpm_build_elastance(cpm_ctx* c) {
     launch_gemm_nt(s, n, n, 2 * nkc, 1.0, d_C, 2 * nkc, d_C, 2 * nkc, 1.0, c->d_A, n);
   }
   launch_symmetrize(s, n, c->d_A);
+  if (c->geometry == CPM_SLAB) {
+    // the dipole correction's electrode block: A += kappa z z^T (a rank-one
+    // update S -= u u^T / s with u = z and s = -1/kappa)
+    const double inv = -1.0 / c->slab_kappa;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(c->d_scalar, &inv, sizeof(double), hipMemcpyHostToDevice));
+    launch_rank1(s, n, c->d_A, c->d_ze, c->d_scalar);
+  }
   // inverse (in d_S), projections
   HIP_TRY(c, hipMemcpyAsync(c->d_S, c->d_A, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, s));
   double *dinv, *pc, *rx, *u;
@@ -1180,6 +1261,7 @@ int cpm_build_elastance(cpm_ctx* c) {
   if (c->precision == CPM_MIXED) launch_split_matrix(s, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
   TRY(check_launch(c));
   HIP_TRY(c, hipStreamSynchronize(s));
+  TRY(slab_zsc(c));
   // the chunk buffers are released now (they are large)
   for (void* p : {(void*)d_kv, (void*)d_sk, (void*)d_C, (void*)dinv, (void*)pc, (void*)rx, (void*)u}) {
     hipFree(p);
@@ -1199,6 +1281,7 @@ int cpm_set_matrix(cpm_ctx* c, const double* host_S) {
   launch_permute(c->stream, 1, n, c->d_epos, c->d_Sc, c->d_Sc_s);
   if (c->precision == CPM_MIXED) launch_split_matrix(c->stream, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  TRY(slab_zsc(c));
   c->built = true;
   c->esc_ready = false;
   free_graphs(c);
@@ -1318,6 +1401,56 @@ int cpm_grad(cpm_ctx* c, const double* xyz, double dv, const double* q_target, d
   int r = c->precision == CPM_MIXED ? enqueue_grad<float>(c, xyz, dv, q_target, loss_out, dl_dxyz, dl_ddv, q_out)
                                     : enqueue_grad<double>(c, xyz, dv, q_target, loss_out, dl_dxyz, dl_ddv, q_out);
   if (r) return r;
+  return check_launch(c);
+}
+
+namespace {
+
+// arguments of a profile call, checked; part is left for the caller to set
+int profile_args(cpm_ctx* c, int n_frames, const double* xyz, const double* q, long long q_stride, double dv,
+                 int n_bins, double bulk_lo, double bulk_hi, double* rho_out, double* psi_out, ProfileArgs& p) {
+  if (n_frames < 1 || !xyz || !q || !rho_out || !psi_out) return fail(c, CPM_EINVAL, "bad profile arguments");
+  if (n_bins < 2 || n_bins > PROFILE_MAX_BINS) return fail(c, CPM_EINVAL, "n_bins must be 2..%d", PROFILE_MAX_BINS);
+  if (q_stride < c->n_elec) return fail(c, CPM_EINVAL, "q_stride must be at least n_elec");
+  if (!std::isfinite(dv) || !std::isfinite(bulk_lo) || !std::isfinite(bulk_hi))
+    return fail(c, CPM_ENONFINITE, "non-finite profile argument");
+  if (c->n_heights > PROFILE_MAX_HEIGHTS)
+    return fail(c, CPM_EINVAL, "more than %d distinct electrode heights", PROFILE_MAX_HEIGHTS);
+  const double h = c->box[2] / n_bins;
+  int in_bulk = 0;
+  for (int k = 0; k < n_bins; ++k) in_bulk += ((k + 0.5) * h >= bulk_lo && (k + 0.5) * h < bulk_hi);
+  if (in_bulk == 0) return fail(c, CPM_EINVAL, "the bulk window holds no bin centre");
+  p = ProfileArgs{};
+  p.n_frames = n_frames; p.n_site = c->n_site; p.n_elec = c->n_elec; p.n_bins = n_bins;
+  p.n_heights = c->n_heights;
+  const long long work = (long long)n_frames * std::max(c->n_site, c->n_elec);
+  p.n_part = (int)std::max<long long>(1, std::min<long long>(PROFILE_MAX_PARTS, (work + 8191) / 8192));
+  p.slab = c->geometry == CPM_SLAB;
+  p.xyz = xyz; p.site_q = c->d_site_q; p.q = q; p.q_stride = (size_t)q_stride;
+  p.height_of = c->d_height_of; p.heights = c->d_heights;
+  p.Lz = c->box[2]; p.inv_Lz = 1.0 / c->box[2]; p.inv_h = n_bins / c->box[2];
+  p.area = c->box[0] * c->box[1]; p.eta = c->eta;
+  p.jump = c->geometry == CPM_FINITE_FIELD ? dv : 0.0;
+  p.bulk_lo = bulk_lo; p.bulk_hi = bulk_hi;
+  p.rho_out = rho_out; p.psi_out = psi_out;
+  return CPM_OK;
+}
+
+}  // namespace
+
+int cpm_profile(cpm_ctx* c, int n_frames, const double* site_xyz, const double* q, long long q_stride, double dv,
+                int n_bins, double bulk_lo, double bulk_hi, double* rho_out, double* psi_out) {
+  if (!c) return CPM_EINVAL;
+  ProfileArgs p;
+  TRY(profile_args(c, n_frames, site_xyz, q, q_stride, dv, n_bins, bulk_lo, bulk_hi, rho_out, psi_out, p));
+  const size_t need = (size_t)p.n_part * (p.n_bins + p.n_heights);
+  if (need > c->cap_prof) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    TRY(dalloc(c, &c->d_prof, need));
+    c->cap_prof = need;
+  }
+  p.part = c->d_prof;
+  launch_profile(c->stream, p);
   return check_launch(c);
 }
 

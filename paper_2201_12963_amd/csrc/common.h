@@ -9,6 +9,7 @@
 namespace cpm {
 
 constexpr double KE = 1.43996454784;   // eV nm / e^2
+constexpr double EPS0 = 1.0 / (4.0 * M_PI * KE);   // e / (V nm)
 constexpr int WAVE = 64;
 constexpr int MAX_FFT_FACTORS = 12;
 constexpr int MAX_ORDER = 7;
@@ -199,6 +200,10 @@ struct ForceArgs {
   double out_scale;          // multiplies the Coulomb force (e.g. -1 for a gradient)
   double field;              // -dV/Lz for the finite field (0 otherwise), added along z
   double fieldb;             // same for the second set (per unit dV)
+  // slab geometry: the uniform Coulomb field of the dipole correction,
+  // -k_e 4 pi / V (sum_j Q_j Z_j + z.qa) per frame (V/nm), added along z and
+  // scaled by out_scale like the rest of the Coulomb force; nullptr otherwise
+  const double* field_frame;
   // outputs
   double* f_out; size_t f_frame_stride;   // [frame][n_dv][3][n_site] original order
   // instead of f_out (if non-null): [frame][2][3][n_site] original order,
@@ -289,6 +294,7 @@ struct EnergyArgs {
   const double* zdip;                            // [frame]
   double self_energy;
   int ff; double Lz;
+  double slab_kappa;                             // slab: k_e 4 pi / V (U_elyt += kappa/2 zdip^2), else 0
   int n_dv; const double* dv; double dv_single;
   double* out;                                   // [frame][n_dv][2]
 };
@@ -389,12 +395,46 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
 size_t bin_lds_bytes(int n_site, int n_cells);
 
 // particle-mesh steps (k_pppm.hip)
+// Slab geometry's dipole correction (charged-sheet correction of the
+// z-periodic box): kappa = k_e 4 pi / V, electrode heights ze (wrapped),
+// the electrolyte dipole zdip[frame] = sum_j Q_j Z_j; kappa == 0 means none
+struct SlabTerms {
+  double kappa;
+  const double* ze;
+  const double* zdip;
+  int n_elec;
+};
+
+// b_i -= kappa z_i zdip (the electrolyte-electrode block of the correction)
+__device__ __forceinline__ double slab_b_term(const SlabTerms& sl, int i, int frame) {
+  return sl.kappa != 0.0 ? sl.kappa * sl.ze[i] * sl.zdip[frame] : 0.0;
+}
+
+// One workgroup: field[frame] = -kappa (zdip[frame] + z.q), q of that frame
+__device__ __forceinline__ void slab_field_block(const SlabTerms& sl, const double* q, double* field, int frame) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < sl.n_elec; i += blockDim.x) acc += sl.ze[i] * q[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) t += red[w];
+    field[frame] = -sl.kappa * (sl.zdip[frame] + t);
+  }
+}
+
 template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
-                          const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M);
+                          const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M,
+                          const SlabTerms& sl = SlabTerms{}, double* slab_field = nullptr);
+// the slab field alone (one workgroup per frame), where no spread launch hosts it
+void launch_slab_field(hipStream_t s, int n_frames, const SlabTerms& sl, const double* q, size_t q_stride,
+                       double* field);
 template <typename T>
 void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const int* gidx, const T* gw,
-                       const T* phi, int M, const T* phi_real, double* b);
+                       const T* phi, int M, const T* phi_real, double* b, const SlabTerms& sl = SlabTerms{});
 
 // FFT passes (k_fft.hip)
 template <typename T, typename T2>
@@ -438,7 +478,7 @@ void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, co
 void launch_ewald_sf(hipStream_t s, int n_frames, int nk, const double* kv, const double* ew,
                      const SiteSet<double>& st, double2* rho, double* ek);
 void launch_ewald_phi(hipStream_t s, int n_frames, int nk, int n_elec, const double* ew, const double2* eph,
-                      const double2* rho, const double* phi_real, double* b);
+                      const double2* rho, const double* phi_real, double* b, const SlabTerms& sl = SlabTerms{});
 void launch_ewald_rho_all(hipStream_t s, int n_frames, int nk, int n_elec, const double2* eph, const double* q,
                           size_t q_stride, const double2* rho, double2* out);
 void launch_ewald_field(hipStream_t s, int n_frames, int nk, const double* kv, const double* ew,
@@ -483,5 +523,31 @@ void launch_gemm_bf16x6(hipStream_t s, int M, int N, int K, const unsigned short
                         const unsigned short* B, size_t b_plane, double* D, int ldd);
 void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out,
                  const int* epos = nullptr, double* out_s = nullptr);
+
+// ------------------------------------------- potential profile (k_profile.hip)
+
+constexpr int PROFILE_THREADS = 256;          // histogram workgroups
+constexpr int PROFILE_SOLVE_THREADS = 1024;   // the one solving workgroup (n_bins <= 2048)
+constexpr int PROFILE_MAX_BINS = 2048;
+constexpr int PROFILE_MAX_HEIGHTS = 2048;
+constexpr int PROFILE_MAX_PARTS = 128;
+
+struct ProfileArgs {
+  int n_frames, n_site, n_elec, n_bins, n_heights, n_part;
+  int slab;                 // 1: zero field at z = 0 (slab); 0: the rise over a period is `jump`
+  const double* xyz;        // [frame][3][n_site]
+  const double* site_q;     // [n_site]
+  const double* q;          // electrode charges, frame f at q + f * q_stride
+  size_t q_stride;
+  const int* height_of;     // [n_elec] index of the atom's height
+  const double* heights;    // [n_heights] distinct wrapped electrode heights
+  double Lz, inv_Lz, inv_h, area, eta, jump, bulk_lo, bulk_hi;
+  double* part;             // scratch [n_part][n_bins + n_heights]
+  double* rho_out;          // [n_bins] e / nm^3
+  double* psi_out;          // [n_bins] V
+};
+size_t profile_partial_lds(int n_bins, int n_heights);
+size_t profile_solve_lds(int n_bins, int n_heights);
+void launch_profile(hipStream_t s, const ProfileArgs& p);
 
 }  // namespace cpm

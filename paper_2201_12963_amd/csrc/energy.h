@@ -35,8 +35,9 @@ __device__ __forceinline__ void energy_block(const EnergyArgs& ea, int frame) {
     S[t] = red[0][t];
     for (int w = 1; w < nw; ++w) S[t] += red[w][t];
   }
-  double u_elyt = S[8] + S[9] - ea.self_energy;
   double zdip = ea.zdip ? ea.zdip[frame] : 0.0;
+  // slab geometry: the electrolyte block of the dipole correction
+  double u_elyt = S[8] + S[9] - ea.self_energy + 0.5 * ea.slab_kappa * zdip * zdip;
   for (int v = threadIdx.x; v < ea.n_dv; v += blockDim.x) {
     double dv = ea.dv ? ea.dv[v] : ea.dv_single;
     double qb = S[0] + dv * S[1];

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(256) void k_ewald_sf(int nk, const double* __restri
 
 __global__ __launch_bounds__(256) void k_ewald_phi(int nk, int n_elec, const double* __restrict__ ew,
                                                    const double2* __restrict__ eph, const double2* __restrict__ rho_all,
-                                                   const double* __restrict__ phi_real_all, double* __restrict__ b_all) {
+                                                   const double* __restrict__ phi_real_all, double* __restrict__ b_all,
+                                                   SlabTerms sl) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   const int frame = blockIdx.y;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(256) void k_ewald_phi(int nk, int n_elec, const dou
   acc = wave_sum(acc);
   if (lane == 0) {
     size_t o = (size_t)frame * n_elec + i;
-    b_all[o] = -(phi_real_all[o] + acc);
+    b_all[o] = -(phi_real_all[o] + acc) - slab_b_term(sl, i, frame);
   }
 }
 
@@ -112,9 +113,9 @@ void launch_ewald_sf(hipStream_t s, int n_frames, int nk, const double* kv, cons
   hipLaunchKernelGGL(k_ewald_sf, dim3((nk + 3) / 4, n_frames), dim3(256), 0, s, nk, kv, ew, st, rho, ek);
 }
 void launch_ewald_phi(hipStream_t s, int n_frames, int nk, int n_elec, const double* ew, const double2* eph,
-                      const double2* rho, const double* phi_real, double* b) {
+                      const double2* rho, const double* phi_real, double* b, const SlabTerms& sl) {
   hipLaunchKernelGGL(k_ewald_phi, dim3((n_elec + 3) / 4, n_frames), dim3(256), 0, s, nk, n_elec, ew, eph, rho,
-                     phi_real, b);
+                     phi_real, b, sl);
 }
 void launch_ewald_rho_all(hipStream_t s, int n_frames, int nk, int n_elec, const double2* eph, const double* q,
                           size_t q_stride, const double2* rho, double2* out) {

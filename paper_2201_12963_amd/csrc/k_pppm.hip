@@ -24,12 +24,17 @@ __global__ __launch_bounds__(256) void k_spread_elec(int n_touch, const int* __r
                                                      const double* __restrict__ val_d,
                                                      const float* __restrict__ val_f,
                                                      const double* __restrict__ q_all, size_t q_stride,
-                                                     double* __restrict__ rho_d, float* __restrict__ rho_f, int M) {
+                                                     double* __restrict__ rho_d, float* __restrict__ rho_f, int M,
+                                                     SlabTerms sl, double* __restrict__ slab_field) {
   const int sub = threadIdx.x & 15;
   const int t = blockIdx.x * (blockDim.x / 16) + (threadIdx.x >> 4);
   const int frame = blockIdx.y;
-  const bool ok = t < n_touch;
   const double* q = q_all + (size_t)frame * q_stride;
+  if (slab_field && blockIdx.x == gridDim.x - 1) {   // the frame's slab field, one extra workgroup
+    slab_field_block(sl, q, slab_field, frame);
+    return;
+  }
+  const bool ok = t < n_touch;
   double acc = 0.0;
   if (ok) {
     const int k1 = rowptr[t + 1];
@@ -48,7 +53,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gather_b(int n_elec, int P3, const int* __restrict__ gidx,
                                                   const T* __restrict__ gw, const T* __restrict__ phi_all,
                                                   int M, const T* __restrict__ phi_real_all,
-                                                  double* __restrict__ b_all) {
+                                                  double* __restrict__ b_all, SlabTerms sl) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   const int frame = blockIdx.y;
@@ -59,7 +64,7 @@ __global__ __launch_bounds__(256) void k_gather_b(int n_elec, int P3, const int*
   acc = wave_sum(acc);
   if (lane == 0) {
     size_t o = (size_t)frame * n_elec + i;
-    b_all[o] = -((double)phi_real_all[o] + (double)acc);
+    b_all[o] = -((double)phi_real_all[o] + (double)acc) - slab_b_term(sl, i, frame);
   }
 }
 
@@ -69,7 +74,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gather_b16(int n_elec, int P3, const int* __restrict__ gidx,
                                                     const T* __restrict__ gw, const T* __restrict__ phi_all,
                                                     int M, const T* __restrict__ phi_real_all,
-                                                    double* __restrict__ b_all) {
+                                                    double* __restrict__ b_all, SlabTerms sl) {
   const int sub = threadIdx.x & 15;
   const int i = blockIdx.x * (blockDim.x / 16) + (threadIdx.x >> 4);
   const int frame = blockIdx.y;
@@ -82,39 +87,52 @@ __global__ __launch_bounds__(256) void k_gather_b16(int n_elec, int P3, const in
   for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
   if (live && sub == 0) {
     size_t o = (size_t)frame * n_elec + i;
-    b_all[o] = -((double)phi_real_all[o] + (double)acc);
+    b_all[o] = -((double)phi_real_all[o] + (double)acc) - slab_b_term(sl, i, frame);
   }
 }
 
 template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
-                          const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M) {
-  dim3 grid((n_touch + 15) / 16, n_frames);
+                          const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M,
+                          const SlabTerms& sl, double* slab_field) {
+  dim3 grid((n_touch + 15) / 16 + (slab_field ? 1 : 0), n_frames);
   const bool dbl = std::is_same<T, double>::value;
   hipLaunchKernelGGL(k_spread_elec, grid, dim3(256), 0, s, n_touch, touch, rowptr, col,
                      dbl ? (const double*)val : nullptr, dbl ? nullptr : (const float*)val, q, q_stride,
-                     dbl ? (double*)rho : nullptr, dbl ? nullptr : (float*)rho, M);
+                     dbl ? (double*)rho : nullptr, dbl ? nullptr : (float*)rho, M, sl, slab_field);
+}
+
+__global__ __launch_bounds__(256) void k_slab_field(SlabTerms sl, const double* __restrict__ q_all, size_t q_stride,
+                                                    double* __restrict__ field) {
+  slab_field_block(sl, q_all + (size_t)blockIdx.x * q_stride, field, blockIdx.x);
+}
+
+void launch_slab_field(hipStream_t s, int n_frames, const SlabTerms& sl, const double* q, size_t q_stride,
+                       double* field) {
+  hipLaunchKernelGGL(k_slab_field, dim3(n_frames), dim3(256), 0, s, sl, q, q_stride, field);
 }
 
 template <typename T>
 void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const int* gidx, const T* gw,
-                       const T* phi, int M, const T* phi_real, double* b) {
+                       const T* phi, int M, const T* phi_real, double* b, const SlabTerms& sl) {
   if (n_frames == 1) {
     dim3 grid((n_elec + 3) / 4, 1);
-    hipLaunchKernelGGL(k_gather_b<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b);
+    hipLaunchKernelGGL(k_gather_b<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b, sl);
   } else {
     dim3 grid((n_elec + 15) / 16, n_frames);
-    hipLaunchKernelGGL(k_gather_b16<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b);
+    hipLaunchKernelGGL(k_gather_b16<T>, grid, dim3(256), 0, s, n_elec, P3, gidx, gw, phi, M, phi_real, b, sl);
   }
 }
 
 template void launch_spread_elec_t<double>(hipStream_t, int, int, const int*, const int*, const int*,
-                                           const double*, const double*, size_t, double*, int);
+                                           const double*, const double*, size_t, double*, int, const SlabTerms&,
+                                           double*);
 template void launch_spread_elec_t<float>(hipStream_t, int, int, const int*, const int*, const int*,
-                                          const float*, const double*, size_t, float*, int);
+                                          const float*, const double*, size_t, float*, int, const SlabTerms&,
+                                          double*);
 template void launch_gather_b_t<double>(hipStream_t, int, int, int, const int*, const double*, const double*,
-                                        int, const double*, double*);
+                                        int, const double*, double*, const SlabTerms&);
 template void launch_gather_b_t<float>(hipStream_t, int, int, int, const int*, const float*, const float*,
-                                       int, const float*, double*);
+                                       int, const float*, double*, const SlabTerms&);
 
 }  // namespace cpm

@@ -219,6 +219,7 @@ __global__ __launch_bounds__(256) void k_site_forces(Cell cell, ElecSet<T> el, S
   }
   F[2] += qj * fa.field;
   FB[2] += qj * fa.fieldb;
+  if (fa.field_frame) F[2] += fa.out_scale * qj * fa.field_frame[frame];
   if (fa.f_comp) {
     if (lane < 6) {
       const double val = lane == 0 ? F[0] : lane == 1 ? F[1] : lane == 2 ? F[2]
@@ -332,6 +333,7 @@ __global__ __launch_bounds__(G16_THREADS) void k_site_forces_g16(SiteSet<T> st, 
   }
   F[2] += qj * fa.field;
   FB[2] += qj * fa.fieldb;
+  if (fa.field_frame) F[2] += fa.out_scale * qj * fa.field_frame[frame];
   if (!live) return;
   if (fa.f_comp) {
     if (sub < 6) {

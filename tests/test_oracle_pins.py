@@ -655,3 +655,114 @@ def test_slab_agrees_with_doubled_cell():
         for m in (up, ~up):
             assert abs(qs[m].sum() / qd[m].sum() - 1.0) < 1e-10
         assert np.abs(qs - qd).max() < 2e-4 * np.abs(qs).max()
+
+
+# --------------------------------------------------------------------------
+# 1D Poisson potential profile (Eq. 16)
+# --------------------------------------------------------------------------
+
+def _gaussian_sheets_potential(z, zs, sig, eta):
+    """Isolated potential of Gaussian sheets (areal charges sig at heights zs,
+    profile sig eta/sqrt(pi) exp(-eta^2 (z - zs)^2)), up to a constant:
+    -(sig / 2 eps0) [u erf(eta u) + exp(-eta^2 u^2)/(eta sqrt(pi))], u = z - zs."""
+    from scipy.special import erf
+    out = np.zeros_like(z)
+    for c, s in zip(zs, sig):
+        u = z - c
+        out += -(s / (2 * EPS0)) * (u * erf(eta * u) + np.exp(-(eta * u) ** 2) / (eta * math.sqrt(math.pi)))
+    return out
+
+
+def _charged_layers(geometry, n_bins):
+    """Empty tiny capacitor (slab or doubled cell) with its closed-form charges."""
+    from workloads import make_workload
+    w = make_workload("tiny", geometry).empty()
+    seff = honeycomb_seff(w.box[0] / 6, w.box[1] / 3, w.eta)
+    area = w.box[0] * w.box[1]
+    qplus = EPS0 * area * 2.0 / (4.34 - seff)
+    # per-atom charge: each layer shares its electrode's net charge equally
+    q = np.zeros(w.n_elec)
+    for m in np.unique(np.round(w.elec_xyz[2], 9)):
+        sel = np.isclose(w.elec_xyz[2], m)
+        side = w.elec_side[sel][0]
+        q[sel] = side * qplus / sel.sum()
+    return w, q, area
+
+
+@pytest.mark.parametrize("geometry", ["slab", "dc"])
+def test_profile_of_gaussian_sheets(geometry):
+    """Electrode Gaussians alone: the finite-difference profile converges to the
+    closed-form potential of Gaussian sheets at second order in the grid step,
+    and its drop between the electrode planes is (sigma/eps0)(g - 1/(eta sqrt(pi)))."""
+    from oracle import profile
+    errs = []
+    for n_bins in (2000, 4000):
+        w, q, area = _charged_layers(geometry, n_bins)
+        z0 = w.elec_xyz[2].min()                     # lower electrode plane
+        rho = profile.density(w, np.zeros((1, 3, 0)), q[None, :], n_bins)
+        bulk = (z0 + 1.5, z0 + 2.8)
+        psi = profile.potential(rho, w.box, geometry, 2.0, bulk)
+        zc = (np.arange(n_bins) + 0.5) * w.box[2] / n_bins
+        zs = np.unique(np.round(w.elec_xyz[2], 9))
+        sig = np.array([q[np.isclose(w.elec_xyz[2], c)].sum() / area for c in zs])
+        # images one period away (doubled cell: the stack is periodic)
+        zz, ss = list(zs), list(sig)
+        if geometry == "dc":
+            for img in (-1, 1):
+                zz += list(zs + img * w.box[2])
+                ss += list(sig)
+        exact = _gaussian_sheets_potential(zc, np.array(zz), np.array(ss), w.eta)
+        sel = (zc >= bulk[0]) & (zc < bulk[1])
+        exact -= exact[sel].mean()
+        errs.append(np.abs(psi - exact).max())
+    assert errs[0] < 2e-4 * 2.0
+    assert 3.5 < errs[0] / errs[1] < 4.5              # second order
+    # drop across the capacitor at the electrode planes (fine grid)
+    sig_up = sig[np.argmax(sig)]
+    g = 4.34
+    i_lo = np.argmin(np.abs(zc - z0))
+    i_hi = np.argmin(np.abs(zc - (z0 + g)))
+    drop = psi[i_hi] - psi[i_lo]
+    want = sig_up / EPS0 * (g - 1.0 / (w.eta * math.sqrt(math.pi)))
+    assert abs(drop - want) < 2e-3 * want
+
+
+def test_profile_of_point_sheets_is_exact():
+    """Electrolyte charges at bin centres are sheets at grid points, and the
+    second-difference solution of sheets is the piecewise-linear potential
+    exactly: zero-flux ends (slab), then a finite-field rise of dpsi."""
+    from oracle import profile
+    from workloads import make_workload
+    n_bins = 600
+    w = make_workload("tiny", "slab").empty()
+    h = w.box[2] / n_bins
+    area = w.box[0] * w.box[1]
+    zq = np.array([100.5, 250.5, 251.5, 400.5]) * h
+    qq = np.array([0.7, -1.1, 0.9, -0.5])
+    w = dataclasses.replace(w, site_q=qq)
+    x = np.zeros((1, 3, 4))
+    x[0, 2] = zq
+    rho = profile.density(w, x, np.zeros((1, w.n_elec)), n_bins)
+    zc = (np.arange(n_bins) + 0.5) * h
+    bulk = (zc[300], zc[320])
+    psi = profile.potential(rho, w.box, "slab", 0.0, bulk)
+    exact = np.zeros(n_bins)
+    for c, s in zip(zq, qq / area):
+        exact += -(s / (2 * EPS0)) * np.abs(zc - c)
+    # zero field at the ends: the point sheets are neutral, so the isolated
+    # potential is flat outside them already
+    sel = (zc >= bulk[0]) & (zc < bulk[1])
+    exact -= exact[sel].mean()
+    assert np.abs(psi - exact).max() < 1e-9 * np.abs(exact).max()
+    # finite field: the same charges plus the linear rise dv z / Lz
+    dv = 1.3
+    wf = dataclasses.replace(w, geometry="ff")
+    psi_f = profile.potential(rho, wf.box, "ff", dv, bulk)
+    # a linear term solves the Laplace equation, so the solution is the
+    # isolated one plus a ramp a z whose total rise over the period is dv:
+    # iso(Lz) - iso(0) = p/eps0 (p the areal dipole), a Lz = dv - p/eps0
+    dip = np.sum(qq / area * zq)
+    ramp = (dv - dip / EPS0) * zc / w.box[2]
+    ex_f = exact + ramp
+    ex_f -= ex_f[sel].mean()
+    assert np.abs(psi_f - ex_f).max() < 1e-9 * np.abs(ex_f).max()

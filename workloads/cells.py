@@ -209,12 +209,18 @@ SLAB_FACTOR = 3.0   # periodic length over the cell's length in slab geometry
 
 
 def _slab(w: Workload, factor: float) -> Workload:
-    """Slab geometry: the same cell inside a z-period `factor` times as long,
-    the rest empty, and the mesh lengthened in z in proportion (same spacing)."""
+    """Slab geometry: the same cell in the middle of a z-period `factor` times
+    as long (empty space of equal depth below and above it, across z = 0),
+    and the mesh lengthened in z in proportion (same spacing)."""
     box = w.box.copy()
     box[2] = factor * w.box[2]
     kz = int(round(factor * w.mesh[2]))
-    return dataclasses.replace(w, geometry="slab", box=box, mesh=(w.mesh[0], w.mesh[1], kz))
+    dz = 0.5 * (box[2] - w.box[2])
+    ex, sx = w.elec_xyz.copy(), w.site_xyz.copy()
+    ex[2] += dz
+    sx[2] += dz
+    return dataclasses.replace(w, geometry="slab", box=box, mesh=(w.mesh[0], w.mesh[1], kz),
+                               elec_xyz=ex, site_xyz=sx, site_zmin=w.site_zmin + dz, site_zmax=w.site_zmax + dz)
 
 
 def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None, layers: int = 1,
