@@ -181,6 +181,20 @@ int cpm_grad(cpm_ctx* ctx, const double* site_xyz, double dv, const double* q_ta
 int cpm_profile(cpm_ctx* ctx, int n_frames, const double* site_xyz, const double* q, long long q_stride,
                 double dv, int n_bins, double bulk_lo, double bulk_hi, double* rho_out, double* psi_out);
 
+/* cpm_profile for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results and errors, but the histogram scratch is a
+ * file-scope device array of 4 MiB per GPU (128 partitions x (2048 bins +
+ * 2048 heights) doubles, the most the argument limits allow; a request
+ * beyond it is CPM_EINVAL) whose address the library resolves once per
+ * device when a context is created, so the call itself allocates nothing
+ * and never synchronises.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams, or from different
+ * contexts) race.  Each partition is written whole before it is read, so no
+ * clearing is needed between calls. */
+int cpm_profile_noalloc(cpm_ctx* ctx, int n_frames, const double* site_xyz, const double* q, long long q_stride,
+                        double dv, int n_bins, double bulk_lo, double bulk_hi, double* rho_out, double* psi_out);
+
 /* Copies of internal matrices for tests and checkpoints (synchronises):
  * which = 0: A, 1: S (projected inverse), 2: S c (n_elec values).
  * host_out holds n_elec*n_elec (or n_elec) doubles. */

@@ -34,7 +34,7 @@ _STATUS_NAMES = {0: "CPM_OK", -1: "CPM_EINVAL", -2: "CPM_ESTATE", -3: "CPM_ENOTS
 
 EXPORTED = ("cpm_create", "cpm_set_stream", "cpm_build_elastance", "cpm_solve", "cpm_solve_batch",
             "cpm_grad", "cpm_get_matrix", "cpm_set_matrix", "cpm_get_buffer", "cpm_sync_status",
-            "cpm_last_error", "cpm_destroy", "cpm_replay_kernel", "cpm_profile")
+            "cpm_last_error", "cpm_destroy", "cpm_replay_kernel", "cpm_profile", "cpm_profile_noalloc")
 
 
 class CpmError(RuntimeError):
@@ -93,6 +93,8 @@ def load_library():
     lib.cpm_profile.argtypes = [vp, ip, vp, vp, ctypes.c_longlong, ctypes.c_double, ip, ctypes.c_double,
                                 ctypes.c_double, vp, vp]
     lib.cpm_profile.restype = ip
+    lib.cpm_profile_noalloc.argtypes = lib.cpm_profile.argtypes
+    lib.cpm_profile_noalloc.restype = ip
     lib.cpm_replay_kernel.argtypes = [vp, ip, ip]
     lib.cpm_replay_kernel.restype = ip
     lib.cpm_sync_status.argtypes = [vp]

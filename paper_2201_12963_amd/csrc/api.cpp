@@ -102,6 +102,7 @@ struct cpm_ctx {
   double* d_heights = nullptr;
   double* d_prof = nullptr;
   size_t cap_prof = 0;
+  double* d_prof_static = nullptr;         // this device's file-scope profile scratch (cpm_profile_noalloc)
 
   // ---- PPPM
   MeshInfo mi{};
@@ -1059,7 +1060,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       (r = dalloc(c, &c->d_Sc, ne)) || (r = dalloc(c, &c->d_Sc_s, ne)) || (r = dalloc(c, &c->d_status, 4)) ||
       (r = dalloc(c, &c->d_scalar, 8)))
     return bad(r);
-  c->n_pad = (ne + 15) / 16 * 16;
+  c->n_pad = (ne + 31) / 32 * 32;          // rows of the bf16 split operands: whole 32-deep MFMA slabs
   if (c->precision == CPM_MIXED) {
     if (ne > 4096) { fail(c, CPM_EINVAL, "mixed precision supports up to 4096 electrode atoms"); return bad(CPM_EINVAL); }
     if ((r = dalloc(c, &c->d_Sf, (size_t)ne * ne)) || (r = dalloc(c, &c->d_Ssplit, (size_t)3 * ne * c->n_pad)))
@@ -1186,6 +1187,14 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
       return bad(r);
   }
   if ((r = alloc_frames(c, 1))) return bad(r);
+  {
+    // set-up of cpm_profile_noalloc: this device's address of its scratch
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || profile_static_scratch(dev, &c->d_prof_static) != 0) {
+      fail(c, CPM_EDEVICE, "cannot resolve the profile scratch on device %d", dev);
+      return bad(CPM_EDEVICE);
+    }
+  }
   *out = c;
   return CPM_OK;
 }
@@ -1450,6 +1459,20 @@ int cpm_profile(cpm_ctx* c, int n_frames, const double* site_xyz, const double* 
     c->cap_prof = need;
   }
   p.part = c->d_prof;
+  launch_profile(c->stream, p);
+  return check_launch(c);
+}
+
+int cpm_profile_noalloc(cpm_ctx* c, int n_frames, const double* site_xyz, const double* q, long long q_stride,
+                        double dv, int n_bins, double bulk_lo, double bulk_hi, double* rho_out, double* psi_out) {
+  if (!c) return CPM_EINVAL;
+  ProfileArgs p;
+  TRY(profile_args(c, n_frames, site_xyz, q, q_stride, dv, n_bins, bulk_lo, bulk_hi, rho_out, psi_out, p));
+  const size_t need = (size_t)p.n_part * (p.n_bins + p.n_heights);
+  if (need > PROFILE_STATIC_DOUBLES)
+    return fail(c, CPM_EINVAL, "profile scratch of %zu doubles exceeds the static %zu", need, PROFILE_STATIC_DOUBLES);
+  if (!c->d_prof_static) return fail(c, CPM_ESTATE, "profile scratch not set up");
+  p.part = c->d_prof_static;
   launch_profile(c->stream, p);
   return check_launch(c);
 }

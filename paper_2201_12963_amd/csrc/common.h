@@ -546,6 +546,12 @@ struct ProfileArgs {
   double* rho_out;          // [n_bins] e / nm^3
   double* psi_out;          // [n_bins] V
 };
+// file-scope scratch of cpm_profile_noalloc (k_profile.hip): 4 MiB per GPU
+constexpr size_t PROFILE_STATIC_DOUBLES = (size_t)PROFILE_MAX_PARTS * (PROFILE_MAX_BINS + PROFILE_MAX_HEIGHTS);
+constexpr int PROFILE_MAX_DEVICES = 64;
+// device address of that scratch on `device` (current in the caller), looked
+// up once per device; 0 on success
+int profile_static_scratch(int device, double** out);
 size_t profile_partial_lds(int n_bins, int n_heights);
 size_t profile_solve_lds(int n_bins, int n_heights);
 void launch_profile(hipStream_t s, const ProfileArgs& p);

@@ -18,6 +18,8 @@
 // flattened (frame, site) and (frame, atom) indices per workgroup, written
 // whole to scratch, so the scratch needs no clearing), then one workgroup
 // that sums the partitions, adds the electrode Gaussians and solves.
+#include <mutex>
+
 #include "common.h"
 
 namespace cpm {
@@ -146,6 +148,38 @@ __global__ __launch_bounds__(PROFILE_SOLVE_THREADS) void k_profile_solve(Profile
 size_t profile_partial_lds(int n_bins, int n_heights) { return (size_t)(n_bins + n_heights) * sizeof(double); }
 size_t profile_solve_lds(int n_bins, int n_heights) {
   return (size_t)(2 * n_bins + n_heights + PROFILE_SOLVE_THREADS) * sizeof(double);
+}
+
+// ------------------------------------------------ scratch without allocation
+//
+// For callers that cannot allocate (code under HIP graph capture, serving
+// loops, harnesses that forbid hipMalloc), cpm_profile_noalloc takes its
+// histogram partitions from this file-scope array instead of the context's
+// allocation.  PROFILE_STATIC_DOUBLES covers the largest request the
+// argument limits allow (128 partitions x (2048 bins + 2048 heights)).
+// Every call on one GPU shares that GPU's copy, which keeps the last call's
+// contents; each partition is written whole before it is read, so nothing
+// needs clearing, and calls that overlap on one GPU race.
+static __device__ __align__(256) double scratch[PROFILE_STATIC_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[PROFILE_MAX_DEVICES] = {};
+}  // namespace
+
+int profile_static_scratch(int device, double** out) {
+  *out = nullptr;
+  if (device < 0 || device >= PROFILE_MAX_DEVICES) return -1;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    // the device's own address of the array (the host-side name is only a
+    // stand-in); the device is current in the caller
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+    g_scratch_ptr[device] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[device]);
+  return 0;
 }
 
 void launch_profile(hipStream_t s, const ProfileArgs& p) {
