@@ -448,7 +448,7 @@ template <> struct Bufs<float> {
 // spread scans the raw positions and needs no cell list), and the real-space
 // part of b as extra workgroups of the z pass that follows.
 template <typename T>
-int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
+int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces, bool need_b = true) {
   using B = Bufs<T>;
   using T2 = typename B::T2;
   hipStream_t s = c->stream;
@@ -491,8 +491,12 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
     if (rb.tiles) rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
-                            forces ? B::save(c) : nullptr, 0, c->d_ek, true, rb.tiles ? nullptr : &rb, nullptr);
+                            forces ? B::save(c) : nullptr, 0, c->d_ek, true,
+                            (rb.tiles || !need_b) ? nullptr : &rb, nullptr);
     });
+    // forces at given charges (MD steps between charge updates): only the
+    // saved site spectrum is needed, not b
+    if (!need_b) return CPM_OK;
     // timed alone through the stand-alone kernel with the same body
     if (!rb.tiles) keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     rec(c, CPM_KERNEL_FFT_XY_INV, s, [=](hipStream_t s) {
@@ -504,8 +508,12 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces) {
     });
   } else {
     rec(c, CPM_KERNEL_BIN, s, [=](hipStream_t s) { launch_bin_sites(s, nf, ba); });
-    rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     SiteSet<double> sd = Bufs<double>::sites(c);
+    if (!need_b) {
+      launch_ewald_sf(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok, c->d_ek);
+      return CPM_OK;
+    }
+    rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     launch_ewald_sf(s, nf, c->nk, c->d_kv, c->d_ew, sd, c->d_rhok, c->d_ek);
     launch_ewald_phi(s, nf, c->nk, c->n_elec, c->d_ew, c->d_eph, c->d_rhok, c->d_phir, c->d_b, slab_terms(c));
   }
@@ -655,6 +663,24 @@ int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, doubl
     TRY(enqueue_forces<T>(c, 1, q_out, c->n_elec, c->d_qs, fa, e_out ? &ea : nullptr));
   }
   return CPM_OK;
+}
+
+// Coulomb forces on the sites at given electrode charges q (device, original
+// order), without b or a charge solve: the MD steps between charge updates
+template <typename T>
+int enqueue_forces_at(cpm_ctx* c, const double* xyz, double dv, const double* q, double* f_out) {
+  hipStream_t s = c->stream;
+  TRY(enqueue_b<T>(c, 1, xyz, true, false));
+  launch_permute(s, 1, c->n_elec, c->d_epos, q, c->d_qs);
+  ForceArgs<T> fa{};
+  fa.out_scale = 1.0;
+  fa.field = (c->geometry == CPM_FINITE_FIELD) ? -dv / c->box[2] : 0.0;
+  fa.f_out = f_out;
+  fa.f_frame_stride = 3 * (size_t)c->n_site;
+  fa.n_dv = 1;
+  fa.dv = nullptr;
+  fa.u_site = c->d_usite;
+  return enqueue_forces<T>(c, 1, q, c->n_elec, c->d_qs, fa, nullptr);
 }
 
 // Adjoint of L = sum (q - t)^2 + U_coul through q* = S v(R)

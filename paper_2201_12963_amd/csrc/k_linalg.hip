@@ -57,49 +57,6 @@ __global__ __launch_bounds__(256) void k_phase_matrix(int n, int nkc, int k0, in
   C[(size_t)i * 2 * nkc + nkc + c] = sk[k] * s;
 }
 
-// D[M x N] = beta D + alpha A B^T, A (M x K) and B (N x K) row-major with
-// leading dimensions lda, ldb, D with ldd.  64 x 64 tiles, 16-deep k-slabs
-// through LDS, 4 x 4 outputs per thread.
-__global__ __launch_bounds__(256) void k_gemm_nt(int M, int N, int K, double alpha, const double* __restrict__ A,
-                                                 int lda, const double* __restrict__ B, int ldb, double beta,
-                                                 double* __restrict__ D, int ldd) {
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  double acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int t = threadIdx.x; t < 64 * 16; t += 256) {
-      int r = t >> 4, kk = t & 15;
-      int gi = i0 + r, gj = j0 + r, gk = k0 + kk;
-      As[kk][r] = (gi < M && gk < K) ? A[(size_t)gi * lda + gk] : 0.0;
-      Bs[kk][r] = (gj < N && gk < K) ? B[(size_t)gj * ldb + gk] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) { a[u] = As[kk][ty + 16 * u]; b[u] = Bs[kk][tx + 16 * u]; }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      int gi = i0 + ty + 16 * u, gj = j0 + tx + 16 * v;
-      if (gi < M && gj < N) {
-        double* d = D + (size_t)gi * ldd + gj;
-        *d = (beta == 0.0 ? 0.0 : beta * *d) + alpha * acc[u][v];
-      }
-    }
-}
-
 __global__ void k_symmetrize(int n, double* __restrict__ A) {
   const int j = blockIdx.x * 16 + (threadIdx.x & 15);
   const int i = blockIdx.y * 16 + (threadIdx.x >> 4);
@@ -405,11 +362,6 @@ void launch_phase_matrix(hipStream_t s, int n, int nkc, int k0, int nk, const do
                          const double* ex, const double* ey, const double* ez, double* C) {
   hipLaunchKernelGGL(k_phase_matrix, dim3((nkc + 255) / 256, n), dim3(256), 0, s, n, nkc, k0, nk, kv, sk, ex, ey,
                      ez, C);
-}
-void launch_gemm_nt(hipStream_t s, int M, int N, int K, double alpha, const double* A, int lda, const double* B,
-                    int ldb, double beta, double* D, int ldd) {
-  hipLaunchKernelGGL(k_gemm_nt, dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                     beta, D, ldd);
 }
 void launch_symmetrize(hipStream_t s, int n, double* A) {
   hipLaunchKernelGGL(k_symmetrize, dim3((n + 15) / 16, (n + 15) / 16), dim3(256), 0, s, n, A);

@@ -5,16 +5,13 @@
 // the large common offset of b before rounding), then an FP64 re-projection
 // onto the neutral subspace (per sub-cell for the doubled cell).
 //
-// Batch: Q = S B as a split-precision GEMM on the bf16 matrix cores.  Each
-// operand is written as three bf16 terms x = x0 + x1 + x2 (x0 = bf16(x),
-// x1 = bf16(x - x0), x2 = bf16(x - x0 - x1), about 2^-25 relative left over)
-// and S B ~ sum of the six products x_a y_b with a + b <= 2, accumulated in
-// FP32 by v_mfma_f32_16x16x16 bf16.  Two terms (three products) are not
+// Batch: Q = S B as a split-precision GEMM on the bf16 matrix cores
+// (k_gemm.hip).  Each operand is written here as three bf16 terms
+// x = x0 + x1 + x2 (x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1),
+// about 2^-25 relative left over) and S B ~ sum of the six products x_a y_b
+// with a + b <= 2, accumulated in FP32.  Two terms (three products) are not
 // enough here: the rows of S sum to zero, so |q_i| is a small fraction of
 // sum_j |S_ij b_j| and a 2^-17 relative product error shows up as ~1e-5 e.
-// A 256-thread workgroup owns a 64 x 64 output tile, each wavefront a
-// 32 x 32 quarter (2 x 2 MFMA blocks); operand slabs of 64 x 16 pass through
-// LDS.
 #include "common.h"
 
 namespace cpm {
@@ -128,63 +125,6 @@ __global__ __launch_bounds__(256) void k_reproject(int n, const unsigned char* _
   for (int i = threadIdx.x; i < n; i += blockDim.x) Q[i] -= (sub1 && sub1[i]) ? m1 : m0;
 }
 
-// D[f][i] = sum_k A[f][k] B[i][k]; A and B given as three bf16 terms of rows
-// of length K (K a multiple of 16; rows beyond M or N read as zero).
-typedef short short4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(256) void k_gemm_bf16x6(int M, int N, int K, const unsigned short* __restrict__ A,
-                                                     size_t a_plane, const unsigned short* __restrict__ B,
-                                                     size_t b_plane, double* __restrict__ D, int ldd) {
-  __shared__ unsigned short sA[3][64][16 + 4], sB[3][64][16 + 4];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  float4_t acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
-  // MFMA operand layout (16 x 16 x 16, bf16): lane l feeds row/column l % 16
-  // with k = 4 (l / 16) .. 4 (l / 16) + 3
-  const int r = lane & 15, kg = (lane >> 4) * 4;
-  const int lrow = threadIdx.x >> 2, lk = (threadIdx.x & 3) * 4;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int ga = m0 + lrow, gb = n0 + lrow;
-    for (int p = 0; p < 3; ++p)
-      for (int t = 0; t < 4; ++t) {
-        sA[p][lrow][lk + t] = ga < M ? A[p * a_plane + (size_t)ga * K + k0 + lk + t] : 0;
-        sB[p][lrow][lk + t] = gb < N ? B[p * b_plane + (size_t)gb * K + k0 + lk + t] : 0;
-      }
-    __syncthreads();
-    short4_t av[3][2], bv[3][2];
-    for (int p = 0; p < 3; ++p)
-      for (int a = 0; a < 2; ++a)
-        for (int t = 0; t < 4; ++t) {
-          av[p][a][t] = (short)sA[p][wm + 16 * a + r][kg + t];
-          bv[p][a][t] = (short)sB[p][wn + 16 * a + r][kg + t];
-        }
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        // smallest terms first
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[1][a], bv[1][b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[2][a], bv[0][b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[0][a], bv[2][b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[1][a], bv[0][b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[0][a], bv[1][b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[0][a], bv[0][b], acc[a][b], 0, 0, 0);
-      }
-    __syncthreads();
-  }
-  // D block layout: lane holds rows 4 (lane / 16) + t of column lane % 16
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int t = 0; t < 4; ++t) {
-        int gm = m0 + wm + 16 * a + (lane >> 4) * 4 + t;
-        int gn = n0 + wn + 16 * b + (lane & 15);
-        if (gm < M && gn < N) D[(size_t)gm * ldd + gn] = (double)acc[a][b][t];
-      }
-}
-
 // ------------------------------------------------------------ launchers
 
 void launch_split_matrix(hipStream_t s, int n, int n_pad, const double* S, float* Sf, unsigned short* split) {
@@ -203,10 +143,4 @@ void launch_charges_f32(hipStream_t s, int n_frames, int n, const float* Sf, con
 void launch_reproject(hipStream_t s, int n_frames, int n, const unsigned char* sub1, double* Q0) {
   hipLaunchKernelGGL(k_reproject, dim3(n_frames), dim3(256), 0, s, n, sub1, Q0);
 }
-void launch_gemm_bf16x6(hipStream_t s, int M, int N, int K, const unsigned short* A, size_t a_plane,
-                        const unsigned short* B, size_t b_plane, double* D, int ldd) {
-  hipLaunchKernelGGL(k_gemm_bf16x6, dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, s, M, N, K, A, a_plane, B,
-                     b_plane, D, ldd);
-}
-
 }  // namespace cpm
