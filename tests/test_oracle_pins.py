@@ -766,3 +766,107 @@ def test_profile_of_point_sheets_is_exact():
     ex_f = exact + ramp
     ex_f -= ex_f[sel].mean()
     assert np.abs(psi_f - ex_f).max() < 1e-9 * np.abs(ex_f).max()
+
+
+# --------------------------------------------------------------------------
+# the MD loop (velocity Verlet, SHAKE/RATTLE, Nose-Hoover, charges every k steps)
+# --------------------------------------------------------------------------
+
+def test_md_verlet_harmonic_closed_form():
+    """Velocity Verlet on x'' = -w^2 x from rest: x_n = cos(n theta) exactly,
+    cos(theta) = 1 - (w dt)^2 / 2 (the Stormer recursion)."""
+    from oracle import md
+    m, k, dt = np.array([2.0]), 50.0, 0.01
+    w = math.sqrt(k / m[0])
+    theta = math.acos(1.0 - 0.5 * (w * dt) ** 2)
+    con = md.Constraints(np.zeros(0, int), np.zeros(0, int), np.zeros(0))
+    box = np.array([1e6, 1e6, 1e6])
+    force = lambda x: -k * x
+    x = np.array([[1.0], [0.0], [0.0]])
+    v = np.zeros((3, 1))
+    f = force(x)
+    for n in range(1, 1001):
+        x, v, f = md.verlet_step(x, v, f, m, con, box, dt, force)
+        assert abs(x[0, 0] - math.cos(n * theta)) < 1e-11
+
+
+def test_md_rigid_rotor_constraints_and_momenta():
+    """A free rigid three-site molecule: SHAKE/RATTLE keep the two bonds and
+    the third side to tolerance, and momentum and angular momentum (the
+    constraint forces are central pair forces) are conserved."""
+    from oracle import md
+    from workloads.cells import BOND, CATION_MASS
+    m = np.array(CATION_MASS)
+    con = md.rigid_constraints(np.array([3]), BOND)
+    box = np.array([50.0, 50.0, 50.0])
+    u = np.array([1.0, 0.0, 0.0]); p = np.array([0.0, 1.0, 0.0])
+    c = np.array([5.0, 5.0, 5.0])
+    x = np.stack([c, c + BOND * u, c + BOND * (math.cos(2 * math.pi / 3) * u + math.sin(2 * math.pi / 3) * p)], 1)
+    v = md.rattle(np.random.default_rng(3).normal(0.0, 2.0, (3, 3)), x, m, con, box)
+    force = lambda x: np.zeros_like(x)
+    f = force(x)
+
+    def moments(x, v):
+        P = (m * v).sum(1)
+        L = np.cross(x.T, (m * v).T).sum(0)
+        return P, L
+
+    P0, L0 = moments(x, v)
+    for _ in range(2000):
+        x, v, f = md.verlet_step(x, v, f, m, con, box, 0.002, force)
+    for i, j, d in zip(con.i, con.j, con.d):
+        assert abs(np.linalg.norm(x[:, i] - x[:, j]) - d) < 1e-11
+        assert abs((v[:, i] - v[:, j]) @ (x[:, i] - x[:, j])) < 1e-9
+    P1, L1 = moments(x, v)
+    assert np.abs(P1 - P0).max() < 1e-10 * np.abs(P0).max()
+    assert np.abs(L1 - L0).max() < 1e-9 * np.abs(L0).max()
+
+
+@pytest.mark.slow
+def test_md_extended_energy_second_order():
+    """With the charges solved every step, the forces are -grad(E_cp + U_LJ),
+    so the thermostatted loop conserves its extended energy up to the
+    integrator's O(dt^2) error: over the same 40 fs the largest excursion of
+    the extended energy shrinks about fourfold when dt is halved."""
+    from oracle import md
+    from workloads import md_setup
+    w, A, S = built("tiny", "ff")
+    base = md_setup(w)
+    v0 = np.random.default_rng(8).normal(0.0, 1.0, (3, w.n_site)) * np.sqrt(md.KB * 400.0 / base.site_mass)
+    excursion = []
+    for dt, n in ((0.002, 20), (0.001, 40)):
+        setup = dataclasses.replace(base, dt=dt, charge_every=1)
+        loop = md.Loop(w, A, S, "ewald", setup, w.dv)
+        s = loop.start(w.site_xyz, v0)
+        h0 = loop.extended_energy(s, s.e_cp)
+        hs = []
+        for _ in range(n):
+            s = loop.step(s)
+            hs.append(loop.extended_energy(s, s.e_cp) - h0)
+        excursion.append(np.abs(hs).max())
+        # constraints hold along the way
+        for i, j, d in zip(loop.con.i, loop.con.j, loop.con.d):
+            r = md.min_image((s.x[:, i] - s.x[:, j])[:, None], w.box)[:, 0]
+            assert abs(np.linalg.norm(r) - d) < 1e-10
+    assert 3.0 < excursion[0] / excursion[1] < 5.5
+
+
+def test_md_charges_held_between_updates():
+    """Charges change only on every k-th step (k = 5), and then equal a fresh
+    solve at the new positions."""
+    from oracle import md
+    from workloads import md_setup
+    w, A, S = built("tiny", "ff")
+    loop = md.Loop(w, A, S, "ewald", md_setup(w), w.dv)
+    s = loop.start(w.site_xyz, np.zeros((3, w.n_site)))
+    qs, xs = [s.q.copy()], [s.x.copy()]
+    for _ in range(6):
+        s = loop.step(s)
+        qs.append(s.q.copy())
+        xs.append(s.x.copy())
+    for n in (1, 2, 3, 4):
+        assert np.array_equal(qs[n], qs[0])
+    assert not np.array_equal(qs[5], qs[4])
+    fresh = cpm.step(w, A, S, cpm.Electrostatics(w, "ewald"), site_xyz=xs[5], with_forces=False)["q"]
+    assert np.abs(qs[5] - fresh).max() < 1e-15
+    assert np.array_equal(qs[6], qs[5])

@@ -27,4 +27,6 @@ from .cells import (  # noqa: F401
     perturbed_frames,
     random_walk,
     WORKLOAD_NAMES,
+    MDSetup,
+    md_setup,
 )

@@ -68,6 +68,8 @@ class Workload:
     site_q: np.ndarray
     site_zmin: np.ndarray          # per-site z window used by the random walk
     site_zmax: np.ndarray
+    mol_size: Optional[np.ndarray] = None   # sites of each molecule in site order (3: cation, 1: ion)
+    lj_elec_xyz: Optional[np.ndarray] = None  # every graphene atom of the three-sheet electrodes (uncharged ones too)
     dv: float = 2.0                # V
     seed: int = 0
 
@@ -180,6 +182,17 @@ def random_electrolyte(rng, n_pairs, lx, ly, zmin, zmax, cation_sites):
     return placed[:n].T.copy(), charges[:n].copy()
 
 
+def molecule_sizes(site_q: np.ndarray) -> np.ndarray:
+    """Sites per molecule in site order: a 3-site cation starts with its +0.4 e
+    central site; every other site is an ion of its own."""
+    sizes, j = [], 0
+    while j < site_q.size:
+        k = 3 if abs(site_q[j] - CATION_Q[0]) < 1e-12 else 1
+        sizes.append(k)
+        j += k
+    return np.array(sizes, dtype=np.int32)
+
+
 def _double(w: Workload, z_lo: float, z_hi: float) -> Workload:
     """Doubled-cell construction from a single finite-field style cell."""
     lz = w.box[2]
@@ -202,6 +215,8 @@ def _double(w: Workload, z_lo: float, z_hi: float) -> Workload:
         site_q=np.concatenate([w.site_q, w.site_q]),
         site_zmin=np.concatenate([w.site_zmin, zmin2]),
         site_zmax=np.concatenate([w.site_zmax, zmax2]),
+        mol_size=np.concatenate([w.mol_size, w.mol_size]),
+        lj_elec_xyz=np.concatenate([w.lj_elec_xyz, w.lj_elec_xyz + np.array([[0.0], [0.0], [lz]])], axis=1),
     )
 
 
@@ -216,11 +231,13 @@ def _slab(w: Workload, factor: float) -> Workload:
     box[2] = factor * w.box[2]
     kz = int(round(factor * w.mesh[2]))
     dz = 0.5 * (box[2] - w.box[2])
-    ex, sx = w.elec_xyz.copy(), w.site_xyz.copy()
+    ex, sx, lj = w.elec_xyz.copy(), w.site_xyz.copy(), w.lj_elec_xyz.copy()
     ex[2] += dz
     sx[2] += dz
+    lj[2] += dz
     return dataclasses.replace(w, geometry="slab", box=box, mesh=(w.mesh[0], w.mesh[1], kz),
-                               elec_xyz=ex, site_xyz=sx, site_zmin=w.site_zmin + dz, site_zmax=w.site_zmax + dz)
+                               elec_xyz=ex, site_xyz=sx, site_zmin=w.site_zmin + dz, site_zmax=w.site_zmax + dz,
+                               lj_elec_xyz=lj)
 
 
 def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None, layers: int = 1,
@@ -249,8 +266,8 @@ def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None, l
         # electrode must not cross it)
         z_lo = 2 * INTERLAYER if layers == 3 else 0.0
         z_hi = z_lo + 4.34
-        lo, lo_l = electrode(6, 3, lx, ly, z_lo, -1, layers)
-        hi, hi_l = electrode(6, 3, lx, ly, z_hi, +1, layers)
+        lo, lo_l = electrode(6, 3, lx, ly, z_lo, -1, 3)
+        hi, hi_l = electrode(6, 3, lx, ly, z_hi, +1, 3)
         seed = 1 if seed is None else seed
         rng = np.random.default_rng(seed)
         sxyz, sq = random_electrolyte(rng, 50, lx, ly, z_lo + MIN_SEP, z_hi - MIN_SEP, 1)
@@ -261,8 +278,8 @@ def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None, l
         lx = ly = 3.4 * reps
         lz = 12.625
         z_lo, z_hi = 1.3125, 11.3125
-        lo, lo_l = electrode(11 * reps, 10 * reps, lx, ly, z_lo, -1, layers)
-        hi, hi_l = electrode(11 * reps, 10 * reps, lx, ly, z_hi, +1, layers)
+        lo, lo_l = electrode(11 * reps, 10 * reps, lx, ly, z_lo, -1, 3)
+        hi, hi_l = electrode(11 * reps, 10 * reps, lx, ly, z_hi, +1, 3)
         seed = (2 if name == "paper" else 3) if seed is None else seed
         rng = np.random.default_rng(seed)
         sxyz, sq = random_electrolyte(rng, 320 * reps * reps, lx, ly,
@@ -275,6 +292,12 @@ def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None, l
                           alpha_exact=1.6, rcut_exact=3.7, kcut_exact=17.5)
     else:
         raise ValueError(f"unknown workload {name!r}")
+    # all three sheets take part in the Lennard-Jones interactions; the
+    # constant-potential charges sit on the nearest sheet only (layers = 1) or
+    # on all three
+    lj_all = np.concatenate([lo, hi], axis=1)
+    keep_lo, keep_hi = lo_l < layers, hi_l < layers
+    lo, lo_l, hi, hi_l = lo[:, keep_lo], lo_l[keep_lo], hi[:, keep_hi], hi_l[keep_hi]
     n_half = lo.shape[1]
     w = Workload(
         name=name, geometry="ff", box=np.array([lx, ly, lz]), eta=eta,
@@ -282,6 +305,7 @@ def make_workload(name: str, geometry: str = "ff", seed: Optional[int] = None, l
         elec_side=np.concatenate([-np.ones(n_half, np.int8), np.ones(n_half, np.int8)]),
         elec_sub=None, elec_layer=np.concatenate([lo_l, hi_l]), site_xyz=sxyz, site_q=sq,
         site_zmin=np.full(sq.shape, z_lo + MIN_SEP), site_zmax=np.full(sq.shape, z_hi - MIN_SEP),
+        mol_size=molecule_sizes(sq), lj_elec_xyz=lj_all,
         seed=seed, **params)
     if geometry == "dc":
         w = _double(w, z_lo, z_hi)
@@ -317,3 +341,74 @@ def perturbed_frames(w: Workload, n_frames: int, sigma: float = 0.05, seed: int 
     out = w.site_xyz[None, :, :] + rng.normal(0.0, sigma, size=(n_frames, 3, w.n_site))
     out %= w.box[None, :, None]
     return out
+
+
+# --------------------------------------------------------------------------
+# molecular dynamics inputs
+# --------------------------------------------------------------------------
+
+# Synthetic stand-ins for the coarse-grained ionic liquid and graphene force
+# fields (the paper takes them from the literature, which is not at hand):
+# masses of the three cation sites and the anion (a 139 + 145 amu ion pair),
+# Lennard-Jones sigma (nm) and epsilon (kJ/mol) per site kind, graphene
+# carbon, Lorentz-Berthelot combination.  sigma is kept near the 0.3 nm
+# placement separation so that the seeded configurations start without
+# overlaps.
+CATION_MASS = (67.0, 15.0, 57.0)
+ANION_MASS = 145.0
+SINGLE_CATION_MASS = 139.0
+SITE_SIGMA, SITE_EPS = 0.30, 1.5
+CARBON_SIGMA, CARBON_EPS, CARBON_MASS = 0.34, 0.23, 12.011
+LJ_CUT = 1.6              # nm (appendix: non-Coulombic cutoff 16 A)
+MD_DT = 0.002             # ps (2 fs)
+MD_TEMPERATURE = 400.0    # K
+MD_TAU = 0.1              # ps, Nose-Hoover time constant
+MD_CHARGE_EVERY = 5       # charge update every 5 steps
+
+
+@dataclasses.dataclass
+class MDSetup:
+    """Inputs of the constant-potential MD loop for one workload."""
+
+    site_mass: np.ndarray          # (n_site,) amu
+    site_sigma: np.ndarray         # (n_site,) nm
+    site_eps: np.ndarray           # (n_site,) kJ/mol
+    lj_elec_xyz: np.ndarray        # (3, n) every graphene atom (all sheets), fixed
+    carbon_sigma: float
+    carbon_eps: float
+    lj_cut: float
+    mol_size: np.ndarray           # (n_mol,) 3 (rigid cation) or 1
+    mol_group: np.ndarray          # (n_mol,) thermostat group (doubled cell: one per sub-cell)
+    n_groups: int
+    bond: float                    # cation bond length (nm); the third side is bond * sqrt(3)
+    dt: float
+    temperature: float
+    tau: float
+    charge_every: int
+
+
+def md_setup(w: Workload) -> MDSetup:
+    """Force field, rigid molecules and thermostat groups for a workload; the
+    Lennard-Jones electrodes are all three sheets of each electrode whatever
+    the workload charges."""
+    sizes = w.mol_size
+    mass = np.empty(w.n_site)
+    j = 0
+    for k in sizes:
+        if k == 3:
+            mass[j:j + 3] = CATION_MASS
+        else:
+            mass[j] = ANION_MASS if w.site_q[j] < 0 else SINGLE_CATION_MASS
+        j += k
+    n_mol = sizes.size
+    if w.geometry == "dc":
+        groups = np.concatenate([np.zeros(n_mol // 2, np.int32), np.ones(n_mol - n_mol // 2, np.int32)])
+        n_groups = 2
+    else:
+        groups = np.zeros(n_mol, np.int32)
+        n_groups = 1
+    lj = w.lj_elec_xyz
+    return MDSetup(site_mass=mass, site_sigma=np.full(w.n_site, SITE_SIGMA), site_eps=np.full(w.n_site, SITE_EPS),
+                   lj_elec_xyz=np.ascontiguousarray(lj), carbon_sigma=CARBON_SIGMA, carbon_eps=CARBON_EPS,
+                   lj_cut=LJ_CUT, mol_size=sizes, mol_group=groups, n_groups=n_groups, bond=BOND, dt=MD_DT,
+                   temperature=MD_TEMPERATURE, tau=MD_TAU, charge_every=MD_CHARGE_EVERY)
