@@ -454,6 +454,48 @@ def three_layer_form(torch, n_frames=4096, n_dv=32, reps=3):
                 fp64_per_kernel=kern)
 
 
+def md_form(torch, steps=500, warmup=50):
+    """The constant-potential MD loop (velocity Verlet 2 fs, Nose-Hoover 400 K,
+    rigid cations, Lennard-Jones, charges every fifth step) on the paper cell
+    in finite-field, doubled-cell and slab geometry: MD steps/s and simulated
+    ns per day; the doubled cell counts twice (two independent cells, as the
+    paper counts its cost)."""
+    from paper_2201_12963_amd import MDLoop
+    from workloads import make_workload, md_setup
+    out = {}
+    for geo in ("ff", "dc", "slab"):
+        w = make_workload("paper", geo)
+        setup = md_setup(w)
+        ctx, stream = make_ctx(torch, w)
+        mdl = MDLoop(ctx, setup)
+        rng = np.random.default_rng(17)
+        v0 = rng.normal(0.0, 1.0, (3, w.n_site)) * np.sqrt(0.0083144626 * setup.temperature / setup.site_mass)
+        x = torch.tensor(w.site_xyz, dtype=torch.float64, device="cuda")
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        q = torch.empty(w.n_elec, dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(stream):
+            mdl.run(x, v, w.dv, warmup, q_out=q, thermo=False)
+        stream.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            mdl.run(x, v, w.dv, steps, q_out=q, thermo=False)
+            b.record(stream)
+        stream.synchronize()
+        if ctx.sync_status() != 0:
+            raise RuntimeError("kernel status flag raised during the MD loop")
+        ms = a.elapsed_time(b) / steps
+        per_cell = 2.0 if geo == "dc" else 1.0
+        out[geo] = dict(steps_per_s=1000.0 / ms, us_per_step=ms * 1e3,
+                        ns_per_day=per_cell * 1000.0 / ms * setup.dt * 1e-3 * 86400.0)
+        mdl.close()
+        ctx.close()
+    return dict(workload="paper-shaped cell, 320 ion pairs (640 in the doubled cell), rigid 3-site cations, "
+                         "Lennard-Jones with all three graphene sheets (synthetic parameters), 2 fs steps, "
+                         "charges every 5 steps", **out)
+
+
 def gradient_form(torch, reps=50):
     from workloads import make_workload
     w = make_workload("large", "ff")
@@ -482,7 +524,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--only", choices=("precision", "batched", "gradient", "three_layer"),
+    ap.add_argument("--only", choices=("precision", "batched", "gradient", "three_layer", "md"),
                     help="run only this form and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -495,7 +537,7 @@ def main():
 
     if args.only:
         form = {"precision": lambda t: precision_form(t)[0], "batched": batched_form,
-                "gradient": gradient_form, "three_layer": three_layer_form}[args.only]
+                "gradient": gradient_form, "three_layer": three_layer_form, "md": md_form}[args.only]
         print(json.dumps({args.only: form(torch)}), flush=True)
         return
 
@@ -540,6 +582,7 @@ def main():
             "gradient": gradient_form(torch),
             "geometries": geometry_form(torch, line["config"]["finite_field_steps_per_s"], line["value"]),
             "three_layer": three_layer_form(torch),
+            "md": md_form(torch),
         }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wd, trajd, parity=precision_state)

@@ -195,6 +195,65 @@ int cpm_profile(cpm_ctx* ctx, int n_frames, const double* site_xyz, const double
 int cpm_profile_noalloc(cpm_ctx* ctx, int n_frames, const double* site_xyz, const double* q, long long q_stride,
                         double dv, int n_bins, double bulk_lo, double bulk_hi, double* rho_out, double* psi_out);
 
+/* ---------------------------------------------------------------- MD loop
+ * The constant-potential MD loop of the paper's simulations (appendix,
+ * force-field and production paragraphs): velocity Verlet, a Nose-Hoover
+ * thermostat on the electrolyte (one per group; the doubled cell uses one
+ * per sub-cell), rigid three-site molecules held by SHAKE and RATTLE,
+ * Lennard-Jones site-site (different molecules) and site-graphene
+ * interactions cut at lj_cut with the energy shifted to zero there
+ * (Lorentz-Berthelot), and the Coulomb forces of this context with the
+ * electrode charges re-solved every charge_every steps (between updates the
+ * forces use the last charges).  Units: nm, ps, amu, kJ/mol.  Per step:
+ *   thermostat half step; v += dt/2 F/m; x += dt v; SHAKE; v = dx/dt;
+ *   F = F_LJ + F_Coulomb; v += dt/2 F/m; RATTLE; thermostat half step,
+ * the thermostat half step being xi += dt/4 (K2 - N_f kT)/Q; eta += dt/2 xi;
+ * v *= exp(-xi dt/2); xi += dt/4 (K2' - N_f kT)/Q with K2 = sum m v^2,
+ * N_f = 3 sites - 3 per rigid molecule, Q = N_f kT tau^2. */
+typedef struct cpm_md cpm_md;
+typedef struct {
+  int n_mol;                  /* molecules, in site order */
+  const int* mol_size;        /* host [n_mol]: 3 (rigid: sides bond, bond, bond sqrt 3 from the first site) or 1 */
+  const int* mol_group;       /* host [n_mol]: thermostat group, 0 .. n_groups-1 */
+  int n_groups;               /* 1 or 2 */
+  const double* site_mass;    /* host [n_site] amu */
+  const double* site_sigma;   /* host [n_site] nm */
+  const double* site_eps;     /* host [n_site] kJ/mol */
+  int n_lj_elec;              /* graphene atoms taking part in the Lennard-Jones sums (fixed) */
+  const double* lj_elec_xyz;  /* host [3][n_lj_elec] */
+  double carbon_sigma, carbon_eps;
+  double lj_cut;              /* nm, below half the smallest box length */
+  double bond;                /* nm */
+  double dt;                  /* ps */
+  double temperature;         /* K */
+  double tau;                 /* ps, thermostat time constant */
+  int charge_every;           /* charge update every this many steps */
+} cpm_md_desc;
+
+/* MD loop on a built FP64 context (which it uses for the Coulomb forces and
+ * must not be destroyed first).  Copies the tables; CPM_EINVAL for a bad
+ * table, CPM_ESTATE before cpm_build_elastance. */
+int cpm_md_create(cpm_ctx* ctx, const cpm_md_desc* desc, cpm_md** out);
+
+/* n_steps steps from the state in x and v (device [3][n_site], updated in
+ * place).  The first call makes v normal to the constraints and evaluates
+ * the forces with a charge solve; later calls continue from the forces,
+ * charges and thermostat state the loop holds (so x and v must be the last
+ * call's).  q_out (device [n_elec] or NULL): the charges of the last update;
+ * thermo_out (device [n_steps][4] or NULL): per step the kinetic energy, the
+ * Lennard-Jones energy, E_cp of the last charge update and the thermostat's
+ * energy sum_g (Q xi^2/2 + N_f kT eta) (kJ/mol).  Asynchronous. */
+int cpm_md_run(cpm_md* md, double* x, double* v, double dv, int n_steps, double* q_out, double* thermo_out);
+
+/* Thermostat variables (host [n_groups] each, nullable) and the step count;
+ * synchronises. */
+int cpm_md_state(cpm_md* md, double* xi_host, double* eta_host, long long* step_host);
+
+/* Switch the thermostat off (0: constant energy) or on (default). */
+int cpm_md_set_thermostat(cpm_md* md, int on);
+
+void cpm_md_destroy(cpm_md* md);
+
 /* Copies of internal matrices for tests and checkpoints (synchronises):
  * which = 0: A, 1: S (projected inverse), 2: S c (n_elec values).
  * host_out holds n_elec*n_elec (or n_elec) doubles. */

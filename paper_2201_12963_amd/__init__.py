@@ -5,6 +5,6 @@ Python side: `binding.Context` wraps the C-ABI library (libcpm.so, built by
 """
 
 from .binding import (  # noqa: F401
-    Context, CpmError, load_library,
+    Context, CpmError, MDLoop, load_library,
     FINITE_FIELD, DOUBLED_CELL, SLAB, KSPACE_EWALD, KSPACE_PPPM, FP64, MIXED,
 )

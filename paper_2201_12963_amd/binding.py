@@ -34,7 +34,26 @@ _STATUS_NAMES = {0: "CPM_OK", -1: "CPM_EINVAL", -2: "CPM_ESTATE", -3: "CPM_ENOTS
 
 EXPORTED = ("cpm_create", "cpm_set_stream", "cpm_build_elastance", "cpm_solve", "cpm_solve_batch",
             "cpm_grad", "cpm_get_matrix", "cpm_set_matrix", "cpm_get_buffer", "cpm_sync_status",
-            "cpm_last_error", "cpm_destroy", "cpm_replay_kernel", "cpm_profile", "cpm_profile_noalloc")
+            "cpm_last_error", "cpm_destroy", "cpm_replay_kernel", "cpm_profile", "cpm_profile_noalloc",
+            "cpm_md_create", "cpm_md_run", "cpm_md_state", "cpm_md_set_thermostat", "cpm_md_destroy")
+
+
+class MDDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_mol", ctypes.c_int),
+        ("mol_size", ctypes.POINTER(ctypes.c_int)),
+        ("mol_group", ctypes.POINTER(ctypes.c_int)),
+        ("n_groups", ctypes.c_int),
+        ("site_mass", ctypes.POINTER(ctypes.c_double)),
+        ("site_sigma", ctypes.POINTER(ctypes.c_double)),
+        ("site_eps", ctypes.POINTER(ctypes.c_double)),
+        ("n_lj_elec", ctypes.c_int),
+        ("lj_elec_xyz", ctypes.POINTER(ctypes.c_double)),
+        ("carbon_sigma", ctypes.c_double), ("carbon_eps", ctypes.c_double),
+        ("lj_cut", ctypes.c_double), ("bond", ctypes.c_double), ("dt", ctypes.c_double),
+        ("temperature", ctypes.c_double), ("tau", ctypes.c_double),
+        ("charge_every", ctypes.c_int),
+    ]
 
 
 class CpmError(RuntimeError):
@@ -95,6 +114,16 @@ def load_library():
     lib.cpm_profile.restype = ip
     lib.cpm_profile_noalloc.argtypes = lib.cpm_profile.argtypes
     lib.cpm_profile_noalloc.restype = ip
+    lib.cpm_md_create.argtypes = [vp, ctypes.POINTER(MDDesc), ctypes.POINTER(vp)]
+    lib.cpm_md_create.restype = ip
+    lib.cpm_md_run.argtypes = [vp, vp, vp, ctypes.c_double, ip, vp, vp]
+    lib.cpm_md_run.restype = ip
+    lib.cpm_md_state.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.cpm_md_state.restype = ip
+    lib.cpm_md_set_thermostat.argtypes = [vp, ip]
+    lib.cpm_md_set_thermostat.restype = ip
+    lib.cpm_md_destroy.argtypes = [vp]
+    lib.cpm_md_destroy.restype = None
     lib.cpm_replay_kernel.argtypes = [vp, ip, ip]
     lib.cpm_replay_kernel.restype = ip
     lib.cpm_sync_status.argtypes = [vp]
@@ -174,7 +203,7 @@ class Context:
         if r != CPM_OK:
             raise CpmError(r, self._lib.cpm_last_error(self._ctx).decode())
 
-    def _call(self, fn, *args):
+    def _call(self, fn, *args, handle=None):
         """Run one library call with its stream ordered against the caller's.
 
         Inputs and outputs are tensors made or last touched on the caller's
@@ -187,7 +216,7 @@ class Context:
         other = cur.cuda_stream != self.stream.cuda_stream
         if other:
             self.stream.wait_stream(cur)
-        r = fn(self._ctx, *args)
+        r = fn(self._ctx if handle is None else handle, *args)
         if other:
             cur.wait_stream(self.stream)
         self._check(r)
@@ -286,6 +315,71 @@ class Context:
         if self._ctx:
             self._lib.cpm_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MDLoop:
+    """The constant-potential MD loop on a built Context (wraps cpm_md)."""
+
+    def __init__(self, ctx: Context, setup):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        self._md = ctypes.c_void_p()
+        self.n_groups = int(setup.n_groups)
+        keep = [np.ascontiguousarray(setup.mol_size, dtype=np.int32),
+                np.ascontiguousarray(setup.mol_group, dtype=np.int32),
+                np.ascontiguousarray(setup.site_mass, dtype=np.float64),
+                np.ascontiguousarray(setup.site_sigma, dtype=np.float64),
+                np.ascontiguousarray(setup.site_eps, dtype=np.float64),
+                np.ascontiguousarray(setup.lj_elec_xyz, dtype=np.float64)]
+        self._keep = keep
+        d = MDDesc()
+        d.n_mol = keep[0].size
+        d.mol_size = keep[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.mol_group = keep[1].ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.n_groups = self.n_groups
+        d.site_mass = keep[2].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.site_sigma = keep[3].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.site_eps = keep[4].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.n_lj_elec = keep[5].shape[1]
+        d.lj_elec_xyz = keep[5].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.carbon_sigma, d.carbon_eps = float(setup.carbon_sigma), float(setup.carbon_eps)
+        d.lj_cut, d.bond, d.dt = float(setup.lj_cut), float(setup.bond), float(setup.dt)
+        d.temperature, d.tau, d.charge_every = float(setup.temperature), float(setup.tau), int(setup.charge_every)
+        ctx._check(self._lib.cpm_md_create(ctx._ctx, ctypes.byref(d), ctypes.byref(self._md)))
+
+    def run(self, x: torch.Tensor, v: torch.Tensor, dv: float, n_steps: int, q_out=None, thermo=True):
+        """n_steps steps; x and v (device [3][n_site]) are updated in place.
+        Returns (q, thermo [n_steps][4] or None)."""
+        dev = x.device
+        if q_out is None:
+            q_out = torch.empty(self.ctx.n_elec, dtype=torch.float64, device=dev)
+        th = torch.empty((n_steps, 4), dtype=torch.float64, device=dev) if thermo and n_steps > 0 else None
+        self.ctx._call(self._lib.cpm_md_run, _ptr(x), _ptr(v), float(dv), int(n_steps), _ptr(q_out), _ptr(th),
+                       handle=self._md)
+        return q_out, th
+
+    def set_thermostat(self, on: bool):
+        self._lib.cpm_md_set_thermostat(self._md, 1 if on else 0)
+
+    def state(self):
+        xi = np.zeros(self.n_groups)
+        eta = np.zeros(self.n_groups)
+        step = ctypes.c_longlong()
+        self.ctx._check(self._lib.cpm_md_state(self._md, xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               ctypes.byref(step)))
+        return xi, eta, int(step.value)
+
+    def close(self):
+        if self._md:
+            self._lib.cpm_md_destroy(self._md)
+            self._md = ctypes.c_void_p()
 
     def __del__(self):
         try:

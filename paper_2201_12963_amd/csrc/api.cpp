@@ -12,6 +12,7 @@
 #include <cstring>
 #include <functional>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -67,6 +68,8 @@ struct cpm_ctx {
   int n_items = 0;
   int *d_item_c = nullptr, *d_item_lo = nullptr, *d_item_hi = nullptr;
   float* d_Sf = nullptr;
+  double* d_colsum = nullptr;              // [2][n_elec] column sums of d_Sf per neutrality group (mixed)
+  double inv_n0 = 0.0, inv_n1 = 0.0;       // 1 / atoms per group
   unsigned short *d_Ssplit = nullptr, *d_bsplit = nullptr;   // three bf16 terms each
   unsigned char* d_sub1 = nullptr;
   int n_pad = 0;
@@ -128,6 +131,18 @@ struct cpm_ctx {
   // ---- graphs
   std::vector<GraphEntry> graphs;
   unsigned long long tick = 0;
+};
+
+struct cpm_md {
+  cpm_ctx* c = nullptr;
+  MDArgs a{};
+  int charge_every = 5;
+  long long step = 0;
+  bool started = false;
+  double* d_q = nullptr;       // electrode charges of the last update
+  double* d_fc = nullptr;      // Coulomb forces (eV/nm)
+  double* d_energy = nullptr;  // {U_coul, E_cp} of the last update
+  std::vector<void*> allocs;
 };
 
 namespace {
@@ -639,11 +654,11 @@ int enqueue_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, doubl
   const bool need_forces = f_out || e_out;
   TRY(enqueue_b<T>(c, 1, xyz, need_forces));
   if (std::is_same<T, float>::value) {
-    // FP32 GEMV on centred b, FP64 re-projection, then q = Q0 + dV S c
+    // FP32-stored S, FP64 products, neutrality by the precomputed column
+    // sums: one launch, half the bytes of the FP64 GEMV
     rec(c, CPM_KERNEL_CHARGES, s, [=](hipStream_t s) {
-      launch_charges_f32(s, 1, c->n_elec, c->d_Sf, c->d_b, c->d_Q0);
-      launch_reproject(s, 1, c->n_elec, c->d_sub1, c->d_Q0);
-      launch_axpy(s, c->n_elec, c->d_Q0, c->d_Sc, dv, q_out, c->d_epos, c->d_qs);
+      launch_charges_mixed(s, 1, c->n_elec, c->d_Sf, c->d_colsum, c->d_sub1, c->inv_n0, c->inv_n1, c->d_b, c->d_Sc,
+                           dv, c->d_Q0, q_out, c->d_epos, c->d_qs);
     });
   } else {
     rec(c, CPM_KERNEL_CHARGES, s, [=](hipStream_t s) {
@@ -1088,9 +1103,14 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     return bad(r);
   c->n_pad = (ne + 31) / 32 * 32;          // rows of the bf16 split operands: whole 32-deep MFMA slabs
   if (c->precision == CPM_MIXED) {
-    if (ne > 4096) { fail(c, CPM_EINVAL, "mixed precision supports up to 4096 electrode atoms"); return bad(CPM_EINVAL); }
-    if ((r = dalloc(c, &c->d_Sf, (size_t)ne * ne)) || (r = dalloc(c, &c->d_Ssplit, (size_t)3 * ne * c->n_pad)))
+    if ((r = dalloc(c, &c->d_Sf, (size_t)ne * ne)) || (r = dalloc(c, &c->d_Ssplit, (size_t)3 * ne * c->n_pad)) ||
+        (r = dalloc(c, &c->d_colsum, (size_t)2 * ne)))
       return bad(r);
+    int n1 = 0;
+    if (c->geometry == CPM_DOUBLED_CELL)
+      for (int i = 0; i < ne; ++i) n1 += c->sub[i] != 0;
+    c->inv_n0 = 1.0 / (ne - n1);
+    c->inv_n1 = n1 > 0 ? 1.0 / n1 : 0.0;
   }
   if (c->geometry == CPM_DOUBLED_CELL && (r = upload(c, &c->d_sub1, c->sub))) return bad(r);
   if (hipMemset(c->d_status, 0, 4 * sizeof(int)) != hipSuccess) { fail(c, CPM_EDEVICE, "memset"); return bad(CPM_EDEVICE); }
@@ -1293,7 +1313,10 @@ int cpm_build_elastance(cpm_ctx* c) {
   }
   launch_matvec(s, n, c->d_S, c->d_c, c->d_Sc);            // S c
   launch_permute(s, 1, n, c->d_epos, c->d_Sc, c->d_Sc_s);
-  if (c->precision == CPM_MIXED) launch_split_matrix(s, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
+  if (c->precision == CPM_MIXED) {
+    launch_split_matrix(s, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
+    launch_colsum(s, n, c->d_Sf, c->d_sub1, c->d_colsum);
+  }
   TRY(check_launch(c));
   HIP_TRY(c, hipStreamSynchronize(s));
   TRY(slab_zsc(c));
@@ -1314,7 +1337,10 @@ int cpm_set_matrix(cpm_ctx* c, const double* host_S) {
   HIP_TRY(c, hipMemcpy(c->d_S, host_S, (size_t)n * n * sizeof(double), hipMemcpyHostToDevice));
   launch_matvec(c->stream, n, c->d_S, c->d_c, c->d_Sc);
   launch_permute(c->stream, 1, n, c->d_epos, c->d_Sc, c->d_Sc_s);
-  if (c->precision == CPM_MIXED) launch_split_matrix(c->stream, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
+  if (c->precision == CPM_MIXED) {
+    launch_split_matrix(c->stream, n, c->n_pad, c->d_S, c->d_Sf, c->d_Ssplit);
+    launch_colsum(c->stream, n, c->d_Sf, c->d_sub1, c->d_colsum);
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   TRY(slab_zsc(c));
   c->built = true;
@@ -1501,6 +1527,149 @@ int cpm_profile_noalloc(cpm_ctx* c, int n_frames, const double* site_xyz, const 
   p.part = c->d_prof_static;
   launch_profile(c->stream, p);
   return check_launch(c);
+}
+
+int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
+  if (out) *out = nullptr;
+  if (!c || !d || !out) return CPM_EINVAL;
+  if (!c->built) return fail(c, CPM_ESTATE, "cpm_md_create before cpm_build_elastance");
+  if (c->precision != CPM_FP64) return fail(c, CPM_EINVAL, "the MD loop runs the FP64 path");
+  if (d->n_mol < 1 || !d->mol_size || !d->mol_group || !d->site_mass || !d->site_sigma || !d->site_eps)
+    return fail(c, CPM_EINVAL, "bad molecule or site tables");
+  if (d->n_groups < 1 || d->n_groups > MD_MAX_GROUPS) return fail(c, CPM_EINVAL, "n_groups must be 1..%d", MD_MAX_GROUPS);
+  if (d->n_lj_elec < 0 || (d->n_lj_elec > 0 && !d->lj_elec_xyz)) return fail(c, CPM_EINVAL, "bad graphene atoms");
+  if (!(d->dt > 0) || !(d->temperature > 0) || !(d->tau > 0) || !(d->lj_cut > 0) || !(d->bond > 0) ||
+      d->charge_every < 1)
+    return fail(c, CPM_EINVAL, "dt, temperature, tau, lj_cut, bond and charge_every must be positive");
+  if (2.0 * d->lj_cut > std::min(c->box[0], std::min(c->box[1], c->box[2])))
+    return fail(c, CPM_EINVAL, "the Lennard-Jones cutoff must be below half the smallest box length");
+  const int ns = c->n_site;
+  std::vector<int> start(d->n_mol), mol_of(ns);
+  std::vector<double> nsite_g(d->n_groups, 0.0), ncon_g(d->n_groups, 0.0);
+  int at = 0;
+  for (int m = 0; m < d->n_mol; ++m) {
+    const int k = d->mol_size[m], g = d->mol_group[m];
+    if (k != 1 && k != 3) return fail(c, CPM_EINVAL, "molecules have 1 or 3 sites");
+    if (g < 0 || g >= d->n_groups) return fail(c, CPM_EINVAL, "molecule %d: group out of range", m);
+    if (at + k > ns) return fail(c, CPM_EINVAL, "molecules hold more sites than the context");
+    start[m] = at;
+    for (int t = 0; t < k; ++t) {
+      if (!(d->site_mass[at + t] > 0)) return fail(c, CPM_EINVAL, "site masses must be positive");
+      mol_of[at + t] = m;
+    }
+    nsite_g[g] += k;
+    ncon_g[g] += k == 3 ? 3 : 0;
+    at += k;
+  }
+  if (at != ns) return fail(c, CPM_EINVAL, "molecules hold %d sites, the context %d", at, ns);
+  cpm_md* md = new cpm_md();
+  md->c = c;
+  md->charge_every = d->charge_every;
+  auto bad = [&](int code) {
+    for (void* p : md->allocs) hipFree(p);
+    delete md;
+    return code;
+  };
+  auto up = [&](auto** p, const auto* h, size_t n) -> int {
+    using T = std::remove_const_t<std::remove_pointer_t<decltype(h)>>;
+    T* q = nullptr;
+    if (hipMalloc((void**)&q, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess)
+      return fail(c, CPM_ENOMEM, "hipMalloc failed");
+    md->allocs.push_back(q);
+    if (n && h && hipMemcpy(q, h, n * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(c, CPM_EDEVICE, "upload failed");
+    *p = q;
+    return CPM_OK;
+  };
+  MDArgs& a = md->a;
+  a.n_site = ns; a.n_mol = d->n_mol; a.n_groups = d->n_groups; a.n_lj_elec = d->n_lj_elec; a.thermostat = 1;
+  a.carbon_sigma = d->carbon_sigma; a.carbon_eps = d->carbon_eps; a.lj_cut = d->lj_cut; a.bond = d->bond;
+  a.dt = d->dt; a.kt = 0.0083144626 * d->temperature;
+  for (int k = 0; k < 3; ++k) { a.box[k] = c->box[k]; a.inv_box[k] = 1.0 / c->box[k]; }
+  for (int g = 0; g < d->n_groups; ++g) {
+    a.nf[g] = 3.0 * nsite_g[g] - ncon_g[g];
+    a.Q[g] = a.nf[g] * a.kt * d->tau * d->tau;
+  }
+  const double* mass_c; const double* sig_c; const double* eps_c; const int *ms, *mz, *mg, *mo; const double* cx;
+  double *f_lj, *u_lj, *xi, *eta, *q, *fc, *en;
+  int r;
+  std::vector<double> zeros(2 * MD_MAX_GROUPS, 0.0);
+  std::vector<int> sizes(d->mol_size, d->mol_size + d->n_mol), groups(d->mol_group, d->mol_group + d->n_mol);
+  if ((r = up(&mass_c, d->site_mass, ns)) || (r = up(&sig_c, d->site_sigma, ns)) || (r = up(&eps_c, d->site_eps, ns)) ||
+      (r = up(&ms, start.data(), d->n_mol)) || (r = up(&mz, sizes.data(), d->n_mol)) ||
+      (r = up(&mg, groups.data(), d->n_mol)) || (r = up(&mo, mol_of.data(), ns)) ||
+      (r = up(&cx, d->lj_elec_xyz, 3 * (size_t)d->n_lj_elec)) || (r = up(&f_lj, (const double*)nullptr, 3 * (size_t)ns)) ||
+      (r = up(&u_lj, (const double*)nullptr, ns)) || (r = up(&xi, zeros.data(), MD_MAX_GROUPS)) ||
+      (r = up(&eta, zeros.data(), MD_MAX_GROUPS)) || (r = up(&q, (const double*)nullptr, c->n_elec)) ||
+      (r = up(&fc, (const double*)nullptr, 3 * (size_t)ns)) || (r = up(&en, zeros.data(), 2)))
+    return bad(r);
+  a.mass = mass_c; a.sigma = sig_c; a.eps = eps_c; a.mol_start = ms; a.mol_size = mz; a.mol_group = mg; a.mol_of = mo;
+  a.cx = cx; a.f_lj = f_lj; a.u_lj = u_lj; a.xi = xi; a.eta = eta; a.f_c = fc; a.energy = en;
+  md->d_q = q; md->d_fc = fc; md->d_energy = en;
+  *out = md;
+  return CPM_OK;
+}
+
+namespace {
+
+// forces at the current positions: Lennard-Jones, and the Coulomb forces
+// with a charge solve (update) or at the charges of the last update
+int md_forces(cpm_md* md, double* x, double dv, bool update) {
+  cpm_ctx* c = md->c;
+  launch_lj(c->stream, md->a);
+  if (update) return enqueue_solve<double>(c, x, dv, md->d_q, md->d_fc, md->d_energy);
+  return enqueue_forces_at<double>(c, x, dv, md->d_q, md->d_fc);
+}
+
+}  // namespace
+
+int cpm_md_run(cpm_md* md, double* x, double* v, double dv, int n_steps, double* q_out, double* thermo_out) {
+  if (!md) return CPM_EINVAL;
+  cpm_ctx* c = md->c;
+  if (!x || !v || n_steps < 0) return fail(c, CPM_EINVAL, "bad MD run arguments");
+  if (!std::isfinite(dv)) return fail(c, CPM_ENONFINITE, "non-finite dV");
+  MDArgs& a = md->a;
+  a.x = x; a.v = v; a.thermo_out = nullptr;
+  hipStream_t s = c->stream;
+  if (!md->started) {
+    // velocities normal to the constraints, forces with fresh charges
+    launch_md_integrate(s, a, 4, 0);
+    TRY(md_forces(md, x, dv, true));
+    md->started = true;
+  }
+  a.thermo_out = thermo_out;
+  for (int i = 0; i < n_steps; ++i) {
+    // end of the previous step (from the second step of this call on), start of this one
+    launch_md_integrate(s, a, i == 0 ? 2 : 3, i - 1);
+    ++md->step;
+    TRY(md_forces(md, x, dv, md->step % md->charge_every == 0));
+  }
+  if (n_steps > 0) launch_md_integrate(s, a, 1, n_steps - 1);
+  if (q_out) HIP_TRY(c, hipMemcpyAsync(q_out, md->d_q, c->n_elec * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return check_launch(c);
+}
+
+int cpm_md_state(cpm_md* md, double* xi_host, double* eta_host, long long* step_host) {
+  if (!md) return CPM_EINVAL;
+  cpm_ctx* c = md->c;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (xi_host) HIP_TRY(c, hipMemcpy(xi_host, md->a.xi, md->a.n_groups * sizeof(double), hipMemcpyDeviceToHost));
+  if (eta_host) HIP_TRY(c, hipMemcpy(eta_host, md->a.eta, md->a.n_groups * sizeof(double), hipMemcpyDeviceToHost));
+  if (step_host) *step_host = md->step;
+  return CPM_OK;
+}
+
+int cpm_md_set_thermostat(cpm_md* md, int on) {
+  if (!md) return CPM_EINVAL;
+  md->a.thermostat = on ? 1 : 0;
+  return CPM_OK;
+}
+
+void cpm_md_destroy(cpm_md* md) {
+  if (!md) return;
+  if (md->c && md->c->stream) hipStreamSynchronize(md->c->stream);
+  for (void* p : md->allocs) hipFree(p);
+  delete md;
 }
 
 int cpm_get_matrix(cpm_ctx* c, int which, double* host_out) {

@@ -517,12 +517,16 @@ void launch_grad_finish(hipStream_t s, int n, const double* q, const double* t, 
 // mixed precision (k_mixed.hip)
 void launch_split_matrix(hipStream_t s, int n, int n_pad, const double* S, float* Sf, unsigned short* split);
 void launch_split_b(hipStream_t s, int n_frames, int n, int n_pad, const double* b, unsigned short* split);
-void launch_charges_f32(hipStream_t s, int n_frames, int n, const float* Sf, const double* b, double* Q0);
+// column sums of Sf over the neutrality groups, colsum [2][n] (FP64)
+void launch_colsum(hipStream_t s, int n, const float* Sf, const unsigned char* sub1, double* colsum);
+// one-frame mixed charges: q = Sf b - (colsum_g . b)/n_g + dV S c, FP64 products
+void launch_charges_mixed(hipStream_t s, int n_frames, int n, const float* Sf, const double* colsum,
+                          const unsigned char* sub1, double inv_n0, double inv_n1, const double* b, const double* Sc,
+                          double dv, double* Q0, double* q, const int* epos, double* qs);
 void launch_reproject(hipStream_t s, int n_frames, int n, const unsigned char* sub1, double* Q0);
 void launch_gemm_bf16x6(hipStream_t s, int M, int N, int K, const unsigned short* A, size_t a_plane,
                         const unsigned short* B, size_t b_plane, double* D, int ldd);
-void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out,
-                 const int* epos = nullptr, double* out_s = nullptr);
+
 
 // ------------------------------------------- potential profile (k_profile.hip)
 
@@ -555,5 +559,32 @@ int profile_static_scratch(int device, double** out);
 size_t profile_partial_lds(int n_bins, int n_heights);
 size_t profile_solve_lds(int n_bins, int n_heights);
 void launch_profile(hipStream_t s, const ProfileArgs& p);
+
+// ----------------------------------------------------- MD loop (k_md.hip)
+
+constexpr int MD_THREADS = 1024;      // the integrator's one workgroup
+constexpr int MD_MAX_GROUPS = 2;      // thermostat groups (doubled cell: one per sub-cell)
+constexpr int MD_MAX_ITER = 500;      // SHAKE / RATTLE sweeps
+constexpr double MD_TOL = 1e-13;      // relative constraint tolerance
+constexpr int MD_THERMO = 4;          // per-step record: KE, U_LJ, E_cp (last update), thermostat energy (kJ/mol)
+
+struct MDArgs {
+  int n_site, n_mol, n_groups, n_lj_elec, thermostat;
+  double* x; double* v;                 // [3][n_site] positions (nm), velocities (nm/ps)
+  double* f_lj;                         // [3][n_site] kJ/mol/nm (written by k_lj)
+  const double* f_c;                    // [3][n_site] Coulomb force, eV/nm
+  double* u_lj;                         // [n_site] Lennard-Jones energy share per site (written by k_lj)
+  const double* mass; const double* sigma; const double* eps;   // [n_site]
+  const int* mol_start; const int* mol_size; const int* mol_group; const int* mol_of;
+  const double* cx;                     // [3][n_lj_elec] graphene atoms
+  double carbon_sigma, carbon_eps, lj_cut, bond, dt, kt;
+  double box[3], inv_box[3];
+  double nf[MD_MAX_GROUPS], Q[MD_MAX_GROUPS];
+  double* xi; double* eta;              // [n_groups] thermostat state (device)
+  const double* energy;                 // [2] the last charge update's {U_coul, E_cp} (eV)
+  double* thermo_out;                   // [step][MD_THERMO] or nullptr
+};
+void launch_lj(hipStream_t s, const MDArgs& a);
+void launch_md_integrate(hipStream_t s, const MDArgs& a, int mode, int rec_step);
 
 }  // namespace cpm
