@@ -7,7 +7,7 @@ per-step kinetic and Lennard-Jones energies, and at the end positions,
 velocities, charges and the thermostat variables.  Cases: the paper-shaped
 cell in finite field (rigid 3-site cations, PPPM) and doubled cell (two
 thermostats), and the tiny cell with explicit Ewald (single-site ions, a
-0.7 nm Lennard-Jones cutoff that its 1.476 nm box allows).
+0.6 nm Lennard-Jones cutoff that its 1.278 nm side allows).
 """
 
 import sys
@@ -43,8 +43,8 @@ def test_md_loop_parity(torch_dev, name, geometry, n_steps):
     import dataclasses
     w, A, S = built(name, geometry)
     setup = md_setup(w)
-    if name == "tiny":      # a 1.476 nm box holds a minimum-image cutoff of at most 0.738 nm
-        setup = dataclasses.replace(setup, lj_cut=0.7)
+    if name == "tiny":      # its 1.278 nm side holds a minimum-image cutoff of at most 0.639 nm
+        setup = dataclasses.replace(setup, lj_cut=0.6)
     v0 = np.random.default_rng(17).normal(0.0, 1.0, (3, w.n_site)) * np.sqrt(md.KB * setup.temperature /
                                                                              setup.site_mass)
     method = "pppm" if w.kspace == "pppm" else "ewald"
