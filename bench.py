@@ -371,8 +371,11 @@ def batched_form(torch, n_frames=4096, n_dv=32, reps=3):
         stream.synchronize()
         ms = a.elapsed_time(b) / reps
         from paper_2201_12963_amd.binding import BUF_BATCH_CHUNK
+        tuned = ctx.get_buffer(BUF_BATCH_CHUNK)
         out[label] = dict(frames_per_s=n_frames * n_dv / (ms * 1e-3), ms_per_batch=ms,
-                          frames_per_launch=int(ctx.get_buffer(BUF_BATCH_CHUNK)[0]))
+                          frames_per_launch=int(tuned[0]),
+                          launch_shapes={"site_pair_tiles_per_cell": int(tuned[1]),
+                                         "xy_planes_per_workgroup": "as many as fit" if tuned[2] == 0 else int(tuned[2])})
         out[label + "_q"] = q[:, 7].cpu().numpy()
         # every kernel of the batch timed alone (the last launch of each, over
         # frames_per_launch frames)
@@ -389,6 +392,7 @@ def batched_form(torch, n_frames=4096, n_dv=32, reps=3):
                 mixed_frames_per_s=out["mixed"]["frames_per_s"], mixed_ms_per_batch=out["mixed"]["ms_per_batch"],
                 mixed_vs_fp64_q_max_err_e=dq,
                 frames_per_launch={"fp64": out["fp64"]["frames_per_launch"], "mixed": out["mixed"]["frames_per_launch"]},
+                launch_shapes={"fp64": out["fp64"]["launch_shapes"], "mixed": out["mixed"]["launch_shapes"]},
                 fp64_per_kernel=out["fp64_kernels"],
                 mixed_per_kernel=out["mixed_kernels"])
 

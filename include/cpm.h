@@ -142,12 +142,21 @@ int cpm_solve(cpm_ctx* ctx, const double* site_xyz, double dv,
  * are affine in dV, so each frame is solved once and the dV sweep is a
  * rank-one update.  Frames go through in launches of up to 4096: the first
  * call with at least 128 frames times launches of 64, 128, ... frames on its
- * own first frames and keeps the fastest size for the context (it
- * synchronises the stream once; setting CPM_BATCH_CHUNK in the environment
- * fixes the size and skips this).  CPM_ENOMEM if the scratch does not fit. */
+ * own first frames and keeps the fastest size for the context, then at that
+ * size times the site-pair tiles with 1, 2 and 4 workgroups per cell and the
+ * x-y passes with one plane or as many as fit per workgroup, and keeps the
+ * fastest of each (it synchronises the stream; setting CPM_BATCH_CHUNK in the
+ * environment fixes the size and skips all of it).  CPM_ENOMEM if the
+ * scratch does not fit. */
 int cpm_solve_batch(cpm_ctx* ctx, int n_frames, const double* site_xyz,
                     int n_dv, const double* dv_host,
                     double* q_out, double* f_out, double* energy_out);
+
+/* Fix the batch launch shapes instead of tuning them (for callers that tune
+ * themselves, and for tests): frames per launch (1..4096), site-pair tile
+ * workgroups per cell (1..64) and x-y planes per many-frame workgroup (0: as
+ * many as fit in LDS, 1: one).  CPM_EINVAL outside those ranges. */
+int cpm_set_batch_shape(cpm_ctx* ctx, int frames_per_launch, int tiles_per_cell, int xy_planes);
 
 /* Gradient of L = sum_i (q*_i - t_i)^2 + U_coul(R, q*(R)) by the adjoint:
  * lambda = S [2 (q* - t) + dV c]; dL/dR_j is minus the Coulomb force on
@@ -273,7 +282,8 @@ int cpm_set_matrix(cpm_ctx* ctx, const double* host_S);
  *   CPM_BUF_PHI_MESH  double [Kz][Ky][Kx] electrolyte potential mesh (V)
  *   CPM_BUF_FIELD_MESH double [3][Kz][Ky][Kx] field of all charges (V/nm)
  *   CPM_BUF_NCELL     int32 [3]  cells per axis
- *   CPM_BUF_BATCH_CHUNK int32 [1] frames per launch chosen for cpm_solve_batch (0: not yet) */
+ *   CPM_BUF_BATCH_CHUNK int32 [3] the batch tuner's choices: frames per launch (0: not tuned yet),
+ *                       site-pair tile workgroups per cell, x-y planes per workgroup (0: as many as fit) */
 enum {
   CPM_BUF_CELL_START = 0, CPM_BUF_SITE_ORDER = 1, CPM_BUF_PHI_REAL = 2, CPM_BUF_B = 3,
   CPM_BUF_RHO_MESH = 4, CPM_BUF_PHI_MESH = 5, CPM_BUF_FIELD_MESH = 6, CPM_BUF_NCELL = 7,

@@ -35,7 +35,8 @@ _STATUS_NAMES = {0: "CPM_OK", -1: "CPM_EINVAL", -2: "CPM_ESTATE", -3: "CPM_ENOTS
 EXPORTED = ("cpm_create", "cpm_set_stream", "cpm_build_elastance", "cpm_solve", "cpm_solve_batch",
             "cpm_grad", "cpm_get_matrix", "cpm_set_matrix", "cpm_get_buffer", "cpm_sync_status",
             "cpm_last_error", "cpm_destroy", "cpm_replay_kernel", "cpm_profile", "cpm_profile_noalloc",
-            "cpm_md_create", "cpm_md_run", "cpm_md_state", "cpm_md_set_thermostat", "cpm_md_destroy")
+            "cpm_md_create", "cpm_md_run", "cpm_md_state", "cpm_md_set_thermostat", "cpm_md_destroy",
+            "cpm_set_batch_shape")
 
 
 class MDDesc(ctypes.Structure):
@@ -124,6 +125,8 @@ def load_library():
     lib.cpm_md_set_thermostat.restype = ip
     lib.cpm_md_destroy.argtypes = [vp]
     lib.cpm_md_destroy.restype = None
+    lib.cpm_set_batch_shape.argtypes = [vp, ip, ip, ip]
+    lib.cpm_set_batch_shape.restype = ip
     lib.cpm_replay_kernel.argtypes = [vp, ip, ip]
     lib.cpm_replay_kernel.restype = ip
     lib.cpm_sync_status.argtypes = [vp]
@@ -251,6 +254,11 @@ class Context:
         self._call(self._lib.cpm_solve_batch, n_frames, _ptr(site_xyz), dv.size,
                    dv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(q_out), _ptr(f_out), _ptr(energy_out))
         return q_out, f_out, energy_out
+
+    def set_batch_shape(self, frames_per_launch: int, tiles_per_cell: int, xy_planes: int):
+        """Fix the batch launch shapes (skips the tuner)."""
+        self._check(self._lib.cpm_set_batch_shape(self._ctx, int(frames_per_launch), int(tiles_per_cell),
+                                                  int(xy_planes)))
 
     def grad(self, site_xyz: torch.Tensor, dv: float, q_target: torch.Tensor):
         dev = site_xyz.device

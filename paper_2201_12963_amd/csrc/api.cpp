@@ -88,6 +88,7 @@ struct cpm_ctx {
   double *d_g = nullptr, *d_qa = nullptr, *d_dv = nullptr;
   int cap_dv = 0;
   int batch_chunk = 0;                     // frames per batched launch chosen by the tuner (0: not yet)
+  int pair_tsplit = 1;                     // batched site-pair tiles: workgroups per cell (tuned)
   // k-space field mesh of the electrode charges S c alone (batched dV sweep)
   double* d_ESc = nullptr;
   float* d_EScf = nullptr;
@@ -564,7 +565,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
   PairArgs<T> pa{};
   // one frame: a wavefront per site (short chains, all in flight at once);
   // many frames: cell tiles
-  pa.tsplit = nf == 1 ? 0 : 1;
+  pa.tsplit = nf == 1 ? 0 : c->pair_tsplit;
   pa.n_blocks = c->n_site == 0 ? 0 : pa.tsplit > 0 ? c->cell.n_cells * pa.tsplit : (c->n_site + 3) / 4;
   pa.cell = c->cell;
   pa.st = st;
@@ -831,6 +832,43 @@ int tune_batch_chunk(cpm_ctx* c, int n_frames, Run run) {
     if (rc) break;
     const float per_frame = ms / (float)k;
     if (k == cand.front() || per_frame < best_t) { best_t = per_frame; best = k; }
+  }
+  // then the launch shapes at that size: site-pair tiles per cell and x-y
+  // planes per workgroup, each the fastest of its candidates with the other
+  // at its current setting
+  auto time_run = [&](int k, float& ms) -> int {
+    ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, CPM_EDEVICE, "hipEventRecord failed");
+      int r = run(k, 0);
+      if (r) return r;
+      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return fail(c, CPM_EDEVICE, "timing a launch shape failed");
+    }
+    return CPM_OK;
+  };
+  if (rc == CPM_OK) {
+    float t_best = 0.0f;
+    int ts_best = c->pair_tsplit;
+    for (int ts : {1, 2, 4}) {
+      c->pair_tsplit = ts;
+      float ms;
+      if ((rc = time_run(best, ms))) break;
+      if (ts == 1 || ms < t_best) { t_best = ms; ts_best = ts; }
+    }
+    c->pair_tsplit = ts_best;
+  }
+  if (rc == CPM_OK) {
+    float t_best = 0.0f;
+    int pl_best = 0;
+    for (int pl : {0, 1}) {
+      c->px.planes = pl;
+      float ms;
+      if ((rc = time_run(best, ms))) break;
+      if (pl == 0 || ms < t_best) { t_best = ms; pl_best = pl; }
+    }
+    c->px.planes = pl_best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1453,6 +1491,18 @@ int cpm_solve_batch(cpm_ctx* c, int n_frames, const double* xyz, int n_dv, const
   return check_launch(c);
 }
 
+int cpm_set_batch_shape(cpm_ctx* c, int frames_per_launch, int tiles_per_cell, int xy_planes) {
+  if (!c) return CPM_EINVAL;
+  if (frames_per_launch < 1 || frames_per_launch > BATCH_CHUNK_MAX)
+    return fail(c, CPM_EINVAL, "frames per launch must be 1..%d", BATCH_CHUNK_MAX);
+  if (tiles_per_cell < 1 || tiles_per_cell > TILE_TGT) return fail(c, CPM_EINVAL, "tiles per cell must be 1..%d", TILE_TGT);
+  if (xy_planes != 0 && xy_planes != 1) return fail(c, CPM_EINVAL, "x-y planes per workgroup must be 0 or 1");
+  c->batch_chunk = frames_per_launch;
+  c->pair_tsplit = tiles_per_cell;
+  c->px.planes = xy_planes;
+  return CPM_OK;
+}
+
 int cpm_grad(cpm_ctx* c, const double* xyz, double dv, const double* q_target, double* loss_out, double* dl_dxyz,
              double* dl_ddv, double* q_out) {
   if (!c) return CPM_EINVAL;
@@ -1704,8 +1754,11 @@ long long cpm_get_buffer(cpm_ctx* c, int which, void* host_out) {
       if (host_out) std::memcpy(host_out, c->cell.nc, 3 * sizeof(int));
       return 3;
     case CPM_BUF_BATCH_CHUNK:
-      if (host_out) std::memcpy(host_out, &c->batch_chunk, sizeof(int));
-      return 1;
+      if (host_out) {
+        const int v[3] = {c->batch_chunk, c->pair_tsplit, c->px.planes};
+        std::memcpy(host_out, v, sizeof(v));
+      }
+      return 3;
     default: return fail(c, CPM_EINVAL, "unknown buffer %d", which);
   }
   if (!host_out) return (long long)count;

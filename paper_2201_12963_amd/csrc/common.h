@@ -48,6 +48,7 @@ struct FFTPlan1D {     // mixed-radix Stockham plan for one axis
   int fac[MAX_FFT_FACTORS];
   const double2* tw;   // e^{-2 pi i t / n}, t = 0..n-1
   const float2* twf;
+  int planes;          // x plan only: most planes per many-frame x-y workgroup (0: as many as fit)
 };
 
 struct MeshInfo {

@@ -711,7 +711,8 @@ template <typename T, typename T2>
 void launch_xy_many(hipStream_t s, const FFTPlan1D& px, const FFTPlan1D& py, int Kz, int ny, int mode,
                     const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im, size_t out_re_stride, int split,
                     const T2* in_c2, T* out_re2) {
-  const int pl = xy_planes_fit<T2>(px, py);
+  int pl = xy_planes_fit<T2>(px, py);
+  if (px.planes > 0 && px.planes < pl) pl = 1;          // the tuner's choice (one plane, or as many as fit)
   auto* k = pl == 1 ? k_fft_xy<T, T2, false, 1> : k_fft_xy<T, T2, false, xy_planes_many<T2>()>;
   hipLaunchKernelGGL(k, dim3((Kz + pl - 1) / pl, ny), dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, pl), s, px, py, Kz,
                      mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, split, in_c2, out_re2);

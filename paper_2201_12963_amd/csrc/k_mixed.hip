@@ -50,17 +50,6 @@ __global__ __launch_bounds__(256) void k_split_matrix(int n, int n_pad, const do
   for (int k = 0; k < 3; ++k) split[k * plane + (size_t)row * n_pad + col] = t[k];
 }
 
-// out = x + a y (and its cell-sorted copy out_s[epos[i]], if given)
-__global__ __launch_bounds__(256) void k_axpy(int n, const double* __restrict__ x, const double* __restrict__ y,
-                                              double a, double* __restrict__ out, const int* __restrict__ epos,
-                                              double* __restrict__ out_s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    const double v = x[i] + a * y[i];
-    out[i] = v;
-    if (out_s) out_s[epos[i]] = v;
-  }
-}
 
 // mean-centred b of each frame, split into three bf16 terms, rows [frame][n_pad]
 // (term k at split[k * n_frames * n_pad + ...])
@@ -83,29 +72,79 @@ __global__ __launch_bounds__(256) void k_split_b(int n, int n_pad, const double*
   }
 }
 
-// Q0[f][i] = sum_j Sf[i][j] (b[f][j] - mean_f b), FP32 accumulation; one wavefront per row
-__global__ __launch_bounds__(256) void k_charges_f32(int n, const float* __restrict__ Sf, const double* __restrict__ b_all,
-                                                     double* __restrict__ Q0_all) {
-  __shared__ float bc[4096];
-  __shared__ double red[4];
+// Column sums of the FP32 copy of S over each neutrality group (group 1: the
+// first sub-cell of the doubled cell, group 0: the rest; one group for the
+// finite field and slab), in FP64: colsum[g][j] = sum_{i in g} Sf[i][j].
+// One thread per column (rows read in turn, coalesced across the columns).
+__global__ __launch_bounds__(256) void k_colsum(int n, const float* __restrict__ Sf,
+                                                const unsigned char* __restrict__ sub1, double* __restrict__ colsum) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double v = (double)Sf[(size_t)i * n + j];
+    if (sub1 && sub1[i]) s1 += v; else s0 += v;
+  }
+  colsum[j] = s0;
+  colsum[n + j] = s1;
+}
+
+// One-frame mixed charge step in one launch: q = Sf b - m_g + dV S c with S
+// stored in FP32 (half the bytes the FP64 GEMV streams) but products and sums
+// in FP64, and m_g = colsum_g . b / n_g the mean of (Sf b) over the atom's
+// neutrality group: sum_{i in g} (Sf b)_i = colsum_g . b, so subtracting m_g
+// re-projects onto the neutral subspace exactly as a pass over the finished
+// charges would, without that pass.  Every workgroup forms the two means
+// from the cached colsum and b; a wavefront per row of S.
+__global__ __launch_bounds__(256) void k_charges_mixed(int n, const float* __restrict__ Sf,
+                                                       const double* __restrict__ colsum,
+                                                       const unsigned char* __restrict__ sub1, double inv_n0,
+                                                       double inv_n1, const double* __restrict__ b_all,
+                                                       const double* __restrict__ Sc, double dv,
+                                                       double* __restrict__ Q0_all, double* __restrict__ q_all,
+                                                       const int* __restrict__ epos, double* __restrict__ qs_all) {
+  __shared__ double red[2][4];
   const int lane = threadIdx.x & (WAVE - 1);
   const int frame = blockIdx.y;
   const double* b = b_all + (size_t)frame * n;
-  double s = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) s += b[j];
-  s = wave_sum(s);
-  if (lane == 0) red[threadIdx.x >> 6] = s;
+  double m0 = 0.0, m1 = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double bj = b[j];
+    m0 = fma(colsum[j], bj, m0);
+    m1 = fma(colsum[n + j], bj, m1);
+  }
+  m0 = wave_sum(m0);
+  m1 = wave_sum(m1);
+  if (lane == 0) { red[0][threadIdx.x >> 6] = m0; red[1][threadIdx.x >> 6] = m1; }
   __syncthreads();
-  const double mean = (red[0] + red[1] + red[2] + red[3]) / n;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) bc[j] = (float)(b[j] - mean);
-  __syncthreads();
+  const double mean0 = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3])) * inv_n0;
+  const double mean1 = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3])) * inv_n1;
   const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
   if (i >= n) return;
-  const float* row = Sf + (size_t)i * n;
-  float acc = 0.0f;
-  for (int j = lane; j < n; j += WAVE) acc = fmaf(row[j], bc[j], acc);
-  acc = wave_sum(acc);
-  if (lane == 0) Q0_all[(size_t)frame * n + i] = (double)acc;
+  const int ep = qs_all ? epos[i] : 0;
+  double a0 = 0.0, a1 = 0.0;
+  if ((n & 3) == 0) {       // rows 16-byte aligned: four FP32 values per load
+    const float4* row = reinterpret_cast<const float4*>(Sf + (size_t)i * n);
+    const double2* b2 = reinterpret_cast<const double2*>(b);
+    const int n4 = n >> 2;
+    for (int j = lane; j < n4; j += WAVE) {
+      const float4 sv = row[j];
+      const double2 v0 = b2[2 * j], v1 = b2[2 * j + 1];
+      a0 = fma((double)sv.x, v0.x, fma((double)sv.y, v0.y, a0));
+      a1 = fma((double)sv.z, v1.x, fma((double)sv.w, v1.y, a1));
+    }
+  } else {
+    const float* row = Sf + (size_t)i * n;
+    for (int j = lane; j < n; j += WAVE) a0 = fma((double)row[j], b[j], a0);
+  }
+  const double acc = wave_sum(a0 + a1) - ((sub1 && sub1[i]) ? mean1 : mean0);
+  if (lane == 0) {
+    const size_t o = (size_t)frame * n + i;
+    const double qv = acc + dv * Sc[i];
+    if (Q0_all) Q0_all[o] = acc;
+    if (q_all) q_all[o] = qv;
+    if (qs_all) qs_all[(size_t)frame * n + ep] = qv;
+  }
 }
 
 // FP64 re-projection onto the neutral subspace: Q0 -= mean over each sub-cell
@@ -130,15 +169,17 @@ __global__ __launch_bounds__(256) void k_reproject(int n, const unsigned char* _
 void launch_split_matrix(hipStream_t s, int n, int n_pad, const double* S, float* Sf, unsigned short* split) {
   hipLaunchKernelGGL(k_split_matrix, dim3((n_pad + 255) / 256, n), dim3(256), 0, s, n, n_pad, S, Sf, split);
 }
-void launch_axpy(hipStream_t s, int n, const double* x, const double* y, double a, double* out, const int* epos,
-                 double* out_s) {
-  hipLaunchKernelGGL(k_axpy, dim3((n + 255) / 256), dim3(256), 0, s, n, x, y, a, out, epos, out_s);
-}
 void launch_split_b(hipStream_t s, int n_frames, int n, int n_pad, const double* b, unsigned short* split) {
   hipLaunchKernelGGL(k_split_b, dim3(n_frames), dim3(256), 0, s, n, n_pad, b, split);
 }
-void launch_charges_f32(hipStream_t s, int n_frames, int n, const float* Sf, const double* b, double* Q0) {
-  hipLaunchKernelGGL(k_charges_f32, dim3((n + 3) / 4, n_frames), dim3(256), 0, s, n, Sf, b, Q0);
+void launch_colsum(hipStream_t s, int n, const float* Sf, const unsigned char* sub1, double* colsum) {
+  hipLaunchKernelGGL(k_colsum, dim3((n + 255) / 256), dim3(256), 0, s, n, Sf, sub1, colsum);
+}
+void launch_charges_mixed(hipStream_t s, int n_frames, int n, const float* Sf, const double* colsum,
+                          const unsigned char* sub1, double inv_n0, double inv_n1, const double* b, const double* Sc,
+                          double dv, double* Q0, double* q, const int* epos, double* qs) {
+  hipLaunchKernelGGL(k_charges_mixed, dim3((n + 3) / 4, n_frames), dim3(256), 0, s, n, Sf, colsum, sub1, inv_n0, inv_n1,
+                     b, Sc, dv, Q0, q, epos, qs);
 }
 void launch_reproject(hipStream_t s, int n_frames, int n, const unsigned char* sub1, double* Q0) {
   hipLaunchKernelGGL(k_reproject, dim3(n_frames), dim3(256), 0, s, n, sub1, Q0);

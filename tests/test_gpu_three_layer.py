@@ -104,12 +104,14 @@ def test_three_layer_step_and_batch(torch_dev, geometry):
     ctx.close()
 
 
-def test_three_layer_mixed_single_frame(torch_dev):
-    """The precision form on 2640 charged atoms against the oracle."""
+@pytest.mark.parametrize("geometry", ["ff", "dc"])
+def test_three_layer_mixed_single_frame(torch_dev, geometry):
+    """The precision form on 2640 (5280 in the doubled cell) charged atoms
+    against the oracle; more than 4096 atoms need no special path."""
     torch = torch_dev
     from paper_2201_12963_amd import Context, MIXED
-    _say("[gpu] three-layer paper ff, mixed precision")
-    w, A, S = built3("paper", "ff")
+    _say(f"[gpu] three-layer paper {geometry}, mixed precision")
+    w, A, S = built3("paper", geometry)
     ref = cpm.step(w, A, S, cpm.Electrostatics(w, "pppm"))
     stream = torch.cuda.Stream()
     ctx = Context.from_workload(w, precision=MIXED, stream=stream)
@@ -123,4 +125,7 @@ def test_three_layer_mixed_single_frame(torch_dev):
          f"U_coul {abs(e[0] - ref['u_coul']):.3e} eV")
     assert dq < Q_TOL
     assert rel_rms(f, ref["f"]) < F_RTOL
+    assert abs(q.sum()) < 1e-12
+    if geometry == "dc":
+        assert abs(q[w.elec_sub == 1].sum()) < 1e-12
     ctx.close()

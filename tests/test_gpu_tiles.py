@@ -147,9 +147,11 @@ def test_batch_size_tuner_keeps_results(torch_dev):
         Qb, Fb, Eb = ctx.solve_batch(X, dvs)
     stream.synchronize()
     assert ctx.sync_status() == 0
-    chunk = int(ctx.get_buffer(BUF_BATCH_CHUNK)[0])
-    _say(f"    frames per launch {chunk}")
+    tuned = ctx.get_buffer(BUF_BATCH_CHUNK)
+    chunk = int(tuned[0])
+    _say(f"    frames per launch {chunk}, site-pair tiles per cell {tuned[1]}, x-y planes {tuned[2]}")
     assert chunk in (64, 128)
+    assert tuned[1] in (1, 2, 4) and tuned[2] in (0, 1)
     Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
     for fi in (0, chunk - 1, chunk, 199):
         x = torch.tensor(frames[fi], dtype=torch.float64, device="cuda")
@@ -264,4 +266,39 @@ def test_calls_outside_the_context_stream(torch_dev):
         loss.backward()
         assert abs(loss.item() - ref_grad[0].item()) < 1e-11 * abs(ref_grad[0].item())
         assert torch.allclose(x.grad, ref_grad[1], rtol=0, atol=1e-11 * float(ref_grad[1].abs().max()))
+    ctx.close()
+
+
+@pytest.mark.parametrize("tiles_per_cell,xy_planes", [(1, 1), (2, 0), (4, 1), (3, 0)])
+def test_batch_launch_shapes(torch_dev, tiles_per_cell, xy_planes):
+    """Every launch shape the tuner may pick (and one it does not) gives the
+    single-frame results: site-pair tiles split 1-4 ways per cell, one or
+    several x-y planes per workgroup."""
+    torch = torch_dev
+    from paper_2201_12963_amd import Context
+    from workloads import perturbed_frames
+    _say(f"[gpu] batch shape: {tiles_per_cell} tiles per cell, x-y planes {xy_planes}")
+    w, A, S = built("paper", "dc")
+    frames = perturbed_frames(w, 40, sigma=0.05, seed=19)
+    dvs = np.array([0.5, 3.0])
+    stream = torch.cuda.Stream()
+    ctx = Context.from_workload(w, stream=stream)
+    ctx.build_elastance()
+    ctx.set_batch_shape(16, tiles_per_cell, xy_planes)
+    X = torch.tensor(frames, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        Qb, Fb, Eb = ctx.solve_batch(X, dvs)
+    stream.synchronize()
+    assert ctx.sync_status() == 0
+    Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
+    for fi in (0, 17, 39):
+        x = torch.tensor(frames[fi], dtype=torch.float64, device="cuda")
+        for vi, dv in enumerate(dvs):
+            with torch.cuda.stream(stream):
+                q, f, e = ctx.solve(x, float(dv))
+            stream.synchronize()
+            q, f, e = q.cpu().numpy(), f.cpu().numpy(), e.cpu().numpy()
+            assert np.abs(Qb[fi, vi] - q).max() < 1e-11
+            assert rel_rms(Fb[fi, vi], f) < 1e-10
+            assert np.abs(Eb[fi, vi] - e).max() < 1e-9 * np.abs(e).max()
     ctx.close()
