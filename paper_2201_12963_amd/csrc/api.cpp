@@ -1633,7 +1633,7 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
   };
   MDArgs& a = md->a;
   a.n_site = ns; a.n_mol = d->n_mol; a.n_groups = d->n_groups; a.n_lj_elec = d->n_lj_elec; a.thermostat = 1;
-  a.carbon_sigma = d->carbon_sigma; a.carbon_eps = d->carbon_eps; a.lj_cut = d->lj_cut; a.bond = d->bond;
+  a.carbon_sigma = d->carbon_sigma; a.carbon_sqeps = std::sqrt(d->carbon_eps); a.lj_cut = d->lj_cut; a.bond = d->bond;
   a.dt = d->dt; a.kt = 0.0083144626 * d->temperature;
   for (int k = 0; k < 3; ++k) { a.box[k] = c->box[k]; a.inv_box[k] = 1.0 / c->box[k]; }
   for (int g = 0; g < d->n_groups; ++g) {
@@ -1645,7 +1645,12 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
   int r;
   std::vector<double> zeros(2 * MD_MAX_GROUPS, 0.0);
   std::vector<int> sizes(d->mol_size, d->mol_size + d->n_mol), groups(d->mol_group, d->mol_group + d->n_mol);
-  if ((r = up(&mass_c, d->site_mass, ns)) || (r = up(&sig_c, d->site_sigma, ns)) || (r = up(&eps_c, d->site_eps, ns)) ||
+  std::vector<double> sqeps(ns);
+  for (int j = 0; j < ns; ++j) {
+    if (!(d->site_eps[j] >= 0.0)) { for (void* p : md->allocs) hipFree(p); delete md; return fail(c, CPM_EINVAL, "epsilon must be >= 0"); }
+    sqeps[j] = std::sqrt(d->site_eps[j]);
+  }
+  if ((r = up(&mass_c, d->site_mass, ns)) || (r = up(&sig_c, d->site_sigma, ns)) || (r = up(&eps_c, sqeps.data(), ns)) ||
       (r = up(&ms, start.data(), d->n_mol)) || (r = up(&mz, sizes.data(), d->n_mol)) ||
       (r = up(&mg, groups.data(), d->n_mol)) || (r = up(&mo, mol_of.data(), ns)) ||
       (r = up(&cx, d->lj_elec_xyz, 3 * (size_t)d->n_lj_elec)) || (r = up(&f_lj, (const double*)nullptr, 3 * (size_t)ns)) ||
@@ -1653,7 +1658,7 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
       (r = up(&eta, zeros.data(), MD_MAX_GROUPS)) || (r = up(&q, (const double*)nullptr, c->n_elec)) ||
       (r = up(&fc, (const double*)nullptr, 3 * (size_t)ns)) || (r = up(&en, zeros.data(), 2)))
     return bad(r);
-  a.mass = mass_c; a.sigma = sig_c; a.eps = eps_c; a.mol_start = ms; a.mol_size = mz; a.mol_group = mg; a.mol_of = mo;
+  a.mass = mass_c; a.sigma = sig_c; a.sqeps = eps_c; a.mol_start = ms; a.mol_size = mz; a.mol_group = mg; a.mol_of = mo;
   a.cx = cx; a.f_lj = f_lj; a.u_lj = u_lj; a.xi = xi; a.eta = eta; a.f_c = fc; a.energy = en;
   md->d_q = q; md->d_fc = fc; md->d_energy = en;
   *out = md;

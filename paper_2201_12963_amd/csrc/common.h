@@ -575,10 +575,10 @@ struct MDArgs {
   double* f_lj;                         // [3][n_site] kJ/mol/nm (written by k_lj)
   const double* f_c;                    // [3][n_site] Coulomb force, eV/nm
   double* u_lj;                         // [n_site] Lennard-Jones energy share per site (written by k_lj)
-  const double* mass; const double* sigma; const double* eps;   // [n_site]
+  const double* mass; const double* sigma; const double* sqeps;   // [n_site] (sqeps: sqrt(epsilon))
   const int* mol_start; const int* mol_size; const int* mol_group; const int* mol_of;
   const double* cx;                     // [3][n_lj_elec] graphene atoms
-  double carbon_sigma, carbon_eps, lj_cut, bond, dt, kt;
+  double carbon_sigma, carbon_sqeps, lj_cut, bond, dt, kt;
   double box[3], inv_box[3];
   double nf[MD_MAX_GROUPS], Q[MD_MAX_GROUPS];
   double* xi; double* eta;              // [n_groups] thermostat state (device)

@@ -12,9 +12,13 @@
 //   xi += dt/4 (K2 - N_f kT)/Q; eta += dt/2 xi; v *= exp(-xi dt/2);
 //   K2 *= exp(-xi dt); xi += dt/4 (K2 - N_f kT)/Q
 //
-// k_lj: one wavefront per site over all sites and graphene atoms (minimum
+// SHAKE and RATTLE solve a molecule's three constraints together (Newton
+// steps on the multipliers; a 3 x 3 linear solve for the velocities): the
+// same constrained positions and velocities as one constraint at a time.
+//
+// k_lj: one workgroup per site over all sites and graphene atoms (minimum
 // image, pairs of one molecule excluded, energy shifted to zero at the
-// cutoff).  k_md_integrate: one 1024-thread workgroup for the whole
+// cutoff; Lorentz-Berthelot mixing from the stored square roots of epsilon).  k_md_integrate: one 1024-thread workgroup for the whole
 // electrolyte (a thread per molecule, its sites in registers), since the
 // thermostat needs the groups' kinetic energies between the two halves of
 // the update; one launch joins the end of one step and the start of the
@@ -27,42 +31,45 @@ constexpr double KB_KJ = 0.0083144626;      // kJ/mol/K
 constexpr double EV_KJ = 96.48533212;       // kJ/mol per eV
 
 __global__ __launch_bounds__(256) void k_lj(MDArgs a) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int i = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x >> 6);
-  if (i >= a.n_site) return;
+  // one workgroup per site: its 256 threads share the partners, so that a
+  // site's sum is spread over four wavefronts and every CU holds many sites
+  __shared__ double red[4][4];
+  const int i = blockIdx.x;
   const double xi = a.x[i], yi = a.x[a.n_site + i], zi = a.x[2 * a.n_site + i];
-  const double si = a.sigma[i], ei = a.eps[i];
+  const double si = a.sigma[i], qi = a.sqeps[i];
   const int mi = a.mol_of[i];
   const double rc2 = a.lj_cut * a.lj_cut;
-  double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, uw = 1.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, uw = 0.5;   // a site-site pair's energy is shared by its sites
   auto pair = [&](double dx, double dy, double dz, double sig, double eps) {
     dx -= a.box[0] * rint(dx * a.inv_box[0]);
     dy -= a.box[1] * rint(dy * a.inv_box[1]);
     dz -= a.box[2] * rint(dz * a.inv_box[2]);
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < rc2 && r2 > 0.0) {
-      const double s2 = sig * sig;
-      const double s6 = s2 * s2 * s2 / (r2 * r2 * r2);
-      const double c6 = s2 * s2 * s2 / (rc2 * rc2 * rc2);
-      const double fr = 24.0 * eps * (2.0 * s6 * s6 - s6) / r2;
+      const double ir2 = 1.0 / r2;
+      const double t = sig * sig * ir2, s6 = t * t * t;
+      const double tc = sig * sig / rc2, c6 = tc * tc * tc;
+      const double fr = 24.0 * eps * (2.0 * s6 * s6 - s6) * ir2;
       fx += fr * dx; fy += fr * dy; fz += fr * dz;
       u += uw * (4.0 * eps * (s6 * s6 - s6) - 4.0 * eps * (c6 * c6 - c6));
     }
   };
-  uw = 0.5;                       // a site-site pair's energy is shared by its two sites
-  for (int j = lane; j < a.n_site; j += WAVE) {
+  for (int j = threadIdx.x; j < a.n_site; j += blockDim.x) {
     if (a.mol_of[j] == mi) continue;
-    pair(xi - a.x[j], yi - a.x[a.n_site + j], zi - a.x[2 * a.n_site + j], 0.5 * (si + a.sigma[j]),
-         sqrt(ei * a.eps[j]));
+    pair(xi - a.x[j], yi - a.x[a.n_site + j], zi - a.x[2 * a.n_site + j], 0.5 * (si + a.sigma[j]), qi * a.sqeps[j]);
   }
   uw = 1.0;
-  const double sc = 0.5 * (si + a.carbon_sigma), ec = sqrt(ei * a.carbon_eps);
-  for (int j = lane; j < a.n_lj_elec; j += WAVE)
+  const double sc = 0.5 * (si + a.carbon_sigma), ec = qi * a.carbon_sqeps;
+  for (int j = threadIdx.x; j < a.n_lj_elec; j += blockDim.x)
     pair(xi - a.cx[j], yi - a.cx[a.n_lj_elec + j], zi - a.cx[2 * a.n_lj_elec + j], sc, ec);
   fx = wave_sum(fx); fy = wave_sum(fy); fz = wave_sum(fz); u = wave_sum(u);
-  if (lane == 0) {
-    a.f_lj[i] = fx; a.f_lj[a.n_site + i] = fy; a.f_lj[2 * a.n_site + i] = fz;
-    a.u_lj[i] = u;
+  const int w = threadIdx.x / WAVE;
+  if ((threadIdx.x & (WAVE - 1)) == 0) { red[w][0] = fx; red[w][1] = fy; red[w][2] = fz; red[w][3] = u; }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const double t = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    if (threadIdx.x < 3) a.f_lj[threadIdx.x * a.n_site + i] = t;
+    else a.u_lj[i] = t;
   }
 }
 
@@ -72,52 +79,87 @@ __device__ __forceinline__ double md_diff(const MDArgs& a, double p, double q, i
   return r - a.box[d] * rint(r * a.inv_box[d]);
 }
 
-// SHAKE of one rigid three-site molecule in registers: move the new
-// positions p along the old constraint vectors o until the three distances
-// hold (Gauss-Seidel over the constraints, same order as the oracle)
+// Constraint solves of one rigid three-site molecule, in registers.  The
+// three constraints c = (0,1), (0,2), (1,2) are taken together: site s moves
+// by g_c sigma_sc v_c / m_s for each c (sigma = +1 on the constraint's first
+// site, -1 on its second, v_c the constraint's vector), so the bond vector
+// of constraint a changes by sum_b K_ab g_b v_b with
+// K_ab = sigma(i_a, b) / m(i_a) - sigma(j_a, b) / m(j_a).
+
+__device__ __forceinline__ double md_kab(int a, int b, const double m[3]) {
+  const int ci[3] = {0, 0, 1}, cj[3] = {1, 2, 2};
+  auto sig = [&](int s, int c) { return s == ci[c] ? 1.0 : (s == cj[c] ? -1.0 : 0.0); };
+  return sig(ci[a], b) / m[ci[a]] - sig(cj[a], b) / m[cj[a]];
+}
+
+// x = M^-1 y for a 3 x 3 matrix (Cramer's rule; M is well conditioned here:
+// the three bond vectors of the triangle are independent)
+__device__ __forceinline__ void solve3(const double M[3][3], const double y[3], double x[3]) {
+  const double c00 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+  const double c01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+  const double c02 = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+  const double det = M[0][0] * c00 + M[0][1] * c01 + M[0][2] * c02;
+  const double id = 1.0 / det;
+  x[0] = id * (y[0] * c00 + y[1] * (M[0][2] * M[2][1] - M[0][1] * M[2][2]) + y[2] * (M[0][1] * M[1][2] - M[0][2] * M[1][1]));
+  x[1] = id * (y[0] * c01 + y[1] * (M[0][0] * M[2][2] - M[0][2] * M[2][0]) + y[2] * (M[0][2] * M[1][0] - M[0][0] * M[1][2]));
+  x[2] = id * (y[0] * c02 + y[1] * (M[0][1] * M[2][0] - M[0][0] * M[2][1]) + y[2] * (M[0][0] * M[1][1] - M[0][1] * M[1][0]));
+}
+
+// SHAKE: move the new positions p along the old bond vectors (from o) until
+// |p_i - p_j| = d for all three constraints, by Newton steps on the three
+// multipliers together (the same fixed point as one constraint at a time,
+// reached in a few steps)
 __device__ void shake3(const MDArgs& a, double p[3][3], const double o[3][3], const double m[3]) {
   const int ci[3] = {0, 0, 1}, cj[3] = {1, 2, 2};
   const double d[3] = {a.bond, a.bond, a.bond * 1.7320508075688772};
+  double ro[3][3];                                     // [constraint][axis], fixed during the solve
+  _Pragma("unroll") for (int c = 0; c < 3; ++c)
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) ro[c][k] = md_diff(a, o[k][ci[c]], o[k][cj[c]], k);
+  double K[3][3];
+  _Pragma("unroll") for (int x = 0; x < 3; ++x)
+    _Pragma("unroll") for (int y = 0; y < 3; ++y) K[x][y] = md_kab(x, y, m);
   for (int it = 0; it < MD_MAX_ITER; ++it) {
+    double r[3][3], f[3];
     bool done = true;
     _Pragma("unroll") for (int c = 0; c < 3; ++c) {
-      const int i = ci[c], j = cj[c];
-      double r[3], ro[3];
-      _Pragma("unroll") for (int k = 0; k < 3; ++k) { r[k] = md_diff(a, p[k][i], p[k][j], k); ro[k] = md_diff(a, o[k][i], o[k][j], k); }
-      const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-      const double diff = d[c] * d[c] - rr;
-      if (fabs(diff) > MD_TOL * d[c] * d[c]) {
-        done = false;
-        const double g = diff / (2.0 * (ro[0] * r[0] + ro[1] * r[1] + ro[2] * r[2]) * (1.0 / m[i] + 1.0 / m[j]));
-        _Pragma("unroll") for (int k = 0; k < 3; ++k) { p[k][i] += g * ro[k] / m[i]; p[k][j] -= g * ro[k] / m[j]; }
-      }
+      _Pragma("unroll") for (int k = 0; k < 3; ++k) r[c][k] = md_diff(a, p[k][ci[c]], p[k][cj[c]], k);
+      f[c] = r[c][0] * r[c][0] + r[c][1] * r[c][1] + r[c][2] * r[c][2] - d[c] * d[c];
+      done = done && fabs(f[c]) <= MD_TOL * d[c] * d[c];
     }
     if (done) return;
+    double J[3][3], g[3];
+    _Pragma("unroll") for (int x = 0; x < 3; ++x)
+      _Pragma("unroll") for (int y = 0; y < 3; ++y)
+        J[x][y] = 2.0 * K[x][y] * (r[x][0] * ro[y][0] + r[x][1] * ro[y][1] + r[x][2] * ro[y][2]);
+    solve3(J, f, g);
+    _Pragma("unroll") for (int c = 0; c < 3; ++c)
+      _Pragma("unroll") for (int k = 0; k < 3; ++k) {
+        p[k][ci[c]] -= g[c] * ro[c][k] / m[ci[c]];
+        p[k][cj[c]] += g[c] * ro[c][k] / m[cj[c]];
+      }
   }
 }
 
-// RATTLE of one rigid molecule's velocities: remove the components along
-// the constraints (Gauss-Seidel, same order and test as the oracle)
+// RATTLE: remove the velocity components along the three constraints, a
+// linear 3 x 3 system for the multipliers solved at once
 __device__ void rattle3(const MDArgs& a, double v[3][3], const double p[3][3], const double m[3]) {
   const int ci[3] = {0, 0, 1}, cj[3] = {1, 2, 2};
-  const double d[3] = {a.bond, a.bond, a.bond * 1.7320508075688772};
-  for (int it = 0; it < MD_MAX_ITER; ++it) {
-    bool done = true;
-    _Pragma("unroll") for (int c = 0; c < 3; ++c) {
-      const int i = ci[c], j = cj[c];
-      double r[3];
-      _Pragma("unroll") for (int k = 0; k < 3; ++k) r[k] = md_diff(a, p[k][i], p[k][j], k);
-      const double vr = (v[0][i] - v[0][j]) * r[0] + (v[1][i] - v[1][j]) * r[1] + (v[2][i] - v[2][j]) * r[2];
-      double vmax_i = 0.0, vmax_j = 0.0;
-      _Pragma("unroll") for (int k = 0; k < 3; ++k) { vmax_i = fmax(vmax_i, fabs(v[k][i])); vmax_j = fmax(vmax_j, fabs(v[k][j])); }
-      if (fabs(vr) > MD_TOL * d[c] * (vmax_i + vmax_j + 1e-300)) {
-        done = false;
-        const double kk = vr / (d[c] * d[c] * (1.0 / m[i] + 1.0 / m[j]));
-        _Pragma("unroll") for (int k = 0; k < 3; ++k) { v[k][i] -= kk * r[k] / m[i]; v[k][j] += kk * r[k] / m[j]; }
-      }
-    }
-    if (done) return;
+  double r[3][3], vr[3];
+  _Pragma("unroll") for (int c = 0; c < 3; ++c) {
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) r[c][k] = md_diff(a, p[k][ci[c]], p[k][cj[c]], k);
+    vr[c] = (v[0][ci[c]] - v[0][cj[c]]) * r[c][0] + (v[1][ci[c]] - v[1][cj[c]]) * r[c][1] +
+            (v[2][ci[c]] - v[2][cj[c]]) * r[c][2];
   }
+  double M[3][3], kk[3];
+  _Pragma("unroll") for (int x = 0; x < 3; ++x)
+    _Pragma("unroll") for (int y = 0; y < 3; ++y)
+      M[x][y] = md_kab(x, y, m) * (r[x][0] * r[y][0] + r[x][1] * r[y][1] + r[x][2] * r[y][2]);
+  solve3(M, vr, kk);
+  _Pragma("unroll") for (int c = 0; c < 3; ++c)
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) {
+      v[k][ci[c]] -= kk[c] * r[c][k] / m[ci[c]];
+      v[k][cj[c]] += kk[c] * r[c][k] / m[cj[c]];
+    }
 }
 
 // per-group totals of a per-thread partial (every thread gets the totals)
@@ -265,7 +307,7 @@ __global__ __launch_bounds__(MD_THREADS) void k_md_integrate(MDArgs a, int mode,
 }
 
 void launch_lj(hipStream_t s, const MDArgs& a) {
-  hipLaunchKernelGGL(k_lj, dim3((a.n_site + 3) / 4), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_lj, dim3(a.n_site), dim3(256), 0, s, a);
 }
 void launch_md_integrate(hipStream_t s, const MDArgs& a, int mode, int rec_step) {
   hipLaunchKernelGGL(k_md_integrate, dim3(1), dim3(MD_THREADS), 0, s, a, mode, rec_step);
