@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -89,6 +90,7 @@ struct cpm_ctx {
   int cap_dv = 0;
   int batch_chunk = 0;                     // frames per batched launch chosen by the tuner (0: not yet)
   int pair_tsplit = 1;                     // batched site-pair tiles: workgroups per cell (tuned)
+  int *d_fwd_n = nullptr, *d_fwd_lo = nullptr, *d_fwd_hi = nullptr;   // forward stencils (no images only)
   // k-space field mesh of the electrode charges S c alone (batched dV sweep)
   double* d_ESc = nullptr;
   float* d_EScf = nullptr;
@@ -213,8 +215,11 @@ double wrap_host(double x, double L) { return x - L * std::floor(x / L); }
 // Stencil groups of every cell of the grid: the distinct neighbour cells
 // (offsets -1, 0, 1 per axis, fewer where the axis has under 3 cells),
 // sorted and joined into runs of consecutive cell indices [lo, hi); n[c]
-// groups per cell at [c * STENCIL_MAX + k] (unused entries 0).
-void stencil_groups(const Cell& cl, std::vector<int>& n, std::vector<int>& lo, std::vector<int>& hi) {
+// groups per cell at [c * STENCIL_MAX + k] (unused entries 0).  forward:
+// only the cells of index >= c (the stencil is symmetric, so every pair of
+// neighbouring cells appears once, in the lower cell's list).
+void stencil_groups(const Cell& cl, std::vector<int>& n, std::vector<int>& lo, std::vector<int>& hi,
+                    bool forward = false) {
   n.assign(cl.n_cells, 0);
   lo.assign((size_t)cl.n_cells * STENCIL_MAX, 0);
   hi.assign((size_t)cl.n_cells * STENCIL_MAX, 0);
@@ -232,6 +237,7 @@ void stencil_groups(const Cell& cl, std::vector<int>& n, std::vector<int>& lo, s
           cells.push_back((nb(cz, a, cl.nc[2]) * cl.nc[1] + nb(cy, b, cl.nc[1])) * cl.nc[0] + nb(cx, d, cl.nc[0]));
     std::sort(cells.begin(), cells.end());
     cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+    if (forward) cells.erase(std::remove_if(cells.begin(), cells.end(), [c](int v) { return v < c; }), cells.end());
     int k = -1;
     for (size_t t = 0; t < cells.size(); ++t) {
       if (t == 0 || cells[t] != cells[t - 1] + 1) {
@@ -583,6 +589,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     pa.qb_s = fa.qb_s;
     pa.f_elec = c->d_felec;
     fa.f_elec = c->d_felec;
+    pa.fwd_n = c->d_fwd_n; pa.fwd_lo = c->d_fwd_lo; pa.fwd_hi = c->d_fwd_hi;
   }
   if (c->kspace == CPM_KSPACE_PPPM) {
     // the electrode spread stays a kernel of its own: only the few planes
@@ -1041,6 +1048,13 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     if ((r = upload(c, &dn, gn)) || (r = upload(c, &dl, glo)) || (r = upload(c, &dh, ghi))) return bad(r);
     cl.grp_n = dn; cl.grp_lo = dl; cl.grp_hi = dh;
   }
+  if (cl.img[0] == 0 && cl.img[1] == 0 && cl.img[2] == 0) {
+    // forward stencils for the many-frame pair tiles (each pair once)
+    std::vector<int> fn, flo, fhi;
+    stencil_groups(cl, fn, flo, fhi, true);
+    if ((r = upload(c, &c->d_fwd_n, fn)) || (r = upload(c, &c->d_fwd_lo, flo)) || (r = upload(c, &c->d_fwd_hi, fhi)))
+      return bad(r);
+  }
   c->cell_b = cl;
   for (int k = 0; k < 3; ++k) c->cell_b.img[k] = (int)std::floor(c->rcut_b / c->box[k] + 0.5);
   if (bin_lds_bytes(ns, cl.n_cells) > LDS_LIMIT) {
@@ -1112,18 +1126,49 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
     c->n_heights = (int)hs.size();
     if ((r = upload(c, &c->d_height_of, hof)) || (r = upload(c, &c->d_heights, hs))) return bad(r);
   }
-  // electrode atoms in reach of every cell: the stencil groups' ranges of
-  // the sorted atoms, empty ones dropped and adjacent ones joined
+  // electrode atoms in reach of every cell: the stencil cells' ranges of the
+  // sorted atoms, empty ones dropped and adjacent ones joined.  Without
+  // periodic images a stencil cell is also dropped when the bounding box of
+  // its atoms lies at least rcut from the cell (minimum-image distance per
+  // axis, with a margin for the rounding of the cell bounds): the electrodes
+  // are fixed, so the sites next to an electrode's cell but beyond the cutoff
+  // from its atoms test none of them.
+  const bool no_img = cl.img[0] == 0 && cl.img[1] == 0 && cl.img[2] == 0;
+  std::vector<double> bb((size_t)cl.n_cells * 6, 0.0);      // per cell: lo[3], hi[3] of its atoms
+  for (int e = 0; e < cl.n_cells; ++e)
+    for (int k = ecs[e]; k < ecs[e + 1]; ++k) {
+      const double p[3] = {sxe[k], sye[k], sze[k]};
+      for (int a = 0; a < 3; ++a) {
+        if (k == ecs[e] || p[a] < bb[(size_t)e * 6 + a]) bb[(size_t)e * 6 + a] = p[a];
+        if (k == ecs[e] || p[a] > bb[(size_t)e * 6 + 3 + a]) bb[(size_t)e * 6 + 3 + a] = p[a];
+      }
+    }
+  auto in_reach = [&](int cc2, int e) {
+    if (!no_img) return true;
+    const int ci[3] = {cc2 % cl.nc[0], (cc2 / cl.nc[0]) % cl.nc[1], cc2 / (cl.nc[0] * cl.nc[1])};
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double L = cl.L[a], w = L / cl.nc[a], margin = 1e-9 * L;
+      const double c0 = ci[a] * w - margin, c1 = (ci[a] + 1) * w + margin;
+      const double b0 = bb[(size_t)e * 6 + a], b1 = bb[(size_t)e * 6 + 3 + a];
+      double gap = std::numeric_limits<double>::infinity();
+      for (int sh = -1; sh <= 1; ++sh)
+        gap = std::min(gap, std::max(0.0, std::max(b0 + sh * L - c1, c0 - (b1 + sh * L))));
+      d2 += gap * gap;
+    }
+    return d2 < c->rcut * c->rcut;
+  };
   std::vector<int> rn(cl.n_cells, 0), rlo((size_t)cl.n_cells * STENCIL_MAX, 0), rhi((size_t)cl.n_cells * STENCIL_MAX, 0);
   for (int cc2 = 0; cc2 < cl.n_cells; ++cc2) {
     int k = 0;
     const size_t base = (size_t)cc2 * STENCIL_MAX;
-    for (int g = 0; g < gn[cc2]; ++g) {
-      const int lo = ecs[glo[base + g]], hi = ecs[ghi[base + g]];
-      if (hi <= lo) continue;
-      if (k > 0 && rhi[base + k - 1] == lo) rhi[base + k - 1] = hi;
-      else { rlo[base + k] = lo; rhi[base + k] = hi; ++k; }
-    }
+    for (int g = 0; g < gn[cc2]; ++g)
+      for (int e = glo[base + g]; e < ghi[base + g]; ++e) {
+        const int lo = ecs[e], hi = ecs[e + 1];
+        if (hi <= lo || !in_reach(cc2, e)) continue;
+        if (k > 0 && rhi[base + k - 1] == lo) rhi[base + k - 1] = hi;
+        else { rlo[base + k] = lo; rhi[base + k] = hi; ++k; }
+      }
     rn[cc2] = k;
   }
   {

@@ -270,6 +270,14 @@ struct PairArgs {
   const double* qa_s; size_t qa_stride;
   const double* qb_s;
   double* f_elec;
+  // tiles without periodic images: the forward half of every cell's stencil
+  // (the cell itself and its neighbours of larger index, as runs like
+  // Cell::grp_*), or nullptr; with it every site pair is evaluated once and
+  // both ends are accumulated (f_pair and u_site then take atomic adds and
+  // are cleared before the launch)
+  const int* fwd_n;
+  const int* fwd_lo;
+  const int* fwd_hi;
 };
 
 // z pass: a lane prefetches the multiplier (and saved spectrum) of the
@@ -387,7 +395,7 @@ template <typename T>
 void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa);
 // LDS of a site-pair workgroup (tsplit > 0: tile form)
 template <typename T>
-size_t site_pairs_lds(int tsplit);
+size_t site_pairs_lds(int tsplit, bool n3);
 // forces: the site-force workgroups; ea (or nullptr): one more workgroup per
 // frame that reduces the energies
 template <typename T>

@@ -29,16 +29,45 @@ __global__ __launch_bounds__(TILE_THREADS) void k_site_pairs(PairArgs<T> pa) {
 
 // The cell-tile form (many frames) as a kernel of its own, held to five
 // wavefronts per SIMD (its ~32 KB of LDS allow five workgroups per CU; the
-// few registers it then spills cost less than the fifth workgroup gains:
-// 12.3 -> 11.6 ms per 4096 frames)
+// few registers it then spills cost less than the fifth workgroup gains).
 template <typename T>
 __global__ __launch_bounds__(TILE_THREADS, 5) void k_site_pairs_tiles(PairArgs<T> pa) {
   extern __shared__ __align__(16) unsigned char lds[];
-  site_pairs_block(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
+  site_pairs_block<T, 0>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
+}
+
+// The site-electrode sums of many frames beside k_site_pairs_n3 (~28 KB of
+// LDS; four workgroups per CU leave the FP64 form its registers).
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS, 4) void k_site_elec_tiles(PairArgs<T> pa) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  site_pairs_block<T, 1>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
+}
+
+// The site-site sums of many frames with every pair once (no periodic
+// images): ~35 KB of LDS, four workgroups per CU.
+template <typename T>
+__global__ __launch_bounds__(TILE_THREADS, 4) void k_site_pairs_n3(PairArgs<T> pa) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  site_pairs_block<T, 2>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
+}
+
+// clears n doubles (the atomic targets of the each-pair-once tiles)
+__global__ __launch_bounds__(256) void k_zero(double* __restrict__ p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+
+void launch_zero(hipStream_t s, double* p, size_t n) {
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
 }
 
 template <typename T>
-size_t site_pairs_lds(int tsplit) { return tsplit > 0 ? PairLds<T>::total : 4 * wave_scratch_bytes<T>(); }
+size_t site_pairs_lds(int tsplit, bool n3) {
+  return tsplit > 0 ? (n3 ? PairN3Lds<T>::total : PairLds<T>::total) : 4 * wave_scratch_bytes<T>();
+}
 
 
 // The rest of the force on every site, once the electrode charges are known
@@ -356,12 +385,19 @@ __global__ __launch_bounds__(G16_THREADS) void k_site_forces_g16(SiteSet<T> st, 
 template <typename T>
 void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
   if (pa.n_blocks == 0 || n_frames == 0) return;
-  if (pa.tsplit > 0)
-    hipLaunchKernelGGL(k_site_pairs_tiles<T>, dim3(pa.n_blocks, n_frames), dim3(TILE_THREADS),
-                       site_pairs_lds<T>(pa.tsplit), s, pa);
-  else
-    hipLaunchKernelGGL(k_site_pairs<T>, dim3(pa.n_blocks, n_frames), dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit),
-                       s, pa);
+  const dim3 grid(pa.n_blocks, n_frames);
+  if (pa.tsplit > 0 && pa.fwd_n) {
+    // site-site pairs once each (both ends take atomic adds), then the
+    // site-electrode pairs
+    launch_zero(s, pa.f_pair, (size_t)n_frames * 3 * pa.st.n);
+    if (pa.u_site) launch_zero(s, pa.u_site, (size_t)n_frames * pa.st.n);
+    hipLaunchKernelGGL(k_site_pairs_n3<T>, grid, dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit, true), s, pa);
+    if (pa.f_elec) hipLaunchKernelGGL(k_site_elec_tiles<T>, grid, dim3(TILE_THREADS), ElecTileLds<T>::total, s, pa);
+  } else if (pa.tsplit > 0) {
+    hipLaunchKernelGGL(k_site_pairs_tiles<T>, grid, dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit, false), s, pa);
+  } else {
+    hipLaunchKernelGGL(k_site_pairs<T>, grid, dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit, false), s, pa);
+  }
 }
 
 template <typename T>
@@ -419,8 +455,8 @@ template void launch_real_b_t<double>(hipStream_t, int, const RealBArgs<double>&
 template void launch_real_b_t<float>(hipStream_t, int, const RealBArgs<float>&);
 template void launch_site_pairs_t<double>(hipStream_t, int, const PairArgs<double>&);
 template void launch_site_pairs_t<float>(hipStream_t, int, const PairArgs<float>&);
-template size_t site_pairs_lds<double>(int);
-template size_t site_pairs_lds<float>(int);
+template size_t site_pairs_lds<double>(int, bool);
+template size_t site_pairs_lds<float>(int, bool);
 template void launch_site_forces_t<double>(hipStream_t, int, const Cell&, const ElecSet<double>&,
                                            const SiteSet<double>&, const ForceArgs<double>&, bool,
                                            const EnergyArgs*);

@@ -30,19 +30,27 @@ __device__ __forceinline__ double recip_nr(double d) {
   return y;
 }
 
-// erfcx(x) = exp(x^2) erfc(x) for 0 <= x <= ERFCX_XMAX: Clenshaw sum of the
-// Chebyshev series in u(t), t = 2/(2 + x) (coefficients in erfcx_cheb.h)
+// erfcx(x) = exp(x^2) erfc(x) for 0 <= x <= ERFCX_XMAX: the degree-20
+// polynomial in u(t), t = 2/(2 + x) (coefficients in erfcx_cheb.h), by
+// Estrin's scheme: coefficient pairs, then pairs of pairs with u^2, u^4,
+// u^8, u^16, a dependency chain of ~7 operations where Horner's would be 20
 __device__ __forceinline__ double erfcx_cheb(double x) {
+  static_assert(ERFCX_DEG == 20, "Estrin tree below is written for degree 20");
   const double t = 2.0 * recip_nr(2.0 + x);
   const double u = (t - ERFCX_TMIN) * (2.0 / (1.0 - ERFCX_TMIN)) - 1.0;
-  double b1 = 0.0, b2 = 0.0;
+  const double u2 = u * u, u4 = u2 * u2, u8 = u4 * u4, u16 = u8 * u8;
+  const double* a = ERFCX_POLY;
+  double p[11];
 #pragma unroll
-  for (int k = ERFCX_DEG; k > 0; --k) {
-    double b0 = fma(2.0 * u, b1, ERFCX_CHEB[k] - b2);
-    b2 = b1;
-    b1 = b0;
-  }
-  return fma(u, b1, ERFCX_CHEB[0] - b2);
+  for (int i = 0; i < 10; ++i) p[i] = fma(a[2 * i + 1], u, a[2 * i]);
+  p[10] = a[20];
+  double q[6];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) q[i] = fma(p[2 * i + 1], u2, p[2 * i]);
+  q[5] = p[10];
+  const double r0 = fma(q[1], u4, q[0]), r1 = fma(q[3], u4, q[2]), r2 = fma(q[5], u4, q[4]);
+  const double s0 = fma(r1, u8, r0);
+  return fma(r2, u16, s0);
 }
 
 // erfc(x) given e = exp(-x^2), 0 <= x <= ERFCX_XMAX (alpha rcut is checked

@@ -17,6 +17,10 @@
 // costs only its share of the tests.  The summation order of a target's
 // pairs follows the atomics' arrival, so results can differ between runs
 // by rounding.
+//
+// Without periodic images the site-site pairs take a form of their own
+// (site_pairs_n3_tile below) that evaluates every pair once, and the
+// site-electrode pairs a launch of their own (site_elec_tile).
 #pragma once
 #include "pairs.h"
 
@@ -52,6 +56,16 @@ __device__ __forceinline__ void tile_runs(const Cell& cell, int c, const int* cs
   const int ng = cell.grp_n[c];
   int lo = 0, hi = 0;
   if (lane < ng) { lo = cs[cell.grp_lo[c * STENCIL_MAX + lane]]; hi = cs[cell.grp_hi[c * STENCIL_MAX + lane]]; }
+  tile_scan_runs(ng, lo, hi, R);
+}
+
+// runs of the forward half of the stencil of cell c (tables as Cell::grp_*)
+__device__ __forceinline__ void tile_runs_fwd(const int* fn, const int* flo, const int* fhi, int c, const int* cs,
+                                              TileRuns* R) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int ng = fn[c];
+  int lo = 0, hi = 0;
+  if (lane < ng) { lo = cs[flo[c * STENCIL_MAX + lane]]; hi = cs[fhi[c * STENCIL_MAX + lane]]; }
   tile_scan_runs(ng, lo, hi, R);
 }
 
@@ -350,6 +364,305 @@ __device__ __forceinline__ void site_pairs_tile(const PairArgs<T>& pa, int c, in
   }
 }
 
+// ------------------------------------------------- site pairs, each once
+
+// LDS of the each-pair-once tile: the stencil runs, the staged candidates
+// (two 16-byte arrays: x and y; z and the sorted index; then the charges),
+// four FP64 sums per candidate and per target (force, potential), the
+// targets' charges, one pair queue per wavefront
+template <typename T>
+struct PairN3Lds {
+  static constexpr size_t runs = 0;
+  static constexpr size_t rec = (sizeof(TileRuns) + 31) / 32 * 32;     // xy [TILE_CAND], then zs [TILE_CAND]
+  static constexpr size_t cq = rec + (size_t)TILE_CAND * 32;
+  static constexpr size_t cacc = cq + ((size_t)TILE_CAND * sizeof(T) + 15) / 16 * 16;
+  static constexpr size_t tacc = cacc + 4 * (size_t)TILE_CAND * sizeof(double);
+  static constexpr size_t tq = tacc + 4 * (size_t)TILE_TGT * sizeof(double);
+  static constexpr size_t queue = tq + ((size_t)TILE_TGT * sizeof(T) + 15) / 16 * 16;
+  static constexpr size_t queue_bytes = (TileQ<T, 3>::bytes() + 15) / 16 * 16;
+  static constexpr size_t total = queue + (TILE_THREADS / WAVE) * queue_bytes;
+};
+
+// Site-site sums of the targets [t_lo, t_hi) of cell c with every pair once
+// (no periodic images): the candidates are the sites of the forward half of
+// the stencil (pa.fwd_*) of larger sorted index than the target, so each
+// pair inside the cutoff is met by exactly one work item, which adds
+// Q_k g0(r) r_vec to the target's and -Q_j g0(r) r_vec to the candidate's
+// force sum, and Q_k erfc(alpha r)/r, Q_j erfc(alpha r)/r to their
+// potential sums.  Thread (ti, sl) tests the candidates of block sl of the
+// nsl contiguous blocks of a staged set, starting at offset ti within it,
+// so that the lanes of a wavefront read, and later add into, distinct
+// candidates.  The candidates' sums go to f_pair and u_site with FP64
+// atomic adds after every staged set, the targets' after the last one: both
+// arrays are cleared before the launch.  lds: PairN3Lds<T>::total bytes.
+template <typename T>
+__device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
+                                                   unsigned char* lds) {
+  using L = PairN3Lds<T>;
+  constexpr int CAP = TileQ<T, 3>::CAP;
+  TileRuns* R = reinterpret_cast<TileRuns*>(lds + L::runs);
+  double2* rxy = reinterpret_cast<double2*>(lds + L::rec);      // [TILE_CAND] x, y
+  double2* rzs = rxy + TILE_CAND;                                 // [TILE_CAND] z, sorted index
+  T* cq = reinterpret_cast<T*>(lds + L::cq);                      // [TILE_CAND]
+  double* cacc = reinterpret_cast<double*>(lds + L::cacc);       // [4][TILE_CAND]
+  double* tacc = reinterpret_cast<double*>(lds + L::tacc);       // [4][TILE_TGT]
+  T* tq = reinterpret_cast<T*>(lds + L::tq);                      // [TILE_TGT]
+  TileQ<T, 3> Q;
+  Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int n = pa.st.n;
+  const size_t fo = (size_t)frame * n;
+  const int* cs = pa.st.cell_start + (size_t)frame * (pa.cell.n_cells + 1);
+  const double* sx = pa.st.x + fo; const double* sy = pa.st.y + fo; const double* sz = pa.st.z + fo;
+  const double* sq = pa.st.q + fo;
+  double* fp = pa.f_pair + (size_t)frame * 3 * n;
+  double* us = pa.u_site ? pa.u_site + fo : nullptr;
+  const double L0 = pa.cell.L[0], L1 = pa.cell.L[1], L2 = pa.cell.L[2];
+  const double iL0 = pa.cell.invL[0], iL1 = pa.cell.invL[1], iL2 = pa.cell.invL[2];
+  const double rc2 = pa.rc2;
+  const T alpha = pa.alpha;
+  if (threadIdx.x < WAVE) tile_runs_fwd(pa.fwd_n, pa.fwd_lo, pa.fwd_hi, c, cs, R);
+
+  // queued pairs: both ends' sums
+  auto eval = [&](int l) {
+    const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l];
+    const int e = Q.t[l];
+    const int tt = e & 255, kc = e >> 8;
+    const T qc = cq[kc], qt = tq[tt];
+    T g, pot;
+    g0_terms(qx * qx + qy * qy + qz * qz, alpha, g, pot);
+    const T wc = qc * g, wt = qt * g;
+    atomicAdd(tacc + tt, (double)(wc * qx));
+    atomicAdd(tacc + TILE_TGT + tt, (double)(wc * qy));
+    atomicAdd(tacc + 2 * TILE_TGT + tt, (double)(wc * qz));
+    atomicAdd(tacc + 3 * TILE_TGT + tt, (double)(qc * pot));
+    atomicAdd(cacc + kc, (double)(-wt * qx));
+    atomicAdd(cacc + TILE_CAND + kc, (double)(-wt * qy));
+    atomicAdd(cacc + 2 * TILE_CAND + kc, (double)(-wt * qz));
+    atomicAdd(cacc + 3 * TILE_CAND + kc, (double)(qt * pot));
+  };
+
+  for (int t0 = t_lo; t0 < t_hi; t0 += TILE_TGT) {
+    const TileMap m(min(TILE_TGT, t_hi - t0));
+    const int j = t0 + m.ti;
+    const double xt = sx[j], yt = sy[j], zt = sz[j];
+    for (int i = threadIdx.x; i < 4 * TILE_TGT; i += TILE_THREADS) tacc[i] = 0.0;
+    if ((int)threadIdx.x < m.ntc) tq[threadIdx.x] = (T)sq[t0 + threadIdx.x];
+    for (int c0 = 0;; c0 += TILE_CAND) {
+      __syncthreads();
+      const int total = R->total;
+      const int nck = min(TILE_CAND, total - c0);
+      for (int k = threadIdx.x; k < nck; k += TILE_THREADS) {
+        const int s = tile_src(R, c0 + k);
+        rxy[k] = make_double2(sx[s], sy[s]);
+        rzs[k] = make_double2(sz[s], __longlong_as_double((long long)s));
+        cq[k] = (T)sq[s];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cacc[u * TILE_CAND + k] = 0.0;
+      }
+      __syncthreads();
+      const int bs = nck > 0 ? (nck + m.nsl - 1) / m.nsl : 0;     // block length
+      const int b0 = m.sl * bs, bend = b0 + bs;
+      int k = b0 + (bs > 0 ? m.ti % bs : 0);
+      int nq = 0;
+      // two candidates per step: both records are read before either is
+      // tested (independent chains the compiler interleaves)
+      for (int it = 0; it < bs; it += 2) {
+        int kk[2], kr[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          kk[h] = k;
+          kr[h] = k < nck ? k : 0;
+          if (++k == bend) k = b0;
+        }
+        double2 pxy[2], pzs[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) { pxy[h] = rxy[kr[h]]; pzs[h] = rzs[kr[h]]; }
+        double pz[2];
+        int ps[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) { pz[h] = pzs[h].x; ps[h] = (int)__double_as_longlong(pzs[h].y); }
+        bool in[2];
+        T dx[2], dy[2], dz[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const bool valid = m.act && it + h < bs && kk[h] < nck;
+          double ex = xt - pxy[h].x, ey = yt - pxy[h].y, ez = zt - pz[h];
+          ex = fma(-L0, rint(ex * iL0), ex);
+          ey = fma(-L1, rint(ey * iL1), ey);
+          ez = fma(-L2, rint(ez * iL2), ez);
+          in[h] = valid && ps[h] > j && fma(ez, ez, fma(ey, ey, ex * ex)) < rc2;
+          dx[h] = (T)ex; dy[h] = (T)ey; dz[h] = (T)ez;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const T val[3] = {dx[h], dy[h], dz[h]};
+          nq = tq_push(Q, nq, in[h], val, tq_pack(m.ti, kk[h]));
+          if (nq >= WAVE) {
+            eval(lane);
+            nq = tq_pop(Q, nq);
+          }
+        }
+      }
+      if (lane < nq) eval(lane);
+      __syncthreads();
+      // the candidates' sums (each site appears in one staged set of a work item)
+      for (int k2 = threadIdx.x; k2 < nck; k2 += TILE_THREADS) {
+        const double fx = cacc[k2], fy = cacc[TILE_CAND + k2], fz = cacc[2 * TILE_CAND + k2];
+        const double u = cacc[3 * TILE_CAND + k2];
+        if (fx != 0.0 || fy != 0.0 || fz != 0.0 || u != 0.0) {
+          const int s = (int)__double_as_longlong(rzs[k2].y);
+          atomicAdd(fp + s, fx);
+          atomicAdd(fp + n + s, fy);
+          atomicAdd(fp + 2 * (size_t)n + s, fz);
+          if (us) atomicAdd(us + s, 0.5 * KE * sq[s] * u);
+        }
+      }
+      if (c0 + TILE_CAND >= total) break;
+    }
+    // the targets' sums (their staged sets are done: the last barrier above
+    // follows every evaluation)
+    if ((int)threadIdx.x < m.ntc) {
+      const int jj = t0 + threadIdx.x;
+      atomicAdd(fp + jj, tacc[threadIdx.x]);
+      atomicAdd(fp + n + jj, tacc[TILE_TGT + threadIdx.x]);
+      atomicAdd(fp + 2 * (size_t)n + jj, tacc[2 * TILE_TGT + threadIdx.x]);
+      if (us) atomicAdd(us + jj, 0.5 * KE * sq[jj] * tacc[3 * TILE_TGT + threadIdx.x]);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------ site-electrode pairs
+
+// LDS of the site-electrode tile: the runs, the staged atoms (x, y, z and
+// the two charge sets), six FP64 sums per target, one queue per wavefront
+template <typename T>
+struct ElecTileLds {
+  static constexpr size_t runs = 0;
+  static constexpr size_t pos = (sizeof(TileRuns) + 15) / 16 * 16;                  // x, y, z [TILE_CAND]
+  static constexpr size_t qab = pos + 3 * (size_t)TILE_CAND * sizeof(double);       // qa, qb [TILE_CAND]
+  static constexpr size_t tacc = qab + (2 * (size_t)TILE_CAND * sizeof(T) + 15) / 16 * 16;
+  static constexpr size_t queue = tacc + 6 * (size_t)TILE_TGT * sizeof(double);
+  static constexpr size_t queue_bytes = (TileQ<T, 3>::bytes() + 15) / 16 * 16;
+  static constexpr size_t total = queue + (TILE_THREADS / WAVE) * queue_bytes;
+};
+
+// Site-electrode sums of the targets [t_lo, t_hi) of cell c (a launch of
+// their own beside site_pairs_n3_tile): f_elec gets sum_i q_i g1(r) r_vec
+// for the charges qa_s and qb_s (without k_e and Q_j).  A cell with no
+// electrode atom in reach writes zeros.  Thread (ti, sl) tests candidates
+// sl, sl + nsl, ... (the lanes of a wavefront read few distinct atoms,
+// which LDS broadcasts); pairs inside the cutoff are evaluated 64 at a time
+// from the wavefront's queue.  lds: ElecTileLds<T>::total bytes.
+template <typename T>
+__device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
+                                               unsigned char* lds) {
+  using L = ElecTileLds<T>;
+  constexpr int CAP = TileQ<T, 3>::CAP;
+  const int n = pa.st.n;
+  double* fe = pa.f_elec + (size_t)frame * 6 * n;
+  if (pa.el.run_n[c] == 0) {
+    for (int i = t_lo + threadIdx.x; i < t_hi; i += TILE_THREADS)
+#pragma unroll
+      for (int u = 0; u < 6; ++u) fe[(size_t)u * n + i] = 0.0;
+    return;
+  }
+  TileRuns* R = reinterpret_cast<TileRuns*>(lds + L::runs);
+  double* px = reinterpret_cast<double*>(lds + L::pos);
+  double* py = px + TILE_CAND;
+  double* pz = py + TILE_CAND;
+  T* qa = reinterpret_cast<T*>(lds + L::qab);
+  T* qb = qa + TILE_CAND;
+  double* tacc = reinterpret_cast<double*>(lds + L::tacc);       // [6][TILE_TGT]
+  TileQ<T, 3> Q;
+  Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const size_t fo = (size_t)frame * n;
+  const double* sx = pa.st.x + fo; const double* sy = pa.st.y + fo; const double* sz = pa.st.z + fo;
+  const double* qa_e = pa.qa_s + (size_t)frame * pa.qa_stride;
+  const double* qb_e = pa.qb_s;
+  const double L0 = pa.cell.L[0], L1 = pa.cell.L[1], L2 = pa.cell.L[2];
+  const double iL0 = pa.cell.invL[0], iL1 = pa.cell.invL[1], iL2 = pa.cell.invL[2];
+  const double rc2 = pa.rc2;
+  const T alpha = pa.alpha, eta = pa.eta;
+  if (threadIdx.x < WAVE) tile_elec_runs(pa.el, c, R);
+
+  auto eval = [&](int l) {
+    const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l];
+    const int e = Q.t[l];
+    const int tt = e & 255, kc = e >> 8;
+    const T g = g1_force(qx * qx + qy * qy + qz * qz, alpha, eta);
+    const T wa = qa[kc] * g, wb = qb[kc] * g;
+    atomicAdd(tacc + tt, (double)(wa * qx));
+    atomicAdd(tacc + TILE_TGT + tt, (double)(wa * qy));
+    atomicAdd(tacc + 2 * TILE_TGT + tt, (double)(wa * qz));
+    atomicAdd(tacc + 3 * TILE_TGT + tt, (double)(wb * qx));
+    atomicAdd(tacc + 4 * TILE_TGT + tt, (double)(wb * qy));
+    atomicAdd(tacc + 5 * TILE_TGT + tt, (double)(wb * qz));
+  };
+
+  for (int t0 = t_lo; t0 < t_hi; t0 += TILE_TGT) {
+    const TileMap m(min(TILE_TGT, t_hi - t0));
+    const double xt = sx[t0 + m.ti], yt = sy[t0 + m.ti], zt = sz[t0 + m.ti];
+    for (int i = threadIdx.x; i < 6 * TILE_TGT; i += TILE_THREADS) tacc[i] = 0.0;
+    for (int c0 = 0;; c0 += TILE_CAND) {
+      __syncthreads();
+      const int total = R->total;
+      const int nck = min(TILE_CAND, total - c0);
+      for (int k = threadIdx.x; k < nck; k += TILE_THREADS) {
+        const int s = tile_src(R, c0 + k);
+        px[k] = pa.el.x[s]; py[k] = pa.el.y[s]; pz[k] = pa.el.z[s];
+        qa[k] = (T)qa_e[s];
+        qb[k] = qb_e ? (T)qb_e[s] : (T)0;
+      }
+      __syncthreads();
+      const int n_iter = nck > 0 ? (nck + m.nsl - 1) / m.nsl : 0;
+      int nq = 0;
+      for (int it = 0; it < n_iter; it += 2) {
+        int kk[2], kr[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          kk[h] = m.sl + (it + h) * m.nsl;
+          kr[h] = kk[h] < nck ? kk[h] : 0;
+        }
+        double ax[2], ay[2], az[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) { ax[h] = px[kr[h]]; ay[h] = py[kr[h]]; az[h] = pz[kr[h]]; }
+        bool in[2];
+        T dx[2], dy[2], dz[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double ex = xt - ax[h], ey = yt - ay[h], ez = zt - az[h];
+          ex = fma(-L0, rint(ex * iL0), ex);
+          ey = fma(-L1, rint(ey * iL1), ey);
+          ez = fma(-L2, rint(ez * iL2), ez);
+          in[h] = m.act && kk[h] < nck && fma(ez, ez, fma(ey, ey, ex * ex)) < rc2;
+          dx[h] = (T)ex; dy[h] = (T)ey; dz[h] = (T)ez;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const T val[3] = {dx[h], dy[h], dz[h]};
+          nq = tq_push(Q, nq, in[h], val, tq_pack(m.ti, kk[h]));
+          if (nq >= WAVE) {
+            eval(lane);
+            nq = tq_pop(Q, nq);
+          }
+        }
+      }
+      if (lane < nq) eval(lane);
+      if (c0 + TILE_CAND >= total) break;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < m.ntc) {
+      const int jj = t0 + threadIdx.x;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) fe[(size_t)u * n + jj] = tacc[u * TILE_TGT + threadIdx.x];
+    }
+    __syncthreads();
+  }
+}
+
 // Real-space electrolyte potential at the electrode atoms of one work item
 // (atoms [t_lo, t_hi) of cell c, t_hi - t_lo <= TILE_TGT):
 // k_e sum_j Q_j g1(r) over the sites of the stencil.  lds: PairLds<T>::total.
@@ -404,10 +717,21 @@ __device__ __forceinline__ void real_b_block(const RealBArgs<T>& rb, int b, int 
   real_b_tile(rb, rb.item_c[b], rb.item_lo[b], rb.item_hi[b], frame, lds);
 }
 
+// work item b of a frame's tiles (tsplit > 0): share b mod tsplit of the
+// sorted sites [t_lo, t_hi) of cell b / tsplit
+__device__ __forceinline__ void tile_item(int b, int tsplit, const int* cs, int& c, int& t_lo, int& t_hi) {
+  c = b / tsplit;
+  const int s = b - c * tsplit;
+  const int lo = cs[c], n = cs[c + 1] - lo;
+  t_lo = lo + (int)(((long long)n * s) / tsplit);
+  t_hi = lo + (int)(((long long)n * (s + 1)) / tsplit);
+}
+
 // workgroup b of a frame's site-pair work: with tsplit > 0, share b mod
-// tsplit of the sites of cell b / tsplit (tiles); with tsplit == 0, sites
-// 4b .. 4b+3 (one wavefront each)
-template <typename T>
+// tsplit of the sites of cell b / tsplit (tiles; MODE 1: the site-electrode
+// sums alone, MODE 2: the site-site sums with every pair once); with
+// tsplit == 0, sites 4b .. 4b+3 (one wavefront each)
+template <typename T, int MODE = 0>
 __device__ __forceinline__ void site_pairs_block(const PairArgs<T>& pa, int b, int frame, unsigned char* lds) {
   if (pa.tsplit == 0) {
     // one wavefront per site, four per workgroup
@@ -417,12 +741,11 @@ __device__ __forceinline__ void site_pairs_block(const PairArgs<T>& pa, int b, i
                       reinterpret_cast<T*>(lds + (threadIdx.x >> 6) * wave_scratch_bytes<T>()));
     return;
   }
-  const int c = b / pa.tsplit, s = b - c * pa.tsplit;
-  const int* cs = pa.st.cell_start + (size_t)frame * (pa.cell.n_cells + 1);
-  const int lo = cs[c], n = cs[c + 1] - lo;
-  const int t_lo = lo + (int)(((long long)n * s) / pa.tsplit);
-  const int t_hi = lo + (int)(((long long)n * (s + 1)) / pa.tsplit);
-  site_pairs_tile(pa, c, t_lo, t_hi, frame, lds);
+  int c, t_lo, t_hi;
+  tile_item(b, pa.tsplit, pa.st.cell_start + (size_t)frame * (pa.cell.n_cells + 1), c, t_lo, t_hi);
+  if (MODE == 2) site_pairs_n3_tile(pa, c, t_lo, t_hi, frame, lds);
+  else if (MODE == 1) site_elec_tile(pa, c, t_lo, t_hi, frame, lds);
+  else site_pairs_tile(pa, c, t_lo, t_hi, frame, lds);
 }
 
 }  // namespace cpm
