@@ -213,41 +213,48 @@ int cell_coord_host(double x, double L, int n) {
 double wrap_host(double x, double L) { return x - L * std::floor(x / L); }
 
 // Stencil groups of every cell of the grid: the distinct neighbour cells
-// (offsets -1, 0, 1 per axis, fewer where the axis has under 3 cells),
+// (offsets -r .. r along an axis of reach r: 1, or 2 along a z axis cut into
+// cells half the cutoff thick; fewer where the axis has under 2r + 1 cells),
 // sorted and joined into runs of consecutive cell indices [lo, hi); n[c]
 // groups per cell at [c * STENCIL_MAX + k] (unused entries 0).  forward:
 // only the cells of index >= c (the stencil is symmetric, so every pair of
-// neighbouring cells appears once, in the lower cell's list).
-void stencil_groups(const Cell& cl, std::vector<int>& n, std::vector<int>& lo, std::vector<int>& hi,
-                    bool forward = false) {
+// neighbouring cells appears once, in the lower cell's list).  Returns the
+// largest group count.
+int stencil_groups(const Cell& cl, const int* reach, std::vector<int>& n, std::vector<int>& lo, std::vector<int>& hi,
+                   bool forward = false) {
   n.assign(cl.n_cells, 0);
   lo.assign((size_t)cl.n_cells * STENCIL_MAX, 0);
   hi.assign((size_t)cl.n_cells * STENCIL_MAX, 0);
-  auto count = [](int m) { return m >= 3 ? 3 : m; };
-  auto nb = [](int c, int s, int m) {
-    if (m >= 3) { int v = c + s - 1; return v < 0 ? v + m : (v >= m ? v - m : v); }
-    return (c + s) % m;
-  };
+  int most = 0;
   for (int c = 0; c < cl.n_cells; ++c) {
-    const int cx = c % cl.nc[0], cy = (c / cl.nc[0]) % cl.nc[1], cz = c / (cl.nc[0] * cl.nc[1]);
+    const int cc[3] = {c % cl.nc[0], (c / cl.nc[0]) % cl.nc[1], c / (cl.nc[0] * cl.nc[1])};
+    std::vector<int> nbr[3];
+    for (int a = 0; a < 3; ++a) {
+      const int m = cl.nc[a], r = reach[a];
+      if (m >= 2 * r + 1)
+        for (int s = -r; s <= r; ++s) nbr[a].push_back(((cc[a] + s) % m + m) % m);
+      else
+        for (int s = 0; s < m; ++s) nbr[a].push_back(s);
+    }
     std::vector<int> cells;
-    for (int a = 0; a < count(cl.nc[2]); ++a)
-      for (int b = 0; b < count(cl.nc[1]); ++b)
-        for (int d = 0; d < count(cl.nc[0]); ++d)
-          cells.push_back((nb(cz, a, cl.nc[2]) * cl.nc[1] + nb(cy, b, cl.nc[1])) * cl.nc[0] + nb(cx, d, cl.nc[0]));
+    for (int z : nbr[2])
+      for (int y : nbr[1])
+        for (int x : nbr[0]) cells.push_back((z * cl.nc[1] + y) * cl.nc[0] + x);
     std::sort(cells.begin(), cells.end());
     cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
     if (forward) cells.erase(std::remove_if(cells.begin(), cells.end(), [c](int v) { return v < c; }), cells.end());
     int k = -1;
     for (size_t t = 0; t < cells.size(); ++t) {
       if (t == 0 || cells[t] != cells[t - 1] + 1) {
-        ++k;
+        if (++k >= STENCIL_MAX) return STENCIL_MAX + 1;
         lo[(size_t)c * STENCIL_MAX + k] = cells[t];
       }
       hi[(size_t)c * STENCIL_MAX + k] = cells[t] + 1;
     }
     n[c] = k + 1;
+    most = std::max(most, k + 1);
   }
+  return most;
 }
 
 // half-space k-vectors with 0 < |k| <= kcut: (n1 > 0) or (n1 == 0, n2 > 0) or (n1 == n2 == 0, n3 > 0)
@@ -1034,15 +1041,28 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   // cells
   Cell& cl = c->cell;
   cl.n_cells = 1;
+  // cells at least rcut wide (offsets -1, 0, 1 cover the cutoff), except
+  // that a z axis of three or more rcut is cut into cells at least rcut/2
+  // thick with offsets -2 .. 2: the candidates of a cell then span 2.5 rcut
+  // of z instead of 3 (the electrolyte fills whole x-y planes of the cells
+  // this method simulates, so the z window sets the count)
+  int reach[3] = {1, 1, 1};
   for (int k = 0; k < 3; ++k) {
     cl.L[k] = c->box[k];
     cl.invL[k] = 1.0 / c->box[k];
     cl.nc[k] = std::max(1, (int)std::floor(c->box[k] / c->rcut));
     cl.img[k] = (int)std::floor(c->rcut / c->box[k] + 0.5);
-    cl.n_cells *= cl.nc[k];
   }
+  if (cl.nc[2] >= 3) {
+    cl.nc[2] = (int)std::floor(2.0 * c->box[2] / c->rcut);
+    reach[2] = 2;
+  }
+  for (int k = 0; k < 3; ++k) cl.n_cells *= cl.nc[k];
   std::vector<int> gn, glo, ghi;
-  stencil_groups(cl, gn, glo, ghi);
+  if (stencil_groups(cl, reach, gn, glo, ghi) > STENCIL_MAX) {
+    fail(c, CPM_EINVAL, "cell stencil needs more than %d index runs", STENCIL_MAX);
+    return bad(CPM_EINVAL);
+  }
   {
     int *dn, *dl, *dh;
     if ((r = upload(c, &dn, gn)) || (r = upload(c, &dl, glo)) || (r = upload(c, &dh, ghi))) return bad(r);
@@ -1051,7 +1071,7 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
   if (cl.img[0] == 0 && cl.img[1] == 0 && cl.img[2] == 0) {
     // forward stencils for the many-frame pair tiles (each pair once)
     std::vector<int> fn, flo, fhi;
-    stencil_groups(cl, fn, flo, fhi, true);
+    stencil_groups(cl, reach, fn, flo, fhi, true);
     if ((r = upload(c, &c->d_fwd_n, fn)) || (r = upload(c, &c->d_fwd_lo, flo)) || (r = upload(c, &c->d_fwd_hi, fhi)))
       return bad(r);
   }

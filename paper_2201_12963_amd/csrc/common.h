@@ -13,7 +13,7 @@ constexpr double EPS0 = 1.0 / (4.0 * M_PI * KE);   // e / (V nm)
 constexpr int WAVE = 64;
 constexpr int MAX_FFT_FACTORS = 12;
 constexpr int MAX_ORDER = 7;
-constexpr int STENCIL_MAX = 27;   // neighbour cells of a cell, itself included
+constexpr int STENCIL_MAX = 32;   // index runs of the neighbour cells of a cell (one wavefront half)
 // dynamic LDS a launch may ask for (of the 160 KiB of a gfx950 CU)
 constexpr size_t LDS_LIMIT = 150 * 1024;
 // cell tiles of the real-space sums: workgroup size, candidates staged in

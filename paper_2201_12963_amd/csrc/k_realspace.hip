@@ -36,18 +36,20 @@ __global__ __launch_bounds__(TILE_THREADS, 5) void k_site_pairs_tiles(PairArgs<T
   site_pairs_block<T, 0>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }
 
-// The site-electrode sums of many frames beside k_site_pairs_n3 (~28 KB of
-// LDS; four workgroups per CU leave the FP64 form its registers).
+// The site-electrode sums of many frames beside k_site_pairs_n3 (~20 KB of
+// LDS in FP64): four workgroups per CU leave the FP64 form its registers,
+// the FP32 form fits six.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS, 4) void k_site_elec_tiles(PairArgs<T> pa) {
+__global__ __launch_bounds__(TILE_THREADS, sizeof(T) == 8 ? 4 : 6) void k_site_elec_tiles(PairArgs<T> pa) {
   extern __shared__ __align__(16) unsigned char lds[];
   site_pairs_block<T, 1>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }
 
 // The site-site sums of many frames with every pair once (no periodic
-// images): ~35 KB of LDS, four workgroups per CU.
+// images): ~25 KB of LDS in FP64; four workgroups per CU in FP64 (a fifth
+// would spill registers in the pair loop), six in FP32.
 template <typename T>
-__global__ __launch_bounds__(TILE_THREADS, 4) void k_site_pairs_n3(PairArgs<T> pa) {
+__global__ __launch_bounds__(TILE_THREADS, sizeof(T) == 8 ? 4 : 6) void k_site_pairs_n3(PairArgs<T> pa) {
   extern __shared__ __align__(16) unsigned char lds[];
   site_pairs_block<T, 2>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }

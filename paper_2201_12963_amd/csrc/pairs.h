@@ -9,8 +9,9 @@
 // test the candidate partners of the neighbouring cells and queue those
 // inside the cutoff (pair compaction below).  Partners are read from the
 // cell-sorted SoA copies, so a wavefront's loads of one cell are contiguous;
-// the 27 (or fewer, for cells that wrap onto themselves) neighbour cells
-// cover every partner within rcut because cells are at least rcut wide.
+// the neighbour cells (offsets -1 .. 1, or -2 .. 2 along a z axis of cells
+// at least rcut/2 thick; fewer for cells that wrap onto themselves) cover
+// every partner within rcut.
 // Extra periodic images are looped over when the cell is shorter than
 // 2 rcut.  Results are reduced across the wavefront with butterfly shuffles;
 // no atomics, so every run sums in the same order.
@@ -150,7 +151,7 @@ __device__ __forceinline__ int stencil_runs(const Cell& cell, int c, const int* 
 // Cell of a wrapped position (the binning's arithmetic on the wrapped
 // coordinate; where the two could differ in the last bit the position lies
 // on a cell face, and the stencils of both cells hold every partner within
-// the cutoff, cells being at least rcut wide)
+// the cutoff: a stencil reaches at least rcut past its cell on every side)
 __device__ __forceinline__ int site_cell(const Cell& cell, double x, double y, double z) {
   return (cell_coord(z, cell.L[2], cell.nc[2]) * cell.nc[1] + cell_coord(y, cell.L[1], cell.nc[1])) * cell.nc[0] +
          cell_coord(x, cell.L[0], cell.nc[0]);

@@ -135,6 +135,32 @@ __device__ __forceinline__ int tq_pop(const TileQ<T, NV>& q, int n) {
   return rest;
 }
 
+// per-wavefront queue of packed pair indices alone (the displacement is
+// recomputed when the pair is evaluated)
+struct TileQI {
+  static constexpr int CAP = 2 * WAVE;
+  int* t;      // [CAP]
+  static constexpr size_t bytes() { return (size_t)CAP * sizeof(int); }
+  __device__ __forceinline__ void bind(unsigned char* base) { t = reinterpret_cast<int*>(base); }
+};
+
+__device__ __forceinline__ int tqi_push(const TileQI& q, int n, bool in, int e) {
+  const unsigned long long m = __ballot(in);
+  if (in) q.t[n + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = e;
+  __builtin_amdgcn_wave_barrier();
+  return n + __popcll(m);
+}
+
+__device__ __forceinline__ int tqi_pop(const TileQI& q, int n) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int rest = n - WAVE;
+  const int e = lane < rest ? q.t[WAVE + lane] : 0;
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rest) q.t[lane] = e;
+  __builtin_amdgcn_wave_barrier();
+  return rest;
+}
+
 // LDS of a tile workgroup: runs, staged candidates (FP64 position, NQ
 // charges of T, one int), four queues of NV values, NACC FP64 accumulators
 // per target (FP64 LDS atomics in every precision: FP32 ones measured
@@ -369,7 +395,8 @@ __device__ __forceinline__ void site_pairs_tile(const PairArgs<T>& pa, int c, in
 // LDS of the each-pair-once tile: the stencil runs, the staged candidates
 // (two 16-byte arrays: x and y; z and the sorted index; then the charges),
 // four FP64 sums per candidate and per target (force, potential), the
-// targets' charges, one pair queue per wavefront
+// targets' positions and charges, one queue of packed pair indices per
+// wavefront
 template <typename T>
 struct PairN3Lds {
   static constexpr size_t runs = 0;
@@ -377,9 +404,10 @@ struct PairN3Lds {
   static constexpr size_t cq = rec + (size_t)TILE_CAND * 32;
   static constexpr size_t cacc = cq + ((size_t)TILE_CAND * sizeof(T) + 15) / 16 * 16;
   static constexpr size_t tacc = cacc + 4 * (size_t)TILE_CAND * sizeof(double);
-  static constexpr size_t tq = tacc + 4 * (size_t)TILE_TGT * sizeof(double);
+  static constexpr size_t tpos = tacc + 4 * (size_t)TILE_TGT * sizeof(double);     // x, y, z [TILE_TGT]
+  static constexpr size_t tq = tpos + 3 * (size_t)TILE_TGT * sizeof(double);
   static constexpr size_t queue = tq + ((size_t)TILE_TGT * sizeof(T) + 15) / 16 * 16;
-  static constexpr size_t queue_bytes = (TileQ<T, 3>::bytes() + 15) / 16 * 16;
+  static constexpr size_t queue_bytes = (TileQI::bytes() + 15) / 16 * 16;
   static constexpr size_t total = queue + (TILE_THREADS / WAVE) * queue_bytes;
 };
 
@@ -399,15 +427,15 @@ template <typename T>
 __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
                                                    unsigned char* lds) {
   using L = PairN3Lds<T>;
-  constexpr int CAP = TileQ<T, 3>::CAP;
   TileRuns* R = reinterpret_cast<TileRuns*>(lds + L::runs);
   double2* rxy = reinterpret_cast<double2*>(lds + L::rec);      // [TILE_CAND] x, y
   double2* rzs = rxy + TILE_CAND;                                 // [TILE_CAND] z, sorted index
   T* cq = reinterpret_cast<T*>(lds + L::cq);                      // [TILE_CAND]
   double* cacc = reinterpret_cast<double*>(lds + L::cacc);       // [4][TILE_CAND]
   double* tacc = reinterpret_cast<double*>(lds + L::tacc);       // [4][TILE_TGT]
+  double* tpx = reinterpret_cast<double*>(lds + L::tpos);        // [3][TILE_TGT]
   T* tq = reinterpret_cast<T*>(lds + L::tq);                      // [TILE_TGT]
-  TileQ<T, 3> Q;
+  TileQI Q;
   Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
   const int lane = threadIdx.x & (WAVE - 1);
   const int n = pa.st.n;
@@ -423,11 +451,18 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
   const T alpha = pa.alpha;
   if (threadIdx.x < WAVE) tile_runs_fwd(pa.fwd_n, pa.fwd_lo, pa.fwd_hi, c, cs, R);
 
-  // queued pairs: both ends' sums
+  // queued pair e = target | candidate << 8: the displacement again (the
+  // same operations as the test, so the same bits), then both ends' sums
   auto eval = [&](int l) {
-    const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l];
     const int e = Q.t[l];
     const int tt = e & 255, kc = e >> 8;
+    const double2 cxy = rxy[kc];
+    const double cz = rzs[kc].x;
+    double ex = tpx[tt] - cxy.x, ey = tpx[TILE_TGT + tt] - cxy.y, ez = tpx[2 * TILE_TGT + tt] - cz;
+    ex = fma(-L0, rint(ex * iL0), ex);
+    ey = fma(-L1, rint(ey * iL1), ey);
+    ez = fma(-L2, rint(ez * iL2), ez);
+    const T qx = (T)ex, qy = (T)ey, qz = (T)ez;
     const T qc = cq[kc], qt = tq[tt];
     T g, pot;
     g0_terms(qx * qx + qy * qy + qz * qz, alpha, g, pot);
@@ -447,7 +482,10 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
     const int j = t0 + m.ti;
     const double xt = sx[j], yt = sy[j], zt = sz[j];
     for (int i = threadIdx.x; i < 4 * TILE_TGT; i += TILE_THREADS) tacc[i] = 0.0;
-    if ((int)threadIdx.x < m.ntc) tq[threadIdx.x] = (T)sq[t0 + threadIdx.x];
+    if ((int)threadIdx.x < m.ntc) {
+      tq[threadIdx.x] = (T)sq[t0 + threadIdx.x];
+      tpx[threadIdx.x] = xt; tpx[TILE_TGT + threadIdx.x] = yt; tpx[2 * TILE_TGT + threadIdx.x] = zt;
+    }
     for (int c0 = 0;; c0 += TILE_CAND) {
       __syncthreads();
       const int total = R->total;
@@ -478,29 +516,22 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
         double2 pxy[2], pzs[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) { pxy[h] = rxy[kr[h]]; pzs[h] = rzs[kr[h]]; }
-        double pz[2];
-        int ps[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) { pz[h] = pzs[h].x; ps[h] = (int)__double_as_longlong(pzs[h].y); }
         bool in[2];
-        T dx[2], dy[2], dz[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const bool valid = m.act && it + h < bs && kk[h] < nck;
-          double ex = xt - pxy[h].x, ey = yt - pxy[h].y, ez = zt - pz[h];
+          double ex = xt - pxy[h].x, ey = yt - pxy[h].y, ez = zt - pzs[h].x;
           ex = fma(-L0, rint(ex * iL0), ex);
           ey = fma(-L1, rint(ey * iL1), ey);
           ez = fma(-L2, rint(ez * iL2), ez);
-          in[h] = valid && ps[h] > j && fma(ez, ez, fma(ey, ey, ex * ex)) < rc2;
-          dx[h] = (T)ex; dy[h] = (T)ey; dz[h] = (T)ez;
+          in[h] = valid && (int)__double_as_longlong(pzs[h].y) > j && fma(ez, ez, fma(ey, ey, ex * ex)) < rc2;
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const T val[3] = {dx[h], dy[h], dz[h]};
-          nq = tq_push(Q, nq, in[h], val, tq_pack(m.ti, kk[h]));
+          nq = tqi_push(Q, nq, in[h], tq_pack(m.ti, kk[h]));
           if (nq >= WAVE) {
             eval(lane);
-            nq = tq_pop(Q, nq);
+            nq = tqi_pop(Q, nq);
           }
         }
       }
@@ -536,15 +567,17 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
 // ------------------------------------------------ site-electrode pairs
 
 // LDS of the site-electrode tile: the runs, the staged atoms (x, y, z and
-// the two charge sets), six FP64 sums per target, one queue per wavefront
+// the two charge sets), six FP64 sums and the position of every target, one
+// queue of packed pair indices per wavefront
 template <typename T>
 struct ElecTileLds {
   static constexpr size_t runs = 0;
   static constexpr size_t pos = (sizeof(TileRuns) + 15) / 16 * 16;                  // x, y, z [TILE_CAND]
   static constexpr size_t qab = pos + 3 * (size_t)TILE_CAND * sizeof(double);       // qa, qb [TILE_CAND]
   static constexpr size_t tacc = qab + (2 * (size_t)TILE_CAND * sizeof(T) + 15) / 16 * 16;
-  static constexpr size_t queue = tacc + 6 * (size_t)TILE_TGT * sizeof(double);
-  static constexpr size_t queue_bytes = (TileQ<T, 3>::bytes() + 15) / 16 * 16;
+  static constexpr size_t tpos = tacc + 6 * (size_t)TILE_TGT * sizeof(double);      // x, y, z [TILE_TGT]
+  static constexpr size_t queue = tpos + 3 * (size_t)TILE_TGT * sizeof(double);
+  static constexpr size_t queue_bytes = (TileQI::bytes() + 15) / 16 * 16;
   static constexpr size_t total = queue + (TILE_THREADS / WAVE) * queue_bytes;
 };
 
@@ -559,7 +592,6 @@ template <typename T>
 __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
                                                unsigned char* lds) {
   using L = ElecTileLds<T>;
-  constexpr int CAP = TileQ<T, 3>::CAP;
   const int n = pa.st.n;
   double* fe = pa.f_elec + (size_t)frame * 6 * n;
   if (pa.el.run_n[c] == 0) {
@@ -575,7 +607,8 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
   T* qa = reinterpret_cast<T*>(lds + L::qab);
   T* qb = qa + TILE_CAND;
   double* tacc = reinterpret_cast<double*>(lds + L::tacc);       // [6][TILE_TGT]
-  TileQ<T, 3> Q;
+  double* tpx = reinterpret_cast<double*>(lds + L::tpos);        // [3][TILE_TGT]
+  TileQI Q;
   Q.bind(lds + L::queue + (threadIdx.x >> 6) * L::queue_bytes);
   const int lane = threadIdx.x & (WAVE - 1);
   const size_t fo = (size_t)frame * n;
@@ -588,10 +621,16 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
   const T alpha = pa.alpha, eta = pa.eta;
   if (threadIdx.x < WAVE) tile_elec_runs(pa.el, c, R);
 
+  // queued pair e = target | atom << 8: the displacement again (the same
+  // operations as the test), then the target's sums for both charge sets
   auto eval = [&](int l) {
-    const T qx = Q.v[l], qy = Q.v[CAP + l], qz = Q.v[2 * CAP + l];
     const int e = Q.t[l];
     const int tt = e & 255, kc = e >> 8;
+    double ex = tpx[tt] - px[kc], ey = tpx[TILE_TGT + tt] - py[kc], ez = tpx[2 * TILE_TGT + tt] - pz[kc];
+    ex = fma(-L0, rint(ex * iL0), ex);
+    ey = fma(-L1, rint(ey * iL1), ey);
+    ez = fma(-L2, rint(ez * iL2), ez);
+    const T qx = (T)ex, qy = (T)ey, qz = (T)ez;
     const T g = g1_force(qx * qx + qy * qy + qz * qz, alpha, eta);
     const T wa = qa[kc] * g, wb = qb[kc] * g;
     atomicAdd(tacc + tt, (double)(wa * qx));
@@ -606,6 +645,9 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
     const TileMap m(min(TILE_TGT, t_hi - t0));
     const double xt = sx[t0 + m.ti], yt = sy[t0 + m.ti], zt = sz[t0 + m.ti];
     for (int i = threadIdx.x; i < 6 * TILE_TGT; i += TILE_THREADS) tacc[i] = 0.0;
+    if ((int)threadIdx.x < m.ntc) {
+      tpx[threadIdx.x] = xt; tpx[TILE_TGT + threadIdx.x] = yt; tpx[2 * TILE_TGT + threadIdx.x] = zt;
+    }
     for (int c0 = 0;; c0 += TILE_CAND) {
       __syncthreads();
       const int total = R->total;
@@ -630,7 +672,6 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
 #pragma unroll
         for (int h = 0; h < 2; ++h) { ax[h] = px[kr[h]]; ay[h] = py[kr[h]]; az[h] = pz[kr[h]]; }
         bool in[2];
-        T dx[2], dy[2], dz[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           double ex = xt - ax[h], ey = yt - ay[h], ez = zt - az[h];
@@ -638,15 +679,13 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
           ey = fma(-L1, rint(ey * iL1), ey);
           ez = fma(-L2, rint(ez * iL2), ez);
           in[h] = m.act && kk[h] < nck && fma(ez, ez, fma(ey, ey, ex * ex)) < rc2;
-          dx[h] = (T)ex; dy[h] = (T)ey; dz[h] = (T)ez;
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const T val[3] = {dx[h], dy[h], dz[h]};
-          nq = tq_push(Q, nq, in[h], val, tq_pack(m.ti, kk[h]));
+          nq = tqi_push(Q, nq, in[h], tq_pack(m.ti, kk[h]));
           if (nq >= WAVE) {
             eval(lane);
-            nq = tq_pop(Q, nq);
+            nq = tqi_pop(Q, nq);
           }
         }
       }

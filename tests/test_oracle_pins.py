@@ -470,6 +470,32 @@ def test_cell_binning_is_a_valid_stable_partition():
         assert np.all(x >= lo - 1e-12) and np.all(x < hi + 1e-12)
 
 
+def test_cell_stencil_holds_every_pair_within_the_cutoff():
+    """Brute force over the site pairs of the doubled paper cell: the cells of
+    two sites within rcut lie within the grid's reach of each other along
+    every axis (periodically), so the stencils of the pair kernels see them."""
+    w = workload("paper", "dc")
+    n = cells.cell_grid(w.box, w.rcut)
+    reach = cells.cell_reach(w.box, w.rcut)
+    assert n[2] * w.rcut / 2 <= w.box[2] and all(
+        L / m * r >= w.rcut - 1e-12 for L, m, r in zip(w.box, n, reach) if m >= 2 * r + 1)
+    x = np.asarray(w.site_xyz)
+    cid = cells.cell_of(x, w.box, n)
+    cz, rem = np.divmod(cid, n[0] * n[1])
+    cy, cx = np.divmod(rem, n[0])
+    cc = (cx, cy, cz)
+    d = x[:, :, None] - x[:, None, :]
+    box = np.asarray(w.box)[:, None, None]
+    d -= box * np.round(d / box)
+    i, j = np.nonzero(((d ** 2).sum(0) < w.rcut ** 2) & ~np.eye(x.shape[1], dtype=bool))
+    assert i.size > 100000
+    for a in range(3):
+        if n[a] >= 2 * reach[a] + 1:
+            gap = np.abs(cc[a][i] - cc[a][j])
+            gap = np.minimum(gap, n[a] - gap)
+            assert gap.max() <= reach[a]
+
+
 # --------------------------------------------------------------------------
 # three charged sheets per electrode (snapshot re-solves)
 # --------------------------------------------------------------------------
