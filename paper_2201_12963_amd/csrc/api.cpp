@@ -597,6 +597,12 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     pa.f_elec = c->d_felec;
     fa.f_elec = c->d_felec;
     pa.fwd_n = c->d_fwd_n; pa.fwd_lo = c->d_fwd_lo; pa.fwd_hi = c->d_fwd_hi;
+    // |z_target - z_centre| <= w/2, so a pair within rcut has the staged
+    // image's |dz| < rcut + w/2 < Lz/2 when Lz > 2 rcut + w: the same image
+    // as the minimum image of the pair
+    const Cell& cl = c->cell;
+    pa.zshift = (cl.img[0] | cl.img[1] | cl.img[2]) == 0 && cl.nc[2] >= 5 &&
+                cl.L[2] > 2.0 * c->rcut + cl.L[2] / cl.nc[2];
   }
   if (c->kspace == CPM_KSPACE_PPPM) {
     // the electrode spread stays a kernel of its own: only the few planes

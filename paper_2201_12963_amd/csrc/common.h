@@ -278,6 +278,12 @@ struct PairArgs {
   const int* fwd_n;
   const int* fwd_lo;
   const int* fwd_hi;
+  // z images fixed per work item (no periodic images, the z axis cut into at
+  // least five cells and longer than 2 rcut plus a cell): candidates are
+  // staged at the z image nearest the centre of the target cell, which for
+  // every pair inside the cutoff is the minimum image, so the tests skip the
+  // z minimum image
+  int zshift;
 };
 
 // z pass: a lane prefetches the multiplier (and saved spectrum) of the

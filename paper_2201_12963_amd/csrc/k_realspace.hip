@@ -39,19 +39,19 @@ __global__ __launch_bounds__(TILE_THREADS, 5) void k_site_pairs_tiles(PairArgs<T
 // The site-electrode sums of many frames beside k_site_pairs_n3 (~20 KB of
 // LDS in FP64): four workgroups per CU leave the FP64 form its registers,
 // the FP32 form fits six.
-template <typename T>
+template <typename T, bool ZS>
 __global__ __launch_bounds__(TILE_THREADS, sizeof(T) == 8 ? 4 : 6) void k_site_elec_tiles(PairArgs<T> pa) {
   extern __shared__ __align__(16) unsigned char lds[];
-  site_pairs_block<T, 1>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
+  site_pairs_block<T, 1, ZS>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }
 
 // The site-site sums of many frames with every pair once (no periodic
 // images): ~25 KB of LDS in FP64; four workgroups per CU in FP64 (a fifth
 // would spill registers in the pair loop), six in FP32.
-template <typename T>
+template <typename T, bool ZS>
 __global__ __launch_bounds__(TILE_THREADS, sizeof(T) == 8 ? 4 : 6) void k_site_pairs_n3(PairArgs<T> pa) {
   extern __shared__ __align__(16) unsigned char lds[];
-  site_pairs_block<T, 2>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
+  site_pairs_block<T, 2, ZS>(pa, xcd_block(blockIdx.x, gridDim.x), blockIdx.y, lds);
 }
 
 // clears n doubles (the atomic targets of the each-pair-once tiles)
@@ -393,8 +393,17 @@ void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
     // site-electrode pairs
     launch_zero(s, pa.f_pair, (size_t)n_frames * 3 * pa.st.n);
     if (pa.u_site) launch_zero(s, pa.u_site, (size_t)n_frames * pa.st.n);
-    hipLaunchKernelGGL(k_site_pairs_n3<T>, grid, dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit, true), s, pa);
-    if (pa.f_elec) hipLaunchKernelGGL(k_site_elec_tiles<T>, grid, dim3(TILE_THREADS), ElecTileLds<T>::total, s, pa);
+    const size_t lds = site_pairs_lds<T>(pa.tsplit, true);
+    if (pa.zshift)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_site_pairs_n3<T, true>), grid, dim3(TILE_THREADS), lds, s, pa);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_site_pairs_n3<T, false>), grid, dim3(TILE_THREADS), lds, s, pa);
+    if (pa.f_elec && pa.zshift)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_site_elec_tiles<T, true>), grid, dim3(TILE_THREADS), ElecTileLds<T>::total,
+                         s, pa);
+    else if (pa.f_elec)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_site_elec_tiles<T, false>), grid, dim3(TILE_THREADS), ElecTileLds<T>::total,
+                         s, pa);
   } else if (pa.tsplit > 0) {
     hipLaunchKernelGGL(k_site_pairs_tiles<T>, grid, dim3(TILE_THREADS), site_pairs_lds<T>(pa.tsplit, false), s, pa);
   } else {

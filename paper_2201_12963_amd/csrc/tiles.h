@@ -423,7 +423,7 @@ struct PairN3Lds {
 // candidates.  The candidates' sums go to f_pair and u_site with FP64
 // atomic adds after every staged set, the targets' after the last one: both
 // arrays are cleared before the launch.  lds: PairN3Lds<T>::total bytes.
-template <typename T>
+template <typename T, bool ZS>
 __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
                                                    unsigned char* lds) {
   using L = PairN3Lds<T>;
@@ -449,6 +449,9 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
   const double iL0 = pa.cell.invL[0], iL1 = pa.cell.invL[1], iL2 = pa.cell.invL[2];
   const double rc2 = pa.rc2;
   const T alpha = pa.alpha;
+  // ZS: the z image nearest the target cell's centre zc, fixed at staging
+  const int ncz = pa.cell.nc[2];
+  const double zc = ((double)(c / (pa.cell.nc[0] * pa.cell.nc[1])) + 0.5) * (L2 / ncz);
   if (threadIdx.x < WAVE) tile_runs_fwd(pa.fwd_n, pa.fwd_lo, pa.fwd_hi, c, cs, R);
 
   // queued pair e = target | candidate << 8: the displacement again (the
@@ -461,7 +464,7 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
     double ex = tpx[tt] - cxy.x, ey = tpx[TILE_TGT + tt] - cxy.y, ez = tpx[2 * TILE_TGT + tt] - cz;
     ex = fma(-L0, rint(ex * iL0), ex);
     ey = fma(-L1, rint(ey * iL1), ey);
-    ez = fma(-L2, rint(ez * iL2), ez);
+    if (!ZS) ez = fma(-L2, rint(ez * iL2), ez);
     const T qx = (T)ex, qy = (T)ey, qz = (T)ez;
     const T qc = cq[kc], qt = tq[tt];
     T g, pot;
@@ -492,8 +495,10 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
       const int nck = min(TILE_CAND, total - c0);
       for (int k = threadIdx.x; k < nck; k += TILE_THREADS) {
         const int s = tile_src(R, c0 + k);
+        double z = sz[s];
+        if (ZS) z -= L2 * rint((z - zc) * iL2);
         rxy[k] = make_double2(sx[s], sy[s]);
-        rzs[k] = make_double2(sz[s], __longlong_as_double((long long)s));
+        rzs[k] = make_double2(z, __longlong_as_double((long long)s));
         cq[k] = (T)sq[s];
 #pragma unroll
         for (int u = 0; u < 4; ++u) cacc[u * TILE_CAND + k] = 0.0;
@@ -523,7 +528,7 @@ __device__ __forceinline__ void site_pairs_n3_tile(const PairArgs<T>& pa, int c,
           double ex = xt - pxy[h].x, ey = yt - pxy[h].y, ez = zt - pzs[h].x;
           ex = fma(-L0, rint(ex * iL0), ex);
           ey = fma(-L1, rint(ey * iL1), ey);
-          ez = fma(-L2, rint(ez * iL2), ez);
+          if (!ZS) ez = fma(-L2, rint(ez * iL2), ez);
           in[h] = valid && (int)__double_as_longlong(pzs[h].y) > j && fma(ez, ez, fma(ey, ey, ex * ex)) < rc2;
         }
 #pragma unroll
@@ -588,7 +593,7 @@ struct ElecTileLds {
 // sl, sl + nsl, ... (the lanes of a wavefront read few distinct atoms,
 // which LDS broadcasts); pairs inside the cutoff are evaluated 64 at a time
 // from the wavefront's queue.  lds: ElecTileLds<T>::total bytes.
-template <typename T>
+template <typename T, bool ZS>
 __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int t_lo, int t_hi, int frame,
                                                unsigned char* lds) {
   using L = ElecTileLds<T>;
@@ -619,6 +624,9 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
   const double iL0 = pa.cell.invL[0], iL1 = pa.cell.invL[1], iL2 = pa.cell.invL[2];
   const double rc2 = pa.rc2;
   const T alpha = pa.alpha, eta = pa.eta;
+  // ZS: the z image nearest the target cell's centre zc, fixed at staging
+  const int ncz = pa.cell.nc[2];
+  const double zc = ((double)(c / (pa.cell.nc[0] * pa.cell.nc[1])) + 0.5) * (L2 / ncz);
   if (threadIdx.x < WAVE) tile_elec_runs(pa.el, c, R);
 
   // queued pair e = target | atom << 8: the displacement again (the same
@@ -629,7 +637,7 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
     double ex = tpx[tt] - px[kc], ey = tpx[TILE_TGT + tt] - py[kc], ez = tpx[2 * TILE_TGT + tt] - pz[kc];
     ex = fma(-L0, rint(ex * iL0), ex);
     ey = fma(-L1, rint(ey * iL1), ey);
-    ez = fma(-L2, rint(ez * iL2), ez);
+    if (!ZS) ez = fma(-L2, rint(ez * iL2), ez);
     const T qx = (T)ex, qy = (T)ey, qz = (T)ez;
     const T g = g1_force(qx * qx + qy * qy + qz * qz, alpha, eta);
     const T wa = qa[kc] * g, wb = qb[kc] * g;
@@ -654,7 +662,9 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
       const int nck = min(TILE_CAND, total - c0);
       for (int k = threadIdx.x; k < nck; k += TILE_THREADS) {
         const int s = tile_src(R, c0 + k);
-        px[k] = pa.el.x[s]; py[k] = pa.el.y[s]; pz[k] = pa.el.z[s];
+        double z = pa.el.z[s];
+        if (ZS) z -= L2 * rint((z - zc) * iL2);
+        px[k] = pa.el.x[s]; py[k] = pa.el.y[s]; pz[k] = z;
         qa[k] = (T)qa_e[s];
         qb[k] = qb_e ? (T)qb_e[s] : (T)0;
       }
@@ -677,7 +687,7 @@ __device__ __forceinline__ void site_elec_tile(const PairArgs<T>& pa, int c, int
           double ex = xt - ax[h], ey = yt - ay[h], ez = zt - az[h];
           ex = fma(-L0, rint(ex * iL0), ex);
           ey = fma(-L1, rint(ey * iL1), ey);
-          ez = fma(-L2, rint(ez * iL2), ez);
+          if (!ZS) ez = fma(-L2, rint(ez * iL2), ez);
           in[h] = m.act && kk[h] < nck && fma(ez, ez, fma(ey, ey, ex * ex)) < rc2;
         }
 #pragma unroll
@@ -768,9 +778,10 @@ __device__ __forceinline__ void tile_item(int b, int tsplit, const int* cs, int&
 
 // workgroup b of a frame's site-pair work: with tsplit > 0, share b mod
 // tsplit of the sites of cell b / tsplit (tiles; MODE 1: the site-electrode
-// sums alone, MODE 2: the site-site sums with every pair once); with
-// tsplit == 0, sites 4b .. 4b+3 (one wavefront each)
-template <typename T, int MODE = 0>
+// sums alone, MODE 2: the site-site sums with every pair once; ZS: z images
+// fixed at staging, PairArgs::zshift); with tsplit == 0, sites 4b .. 4b+3
+// (one wavefront each)
+template <typename T, int MODE = 0, bool ZS = false>
 __device__ __forceinline__ void site_pairs_block(const PairArgs<T>& pa, int b, int frame, unsigned char* lds) {
   if (pa.tsplit == 0) {
     // one wavefront per site, four per workgroup
@@ -782,8 +793,8 @@ __device__ __forceinline__ void site_pairs_block(const PairArgs<T>& pa, int b, i
   }
   int c, t_lo, t_hi;
   tile_item(b, pa.tsplit, pa.st.cell_start + (size_t)frame * (pa.cell.n_cells + 1), c, t_lo, t_hi);
-  if (MODE == 2) site_pairs_n3_tile(pa, c, t_lo, t_hi, frame, lds);
-  else if (MODE == 1) site_elec_tile(pa, c, t_lo, t_hi, frame, lds);
+  if (MODE == 2) site_pairs_n3_tile<T, ZS>(pa, c, t_lo, t_hi, frame, lds);
+  else if (MODE == 1) site_elec_tile<T, ZS>(pa, c, t_lo, t_hi, frame, lds);
   else site_pairs_tile(pa, c, t_lo, t_hi, frame, lds);
 }
 
