@@ -137,3 +137,33 @@ def test_batch_matches_single_frames(torch_dev, geometry):
         assert abs(Eb[fi, vi, 0] - ref["u_coul"]) < 1e-9 * abs(ref["u_coul"])
         assert abs(Eb[fi, vi, 1] - ref["e_cp"]) < 1e-9 * abs(ref["e_cp"])
     ctx.close()
+
+
+def test_batch_matches_single_frames_large_cell(torch_dev):
+    """The batched pair tiles on a grid whose x-y stencil is a proper subset of
+    the cross-section (5 x 5 cells in x-y, 21 along z): forward stencils of
+    several runs, periodic wraps in x and y, each pair once.  The one-frame
+    path of the same cell is held to the oracle in test_gpu_mixed."""
+    torch = torch_dev
+    from workloads import perturbed_frames
+    _say("[gpu] batch large ff")
+    w = workload("large", "ff")
+    frames = perturbed_frames(w, 3, sigma=0.05, seed=9)
+    dvs = np.array([0.0, 3.0])
+    ctx, stream = gpu_context(torch, w)
+    X = torch.tensor(frames, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        Qb, Fb, Eb = ctx.solve_batch(X, dvs)
+    stream.synchronize()
+    Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
+    for fi in range(frames.shape[0]):
+        x = torch.tensor(frames[fi], dtype=torch.float64, device="cuda")
+        for vi, dv in enumerate(dvs):
+            with torch.cuda.stream(stream):
+                q, f, e = ctx.solve(x, float(dv))
+            stream.synchronize()
+            q, f, e = q.cpu().numpy(), f.cpu().numpy(), e.cpu().numpy()
+            assert np.abs(Qb[fi, vi] - q).max() < 1e-11
+            assert rel_rms(Fb[fi, vi], f) < 1e-10
+            assert np.abs(Eb[fi, vi] - e).max() < 1e-9 * np.abs(e).max()
+    ctx.close()
