@@ -1712,7 +1712,7 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
     a.Q[g] = a.nf[g] * a.kt * d->tau * d->tau;
   }
   const double* mass_c; const double* sig_c; const double* eps_c; const int *ms, *mz, *mg, *mo; const double* cx;
-  double *f_lj, *u_lj, *xi, *eta, *q, *fc, *en;
+  double *f_lj, *u_lj, *xi, *eta, *nh_in, *part, *q, *fc, *en;
   int r;
   std::vector<double> zeros(2 * MD_MAX_GROUPS, 0.0);
   std::vector<int> sizes(d->mol_size, d->mol_size + d->n_mol), groups(d->mol_group, d->mol_group + d->n_mol);
@@ -1721,16 +1721,52 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
     if (!(d->site_eps[j] >= 0.0)) { for (void* p : md->allocs) hipFree(p); delete md; return fail(c, CPM_EINVAL, "epsilon must be >= 0"); }
     sqeps[j] = std::sqrt(d->site_eps[j]);
   }
+  // z windows of the Lennard-Jones partners over the electrostatic cell grid:
+  // the graphene atoms sorted by wrapped z, and per z layer the (at most
+  // two, across the periodic boundary) index ranges of those within lj_cut
+  const Cell& cl = c->cell;
+  const int ncz = cl.nc[2], nlj = d->n_lj_elec;
+  const double Lz = cl.L[2], wz = Lz / ncz;
+  std::vector<int> cord(nlj);
+  std::vector<double> cz(nlj);
+  for (int i = 0; i < nlj; ++i) { cord[i] = i; cz[i] = wrap_host(d->lj_elec_xyz[2 * nlj + i], Lz); }
+  std::stable_sort(cord.begin(), cord.end(), [&](int p1, int p2) { return cz[p1] < cz[p2]; });
+  std::vector<double> cxs(3 * (size_t)nlj), czs(nlj);
+  for (int i = 0; i < nlj; ++i) {
+    for (int k = 0; k < 3; ++k) cxs[(size_t)k * nlj + i] = d->lj_elec_xyz[(size_t)k * nlj + cord[i]];
+    czs[i] = cz[cord[i]];
+  }
+  std::vector<int> crun(4 * (size_t)ncz, 0);
+  auto lower = [&](double z) { return (int)(std::lower_bound(czs.begin(), czs.end(), z) - czs.begin()); };
+  const double pad = d->lj_cut + 1e-9 * Lz;                  // margin for the rounding of the layer bounds
+  for (int L = 0; L < ncz; ++L) {
+    const double lo = L * wz - pad, hi = (L + 1) * wz + pad;
+    int* q2 = &crun[4 * (size_t)L];
+    if (hi - lo >= Lz) { q2[0] = 0; q2[1] = nlj; continue; }
+    if (lo < 0.0) {                 // [lo + Lz, Lz) and [0, hi)
+      q2[0] = lower(lo + Lz); q2[1] = nlj; q2[2] = 0; q2[3] = lower(hi);
+    } else if (hi > Lz) {           // [lo, Lz) and [0, hi - Lz)
+      q2[0] = lower(lo); q2[1] = nlj; q2[2] = 0; q2[3] = lower(hi - Lz);
+    } else {
+      q2[0] = lower(lo); q2[1] = lower(hi);
+    }
+  }
+  const int reach = (int)std::ceil(pad / wz);                 // layers of sites within lj_cut, the same margin
+  const int* crun_d;
   if ((r = up(&mass_c, d->site_mass, ns)) || (r = up(&sig_c, d->site_sigma, ns)) || (r = up(&eps_c, sqeps.data(), ns)) ||
       (r = up(&ms, start.data(), d->n_mol)) || (r = up(&mz, sizes.data(), d->n_mol)) ||
       (r = up(&mg, groups.data(), d->n_mol)) || (r = up(&mo, mol_of.data(), ns)) ||
-      (r = up(&cx, d->lj_elec_xyz, 3 * (size_t)d->n_lj_elec)) || (r = up(&f_lj, (const double*)nullptr, 3 * (size_t)ns)) ||
+      (r = up(&cx, cxs.data(), 3 * (size_t)nlj)) || (r = up(&crun_d, crun.data(), 4 * (size_t)ncz)) ||
+      (r = up(&f_lj, (const double*)nullptr, 3 * (size_t)ns)) ||
       (r = up(&u_lj, (const double*)nullptr, ns)) || (r = up(&xi, zeros.data(), MD_MAX_GROUPS)) ||
-      (r = up(&eta, zeros.data(), MD_MAX_GROUPS)) || (r = up(&q, (const double*)nullptr, c->n_elec)) ||
+      (r = up(&eta, zeros.data(), MD_MAX_GROUPS)) ||
+      (r = up(&nh_in, zeros.data(), 2 * MD_MAX_GROUPS)) || (r = up(&part, (const double*)nullptr, (size_t)md_workgroups(d->n_mol) * MD_PART)) || (r = up(&q, (const double*)nullptr, c->n_elec)) ||
       (r = up(&fc, (const double*)nullptr, 3 * (size_t)ns)) || (r = up(&en, zeros.data(), 2)))
     return bad(r);
   a.mass = mass_c; a.sigma = sig_c; a.sqeps = eps_c; a.mol_start = ms; a.mol_size = mz; a.mol_group = mg; a.mol_of = mo;
-  a.cx = cx; a.f_lj = f_lj; a.u_lj = u_lj; a.xi = xi; a.eta = eta; a.f_c = fc; a.energy = en;
+  a.cx = cx; a.f_lj = f_lj; a.u_lj = u_lj; a.xi = xi; a.eta = eta; a.nh_in = nh_in; a.md_part = part; a.f_c = fc; a.energy = en;
+  a.cell_start = c->d_cell_start; a.order = c->d_order; a.carbon_run = crun_d;
+  a.nc_z = ncz; a.nxy = cl.nc[0] * cl.nc[1]; a.lj_reach = reach; a.Lz = Lz;
   md->d_q = q; md->d_fc = fc; md->d_energy = en;
   *out = md;
   return CPM_OK;
@@ -1742,9 +1778,14 @@ namespace {
 // with a charge solve (update) or at the charges of the last update
 int md_forces(cpm_md* md, double* x, double dv, bool update) {
   cpm_ctx* c = md->c;
+  // the Coulomb part first: its binning of x gives the Lennard-Jones kernel
+  // its z windows
+  TRY(update ? enqueue_solve<double>(c, x, dv, md->d_q, md->d_fc, md->d_energy)
+             : enqueue_forces_at<double>(c, x, dv, md->d_q, md->d_fc));
+  md->a.cell_start = c->d_cell_start;
+  md->a.order = c->d_order;
   launch_lj(c->stream, md->a);
-  if (update) return enqueue_solve<double>(c, x, dv, md->d_q, md->d_fc, md->d_energy);
-  return enqueue_forces_at<double>(c, x, dv, md->d_q, md->d_fc);
+  return CPM_OK;
 }
 
 }  // namespace

@@ -577,11 +577,12 @@ void launch_profile(hipStream_t s, const ProfileArgs& p);
 
 // ----------------------------------------------------- MD loop (k_md.hip)
 
-constexpr int MD_THREADS = 1024;      // the integrator's one workgroup
 constexpr int MD_MAX_GROUPS = 2;      // thermostat groups (doubled cell: one per sub-cell)
 constexpr int MD_MAX_ITER = 500;      // SHAKE / RATTLE sweeps
 constexpr double MD_TOL = 1e-13;      // relative constraint tolerance
 constexpr int MD_THERMO = 4;          // per-step record: KE, U_LJ, E_cp (last update), thermostat energy (kJ/mol)
+constexpr int MD_PART = MD_MAX_GROUPS + 1;   // per-workgroup partials: sum m v^2 per group, sum U_LJ
+inline int md_workgroups(int n_mol) { return (n_mol + WAVE - 1) / WAVE; }   // integrator: a wavefront per 64 molecules
 
 struct MDArgs {
   int n_site, n_mol, n_groups, n_lj_elec, thermostat;
@@ -591,11 +592,23 @@ struct MDArgs {
   double* u_lj;                         // [n_site] Lennard-Jones energy share per site (written by k_lj)
   const double* mass; const double* sigma; const double* sqeps;   // [n_site] (sqeps: sqrt(epsilon))
   const int* mol_start; const int* mol_size; const int* mol_group; const int* mol_of;
-  const double* cx;                     // [3][n_lj_elec] graphene atoms
+  const double* cx;                     // [3][n_lj_elec] graphene atoms, sorted by wrapped z
   double carbon_sigma, carbon_sqeps, lj_cut, bond, dt, kt;
+  // partners by z window (the electrostatic binning of the same positions):
+  // a site of z layer cz (of nc_z layers of the cell grid, nxy cells each)
+  // meets the sites of layers cz - lj_reach .. cz + lj_reach (all of them when
+  // that spans the axis) and the graphene atoms of carbon_run[4 cz ..] (two
+  // index ranges [lo, hi) of the sorted atoms within lj_cut of the layer);
+  // cell_start / order: the binning's per-cell starts and sorted-to-original
+  // site indices
+  const int* cell_start; const int* order; const int* carbon_run;
+  int nc_z, nxy, lj_reach;
+  double Lz;
   double box[3], inv_box[3];
   double nf[MD_MAX_GROUPS], Q[MD_MAX_GROUPS];
   double* xi; double* eta;              // [n_groups] thermostat state (device)
+  double* nh_in;                        // [2][MD_MAX_GROUPS] xi, eta as the update found them
+  double* md_part;                      // [md_workgroups(n_mol)][MD_PART] the integrator's partial sums
   const double* energy;                 // [2] the last charge update's {U_coul, E_cp} (eV)
   double* thermo_out;                   // [step][MD_THERMO] or nullptr
 };

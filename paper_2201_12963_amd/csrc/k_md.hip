@@ -16,24 +16,25 @@
 // steps on the multipliers; a 3 x 3 linear solve for the velocities): the
 // same constrained positions and velocities as one constraint at a time.
 //
-// k_lj: one workgroup per site over all sites and graphene atoms (minimum
-// image, pairs of one molecule excluded, energy shifted to zero at the
-// cutoff; Lorentz-Berthelot mixing from the stored square roots of epsilon).  k_md_integrate: one 1024-thread workgroup for the whole
-// electrolyte (a thread per molecule, its sites in registers), since the
-// thermostat needs the groups' kinetic energies between the two halves of
-// the update; one launch joins the end of one step and the start of the
-// next.
+// k_lj: one workgroup per site over the sites and graphene atoms of the z
+// layers within the cutoff (the layers of the electrostatic cell grid, whose
+// binning of the same positions runs first; minimum image, pairs of one
+// molecule excluded, energy shifted to zero at the cutoff; Lorentz-Berthelot
+// mixing from the stored square roots of epsilon).  k_md_end / k_md_start:
+// the update, a thread per molecule with its sites in registers; one pair of
+// launches joins the end of one step and the start of the next.
 #include "common.h"
+#include "bin.h"
 
 namespace cpm {
 
 constexpr double KB_KJ = 0.0083144626;      // kJ/mol/K
 constexpr double EV_KJ = 96.48533212;       // kJ/mol per eV
 
-__global__ __launch_bounds__(256) void k_lj(MDArgs a) {
-  // one workgroup per site: its 256 threads share the partners, so that a
-  // site's sum is spread over four wavefronts and every CU holds many sites
-  __shared__ double red[4][4];
+template <int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_lj(MDArgs a) {
+  // one workgroup of NW wavefronts per site, its threads sharing the partners
+  __shared__ double red[NW][4];
   const int i = blockIdx.x;
   const double xi = a.x[i], yi = a.x[a.n_site + i], zi = a.x[2 * a.n_site + i];
   const double si = a.sigma[i], qi = a.sqeps[i];
@@ -54,20 +55,40 @@ __global__ __launch_bounds__(256) void k_lj(MDArgs a) {
       u += uw * (4.0 * eps * (s6 * s6 - s6) - 4.0 * eps * (c6 * c6 - c6));
     }
   };
-  for (int j = threadIdx.x; j < a.n_site; j += blockDim.x) {
-    if (a.mol_of[j] == mi) continue;
-    pair(xi - a.x[j], yi - a.x[a.n_site + j], zi - a.x[2 * a.n_site + j], 0.5 * (si + a.sigma[j]), qi * a.sqeps[j]);
+  // the z layer of the site, by the binning's arithmetic on the same
+  // coordinate, and the sorted-site ranges of the layers within lj_reach
+  int cz;
+  wrap_and_cell(zi, a.Lz, a.nc_z, cz);
+  const int* cs = a.cell_start;
+  int lo0 = 0, hi0 = a.n_site, lo1 = 0, hi1 = 0;
+  if (2 * a.lj_reach + 1 < a.nc_z) {
+    const int la = cz - a.lj_reach, lb = cz + a.lj_reach;
+    if (la < 0) { lo0 = cs[(la + a.nc_z) * a.nxy]; hi1 = cs[(lb + 1) * a.nxy]; }
+    else if (lb >= a.nc_z) { lo0 = cs[la * a.nxy]; hi1 = cs[(lb + 1 - a.nc_z) * a.nxy]; }
+    else { lo0 = cs[la * a.nxy]; hi0 = cs[(lb + 1) * a.nxy]; }
   }
+  auto site = [&](int s) {
+    const int j = a.order[s];
+    if (a.mol_of[j] == mi) return;
+    pair(xi - a.x[j], yi - a.x[a.n_site + j], zi - a.x[2 * a.n_site + j], 0.5 * (si + a.sigma[j]), qi * a.sqeps[j]);
+  };
+  for (int s = lo0 + threadIdx.x; s < hi0; s += blockDim.x) site(s);
+  for (int s = lo1 + threadIdx.x; s < hi1; s += blockDim.x) site(s);
   uw = 1.0;
   const double sc = 0.5 * (si + a.carbon_sigma), ec = qi * a.carbon_sqeps;
-  for (int j = threadIdx.x; j < a.n_lj_elec; j += blockDim.x)
-    pair(xi - a.cx[j], yi - a.cx[a.n_lj_elec + j], zi - a.cx[2 * a.n_lj_elec + j], sc, ec);
+  const int* cr = a.carbon_run + 4 * cz;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    for (int j = cr[2 * h] + threadIdx.x; j < cr[2 * h + 1]; j += blockDim.x)
+      pair(xi - a.cx[j], yi - a.cx[a.n_lj_elec + j], zi - a.cx[2 * a.n_lj_elec + j], sc, ec);
   fx = wave_sum(fx); fy = wave_sum(fy); fz = wave_sum(fz); u = wave_sum(u);
   const int w = threadIdx.x / WAVE;
   if ((threadIdx.x & (WAVE - 1)) == 0) { red[w][0] = fx; red[w][1] = fy; red[w][2] = fz; red[w][3] = u; }
   __syncthreads();
   if (threadIdx.x < 4) {
-    const double t = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    double t = red[0][threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) t += red[k][threadIdx.x];
     if (threadIdx.x < 3) a.f_lj[threadIdx.x * a.n_site + i] = t;
     else a.u_lj[i] = t;
   }
@@ -162,22 +183,6 @@ __device__ void rattle3(const MDArgs& a, double v[3][3], const double p[3][3], c
     }
 }
 
-// per-group totals of a per-thread partial (every thread gets the totals)
-__device__ void group_sums(int n_groups, const double* part, double* out, double* red) {
-  const int nw = blockDim.x / WAVE, w = threadIdx.x / WAVE;
-  for (int g = 0; g < n_groups; ++g) {
-    const double s = wave_sum(part[g]);
-    if ((threadIdx.x & (WAVE - 1)) == 0) red[g * nw + w] = s;
-  }
-  __syncthreads();
-  for (int g = 0; g < n_groups; ++g) {
-    double t = 0.0;
-    for (int k = 0; k < nw; ++k) t += red[g * nw + k];
-    out[g] = t;
-  }
-  __syncthreads();
-}
-
 // one molecule's sites (up to 3) between global memory and registers
 struct MolRegs {
   int s0, n, g;
@@ -200,93 +205,117 @@ __device__ __forceinline__ double mol_force(const MDArgs& a, const MolRegs& r, i
   return a.f_lj[o] + EV_KJ * a.f_c[o];
 }
 
-// one thermostat half step: the groups' sum m v^2 from the velocities in
-// memory, xi and eta advanced identically in every thread, velocities scaled
-__device__ void thermostat_half(const MDArgs& a, double* xi, double* eta, double* red) {
-  double part[MD_MAX_GROUPS] = {};
-  for (int mol = threadIdx.x; mol < a.n_mol; mol += blockDim.x) {
-    const int s0 = a.mol_start[mol], n = a.mol_size[mol], g = a.mol_group[mol];
-    for (int s = 0; s < n; ++s) {
-      double vv = 0.0;
-      _Pragma("unroll") for (int k = 0; k < 3; ++k) { const double c = a.v[k * a.n_site + s0 + s]; vv += c * c; }
-      part[g] += a.mass[s0 + s] * vv;
-    }
-  }
-  double k2[MD_MAX_GROUPS], scale[MD_MAX_GROUPS];
-  group_sums(a.n_groups, part, k2, red);
-  for (int g = 0; g < a.n_groups; ++g) {
-    xi[g] += 0.25 * a.dt * (k2[g] - a.nf[g] * a.kt) / a.Q[g];
-    eta[g] += 0.5 * a.dt * xi[g];
-    scale[g] = exp(-0.5 * a.dt * xi[g]);
-    k2[g] *= scale[g] * scale[g];
-    xi[g] += 0.25 * a.dt * (k2[g] - a.nf[g] * a.kt) / a.Q[g];
-  }
-  for (int mol = threadIdx.x; mol < a.n_mol; mol += blockDim.x) {
-    const int s0 = a.mol_start[mol], n = a.mol_size[mol], g = a.mol_group[mol];
-    for (int s = 0; s < n; ++s)
-      _Pragma("unroll") for (int k = 0; k < 3; ++k) a.v[k * a.n_site + s0 + s] *= scale[g];
-  }
+// the value of a per-group register array at a run-time group index
+__device__ __forceinline__ double group_pick(const double* v, int g) {
+  double r = v[0];
+  _Pragma("unroll") for (int k = 1; k < MD_MAX_GROUPS; ++k) if (g == k) r = v[k];
+  return r;
+}
+
+// one Nose-Hoover half step of group g from its sum k2 = sum m v^2 (k2 is
+// left at the scaled velocities' value); returns the velocity scale
+__device__ __forceinline__ double nh_half(const MDArgs& a, int g, double& k2, double& xi, double& eta) {
+  xi += 0.25 * a.dt * (k2 - a.nf[g] * a.kt) / a.Q[g];
+  eta += 0.5 * a.dt * xi;
+  const double scale = exp(-0.5 * a.dt * xi);
+  k2 *= scale * scale;
+  xi += 0.25 * a.dt * (k2 - a.nf[g] * a.kt) / a.Q[g];
+  return scale;
 }
 
 // mode bit 4: RATTLE of the initial velocities; bit 1: end of a step (kick
 // with the new forces, RATTLE, thermostat half step, record rec_step); bit 2:
-// start of a step (thermostat half step, kick, drift, SHAKE).  Every thread
-// handles molecules threadIdx.x + k blockDim.x in every phase, so it only
-// re-reads what it wrote itself; the group sums go through LDS.
-__global__ __launch_bounds__(MD_THREADS) void k_md_integrate(MDArgs a, int mode, int rec_step) {
-  __shared__ double red[MD_MAX_GROUPS * (MD_THREADS / WAVE)];
-  double xi[MD_MAX_GROUPS], eta[MD_MAX_GROUPS];
-  for (int g = 0; g < a.n_groups; ++g) { xi[g] = a.xi[g]; eta[g] = a.eta[g]; }
-  if (mode & 4) {
-    for (int mol = threadIdx.x; mol < a.n_mol; mol += blockDim.x) {
-      MolRegs r;
-      mol_load(a, mol, r);
-      if (r.n != 3) continue;
-      rattle3(a, r.v, r.p, r.m);
-      _Pragma("unroll") for (int s = 0; s < 3; ++s)
-        _Pragma("unroll") for (int k = 0; k < 3; ++k) a.v[k * a.n_site + r.s0 + s] = r.v[k][s];
-    }
-  }
-  if (mode & 1) {
-    for (int mol = threadIdx.x; mol < a.n_mol; mol += blockDim.x) {
-      MolRegs r;
-      mol_load(a, mol, r);
+// start of a step (thermostat half step, kick, drift, SHAKE).  The thermostat
+// needs every group's sum of m v^2 between the kick and the scaling, so an
+// update is two launches of one wavefront per 64 molecules (a thread per
+// molecule): k_md_end does the end-of-step kick and RATTLE and leaves one
+// partial sum per workgroup; k_md_start totals the partials (the same order
+// in every workgroup, so every workgroup holds the same thermostat state),
+// scales, and does the start-of-step kick, drift and SHAKE.  A scaling
+// multiplies sum m v^2 by the square of the scale, so both half steps of a
+// joined end and start come from the one sum.
+__global__ __launch_bounds__(WAVE) void k_md_end(MDArgs a, int mode) {
+  const int mol = blockIdx.x * WAVE + threadIdx.x;
+  double part[MD_MAX_GROUPS] = {};
+  if (mol < a.n_mol) {
+    MolRegs r;
+    mol_load(a, mol, r);
+    if (mode & 1)
       _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
         _Pragma("unroll") for (int k = 0; k < 3; ++k) r.v[k][s] += 0.5 * a.dt * mol_force(a, r, k, s) / r.m[s];
-      if (r.n == 3) rattle3(a, r.v, r.p, r.m);
+    if ((mode & 5) && r.n == 3) rattle3(a, r.v, r.p, r.m);
+    if (mode & 5)
       _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
         _Pragma("unroll") for (int k = 0; k < 3; ++k) a.v[k * a.n_site + r.s0 + s] = r.v[k][s];
-    }
-    if (a.thermostat) thermostat_half(a, xi, eta, red);
-    if (a.thermo_out) {
-      double part[MD_MAX_GROUPS] = {}, tot[MD_MAX_GROUPS];
-      for (int mol = threadIdx.x; mol < a.n_mol; mol += blockDim.x) {
-        MolRegs r;
-        mol_load(a, mol, r);
-        _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
-          part[0] += 0.5 * r.m[s] * (r.v[0][s] * r.v[0][s] + r.v[1][s] * r.v[1][s] + r.v[2][s] * r.v[2][s]);
+    double mv2 = 0.0;
+    _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
+      mv2 += r.m[s] * (r.v[0][s] * r.v[0][s] + r.v[1][s] * r.v[1][s] + r.v[2][s] * r.v[2][s]);
+    _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) if (g == r.g) part[g] = mv2;
+  }
+  double ul = 0.0;
+  if ((mode & 1) && a.thermo_out)
+    for (int i = mol; i < a.n_site; i += gridDim.x * WAVE) ul += a.u_lj[i];
+  _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) part[g] = wave_sum(part[g]);
+  ul = wave_sum(ul);
+  if (threadIdx.x == 0) {
+    double* o = a.md_part + (size_t)blockIdx.x * MD_PART;
+    _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) o[g] = part[g];
+    o[MD_MAX_GROUPS] = ul;
+    // the thermostat state that k_md_start reads (it writes a.xi, a.eta)
+    if (blockIdx.x == 0)
+      _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) {
+        a.nh_in[g] = a.xi[g];
+        a.nh_in[MD_MAX_GROUPS + g] = a.eta[g];
       }
-      group_sums(1, part, tot, red);
-      const double ke = tot[0];
-      part[0] = 0.0;
-      for (int i = threadIdx.x; i < a.n_site; i += blockDim.x) part[0] += a.u_lj[i];
-      group_sums(1, part, tot, red);
-      if (threadIdx.x == 0) {
-        double th = 0.0;
-        for (int g = 0; g < a.n_groups; ++g) th += 0.5 * a.Q[g] * xi[g] * xi[g] + a.nf[g] * a.kt * eta[g];
-        double* o = a.thermo_out + (size_t)rec_step * MD_THERMO;
-        o[0] = ke;
-        o[1] = tot[0];
-        o[2] = EV_KJ * a.energy[1];
-        o[3] = th;
+  }
+}
+
+__global__ __launch_bounds__(WAVE) void k_md_start(MDArgs a, int mode, int rec_step, int n_part) {
+  double k2[MD_MAX_GROUPS] = {}, ul = 0.0;
+  for (int b = threadIdx.x; b < n_part; b += WAVE) {
+    const double* o = a.md_part + (size_t)b * MD_PART;
+    _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) k2[g] += o[g];
+    ul += o[MD_MAX_GROUPS];
+  }
+  _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) k2[g] = wave_sum(k2[g]);
+  ul = wave_sum(ul);
+  double xi[MD_MAX_GROUPS], eta[MD_MAX_GROUPS], s1[MD_MAX_GROUPS], s2[MD_MAX_GROUPS];
+  _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) {
+    xi[g] = a.nh_in[g]; eta[g] = a.nh_in[MD_MAX_GROUPS + g];
+    s1[g] = 1.0; s2[g] = 1.0;
+  }
+  const bool nh = a.thermostat != 0;
+  if (mode & 1) {
+    if (nh)
+      _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g)
+        if (g < a.n_groups) s1[g] = nh_half(a, g, k2[g], xi[g], eta[g]);
+    if (a.thermo_out && blockIdx.x == 0 && threadIdx.x == 0) {
+      double ke = 0.0, th = 0.0;
+      for (int g = 0; g < a.n_groups; ++g) {
+        ke += 0.5 * k2[g];
+        th += 0.5 * a.Q[g] * xi[g] * xi[g] + a.nf[g] * a.kt * eta[g];
       }
+      double* o = a.thermo_out + (size_t)rec_step * MD_THERMO;
+      o[0] = ke;
+      o[1] = ul;
+      o[2] = EV_KJ * a.energy[1];
+      o[3] = th;
     }
   }
-  if (mode & 2) {
-    if (a.thermostat) thermostat_half(a, xi, eta, red);
-    for (int mol = threadIdx.x; mol < a.n_mol; mol += blockDim.x) {
-      MolRegs r;
-      mol_load(a, mol, r);
+  if ((mode & 2) && nh)
+    _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g)
+      if (g < a.n_groups) s2[g] = nh_half(a, g, k2[g], xi[g], eta[g]);
+  const int mol = blockIdx.x * WAVE + threadIdx.x;
+  if (mol < a.n_mol) {
+    MolRegs r;
+    mol_load(a, mol, r);
+    const double c1 = group_pick(s1, r.g), c2 = group_pick(s2, r.g);
+    _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
+      _Pragma("unroll") for (int k = 0; k < 3; ++k) {
+        if ((mode & 1) && nh) r.v[k][s] *= c1;
+        if ((mode & 2) && nh) r.v[k][s] *= c2;
+      }
+    if (mode & 2) {
       double o[3][3];
       _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
         _Pragma("unroll") for (int k = 0; k < 3; ++k) {
@@ -300,17 +329,23 @@ __global__ __launch_bounds__(MD_THREADS) void k_md_integrate(MDArgs a, int mode,
           a.x[k * a.n_site + r.s0 + s] = r.p[k][s];
           a.v[k * a.n_site + r.s0 + s] = (r.p[k][s] - o[k][s]) / a.dt;
         }
+    } else {
+      _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
+        _Pragma("unroll") for (int k = 0; k < 3; ++k) a.v[k * a.n_site + r.s0 + s] = r.v[k][s];
     }
   }
-  if (threadIdx.x == 0)
+  if (blockIdx.x == 0 && threadIdx.x == 0)
     for (int g = 0; g < a.n_groups; ++g) { a.xi[g] = xi[g]; a.eta[g] = eta[g]; }
 }
 
+constexpr int LJ_WAVES = 4;
 void launch_lj(hipStream_t s, const MDArgs& a) {
-  hipLaunchKernelGGL(k_lj, dim3(a.n_site), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_lj<LJ_WAVES>, dim3(a.n_site), dim3(LJ_WAVES * WAVE), 0, s, a);
 }
 void launch_md_integrate(hipStream_t s, const MDArgs& a, int mode, int rec_step) {
-  hipLaunchKernelGGL(k_md_integrate, dim3(1), dim3(MD_THREADS), 0, s, a, mode, rec_step);
+  const int nb = md_workgroups(a.n_mol);
+  hipLaunchKernelGGL(k_md_end, dim3(nb), dim3(WAVE), 0, s, a, mode);
+  if (mode & 3) hipLaunchKernelGGL(k_md_start, dim3(nb), dim3(WAVE), 0, s, a, mode, rec_step, nb);
 }
 
 }  // namespace cpm
