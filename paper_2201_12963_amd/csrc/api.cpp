@@ -115,6 +115,7 @@ struct cpm_ctx {
   FFTPlan1D px{}, py{}, pz{};
   ZPassArgs za_pot{}, za_field{};
   double *d_G = nullptr, *d_rho = nullptr, *d_phi = nullptr, *d_E = nullptr, *d_rho_e = nullptr;
+  double* d_fpart = nullptr;   // [frame][n_site][6 P] per-plane field shares at the sites (FP64, or FP32 in the mixed form)
   double2 *d_c1 = nullptr, *d_c2 = nullptr, *d_save = nullptr;
   float *d_Gf = nullptr, *d_rhof = nullptr, *d_phif = nullptr, *d_Ef = nullptr, *d_rho_ef = nullptr;
   float2 *d_c1f = nullptr, *d_c2f = nullptr, *d_savef = nullptr;
@@ -386,6 +387,7 @@ int alloc_frames(cpm_ctx* c, int nf) {
     const size_t M = c->mi.M;
     c->n_ek = c->za_pot.n_blocks;
     TRY(dalloc(c, &c->d_ek, (size_t)nf * c->n_ek));
+    if (nf > 1) TRY(dalloc(c, &c->d_fpart, (size_t)nf * ns * 6 * c->mi.order));
     if (!mixed) {
       TRY(dalloc(c, &c->d_rho, nf * M));
       TRY(dalloc(c, &c->d_phi, nf * M));
@@ -630,12 +632,33 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     // c1 -> Ex (re), Ey (im); c2 -> Ez; field meshes are [frame][3][M]
     T* E = B::E(c);
     const size_t M = c->mi.M;
-    rec(c, CPM_KERNEL_FFT_XY_INV_E, s, [=](hipStream_t s) {
-      launch_fft_xy_field_inv_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], B::c1(c), B::c2(c), E, 3 * M);
-    });
     fa.Ea = E;
     fa.Ea_frame_stride = 3 * M;
     fa.Esite = nullptr;
+    fa.Epart = nullptr;
+    if (nf > 1 && fa.f_elec && c->mi.order == 5) {
+      // many frames, with the site-electrode sums in the tiles (order 5):
+      // the inverse pass interpolates the field at the sites plane by plane
+      // (no field mesh is written), and the site-force kernel sums those
+      // shares
+      InterpArgs<T> ia{};
+      const Cell& cl = c->cell;
+      ia.sx = c->d_sx; ia.sy = c->d_sy; ia.sz = c->d_sz;
+      ia.cell_start = c->d_cell_start;
+      ia.n = c->n_site; ia.n_cells = cl.n_cells; ia.nxy = cl.nc[0] * cl.nc[1]; ia.ncz = cl.nc[2];
+      ia.inv_wz = cl.nc[2] / cl.L[2];
+      ia.Eb = fa.Eb;
+      ia.part = reinterpret_cast<T*>(c->d_fpart);
+      ia.mi = c->mi;
+      fa.Epart = ia.part;
+      rec(c, CPM_KERNEL_FFT_XY_INV_E, s, [=](hipStream_t s) {
+        launch_fft_xy_field_inv_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], B::c1(c), B::c2(c), nullptr, 3 * M, &ia);
+      });
+    } else {
+      rec(c, CPM_KERNEL_FFT_XY_INV_E, s, [=](hipStream_t s) {
+        launch_fft_xy_field_inv_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], B::c1(c), B::c2(c), E, 3 * M);
+      });
+    }
   } else {
     rec(c, CPM_KERNEL_SITE_PAIRS, s, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
     if (fa.field_frame) launch_slab_field(s, nf, sl, qa, qa_stride, c->d_slabfield);

@@ -180,6 +180,25 @@ struct ElecSet {       // cell-sorted electrode atoms (static), FP64 positions
   const int* run_n; const int* run_lo; const int* run_hi;
 };
 
+// Many frames: the site-force interpolation done by the field's inverse x-y
+// pass, plane by plane, while each plane's field is in LDS.  A site's
+// stencil covers P consecutive planes (slot = plane - first plane, mod K_z);
+// the workgroup of a plane writes, for every site its stencil reaches, the
+// plane's share of the interpolated field, sum over the in-plane points of
+// w_x w_y E times w_z of the slot, for the frame's field (components 0-2)
+// and the static second field Eb (3-5).  The site-force kernel sums the P
+// slots.  Candidates come from the binning's z layers around the planes.
+template <typename T>
+struct InterpArgs {
+  const double* sx; const double* sy; const double* sz;   // [frame][n] cell-sorted wrapped positions
+  const int* cell_start;        // [frame][n_cells + 1]
+  int n, n_cells, nxy, ncz;     // sites; cells; cells per z layer; z layers
+  double inv_wz;                // z layers per nm
+  const T* Eb;                  // [3][M] static second field, or nullptr
+  T* part;                      // [frame][n][6 P] sorted order, slot-major (slot * 6 + component)
+  MeshInfo mi;
+};
+
 template <typename T>
 struct ForceArgs {
   T alpha, eta;
@@ -192,6 +211,10 @@ struct ForceArgs {
   // explicit-Ewald path instead of a mesh: k-space field at the sites,
   // [frame][3][n_site] in cell-sorted order (V/nm), or nullptr
   const double* Esite;
+  // many frames: the interpolated fields as per-plane partial sums written
+  // by the field's inverse x-y pass ([frame][n_site][6 P], see InterpArgs),
+  // in place of the gathers from Ea and Eb, or nullptr
+  const T* Epart;
   // electrode charges, original order: qa per frame (stride n_elec), qb shared;
   // the same in the electrodes' cell-sorted order (what the pair walk reads)
   const double* qa; size_t qa_frame_stride;
@@ -460,7 +483,8 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
 // both in one launch; E frames frame_stride apart, components M apart
 template <typename T, typename T2>
 void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
-                               const T2* c1, const T2* c2, T* E, size_t frame_stride);
+                               const T2* c1, const T2* c2, T* E, size_t frame_stride,
+                               const InterpArgs<T>* ia = nullptr);
 // z pass; z_pass false launches only the workgroups of pa (if any)
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,

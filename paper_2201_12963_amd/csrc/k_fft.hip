@@ -297,6 +297,110 @@ __device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int si
   return src;
 }
 
+// ------------------------------------------- site interpolation by plane
+
+// The field planes z .. z + np - 1 of one frame are in E (part 0: Ex in .x,
+// Ey in .y; part 1: Ez in .x); `free` holds as many planes.  Every site whose
+// stencil reaches one of them gets, per reached plane, its partial sums of
+// the frame's field and of the static field Eb (InterpArgs).  B-splines of
+// order 5 (the launch takes this path only then), with the stencil start and
+// the weights of the site-force gather (the same spline_triangle_d calls on
+// the same coordinates); a site's stencil covers planes first .. first + 4
+// (mod K_z), i.e. scaled z within 5/2 of the plane, so the candidates are the
+// sites of the binning's z layers within that distance, one layer of margin
+// on each side.  A thread takes a site, its planes one after the other and
+// their rows one after the other (few registers: the x-y pass it rides in
+// keeps its occupancy).
+template <typename T, typename T2>
+__device__ void plane_interp(const InterpArgs<T>& ia, const T2* E, T2* free, int frame, int part, int z0, int np,
+                             int Kx, int Ky, int Kz) {
+  constexpr int P = 5;
+  const int NP = Kx * Ky;
+  const size_t M = ia.mi.M;
+  // the static field's planes beside the frame's
+  for (int i = threadIdx.x; i < np * NP; i += blockDim.x) {
+    const size_t m = (size_t)z0 * NP + i;
+    T2 v = T2{(T)0, (T)0};
+    if (ia.Eb) v = part ? T2{ia.Eb[2 * M + m], (T)0} : T2{ia.Eb[m], ia.Eb[M + m]};
+    free[i] = v;
+  }
+  __syncthreads();
+  // candidate sites: the z layers within P/2 planes (plus a layer) of the
+  // group, as one or two ranges of the cell-sorted sites
+  const double h = ia.mi.h[2];
+  const int la = (int)floor((z0 - 0.5 * P) * h * ia.inv_wz) - 1;
+  const int lb = (int)floor((z0 + np - 1 + 0.5 * P) * h * ia.inv_wz) + 1;
+  const int* cs = ia.cell_start + (size_t)frame * (ia.n_cells + 1);
+  int lo0 = 0, hi0 = ia.n, lo1 = 0, hi1 = 0;
+  if (lb - la + 1 < ia.ncz) {
+    const int a = ((la % ia.ncz) + ia.ncz) % ia.ncz, b = ((lb % ia.ncz) + ia.ncz) % ia.ncz;
+    if (a <= b) { lo0 = cs[a * ia.nxy]; hi0 = cs[(b + 1) * ia.nxy]; }
+    else { lo0 = cs[a * ia.nxy]; hi0 = ia.n; lo1 = 0; hi1 = cs[(b + 1) * ia.nxy]; }
+  }
+  const int n0 = hi0 - lo0, n_cand = n0 + (hi1 - lo1);
+  const size_t fo = (size_t)frame * ia.n;
+  for (int c = threadIdx.x; c < n_cand; c += blockDim.x) {
+    const int j = c < n0 ? lo0 + c : lo1 + (c - n0);
+    T Bz[MAX_ORDER];
+    int fz = spline_triangle_d<T, 5>(ia.sz[fo + j] * ia.mi.invh[2], P, Bz);
+    fz = ((fz % Kz) + Kz) % Kz;
+    int d0 = z0 - fz;
+    d0 += d0 < 0 ? Kz : 0;               // slot of plane z0; plane z0 + p has slot d0 + p (mod Kz)
+    int d1 = d0 + np - 1;
+    d1 -= d1 >= Kz ? Kz : 0;
+    if (d0 >= P && d1 >= P && d1 >= d0) continue;     // no plane of the group within the stencil
+    T Bx[MAX_ORDER], By[MAX_ORDER];
+    int fx = spline_triangle_d<T, 5>(ia.sx[fo + j] * ia.mi.invh[0], P, Bx);
+    int fy = spline_triangle_d<T, 5>(ia.sy[fo + j] * ia.mi.invh[1], P, By);
+    fx = ((fx % Kx) + Kx) % Kx;
+    fy = ((fy % Ky) + Ky) % Ky;
+    T* out = ia.part + (fo + j) * (6 * P);
+#pragma unroll 1
+    for (int p = 0; p < np; ++p) {
+      int sl = d0 + p;
+      sl -= sl >= Kz ? Kz : 0;
+      if (sl >= P) continue;
+      const T2* Ep = E + p * NP;
+      const T2* Fp = free + p * NP;
+      T ax = 0, ay = 0, bx = 0, by = 0;
+#pragma unroll 1
+      for (int ty = 0; ty < P; ++ty) {
+        // offset o takes weight B[P - 1 - o] (selected: the weights stay in registers)
+        const T wy = ty == 0 ? By[4] : ty == 1 ? By[3] : ty == 2 ? By[2] : ty == 3 ? By[1] : By[0];
+        int iy = fy + ty;
+        iy -= iy >= Ky ? Ky : 0;
+        const T2* er = Ep + iy * Kx;
+        const T2* fr = Fp + iy * Kx;
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) {
+          int ix = fx + tx;
+          ix -= ix >= Kx ? Kx : 0;
+          const T w = Bx[P - 1 - tx] * wy;
+          const T2 e = er[ix];
+          ax += w * e.x; ay += w * e.y;
+        }
+#pragma unroll
+        for (int tx = 0; tx < P; ++tx) {
+          int ix = fx + tx;
+          ix -= ix >= Kx ? Kx : 0;
+          const T w = Bx[P - 1 - tx] * wy;
+          const T2 f = fr[ix];
+          bx += w * f.x; by += w * f.y;
+        }
+      }
+      const T wz = sl == 0 ? Bz[4] : sl == 1 ? Bz[3] : sl == 2 ? Bz[2] : sl == 3 ? Bz[1] : Bz[0];
+      T* o6 = out + sl * 6;
+      if (part == 0) {
+        o6[0] = wz * ax; o6[1] = wz * ay;
+        o6[3] = wz * bx; o6[4] = wz * by;
+      } else {
+        o6[2] = wz * ax;
+        o6[5] = wz * bx;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ x-y pass
 
 // mode 0: forward, real input -> complex output
@@ -304,12 +408,15 @@ __device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int si
 // split (mode 1 only): blockIdx.y = 2 frame + part; part 1 transforms in_c2
 // into out_re2 (real part only), part 0 in_c as above
 // DIRECT: a one-frame launch (short lines are summed directly, see dft_lines)
-template <typename T, typename T2, bool DIRECT, int PL>
-__global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
+// INTERP (many frames, the field's split inverse): instead of writing the
+// field planes, interpolate them at the sites (plane_interp)
+template <typename T, typename T2, bool DIRECT, int PL, bool INTERP = false>
+__global__ __launch_bounds__(INTERP ? XY_THREADS_MANY : XY_THREADS, INTERP ? 5 : 1) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
                                                 const T* __restrict__ in_re, const T2* __restrict__ in_c,
                                                 T2* __restrict__ out_c, T* __restrict__ out_re,
                                                 T* __restrict__ out_im, size_t out_re_stride, int split,
-                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
+                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2,
+                                                InterpArgs<T> ia) {
   extern __shared__ __align__(16) unsigned char smem[];
   // PL consecutive planes per workgroup (many frames: the stages of several
   // 18-point planes fill a 256-thread workgroup better than one; one plane
@@ -338,7 +445,9 @@ __global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D p
   T2* r1 = plane_lines(A, B, px, twx, Ky, 1, Kx, sigma, DIRECT, np, NP);        // along x
   T2* o1 = (r1 == A) ? B : A;
   T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, DIRECT, np, NP);      // along y
-  if (mode == 0) {
+  if (INTERP) {
+    plane_interp<T, T2>(ia, r2, (r2 == A) ? B : A, frame, part, z, np, Kx, Ky, Kz);
+  } else if (mode == 0) {
     for (int i = threadIdx.x; i < np * NP; i += blockDim.x) out_c[off + i] = r2[i];
   } else {
     const size_t ro = (size_t)frame * out_re_stride + (size_t)z * NP;
@@ -710,12 +819,14 @@ size_t fft_xy_lds_bytes(int Kx, int Ky, int elt_bytes, int planes) {
 template <typename T, typename T2>
 void launch_xy_many(hipStream_t s, const FFTPlan1D& px, const FFTPlan1D& py, int Kz, int ny, int mode,
                     const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im, size_t out_re_stride, int split,
-                    const T2* in_c2, T* out_re2) {
+                    const T2* in_c2, T* out_re2, const InterpArgs<T>* ia = nullptr) {
   int pl = xy_planes_fit<T2>(px, py);
   if (px.planes > 0 && px.planes < pl) pl = 1;          // the tuner's choice (one plane, or as many as fit)
   auto* k = pl == 1 ? k_fft_xy<T, T2, false, 1> : k_fft_xy<T, T2, false, xy_planes_many<T2>()>;
+  if (ia) k = pl == 1 ? k_fft_xy<T, T2, false, 1, true> : k_fft_xy<T, T2, false, xy_planes_many<T2>(), true>;
   hipLaunchKernelGGL(k, dim3((Kz + pl - 1) / pl, ny), dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, pl), s, px, py, Kz,
-                     mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, split, in_c2, out_re2);
+                     mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, split, in_c2, out_re2,
+                     ia ? *ia : InterpArgs<T>{});
 }
 
 template <typename T, typename T2>
@@ -725,7 +836,8 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
   if (n_frames == 1)
     hipLaunchKernelGGL((k_fft_xy<T, T2, true, 1>), dim3(Kz, 1), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
-                       Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
+                       Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr,
+                       InterpArgs<T>{});
   else
     launch_xy_many<T, T2>(s, px, py, Kz, n_frames, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0,
                           (const T2*)nullptr, (T*)nullptr);
@@ -733,14 +845,15 @@ void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFT
 
 template <typename T, typename T2>
 void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
-                               const T2* c1, const T2* c2, T* E, size_t frame_stride) {
+                               const T2* c1, const T2* c2, T* E, size_t frame_stride, const InterpArgs<T>* ia) {
   const size_t M = (size_t)px.n * py.n * Kz;
   if (n_frames == 1)
     hipLaunchKernelGGL((k_fft_xy<T, T2, true, 1>), dim3(Kz, 2), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
-                       Kz, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
+                       Kz, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M,
+                       InterpArgs<T>{});
   else
     launch_xy_many<T, T2>(s, px, py, Kz, 2 * n_frames, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride,
-                          1, c2, E + 2 * M);
+                          1, c2, E + 2 * M, ia);
 }
 
 template <typename T, typename T2>
@@ -794,8 +907,10 @@ template void launch_fft_z_t<float, float2>(hipStream_t, int, const FFTPlan1D&, 
                                             const float*, float2*, float2*, float2*, int, double*, bool,
                                             const RealBArgs<float>*, const PairArgs<float>*);
 template void launch_fft_xy_field_inv_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&,
-                                                         int, const double2*, const double2*, double*, size_t);
+                                                         int, const double2*, const double2*, double*, size_t,
+                                                         const InterpArgs<double>*);
 template void launch_fft_xy_field_inv_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
-                                                       const float2*, const float2*, float*, size_t);
+                                                       const float2*, const float2*, float*, size_t,
+                                                       const InterpArgs<float>*);
 
 }  // namespace cpm

@@ -384,6 +384,64 @@ __global__ __launch_bounds__(G16_THREADS) void k_site_forces_g16(SiteSet<T> st, 
   }
 }
 
+// The same when the field's inverse pass has interpolated plane by plane
+// (fa.Epart, many frames, order 5): a thread per site sums its P slots of the
+// six components (the frame's field and the static second field) and
+// combines them with the pair sums as above.
+template <typename T, bool TWO>
+__global__ __launch_bounds__(256) void k_site_forces_sum(SiteSet<T> st, ForceArgs<T> fa, int n_force_blocks,
+                                                         EnergyArgs en) {
+  int bx = blockIdx.x, frame = blockIdx.y;
+  if (gridDim.y > 1) {
+    const int L = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    frame = L / gridDim.x;
+    bx = L - frame * gridDim.x;
+  }
+  if (bx >= n_force_blocks) {
+    energy_block(en, frame);
+    return;
+  }
+  const int j = bx * blockDim.x + threadIdx.x;
+  if (j >= st.n) return;
+  const size_t fo = (size_t)frame * st.n;
+  const double qj = st.q[fo + j];
+  const int orig = st.order[fo + j];
+  const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
+  const double* fep = fa.f_elec + (size_t)frame * 6 * st.n;
+  const int P = fa.mi.order;
+  const T* pp = fa.Epart + (fo + j) * (6 * P);
+  T e[6] = {0, 0, 0, 0, 0, 0};
+  for (int sl = 0; sl < P; ++sl)
+#pragma unroll
+    for (int u = 0; u < 6; ++u) e[u] += pp[sl * 6 + u];
+  double F[3], FB[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    F[d] = fa.out_scale * qj * ((double)e[d] + KE * (fp[(size_t)d * st.n + j] + fep[(size_t)d * st.n + j]));
+    FB[d] = TWO ? fa.out_scale * qj * ((double)e[3 + d] + KE * fep[(size_t)(3 + d) * st.n + j]) : 0.0;
+  }
+  F[2] += qj * fa.field;
+  FB[2] += qj * fa.fieldb;
+  if (fa.field_frame) F[2] += fa.out_scale * qj * fa.field_frame[frame];
+  if (fa.f_comp) {
+    double* o = fa.f_comp + (size_t)frame * 6 * st.n + orig;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o[(size_t)d * st.n] = F[d];
+      o[(size_t)(3 + d) * st.n] = FB[d];
+    }
+    return;
+  }
+  double* fout = fa.f_out + (size_t)frame * fa.f_frame_stride;
+  for (int v = 0; v < fa.n_dv; ++v) {
+    const double dv = fa.dv ? fa.dv[v] : 0.0;
+    double* o = fout + (size_t)v * 3 * st.n;
+    o[orig] = F[0] + dv * FB[0];
+    o[st.n + orig] = F[1] + dv * FB[1];
+    o[2 * st.n + orig] = F[2] + dv * FB[2];
+  }
+}
+
 template <typename T>
 void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
   if (pa.n_blocks == 0 || n_frames == 0) return;
@@ -439,6 +497,17 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
     parts = 2 * st.n * n_frames <= r ? 2 : 1;
   }
   const EnergyArgs e = ea ? *ea : EnergyArgs{};
+  if (!walk && fa.Epart) {
+    // a thread per site sums the interpolation's per-plane shares
+    const int nfb = forces ? (st.n + 255) / 256 : 0;
+    dim3 grid(nfb + (ea ? 1 : 0), n_frames);
+    if (grid.x == 0) return;
+    if (two)
+      hipLaunchKernelGGL((k_site_forces_sum<T, true>), grid, dim3(256), 0, s, st, fa, nfb, e);
+    else
+      hipLaunchKernelGGL((k_site_forces_sum<T, false>), grid, dim3(256), 0, s, st, fa, nfb, e);
+    return;
+  }
   if (!walk) {
     // sixteen lanes per site
     const int nfb = forces ? (st.n + G16_THREADS / 16 - 1) / (G16_THREADS / 16) : 0;
