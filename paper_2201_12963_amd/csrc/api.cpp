@@ -114,6 +114,10 @@ struct cpm_ctx {
   MeshInfo mi{};
   FFTPlan1D px{}, py{}, pz{};
   ZPassArgs za_pot{}, za_field{};
+  ZMask zmask_e{};             // the electrode charge's planes (many-frame field pass)
+  bool zmask_ok = false;       // K_z <= 256: the field pass can take the mask
+  int* d_zl = nullptr;         // the planes the electrode stencils reach, ascending
+  int n_zl = 0;
   double *d_G = nullptr, *d_rho = nullptr, *d_phi = nullptr, *d_E = nullptr, *d_rho_e = nullptr;
   double* d_fpart = nullptr;   // [frame][n_site][6 P] per-plane field shares at the sites (FP64, or FP32 in the mixed form)
   double2 *d_c1 = nullptr, *d_c2 = nullptr, *d_save = nullptr;
@@ -530,8 +534,10 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces, bool need_b = 
     if (!need_b) return CPM_OK;
     // timed alone through the stand-alone kernel with the same body
     if (!rb.tiles) keep(c, CPM_KERNEL_REAL_B, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
+    // (many frames: only the planes the electrode stencils read)
     rec(c, CPM_KERNEL_FFT_XY_INV, s, [=](hipStream_t s) {
-      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr);
+      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 1, nullptr, B::c1(c), nullptr, B::phi(c), nullptr, 0,
+                             c->d_zl, c->n_zl);
     });
     rec(c, CPM_KERNEL_GATHER_B, s, [=](hipStream_t s) {
       launch_gather_b_t<T>(s, nf, c->n_elec, c->P3, c->d_gidx, B::gw(c), B::phi(c), c->mi.M, B::phir(c), c->d_b,
@@ -606,6 +612,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     pa.zshift = (cl.img[0] | cl.img[1] | cl.img[2]) == 0 && cl.nc[2] >= 5 &&
                 cl.L[2] > 2.0 * c->rcut + cl.L[2] / cl.nc[2];
   }
+  const T* epart = nullptr;   // the interpolation's per-plane shares (many frames, order 5)
   if (c->kspace == CPM_KSPACE_PPPM) {
     // the electrode spread stays a kernel of its own: only the few planes
     // near the electrodes hold charge, and a per-plane fusion would leave
@@ -614,8 +621,12 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
       launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
                               B::rho_e(c), c->mi.M, sl, fa.field_frame ? c->d_slabfield : nullptr);
     });
+    // many frames: only the planes holding electrode charge, which the
+    // field pass then reads alone (the others are zero)
+    const bool planes = nf > 1 && c->zmask_ok;
     rec(c, CPM_KERNEL_FFT_XY_FWD_E, s, [=](hipStream_t s) {
-      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr);
+      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr, 0,
+                             planes ? c->d_zl : nullptr, planes ? c->n_zl : 0);
     });
     // one frame: the site-pair workgroups ride in the z pass (latency);
     // many frames: a launch of their own, so that the z pass keeps its small
@@ -623,7 +634,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     const bool host_pairs = nf == 1;
     rec(c, CPM_KERNEL_FFT_Z_FIELD, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, true,
-                            nullptr, host_pairs ? &pa : nullptr);
+                            nullptr, host_pairs ? &pa : nullptr, planes ? &c->zmask_e : nullptr);
     });
     if (host_pairs)   // timed alone through the stand-alone kernel with the same body
       keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
@@ -635,7 +646,6 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     fa.Ea = E;
     fa.Ea_frame_stride = 3 * M;
     fa.Esite = nullptr;
-    fa.Epart = nullptr;
     if (nf > 1 && fa.f_elec && c->mi.order == 5) {
       // many frames, with the site-electrode sums in the tiles (order 5):
       // the inverse pass interpolates the field at the sites plane by plane
@@ -650,7 +660,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
       ia.Eb = fa.Eb;
       ia.part = reinterpret_cast<T*>(c->d_fpart);
       ia.mi = c->mi;
-      fa.Epart = ia.part;
+      epart = ia.part;
       rec(c, CPM_KERNEL_FFT_XY_INV_E, s, [=](hipStream_t s) {
         launch_fft_xy_field_inv_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], B::c1(c), B::c2(c), nullptr, 3 * M, &ia);
       });
@@ -671,11 +681,11 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
   const bool with_e = ea != nullptr;
   const EnergyArgs e = with_e ? *ea : EnergyArgs{};
   rec(c, CPM_KERNEL_SITE_FORCES, s, [=](hipStream_t s) {
-    launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa, true, with_e ? &e : nullptr);
+    launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa, true, with_e ? &e : nullptr, epart);
   });
   if (with_e)
     keep(c, CPM_KERNEL_ENERGY, [=](hipStream_t s) {
-      launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa, false, &e);
+      launch_site_forces_t<T>(s, nf, c->cell, B::elec(c), st, fa, false, &e, epart);
     });
   return CPM_OK;
 }
@@ -1335,13 +1345,27 @@ int cpm_create(const cpm_desc* d, void* hip_stream, cpm_ctx** out) {
         fillp[sl]++;
       }
     c->n_touch = (int)touch.size();
+    // the planes the electrode stencils reach: many-frame launches transform
+    // only these for the electrode charge (the other planes hold none) and
+    // for the potential (read only at the electrode atoms)
+    std::vector<int> zl;
+    {
+      std::vector<char> used(mi.K[2], 0);
+      for (int g : gidx) used[g / (mi.K[0] * mi.K[1])] = 1;
+      for (int z = 0; z < mi.K[2]; ++z)
+        if (used[z]) zl.push_back(z);
+    }
+    c->n_zl = (int)zl.size();
+    c->zmask_ok = mi.K[2] <= 256;
+    if (c->zmask_ok)
+      for (int z : zl) c->zmask_e.w[z >> 6] |= 1ull << (z & 63);
     if (bin_lds_spread(ns, cl.n_cells) > LDS_LIMIT) {
       fail(c, CPM_EINVAL, "%d sites in %d cells exceed the binning workgroup's LDS", ns, cl.n_cells);
       return bad(CPM_EINVAL);
     }
     std::vector<float> gwf(gw.begin(), gw.end()), valf(val.begin(), val.end());
     if ((r = upload(c, &c->d_gidx, gidx)) || (r = upload(c, &c->d_gw, gw)) || (r = upload(c, &c->d_gwf, gwf)) ||
-        (r = upload(c, &c->d_touch, touch)) || (r = upload(c, &c->d_rowptr, rowptr)) || (r = upload(c, &c->d_col, col)) ||
+        (r = upload(c, &c->d_touch, touch)) || (r = upload(c, &c->d_zl, zl)) || (r = upload(c, &c->d_rowptr, rowptr)) || (r = upload(c, &c->d_col, col)) ||
         (r = upload(c, &c->d_val, val)) || (r = upload(c, &c->d_valf, valf)))
       return bad(r);
   } else {

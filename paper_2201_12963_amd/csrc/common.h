@@ -211,10 +211,6 @@ struct ForceArgs {
   // explicit-Ewald path instead of a mesh: k-space field at the sites,
   // [frame][3][n_site] in cell-sorted order (V/nm), or nullptr
   const double* Esite;
-  // many frames: the interpolated fields as per-plane partial sums written
-  // by the field's inverse x-y pass ([frame][n_site][6 P], see InterpArgs),
-  // in place of the gathers from Ea and Eb, or nullptr
-  const T* Epart;
   // electrode charges, original order: qa per frame (stride n_elec), qb shared;
   // the same in the electrodes' cell-sorted order (what the pair walk reads)
   const double* qa; size_t qa_frame_stride;
@@ -323,6 +319,12 @@ struct ZPassArgs {
   double twopi_L[3];       // 2 pi / L_d
 };
 
+// Many-frame field pass: only the planes z with bit z set hold data (the
+// electrode charge's planes; K_z <= 256); the others are taken as zero
+struct ZMask {
+  unsigned long long w[4];
+};
+
 struct EnergyArgs {
   int n_elec, n_site, n_ek;
   const double* Q0; const double* b;            // [frame][n_elec]
@@ -428,8 +430,12 @@ size_t site_pairs_lds(int tsplit, bool n3);
 // forces: the site-force workgroups; ea (or nullptr): one more workgroup per
 // frame that reduces the energies
 template <typename T>
+// epart (many frames): the interpolated fields as per-plane shares written
+// by the field's inverse x-y pass ([frame][n_site][6 P], see InterpArgs), in
+// place of the gathers from fa.Ea and fa.Eb, or nullptr
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
-                          const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea);
+                          const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea,
+                          const T* epart = nullptr);
 size_t bin_lds_bytes(int n_site, int n_cells);
 
 // particle-mesh steps (k_pppm.hip)
@@ -478,7 +484,8 @@ void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const in
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                      int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
-                     size_t out_re_stride = 0);
+                     size_t out_re_stride = 0, const int* zl = nullptr, int n_zl = 0);
+// (zl: many frames only, the n_zl planes to transform, ascending; nullptr: all)
 // inverse x-y pass of the field: c1 -> E[0] (re), E[1] (im); c2 -> E[2];
 // both in one launch; E frames frame_stride apart, components M apart
 template <typename T, typename T2>
@@ -489,7 +496,7 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass = true,
-                    const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr);
+                    const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr, const ZMask* zm = nullptr);
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky);
 // dynamic LDS of an x-y launch holding `planes` planes of elt_bytes complex values

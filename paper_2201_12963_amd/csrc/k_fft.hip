@@ -410,13 +410,16 @@ __device__ void plane_interp(const InterpArgs<T>& ia, const T2* E, T2* free, int
 // DIRECT: a one-frame launch (short lines are summed directly, see dft_lines)
 // INTERP (many frames, the field's split inverse): instead of writing the
 // field planes, interpolate them at the sites (plane_interp)
-template <typename T, typename T2, bool DIRECT, int PL, bool INTERP = false>
-__global__ __launch_bounds__(INTERP ? XY_THREADS_MANY : XY_THREADS, INTERP ? 5 : 1) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
-                                                const T* __restrict__ in_re, const T2* __restrict__ in_c,
-                                                T2* __restrict__ out_c, T* __restrict__ out_re,
-                                                T* __restrict__ out_im, size_t out_re_stride, int split,
-                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2,
-                                                InterpArgs<T> ia) {
+// zl (many frames): transform only the n_zl planes listed (ascending), PL
+// list entries per workgroup, or every plane if nullptr
+// (the body; k_fft_xy and k_fft_xy_many below are its launches)
+template <typename T, typename T2, bool DIRECT, int PL, bool INTERP>
+__device__ __forceinline__ void fft_xy_body(const FFTPlan1D& px, const FFTPlan1D& py, int Kz, int mode,
+                                            const T* __restrict__ in_re, const T2* __restrict__ in_c,
+                                            T2* __restrict__ out_c, T* __restrict__ out_re,
+                                            T* __restrict__ out_im, size_t out_re_stride, int split,
+                                            const T2* __restrict__ in_c2, T* __restrict__ out_re2,
+                                            const int* __restrict__ zl, int n_zl, const InterpArgs<T>& ia) {
   extern __shared__ __align__(16) unsigned char smem[];
   // PL consecutive planes per workgroup (many frames: the stages of several
   // 18-point planes fill a 256-thread workgroup better than one; one plane
@@ -429,13 +432,27 @@ __global__ __launch_bounds__(INTERP ? XY_THREADS_MANY : XY_THREADS, INTERP ? 5 :
   T2* twy = twx + Kx;
   load_twiddles(px, twx);
   load_twiddles(py, twy);
-  const int z = blockIdx.x * PL;
-  const int np = min(PL, Kz - z);
+  if (DIRECT || INTERP) zl = nullptr;                       // (a plane list only in plain many-frame launches)
+  const int z = blockIdx.x * PL;                            // first plane (or list entry)
+  const int np = min(PL, (zl ? n_zl : Kz) - z);
   const int part = split ? (int)(blockIdx.y & 1) : 0;
   const int frame = split ? (int)(blockIdx.y >> 1) : (int)blockIdx.y;
   if (part) { in_c = in_c2; out_re = out_re2; out_im = nullptr; }
   const size_t off = ((size_t)frame * Kz + z) * NP;         // the workgroup's planes are contiguous
-  if (mode == 0) {
+  // mesh offset (within the frame) of the workgroup's point i: listed planes
+  // need not be contiguous
+  auto listed = [&](int i) -> size_t {
+    const int p = i / NP;
+    return (size_t)zl[z + p] * NP + (i - p * NP);
+  };
+  if (zl) {
+    const size_t fo = (size_t)frame * Kz * NP;
+    if (mode == 0) {
+      for (int i = threadIdx.x; i < np * NP; i += blockDim.x) A[i] = T2{in_re[fo + listed(i)], (T)0};
+    } else {
+      for (int i = threadIdx.x; i < np * NP; i += blockDim.x) A[i] = in_c[fo + listed(i)];
+    }
+  } else if (mode == 0) {
     for (int i = threadIdx.x; i < np * NP; i += blockDim.x) A[i] = T2{in_re[off + i], (T)0};
   } else {
     for (int i = threadIdx.x; i < np * NP; i += blockDim.x) A[i] = in_c[off + i];
@@ -447,6 +464,17 @@ __global__ __launch_bounds__(INTERP ? XY_THREADS_MANY : XY_THREADS, INTERP ? 5 :
   T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, DIRECT, np, NP);      // along y
   if (INTERP) {
     plane_interp<T, T2>(ia, r2, (r2 == A) ? B : A, frame, part, z, np, Kx, Ky, Kz);
+  } else if (zl) {
+    const size_t fo = (size_t)frame * Kz * NP, ro = (size_t)frame * out_re_stride;
+    for (int i = threadIdx.x; i < np * NP; i += blockDim.x) {
+      const size_t m = listed(i);
+      if (mode == 0) {
+        out_c[fo + m] = r2[i];
+      } else {
+        out_re[ro + m] = r2[i].x;
+        if (out_im) out_im[ro + m] = r2[i].y;
+      }
+    }
   } else if (mode == 0) {
     for (int i = threadIdx.x; i < np * NP; i += blockDim.x) out_c[off + i] = r2[i];
   } else {
@@ -456,6 +484,27 @@ __global__ __launch_bounds__(INTERP ? XY_THREADS_MANY : XY_THREADS, INTERP ? 5 :
       if (out_im) out_im[ro + i] = r2[i].y;
     }
   }
+}
+
+// one frame (DIRECT) or many frames with every plane
+template <typename T, typename T2, bool DIRECT, int PL>
+__global__ __launch_bounds__(XY_THREADS) void k_fft_xy(FFTPlan1D px, FFTPlan1D py, int Kz, int mode,
+                                                const T* __restrict__ in_re, const T2* __restrict__ in_c,
+                                                T2* __restrict__ out_c, T* __restrict__ out_re,
+                                                T* __restrict__ out_im, size_t out_re_stride, int split,
+                                                const T2* __restrict__ in_c2, T* __restrict__ out_re2) {
+  fft_xy_body<T, T2, DIRECT, PL, false>(px, py, Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, split,
+                                        in_c2, out_re2, nullptr, 0, InterpArgs<T>{});
+}
+
+// many frames: a plane list (zl) or the interpolation at the sites (INTERP)
+template <typename T, typename T2, int PL, bool INTERP>
+__global__ __launch_bounds__(INTERP ? XY_THREADS_MANY : XY_THREADS, INTERP ? 5 : 1) void k_fft_xy_many(
+    FFTPlan1D px, FFTPlan1D py, int Kz, int mode, const T* __restrict__ in_re, const T2* __restrict__ in_c,
+    T2* __restrict__ out_c, T* __restrict__ out_re, T* __restrict__ out_im, size_t out_re_stride, int split,
+    const T2* __restrict__ in_c2, T* __restrict__ out_re2, const int* __restrict__ zl, int n_zl, InterpArgs<T> ia) {
+  fft_xy_body<T, T2, false, PL, INTERP>(px, py, Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, split,
+                                        in_c2, out_re2, zl, n_zl, ia);
 }
 
 // ------------------------------------------------- spread fused with x-y
@@ -619,12 +668,21 @@ template <typename T> __device__ __forceinline__ T mode_k(int i, int K, T twopi_
 //          data1 = IFFT_z((-i kx + ky) G X)  [Ex + i Ey after the x-y inverse]
 //          data2 = IFFT_z(-i kz G X)         [Ez]
 // MULTI: many frames, lpw columns per wavefront (else one, and hosted work)
-template <typename T, typename T2, bool MULTI>
-__global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
-                                               T2* __restrict__ data1, T2* __restrict__ data2,
-                                               T2* __restrict__ save, int add_saved,
-                                               double* __restrict__ energy_part, int n_z_blocks,
-                                               RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride) {
+// plane z of a masked field pass holds data (the mask words are selected,
+// not indexed, so that they stay in scalar registers)
+__device__ __forceinline__ bool zplane_on(const ZMask& zm, int z) {
+  const unsigned long long w = z < 64 ? zm.w[0] : z < 128 ? zm.w[1] : z < 192 ? zm.w[2] : zm.w[3];
+  return (w >> (z & 63)) & 1ull;
+}
+
+// (the body; k_fft_z and k_fft_z_masked below are its launches)
+template <typename T, typename T2, bool MULTI, bool MASK>
+__device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs& za, const T* __restrict__ G,
+                                           T2* __restrict__ data1, T2* __restrict__ data2,
+                                           T2* __restrict__ save, int add_saved,
+                                           double* __restrict__ energy_part, int n_z_blocks,
+                                           const RealBArgs<T>& rb, const PairArgs<T>& pa, int lpw, int ek_stride,
+                                           const ZMask& zm) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   if (!MULTI && (int)blockIdx.x >= n_z_blocks) {
@@ -677,13 +735,14 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
     gk[u] = (T)0;
     sv[u] = T2{(T)0, (T)0};
     if (active && z < Kz) {
-      Al[z] = data1[fo + z * plane + cxy];
+      Al[z] = (!MASK || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
       gk[u] = G[z * plane + cxy];
       if (za.mode == 1 && add_saved) sv[u] = save[fo + z * plane + cxy];
     }
   }
   if (active)
-    for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs) Al[z] = data1[fo + z * plane + cxy];
+    for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs)
+      Al[z] = (!MASK || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
   __syncthreads();                                         // twiddles
   double e = 0.0;
   if (wave_on) {
@@ -760,6 +819,28 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
   }
 }
 
+template <typename T, typename T2, bool MULTI>
+__global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
+                                               T2* __restrict__ data1, T2* __restrict__ data2,
+                                               T2* __restrict__ save, int add_saved,
+                                               double* __restrict__ energy_part, int n_z_blocks,
+                                               RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride) {
+  fft_z_body<T, T2, MULTI, false>(pz, za, G, data1, data2, save, add_saved, energy_part, n_z_blocks, rb, pa, lpw,
+                                  ek_stride, ZMask{});
+}
+
+// the field pass of many frames reading only the masked planes
+template <typename T, typename T2, bool MULTI>
+__global__ __launch_bounds__(256) void k_fft_z_masked(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
+                                                      T2* __restrict__ data1, T2* __restrict__ data2,
+                                                      T2* __restrict__ save, int add_saved,
+                                                      double* __restrict__ energy_part, int n_z_blocks,
+                                                      RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride,
+                                                      ZMask zm) {
+  fft_z_body<T, T2, MULTI, true>(pz, za, G, data1, data2, save, add_saved, energy_part, n_z_blocks, rb, pa, lpw,
+                                 ek_stride, zm);
+}
+
 
 // ------------------------------------------------------------------ launchers
 
@@ -819,28 +900,37 @@ size_t fft_xy_lds_bytes(int Kx, int Ky, int elt_bytes, int planes) {
 template <typename T, typename T2>
 void launch_xy_many(hipStream_t s, const FFTPlan1D& px, const FFTPlan1D& py, int Kz, int ny, int mode,
                     const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im, size_t out_re_stride, int split,
-                    const T2* in_c2, T* out_re2, const InterpArgs<T>* ia = nullptr) {
+                    const T2* in_c2, T* out_re2, const InterpArgs<T>* ia = nullptr, const int* zl = nullptr,
+                    int n_zl = 0) {
   int pl = xy_planes_fit<T2>(px, py);
   if (px.planes > 0 && px.planes < pl) pl = 1;          // the tuner's choice (one plane, or as many as fit)
+  const int nz = zl ? n_zl : Kz;
+  if (nz == 0) return;
+  const dim3 grid((nz + pl - 1) / pl, ny);
+  const size_t lds = fft_xy_lds<T2>(px, py, pl);
+  if (ia || zl) {
+    auto* k = pl == 1 ? k_fft_xy_many<T, T2, 1, false> : k_fft_xy_many<T, T2, xy_planes_many<T2>(), false>;
+    if (ia) k = pl == 1 ? k_fft_xy_many<T, T2, 1, true> : k_fft_xy_many<T, T2, xy_planes_many<T2>(), true>;
+    hipLaunchKernelGGL(k, grid, dim3(XY_THREADS_MANY), lds, s, px, py, Kz, mode, in_re, in_c, out_c, out_re, out_im,
+                       out_re_stride, split, in_c2, out_re2, zl, n_zl, ia ? *ia : InterpArgs<T>{});
+    return;
+  }
   auto* k = pl == 1 ? k_fft_xy<T, T2, false, 1> : k_fft_xy<T, T2, false, xy_planes_many<T2>()>;
-  if (ia) k = pl == 1 ? k_fft_xy<T, T2, false, 1, true> : k_fft_xy<T, T2, false, xy_planes_many<T2>(), true>;
-  hipLaunchKernelGGL(k, dim3((Kz + pl - 1) / pl, ny), dim3(XY_THREADS_MANY), fft_xy_lds<T2>(px, py, pl), s, px, py, Kz,
-                     mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, split, in_c2, out_re2,
-                     ia ? *ia : InterpArgs<T>{});
+  hipLaunchKernelGGL(k, grid, dim3(XY_THREADS_MANY), lds, s, px, py, Kz, mode, in_re, in_c, out_c, out_re, out_im,
+                     out_re_stride, split, in_c2, out_re2);
 }
 
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                      int mode, const T* in_re, const T2* in_c, T2* out_c, T* out_re, T* out_im,
-                     size_t out_re_stride) {
+                     size_t out_re_stride, const int* zl, int n_zl) {
   if (out_re_stride == 0) out_re_stride = (size_t)px.n * py.n * Kz;
   if (n_frames == 1)
     hipLaunchKernelGGL((k_fft_xy<T, T2, true, 1>), dim3(Kz, 1), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
-                       Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr,
-                       InterpArgs<T>{});
+                       Kz, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0, (const T2*)nullptr, (T*)nullptr);
   else
     launch_xy_many<T, T2>(s, px, py, Kz, n_frames, mode, in_re, in_c, out_c, out_re, out_im, out_re_stride, 0,
-                          (const T2*)nullptr, (T*)nullptr);
+                          (const T2*)nullptr, (T*)nullptr, nullptr, zl, n_zl);
 }
 
 template <typename T, typename T2>
@@ -849,8 +939,7 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
   const size_t M = (size_t)px.n * py.n * Kz;
   if (n_frames == 1)
     hipLaunchKernelGGL((k_fft_xy<T, T2, true, 1>), dim3(Kz, 2), dim3(XY_THREADS), fft_xy_lds<T2>(px, py, 1), s, px, py,
-                       Kz, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M,
-                       InterpArgs<T>{});
+                       Kz, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride, 1, c2, E + 2 * M);
   else
     launch_xy_many<T, T2>(s, px, py, Kz, 2 * n_frames, 1, (const T*)nullptr, c1, (T2*)nullptr, E, E + M, frame_stride,
                           1, c2, E + 2 * M, ia);
@@ -859,7 +948,7 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass,
-                    const RealBArgs<T>* rb, const PairArgs<T>* pa) {
+                    const RealBArgs<T>* rb, const PairArgs<T>* pa, const ZMask* zm) {
   const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
   // columns per wavefront: one for one frame (the chain of a column is the
@@ -887,7 +976,13 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
     std::fprintf(stderr, "cpm: no hosted work in a z pass of several columns per wavefront\n");
     std::abort();
   }
-  if (lpw > 1)
+  if (zm && lpw > 1)
+    hipLaunchKernelGGL((k_fft_z_masked<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save,
+                       add_saved, energy_part, nzb, r, p, lpw, za.n_blocks, *zm);
+  else if (zm)
+    hipLaunchKernelGGL((k_fft_z_masked<T, T2, false>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save,
+                       add_saved, energy_part, nzb, r, p, 1, za.n_blocks, *zm);
+  else if (lpw > 1)
     hipLaunchKernelGGL((k_fft_z<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
                        energy_part, nzb, r, p, lpw, za.n_blocks);
   else
@@ -897,15 +992,16 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
 
 template void launch_fft_xy_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
                                                int, const double*, const double2*, double2*, double*,
-                                               double*, size_t);
+                                               double*, size_t, const int*, int);
 template void launch_fft_xy_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int, int,
-                                             const float*, const float2*, float2*, float*, float*, size_t);
+                                             const float*, const float2*, float2*, float*, float*, size_t,
+                                             const int*, int);
 template void launch_fft_z_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                               const double*, double2*, double2*, double2*, int, double*, bool,
-                                              const RealBArgs<double>*, const PairArgs<double>*);
+                                              const RealBArgs<double>*, const PairArgs<double>*, const ZMask*);
 template void launch_fft_z_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                             const float*, float2*, float2*, float2*, int, double*, bool,
-                                            const RealBArgs<float>*, const PairArgs<float>*);
+                                            const RealBArgs<float>*, const PairArgs<float>*, const ZMask*);
 template void launch_fft_xy_field_inv_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&,
                                                          int, const double2*, const double2*, double*, size_t,
                                                          const InterpArgs<double>*);

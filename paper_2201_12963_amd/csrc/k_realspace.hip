@@ -385,12 +385,12 @@ __global__ __launch_bounds__(G16_THREADS) void k_site_forces_g16(SiteSet<T> st, 
 }
 
 // The same when the field's inverse pass has interpolated plane by plane
-// (fa.Epart, many frames, order 5): a thread per site sums its P slots of the
+// (epart, many frames, order 5): a thread per site sums its P slots of the
 // six components (the frame's field and the static second field) and
 // combines them with the pair sums as above.
 template <typename T, bool TWO>
-__global__ __launch_bounds__(256) void k_site_forces_sum(SiteSet<T> st, ForceArgs<T> fa, int n_force_blocks,
-                                                         EnergyArgs en) {
+__global__ __launch_bounds__(256) void k_site_forces_sum(SiteSet<T> st, ForceArgs<T> fa, const T* __restrict__ epart,
+                                                         int n_force_blocks, EnergyArgs en) {
   int bx = blockIdx.x, frame = blockIdx.y;
   if (gridDim.y > 1) {
     const int L = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_site_forces_sum(SiteSet<T> st, ForceArg
   const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
   const double* fep = fa.f_elec + (size_t)frame * 6 * st.n;
   const int P = fa.mi.order;
-  const T* pp = fa.Epart + (fo + j) * (6 * P);
+  const T* pp = epart + (fo + j) * (6 * P);
   T e[6] = {0, 0, 0, 0, 0, 0};
   for (int sl = 0; sl < P; ++sl)
 #pragma unroll
@@ -471,7 +471,8 @@ void launch_site_pairs_t(hipStream_t s, int n_frames, const PairArgs<T>& pa) {
 
 template <typename T>
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
-                          const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea) {
+                          const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea,
+                          const T* epart) {
   // TWO: a second charge set; walk: the kernel walks the electrode atoms
   // itself (no site-electrode sums from the pair tiles; else k_site_forces_g16)
   const bool two = fa.Eb || fa.qb, walk = fa.f_elec == nullptr;
@@ -497,15 +498,15 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
     parts = 2 * st.n * n_frames <= r ? 2 : 1;
   }
   const EnergyArgs e = ea ? *ea : EnergyArgs{};
-  if (!walk && fa.Epart) {
+  if (!walk && epart) {
     // a thread per site sums the interpolation's per-plane shares
     const int nfb = forces ? (st.n + 255) / 256 : 0;
     dim3 grid(nfb + (ea ? 1 : 0), n_frames);
     if (grid.x == 0) return;
     if (two)
-      hipLaunchKernelGGL((k_site_forces_sum<T, true>), grid, dim3(256), 0, s, st, fa, nfb, e);
+      hipLaunchKernelGGL((k_site_forces_sum<T, true>), grid, dim3(256), 0, s, st, fa, epart, nfb, e);
     else
-      hipLaunchKernelGGL((k_site_forces_sum<T, false>), grid, dim3(256), 0, s, st, fa, nfb, e);
+      hipLaunchKernelGGL((k_site_forces_sum<T, false>), grid, dim3(256), 0, s, st, fa, epart, nfb, e);
     return;
   }
   if (!walk) {
@@ -539,9 +540,9 @@ template size_t site_pairs_lds<double>(int, bool);
 template size_t site_pairs_lds<float>(int, bool);
 template void launch_site_forces_t<double>(hipStream_t, int, const Cell&, const ElecSet<double>&,
                                            const SiteSet<double>&, const ForceArgs<double>&, bool,
-                                           const EnergyArgs*);
+                                           const EnergyArgs*, const double*);
 template void launch_site_forces_t<float>(hipStream_t, int, const Cell&, const ElecSet<float>&,
                                           const SiteSet<float>&, const ForceArgs<float>&, bool,
-                                          const EnergyArgs*);
+                                          const EnergyArgs*, const float*);
 
 }  // namespace cpm
