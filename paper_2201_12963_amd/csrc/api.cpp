@@ -525,9 +525,11 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces, bool need_b = 
     });
     if (rb.tiles) rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
     rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
+      // (many frames: the result only on the planes the electrode stencils read)
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
                             forces ? B::save(c) : nullptr, 0, c->d_ek, true,
-                            (rb.tiles || !need_b) ? nullptr : &rb, nullptr);
+                            (rb.tiles || !need_b) ? nullptr : &rb, nullptr,
+                            nf > 1 && c->zmask_ok ? &c->zmask_e : nullptr);
     });
     // forces at given charges (MD steps between charge updates): only the
     // saved site spectrum is needed, not b

@@ -319,8 +319,10 @@ struct ZPassArgs {
   double twopi_L[3];       // 2 pi / L_d
 };
 
-// Many-frame field pass: only the planes z with bit z set hold data (the
-// electrode charge's planes; K_z <= 256); the others are taken as zero
+// Many-frame z passes and the planes the electrode stencils reach (bit z of
+// w; K_z <= 256): the field pass reads the electrode spectrum only there
+// (the other planes are taken as zero), the potential pass writes its
+// result only there (nothing else reads it)
 struct ZMask {
   unsigned long long w[4];
 };

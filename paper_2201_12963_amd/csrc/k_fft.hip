@@ -735,14 +735,14 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
     gk[u] = (T)0;
     sv[u] = T2{(T)0, (T)0};
     if (active && z < Kz) {
-      Al[z] = (!MASK || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
+      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
       gk[u] = G[z * plane + cxy];
       if (za.mode == 1 && add_saved) sv[u] = save[fo + z * plane + cxy];
     }
   }
   if (active)
     for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs)
-      Al[z] = (!MASK || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
+      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
   __syncthreads();                                         // twiddles
   double e = 0.0;
   if (wave_on) {
@@ -766,7 +766,8 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
       }
       T2* Y = fft_line_w(X, F1, pz, twz, +1, L, Kz);
       if (active)
-        for (int z = z0; z < Kz; z += zs) data1[fo + z * plane + cxy] = Y[c * Kz + z];
+        for (int z = z0; z < Kz; z += zs)
+          if (!MASK || zplane_on(zm, z)) data1[fo + z * plane + cxy] = Y[c * Kz + z];
     } else {
       // C keeps G X; the first inverse transforms (-i kx + ky) G X (Ex + i Ey
       // after the x-y inverse), the second -i kz G X (Ez)
@@ -829,7 +830,8 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
                                   ek_stride, ZMask{});
 }
 
-// the field pass of many frames reading only the masked planes
+// many frames: the potential pass writing, the field pass reading, only the
+// masked planes (ZMask)
 template <typename T, typename T2, bool MULTI>
 __global__ __launch_bounds__(256) void k_fft_z_masked(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
                                                       T2* __restrict__ data1, T2* __restrict__ data2,
