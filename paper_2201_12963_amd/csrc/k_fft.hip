@@ -307,29 +307,40 @@ __device__ T2* fft_line_w(T2* a, T2* b, const FFTPlan1D& p, const T2* tw, int si
 // the weights of the site-force gather (the same spline_triangle_d calls on
 // the same coordinates); a site's stencil covers planes first .. first + 4
 // (mod K_z), i.e. scaled z within 5/2 of the plane, so the candidates are the
-// sites of the binning's z layers within that distance, one layer of margin
-// on each side.  A thread takes a site, its planes one after the other and
-// their rows one after the other (few registers: the x-y pass it rides in
-// keeps its occupancy).
+// sites of the binning's z layers that meet that distance (plus 1e-6 nm for
+// rounding, far above it and far below a layer).  A thread takes a site, its
+// planes one after the other and their rows one after the other (few
+// registers: the x-y pass it rides in keeps its occupancy).
+// What plane_interp needs from global memory, loaded before the transform so
+// that its latency passes under the transform's stages (which wait on LDS
+// only): the candidate ranges, this thread's first candidate and its
+// position, and this thread's first four points of the static field.
 template <typename T, typename T2>
-__device__ void plane_interp(const InterpArgs<T>& ia, const T2* E, T2* free, int frame, int part, int z0, int np,
-                             int Kx, int Ky, int Kz) {
+struct InterpPre {
+  int lo0, n0, lo1, n_cand;     // candidates: n0 sites from lo0, then from lo1
+  int j;                        // this thread's first candidate (cell-sorted index), or -1
+  double x, y, z;               // its wrapped position
+  T2 eb[4];                     // static field at plane points threadIdx.x + k blockDim.x
+};
+
+template <typename T, typename T2>
+__device__ __forceinline__ void interp_pre(const InterpArgs<T>& ia, int frame, int part, int z0, int np, int NP,
+                                           InterpPre<T, T2>& pre) {
   constexpr int P = 5;
-  const int NP = Kx * Ky;
   const size_t M = ia.mi.M;
-  // the static field's planes beside the frame's
-  for (int i = threadIdx.x; i < np * NP; i += blockDim.x) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = threadIdx.x + k * blockDim.x;
     const size_t m = (size_t)z0 * NP + i;
-    T2 v = T2{(T)0, (T)0};
-    if (ia.Eb) v = part ? T2{ia.Eb[2 * M + m], (T)0} : T2{ia.Eb[m], ia.Eb[M + m]};
-    free[i] = v;
+    pre.eb[k] = T2{(T)0, (T)0};
+    if (ia.Eb && i < np * NP) pre.eb[k] = part ? T2{ia.Eb[2 * M + m], (T)0} : T2{ia.Eb[m], ia.Eb[M + m]};
   }
-  __syncthreads();
-  // candidate sites: the z layers within P/2 planes (plus a layer) of the
-  // group, as one or two ranges of the cell-sorted sites
+  // candidate sites: the z layers that meet scaled z within P/2 of the
+  // group's planes (a margin of 1e-6 nm for rounding), as one or two ranges
+  // of the cell-sorted sites
   const double h = ia.mi.h[2];
-  const int la = (int)floor((z0 - 0.5 * P) * h * ia.inv_wz) - 1;
-  const int lb = (int)floor((z0 + np - 1 + 0.5 * P) * h * ia.inv_wz) + 1;
+  const int la = (int)floor(((z0 - 0.5 * P) * h - 1e-6) * ia.inv_wz);
+  const int lb = (int)floor(((z0 + np - 1 + 0.5 * P) * h + 1e-6) * ia.inv_wz);
   const int* cs = ia.cell_start + (size_t)frame * (ia.n_cells + 1);
   int lo0 = 0, hi0 = ia.n, lo1 = 0, hi1 = 0;
   if (lb - la + 1 < ia.ncz) {
@@ -337,21 +348,55 @@ __device__ void plane_interp(const InterpArgs<T>& ia, const T2* E, T2* free, int
     if (a <= b) { lo0 = cs[a * ia.nxy]; hi0 = cs[(b + 1) * ia.nxy]; }
     else { lo0 = cs[a * ia.nxy]; hi0 = ia.n; lo1 = 0; hi1 = cs[(b + 1) * ia.nxy]; }
   }
-  const int n0 = hi0 - lo0, n_cand = n0 + (hi1 - lo1);
+  pre.lo0 = lo0; pre.n0 = hi0 - lo0; pre.lo1 = lo1; pre.n_cand = pre.n0 + (hi1 - lo1);
+  pre.j = -1;
+  const int c = threadIdx.x;
+  if (c < pre.n_cand) {
+    const int j = c < pre.n0 ? lo0 + c : lo1 + (c - pre.n0);
+    const size_t o = (size_t)frame * ia.n + j;
+    pre.j = j;
+    pre.x = ia.sx[o]; pre.y = ia.sy[o]; pre.z = ia.sz[o];
+  }
+}
+
+template <typename T, typename T2>
+__device__ void plane_interp(const InterpArgs<T>& ia, const InterpPre<T, T2>& pre, const T2* E, T2* free, int frame,
+                             int part, int z0, int np, int Kx, int Ky, int Kz) {
+  constexpr int P = 5;
+  const int NP = Kx * Ky;
+  const size_t M = ia.mi.M;
+  // the static field's planes beside the frame's
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = threadIdx.x + k * blockDim.x;
+    if (i < np * NP) free[i] = pre.eb[k];
+  }
+  for (int i = threadIdx.x + 4 * blockDim.x; i < np * NP; i += blockDim.x) {
+    const size_t m = (size_t)z0 * NP + i;
+    T2 v = T2{(T)0, (T)0};
+    if (ia.Eb) v = part ? T2{ia.Eb[2 * M + m], (T)0} : T2{ia.Eb[m], ia.Eb[M + m]};
+    free[i] = v;
+  }
+  __syncthreads();
   const size_t fo = (size_t)frame * ia.n;
-  for (int c = threadIdx.x; c < n_cand; c += blockDim.x) {
-    const int j = c < n0 ? lo0 + c : lo1 + (c - n0);
-    T Bz[MAX_ORDER];
-    int fz = spline_triangle_d<T, 5>(ia.sz[fo + j] * ia.mi.invh[2], P, Bz);
+  for (int c = threadIdx.x; c < pre.n_cand; c += blockDim.x) {
+    const bool first = c == (int)threadIdx.x;
+    const int j = first ? pre.j : (c < pre.n0 ? pre.lo0 + c : pre.lo1 + (c - pre.n0));
+    const double zj = first ? pre.z : ia.sz[fo + j];
+    const double uz = zj * ia.mi.invh[2];
+    // the stencil start as spline_triangle_d takes it (the weights only for
+    // the sites kept)
+    int fz = (int)floor(uz - 0.5 * P) + 1;
     fz = ((fz % Kz) + Kz) % Kz;
     int d0 = z0 - fz;
     d0 += d0 < 0 ? Kz : 0;               // slot of plane z0; plane z0 + p has slot d0 + p (mod Kz)
     int d1 = d0 + np - 1;
     d1 -= d1 >= Kz ? Kz : 0;
     if (d0 >= P && d1 >= P && d1 >= d0) continue;     // no plane of the group within the stencil
-    T Bx[MAX_ORDER], By[MAX_ORDER];
-    int fx = spline_triangle_d<T, 5>(ia.sx[fo + j] * ia.mi.invh[0], P, Bx);
-    int fy = spline_triangle_d<T, 5>(ia.sy[fo + j] * ia.mi.invh[1], P, By);
+    T Bx[MAX_ORDER], By[MAX_ORDER], Bz[MAX_ORDER];
+    spline_triangle_d<T, 5>(uz, P, Bz);
+    int fx = spline_triangle_d<T, 5>((first ? pre.x : ia.sx[fo + j]) * ia.mi.invh[0], P, Bx);
+    int fy = spline_triangle_d<T, 5>((first ? pre.y : ia.sy[fo + j]) * ia.mi.invh[1], P, By);
     fx = ((fx % Kx) + Kx) % Kx;
     fy = ((fy % Ky) + Ky) % Ky;
     T* out = ia.part + (fo + j) * (6 * P);
@@ -360,8 +405,6 @@ __device__ void plane_interp(const InterpArgs<T>& ia, const T2* E, T2* free, int
       int sl = d0 + p;
       sl -= sl >= Kz ? Kz : 0;
       if (sl >= P) continue;
-      const T2* Ep = E + p * NP;
-      const T2* Fp = free + p * NP;
       T ax = 0, ay = 0, bx = 0, by = 0;
 #pragma unroll 1
       for (int ty = 0; ty < P; ++ty) {
@@ -369,8 +412,8 @@ __device__ void plane_interp(const InterpArgs<T>& ia, const T2* E, T2* free, int
         const T wy = ty == 0 ? By[4] : ty == 1 ? By[3] : ty == 2 ? By[2] : ty == 3 ? By[1] : By[0];
         int iy = fy + ty;
         iy -= iy >= Ky ? Ky : 0;
-        const T2* er = Ep + iy * Kx;
-        const T2* fr = Fp + iy * Kx;
+        const T2* er = E + p * NP + iy * Kx;
+        const T2* fr = free + p * NP + iy * Kx;
 #pragma unroll
         for (int tx = 0; tx < P; ++tx) {
           int ix = fx + tx;
@@ -457,13 +500,15 @@ __device__ __forceinline__ void fft_xy_body(const FFTPlan1D& px, const FFTPlan1D
   } else {
     for (int i = threadIdx.x; i < np * NP; i += blockDim.x) A[i] = in_c[off + i];
   }
+  InterpPre<T, T2> pre;
+  if (INTERP) interp_pre<T, T2>(ia, frame, part, z, np, NP, pre);
   __syncthreads();
   const int sigma = mode == 0 ? -1 : 1;
   T2* r1 = plane_lines(A, B, px, twx, Ky, 1, Kx, sigma, DIRECT, np, NP);        // along x
   T2* o1 = (r1 == A) ? B : A;
   T2* r2 = plane_lines(r1, o1, py, twy, Kx, Kx, 1, sigma, DIRECT, np, NP);      // along y
   if (INTERP) {
-    plane_interp<T, T2>(ia, r2, (r2 == A) ? B : A, frame, part, z, np, Kx, Ky, Kz);
+    plane_interp<T, T2>(ia, pre, r2, (r2 == A) ? B : A, frame, part, z, np, Kx, Ky, Kz);
   } else if (zl) {
     const size_t fo = (size_t)frame * Kz * NP, ro = (size_t)frame * out_re_stride;
     for (int i = threadIdx.x; i < np * NP; i += blockDim.x) {
