@@ -119,7 +119,7 @@ struct cpm_ctx {
   int* d_zl = nullptr;         // the planes the electrode stencils reach, ascending
   int n_zl = 0;
   double *d_G = nullptr, *d_rho = nullptr, *d_phi = nullptr, *d_E = nullptr, *d_rho_e = nullptr;
-  double* d_fpart = nullptr;   // [frame][n_site][6 P] per-plane field shares at the sites (FP64, or FP32 in the mixed form)
+  double* d_fpart = nullptr;   // [frame][6 P][n_site] per-plane field shares at the sites (FP64, or FP32 in the mixed form)
   double2 *d_c1 = nullptr, *d_c2 = nullptr, *d_save = nullptr;
   float *d_Gf = nullptr, *d_rhof = nullptr, *d_phif = nullptr, *d_Ef = nullptr, *d_rho_ef = nullptr;
   float2 *d_c1f = nullptr, *d_c2f = nullptr, *d_savef = nullptr;

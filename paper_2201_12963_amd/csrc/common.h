@@ -195,7 +195,7 @@ struct InterpArgs {
   int n, n_cells, nxy, ncz;     // sites; cells; cells per z layer; z layers
   double inv_wz;                // z layers per nm
   const T* Eb;                  // [3][M] static second field, or nullptr
-  T* part;                      // [frame][n][6 P] sorted order, slot-major (slot * 6 + component)
+  T* part;                      // [frame][6 P][n]: share (slot, component) at row slot * 6 + component, sites in sorted order
   MeshInfo mi;
 };
 
@@ -433,7 +433,7 @@ size_t site_pairs_lds(int tsplit, bool n3);
 // frame that reduces the energies
 template <typename T>
 // epart (many frames): the interpolated fields as per-plane shares written
-// by the field's inverse x-y pass ([frame][n_site][6 P], see InterpArgs), in
+// by the field's inverse x-y pass ([frame][6 P][n_site], see InterpArgs), in
 // place of the gathers from fa.Ea and fa.Eb, or nullptr
 void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const ElecSet<T>& el,
                           const SiteSet<T>& st, const ForceArgs<T>& fa, bool forces, const EnergyArgs* ea,

@@ -399,7 +399,7 @@ __device__ void plane_interp(const InterpArgs<T>& ia, const InterpPre<T, T2>& pr
     int fy = spline_triangle_d<T, 5>((first ? pre.y : ia.sy[fo + j]) * ia.mi.invh[1], P, By);
     fx = ((fx % Kx) + Kx) % Kx;
     fy = ((fy % Ky) + Ky) % Ky;
-    T* out = ia.part + (fo + j) * (6 * P);
+    T* out = ia.part + (size_t)frame * 6 * P * ia.n + j;      // share (slot, component) at [(slot 6 + component) n]
 #pragma unroll 1
     for (int p = 0; p < np; ++p) {
       int sl = d0 + p;
@@ -432,13 +432,13 @@ __device__ void plane_interp(const InterpArgs<T>& ia, const InterpPre<T, T2>& pr
         }
       }
       const T wz = sl == 0 ? Bz[4] : sl == 1 ? Bz[3] : sl == 2 ? Bz[2] : sl == 3 ? Bz[1] : Bz[0];
-      T* o6 = out + sl * 6;
+      T* o6 = out + (size_t)sl * 6 * ia.n;
       if (part == 0) {
-        o6[0] = wz * ax; o6[1] = wz * ay;
-        o6[3] = wz * bx; o6[4] = wz * by;
+        o6[0] = wz * ax; o6[(size_t)ia.n] = wz * ay;
+        o6[3 * (size_t)ia.n] = wz * bx; o6[4 * (size_t)ia.n] = wz * by;
       } else {
-        o6[2] = wz * ax;
-        o6[5] = wz * bx;
+        o6[2 * (size_t)ia.n] = wz * ax;
+        o6[5 * (size_t)ia.n] = wz * bx;
       }
     }
   }

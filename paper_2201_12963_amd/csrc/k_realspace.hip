@@ -409,11 +409,11 @@ __global__ __launch_bounds__(256) void k_site_forces_sum(SiteSet<T> st, ForceArg
   const double* fp = fa.f_pair + (size_t)frame * 3 * st.n;
   const double* fep = fa.f_elec + (size_t)frame * 6 * st.n;
   const int P = fa.mi.order;
-  const T* pp = epart + (fo + j) * (6 * P);
+  const T* pp = epart + (size_t)frame * 6 * P * st.n + j;   // share (slot, component) at [(slot 6 + component) n]
   T e[6] = {0, 0, 0, 0, 0, 0};
   for (int sl = 0; sl < P; ++sl)
 #pragma unroll
-    for (int u = 0; u < 6; ++u) e[u] += pp[sl * 6 + u];
+    for (int u = 0; u < 6; ++u) e[u] += pp[(size_t)(sl * 6 + u) * st.n];
   double F[3], FB[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
