@@ -96,6 +96,8 @@ def kernel_work(w, name, n_frames=1, n_dv=1, mixed=False):
         return "hbm", 8 * ne * ne + n_frames * 8 * 3 * ne, "GB/s"
     if name.startswith("fft_z"):    # complex mesh read and written (+ G once)
         return "hbm", M * 8 + n_frames * M * 16 * 2, "GB/s"
+    if name == "fft_xy_fwd":        # the spread's launch: sites in, the complex planes out
+        return "hbm", n_frames * (nl * 32 + M * 16), "GB/s"
     if name.startswith("fft_xy"):   # real plane in, complex plane out (or back)
         return "hbm", n_frames * M * (8 + 16), "GB/s"
     if name == "spread_elec":       # stencil table once; q read, mesh written per frame

@@ -284,9 +284,10 @@ int cpm_set_matrix(cpm_ctx* ctx, const double* host_S);
  *   CPM_BUF_NCELL     int32 [3]  cells per axis
  *   CPM_BUF_BATCH_CHUNK int32 [3] the batch tuner's choices: frames per launch (0: not tuned yet),
  *                       site-pair tile workgroups per cell, x-y planes per workgroup (0: as many as fit)
- * The meshes are those of a cpm_solve: cpm_solve_batch transforms the
- * potential only on the planes the electrode stencils reach and, at spline
- * order 5, interpolates the field at the sites without storing its mesh. */
+ * The meshes are those of a cpm_solve: cpm_solve_batch does not store the
+ * charge mesh, transforms the potential only on the planes the electrode
+ * stencils reach and, at spline order 5, interpolates the field at the sites
+ * without storing its mesh. */
 enum {
   CPM_BUF_CELL_START = 0, CPM_BUF_SITE_ORDER = 1, CPM_BUF_PHI_REAL = 2, CPM_BUF_B = 3,
   CPM_BUF_RHO_MESH = 4, CPM_BUF_PHI_MESH = 5, CPM_BUF_FIELD_MESH = 6, CPM_BUF_NCELL = 7,

@@ -517,8 +517,10 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces, bool need_b = 
   rb.item_lo = c->d_item_lo;
   rb.item_hi = c->d_item_hi;
   if (c->kspace == CPM_KSPACE_PPPM) {
+    // (the real charge mesh is kept for inspection after one frame only)
     rec(c, CPM_KERNEL_FFT_XY_FWD, s, [=](hipStream_t s) {
-      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, B::rho(c), B::c1(c), true, true);
+      launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, nf == 1 ? B::rho(c) : nullptr,
+                                    B::c1(c), true, true);
     });
     keep(c, CPM_KERNEL_BIN, [=](hipStream_t s) {
       launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, B::rho(c), B::c1(c), false, true);
