@@ -139,6 +139,42 @@ def test_batch_matches_single_frames(torch_dev, geometry):
     ctx.close()
 
 
+@pytest.mark.parametrize("order", [4, 6])
+def test_batch_matches_single_frames_other_spline_orders(torch_dev, order):
+    """Batches at B-spline orders other than 5: the site forces gather the
+    field meshes (the per-plane interpolation inside the inverse x-y pass
+    takes order 5 only), and the planes the electrode stencils reach differ
+    from order 5's.  The batch is compared with single frames of the same
+    context; the single-frame path at these orders is compared with the
+    oracle in test_step_parity_spline_orders."""
+    torch = torch_dev
+    import dataclasses
+    from workloads import perturbed_frames
+    _say(f"[gpu] batch paper ff, order {order}")
+    w0, _, _ = built("paper", "ff")
+    w = dataclasses.replace(w0, order=order)
+    frames = perturbed_frames(w, 5, sigma=0.05, seed=9)
+    dvs = np.array([0.0, 1.5, 4.0])
+    ctx, stream = gpu_context(torch, w)
+    X = torch.tensor(frames, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        Qb, Fb, Eb = ctx.solve_batch(X, dvs)
+    stream.synchronize()
+    assert ctx.sync_status() == 0
+    Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
+    for fi in (0, 4):
+        x = torch.tensor(frames[fi], dtype=torch.float64, device="cuda")
+        for vi, dv in enumerate(dvs):
+            with torch.cuda.stream(stream):
+                q, f, e = ctx.solve(x, float(dv))
+            stream.synchronize()
+            q, f, e = q.cpu().numpy(), f.cpu().numpy(), e.cpu().numpy()
+            assert np.abs(Qb[fi, vi] - q).max() < 1e-11
+            assert rel_rms(Fb[fi, vi], f) < 1e-10
+            assert np.abs(Eb[fi, vi] - e).max() < 1e-9 * np.abs(e).max()
+    ctx.close()
+
+
 def test_batch_matches_single_frames_large_cell(torch_dev):
     """The batched pair tiles on a grid whose x-y stencil is a proper subset of
     the cross-section (5 x 5 cells in x-y, 21 along z): forward stencils of
