@@ -115,6 +115,15 @@ struct cpm_ctx {
   FFTPlan1D px{}, py{}, pz{};
   ZPassArgs za_pot{}, za_field{};
   ZMask zmask_e{};             // the electrode charge's planes (many-frame field pass)
+  // The MD loop's charges stay fixed between updates, and with them the
+  // electrode charge's x-y spectrum: elec_mode 1 makes the one-frame FP64
+  // force pass keep that spectrum in d_c1e (the field's z pass then reads
+  // it there), 2 reuses it (no electrode spread, x-y pass or charge
+  // permutation); elec_owner names the MD loop whose charges d_c1e and the
+  // sorted charges d_qs hold, and every other enqueue clears it
+  double2* d_c1e = nullptr;
+  int elec_mode = 0;
+  const void* elec_owner = nullptr;
   bool zmask_ok = false;       // K_z <= 256: the field pass can take the mask
   int* d_zl = nullptr;         // the planes the electrode stencils reach, ascending
   int n_zl = 0;
@@ -487,6 +496,7 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces, bool need_b = 
   using B = Bufs<T>;
   using T2 = typename B::T2;
   hipStream_t s = c->stream;
+  c->elec_owner = nullptr;
   const bool mixed = std::is_same<T, float>::value;
   BinArgs ba{};
   ba.n_site = c->n_site;
@@ -618,27 +628,35 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
   }
   const T* epart = nullptr;   // the interpolation's per-plane shares (many frames, order 5)
   if (c->kspace == CPM_KSPACE_PPPM) {
-    // the electrode spread stays a kernel of its own: only the few planes
-    // near the electrodes hold charge, and a per-plane fusion would leave
-    // that work to a handful of workgroups
-    rec(c, CPM_KERNEL_SPREAD_ELEC, s, [=](hipStream_t s) {
-      launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
-                              B::rho_e(c), c->mi.M, sl, fa.field_frame ? c->d_slabfield : nullptr);
-    });
+    // (the MD loop's kept electrode spectrum: FP64 one-frame passes only)
+    const int em = (nf == 1 && std::is_same<T, double>::value && c->d_c1e) ? c->elec_mode : 0;
+    T2* espec = em ? reinterpret_cast<T2*>(c->d_c1e) : B::c1(c);
+    if (em != 2) {
+      // the electrode spread stays a kernel of its own: only the few planes
+      // near the electrodes hold charge, and a per-plane fusion would leave
+      // that work to a handful of workgroups
+      rec(c, CPM_KERNEL_SPREAD_ELEC, s, [=](hipStream_t s) {
+        launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
+                                B::rho_e(c), c->mi.M, sl, fa.field_frame ? c->d_slabfield : nullptr);
+      });
+    } else if (fa.field_frame) {
+      launch_slab_field(s, nf, sl, qa, qa_stride, c->d_slabfield);
+    }
     // many frames: only the planes holding electrode charge, which the
     // field pass then reads alone (the others are zero)
     const bool planes = nf > 1 && c->zmask_ok;
-    rec(c, CPM_KERNEL_FFT_XY_FWD_E, s, [=](hipStream_t s) {
-      launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, B::c1(c), nullptr, nullptr, 0,
-                             planes ? c->d_zl : nullptr, planes ? c->n_zl : 0);
-    });
+    if (em != 2)
+      rec(c, CPM_KERNEL_FFT_XY_FWD_E, s, [=](hipStream_t s) {
+        launch_fft_xy_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], 0, B::rho_e(c), nullptr, espec, nullptr, nullptr, 0,
+                               planes ? c->d_zl : nullptr, planes ? c->n_zl : 0);
+      });
     // one frame: the site-pair workgroups ride in the z pass (latency);
     // many frames: a launch of their own, so that the z pass keeps its small
     // LDS footprint and occupancy (throughput)
     const bool host_pairs = nf == 1;
     rec(c, CPM_KERNEL_FFT_Z_FIELD, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, true,
-                            nullptr, host_pairs ? &pa : nullptr, planes ? &c->zmask_e : nullptr);
+                            nullptr, host_pairs ? &pa : nullptr, planes ? &c->zmask_e : nullptr, espec);
     });
     if (host_pairs)   // timed alone through the stand-alone kernel with the same body
       keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
@@ -744,7 +762,7 @@ template <typename T>
 int enqueue_forces_at(cpm_ctx* c, const double* xyz, double dv, const double* q, double* f_out) {
   hipStream_t s = c->stream;
   TRY(enqueue_b<T>(c, 1, xyz, true, false));
-  launch_permute(s, 1, c->n_elec, c->d_epos, q, c->d_qs);
+  if (c->elec_mode != 2) launch_permute(s, 1, c->n_elec, c->d_epos, q, c->d_qs);
   ForceArgs<T> fa{};
   fa.out_scale = 1.0;
   fa.field = (c->geometry == CPM_FINITE_FIELD) ? -dv / c->box[2] : 0.0;
@@ -1819,6 +1837,8 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
   a.cell_start = c->d_cell_start; a.order = c->d_order; a.carbon_run = crun_d;
   a.nc_z = ncz; a.nxy = cl.nc[0] * cl.nc[1]; a.lj_reach = reach; a.Lz = Lz;
   md->d_q = q; md->d_fc = fc; md->d_energy = en;
+  if (c->kspace == CPM_KSPACE_PPPM && !c->d_c1e && dalloc(c, &c->d_c1e, (size_t)c->mi.M) != CPM_OK)
+    return bad(CPM_ENOMEM);
   *out = md;
   return CPM_OK;
 }
@@ -1830,9 +1850,15 @@ namespace {
 int md_forces(cpm_md* md, double* x, double dv, bool update) {
   cpm_ctx* c = md->c;
   // the Coulomb part first: its binning of x gives the Lennard-Jones kernel
-  // its z windows
-  TRY(update ? enqueue_solve<double>(c, x, dv, md->d_q, md->d_fc, md->d_energy)
-             : enqueue_forces_at<double>(c, x, dv, md->d_q, md->d_fc));
+  // its z windows.  Between charge updates the electrode spectrum and the
+  // sorted charges of the last update are reused, if nothing else has run
+  // on the context since
+  c->elec_mode = (!update && c->elec_owner == md) ? 2 : 1;
+  const int r = update ? enqueue_solve<double>(c, x, dv, md->d_q, md->d_fc, md->d_energy)
+                       : enqueue_forces_at<double>(c, x, dv, md->d_q, md->d_fc);
+  c->elec_mode = 0;
+  TRY(r);
+  if (c->d_c1e) c->elec_owner = md;
   md->a.cell_start = c->d_cell_start;
   md->a.order = c->d_order;
   launch_lj(c->stream, md->a);

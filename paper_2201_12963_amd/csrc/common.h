@@ -498,7 +498,10 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass = true,
-                    const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr, const ZMask* zm = nullptr);
+                    const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr, const ZMask* zm = nullptr,
+                    const T2* in1 = nullptr);
+// (in1: the input spectrum if not data1, which then only takes the result;
+// the masked many-frame launches work in place)
 template <typename T, typename T2>
 size_t fft_xy_spread_lds(int Kx, int Ky);
 // dynamic LDS of an x-y launch holding `planes` planes of elt_bytes complex values

@@ -721,9 +721,11 @@ __device__ __forceinline__ bool zplane_on(const ZMask& zm, int z) {
 }
 
 // (the body; k_fft_z and k_fft_z_masked below are its launches)
-template <typename T, typename T2, bool MULTI, bool MASK>
+// SEP: the input spectrum is in1 (a copy kept elsewhere), else data1 itself
+template <typename T, typename T2, bool MULTI, bool MASK, bool SEP>
 __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs& za, const T* __restrict__ G,
-                                           T2* __restrict__ data1, T2* __restrict__ data2,
+                                           const T2* __restrict__ in1, T2* __restrict__ data1,
+                                           T2* __restrict__ data2,
                                            T2* __restrict__ save, int add_saved,
                                            double* __restrict__ energy_part, int n_z_blocks,
                                            const RealBArgs<T>& rb, const PairArgs<T>& pa, int lpw, int ek_stride,
@@ -780,14 +782,14 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
     gk[u] = (T)0;
     sv[u] = T2{(T)0, (T)0};
     if (active && z < Kz) {
-      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
+      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? (SEP ? in1 : data1)[fo + z * plane + cxy] : T2{(T)0, (T)0};
       gk[u] = G[z * plane + cxy];
       if (za.mode == 1 && add_saved) sv[u] = save[fo + z * plane + cxy];
     }
   }
   if (active)
     for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs)
-      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? data1[fo + z * plane + cxy] : T2{(T)0, (T)0};
+      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? (SEP ? in1 : data1)[fo + z * plane + cxy] : T2{(T)0, (T)0};
   __syncthreads();                                         // twiddles
   double e = 0.0;
   if (wave_on) {
@@ -871,8 +873,20 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
                                                T2* __restrict__ save, int add_saved,
                                                double* __restrict__ energy_part, int n_z_blocks,
                                                RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride) {
-  fft_z_body<T, T2, MULTI, false>(pz, za, G, data1, data2, save, add_saved, energy_part, n_z_blocks, rb, pa, lpw,
-                                  ek_stride, ZMask{});
+  fft_z_body<T, T2, MULTI, false, false>(pz, za, G, nullptr, data1, data2, save, add_saved, energy_part, n_z_blocks,
+                                         rb, pa, lpw, ek_stride, ZMask{});
+}
+
+// the same reading its input spectrum from in1 (kept apart from data1,
+// which takes the result)
+template <typename T, typename T2, bool MULTI>
+__global__ __launch_bounds__(256) void k_fft_z_sep(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
+                                                   const T2* __restrict__ in1, T2* __restrict__ data1,
+                                                   T2* __restrict__ data2, T2* __restrict__ save, int add_saved,
+                                                   double* __restrict__ energy_part, int n_z_blocks,
+                                                   RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride) {
+  fft_z_body<T, T2, MULTI, false, true>(pz, za, G, in1, data1, data2, save, add_saved, energy_part, n_z_blocks,
+                                        rb, pa, lpw, ek_stride, ZMask{});
 }
 
 // many frames: the potential pass writing, the field pass reading, only the
@@ -884,8 +898,8 @@ __global__ __launch_bounds__(256) void k_fft_z_masked(FFTPlan1D pz, ZPassArgs za
                                                       double* __restrict__ energy_part, int n_z_blocks,
                                                       RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride,
                                                       ZMask zm) {
-  fft_z_body<T, T2, MULTI, true>(pz, za, G, data1, data2, save, add_saved, energy_part, n_z_blocks, rb, pa, lpw,
-                                 ek_stride, zm);
+  fft_z_body<T, T2, MULTI, true, false>(pz, za, G, nullptr, data1, data2, save, add_saved, energy_part, n_z_blocks,
+                                        rb, pa, lpw, ek_stride, zm);
 }
 
 
@@ -995,7 +1009,8 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass,
-                    const RealBArgs<T>* rb, const PairArgs<T>* pa, const ZMask* zm) {
+                    const RealBArgs<T>* rb, const PairArgs<T>* pa, const ZMask* zm, const T2* in1) {
+  if (!in1) in1 = data1;
   const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
   // columns per wavefront: one for one frame (the chain of a column is the
@@ -1023,12 +1038,22 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
     std::fprintf(stderr, "cpm: no hosted work in a z pass of several columns per wavefront\n");
     std::abort();
   }
+  if (zm && in1 != data1) {
+    std::fprintf(stderr, "cpm: a masked z pass works in place\n");
+    std::abort();
+  }
   if (zm && lpw > 1)
     hipLaunchKernelGGL((k_fft_z_masked<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save,
                        add_saved, energy_part, nzb, r, p, lpw, za.n_blocks, *zm);
   else if (zm)
     hipLaunchKernelGGL((k_fft_z_masked<T, T2, false>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save,
                        add_saved, energy_part, nzb, r, p, 1, za.n_blocks, *zm);
+  else if (in1 != data1 && lpw > 1)
+    hipLaunchKernelGGL((k_fft_z_sep<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, in1, data1, data2, save,
+                       add_saved, energy_part, nzb, r, p, lpw, za.n_blocks);
+  else if (in1 != data1)
+    hipLaunchKernelGGL((k_fft_z_sep<T, T2, false>), grid, dim3(256), lds, s, pz, za, G, in1, data1, data2, save,
+                       add_saved, energy_part, nzb, r, p, 1, za.n_blocks);
   else if (lpw > 1)
     hipLaunchKernelGGL((k_fft_z<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
                        energy_part, nzb, r, p, lpw, za.n_blocks);
@@ -1045,10 +1070,12 @@ template void launch_fft_xy_t<float, float2>(hipStream_t, int, const FFTPlan1D&,
                                              const int*, int);
 template void launch_fft_z_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                               const double*, double2*, double2*, double2*, int, double*, bool,
-                                              const RealBArgs<double>*, const PairArgs<double>*, const ZMask*);
+                                              const RealBArgs<double>*, const PairArgs<double>*, const ZMask*,
+                                              const double2*);
 template void launch_fft_z_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                             const float*, float2*, float2*, float2*, int, double*, bool,
-                                            const RealBArgs<float>*, const PairArgs<float>*, const ZMask*);
+                                            const RealBArgs<float>*, const PairArgs<float>*, const ZMask*,
+                                            const float2*);
 template void launch_fft_xy_field_inv_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&,
                                                          int, const double2*, const double2*, double*, size_t,
                                                          const InterpArgs<double>*);

@@ -88,3 +88,45 @@ def test_md_loop_parity(torch_dev, name, geometry, n_steps):
         assert abs(np.linalg.norm(r) - d) < 1e-10
     mdl.close()
     ctx.close()
+
+
+def test_md_loop_after_another_solve_on_the_context(torch_dev):
+    """Between charge updates the loop reuses the electrode charge's x-y
+    spectrum (PPPM) and sorted charges of the last update.  A solve of other
+    positions on the same context in between replaces the sorted charges;
+    the loop must notice and rebuild them from its own charges, so that the
+    trajectory is the one without the interruption."""
+    torch = torch_dev
+    from oracle import md
+    from paper_2201_12963_amd import Context, MDLoop
+    from workloads import md_setup, perturbed_frames
+    _say("[gpu] md loop paper ff (PPPM), a solve between two runs")
+    w, A, S = built("paper", "ff")
+    setup = md_setup(w)
+    v0 = np.random.default_rng(23).normal(0.0, 1.0, (3, w.n_site)) * np.sqrt(md.KB * setup.temperature /
+                                                                             setup.site_mass)
+    other = perturbed_frames(w, 1, sigma=0.2, seed=5)[0]
+    results = []
+    for interrupt in (False, True):
+        stream = torch.cuda.Stream()
+        ctx = Context.from_workload(w, stream=stream)
+        ctx.build_elastance()
+        mdl = MDLoop(ctx, setup)
+        x = torch.tensor(w.site_xyz, dtype=torch.float64, device="cuda")
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(stream):
+            mdl.run(x, v, w.dv, 7)                   # ends two steps after an update
+            if interrupt:
+                xo = torch.tensor(other, dtype=torch.float64, device="cuda")
+                ctx.solve(xo, 0.5 * w.dv)
+            q, _ = mdl.run(x, v, w.dv, 6)
+        stream.synchronize()
+        assert ctx.sync_status() == 0
+        results.append((x.cpu().numpy(), v.cpu().numpy(), q.cpu().numpy()))
+        mdl.close()
+        ctx.close()
+    (xa, va, qa), (xb, vb, qb) = results
+    _say(f"    x {np.abs(xa - xb).max():.2e} nm, v {np.abs(va - vb).max():.2e}, q {np.abs(qa - qb).max():.2e} e")
+    assert np.abs(xa - xb).max() < 1e-11
+    assert np.abs(va - vb).max() < 1e-8 * np.abs(va).max()
+    assert np.abs(qa - qb).max() < 1e-11
