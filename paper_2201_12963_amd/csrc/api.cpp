@@ -123,6 +123,10 @@ struct cpm_ctx {
   // sorted charges d_qs hold, and every other enqueue clears it
   double2* d_c1e = nullptr;
   int elec_mode = 0;
+  // set by enqueue_b when it leaves out the potential's z pass (forces at
+  // given charges with the kept spectrum: the field pass then transforms the
+  // electrolyte and electrode spectra summed, and no b is needed)
+  bool fold_pot = false;
   const void* elec_owner = nullptr;
   bool zmask_ok = false;       // K_z <= 256: the field pass can take the mask
   int* d_zl = nullptr;         // the planes the electrode stencils reach, ascending
@@ -536,13 +540,18 @@ int enqueue_b(cpm_ctx* c, int nf, const double* xyz, bool forces, bool need_b = 
       launch_fft_xy_spread_t<T, T2>(s, nf, c->px, c->py, c->mi.K[2], c->mi, ba, B::rho(c), B::c1(c), false, true);
     });
     if (rb.tiles) rec(c, CPM_KERNEL_REAL_B, s, [=](hipStream_t s) { launch_real_b_t<T>(s, nf, rb); });
-    rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
-      // (many frames: the result only on the planes the electrode stencils read)
-      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
-                            forces ? B::save(c) : nullptr, 0, c->d_ek, true,
-                            (rb.tiles || !need_b) ? nullptr : &rb, nullptr,
-                            nf > 1 && c->zmask_ok ? &c->zmask_e : nullptr);
-    });
+    // forces at given charges in the MD loop (its electrode spectrum kept):
+    // no potential pass, the field pass folds the two spectra
+    c->fold_pot = !need_b && nf == 1 && c->elec_mode != 0 && c->d_c1e && std::is_same<T, double>::value;
+    if (!c->fold_pot) {
+      rec(c, CPM_KERNEL_FFT_Z_POT, s, [=](hipStream_t s) {
+        // (many frames: the result only on the planes the electrode stencils read)
+        launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_pot, B::G(c), B::c1(c), nullptr,
+                              forces ? B::save(c) : nullptr, 0, c->d_ek, true,
+                              (rb.tiles || !need_b) ? nullptr : &rb, nullptr,
+                              nf > 1 && c->zmask_ok ? &c->zmask_e : nullptr);
+      });
+    }
     // forces at given charges (MD steps between charge updates): only the
     // saved site spectrum is needed, not b
     if (!need_b) return CPM_OK;
@@ -654,9 +663,11 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     // many frames: a launch of their own, so that the z pass keeps its small
     // LDS footprint and occupancy (throughput)
     const bool host_pairs = nf == 1;
+    const bool fold = em != 0 && c->fold_pot;
     rec(c, CPM_KERNEL_FFT_Z_FIELD, s, [=](hipStream_t s) {
-      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), B::save(c), 1, nullptr, true,
-                            nullptr, host_pairs ? &pa : nullptr, planes ? &c->zmask_e : nullptr, espec);
+      launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), fold ? nullptr : B::save(c),
+                            fold ? 2 : 1, nullptr, true, nullptr, host_pairs ? &pa : nullptr,
+                            planes ? &c->zmask_e : nullptr, espec);
     });
     if (host_pairs)   // timed alone through the stand-alone kernel with the same body
       keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });

@@ -709,7 +709,10 @@ template <typename T> __device__ __forceinline__ T mode_k(int i, int K, T twopi_
 
 // mode 0 (potential): X = FFT_z(data1); if save: save = X; energy partial
 //          1/2 sum G |X|^2; data1 = IFFT_z(G X)
-// mode 1 (field):     X = FFT_z(data1) (+ save if add_saved);
+// mode 1 (field):     X = FFT_z(data1) (+ save if add_saved == 1; with a
+//          separate input, SEP, X = FFT_z(in1), or FFT_z(in1 + data1) if
+//          add_saved == 2: the electrode and the electrolyte spectra summed
+//          before the transform, which is linear);
 //          data1 = IFFT_z((-i kx + ky) G X)  [Ex + i Ey after the x-y inverse]
 //          data2 = IFFT_z(-i kz G X)         [Ez]
 // MULTI: many frames, lpw columns per wavefront (else one, and hosted work)
@@ -774,6 +777,14 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
   T2* Al = A + c * Kz;
   // the columns, and the multiplier (and saved spectrum) of this lane's
   // points, loaded together so that their latencies overlap
+  // the input spectrum at point z of this lane's column
+  auto load_in = [&](int z) -> T2 {
+    const size_t o = fo + z * plane + cxy;
+    if (!SEP) return data1[o];
+    T2 a = in1[o];
+    if (add_saved == 2) { const T2 b = data1[o]; a.x += b.x; a.y += b.y; }
+    return a;
+  };
   T gk[ZPASS_PREFETCH];
   T2 sv[ZPASS_PREFETCH];
 #pragma unroll
@@ -782,14 +793,14 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
     gk[u] = (T)0;
     sv[u] = T2{(T)0, (T)0};
     if (active && z < Kz) {
-      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? (SEP ? in1 : data1)[fo + z * plane + cxy] : T2{(T)0, (T)0};
+      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? load_in(z) : T2{(T)0, (T)0};
       gk[u] = G[z * plane + cxy];
-      if (za.mode == 1 && add_saved) sv[u] = save[fo + z * plane + cxy];
+      if (za.mode == 1 && add_saved == 1) sv[u] = save[fo + z * plane + cxy];
     }
   }
   if (active)
     for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs)
-      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? (SEP ? in1 : data1)[fo + z * plane + cxy] : T2{(T)0, (T)0};
+      Al[z] = (!MASK || za.mode == 0 || zplane_on(zm, z)) ? load_in(z) : T2{(T)0, (T)0};
   __syncthreads();                                         // twiddles
   double e = 0.0;
   if (wave_on) {
@@ -823,7 +834,7 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
       T2* Cl = C + c * Kz;
       auto mul = [&](int z, T g, T2 w) {
         T2 v = Xl[z];
-        if (add_saved) { v.x += w.x; v.y += w.y; }
+        if (add_saved == 1) { v.x += w.x; v.y += w.y; }
         v = T2{v.x * g, v.y * g};
         Cl[z] = v;
         F1l[z] = T2{kx * v.y + ky * v.x, -kx * v.x + ky * v.y};
@@ -833,7 +844,7 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
         for (int u = 0; u < ZPASS_PREFETCH; ++u)
           if (z0 + u * zs < Kz) mul(z0 + u * zs, gk[u], sv[u]);
         for (int z = z0 + ZPASS_PREFETCH * zs; z < Kz; z += zs)
-          mul(z, G[z * plane + cxy], add_saved ? save[fo + z * plane + cxy] : T2{(T)0, (T)0});
+          mul(z, G[z * plane + cxy], add_saved == 1 ? save[fo + z * plane + cxy] : T2{(T)0, (T)0});
       }
       T2* Y = fft_line_w(F1, X, pz, twz, +1, L, Kz);
       if (active)
