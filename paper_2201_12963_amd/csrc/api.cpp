@@ -127,6 +127,10 @@ struct cpm_ctx {
   // given charges with the kept spectrum: the field pass then transforms the
   // electrolyte and electrode spectra summed, and no b is needed)
   bool fold_pot = false;
+  // the MD loop's Lennard-Jones sums to ride in its field pass (set by the
+  // loop around its force enqueue), and whether they did
+  const MDArgs* host_lj = nullptr;
+  bool lj_hosted = false;
   const void* elec_owner = nullptr;
   bool zmask_ok = false;       // K_z <= 256: the field pass can take the mask
   int* d_zl = nullptr;         // the planes the electrode stencils reach, ascending
@@ -664,10 +668,13 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
     // LDS footprint and occupancy (throughput)
     const bool host_pairs = nf == 1;
     const bool fold = em != 0 && c->fold_pot;
+    const bool with_lj = em != 0 && c->host_lj;
+    const MDArgs ljv = with_lj ? *c->host_lj : MDArgs{};
+    c->lj_hosted = with_lj;
     rec(c, CPM_KERNEL_FFT_Z_FIELD, s, [=](hipStream_t s) {
       launch_fft_z_t<T, T2>(s, nf, c->pz, c->za_field, B::G(c), B::c1(c), B::c2(c), fold ? nullptr : B::save(c),
                             fold ? 2 : 1, nullptr, true, nullptr, host_pairs ? &pa : nullptr,
-                            planes ? &c->zmask_e : nullptr, espec);
+                            planes ? &c->zmask_e : nullptr, espec, with_lj ? &ljv : nullptr);
     });
     if (host_pairs)   // timed alone through the stand-alone kernel with the same body
       keep(c, CPM_KERNEL_SITE_PAIRS, [=](hipStream_t s) { launch_site_pairs_t<T>(s, nf, pa); });
@@ -1860,19 +1867,24 @@ namespace {
 // with a charge solve (update) or at the charges of the last update
 int md_forces(cpm_md* md, double* x, double dv, bool update) {
   cpm_ctx* c = md->c;
-  // the Coulomb part first: its binning of x gives the Lennard-Jones kernel
-  // its z windows.  Between charge updates the electrode spectrum and the
-  // sorted charges of the last update are reused, if nothing else has run
-  // on the context since
+  // the Coulomb part first: its binning of x gives the Lennard-Jones sums
+  // their z windows, and its field pass hosts them (PPPM; else a launch of
+  // their own follows).  Between charge updates the electrode spectrum and
+  // the sorted charges of the last update are reused, if nothing else has
+  // run on the context since
   c->elec_mode = (!update && c->elec_owner == md) ? 2 : 1;
+  md->a.cell_start = c->d_cell_start;
+  md->a.order = c->d_order;
+  c->host_lj = &md->a;                 // the Lennard-Jones sums ride in the field pass (PPPM)
+  c->lj_hosted = false;
   const int r = update ? enqueue_solve<double>(c, x, dv, md->d_q, md->d_fc, md->d_energy)
                        : enqueue_forces_at<double>(c, x, dv, md->d_q, md->d_fc);
   c->elec_mode = 0;
+  c->host_lj = nullptr;
   TRY(r);
   if (c->d_c1e) c->elec_owner = md;
-  md->a.cell_start = c->d_cell_start;
-  md->a.order = c->d_order;
-  launch_lj(c->stream, md->a);
+  if (!c->lj_hosted) launch_lj(c->stream, md->a);
+  c->lj_hosted = false;
   return CPM_OK;
 }
 

@@ -482,6 +482,8 @@ template <typename T>
 void launch_gather_b_t(hipStream_t s, int n_frames, int n_elec, int P3, const int* gidx, const T* gw,
                        const T* phi, int M, const T* phi_real, double* b, const SlabTerms& sl = SlabTerms{});
 
+struct MDArgs;   // the MD loop's arguments (below)
+
 // FFT passes (k_fft.hip)
 template <typename T, typename T2>
 void launch_fft_xy_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
@@ -499,7 +501,7 @@ template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass = true,
                     const RealBArgs<T>* rb = nullptr, const PairArgs<T>* pa = nullptr, const ZMask* zm = nullptr,
-                    const T2* in1 = nullptr);
+                    const T2* in1 = nullptr, const MDArgs* lj = nullptr);
 // (in1: the input spectrum if not data1, which then only takes the result;
 // the masked many-frame launches work in place)
 template <typename T, typename T2>

@@ -20,6 +20,7 @@
 #include <cstdlib>
 
 #include "common.h"
+#include "lj.h"
 #include "bin.h"
 #include "pairs.h"
 
@@ -725,14 +726,16 @@ __device__ __forceinline__ bool zplane_on(const ZMask& zm, int z) {
 
 // (the body; k_fft_z and k_fft_z_masked below are its launches)
 // SEP: the input spectrum is in1 (a copy kept elsewhere), else data1 itself
-template <typename T, typename T2, bool MULTI, bool MASK, bool SEP>
+// LJ: n_lj more hosted workgroups take the Lennard-Jones sums of the MD
+// loop's sites (lj_site), after those of rb and pa
+template <typename T, typename T2, bool MULTI, bool MASK, bool SEP, bool LJ = false>
 __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs& za, const T* __restrict__ G,
                                            const T2* __restrict__ in1, T2* __restrict__ data1,
                                            T2* __restrict__ data2,
                                            T2* __restrict__ save, int add_saved,
                                            double* __restrict__ energy_part, int n_z_blocks,
                                            const RealBArgs<T>& rb, const PairArgs<T>& pa, int lpw, int ek_stride,
-                                           const ZMask& zm) {
+                                           const ZMask& zm, const MDArgs* lj = nullptr) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[8];
   if (!MULTI && (int)blockIdx.x >= n_z_blocks) {
@@ -745,6 +748,8 @@ __device__ __forceinline__ void fft_z_body(const FFTPlan1D& pz, const ZPassArgs&
     if (hb < rb.n_blocks) {
       const int g = xcd_block(hb, rb.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
       if (g < rb.el.n) real_b_wave(rb.cell, rb.alpha, rb.eta, rb.rc2, rb.el, rb.st, rb.phi_out, g, blockIdx.y, qbuf);
+    } else if (LJ && hb >= rb.n_blocks + pa.n_blocks) {
+      lj_site<4>(*lj, hb - rb.n_blocks - pa.n_blocks);
     } else {
       const int j = xcd_block(hb - rb.n_blocks, pa.n_blocks) * (blockDim.x / WAVE) + (threadIdx.x >> 6);
       if (j < pa.st.n) site_pairs_wave(pa.cell, pa.st, pa.alpha, pa.rc2, pa.f_pair, pa.u_site, j, blockIdx.y, qbuf);
@@ -889,15 +894,17 @@ __global__ __launch_bounds__(256) void k_fft_z(FFTPlan1D pz, ZPassArgs za, const
 }
 
 // the same reading its input spectrum from in1 (kept apart from data1,
-// which takes the result)
+// which takes the result): the MD loop's field pass, with the loop's
+// Lennard-Jones sums as more hosted workgroups (one per site)
 template <typename T, typename T2, bool MULTI>
 __global__ __launch_bounds__(256) void k_fft_z_sep(FFTPlan1D pz, ZPassArgs za, const T* __restrict__ G,
                                                    const T2* __restrict__ in1, T2* __restrict__ data1,
                                                    T2* __restrict__ data2, T2* __restrict__ save, int add_saved,
                                                    double* __restrict__ energy_part, int n_z_blocks,
-                                                   RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride) {
-  fft_z_body<T, T2, MULTI, false, true>(pz, za, G, in1, data1, data2, save, add_saved, energy_part, n_z_blocks,
-                                        rb, pa, lpw, ek_stride, ZMask{});
+                                                   RealBArgs<T> rb, PairArgs<T> pa, int lpw, int ek_stride,
+                                                   MDArgs lj) {
+  fft_z_body<T, T2, MULTI, false, true, true>(pz, za, G, in1, data1, data2, save, add_saved, energy_part,
+                                              n_z_blocks, rb, pa, lpw, ek_stride, ZMask{}, &lj);
 }
 
 // many frames: the potential pass writing, the field pass reading, only the
@@ -1020,8 +1027,14 @@ void launch_fft_xy_field_inv_t(hipStream_t s, int n_frames, const FFTPlan1D& px,
 template <typename T, typename T2>
 void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPassArgs& za, const T* G,
                     T2* data1, T2* data2, T2* save, int add_saved, double* energy_part, bool z_pass,
-                    const RealBArgs<T>* rb, const PairArgs<T>* pa, const ZMask* zm, const T2* in1) {
+                    const RealBArgs<T>* rb, const PairArgs<T>* pa, const ZMask* zm, const T2* in1,
+                    const MDArgs* lj) {
   if (!in1) in1 = data1;
+  if (lj && (in1 == data1 || n_frames != 1)) {
+    std::fprintf(stderr, "cpm: the Lennard-Jones sums ride only in a one-frame field pass with a kept input\n");
+    std::abort();
+  }
+  const int n_lj = lj ? lj->n_site : 0;
   const RealBArgs<T> r = rb ? *rb : RealBArgs<T>{};
   const PairArgs<T> p = pa ? *pa : PairArgs<T>{};
   // columns per wavefront: one for one frame (the chain of a column is the
@@ -1041,7 +1054,7 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
     std::fprintf(stderr, "cpm: only the one-wavefront-per-target pair forms ride in the z pass\n");
     std::abort();
   }
-  dim3 grid(nzb + r.n_blocks + p.n_blocks, n_frames);
+  dim3 grid(nzb + r.n_blocks + p.n_blocks + n_lj, n_frames);
   if (grid.x == 0) return;
   // energy partials: za.n_blocks per frame (the one-column-per-wavefront
   // count the buffers are sized for)
@@ -1061,10 +1074,10 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
                        add_saved, energy_part, nzb, r, p, 1, za.n_blocks, *zm);
   else if (in1 != data1 && lpw > 1)
     hipLaunchKernelGGL((k_fft_z_sep<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, in1, data1, data2, save,
-                       add_saved, energy_part, nzb, r, p, lpw, za.n_blocks);
+                       add_saved, energy_part, nzb, r, p, lpw, za.n_blocks, lj ? *lj : MDArgs{});
   else if (in1 != data1)
     hipLaunchKernelGGL((k_fft_z_sep<T, T2, false>), grid, dim3(256), lds, s, pz, za, G, in1, data1, data2, save,
-                       add_saved, energy_part, nzb, r, p, 1, za.n_blocks);
+                       add_saved, energy_part, nzb, r, p, 1, za.n_blocks, lj ? *lj : MDArgs{});
   else if (lpw > 1)
     hipLaunchKernelGGL((k_fft_z<T, T2, true>), grid, dim3(256), lds, s, pz, za, G, data1, data2, save, add_saved,
                        energy_part, nzb, r, p, lpw, za.n_blocks);
@@ -1082,11 +1095,11 @@ template void launch_fft_xy_t<float, float2>(hipStream_t, int, const FFTPlan1D&,
 template void launch_fft_z_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                               const double*, double2*, double2*, double2*, int, double*, bool,
                                               const RealBArgs<double>*, const PairArgs<double>*, const ZMask*,
-                                              const double2*);
+                                              const double2*, const MDArgs*);
 template void launch_fft_z_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const ZPassArgs&,
                                             const float*, float2*, float2*, float2*, int, double*, bool,
                                             const RealBArgs<float>*, const PairArgs<float>*, const ZMask*,
-                                            const float2*);
+                                            const float2*, const MDArgs*);
 template void launch_fft_xy_field_inv_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&,
                                                          int, const double2*, const double2*, double*, size_t,
                                                          const InterpArgs<double>*);
