@@ -178,6 +178,10 @@ __device__ __forceinline__ double nh_half(const MDArgs& a, int g, double& k2, do
 // joined end and start come from the one sum.
 __global__ __launch_bounds__(WAVE) void k_md_end(MDArgs a, int mode) {
   const int mol = blockIdx.x * WAVE + threadIdx.x;
+  // the Lennard-Jones energies first (independent of the molecule's loads)
+  double ul = 0.0;
+  if ((mode & 1) && a.thermo_out)
+    for (int i = mol; i < a.n_site; i += gridDim.x * WAVE) ul += a.u_lj[i];
   double part[MD_MAX_GROUPS] = {};
   if (mol < a.n_mol) {
     MolRegs r;
@@ -194,9 +198,6 @@ __global__ __launch_bounds__(WAVE) void k_md_end(MDArgs a, int mode) {
       mv2 += r.m[s] * (r.v[0][s] * r.v[0][s] + r.v[1][s] * r.v[1][s] + r.v[2][s] * r.v[2][s]);
     _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) if (g == r.g) part[g] = mv2;
   }
-  double ul = 0.0;
-  if ((mode & 1) && a.thermo_out)
-    for (int i = mol; i < a.n_site; i += gridDim.x * WAVE) ul += a.u_lj[i];
   _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g) part[g] = wave_sum(part[g]);
   ul = wave_sum(ul);
   if (threadIdx.x == 0) {
@@ -213,6 +214,18 @@ __global__ __launch_bounds__(WAVE) void k_md_end(MDArgs a, int mode) {
 }
 
 __global__ __launch_bounds__(WAVE) void k_md_start(MDArgs a, int mode, int rec_step, int n_part) {
+  // the molecule and its forces first: their loads do not wait for the
+  // partial sums, so the two latencies overlap
+  const int mol = blockIdx.x * WAVE + threadIdx.x;
+  const bool live = mol < a.n_mol;
+  MolRegs r;
+  double fm[3][3];
+  if (live) {
+    mol_load(a, mol, r);
+    if (mode & 2)
+      _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
+        _Pragma("unroll") for (int k = 0; k < 3; ++k) fm[k][s] = mol_force(a, r, k, s);
+  }
   double k2[MD_MAX_GROUPS] = {}, ul = 0.0;
   for (int b = threadIdx.x; b < n_part; b += WAVE) {
     const double* o = a.md_part + (size_t)b * MD_PART;
@@ -247,10 +260,7 @@ __global__ __launch_bounds__(WAVE) void k_md_start(MDArgs a, int mode, int rec_s
   if ((mode & 2) && nh)
     _Pragma("unroll") for (int g = 0; g < MD_MAX_GROUPS; ++g)
       if (g < a.n_groups) s2[g] = nh_half(a, g, k2[g], xi[g], eta[g]);
-  const int mol = blockIdx.x * WAVE + threadIdx.x;
-  if (mol < a.n_mol) {
-    MolRegs r;
-    mol_load(a, mol, r);
+  if (live) {
     const double c1 = group_pick(s1, r.g), c2 = group_pick(s2, r.g);
     _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
       _Pragma("unroll") for (int k = 0; k < 3; ++k) {
@@ -262,7 +272,7 @@ __global__ __launch_bounds__(WAVE) void k_md_start(MDArgs a, int mode, int rec_s
       _Pragma("unroll") for (int s = 0; s < 3; ++s) if (s < r.n)
         _Pragma("unroll") for (int k = 0; k < 3; ++k) {
           o[k][s] = r.p[k][s];
-          r.v[k][s] += 0.5 * a.dt * mol_force(a, r, k, s) / r.m[s];
+          r.v[k][s] += 0.5 * a.dt * fm[k][s] / r.m[s];
           r.p[k][s] += a.dt * r.v[k][s];
         }
       if (r.n == 3) shake3(a, r.p, o, r.m);
