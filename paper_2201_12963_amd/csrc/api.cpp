@@ -409,19 +409,23 @@ int alloc_frames(cpm_ctx* c, int nf) {
     c->n_ek = c->za_pot.n_blocks;
     TRY(dalloc(c, &c->d_ek, (size_t)nf * c->n_ek));
     if (nf > 1) TRY(dalloc(c, &c->d_fpart, (size_t)nf * ns * 6 * c->mi.order));
+    // the real charge mesh is stored by one-frame solves only, and the
+    // field mesh by many-frame ones only at orders other than 5 (at 5 the
+    // inverse pass interpolates at the sites)
+    const size_t nf_E = c->mi.order == 5 ? 1 : nf;
     if (!mixed) {
-      TRY(dalloc(c, &c->d_rho, nf * M));
+      TRY(dalloc(c, &c->d_rho, M));
       TRY(dalloc(c, &c->d_phi, nf * M));
-      TRY(dalloc(c, &c->d_E, nf * 3 * M));
+      TRY(dalloc(c, &c->d_E, nf_E * 3 * M));
       TRY(dalloc(c, &c->d_rho_e, nf * M));
       TRY(dalloc(c, &c->d_c1, nf * M));
       TRY(dalloc(c, &c->d_c2, nf * M));
       TRY(dalloc(c, &c->d_save, nf * M));
       HIP_TRY(c, hipMemset(c->d_rho_e, 0, nf * M * sizeof(double)));
     } else {
-      TRY(dalloc(c, &c->d_rhof, nf * M));
+      TRY(dalloc(c, &c->d_rhof, M));
       TRY(dalloc(c, &c->d_phif, nf * M));
-      TRY(dalloc(c, &c->d_Ef, nf * 3 * M));
+      TRY(dalloc(c, &c->d_Ef, nf_E * 3 * M));
       TRY(dalloc(c, &c->d_rho_ef, nf * M));
       TRY(dalloc(c, &c->d_c1f, nf * M));
       TRY(dalloc(c, &c->d_c2f, nf * M));
