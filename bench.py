@@ -230,7 +230,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 413666, "sources_sha256": "daa71c80d5291ec235f79376320a346a45bbe4dd370569b63df28ae15e4f5a5c"}}
+TRAFFIC = {"site_pairs": {"bytes": 413666, "sources_sha256": "08679f4fa2a1702b1998692d9cc3962cb5ed34d4cf5f06a6e90b9b8ccd546f7c"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
