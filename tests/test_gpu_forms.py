@@ -175,6 +175,39 @@ def test_batch_matches_single_frames_other_spline_orders(torch_dev, order):
     ctx.close()
 
 
+def test_batch_matches_single_frames_long_z_mesh(torch_dev):
+    """A z mesh of more than 256 planes: the many-frame passes then transform
+    the electrode charge on every plane (the field pass has no plane mask),
+    while the potential still goes only to the planes the electrode stencils
+    reach, and the interpolation's candidate layers span the longer mesh."""
+    torch = torch_dev
+    import dataclasses
+    from workloads import perturbed_frames
+    _say("[gpu] batch paper ff, mesh 18x18x288")
+    w0, _, _ = built("paper", "ff")
+    w = dataclasses.replace(w0, mesh=(18, 18, 288))
+    frames = perturbed_frames(w, 4, sigma=0.05, seed=12)
+    dvs = np.array([0.0, 3.0])
+    ctx, stream = gpu_context(torch, w)
+    X = torch.tensor(frames, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(stream):
+        Qb, Fb, Eb = ctx.solve_batch(X, dvs)
+    stream.synchronize()
+    assert ctx.sync_status() == 0
+    Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
+    for fi in (0, 3):
+        x = torch.tensor(frames[fi], dtype=torch.float64, device="cuda")
+        for vi, dv in enumerate(dvs):
+            with torch.cuda.stream(stream):
+                q, f, e = ctx.solve(x, float(dv))
+            stream.synchronize()
+            q, f, e = q.cpu().numpy(), f.cpu().numpy(), e.cpu().numpy()
+            assert np.abs(Qb[fi, vi] - q).max() < 1e-11
+            assert rel_rms(Fb[fi, vi], f) < 1e-10
+            assert np.abs(Eb[fi, vi] - e).max() < 1e-9 * np.abs(e).max()
+    ctx.close()
+
+
 def test_batch_matches_single_frames_large_cell(torch_dev):
     """The batched pair tiles on a grid whose x-y stencil is a proper subset of
     the cross-section (5 x 5 cells in x-y, 21 along z): forward stencils of
