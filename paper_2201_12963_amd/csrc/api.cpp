@@ -1554,6 +1554,9 @@ int cpm_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, double* f
   if (!c->built) return fail(c, CPM_ESTATE, "cpm_solve before cpm_build_elastance");
   if (!xyz || !q_out) return fail(c, CPM_EINVAL, "site_xyz and q_out are required");
   if (!std::isfinite(dv)) return fail(c, CPM_ENONFINITE, "non-finite dV");
+  // (a replayed graph does not pass through the enqueue, which clears the MD
+  // loop's claim on the sorted charges that this solve overwrites)
+  c->elec_owner = nullptr;
   auto enqueue = [&]() {
     return c->precision == CPM_MIXED ? enqueue_solve<float>(c, xyz, dv, q_out, f_out, e_out)
                                      : enqueue_solve<double>(c, xyz, dv, q_out, f_out, e_out);
@@ -1938,6 +1941,7 @@ int cpm_md_set_thermostat(cpm_md* md, int on) {
 
 void cpm_md_destroy(cpm_md* md) {
   if (!md) return;
+  if (md->c && md->c->elec_owner == md) md->c->elec_owner = nullptr;
   if (md->c && md->c->stream) hipStreamSynchronize(md->c->stream);
   for (void* p : md->allocs) hipFree(p);
   delete md;

@@ -90,17 +90,20 @@ def test_md_loop_parity(torch_dev, name, geometry, n_steps):
     ctx.close()
 
 
-def test_md_loop_after_another_solve_on_the_context(torch_dev):
+@pytest.mark.parametrize("graph", [False, True])
+def test_md_loop_after_another_solve_on_the_context(torch_dev, graph):
     """Between charge updates the loop reuses the electrode charge's x-y
     spectrum (PPPM) and sorted charges of the last update.  A solve of other
     positions on the same context in between replaces the sorted charges;
     the loop must notice and rebuild them from its own charges, so that the
-    trajectory is the one without the interruption."""
+    trajectory is the one without the interruption.  With graph capture on,
+    the second solve is a replay of the first one's graph, which runs none of
+    the host-side enqueue code."""
     torch = torch_dev
     from oracle import md
     from paper_2201_12963_amd import Context, MDLoop
     from workloads import md_setup, perturbed_frames
-    _say("[gpu] md loop paper ff (PPPM), a solve between two runs")
+    _say(f"[gpu] md loop paper ff (PPPM), solves between runs, graph={graph}")
     w, A, S = built("paper", "ff")
     setup = md_setup(w)
     v0 = np.random.default_rng(23).normal(0.0, 1.0, (3, w.n_site)) * np.sqrt(md.KB * setup.temperature /
@@ -109,16 +112,22 @@ def test_md_loop_after_another_solve_on_the_context(torch_dev):
     results = []
     for interrupt in (False, True):
         stream = torch.cuda.Stream()
-        ctx = Context.from_workload(w, stream=stream)
+        ctx = Context.from_workload(w, stream=stream, graph=graph)
         ctx.build_elastance()
         mdl = MDLoop(ctx, setup)
         x = torch.tensor(w.site_xyz, dtype=torch.float64, device="cuda")
         v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        xo = torch.tensor(other, dtype=torch.float64, device="cuda")
+        qo = torch.empty(w.n_elec, dtype=torch.float64, device="cuda")
+        fo = torch.empty((3, w.n_site), dtype=torch.float64, device="cuda")
+        eo = torch.empty(2, dtype=torch.float64, device="cuda")
         with torch.cuda.stream(stream):
             mdl.run(x, v, w.dv, 7)                   # ends two steps after an update
             if interrupt:
-                xo = torch.tensor(other, dtype=torch.float64, device="cuda")
-                ctx.solve(xo, 0.5 * w.dv)
+                ctx.solve(xo, 0.5 * w.dv, qo, fo, eo)
+            mdl.run(x, v, w.dv, 6)                   # ends three steps after an update
+            if interrupt:
+                ctx.solve(xo, 0.5 * w.dv, qo, fo, eo)   # the same arguments (graph: a replay)
             q, _ = mdl.run(x, v, w.dv, 6)
         stream.synchronize()
         assert ctx.sync_status() == 0
