@@ -654,7 +654,7 @@ int enqueue_forces(cpm_ctx* c, int nf, const double* qa, size_t qa_stride, const
       // that work to a handful of workgroups
       rec(c, CPM_KERNEL_SPREAD_ELEC, s, [=](hipStream_t s) {
         launch_spread_elec_t<T>(s, nf, c->n_touch, c->d_touch, c->d_rowptr, c->d_col, B::val(c), qa, qa_stride,
-                                B::rho_e(c), c->mi.M, sl, fa.field_frame ? c->d_slabfield : nullptr);
+                                B::rho_e(c), c->mi.M, sl, fa.field_frame ? c->d_slabfield : nullptr, c->n_elec);
       });
     } else if (fa.field_frame) {
       launch_slab_field(s, nf, sl, qa, qa_stride, c->d_slabfield);

@@ -474,7 +474,7 @@ __device__ __forceinline__ void slab_field_block(const SlabTerms& sl, const doub
 template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
                           const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M,
-                          const SlabTerms& sl = SlabTerms{}, double* slab_field = nullptr);
+                          const SlabTerms& sl = SlabTerms{}, double* slab_field = nullptr, int n_elec = 0);
 // the slab field alone (one workgroup per frame), where no spread launch hosts it
 void launch_slab_field(hipStream_t s, int n_frames, const SlabTerms& sl, const double* q, size_t q_stride,
                        double* field);
