@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # FP64 vector (and FP64 matrix) peak
 BF16_PEAK_TFLOPS = 2500.0      # dense bf16 matrix peak
+FP32_PEAK_TFLOPS = 157.3       # FP32 vector peak (the mixed form's pair arithmetic)
 REPLAYS = int(os.environ.get("CPM_BENCH_REPLAYS", "200"))
 
 # Algorithmic FP64 operation counts of the per-pair formulas (erfc ~ 20 and
@@ -65,6 +66,16 @@ def pair_counts(w):
     return _PAIRS[key]
 
 
+def listed_planes(w):
+    """Number of z planes that the electrode atoms' order-P stencils reach
+    (stencil of grid coordinate u from floor(u - P/2) + 1, as the library
+    builds it)."""
+    kz, lz, p = w.mesh[2], w.box[2], w.order
+    u = np.mod(w.elec_xyz[2], lz) * (kz / lz)
+    first = np.unique(np.floor(u - p / 2.0).astype(np.int64) + 1)
+    return len({int((f + t) % kz) for f in first for t in range(p)})
+
+
 def kernel_work(w, name, n_frames=1, n_dv=1, mixed=False):
     """(bound, algorithmic work of one launch over n_frames frames, unit) of a
     step kernel.  Bytes count frame-independent tables (S, S c, electrode
@@ -94,16 +105,29 @@ def kernel_work(w, name, n_frames=1, n_dv=1, mixed=False):
         return "hbm", n_frames * 3 * nl * 8 * (2 + n_dv), "GB/s"
     if name == "charges":           # S streamed once; b read, Q0 and q written per frame
         return "hbm", 8 * ne * ne + n_frames * 8 * 3 * ne, "GB/s"
-    if name.startswith("fft_z"):    # complex mesh read and written (+ G once)
-        return "hbm", M * 8 + n_frames * M * 16 * 2, "GB/s"
+    # mesh passes: reals of the form's precision; in batches the electrode
+    # charge's forward and the potential's inverse x-y passes, and the
+    # potential's z-pass output and the field z pass's electrode input, cover
+    # only the planes the electrode stencils reach (ML points)
+    elt = 4 if mixed else 8
+    cpx = 2 * elt
+    ML = listed_planes(w) * w.mesh[0] * w.mesh[1] if batched and w.mesh[2] <= 256 else M
+    if name == "fft_z_pot":         # G once; spectrum read, saved for the field pass, result written
+        return "hbm", M * elt + n_frames * (M * cpx * 2 + ML * cpx), "GB/s"
+    if name == "fft_z_field":       # G once; saved and electrode spectra read, two field spectra written
+        return "hbm", M * elt + n_frames * (M * cpx * 3 + ML * cpx), "GB/s"
     if name == "fft_xy_fwd":        # the spread's launch: sites in, the complex planes out
-        return "hbm", n_frames * (nl * 32 + M * 16), "GB/s"
-    if name.startswith("fft_xy"):   # real plane in, complex plane out (or back)
-        return "hbm", n_frames * M * (8 + 16), "GB/s"
+        return "hbm", n_frames * (nl * 32 + M * cpx), "GB/s"
+    if name in ("fft_xy_inv", "fft_xy_fwd_e"):   # real plane in, complex plane out (or back)
+        return "hbm", n_frames * ML * (elt + cpx), "GB/s"
+    if name == "fft_xy_inv_e":      # two field spectra in; three field meshes out (batches at
+        #                             order 5: the 30 per-plane shares of every site instead)
+        out = nl * 30 * elt if batched and w.order == 5 else M * 3 * elt
+        return "hbm", n_frames * (M * cpx * 2 + out), "GB/s"
     if name == "spread_elec":       # stencil table once; q read, mesh written per frame
-        return "hbm", ne * P3 * 12 + n_frames * (ne * 8 + M * 8), "GB/s"
+        return "hbm", ne * P3 * (4 + elt) + n_frames * (ne * 8 + ML * elt), "GB/s"
     if name == "gather_b":          # stencil table once; mesh read, b written per frame
-        return "hbm", ne * P3 * 12 + n_frames * (M * 8 + ne * 16), "GB/s"
+        return "hbm", ne * P3 * (4 + elt) + n_frames * (ML * elt + ne * 16), "GB/s"
     if name == "bin":               # positions and charges in; sorted copies, order and the
         #                             wrapped-coordinate scratch (written and read back) out
         return "hbm", n_frames * nl * (32 + 36 + 48), "GB/s"
@@ -191,7 +215,7 @@ def peak_of(bound, mixed=False):
         return HBM_PEAK_GBS
     if bound == "mfma":
         return BF16_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
-    return FP64_PEAK_TFLOPS
+    return FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
 
 
 def per_kernel_roofline(w, kernel_ms, n_frames=1, n_dv=1, mixed=False):
@@ -230,7 +254,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 413666, "sources_sha256": "08679f4fa2a1702b1998692d9cc3962cb5ed34d4cf5f06a6e90b9b8ccd546f7c"}}
+TRAFFIC = {"site_pairs": {"bytes": 413666, "sources_sha256": "d669d742e1a97cd7fa9587e2d1819cfefcf3bcac19e8259d5bf4b731f8d2a77e"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
