@@ -351,7 +351,7 @@ void influence_host(const double* box, const int* K, int P, double alpha, std::v
 }
 
 void free_graphs(cpm_ctx* c) {
-  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   c->graphs.clear();
 }
 
@@ -1522,7 +1522,7 @@ int cpm_build_elastance(cpm_ctx* c) {
   TRY(slab_zsc(c));
   // the chunk buffers are released now (they are large)
   for (void* p : {(void*)d_kv, (void*)d_sk, (void*)d_C, (void*)dinv, (void*)pc, (void*)rx, (void*)u}) {
-    hipFree(p);
+    (void)hipFree(p);
     c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
   }
   c->built = true;
@@ -1584,13 +1584,13 @@ int cpm_solve(cpm_ctx* c, const double* xyz, double dv, double* q_out, double* f
   ge.dv = dv;
   ge.kind = 0;
   e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(c, CPM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
   ge.last_use = ++c->tick;
   if (c->graphs.size() >= 16) {
     auto it = std::min_element(c->graphs.begin(), c->graphs.end(),
                                [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
-    hipGraphExecDestroy(it->exec);
+    (void)hipGraphExecDestroy(it->exec);
     c->graphs.erase(it);
   }
   c->graphs.push_back(ge);
@@ -1781,7 +1781,7 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
   md->c = c;
   md->charge_every = d->charge_every;
   auto bad = [&](int code) {
-    for (void* p : md->allocs) hipFree(p);
+    for (void* p : md->allocs) (void)hipFree(p);
     delete md;
     return code;
   };
@@ -1812,7 +1812,7 @@ int cpm_md_create(cpm_ctx* c, const cpm_md_desc* d, cpm_md** out) {
   std::vector<int> sizes(d->mol_size, d->mol_size + d->n_mol), groups(d->mol_group, d->mol_group + d->n_mol);
   std::vector<double> sqeps(ns);
   for (int j = 0; j < ns; ++j) {
-    if (!(d->site_eps[j] >= 0.0)) { for (void* p : md->allocs) hipFree(p); delete md; return fail(c, CPM_EINVAL, "epsilon must be >= 0"); }
+    if (!(d->site_eps[j] >= 0.0)) { for (void* p : md->allocs) (void)hipFree(p); delete md; return fail(c, CPM_EINVAL, "epsilon must be >= 0"); }
     sqeps[j] = std::sqrt(d->site_eps[j]);
   }
   // z windows of the Lennard-Jones partners over the electrostatic cell grid:
@@ -1942,8 +1942,8 @@ int cpm_md_set_thermostat(cpm_md* md, int on) {
 void cpm_md_destroy(cpm_md* md) {
   if (!md) return;
   if (md->c && md->c->elec_owner == md) md->c->elec_owner = nullptr;
-  if (md->c && md->c->stream) hipStreamSynchronize(md->c->stream);
-  for (void* p : md->allocs) hipFree(p);
+  if (md->c && md->c->stream) (void)hipStreamSynchronize(md->c->stream);
+  for (void* p : md->allocs) (void)hipFree(p);
   delete md;
 }
 
@@ -2024,10 +2024,10 @@ const char* cpm_last_error(const cpm_ctx* c) {
 
 void cpm_destroy(cpm_ctx* c) {
   if (!c) return;
-  if (c->stream) hipStreamSynchronize(c->stream);
-  else hipDeviceSynchronize();
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
   free_graphs(c);
-  for (void* p : c->allocs) hipFree(p);
+  for (void* p : c->allocs) (void)hipFree(p);
   delete c;
 }
 

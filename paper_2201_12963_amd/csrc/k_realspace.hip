@@ -481,19 +481,23 @@ void launch_site_forces_t(hipStream_t s, int n_frames, const Cell& cell, const E
   // held by the first, whose halves wait for each other at a barrier)
   int parts = 1;
   if (walk && forces) {
-    // wavefronts of the walking kernel a device holds, per device (up to 16)
+    // wavefronts of the walking kernel a device holds (kept for devices 0-15,
+    // queried on every call for others); a failed query leaves one
+    // wavefront per site
     static int resident[16][2] = {};
-    int dev = 0;
-    hipGetDevice(&dev);
-    int& r = resident[dev & 15][two ? 1 : 0];
-    if (r <= 0) {
-      int cus = 0, blocks = 0;
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-      if (two)
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, true>, 256, 0);
-      else
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, false>, 256, 0);
-      r = cus * blocks * 4;
+    int dev = 0, r = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      int* kept = dev >= 0 && dev < 16 ? &resident[dev][two ? 1 : 0] : nullptr;
+      r = kept ? *kept : 0;
+      if (r <= 0) {
+        int cus = 0, blocks = 0;
+        const hipError_t e1 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const hipError_t e2 =
+            two ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, true>, 256, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_site_forces<T, false>, 256, 0);
+        r = (e1 == hipSuccess && e2 == hipSuccess) ? cus * blocks * 4 : 0;
+        if (kept) *kept = r;
+      }
     }
     parts = 2 * st.n * n_frames <= r ? 2 : 1;
   }
