@@ -505,7 +505,7 @@ void launch_fft_z_t(hipStream_t s, int n_frames, const FFTPlan1D& pz, const ZPas
 // (in1: the input spectrum if not data1, which then only takes the result;
 // the masked many-frame launches work in place)
 template <typename T, typename T2>
-size_t fft_xy_spread_lds(int Kx, int Ky);
+size_t fft_xy_spread_lds(int Kx, int Ky, int pl = 1);
 // dynamic LDS of an x-y launch holding `planes` planes of elt_bytes complex values
 size_t fft_xy_lds_bytes(int Kx, int Ky, int elt_bytes, int planes);
 // threads of the spread + x-y transform workgroups (which also run the

@@ -565,11 +565,15 @@ __global__ __launch_bounds__(INTERP ? XY_THREADS_MANY : XY_THREADS, INTERP ? 5 :
 // The assembled plane is also written to rho_out (the charge mesh, for
 // inspection), then transformed as in k_fft_xy.  ONE: a one-frame launch
 // (1024 threads; the binning keeps its sites in registers, the planes use
-// the direct sum).  P5: B-splines of order 5 (else any other order).
-template <typename T, typename T2, bool ONE, bool P5>
+// the direct sum).  P5: B-splines of order 5 (else any other order).  SPL:
+// consecutive planes per workgroup (many frames), which share the scan of
+// the sites and every staged site's weights; n_planes counts the workgroups
+// of planes.
+template <typename T, typename T2, bool ONE, bool P5, int SPL>
 __global__ __launch_bounds__(ONE ? SPREAD_THREADS_ONE : SPREAD_THREADS) void k_fft_xy_spread(FFTPlan1D px, FFTPlan1D py, int Kz, MeshInfo mi,
                                                        BinArgs ba, T* __restrict__ rho_out,
                                                        T2* __restrict__ out_c, int n_planes) {
+  static_assert(!ONE || SPL == 1, "a one-frame launch takes one plane per workgroup");
   // 16-byte alignment for the complex values and the FP64 LDS atomics
   extern __shared__ __align__(16) unsigned char smem[];
   if ((int)blockIdx.x >= n_planes) {
@@ -581,18 +585,19 @@ __global__ __launch_bounds__(ONE ? SPREAD_THREADS_ONE : SPREAD_THREADS) void k_f
   }
   const int Kx = px.n, Ky = py.n, NP = Kx * Ky;
   T2* A = reinterpret_cast<T2*>(smem);
-  T2* B = A + NP;
-  T2* twx = B + NP;
+  T2* B = A + SPL * NP;
+  T2* twx = B + SPL * NP;
   T2* twy = twx + Kx;
-  // the real plane accumulates in FP64 in every precision (FP32 LDS atomics
+  // the real planes accumulate in FP64 in every precision (FP32 LDS atomics
   // measured slower than FP64 ones: 6.6 against 3.5 ms for a 4096-frame spread)
-  double* acc = reinterpret_cast<double*>(twy + Ky);       // NP values
-  int* list = reinterpret_cast<int*>(acc + NP);            // staged (site, z slot) entries
+  double* acc = reinterpret_cast<double*>(twy + Ky);       // SPL * NP values
+  int* list = reinterpret_cast<int*>(acc + SPL * NP);      // staged (site, z slot) entries, or sites (SPL > 1)
   load_twiddles(px, twx);
   load_twiddles(py, twy);
-  const int iz = blockIdx.x;
+  const int iz = blockIdx.x * SPL;                         // first plane of the workgroup
+  const int npl = min(SPL, Kz - iz);
   const int frame = blockIdx.y;
-  for (int i = threadIdx.x; i < NP; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < npl * NP; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
   const int P = mi.order;
   const int n = ba.n_site;
@@ -608,10 +613,11 @@ __global__ __launch_bounds__(ONE ? SPREAD_THREADS_ONE : SPREAD_THREADS) void k_f
   // the weights below use the same function, so they agree on the stencil)
   const double rLx = 1.0 / Lx, rLy = 1.0 / Ly, rLz = 1.0 / Lz;
   auto wrap = [](double x, double L, double rL) { return x - L * floor(x * rL); };
-  // one staged (site, z slot) entry: the site's B-spline weights, then its
-  // P x P in-plane contributions added with LDS atomics
+  // one staged entry: the site's B-spline weights, then its P x P in-plane
+  // contributions to each plane of the workgroup its stencil reaches, added
+  // with LDS atomics (SPL == 1: the entry carries the plane's z slot)
   auto add_site = [&](int e) {
-    const int j = e >> 3, tz = e & 7;
+    const int j = SPL == 1 ? e >> 3 : e;
     double xj = sx[j], yj = sy[j];
     if (!isfinite(xj)) xj = 0.0;
     if (!isfinite(yj)) yj = 0.0;
@@ -621,24 +627,37 @@ __global__ __launch_bounds__(ONE ? SPREAD_THREADS_ONE : SPREAD_THREADS) void k_f
     constexpr int ORD = P5 ? 5 : -1;
     int fx = spline_triangle_d<T, ORD>(wrap(xj, Lx, rLx) * ihx, P, Bx);
     int fy = spline_triangle_d<T, ORD>(wrap(yj, Ly, rLy) * ihy, P, By);
-    spline_triangle_d<T, ORD>(wrap(zj, Lz, rLz) * ihz, P, Bz);
+    int fz = spline_triangle_d<T, ORD>(wrap(zj, Lz, rLz) * ihz, P, Bz);
     fx = ((fx % Kx) + Kx) % Kx;
     fy = ((fy % Ky) + Ky) % Ky;
-    T wz = 0;
+    fz = ((fz % Kz) + Kz) % Kz;
 #pragma unroll
-    for (int b = 0; b < MAX_ORDER; ++b) wz = (b == P - 1 - tz) ? Bz[b] : wz;
-    const T qz = (T)q[j] * wz;
+    for (int p = 0; p < SPL; ++p) {
+      int tz;
+      if (SPL == 1) {
+        tz = e & 7;
+      } else {
+        tz = iz + p - fz;
+        tz += (tz < 0) ? Kz : 0;
+        if (p >= npl || tz >= P) continue;
+      }
+      T wz = 0;
 #pragma unroll
-    for (int by = 0; by < MAX_ORDER; ++by) {
-      if (by < P) {
-        int iy = fy + (P - 1 - by); iy -= (iy >= Ky) ? Ky : 0;
-        const T qyz = qz * By[by];
-        double* row = acc + iy * Kx;
+      for (int b = 0; b < MAX_ORDER; ++b) wz = (b == P - 1 - tz) ? Bz[b] : wz;
+      const T qz = (T)q[j] * wz;
+      double* plane = acc + p * NP;
 #pragma unroll
-        for (int bx = 0; bx < MAX_ORDER; ++bx) {
-          if (bx < P) {
-            int ix = fx + (P - 1 - bx); ix -= (ix >= Kx) ? Kx : 0;
-            atomicAdd(row + ix, (double)(qyz * Bx[bx]));
+      for (int by = 0; by < MAX_ORDER; ++by) {
+        if (by < P) {
+          int iy = fy + (P - 1 - by); iy -= (iy >= Ky) ? Ky : 0;
+          const T qyz = qz * By[by];
+          double* row = plane + iy * Kx;
+#pragma unroll
+          for (int bx = 0; bx < MAX_ORDER; ++bx) {
+            if (bx < P) {
+              int ix = fx + (P - 1 - bx); ix -= (ix >= Kx) ? Kx : 0;
+              atomicAdd(row + ix, (double)(qyz * Bx[bx]));
+            }
           }
         }
       }
@@ -677,9 +696,11 @@ __global__ __launch_bounds__(ONE ? SPREAD_THREADS_ONE : SPREAD_THREADS) void k_f
         tz = iz - fz;
         tz += (tz < 0) ? Kz : 0;
       }
-      const bool hit = tz < P;
+      // (several planes: the stencil reaches the first one, or wraps past
+      // Kz into one of the others)
+      const bool hit = j < n && (tz < P || (SPL > 1 && tz > Kz - npl));
       const unsigned long long m = __ballot(hit);
-      if (hit) wl[cnt + __popcll(m & lt)] = j * 8 + tz;   // site index and its z weight slot
+      if (hit) wl[cnt + __popcll(m & lt)] = SPL == 1 ? j * 8 + tz : j;   // site (and its z weight slot)
       cnt += __popcll(m);
     }
     // a wavefront's LDS operations complete in order: its lanes see the list
@@ -688,16 +709,16 @@ __global__ __launch_bounds__(ONE ? SPREAD_THREADS_ONE : SPREAD_THREADS) void k_f
     __builtin_amdgcn_wave_barrier();                      // list read before the next batch writes it
   }
   __syncthreads();
-  const size_t off = ((size_t)frame * Kz + iz) * NP;
-  for (int i = threadIdx.x; i < NP; i += blockDim.x) {
+  const size_t off = ((size_t)frame * Kz + iz) * NP;        // the workgroup's planes are contiguous
+  for (int i = threadIdx.x; i < npl * NP; i += blockDim.x) {
     if (rho_out) rho_out[off + i] = (T)acc[i];
     A[i] = T2{(T)acc[i], (T)0};
   }
   __syncthreads();
-  T2* r1p = plane_lines(A, B, px, twx, Ky, 1, Kx, -1, ONE);
+  T2* r1p = plane_lines(A, B, px, twx, Ky, 1, Kx, -1, ONE, npl, NP);
   T2* o1 = (r1p == A) ? B : A;
-  T2* r2p = plane_lines(r1p, o1, py, twy, Kx, Kx, 1, -1, ONE);
-  for (int i = threadIdx.x; i < NP; i += blockDim.x) out_c[off + i] = r2p[i];
+  T2* r2p = plane_lines(r1p, o1, py, twy, Kx, Kx, 1, -1, ONE, npl, NP);
+  for (int i = threadIdx.x; i < npl * NP; i += blockDim.x) out_c[off + i] = r2p[i];
 }
 
 // ------------------------------------------------------------------- z pass
@@ -923,25 +944,32 @@ __global__ __launch_bounds__(256) void k_fft_z_masked(FFTPlan1D pz, ZPassArgs za
 
 // ------------------------------------------------------------------ launchers
 
-// dynamic LDS of k_fft_xy_spread: two complex planes, twiddles, the real
-// plane and the site staging list
+// dynamic LDS of k_fft_xy_spread over pl planes: two complex planes each,
+// twiddles, the real planes and the site staging list
 template <typename T, typename T2>
-size_t fft_xy_spread_lds(int Kx, int Ky) {
-  return (2 * (size_t)Kx * Ky + Kx + Ky) * sizeof(T2) + (size_t)Kx * Ky * sizeof(double) +
+size_t fft_xy_spread_lds(int Kx, int Ky, int pl) {
+  return (2 * (size_t)pl * Kx * Ky + Kx + Ky) * sizeof(T2) + (size_t)pl * Kx * Ky * sizeof(double) +
          (size_t)SPREAD_LIST * sizeof(int);
 }
+
+// planes per workgroup of a many-frame spread launch (where they fit)
+constexpr int SPREAD_PLANES_MANY = 2;
 
 
 template <typename T, typename T2>
 void launch_fft_xy_spread_t(hipStream_t s, int n_frames, const FFTPlan1D& px, const FFTPlan1D& py, int Kz,
                             const MeshInfo& mi, const BinArgs& ba, T* rho_out, T2* out_c, bool planes, bool bin) {
-  const int np = planes ? Kz : 0;
-  size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n);
+  constexpr int S = SPREAD_PLANES_MANY;
+  const bool multi = n_frames > 1 && fft_xy_spread_lds<T, T2>(px.n, py.n, S) <= LDS_LIMIT;
+  const int spl = multi ? S : 1;
+  const int np = planes ? (Kz + spl - 1) / spl : 0;         // workgroups of planes
+  size_t lds = fft_xy_spread_lds<T, T2>(px.n, py.n, spl);
   if (bin) lds = std::max(lds, bin_lds_spread(ba.n_site, ba.cell.n_cells));
   dim3 grid(np + (bin ? 1 : 0), n_frames);
   if (grid.x == 0) return;
-  auto* k = n_frames == 1 ? (mi.order == 5 ? k_fft_xy_spread<T, T2, true, true> : k_fft_xy_spread<T, T2, true, false>)
-                          : (mi.order == 5 ? k_fft_xy_spread<T, T2, false, true> : k_fft_xy_spread<T, T2, false, false>);
+  auto* k = n_frames == 1 ? (mi.order == 5 ? k_fft_xy_spread<T, T2, true, true, 1> : k_fft_xy_spread<T, T2, true, false, 1>)
+            : multi       ? (mi.order == 5 ? k_fft_xy_spread<T, T2, false, true, S> : k_fft_xy_spread<T, T2, false, false, S>)
+                          : (mi.order == 5 ? k_fft_xy_spread<T, T2, false, true, 1> : k_fft_xy_spread<T, T2, false, false, 1>);
   hipLaunchKernelGGL(k, grid, dim3(n_frames == 1 ? SPREAD_THREADS_ONE : SPREAD_THREADS), lds, s, px, py, Kz, mi, ba, rho_out,
                      out_c, np);
 }
@@ -950,8 +978,8 @@ size_t bin_lds_spread(int n_site, int n_cells) {
   return std::max(bin_body_lds<SPREAD_THREADS>(n_site, n_cells), bin_body_lds<SPREAD_THREADS_ONE>(n_site, n_cells));
 }
 
-template size_t fft_xy_spread_lds<double, double2>(int, int);
-template size_t fft_xy_spread_lds<float, float2>(int, int);
+template size_t fft_xy_spread_lds<double, double2>(int, int, int);
+template size_t fft_xy_spread_lds<float, float2>(int, int, int);
 template void launch_fft_xy_spread_t<double, double2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
                                                       const MeshInfo&, const BinArgs&, double*, double2*, bool, bool);
 template void launch_fft_xy_spread_t<float, float2>(hipStream_t, int, const FFTPlan1D&, const FFTPlan1D&, int,
