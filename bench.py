@@ -254,7 +254,7 @@ ROOFLINE_KERNEL = "site_pairs"
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE), each
 # scaled by the same counter's reading for a 256 MiB device copy; valid
 # only while the kernel's sources are the ones measured (hash below).
-TRAFFIC = {"site_pairs": {"bytes": 413666, "sources_sha256": "d669d742e1a97cd7fa9587e2d1819cfefcf3bcac19e8259d5bf4b731f8d2a77e"}}
+TRAFFIC = {"site_pairs": {"bytes": 413666, "sources_sha256": "16b0805e7eb124f4516189d0cdb35401f2f6c7fce4391fbf60ad96bf17cc99ef"}}
 TRAFFIC_SOURCES = ["csrc/pairs.h", "csrc/tiles.h", "csrc/k_realspace.hip", "csrc/common.h", "csrc/erfcx_cheb.h"]
 
 
