@@ -55,7 +55,8 @@ __global__ __launch_bounds__(256) void k_spread_elec(int n_touch, const int* __r
 // same table entries, so the table is read once per F frames instead of
 // once per frame
 constexpr int SPREAD_FRAMES_THREADS = 512;
-constexpr int SPREAD_FRAMES_LDS = 64 * 1024;     // staged charges per workgroup, bytes
+constexpr int SPREAD_FRAMES_LDS = 64 * 1024;     // staged charges of 8 frames at most, bytes
+constexpr int SPREAD_FRAMES_LDS_MAX = 128 * 1024;  // of 4 or 2 frames (one workgroup per CU)
 constexpr int SPREAD_FRAMES_CHUNKS = 4;          // point chunks (workgroups per frame group)
 
 template <typename T, int F>
@@ -154,12 +155,17 @@ template <typename T>
 void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* touch, const int* rowptr,
                           const int* col, const T* val, const double* q, size_t q_stride, T* rho, int M,
                           const SlabTerms& sl, double* slab_field, int n_elec) {
-  if (n_frames > 1 && n_elec > 0 && n_elec * sizeof(double) <= (size_t)SPREAD_FRAMES_LDS) {
-    // many frames: as many per workgroup (up to 8) as the staging allows
-    const int F = n_elec * sizeof(double) * 8 <= (size_t)SPREAD_FRAMES_LDS   ? 8
-                  : n_elec * sizeof(double) * 4 <= (size_t)SPREAD_FRAMES_LDS ? 4
-                  : n_elec * sizeof(double) * 2 <= (size_t)SPREAD_FRAMES_LDS ? 2
-                                                                             : 1;
+  // many frames: 8 per workgroup where their charges fit in 64 KiB, else 4
+  // or 2 within 128 KiB (8 frames in 112 KiB, one workgroup per CU, measured
+  // slower than 4 in 56 KiB; a single frame per workgroup slower than the
+  // per-frame kernel below, which then serves)
+  const size_t row = (size_t)n_elec * sizeof(double);
+  const int F = n_frames <= 1 || n_elec <= 0            ? 0
+                : 8 * row <= (size_t)SPREAD_FRAMES_LDS     ? 8
+                : 4 * row <= (size_t)SPREAD_FRAMES_LDS_MAX ? 4
+                : 2 * row <= (size_t)SPREAD_FRAMES_LDS_MAX ? 2
+                                                           : 0;
+  if (F > 0) {
     const dim3 grid(SPREAD_FRAMES_CHUNKS, (n_frames + F - 1) / F);
     const size_t lds = (size_t)F * n_elec * sizeof(double);
     auto go = [&](auto kern) {
@@ -168,8 +174,7 @@ void launch_spread_elec_t(hipStream_t s, int n_frames, int n_touch, const int* t
     };
     if (F == 8) go(k_spread_elec_frames<T, 8>);
     else if (F == 4) go(k_spread_elec_frames<T, 4>);
-    else if (F == 2) go(k_spread_elec_frames<T, 2>);
-    else go(k_spread_elec_frames<T, 1>);
+    else go(k_spread_elec_frames<T, 2>);
     if (slab_field) launch_slab_field(s, n_frames, sl, q, q_stride, slab_field);
     return;
   }
