@@ -251,7 +251,12 @@ int cpm_md_create(cpm_ctx* ctx, const cpm_md_desc* desc, cpm_md** out);
  * call's).  q_out (device [n_elec] or NULL): the charges of the last update;
  * thermo_out (device [n_steps][4] or NULL): per step the kinetic energy, the
  * Lennard-Jones energy, E_cp of the last charge update and the thermostat's
- * energy sum_g (Q xi^2/2 + N_f kT eta) (kJ/mol).  Asynchronous. */
+ * energy sum_g (Q xi^2/2 + N_f kT eta) (kJ/mol).  Asynchronous.  Between
+ * charge updates the steps reuse the electrode charge's mesh spectrum and
+ * cell-sorted charges of the loop's last update (PPPM); any other call on
+ * the context in between (a solve, replayed graph included, a batch,
+ * another loop) makes the next step rebuild them from the loop's own
+ * charges, so calls may be interleaved without changing the trajectory. */
 int cpm_md_run(cpm_md* md, double* x, double* v, double dv, int n_steps, double* q_out, double* thermo_out);
 
 /* Thermostat variables (host [n_groups] each, nullable) and the step count;
