@@ -82,14 +82,15 @@ def test_three_layer_step_and_batch(torch_dev, geometry):
     assert rel_rms(f, ref["f"]) < 1e-9
     assert abs(e[0] - ref["u_coul"]) < 1e-9 * abs(ref["u_coul"])
     assert abs(e[1] - ref["e_cp"]) < 1e-9 * abs(ref["e_cp"])
-    # batched re-solve of snapshots over a dV sweep
-    frames = perturbed_frames(w, 64, sigma=0.05, seed=6)
+    # batched re-solve of snapshots over a dV sweep (63 frames: the last group
+    # of frames that share the electrode spread's staging is a partial one)
+    frames = perturbed_frames(w, 63, sigma=0.05, seed=6)
     dvs = np.array([0.0, 1.2, 2.5])
     with torch.cuda.stream(stream):
         Qb, Fb, Eb = ctx.solve_batch(torch.tensor(frames, dtype=torch.float64, device="cuda"), dvs)
     stream.synchronize()
     Qb, Fb, Eb = Qb.cpu().numpy(), Fb.cpu().numpy(), Eb.cpu().numpy()
-    for fi, vi in ((0, 2), (63, 1)):
+    for fi, vi in ((0, 2), (62, 1)):
         r = cpm.step(w, A, S, es, site_xyz=frames[fi], dv=dvs[vi])
         qerr = np.abs(Qb[fi, vi] - r["q"]).max()
         _say(f"    frame {fi} dV {dvs[vi]}: q err {qerr:.2e} e, F rel rms {rel_rms(Fb[fi, vi], r['f']):.2e}")
@@ -107,12 +108,16 @@ def test_three_layer_step_and_batch(torch_dev, geometry):
 @pytest.mark.parametrize("geometry", ["ff", "dc"])
 def test_three_layer_mixed_single_frame(torch_dev, geometry):
     """The precision form on 2640 (5280 in the doubled cell) charged atoms
-    against the oracle; more than 4096 atoms need no special path."""
+    against the oracle, one frame and a batch of 7 (whose electrode spread
+    stages 4, or 2, frames per workgroup, the last group a partial one);
+    more than 4096 atoms need no special path."""
     torch = torch_dev
     from paper_2201_12963_amd import Context, MIXED
+    from workloads import perturbed_frames
     _say(f"[gpu] three-layer paper {geometry}, mixed precision")
     w, A, S = built3("paper", geometry)
-    ref = cpm.step(w, A, S, cpm.Electrostatics(w, "pppm"))
+    es = cpm.Electrostatics(w, "pppm")
+    ref = cpm.step(w, A, S, es)
     stream = torch.cuda.Stream()
     ctx = Context.from_workload(w, precision=MIXED, stream=stream)
     ctx.build_elastance()
@@ -128,4 +133,15 @@ def test_three_layer_mixed_single_frame(torch_dev, geometry):
     assert abs(q.sum()) < 1e-12
     if geometry == "dc":
         assert abs(q[w.elec_sub == 1].sum()) < 1e-12
+    frames = perturbed_frames(w, 7, sigma=0.05, seed=8)
+    dvs = np.array([0.0, 2.5])
+    with torch.cuda.stream(stream):
+        Qb, Fb, Eb = ctx.solve_batch(torch.tensor(frames, dtype=torch.float64, device="cuda"), dvs)
+    stream.synchronize()
+    r = cpm.step(w, A, S, es, site_xyz=frames[6], dv=dvs[1])
+    qb, fb = Qb[6, 1].cpu().numpy(), Fb[6, 1].cpu().numpy()
+    _say(f"    mixed batch frame 6 dV {dvs[1]}: q max {np.abs(qb - r['q']).max():.3e} e, "
+         f"F rel rms {rel_rms(fb, r['f']):.3e}")
+    assert np.abs(qb - r["q"]).max() < Q_TOL
+    assert rel_rms(fb, r["f"]) < F_RTOL
     ctx.close()
